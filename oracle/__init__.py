@@ -1,0 +1,286 @@
+"""Oracle of the isogeometric Galerkin BEM hot path (ctypes binding of bem_oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check in __graft_entry__ and the
+cpu_baseline leg of bench.py may import this package.  The product path (the HIP library
+and its Python binding) never imports, links or executes anything here, and this package
+never imports the product path.
+
+The oracle is plain serial FP64 C++ (oracle/bem_oracle.cpp); this module only marshals
+numpy arrays.  Complex quantities are numpy complex128 arrays, passed as interleaved
+(re, im) doubles.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bem_oracle.cpp")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+# geometry kinds, PDEs and data kinds (same numbering as the C code)
+SPHERE, ELLIPSOID, TORUS, FLAT = 0, 1, 2, 3
+LAPLACE, HELMHOLTZ = 0, 1
+POINT_SOURCE, PLANE_WAVE = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (plain -O2, no fast-math)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "orc_last_error": (ctypes.c_char_p, []),
+            "orc_gauss01": (I, [I, P, P]),
+            "orc_bspline": (I, [I, I, I, I, I64, P, P]),
+            "orc_bspline_count": (I, [I, I, I]),
+            "orc_space_new": (I, [I, P, I, I, D, D, I, I, I, P]),
+            "orc_space_free": (None, [P]),
+            "orc_space_ndof": (I64, [P]),
+            "orc_space_nelem": (I64, [P]),
+            "orc_gamma": (I, [P, I, I64, P, P, P, P]),
+            "orc_area": (I, [P, I, P]),
+            "orc_classify": (I, [P, I64, I64, P]),
+            "orc_pair_block": (I, [P, I64, I64, I, I, P]),
+            "orc_dense": (I, [P, I, I, P]),
+            "orc_density_pairing": (I, [P, I, I, I, I, P]),
+            "orc_rhs": (I, [P, I, P, I, I, P]),
+            "orc_potential": (I, [P, I, P, I64, P, P]),
+            "orc_h2_new": (I, [P, I, D, I, I, I, I, P]),
+            "orc_h2_free": (None, [P]),
+            "orc_h2_info": (I, [P, P]),
+            "orc_h2_lists": (I, [P, P, P]),
+            "orc_h2_clusters": (I, [P, P, P]),
+            "orc_h2_tables": (I, [P, P, P, P, P]),
+            "orc_h2_near_csr": (I, [P, P, P, P]),
+            "orc_h2_moments": (I, [P, P, I, P]),
+            "orc_h2_apply": (I, [P, P, P, I]),
+            "orc_h2_apply_rows": (I, [P, P, P, I64, I, P]),
+            "orc_h2_gmres": (I, [P, P, P, D, I, I, P]),
+            "orc_dense_gmres": (I, [I64, I, P, P, P, D, I, I, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("oracle: " + lib().orc_last_error().decode())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def gauss01(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().orc_gauss01(n, _p(x), _p(w)))
+    return x, w
+
+
+def bspline(d: int, r: int, L: int, j: int, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    _check(lib().orc_bspline(d, r, L, j, x.size, _p(x), _p(out)))
+    return out
+
+
+def bspline_count(d: int, r: int, L: int) -> int:
+    return lib().orc_bspline_count(d, r, L)
+
+
+class Space:
+    """Discrete space S^2 on an analytic multi-patch geometry, with its PDE."""
+
+    def __init__(self, geom: int, gparams=(), pde: int = LAPLACE, kappa: complex = 0.0,
+                 degree: int = 1, knot_rep: int = 1, level: int = 0):
+        gp = np.ascontiguousarray(np.asarray(gparams, dtype=np.float64).reshape(-1))
+        if gp.size == 0:
+            gp = np.zeros(1)
+        h = ctypes.c_void_p()
+        _check(lib().orc_space_new(geom, _p(gp), int(len(gparams)), pde, float(np.real(kappa)),
+                                   float(np.imag(kappa)), degree, knot_rep, level, ctypes.byref(h)))
+        self._h = h
+        self.pde = pde
+        self.complex = pde == HELMHOLTZ
+        self.degree, self.level, self.knot_rep = degree, level, knot_rep
+        self.geom = geom
+        self.dtype = np.complex128 if self.complex else np.float64
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_space_free(self._h)
+            self._h = None
+
+    @property
+    def ndof(self) -> int:
+        return lib().orc_space_ndof(self._h)
+
+    @property
+    def nelem(self) -> int:
+        return lib().orc_space_nelem(self._h)
+
+    def gamma(self, patch: int, st):
+        st = np.ascontiguousarray(st, dtype=np.float64).reshape(-1, 2)
+        n = st.shape[0]
+        xyz = np.zeros((n, 3))
+        kap = np.zeros(n)
+        nrm = np.zeros((n, 3))
+        _check(lib().orc_gamma(self._h, patch, n, _p(st), _p(xyz), _p(kap), _p(nrm)))
+        return xyz, kap, nrm
+
+    def area(self, q: int = 8) -> float:
+        a = ctypes.c_double()
+        _check(lib().orc_area(self._h, q, ctypes.byref(a)))
+        return a.value
+
+    def classify(self, e1: int, e2: int):
+        out = np.zeros(3, dtype=np.int32)
+        _check(lib().orc_classify(self._h, e1, e2, _p(out)))
+        return tuple(int(v) for v in out)
+
+    def pair_block(self, e1: int, e2: int, qg: int = 8, qs: int = 8) -> np.ndarray:
+        nb = (self.degree + 1) ** 2
+        B = np.zeros((nb, nb), dtype=self.dtype)
+        _check(lib().orc_pair_block(self._h, e1, e2, qg, qs, _p(B)))
+        return B
+
+    def dense(self, qg: int = 8, qs: int = 8) -> np.ndarray:
+        N = self.ndof
+        A = np.zeros((N, N), dtype=self.dtype)
+        _check(lib().orc_dense(self._h, qg, qs, _p(A)))
+        return A
+
+    def density_pairing(self, fid: int, gid: int, qg: int = 8, qs: int = 8) -> complex:
+        out = np.zeros(2)
+        _check(lib().orc_density_pairing(self._h, fid, gid, qg, qs, _p(out)))
+        return complex(out[0], out[1])
+
+    def rhs(self, kind: int, params, q: int = 8) -> np.ndarray:
+        prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, 3))
+        nrhs = prm.shape[0]
+        b = np.zeros((nrhs, self.ndof), dtype=self.dtype)
+        _check(lib().orc_rhs(self._h, kind, _p(prm), nrhs, q, _p(b)))
+        return b.T.copy() if nrhs > 1 else b[0]
+
+    def potential(self, rho, pts, q: int = 8) -> np.ndarray:
+        rho = np.ascontiguousarray(rho, dtype=self.dtype)
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        u = np.zeros(pts.shape[0], dtype=self.dtype)
+        _check(lib().orc_potential(self._h, q, _p(rho), pts.shape[0], _p(pts), _p(u)))
+        return u
+
+
+class H2:
+    """H^2 operator of a Space (near field optional: assemble_near=False keeps it lazy)."""
+
+    def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf: int = 0, qg: int = 8,
+                 qs: int = 8, assemble_near: bool = True):
+        self.space = space
+        h = ctypes.c_void_p()
+        _check(lib().orc_h2_new(space._h, q, eta, leaf, qg, qs, int(assemble_near), ctypes.byref(h)))
+        self._h = h
+        self.q, self.eta, self.leaf = q, eta, leaf
+        info = np.zeros(6, dtype=np.int64)
+        _check(lib().orc_h2_info(self._h, _p(info)))
+        self.nclusters, self.nfar, self.nnear, self.nnz, self.nloc, self.qm = (int(v) for v in info)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_h2_free(self._h)
+            self._h = None
+
+    def lists(self):
+        far = np.zeros((self.nfar, 2), dtype=np.int64)
+        near = np.zeros((self.nnear, 2), dtype=np.int64)
+        _check(lib().orc_h2_lists(self._h, _p(far), _p(near)))
+        return far, near
+
+    def clusters(self):
+        ids = np.zeros((self.nclusters, 4), dtype=np.int32)
+        balls = np.zeros((self.nclusters, 4))
+        _check(lib().orc_h2_clusters(self._h, _p(ids), _p(balls)))
+        return ids, balls
+
+    def tables(self):
+        q2 = self.q * self.q
+        K = np.zeros((self.nfar, q2, q2), dtype=self.space.dtype)
+        E0 = np.zeros((self.q, self.q))
+        E1 = np.zeros((self.q, self.q))
+        nl = 1 << self.leaf
+        V1 = np.zeros((nl, self.q, self.nloc))
+        _check(lib().orc_h2_tables(self._h, _p(K), _p(E0), _p(E1), _p(V1)))
+        return K, E0, E1, V1
+
+    def near_csr(self):
+        N = self.space.ndof
+        rowptr = np.zeros(N + 1, dtype=np.int64)
+        col = np.zeros(self.nnz, dtype=np.int64)
+        val = np.zeros(self.nnz, dtype=self.space.dtype)
+        _check(lib().orc_h2_near_csr(self._h, _p(rowptr), _p(col), _p(val)))
+        return rowptr, col, val
+
+    def moments(self, x, direct: bool = False):
+        x = np.ascontiguousarray(x, dtype=self.space.dtype)
+        m = np.zeros((self.nclusters, self.q * self.q), dtype=self.space.dtype)
+        _check(lib().orc_h2_moments(self._h, _p(x), int(direct), _p(m)))
+        return m
+
+    def apply(self, x) -> np.ndarray:
+        x = np.asarray(x, dtype=self.space.dtype)
+        N = self.space.ndof
+        X = np.ascontiguousarray(x.reshape(N, -1).T)
+        Y = np.zeros_like(X)
+        _check(lib().orc_h2_apply(self._h, _p(X), _p(Y), X.shape[0]))
+        return Y.T.reshape(x.shape)
+
+    def apply_rows(self, x, rows, far: bool = True, near: bool = True) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=self.space.dtype)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        y = np.zeros(rows.size, dtype=self.space.dtype)
+        parts = (1 if far else 0) | (2 if near else 0)
+        _check(lib().orc_h2_apply_rows(self._h, _p(x), _p(rows), rows.size, parts, _p(y)))
+        return y
+
+    def gmres(self, b, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
+        b = np.ascontiguousarray(b, dtype=self.space.dtype)
+        x = np.zeros_like(b)
+        st = np.zeros(3)
+        _check(lib().orc_h2_gmres(self._h, _p(b), _p(x), tol, restart, maxit, _p(st)))
+        return x, int(st[0]), float(st[1]), bool(st[2])
+
+
+def dense_gmres(A, b, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
+    A = np.ascontiguousarray(A)
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(b)
+    dt = np.complex128 if cplx else np.float64
+    A = np.ascontiguousarray(A, dtype=dt)
+    b = np.ascontiguousarray(b, dtype=dt)
+    x = np.zeros_like(b)
+    st = np.zeros(3)
+    _check(lib().orc_dense_gmres(A.shape[0], int(cplx), _p(A), _p(b), _p(x), tol, restart, maxit, _p(st)))
+    return x, int(st[0]), float(st[1]), bool(st[2])
