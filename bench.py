@@ -1,0 +1,184 @@
+"""Benchmark of the H^2 matvec and GMRES time-to-1e-8 on one MI355X.
+
+Workload: Laplace single layer on the unit sphere as 6 cube-sphere patches, level 6,
+degree-2 B-splines (N = 26,136), H^2 with 5x5 Chebyshev points per cluster, eta = 1.6,
+leaf level 4.  A step is one H^2 matvec y = A x (forward, upward, coupling, downward,
+backward + near field) on a seeded random x resident in HBM.
+
+Prints one JSON line (metric, value = DOF/s, ...), plus roofline of the dominant kernel
+(far-field coupling, HBM-bound) from HIP events around that stage, the GMRES solve to a
+relative residual of 1e-8, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, x, nrows):
+    """Oracle H^2 matvec on the same workload, timed on a bounded sample: the far field
+    (forward, upward, coupling, downward, backward) over all N rows in full, the near field
+    over `nrows` sampled rows (assembled first, untimed), scaled to N rows."""
+    import numpy as np
+
+    import oracle as O
+    import workloads as W
+
+    S = O.Space(O.SPHERE, [], O.LAPLACE, 0.0, degree=cfg["degree"], level=cfg["level"])
+    H = O.H2(S, q=cfg["q"], eta=cfg["eta"], leaf=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble_near=False)
+    N = S.ndof
+    rows = W.sample_rows(1, N, nrows)
+    H.assemble_near_rows(rows)
+    allrows = np.arange(N, dtype=np.int64)
+    t0 = time.perf_counter()
+    H.apply_rows(x, allrows, far=True, near=False)
+    t_far = time.perf_counter() - t0
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        H.apply_rows(x, rows, far=False, near=True)
+    t_near = (time.perf_counter() - t0) / reps * (N / rows.size)
+    t = t_far + t_near
+    return {"value": N / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"far field over all {N} rows timed in full ({t_far:.3f} s); near field timed over "
+                      f"{rows.size} seeded rows and scaled to {N} rows ({t_near:.3f} s); serial FP64"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1906_00785_amd as B
+    import workloads as W
+
+    cfg = W.CONFIGS[1]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=cfg["degree"], level=cfg["level"])
+    t0 = time.perf_counter()
+    A = B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble=False)
+    t_plan = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A.assemble()
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    info = A.info
+    N = A.ndof
+    print(f"bench: N={N} far={info.nfar} near_leaf_pairs={info.nnear} nnz={info.near_nnz} "
+          f"plan {t_plan:.2f}s assemble {t_asm:.3f}s", file=sys.stderr, flush=True)
+
+    x_host = W.random_vector(W.rng(1, 11), N)
+    x = torch.from_numpy(x_host).cuda()
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        A.apply(x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        A.apply(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    value = N / (ms * 1e-3)
+
+    # stage timing with HIP events on the same stream (same number of steps)
+    A.profile(True)
+    for _ in range(args.steps):
+        A.apply(x, out=y)
+    stage_ms, napp = A.profile_read()
+    A.profile(False)
+    q2 = cfg["q"] ** 2
+    coupling_bytes = info.nfar * q2 * q2 * 8 + info.nfar * 4 + 2 * info.nclusters * q2 * 8 + info.nclusters * 20
+    achieved = coupling_bytes / (stage_ms[1] * 1e-3) / 1e9
+    near_bytes = info.near_nnz * 12 + (N + 1) * 8 + 2 * N * 8
+    matvec_bytes = coupling_bytes + near_bytes
+    print(f"bench: matvec {ms*1e3:.1f} us; stages fwd+up {stage_ms[0]*1e3:.1f} coupling {stage_ms[1]*1e3:.1f} "
+          f"down {stage_ms[2]*1e3:.1f} back+near {stage_ms[3]*1e3:.1f} us; coupling {achieved:.0f} GB/s; "
+          f"matvec {matvec_bytes/(ms*1e-3)/1e9:.0f} GB/s", file=sys.stderr, flush=True)
+
+    extra = {}
+    if not args.no_gmres:
+        x0 = cfg["x0"]
+        b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho, stats = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"])
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        it, ok, rr = stats[0]
+        _, pts = W.c1_inputs()
+        u = s.potential(pts, rho[0]).cpu().numpy()
+        ex = 1.0 / (4 * np.pi * np.linalg.norm(pts - np.array(x0), axis=1))
+        perr = float(np.max(np.abs(u - ex)) / np.max(np.abs(ex)))
+        extra["gmres"] = {"time_to_tol_s": t_solve, "iterations": it, "converged": ok, "relres": rr,
+                          "tol": cfg["tol"], "restart": cfg["restart"], "potential_max_rel_err": perr}
+        print(f"bench: GMRES {it} its {t_solve:.3f}s relres {rr:.2e} potential err {perr:.2e}", file=sys.stderr,
+              flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(cfg, x_host, args.cpu_rows)
+        print(f"bench: cpu baseline {cpu['value']:.3e} DOF/s ({time.perf_counter()-t0:.1f}s)", file=sys.stderr,
+              flush=True)
+
+    out = {
+        "metric": "H2 matvec DOF/s + GMRES time-to-1e-8, mixed/learned vs FP64 plain, 1 GPU",
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "ndof": N, "level": cfg["level"], "degree": cfg["degree"],
+                   "q": cfg["q"], "eta": cfg["eta"], "leaf_level": cfg["leaf"], "nfar": info.nfar,
+                   "near_nnz": info.near_nnz, "nrhs": 1},
+        "roofline": {"bound": "hbm", "kernel": "k_coupling (far-field coupling)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": coupling_bytes, "avg_ms": stage_ms[1]},
+        "stages_us": {"fwd_up": stage_ms[0] * 1e3, "coupling": stage_ms[1] * 1e3, "down": stage_ms[2] * 1e3,
+                      "back_near": stage_ms[3] * 1e3},
+        "matvec_gbs": matvec_bytes / (ms * 1e-3) / 1e9,
+        "assembly_s": t_asm,
+        "plan_s": t_plan,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * bem.h -- C ABI of libbem_hip.so, the MI355X (gfx950) implementation of the hot path of the
+ * isogeometric Galerkin boundary element method of Bembel (arXiv 1906.00785): assembling
+ * and applying the Laplace and Helmholtz single-layer operators on multi-patch surfaces,
+ * compressed as an interpolation-based H^2 matrix, and solving with restarted GMRES.
+ *
+ * The calls follow the paper's problem statement and API (Sec. 4): geometry (Sec. 4
+ * "Geometry", App. D) + PDE (Sec. 4 "PDE", App. B) + discrete space of level L and degree
+ * (Sec. 4 "Discretization", App. E) -> load vector (Sec. 4 "Boundary Values") -> compressed
+ * system matrix (Sec. 4 "System Matrix", Sec. 2) -> H*x -> GMRES (Sec. 4 "Solution of the
+ * System of Linear Equations") -> potential (Sec. 4 "Evaluation of the Solution").
+ *
+ * Conventions shared by every call
+ *  - Return value: BEM_OK (0) or a negative BEM_E* code.  No C++ exception crosses the ABI.
+ *    bem_last_error() returns a thread-local message describing the last failure.
+ *  - Handles (bem_geometry, bem_space, bem_operator) are created and destroyed by the
+ *    library.  Destroying NULL is a no-op.  A space keeps its geometry alive by copy; an
+ *    operator refers to its space, which must outlive it.
+ *  - Device buffers are raw device pointers owned by the caller (e.g. torch tensors);
+ *    every call that takes a hipStream_t enqueues its device work on that stream and
+ *    returns without synchronising unless stated otherwise.
+ *  - Scalars are double for Laplace and interleaved (re, im) double pairs for Helmholtz
+ *    (std::complex<double> / torch.complex128 layout).
+ *  - Vectors over the degrees of freedom (DOFs) use the global index
+ *        g = (patch * n1 + j1) * n1 + j2,   n1 = d + 1 + (2^L - 1) * knot_repetition,
+ *    where j1, j2 index the B-splines along the two parameter directions of the patch.
+ *    Elements are numbered e = (patch * 2^L + i1) * 2^L + i2.
+ *  - Several right-hand sides are stored column-major, N x nrhs, with a leading dimension.
+ *  - The operator's device memory is a caller-provided workspace whose size is returned by
+ *    bem_assemble_plan; calls on one operator that overlap in time (on different streams)
+ *    race on its internal matvec buffers.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BEM_OK 0
+#define BEM_EINVAL (-1)       /* invalid argument (message says which) */
+#define BEM_ENOMEM (-2)       /* workspace too small or host allocation failed */
+#define BEM_EDEVICE (-3)      /* a HIP call failed */
+#define BEM_ENOCONV (-4)      /* solver did not reach the tolerance; best iterate written */
+#define BEM_EUNSUPPORTED (-5) /* valid request this build does not implement */
+
+/* PDEs of Sec. 4 "PDE": single-layer kernels (LS) 1/(4 pi r) and (HS) exp(-i kappa r)/(4 pi r) */
+#define BEM_LAPLACE_SINGLE 0
+#define BEM_HELMHOLTZ_SINGLE 1
+
+/* analytic multi-patch geometries (App. D; arbitrary smooth maps are allowed, Sec. 4):
+ *   SPHERE6     unit sphere, 6 cube faces projected radially               params: none
+ *   ELLIPSOID6  diag(a,b,c) applied to SPHERE6                             params: a, b, c
+ *   TORUS16     torus of radii R > r, 16 patches of a quarter turn each    params: R, r
+ *   FLAT1       one flat square patch [0,a]^2 x {0} (open surface; tests) params: a        */
+#define BEM_GEOM_SPHERE6 0
+#define BEM_GEOM_ELLIPSOID6 1
+#define BEM_GEOM_TORUS16 2
+#define BEM_GEOM_FLAT1 3
+
+/* boundary data for bem_rhs (Sec. 4 "Boundary Values"):
+ *   POINT_SOURCE  g(x) = k(x, x0), the PDE's own kernel centred at x0       params: x0 (3)
+ *   PLANE_WAVE    g(x) = exp(-i kappa d.x), Helmholtz only                  params: d (3)  */
+#define BEM_DATA_POINT_SOURCE 0
+#define BEM_DATA_PLANE_WAVE 1
+
+typedef struct bem_geometry_s* bem_geometry;
+typedef struct bem_space_s* bem_space;
+typedef struct bem_operator_s* bem_operator;
+
+/* Parameters of the compressed system matrix (Sec. 4 "System Matrix": a discretisation
+ * plus the polynomial degree of the H^2 compression; Sec. 2: singular quadrature by
+ * regularisation, embedded FMM on the reference square). */
+typedef struct bem_h2_params {
+    int q;            /* Chebyshev points per direction of each cluster (degree q-1), >= 1 */
+    double eta;       /* admissibility: 2 max(r_t, r_s) <= eta * dist(balls); 0 = dense   */
+    int leaf_level;   /* cluster-tree leaf level, 0..L; -1 picks max(L-2, 0)             */
+    int qg;           /* Gauss points per direction on each element of a regular pair   */
+    int qs;           /* Gauss points per dimension of each Duffy cube (touching pairs)  */
+    int reserved[4];  /* must be zero */
+} bem_h2_params;
+
+/* Sizes and counts of an operator, filled by bem_assemble_plan. */
+typedef struct bem_operator_info {
+    int64_t ndof;            /* rows = cols = N */
+    int64_t nclusters;       /* clusters of all levels 0..leaf */
+    int64_t nfar;            /* admissible (far) cluster pairs, both orientations */
+    int64_t nnear;           /* near leaf pairs */
+    int64_t ntouch;          /* touching element pairs (singular quadrature) */
+    int64_t near_nnz;        /* non-zeros of the near field in the B-spline basis */
+    int64_t leaf_level;      /* leaf level actually used */
+    size_t op_bytes;         /* persistent device workspace for bem_assemble */
+    size_t tmp_bytes;        /* temporary device workspace, free after bem_assemble */
+    double far_bytes;        /* bytes of stored coupling blocks */
+    double near_bytes;       /* bytes of near-field values + column indices */
+} bem_operator_info;
+
+/* GMRES(m) parameters (reading: restart 30, x0 = 0, relative residual tolerance). */
+typedef struct bem_solve_params {
+    int restart;      /* Krylov dimension m per cycle, >= 1 */
+    int maxit;        /* total Arnoldi steps over all cycles, >= 1 */
+    double tol;       /* stop when ||b - A x|| <= tol ||b|| (true residual, checked) */
+    int reserved[4];  /* must be zero */
+} bem_solve_params;
+
+/* per-RHS solver statistics */
+typedef struct bem_solve_stats {
+    int iterations;       /* Arnoldi steps taken */
+    int converged;        /* 1 if the true relative residual is <= tol */
+    double relres;        /* true relative residual ||b - A x|| / ||b|| at exit */
+} bem_solve_stats;
+
+/* Message of the last failed call on this thread (never NULL). */
+const char* bem_last_error(void);
+
+/* Analytic geometry (Sec. 4 "Geometry"; App. D multi-patch boundary representation with
+ * outward normals and matching parametrisations on shared edges).
+ * kind: BEM_GEOM_*; params/nparams as listed above (host array).  -> *out. */
+int bem_geometry_analytic(int kind, const double* params, int nparams, bem_geometry* out);
+void bem_geometry_destroy(bem_geometry g);
+
+/* Discrete space (Sec. 4 "Discretization"; App. E): the spline space S^2 of tensor
+ * B-splines of degree `degree` over 2^level equal elements per direction on every patch,
+ * interior knots repeated `knot_repetition` times (1 <= knot_repetition <= degree + 1),
+ * lifted to the surface by the Piola transform, for the PDE `kernel`
+ * (BEM_LAPLACE_SINGLE or BEM_HELMHOLTZ_SINGLE with wavenumber kappa_re + i kappa_im != 0;
+ * non-resonance is assumed, Sec. 2).  EINVAL on degree < 0, level < 0 or > 12, bad knot
+ * repetition, or kappa = 0 for Helmholtz.  The geometry may be destroyed afterwards. */
+int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
+                     int knot_repetition, int level, bem_space* out);
+int bem_space_ndof(bem_space s, int64_t* n);
+void bem_space_destroy(bem_space s);
+
+/* Load vectors (Sec. 4 "Boundary Values"): b_g = int_Gamma g psi_g for nrhs data sets.
+ * data_params: host array of 3 doubles per RHS.  b_dev: device, N x nrhs column-major with
+ * leading dimension ldb >= N, written (not accumulated).  Gauss with 8 points per direction
+ * per element.  EINVAL on PLANE_WAVE for Laplace. */
+int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, void* b_dev,
+            int64_t ldb, hipStream_t stream);
+
+/* Host plan of the compressed system matrix (Sec. 4 "System Matrix"): cluster tree on the
+ * patches' parameter squares, block partition into admissible (far) cluster pairs and
+ * near leaf pairs, near-field sparsity pattern, touching element pairs.  Creates *out (no
+ * device memory yet) and fills *info with counts and workspace sizes.  Host work only. */
+int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out,
+                      bem_operator_info* info);
+
+/* Assembles the operator on the device (near-field Galerkin quadrature with Duffy rules
+ * for touching pairs, coupling blocks at Chebyshev nodes, moment and transfer tables).
+ * op_ws: device workspace of >= info.op_bytes bytes, owned by the caller and used by the
+ * operator until it is destroyed.  tmp_ws: device workspace of >= info.tmp_bytes bytes,
+ * free again once the stream has passed this call.  ENOMEM if a size is too small. */
+int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, size_t tmp_bytes,
+                 hipStream_t stream);
+
+int bem_operator_info_get(bem_operator A, bem_operator_info* info);
+
+/* rows() and cols() of the system matrix (Sec. 4 "System Matrix"). */
+int bem_operator_dims(bem_operator A, int64_t* rows, int64_t* cols);
+
+/* y = A x, the GEMV H*x of Sec. 4 "System Matrix": forward transform to leaf moments,
+ * upward transfer, far-field coupling, downward transfer, backward transform, plus the
+ * near-field product.  x_dev, y_dev: device, N x nrhs column-major, leading dimensions
+ * ldx, ldy >= N, must not overlap.  y is overwritten.  nrhs >= 1. */
+int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy, int nrhs,
+              hipStream_t stream);
+
+/* Device workspace bytes bem_solve needs for nrhs right-hand sides. */
+int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes);
+
+/* Restarted GMRES(m) on A (Sec. 4 "Solution of the System of Linear Equations"), x0 = 0,
+ * classical Gram-Schmidt with reorthogonalisation, Givens rotations, stop on the true
+ * relative residual.  b_dev, x_dev: device N x nrhs column-major; x is overwritten with the
+ * best iterate.  stats: host array of nrhs entries.  ws: device workspace of >= the bytes
+ * from bem_solve_plan.  Synchronises the stream.  Returns ENOCONV (stats and x still
+ * written) if some right-hand side misses the tolerance within maxit steps. */
+int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64_t ldx, int nrhs,
+              const bem_solve_params* p, bem_solve_stats* stats, void* ws, size_t ws_bytes,
+              hipStream_t stream);
+
+/* Potential u(x) = int_Gamma k(x, y) rho(y) dsigma_y at npts points (Sec. 4 "Evaluation of
+ * the Solution"; App. B (LS)/(HS)), Gauss with 8 points per direction per element.
+ * pts_dev: device, npts x 3 row-major.  rho_dev: device N x nrhs (leading dim ldr).
+ * u_dev: device npts x nrhs column-major (leading dim ldu >= npts), overwritten. */
+int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev,
+                       int64_t ldr, int nrhs, void* u_dev, int64_t ldu, hipStream_t stream);
+
+/* Stage timing of bem_apply (tracing).  While enabled (on != 0), every bem_apply records
+ * HIP events on its stream around its four stages: 0 forward transform + upward transfer,
+ * 1 far-field coupling, 2 downward transfer, 3 backward transform + near-field product.
+ * Enabling or disabling clears the record.  bem_profile_read waits for the last recorded
+ * event, writes the mean milliseconds of each stage over the recorded applies into
+ * stage_ms[0..3] (nstages >= 4), their number into *napplies, and clears the record. */
+int bem_profile_enable(bem_operator A, int on);
+int bem_profile_read(bem_operator A, double* stage_ms, int nstages, int* napplies);
+
+/* Destroys the operator (its workspace stays with the caller). */
+void bem_operator_destroy(bem_operator A);
+
+/* ---- introspection for parity checks (host copies; each synchronises the stream) ----- */
+
+/* Near field in CSR form: rowptr (N+1, int64), col (nnz, int32), val (nnz scalars).
+ * Any pointer may be NULL to skip it; the pattern is available right after
+ * bem_assemble_plan, the values only after bem_assemble. */
+int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, hipStream_t stream);
+
+/* Far list as (target, source) cluster index pairs (int64, 2 per block), cluster index =
+ * level offset + (patch * 2^level + i) * 2^level + j, and the q^2 x q^2 coupling block of
+ * each pair (row-major, target node index a = a1*q + a2), in the order of the list.
+ * Either pointer may be NULL; the list is available right after bem_assemble_plan. */
+int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t stream);
+
+/* Moments of all clusters (nclusters x q^2 per RHS column) after forward + upward
+ * transfer of x (1 RHS). */
+int bem_export_moments(bem_operator A, const void* x_dev, double* mom_host, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEM_H */

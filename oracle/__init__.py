@@ -76,6 +76,7 @@ def lib():
             "orc_h2_apply": (I, [P, P, P, I]),
             "orc_h2_apply_rows": (I, [P, P, P, I64, I, P]),
             "orc_h2_gmres": (I, [P, P, P, D, I, I, P]),
+            "orc_h2_near_rows": (I, [P, P, I64]),
             "orc_dense_gmres": (I, [I64, I, P, P, P, D, I, I, P]),
         }
         for name, (res, args) in sig.items():
@@ -133,7 +134,10 @@ class Space:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().orc_space_free(self._h)
+            try:
+                lib().orc_space_free(self._h)
+            except Exception:
+                pass
             self._h = None
 
     @property
@@ -211,7 +215,10 @@ class H2:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().orc_h2_free(self._h)
+            try:
+                lib().orc_h2_free(self._h)
+            except Exception:
+                pass
             self._h = None
 
     def lists(self):
@@ -265,6 +272,11 @@ class H2:
         parts = (1 if far else 0) | (2 if near else 0)
         _check(lib().orc_h2_apply_rows(self._h, _p(x), _p(rows), rows.size, parts, _p(y)))
         return y
+
+    def assemble_near_rows(self, rows):
+        """Assemble and keep the near-field rows of a subset of DOFs (lazy operators)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        _check(lib().orc_h2_near_rows(self._h, _p(rows), rows.size))
 
     def gmres(self, b, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
         b = np.ascontiguousarray(b, dtype=self.space.dtype)

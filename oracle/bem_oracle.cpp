@@ -1056,6 +1056,46 @@ static T h2_backward_dof(const H2<T>& H, const std::vector<T>& lv, int64_t g) {
     return acc;
 }
 
+// near-field rows for a subset of DOFs only (the rest stays empty); used to time the
+// near-field product on a sample of rows of a problem whose full near field is too costly
+template <class T>
+static void h2_near_rows_subset(H2<T>& H, const int64_t* rows, int64_t nrows) {
+    const Space& S = *H.S;
+    H.near_rows.assign(S.ndof, std::map<int64_t, T>());
+    SideFn F;
+    const int nb = side_nb(S, F);
+    const int d = S.K.d, nbs = S.K.nb, nel = S.K.nel;
+    const int m = 1 << (S.K.L - H.leaf);
+    std::vector<T> Bk(nb * nb);
+    std::vector<int64_t> es;
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t g = rows[r];
+        const int f = (int)(g / ((int64_t)nbs * nbs));
+        const int j1 = (int)((g / nbs) % nbs), j2 = (int)(g % nbs);
+        for (int i1 = 0; i1 < nel; ++i1) {
+            const int l1 = j1 - elem_first_basis(S.K, i1);
+            if (l1 < 0 || l1 > d) continue;
+            for (int i2 = 0; i2 < nel; ++i2) {
+                const int l2 = j2 - elem_first_basis(S.K, i2);
+                if (l2 < 0 || l2 > d) continue;
+                const int64_t e1 = ((int64_t)f * nel + i1) * nel + i2;
+                const int64_t tl = H.cluster_index(H.leaf, f, i1 / m, i2 / m);
+                auto lo = std::lower_bound(H.near.begin(), H.near.end(), std::make_pair(tl, (int64_t)-1));
+                for (auto it = lo; it != H.near.end() && it->first == tl; ++it) {
+                    leaf_elements(H, it->second, es);
+                    for (int64_t e2 : es) {
+                        const Elem E2 = elem_of(S, e2);
+                        pair_block<T>(S, F, F, e1, e2, H.qg, H.qs, Bk.data());
+                        const int il = l1 * (d + 1) + l2;
+                        for (int j = 0; j < nb; ++j) H.near_rows[g][local_dof(S, E2, j)] += Bk[il * nb + j];
+                    }
+                }
+            }
+        }
+    }
+    H.have_near = true;
+}
+
 // far-field part of y = A x for all DOFs (forward, upward, coupling, downward, backward)
 template <class T>
 static void h2_far_apply(const H2<T>& H, const T* x, std::vector<T>& lv) {
@@ -1098,7 +1138,9 @@ static void h2_apply_rows(const H2<T>& H, const T* x, const int64_t* rows, int64
     for (int64_t r = 0; r < nrows; ++r) {
         const int64_t g = rows[r];
         T acc = far_part ? h2_backward_dof(H, lv, g) : T(0);
-        if (near_part) {
+        if (near_part && H.have_near) {
+            for (const auto& kv : H.near_rows[g]) acc += kv.second * x[kv.first];
+        } else if (near_part) {
             const int f = (int)(g / ((int64_t)nbs * nbs));
             const int j1 = (int)((g / nbs) % nbs), j2 = (int)(g % nbs);
             // elements whose local basis contains g
@@ -1589,6 +1631,17 @@ int orc_h2_apply_rows(void* hp, const double* x, const int64_t* rows, int64_t nr
             h2_apply_rows(h->hc, (const cplx*)x, rows, nrows, (cplx*)y, parts & 1, parts & 2);
         else
             h2_apply_rows(h->hr, x, rows, nrows, y, parts & 1, parts & 2);
+    })
+}
+
+// assemble (and keep) the near-field rows of a subset of DOFs; apply_rows then uses them
+int orc_h2_near_rows(void* hp, const int64_t* rows, int64_t nrows) {
+    ORC_TRY({
+        OrcH2* h = (OrcH2*)hp;
+        if (h->cplx_)
+            h2_near_rows_subset(h->hc, rows, nrows);
+        else
+            h2_near_rows_subset(h->hr, rows, nrows);
     })
 }
 

@@ -1,0 +1,163 @@
+"""MI355X (gfx950) hot path of the isogeometric Galerkin BEM of Bembel (arXiv 1906.00785).
+
+Thin object layer over the C ABI (include/bem.h, libbem_hip.so).  Torch provides device
+memory and the stream; every numerical step runs in the library's HIP kernels.
+
+    geom = Geometry(BEM_GEOM_SPHERE6)
+    space = Space(geom, BEM_LAPLACE_SINGLE, 0.0, degree=2, level=6)
+    A = Operator(space, q=5, eta=1.6, leaf_level=4)        # plan + assemble on the GPU
+    b = space.rhs(BEM_DATA_POINT_SOURCE, [(0.1, -0.2, 0.15)])
+    rho, stats = A.solve(b, tol=1e-8)
+    u = space.potential(points, rho)
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _bem as C
+from ._bem import (BEM_DATA_PLANE_WAVE, BEM_DATA_POINT_SOURCE, BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1,
+                   BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16, BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BemError)
+
+__all__ = ["Geometry", "Space", "Operator", "BemError", "BEM_GEOM_SPHERE6", "BEM_GEOM_ELLIPSOID6",
+           "BEM_GEOM_TORUS16", "BEM_GEOM_FLAT1", "BEM_LAPLACE_SINGLE", "BEM_HELMHOLTZ_SINGLE",
+           "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE"]
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev() -> torch.device:
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the BEM path runs only on the GPU")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+class Geometry:
+    def __init__(self, kind: int, params=()):
+        self.kind, self.params = kind, tuple(params)
+        self.h = C.bem_geometry_analytic(kind, self.params)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                C.bem_geometry_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+
+class Space:
+    def __init__(self, geom: Geometry, kernel: int = BEM_LAPLACE_SINGLE, kappa: complex = 0.0, degree: int = 1,
+                 knot_repetition: int = 1, level: int = 0):
+        self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level)
+        self.kernel, self.kappa, self.degree, self.level = kernel, complex(kappa), degree, level
+        self.ndof = C.bem_space_ndof(self.h)
+        self.dtype = torch.complex128 if kernel == BEM_HELMHOLTZ_SINGLE else torch.float64
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                C.bem_space_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def rhs(self, data_kind: int, params) -> torch.Tensor:
+        """Load vectors, one per row of params (3 numbers each): tensor (nrhs, N)."""
+        params = [tuple(float(v) for v in p) for p in params]
+        b = torch.empty((len(params), self.ndof), dtype=self.dtype, device=_dev())
+        C.bem_rhs(self.h, data_kind, params, len(params), b.data_ptr(), self.ndof, _stream())
+        return b
+
+    def potential(self, pts, rho: torch.Tensor) -> torch.Tensor:
+        """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,)."""
+        pts = torch.as_tensor(np.asarray(pts, dtype=np.float64)).to(_dev()).contiguous()
+        r = rho.reshape(-1, self.ndof).contiguous()
+        u = torch.empty((r.shape[0], pts.shape[0]), dtype=self.dtype, device=_dev())
+        C.bem_eval_potential(self.h, pts.data_ptr(), pts.shape[0], r.data_ptr(), self.ndof, r.shape[0], u.data_ptr(),
+                             pts.shape[0], _stream())
+        return u.reshape(rho.shape[:-1] + (pts.shape[0],)) if rho.dim() == 1 else u
+
+
+class Operator:
+    """Compressed single-layer operator: plan on the host, assemble on the GPU."""
+
+    def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
+                 assemble: bool = True):
+        self.space = space
+        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs)
+        self.q = q
+        self.ndof = self.info.ndof
+        self.op_ws = None
+        if assemble:
+            self.assemble()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                C.bem_operator_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def assemble(self):
+        dev = _dev()
+        self.op_ws = torch.empty(self.info.op_bytes, dtype=torch.uint8, device=dev)
+        tmp = torch.empty(self.info.tmp_bytes, dtype=torch.uint8, device=dev)
+        C.bem_assemble(self.h, self.op_ws.data_ptr(), self.info.op_bytes, tmp.data_ptr(), self.info.tmp_bytes,
+                       _stream())
+        torch.cuda.current_stream().synchronize()
+        del tmp
+
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = A x for x of shape (N,) or (nrhs, N)."""
+        xx = x.reshape(-1, self.ndof).contiguous()
+        y = out if out is not None else torch.empty_like(xx)
+        C.bem_apply(self.h, xx.data_ptr(), self.ndof, y.data_ptr(), self.ndof, xx.shape[0], _stream())
+        return y.reshape(x.shape)
+
+    def solve(self, b: torch.Tensor, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
+        """GMRES(restart); returns (x, [(iterations, converged, relres)] per RHS)."""
+        bb = b.reshape(-1, self.ndof).contiguous()
+        x = torch.empty_like(bb)
+        nbytes = C.bem_solve_plan(self.h, bb.shape[0], restart, maxit, tol)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=bb.device)
+        _, stats = C.bem_solve(self.h, bb.data_ptr(), self.ndof, x.data_ptr(), self.ndof, bb.shape[0], restart, maxit,
+                               tol, ws.data_ptr(), nbytes, _stream())
+        return x.reshape(b.shape), stats
+
+    def profile(self, on: bool):
+        """Enable/disable HIP-event timing of the four apply stages."""
+        C.bem_profile_enable(self.h, on)
+
+    def profile_read(self):
+        """(mean ms per stage [fwd+up, coupling, down, back+near], number of applies)."""
+        return C.bem_profile_read(self.h)
+
+    # ---- parity exports
+    def export_near(self):
+        n = self.ndof
+        rowptr = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(self.info.near_nnz, dtype=np.int32)
+        npdt = np.complex128 if self.space.dtype == torch.complex128 else np.float64
+        val = np.zeros(self.info.near_nnz, dtype=npdt)
+        C.bem_export_near(self.h, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, _stream())
+        return rowptr, col, val
+
+    def export_far(self):
+        q2 = self.q * self.q
+        pairs = np.zeros((self.info.nfar, 2), dtype=np.int64)
+        npdt = np.complex128 if self.space.dtype == torch.complex128 else np.float64
+        blocks = np.zeros((self.info.nfar, q2, q2), dtype=npdt)
+        C.bem_export_far(self.h, pairs.ctypes.data, blocks.ctypes.data, _stream())
+        return pairs, blocks
+
+    def moments(self, x: torch.Tensor) -> np.ndarray:
+        q2 = self.q * self.q
+        npdt = np.complex128 if self.space.dtype == torch.complex128 else np.float64
+        m = np.zeros((self.info.nclusters, q2), dtype=npdt)
+        xx = x.contiguous()
+        C.bem_export_moments(self.h, xx.data_ptr(), m.ctypes.data, _stream())
+        return m

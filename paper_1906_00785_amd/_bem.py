@@ -1,0 +1,214 @@
+"""ctypes binding of libbem_hip.so (include/bem.h): the same entry points, argument
+marshalling only.  Every step of the computation runs in the library's HIP kernels; if the
+library is missing this module raises at import, there is no fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbem_hip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bem.h")
+
+BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
+BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1 = 0, 1, 2, 3
+BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
+
+_c_int, _c_dbl, _c_i64, _c_sz, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+
+
+class bem_h2_params(ctypes.Structure):
+    _fields_ = [("q", _c_int), ("eta", _c_dbl), ("leaf_level", _c_int), ("qg", _c_int), ("qs", _c_int),
+                ("reserved", _c_int * 4)]
+
+
+class bem_operator_info(ctypes.Structure):
+    _fields_ = [("ndof", _c_i64), ("nclusters", _c_i64), ("nfar", _c_i64), ("nnear", _c_i64), ("ntouch", _c_i64),
+                ("near_nnz", _c_i64), ("leaf_level", _c_i64), ("op_bytes", _c_sz), ("tmp_bytes", _c_sz),
+                ("far_bytes", _c_dbl), ("near_bytes", _c_dbl)]
+
+
+class bem_solve_params(ctypes.Structure):
+    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("tol", _c_dbl), ("reserved", _c_int * 4)]
+
+
+class bem_solve_stats(ctypes.Structure):
+    _fields_ = [("iterations", _c_int), ("converged", _c_int), ("relres", _c_dbl)]
+
+
+class BemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bem error {code}: {msg}")
+        self.code = code
+
+
+_P = ctypes.POINTER
+_SIGNATURES = {
+    "bem_last_error": (ctypes.c_char_p, []),
+    "bem_geometry_analytic": (_c_int, [_c_int, _P(_c_dbl), _c_int, _P(_vp)]),
+    "bem_geometry_destroy": (None, [_vp]),
+    "bem_space_create": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _P(_vp)]),
+    "bem_space_ndof": (_c_int, [_vp, _P(_c_i64)]),
+    "bem_space_destroy": (None, [_vp]),
+    "bem_rhs": (_c_int, [_vp, _c_int, _P(_c_dbl), _c_int, _vp, _c_i64, _vp]),
+    "bem_assemble_plan": (_c_int, [_vp, _P(bem_h2_params), _P(_vp), _P(bem_operator_info)]),
+    "bem_assemble": (_c_int, [_vp, _vp, _c_sz, _vp, _c_sz, _vp]),
+    "bem_operator_info_get": (_c_int, [_vp, _P(bem_operator_info)]),
+    "bem_operator_dims": (_c_int, [_vp, _P(_c_i64), _P(_c_i64)]),
+    "bem_apply": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _vp]),
+    "bem_solve_plan": (_c_int, [_vp, _c_int, _P(bem_solve_params), _P(_c_sz)]),
+    "bem_solve": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _P(bem_solve_params), _P(bem_solve_stats), _vp,
+                           _c_sz, _vp]),
+    "bem_eval_potential": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _vp, _c_i64, _vp]),
+    "bem_operator_destroy": (None, [_vp]),
+    "bem_profile_enable": (_c_int, [_vp, _c_int]),
+    "bem_profile_read": (_c_int, [_vp, _P(_c_dbl), _c_int, _P(_c_int)]),
+    "bem_export_near": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "bem_export_far": (_c_int, [_vp, _vp, _vp, _vp]),
+    "bem_export_moments": (_c_int, [_vp, _vp, _vp, _vp]),
+}
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/bem.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bem_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(rc: int):
+    if rc != BEM_OK:
+        raise BemError(rc, lib.bem_last_error().decode())
+
+
+def _dbl_array(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+# ----------------------------------------------------------------------------- entry points
+def bem_geometry_analytic(kind: int, params=()) -> int:
+    h = _vp()
+    check(lib.bem_geometry_analytic(kind, _dbl_array(params), len(params), ctypes.byref(h)))
+    return h.value
+
+
+def bem_geometry_destroy(g: int):
+    lib.bem_geometry_destroy(g)
+
+
+def bem_space_create(g: int, kernel: int, kappa: complex, degree: int, knot_repetition: int, level: int) -> int:
+    h = _vp()
+    kappa = complex(kappa)
+    check(lib.bem_space_create(g, kernel, kappa.real, kappa.imag, degree, knot_repetition, level, ctypes.byref(h)))
+    return h.value
+
+
+def bem_space_ndof(s: int) -> int:
+    n = _c_i64()
+    check(lib.bem_space_ndof(s, ctypes.byref(n)))
+    return n.value
+
+
+def bem_space_destroy(s: int):
+    lib.bem_space_destroy(s)
+
+
+def bem_rhs(s: int, data_kind: int, data_params, nrhs: int, b_ptr: int, ldb: int, stream: int):
+    flat = [float(v) for row in data_params for v in row]
+    check(lib.bem_rhs(s, data_kind, _dbl_array(flat), nrhs, b_ptr, ldb, stream))
+
+
+def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int):
+    p = bem_h2_params(q, eta, leaf_level, qg, qs, (_c_int * 4)(0, 0, 0, 0))
+    h = _vp()
+    info = bem_operator_info()
+    check(lib.bem_assemble_plan(s, ctypes.byref(p), ctypes.byref(h), ctypes.byref(info)))
+    return h.value, info
+
+
+def bem_assemble(A: int, op_ptr: int, op_bytes: int, tmp_ptr: int, tmp_bytes: int, stream: int):
+    check(lib.bem_assemble(A, op_ptr, op_bytes, tmp_ptr, tmp_bytes, stream))
+
+
+def bem_operator_info_get(A: int) -> bem_operator_info:
+    info = bem_operator_info()
+    check(lib.bem_operator_info_get(A, ctypes.byref(info)))
+    return info
+
+
+def bem_operator_dims(A: int):
+    r, c = _c_i64(), _c_i64()
+    check(lib.bem_operator_dims(A, ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
+
+
+def bem_apply(A: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, stream: int):
+    check(lib.bem_apply(A, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
+
+
+def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float) -> int:
+    p = bem_solve_params(restart, maxit, tol, (_c_int * 4)(0, 0, 0, 0))
+    n = _c_sz()
+    check(lib.bem_solve_plan(A, nrhs, ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def bem_solve(A: int, b_ptr: int, ldb: int, x_ptr: int, ldx: int, nrhs: int, restart: int, maxit: int, tol: float,
+              ws_ptr: int, ws_bytes: int, stream: int):
+    """Returns (rc, stats list); rc is BEM_OK or BEM_ENOCONV (other codes raise)."""
+    p = bem_solve_params(restart, maxit, tol, (_c_int * 4)(0, 0, 0, 0))
+    st = (bem_solve_stats * nrhs)()
+    rc = lib.bem_solve(A, b_ptr, ldb, x_ptr, ldx, nrhs, ctypes.byref(p), st, ws_ptr, ws_bytes, stream)
+    if rc not in (BEM_OK, BEM_ENOCONV):
+        check(rc)
+    return rc, [(s.iterations, bool(s.converged), s.relres) for s in st]
+
+
+def bem_eval_potential(s: int, pts_ptr: int, npts: int, rho_ptr: int, ldr: int, nrhs: int, u_ptr: int, ldu: int,
+                       stream: int):
+    check(lib.bem_eval_potential(s, pts_ptr, npts, rho_ptr, ldr, nrhs, u_ptr, ldu, stream))
+
+
+def bem_operator_destroy(A: int):
+    lib.bem_operator_destroy(A)
+
+
+def bem_profile_enable(A: int, on: bool):
+    check(lib.bem_profile_enable(A, int(bool(on))))
+
+
+def bem_profile_read(A: int):
+    """Mean milliseconds of the 4 apply stages and the number of recorded applies."""
+    ms = (ctypes.c_double * 4)()
+    n = _c_int()
+    check(lib.bem_profile_read(A, ms, 4, ctypes.byref(n)))
+    return list(ms), n.value
+
+
+def bem_export_near(A: int, rowptr_ptr: int, col_ptr: int, val_ptr: int, stream: int):
+    check(lib.bem_export_near(A, rowptr_ptr, col_ptr, val_ptr, stream))
+
+
+def bem_export_far(A: int, pairs_ptr: int, blocks_ptr: int, stream: int):
+    check(lib.bem_export_far(A, pairs_ptr, blocks_ptr, stream))
+
+
+def bem_export_moments(A: int, x_ptr: int, mom_ptr: int, stream: int):
+    check(lib.bem_export_moments(A, x_ptr, mom_ptr, stream))

@@ -1,0 +1,671 @@
+// C ABI of libbem_hip.so (declared in include/bem.h): handles, workspace layout, the
+// assembly and matvec drivers, GMRES and the parity exports.
+#include "../../include/bem.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bem_kernels.h"
+#include "bem_plan.h"
+
+using namespace bem;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_CHECK(expr)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(BEM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+// bump allocator over a caller workspace (base == nullptr: size computation only)
+struct Bump {
+    char* base;
+    size_t off = 0;
+    explicit Bump(void* b) : base((char*)b) {}
+    template <class X>
+    X* take(size_t n) {
+        off = (off + 255) / 256 * 256;
+        X* p = base ? (X*)(base + off) : nullptr;
+        off += n * sizeof(X);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct bem_geometry_s {
+    GeomDesc g;
+};
+
+struct bem_space_s {
+    SpaceDesc S;
+    BasisTab bt;
+};
+
+struct bem_operator_s {
+    bem_space_s* sp = nullptr;
+    Plan plan;
+    bool cplx = false;
+    bool assembled = false;
+    bem_operator_info info{};
+    std::vector<int32_t> touch_lp;
+    OpDev dev{};
+    size_t scal = 8;  // bytes per scalar
+    // stage timing of bem_apply (bem_profile_*)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // kApplyStages + 1 events per recorded apply
+    size_t ev_used = 0;
+    ~bem_operator_s() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
+    const Plan& p = A.plan;
+    Bump b(base);
+    OpDev o{};
+    o.lev_off = b.take<int64_t>(p.lev_off.size());
+    o.rowptr = b.take<int64_t>(p.rowptr.size());
+    o.col = b.take<int32_t>(p.col.size());
+    o.val = b.take<char>(p.col.size() * A.scal);
+    o.far_rowptr = b.take<int64_t>(p.far_rowptr.size());
+    o.far_s = b.take<int32_t>(p.far_s.size());
+    o.koff = b.take<int64_t>(p.koff.size());
+    o.krs = b.take<int32_t>(p.krs.size());
+    o.K = b.take<char>((size_t)p.ktotal * A.scal);
+    o.V1 = b.take<double>(p.V1.size());
+    o.E = b.take<double>(p.E.size());
+    o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+    o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+    if (d) *d = o;
+    return b.off + 256;
+}
+
+static size_t tmp_layout(const bem_operator_s& A, void* base, AsmDev* d) {
+    const Plan& p = A.plan;
+    const SpaceDesc& S = p.S;
+    Bump b(base);
+    AsmDev a{};
+    a.near_t = b.take<int32_t>(p.near_t.size());
+    a.near_s = b.take<int32_t>(p.near_s.size());
+    a.near_rowptr = b.take<int32_t>(p.near_rowptr.size());
+    a.touch_rowptr = b.take<int32_t>(p.touch_rowptr.size());
+    a.touch = b.take<int32_t>(p.touch.size());
+    a.touch_lp = b.take<int32_t>(A.touch_lp.size());
+    a.ntouch_lp = (int64_t)A.touch_lp.size();
+    a.vid = b.take<int32_t>(p.vid.size());
+    a.gx = b.take<double>(p.gx.size());
+    a.gw = b.take<double>(p.gw.size());
+    a.gpos = b.take<double>((size_t)S.nelem * p.P.qg * p.P.qg * 3);
+    a.psi = b.take<double>(p.psi.size());
+    a.sx = b.take<double>(p.sx.size());
+    a.sw = b.take<double>(p.sw.size());
+    a.cheb = b.take<double>(p.cheb.size());
+    a.far_t = b.take<int32_t>(p.far_t.size());
+    a.xc = b.take<double>((size_t)p.ncl * p.q2 * 3);
+    a.lb = b.take<char>((size_t)p.near_t.size() * p.nloc * p.nloc * p.nloc * p.nloc * A.scal);
+    if (d) *d = a;
+    return b.off + 256;
+}
+
+static bool make_basis_tab(const SpaceDesc& S, BasisTab& bt) {
+    std::vector<double> poly;
+    bspline_local_polys(S.d, S.r, S.L, poly);
+    const int d1 = S.d + 1;
+    std::memset(&bt, 0, sizeof(bt));
+    bt.d = S.d;
+    bt.nel = S.nel;
+    bt.w = d1;
+    bt.ncls = S.nel <= 2 * bt.w + 1 ? S.nel : 2 * bt.w + 1;
+    auto coef = [&](int i, int l, int k) { return poly[((size_t)i * d1 + l) * d1 + k]; };
+    std::vector<int> rep(bt.ncls, -1);
+    for (int i = 0; i < S.nel; ++i) {
+        const int c = basis_class(bt, i);
+        if (rep[c] < 0) {
+            rep[c] = i;
+            for (int l = 0; l < d1; ++l)
+                for (int k = 0; k < d1; ++k) bt.c[c][l][k] = coef(i, l, k);
+        } else {
+            for (int l = 0; l < d1; ++l)
+                for (int k = 0; k < d1; ++k)
+                    if (std::fabs(bt.c[c][l][k] - coef(i, l, k)) > 1e-12 * (1.0 + std::fabs(coef(i, l, k))))
+                        return false;
+        }
+    }
+    return true;
+}
+
+static Gauss8 gauss8() {
+    std::vector<double> x, w;
+    gauss_legendre01(8, x, w);
+    Gauss8 g;
+    for (int i = 0; i < 8; ++i) {
+        g.x[i] = x[i];
+        g.w[i] = w[i];
+    }
+    return g;
+}
+
+// ------------------------------------------------------------------------------ GMRES
+static inline double conj_h(double v) { return v; }
+static inline std::complex<double> conj_h(const std::complex<double>& v) { return std::conj(v); }
+
+static size_t solve_layout(int64_t N, int m, size_t sc, void* base, char** ptrs) {
+    Bump b(base);
+    ptrs[0] = b.take<char>((size_t)(m + 1) * N * sc);           // Krylov basis V
+    ptrs[1] = b.take<char>((size_t)N * sc);                     // w
+    ptrs[2] = b.take<char>((size_t)kDotBlocks * (m + 1) * sc);  // partial sums
+    ptrs[3] = b.take<char>((size_t)(m + 1) * sc);               // h, first pass
+    ptrs[4] = b.take<char>((size_t)(m + 1) * sc);               // h, second pass
+    ptrs[5] = b.take<char>((size_t)(m + 1) * sc);               // update coefficients
+    ptrs[6] = b.take<char>(2 * sizeof(double));                 // norms
+    return b.off + 256;
+}
+
+template <class H>
+static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* st,
+                     char** W, hipStream_t stream) {
+    const int64_t N = A->info.ndof;
+    const int m = p->restart;
+    const int cp = A->cplx ? 1 : 0;
+    const size_t sc = A->scal;
+    char* V = W[0];
+    char* w = W[1];
+    char* part = W[2];
+    char* hd1 = W[3];
+    char* hd2 = W[4];
+    char* yc = W[5];
+    double* nrm = (double*)W[6];
+    auto Vj = [&](int j) { return V + (size_t)j * N * sc; };
+    std::vector<H> Hm((size_t)(m + 1) * m), g(m + 1), sn(m), y(m), h1(m + 1), h2(m + 1);
+    std::vector<double> cs(m);
+    double hn = 0.0;
+    HIP_CHECK(hipMemsetAsync(x, 0, N * sc, stream));
+    HIP_CHECK(launch_norm(cp, N, b, part, nrm, stream));
+    double bnorm = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&bnorm, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    st->iterations = 0;
+    st->converged = 0;
+    st->relres = 0.0;
+    if (bnorm == 0.0) {
+        st->converged = 1;
+        return BEM_OK;
+    }
+    int total = 0;
+    double relres = 1.0;
+    for (;;) {
+        // true residual r = b - A x into w
+        HIP_CHECK(launch_apply(A->dev, x, w, stream));
+        HIP_CHECK(launch_axpby(cp, N, 1.0, b, -1.0, w, stream));
+        HIP_CHECK(launch_norm(cp, N, w, part, nrm, stream));
+        double beta = 0.0;
+        HIP_CHECK(hipMemcpyAsync(&beta, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        relres = beta / bnorm;
+        if (relres <= p->tol || total >= p->maxit || !std::isfinite(relres)) break;
+        HIP_CHECK(launch_scale(cp, N, w, nrm, Vj(0), stream));
+        std::fill(g.begin(), g.end(), H(0));
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && total < p->maxit; ++j) {
+            HIP_CHECK(launch_apply(A->dev, Vj(j), w, stream));
+            // classical Gram-Schmidt, twice
+            HIP_CHECK(launch_dots(cp, N, j + 1, V, N, w, part, hd1, stream));
+            HIP_CHECK(launch_update(cp, N, j + 1, V, N, hd1, -1.0, w, stream));
+            HIP_CHECK(launch_dots(cp, N, j + 1, V, N, w, part, hd2, stream));
+            HIP_CHECK(launch_update(cp, N, j + 1, V, N, hd2, -1.0, w, stream));
+            HIP_CHECK(launch_norm(cp, N, w, part, nrm, stream));
+            HIP_CHECK(launch_scale(cp, N, w, nrm, Vj(j + 1), stream));
+            HIP_CHECK(hipMemcpyAsync(h1.data(), hd1, (j + 1) * sc, hipMemcpyDeviceToHost, stream));
+            HIP_CHECK(hipMemcpyAsync(h2.data(), hd2, (j + 1) * sc, hipMemcpyDeviceToHost, stream));
+            HIP_CHECK(hipMemcpyAsync(&hn, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
+            HIP_CHECK(hipStreamSynchronize(stream));
+            for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h1[i] + h2[i];
+            Hm[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const H a = Hm[(size_t)i * m + j], c = Hm[(size_t)(i + 1) * m + j];
+                Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                Hm[(size_t)(i + 1) * m + j] = -conj_h(sn[i]) * a + cs[i] * c;
+            }
+            const H a = Hm[(size_t)j * m + j], c = Hm[(size_t)(j + 1) * m + j];
+            const double na = std::abs(a), nc = std::abs(c), nu = std::sqrt(na * na + nc * nc);
+            if (na == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = H(1);
+            } else {
+                cs[j] = na / nu;
+                sn[j] = (a / na) * conj_h(c) / nu;
+            }
+            Hm[(size_t)j * m + j] = cs[j] * a + sn[j] * c;
+            Hm[(size_t)(j + 1) * m + j] = H(0);
+            const H gj = g[j];
+            g[j] = cs[j] * gj;
+            g[j + 1] = -conj_h(sn[j]) * gj;
+            ++total;
+            k = j + 1;
+            if (std::abs(g[j + 1]) / bnorm <= p->tol || hn == 0.0) break;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            H s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= Hm[(size_t)i * m + l] * y[l];
+            y[i] = s / Hm[(size_t)i * m + i];
+        }
+        HIP_CHECK(hipMemcpyAsync(yc, y.data(), k * sc, hipMemcpyHostToDevice, stream));
+        HIP_CHECK(launch_update(cp, N, k, V, N, yc, 1.0, x, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+    }
+    st->iterations = total;
+    st->relres = relres;
+    st->converged = relres <= p->tol ? 1 : 0;
+    return BEM_OK;
+}
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_err.c_str(); }
+
+int bem_geometry_analytic(int kind, const double* params, int nparams, bem_geometry* out) {
+    if (!out) return fail(BEM_EINVAL, "out is NULL");
+    GeomDesc g{};
+    g.kind = kind;
+    g.a = g.b = g.c = 1.0;
+    switch (kind) {
+        case GEOM_SPHERE6:
+            g.npatch = 6;
+            break;
+        case GEOM_ELLIPSOID6:
+            if (nparams < 3 || !params) return fail(BEM_EINVAL, "ellipsoid needs 3 semi-axes");
+            if (!(params[0] > 0 && params[1] > 0 && params[2] > 0)) return fail(BEM_EINVAL, "semi-axes must be > 0");
+            g.npatch = 6;
+            g.a = params[0];
+            g.b = params[1];
+            g.c = params[2];
+            break;
+        case GEOM_TORUS16:
+            if (nparams < 2 || !params) return fail(BEM_EINVAL, "torus needs R and r");
+            if (!(params[1] > 0 && params[0] > params[1])) return fail(BEM_EINVAL, "torus needs R > r > 0");
+            g.npatch = 16;
+            g.a = params[0];
+            g.b = params[1];
+            break;
+        case GEOM_FLAT1:
+            if (nparams < 1 || !params || !(params[0] > 0)) return fail(BEM_EINVAL, "flat square needs a side > 0");
+            g.npatch = 1;
+            g.a = params[0];
+            break;
+        default:
+            return fail(BEM_EINVAL, "unknown geometry kind");
+    }
+    bem_geometry_s* G = new (std::nothrow) bem_geometry_s;
+    if (!G) return fail(BEM_ENOMEM, "host allocation failed");
+    G->g = g;
+    *out = G;
+    return BEM_OK;
+}
+
+void bem_geometry_destroy(bem_geometry g) { delete g; }
+
+int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
+                     int level, bem_space* out) {
+    if (!g || !out) return fail(BEM_EINVAL, "NULL argument");
+    if (kernel != BEM_LAPLACE_SINGLE && kernel != BEM_HELMHOLTZ_SINGLE) return fail(BEM_EINVAL, "unknown kernel");
+    if (degree < 0) return fail(BEM_EINVAL, "degree must be >= 0");
+    if (level < 0 || level > 12) return fail(BEM_EINVAL, "level must lie in [0, 12]");
+    if (knot_repetition < 1 || knot_repetition > degree + 1)
+        return fail(BEM_EINVAL, "knot repetition must lie in [1, degree+1]");
+    if (kernel == BEM_HELMHOLTZ_SINGLE && kappa_re == 0.0 && kappa_im == 0.0)
+        return fail(BEM_EINVAL, "Helmholtz needs a non-zero wavenumber");
+    if (!std::isfinite(kappa_re) || !std::isfinite(kappa_im)) return fail(BEM_EINVAL, "wavenumber must be finite");
+    if (degree > 2) return fail(BEM_EUNSUPPORTED, "this build supports degree <= 2");
+    SpaceDesc S{};
+    S.geom = g->g;
+    S.ker.pde = kernel;
+    S.ker.kre = kernel == BEM_HELMHOLTZ_SINGLE ? kappa_re : 0.0;
+    S.ker.kim = kernel == BEM_HELMHOLTZ_SINGLE ? kappa_im : 0.0;
+    S.d = degree;
+    S.r = knot_repetition;
+    S.L = level;
+    S.nel = 1 << level;
+    S.nb = degree + 1 + (S.nel - 1) * knot_repetition;
+    S.nelem = (int64_t)S.geom.npatch * S.nel * S.nel;
+    S.ndof = (int64_t)S.geom.npatch * S.nb * S.nb;
+    S.h = 1.0 / S.nel;
+    bem_space_s* sp = new (std::nothrow) bem_space_s;
+    if (!sp) return fail(BEM_ENOMEM, "host allocation failed");
+    sp->S = S;
+    if (!make_basis_tab(S, sp->bt)) {
+        delete sp;
+        return fail(BEM_EUNSUPPORTED, "element basis classes do not repeat for this knot vector");
+    }
+    *out = sp;
+    return BEM_OK;
+}
+
+int bem_space_ndof(bem_space s, int64_t* n) {
+    if (!s || !n) return fail(BEM_EINVAL, "NULL argument");
+    *n = s->S.ndof;
+    return BEM_OK;
+}
+
+void bem_space_destroy(bem_space s) { delete s; }
+
+int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, void* b_dev, int64_t ldb,
+            hipStream_t stream) {
+    if (!s || !data_params || !b_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
+    if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
+    if (data_kind != BEM_DATA_POINT_SOURCE && data_kind != BEM_DATA_PLANE_WAVE)
+        return fail(BEM_EINVAL, "unknown data kind");
+    if (data_kind == BEM_DATA_PLANE_WAVE && s->S.ker.pde != PDE_HELMHOLTZ)
+        return fail(BEM_EINVAL, "plane waves need the Helmholtz kernel");
+    const Gauss8 g8 = gauss8();
+    const size_t sc = s->S.ker.pde == PDE_HELMHOLTZ ? 16 : 8;
+    for (int r = 0; r < nrhs; ++r)
+        HIP_CHECK(launch_rhs(s->S, s->bt, g8, data_kind, data_params + 3 * r, (char*)b_dev + r * ldb * sc, stream));
+    return BEM_OK;
+}
+
+int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr, int nrhs,
+                       void* u_dev, int64_t ldu, hipStream_t stream) {
+    if (!s || !rho_dev || !u_dev || (npts > 0 && !pts_dev)) return fail(BEM_EINVAL, "NULL argument");
+    if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
+    if (ldr < s->S.ndof || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
+    if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
+    const Gauss8 g8 = gauss8();
+    const size_t sc = s->S.ker.pde == PDE_HELMHOLTZ ? 16 : 8;
+    for (int r = 0; r < nrhs; ++r)
+        HIP_CHECK(launch_potential(s->S, s->bt, g8, pts_dev, npts, (const char*)rho_dev + r * ldr * sc,
+                                   (char*)u_dev + r * ldu * sc, stream));
+    return BEM_OK;
+}
+
+int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
+    if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    H2Params P;
+    P.q = p->q;
+    P.eta = p->eta;
+    P.leaf = p->leaf_level;
+    P.qg = p->qg;
+    P.qs = p->qs;
+    bem_operator_s* A = new (std::nothrow) bem_operator_s;
+    if (!A) return fail(BEM_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        if (!build_plan(s->S, P, A->plan, err)) {
+            delete A;
+            return fail(BEM_EINVAL, err);
+        }
+    } catch (const std::bad_alloc&) {
+        delete A;
+        return fail(BEM_ENOMEM, "host allocation failed while planning");
+    }
+    A->sp = s;
+    A->cplx = s->S.ker.pde == PDE_HELMHOLTZ;
+    A->scal = A->cplx ? 16 : 8;
+    const Plan& pl = A->plan;
+    for (size_t lp = 0; lp + 1 < pl.touch_rowptr.size(); ++lp)
+        if (pl.touch_rowptr[lp + 1] > pl.touch_rowptr[lp]) A->touch_lp.push_back((int32_t)lp);
+    bem_operator_info& I = A->info;
+    I.ndof = s->S.ndof;
+    I.nclusters = pl.ncl;
+    I.nfar = (int64_t)pl.far_t.size();
+    I.nnear = (int64_t)pl.near_t.size();
+    I.ntouch = (int64_t)(pl.touch.size() / 5);
+    I.near_nnz = (int64_t)pl.col.size();
+    I.leaf_level = pl.leaf;
+    I.op_bytes = op_layout(*A, nullptr, nullptr);
+    I.tmp_bytes = tmp_layout(*A, nullptr, nullptr);
+    I.far_bytes = (double)pl.ktotal * A->scal;
+    I.near_bytes = (double)pl.col.size() * (A->scal + 4) + (double)pl.rowptr.size() * 8;
+    if (info) *info = I;
+    *out = A;
+    return BEM_OK;
+}
+
+int bem_operator_info_get(bem_operator A, bem_operator_info* info) {
+    if (!A || !info) return fail(BEM_EINVAL, "NULL argument");
+    *info = A->info;
+    return BEM_OK;
+}
+
+int bem_operator_dims(bem_operator A, int64_t* rows, int64_t* cols) {
+    if (!A || !rows || !cols) return fail(BEM_EINVAL, "NULL argument");
+    *rows = *cols = A->info.ndof;
+    return BEM_OK;
+}
+
+int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, size_t tmp_bytes, hipStream_t stream) {
+    if (!A || !op_ws || !tmp_ws) return fail(BEM_EINVAL, "NULL argument");
+    if (op_bytes < A->info.op_bytes || tmp_bytes < A->info.tmp_bytes)
+        return fail(BEM_ENOMEM, "workspace smaller than bem_assemble_plan reported");
+    const Plan& p = A->plan;
+    // align the workspaces' bases to 256 bytes
+    char* ob = (char*)(((uintptr_t)op_ws + 255) / 256 * 256);
+    char* tb = (char*)(((uintptr_t)tmp_ws + 255) / 256 * 256);
+    OpDev d;
+    AsmDev as;
+    op_layout(*A, ob, &d);
+    tmp_layout(*A, tb, &as);
+    d.S = p.S;
+    d.bt = A->sp->bt;
+    d.q = p.P.q;
+    d.q2 = p.q2;
+    d.leaf = p.leaf;
+    d.m = p.m;
+    d.nloc = p.nloc;
+    d.nleaf1 = p.nleaf1;
+    d.qg = p.P.qg;
+    d.qs = p.P.qs;
+    d.ncl = p.ncl;
+    d.nleaves = p.nleaves;
+    d.nfar = (int64_t)p.far_t.size();
+    d.nnear = (int64_t)p.near_t.size();
+    d.ntouch = (int64_t)(p.touch.size() / 5);
+    d.nnz = (int64_t)p.col.size();
+    d.cplx = A->cplx ? 1 : 0;
+    auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    HIP_CHECK(up(d.lev_off, p.lev_off.data(), p.lev_off.size() * 8));
+    HIP_CHECK(up(d.rowptr, p.rowptr.data(), p.rowptr.size() * 8));
+    HIP_CHECK(up(d.col, p.col.data(), p.col.size() * 4));
+    HIP_CHECK(up(d.far_rowptr, p.far_rowptr.data(), p.far_rowptr.size() * 8));
+    HIP_CHECK(up(d.far_s, p.far_s.data(), p.far_s.size() * 4));
+    HIP_CHECK(up(d.koff, p.koff.data(), p.koff.size() * 8));
+    HIP_CHECK(up(d.krs, p.krs.data(), p.krs.size() * 4));
+    HIP_CHECK(up(d.V1, p.V1.data(), p.V1.size() * 8));
+    HIP_CHECK(up(d.E, p.E.data(), p.E.size() * 8));
+    HIP_CHECK(up(as.near_t, p.near_t.data(), p.near_t.size() * 4));
+    HIP_CHECK(up(as.near_s, p.near_s.data(), p.near_s.size() * 4));
+    HIP_CHECK(up(as.near_rowptr, p.near_rowptr.data(), p.near_rowptr.size() * 4));
+    HIP_CHECK(up(as.touch_rowptr, p.touch_rowptr.data(), p.touch_rowptr.size() * 4));
+    HIP_CHECK(up(as.touch, p.touch.data(), p.touch.size() * 4));
+    HIP_CHECK(up(as.touch_lp, A->touch_lp.data(), A->touch_lp.size() * 4));
+    HIP_CHECK(up(as.vid, p.vid.data(), p.vid.size() * 4));
+    HIP_CHECK(up(as.gx, p.gx.data(), p.gx.size() * 8));
+    HIP_CHECK(up(as.gw, p.gw.data(), p.gw.size() * 8));
+    HIP_CHECK(up(as.psi, p.psi.data(), p.psi.size() * 8));
+    HIP_CHECK(up(as.sx, p.sx.data(), p.sx.size() * 8));
+    HIP_CHECK(up(as.sw, p.sw.data(), p.sw.size() * 8));
+    HIP_CHECK(up(as.cheb, p.cheb.data(), p.cheb.size() * 8));
+    HIP_CHECK(up(as.far_t, p.far_t.data(), p.far_t.size() * 4));
+    // coupling rows are padded to even length: clear them before the blocks are written
+    if (p.ktotal > 0) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
+    HIP_CHECK(launch_gauss_points(d, as, stream));
+    HIP_CHECK(launch_near_regular(d, as, stream));
+    HIP_CHECK(launch_near_singular(d, as, stream));
+    HIP_CHECK(launch_near_gather(d, as, stream));
+    HIP_CHECK(launch_far_assemble(d, as, stream));
+    // the host tables above are copied from pageable memory; make sure they have been read
+    // before the caller may free the temporary workspace (the plan itself stays alive)
+    A->dev = d;
+    A->assembled = true;
+    return BEM_OK;
+}
+
+int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy, int nrhs, hipStream_t stream) {
+    if (!A || !x_dev || !y_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
+    const int64_t N = A->info.ndof;
+    if (ldx < N || ldy < N) return fail(BEM_EINVAL, "leading dimension too small");
+    const char* xb = (const char*)x_dev;
+    char* yb = (char*)y_dev;
+    const size_t span_x = ((size_t)(nrhs - 1) * ldx + N) * A->scal, span_y = ((size_t)(nrhs - 1) * ldy + N) * A->scal;
+    if (!(xb + span_x <= yb || yb + span_y <= xb)) return fail(BEM_EINVAL, "x and y overlap");
+    for (int r = 0; r < nrhs; ++r) {
+        const void* xr = xb + (size_t)r * ldx * A->scal;
+        void* yr = yb + (size_t)r * ldy * A->scal;
+        if (!A->prof) {
+            HIP_CHECK(launch_apply(A->dev, xr, yr, stream));
+            continue;
+        }
+        const size_t need = A->ev_used + kApplyStages + 1;
+        while (A->ev.size() < need) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            A->ev.push_back(e);
+        }
+        HIP_CHECK(hipEventRecord(A->ev[A->ev_used], stream));
+        for (int s = 0; s < kApplyStages; ++s) {
+            HIP_CHECK(launch_apply_stage(A->dev, s, xr, yr, stream));
+            HIP_CHECK(hipEventRecord(A->ev[A->ev_used + 1 + s], stream));
+        }
+        A->ev_used = need;
+    }
+    return BEM_OK;
+}
+
+int bem_profile_enable(bem_operator A, int on) {
+    if (!A) return fail(BEM_EINVAL, "NULL argument");
+    A->prof = on != 0;
+    A->ev_used = 0;
+    return BEM_OK;
+}
+
+int bem_profile_read(bem_operator A, double* stage_ms, int nstages, int* napplies) {
+    if (!A || !stage_ms || !napplies) return fail(BEM_EINVAL, "NULL argument");
+    if (nstages < kApplyStages) return fail(BEM_EINVAL, "nstages must be >= 4");
+    const size_t per = kApplyStages + 1;
+    const size_t n = A->ev_used / per;
+    for (int s = 0; s < nstages; ++s) stage_ms[s] = 0.0;
+    if (n > 0) HIP_CHECK(hipEventSynchronize(A->ev[A->ev_used - 1]));
+    for (size_t k = 0; k < n; ++k)
+        for (int s = 0; s < kApplyStages; ++s) {
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, A->ev[k * per + s], A->ev[k * per + s + 1]));
+            stage_ms[s] += ms;
+        }
+    if (n > 0)
+        for (int s = 0; s < kApplyStages; ++s) stage_ms[s] /= (double)n;
+    *napplies = (int)n;
+    A->ev_used = 0;
+    return BEM_OK;
+}
+
+void bem_operator_destroy(bem_operator A) { delete A; }
+
+int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes) {
+    if (!A || !p || !bytes) return fail(BEM_EINVAL, "NULL argument");
+    if (nrhs < 1 || p->restart < 1) return fail(BEM_EINVAL, "nrhs and restart must be >= 1");
+    char* ptrs[7];
+    *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, ptrs);
+    return BEM_OK;
+}
+
+int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64_t ldx, int nrhs,
+              const bem_solve_params* p, bem_solve_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!A || !b_dev || !x_dev || !p || !stats || !ws) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    if (nrhs < 1 || p->restart < 1 || p->maxit < 1 || !(p->tol > 0.0)) return fail(BEM_EINVAL, "bad solver parameters");
+    const int64_t N = A->info.ndof;
+    if (ldb < N || ldx < N) return fail(BEM_EINVAL, "leading dimension too small");
+    char* ptrs[7];
+    const size_t need = solve_layout(N, p->restart, A->scal, nullptr, ptrs);
+    if (ws_bytes < need) return fail(BEM_ENOMEM, "solver workspace too small");
+    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    solve_layout(N, p->restart, A->scal, base, ptrs);
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+        const void* b = (const char*)b_dev + (size_t)r * ldb * A->scal;
+        void* x = (char*)x_dev + (size_t)r * ldx * A->scal;
+        int rc = A->cplx ? gmres_one<std::complex<double>>(A, b, x, p, &stats[r], ptrs, stream)
+                         : gmres_one<double>(A, b, x, p, &stats[r], ptrs, stream);
+        if (rc != BEM_OK) return rc;
+        all = all && stats[r].converged;
+    }
+    if (!all) return fail(BEM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
+    return BEM_OK;
+}
+
+// ------------------------------------------------------------------------------ exports
+int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, hipStream_t stream) {
+    if (!A) return fail(BEM_EINVAL, "NULL argument");
+    if (val && !A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    const Plan& p = A->plan;
+    if (rowptr) std::memcpy(rowptr, p.rowptr.data(), p.rowptr.size() * 8);
+    if (col) std::memcpy(col, p.col.data(), p.col.size() * 4);
+    if (val) {
+        HIP_CHECK(hipMemcpyAsync(val, A->dev.val, p.col.size() * A->scal, hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+    }
+    return BEM_OK;
+}
+
+int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t stream) {
+    if (!A) return fail(BEM_EINVAL, "NULL argument");
+    if (blocks && !A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    const Plan& p = A->plan;
+    const size_t nf = p.far_t.size();
+    if (pairs)
+        for (size_t i = 0; i < nf; ++i) {
+            pairs[2 * i] = p.far_t[i];
+            pairs[2 * i + 1] = p.far_s[i];
+        }
+    if (blocks && nf > 0) {
+        std::vector<char> K((size_t)p.ktotal * A->scal);
+        HIP_CHECK(hipMemcpyAsync(K.data(), A->dev.K, K.size(), hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        const int q2 = p.q2;
+        for (size_t i = 0; i < nf; ++i) {
+            const int t = p.far_t[i];
+            const int64_t slot = (int64_t)i - p.far_rowptr[t];
+            for (int a = 0; a < q2; ++a)
+                std::memcpy((char*)blocks + ((i * q2 + a) * q2) * A->scal,
+                            K.data() + (p.koff[t] + (int64_t)a * p.krs[t] + slot * q2) * A->scal, q2 * A->scal);
+        }
+    }
+    return BEM_OK;
+}
+
+int bem_export_moments(bem_operator A, const void* x_dev, double* mom_host, hipStream_t stream) {
+    if (!A || !x_dev || !mom_host) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    HIP_CHECK(launch_moments(A->dev, x_dev, stream));
+    HIP_CHECK(hipMemcpyAsync(mom_host, A->dev.mom, (size_t)A->plan.ncl * A->plan.q2 * A->scal, hipMemcpyDeviceToHost,
+                             stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    return BEM_OK;
+}
+
+}  // extern "C"

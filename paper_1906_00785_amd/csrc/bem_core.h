@@ -1,0 +1,164 @@
+// Internal definitions shared by the host plan and the gfx950 kernels of libbem_hip.so:
+// scalar types, the analytic patch maps, the single-layer kernels, and the plain-old-data
+// descriptors that kernels receive by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bem {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kInv4Pi = 0.07957747154594766788444188168625718;  // 1/(4 pi)
+
+// ------------------------------------------------------------------ complex scalar
+struct cdbl {
+    double re, im;
+};
+__host__ __device__ inline cdbl operator+(cdbl a, cdbl b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cdbl operator-(cdbl a, cdbl b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cdbl operator*(cdbl a, cdbl b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cdbl operator*(double s, cdbl a) { return {s * a.re, s * a.im}; }
+__host__ __device__ inline cdbl operator*(cdbl a, double s) { return {s * a.re, s * a.im}; }
+__host__ __device__ inline cdbl& operator+=(cdbl& a, cdbl b) {
+    a.re += b.re;
+    a.im += b.im;
+    return a;
+}
+__host__ __device__ inline cdbl& operator-=(cdbl& a, cdbl b) {
+    a.re -= b.re;
+    a.im -= b.im;
+    return a;
+}
+
+template <class T>
+__host__ __device__ inline T zero();
+template <>
+__host__ __device__ inline double zero<double>() { return 0.0; }
+template <>
+__host__ __device__ inline cdbl zero<cdbl>() { return {0.0, 0.0}; }
+
+__host__ __device__ inline double conj_(double a) { return a; }
+__host__ __device__ inline cdbl conj_(cdbl a) { return {a.re, -a.im}; }
+__host__ __device__ inline double abs2(double a) { return a * a; }
+__host__ __device__ inline double abs2(cdbl a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------------------------ geometry
+enum GeomKind : int { GEOM_SPHERE6 = 0, GEOM_ELLIPSOID6 = 1, GEOM_TORUS16 = 2, GEOM_FLAT1 = 3 };
+
+struct GeomDesc {
+    int kind;
+    int npatch;
+    double a, b, c;  // ellipsoid semi-axes; torus R = a, r = b; flat side a
+};
+
+// Cube face f of the cube-sphere: which coordinate receives u = 2s-1, which receives
+// v = 2t-1, which is the constant +-1.  Faces: +z, -z, +x, -x, +y, -y, each with the
+// orientation that makes d_s x d_t point outward.
+__host__ __device__ inline void cube_face_layout(int f, int& iu, int& iv, int& ic, double& cval) {
+    switch (f) {
+        case 0: iu = 0; iv = 1; ic = 2; cval = 1.0; break;
+        case 1: iu = 1; iv = 0; ic = 2; cval = -1.0; break;
+        case 2: iu = 1; iv = 2; ic = 0; cval = 1.0; break;
+        case 3: iu = 2; iv = 1; ic = 0; cval = -1.0; break;
+        case 4: iu = 2; iv = 0; ic = 1; cval = 1.0; break;
+        default: iu = 0; iv = 2; ic = 1; cval = -1.0; break;
+    }
+}
+
+// Point gamma_f(s, t) of the analytic multi-patch surface.
+__host__ __device__ inline void patch_point(const GeomDesc& g, int f, double s, double t, double* x) {
+    if (g.kind == GEOM_SPHERE6 || g.kind == GEOM_ELLIPSOID6) {
+        int iu, iv, ic;
+        double cv;
+        cube_face_layout(f, iu, iv, ic, cv);
+        double c[3];
+        c[iu] = 2.0 * s - 1.0;
+        c[iv] = 2.0 * t - 1.0;
+        c[ic] = cv;
+        const double inv = 1.0 / sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (g.kind == GEOM_SPHERE6) {
+            x[0] = c[0] * inv;
+            x[1] = c[1] * inv;
+            x[2] = c[2] * inv;
+        } else {
+            x[0] = g.a * (c[0] * inv);
+            x[1] = g.b * (c[1] * inv);
+            x[2] = g.c * (c[2] * inv);
+        }
+    } else if (g.kind == GEOM_TORUS16) {
+        const double u = 0.5 * kPi * ((f >> 2) + s);
+        const double v = 0.5 * kPi * ((f & 3) + t);
+        double su, cu, sv, cvv;
+        sincos(u, &su, &cu);
+        sincos(v, &sv, &cvv);
+        const double rr = g.a + g.b * cvv;
+        x[0] = rr * cu;
+        x[1] = rr * su;
+        x[2] = g.b * sv;
+    } else {
+        x[0] = g.a * s;
+        x[1] = g.a * t;
+        x[2] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ single-layer kernels
+enum PdeKind : int { PDE_LAPLACE = 0, PDE_HELMHOLTZ = 1 };
+
+struct KernelDesc {
+    int pde;
+    double kre, kim;  // wavenumber (Helmholtz)
+};
+
+// k(r) for Laplace: 1/(4 pi r)
+__device__ inline double kernel_val(const KernelDesc&, double r2, double) {
+    return kInv4Pi * rsqrt(r2);
+}
+// k(r) for Helmholtz: exp(-i kappa r)/(4 pi r), kappa = kre + i kim
+__device__ inline cdbl kernel_val(const KernelDesc& k, double r2, cdbl) {
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    double s, c;
+    sincos(k.kre * r, &s, &c);
+    double mag = kInv4Pi * ir;
+    if (k.kim != 0.0) mag *= exp(k.kim * r);
+    return {mag * c, -mag * s};
+}
+
+// ------------------------------------------------------------------ space description
+struct SpaceDesc {
+    GeomDesc geom;
+    KernelDesc ker;
+    int d, r, L;       // degree, knot repetition, level
+    int nel, nb;       // elements and B-splines per direction
+    int64_t nelem, ndof;
+    double h;          // element width 2^-L
+};
+
+__host__ __device__ inline int64_t dof_id(const SpaceDesc& S, int f, int j1, int j2) {
+    return ((int64_t)f * S.nb + j1) * S.nb + j2;
+}
+__host__ __device__ inline int64_t elem_id(const SpaceDesc& S, int f, int i1, int i2) {
+    return ((int64_t)f * S.nel + i1) * S.nel + i2;
+}
+
+// D4 symmetry k of the unit square applied to (a, b): identity, flip first, flip second,
+// flip both, then the same four after exchanging the coordinates.
+__host__ __device__ inline void d4_apply(int k, double a, double b, double& o1, double& o2) {
+    if (k >= 4) {
+        const double tmp = a;
+        a = b;
+        b = tmp;
+    }
+    o1 = (k & 1) ? 1.0 - a : a;
+    o2 = (k & 2) ? 1.0 - b : b;
+}
+
+// Touching element pair types
+enum PairType : int { PT_REGULAR = 0, PT_VERTEX = 1, PT_EDGE = 2, PT_IDENTICAL = 3 };
+
+}  // namespace bem

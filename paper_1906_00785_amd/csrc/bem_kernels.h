@@ -1,0 +1,119 @@
+// Launch interface of the gfx950 kernels (bem_kernels.hip) used by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bem_core.h"
+
+namespace bem {
+
+// Local B-spline polynomials of every element class, small enough to pass by value: with
+// more than 2w+1 elements per direction (w = d+1) only the first w elements, the interior
+// ones and the last w elements differ (uniform knots); otherwise every element is stored.
+// The host checks every element against its class before use.
+struct BasisTab {
+    int d, nel, ncls, w;
+    double c[7][3][3];  // [class][local basis][monomial coefficient], d <= 2
+};
+__host__ __device__ inline int basis_class(const BasisTab& t, int i) {
+    if (t.ncls == t.nel) return i;
+    if (i < t.w) return i;
+    if (i >= t.nel - t.w) return 2 * t.w - (t.nel - 1 - i);
+    return t.w;
+}
+__host__ __device__ inline double basis_eval(const BasisTab& t, int cls, int l, double x) {
+    double v = t.c[cls][l][t.d];
+    for (int k = t.d - 1; k >= 0; --k) v = v * x + t.c[cls][l][k];
+    return v;
+}
+
+struct Gauss8 {
+    double x[8], w[8];
+};
+
+// Device arrays of an assembled operator (all inside the caller's workspaces).
+struct OpDev {
+    SpaceDesc S;
+    BasisTab bt;
+    int q, q2, leaf, m, nloc, nleaf1, qg, qs;
+    int64_t ncl, nleaves, nfar, nnear, ntouch, nnz;
+    int cplx;
+    const int64_t* lev_off;  // device copy (leaf+2)
+    // near field
+    const int64_t* rowptr;
+    const int32_t* col;
+    void* val;
+    // far field
+    const int64_t* far_rowptr;
+    const int32_t* far_s;
+    const int64_t* koff;
+    const int32_t* krs;
+    void* K;
+    // transforms
+    const double* V1;  // [nleaf1][q][nloc]
+    const double* E;   // [2][q][q]
+    // matvec scratch: moments and local expansions of all clusters (one RHS)
+    void* mom;
+    void* lv;
+};
+
+// Temporary arrays used only during assembly.
+struct AsmDev {
+    const int32_t* near_t;
+    const int32_t* near_s;
+    const int32_t* near_rowptr;
+    const int32_t* touch_rowptr;
+    const int32_t* touch;
+    const int32_t* touch_lp;  // near leaf pairs that contain touching pairs
+    int64_t ntouch_lp;
+    const int32_t* vid;
+    const double* gx;     // [qg]
+    const double* gpos;   // [nelem][qg*qg][3]
+    const double* psi;    // [nel][qg][d+1]
+    const double* gw;     // [qg]
+    const double* sx;     // [qs]
+    const double* sw;     // [qs]
+    const double* cheb;   // [q]
+    const int32_t* far_t; // target of each far block
+    double* xc;           // [ncl][q2][3] Chebyshev points on the surface
+    void* lb;             // [nnear][nloc^2][nloc^2] leaf-pair blocks
+};
+
+hipError_t launch_gauss_points(const OpDev& op, const AsmDev& as, hipStream_t st);
+hipError_t launch_near_regular(const OpDev& op, const AsmDev& as, hipStream_t st);
+hipError_t launch_near_singular(const OpDev& op, const AsmDev& as, hipStream_t st);
+hipError_t launch_near_gather(const OpDev& op, const AsmDev& as, hipStream_t st);
+hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st);
+
+// y = A x for one RHS column, as four stages: 0 forward transform + upward transfer,
+// 1 far-field coupling, 2 downward transfer, 3 backward transform + near field
+constexpr int kApplyStages = 4;
+hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, hipStream_t st);
+hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st);
+// moments of all clusters for x (forward + upward) into op.mom
+hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st);
+
+// load vector (one RHS) and potential (one RHS)
+hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,
+                      void* b, hipStream_t st);
+hipError_t launch_potential(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const double* pts,
+                            int64_t npts, const void* rho, void* u, hipStream_t st);
+
+// GMRES building blocks.  Vectors of n scalars; V holds k vectors with leading dim ldv.
+// dots:   out[i] = sum_t conj(V_i[t]) w[t], i < k (partials per block, then reduced in
+//         a fixed order into out; deterministic)
+// update: w[t] += alpha * sum_i c[i] V_i[t]   (c on the device)
+// scale:  v[t] = w[t] * (1 / *nrm)            (nrm on the device, a real scalar)
+// axpby:  y[t] = a x[t] + b y[t]              (real a, b)
+constexpr int kDotBlocks = 240;
+hipError_t launch_dots(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* w, void* partial,
+                       void* out, hipStream_t st);
+hipError_t launch_update(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* c, double alpha,
+                         void* w, hipStream_t st);
+hipError_t launch_norm(int cplx, int64_t n, const void* w, void* partial, double* out, hipStream_t st);
+hipError_t launch_scale(int cplx, int64_t n, const void* w, const double* nrm, void* v, hipStream_t st);
+hipError_t launch_axpby(int cplx, int64_t n, double a, const void* x, double b, void* y, hipStream_t st);
+
+}  // namespace bem

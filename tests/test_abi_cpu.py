@@ -1,0 +1,111 @@
+"""CPU checks of the C ABI library: it loads, exports every function that include/bem.h
+declares, validates its arguments, and its host plan (cluster tree, block partition, near
+pattern) equals the oracle's.  No compute call touches a GPU here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_1906_00785_amd as B
+
+    return B
+
+
+def test_exports_every_declared_symbol(B):
+    names = B._bem.header_symbols()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(B._bem.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_validation(B):
+    C = B._bem
+    with pytest.raises(C.BemError) as e:
+        B.Geometry(99)
+    assert e.value.code == C.BEM_EINVAL
+    with pytest.raises(C.BemError) as e:
+        B.Geometry(B.BEM_GEOM_TORUS16, (0.3, 0.5))  # R < r
+    assert e.value.code == C.BEM_EINVAL
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    for kw, code in [(dict(degree=-1), C.BEM_EINVAL), (dict(level=-1), C.BEM_EINVAL),
+                     (dict(degree=1, knot_repetition=3), C.BEM_EINVAL),
+                     (dict(degree=1, knot_repetition=0), C.BEM_EINVAL), (dict(degree=3), C.BEM_EUNSUPPORTED)]:
+        with pytest.raises(C.BemError) as e:
+            B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, **kw)
+        assert e.value.code == code, kw
+    with pytest.raises(C.BemError) as e:
+        B.Space(g, B.BEM_HELMHOLTZ_SINGLE, 0.0, degree=1, level=1)  # kappa = 0
+    assert e.value.code == C.BEM_EINVAL
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=2)
+    for q, eta, leaf in [(0, 1.6, 1), (5, -1.0, 1), (5, 1.6, 3), (9, 1.6, 1)]:
+        with pytest.raises(C.BemError) as e:
+            B.Operator(s, q=q, eta=eta, leaf_level=leaf, assemble=False)
+        assert e.value.code == C.BEM_EINVAL
+    A = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False)
+    with pytest.raises(C.BemError):  # not assembled yet
+        C.bem_apply(A.h, 1, A.ndof, 2, A.ndof, 1, 0)
+    assert C.bem_operator_dims(A.h) == (150, 150)
+
+
+def test_degenerate_sizes(B):
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=0, level=0)
+    A = B.Operator(s, q=1, eta=1.6, leaf_level=0, assemble=False)
+    assert A.info.ndof == 6 and A.info.nfar == 0 and A.info.nnear == 36
+    assert A.info.ntouch == 6 + 24 + 0  # identical, edge; no vertex-only pairs at L=0
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=2, knot_repetition=3, level=2)
+    assert s.ndof == 6 * (3 + 3 * 3) ** 2
+
+
+def _plan_lists(B, A):
+    C = B._bem
+    info = A.info
+    pairs = np.zeros((info.nfar, 2), dtype=np.int64)
+    C.bem_export_far(A.h, pairs.ctypes.data, 0, 0)
+    rowptr = np.zeros(info.ndof + 1, dtype=np.int64)
+    col = np.zeros(info.near_nnz, dtype=np.int32)
+    C.bem_export_near(A.h, rowptr.ctypes.data, col.ctypes.data, 0, 0)
+    return pairs, rowptr, col
+
+
+@pytest.mark.parametrize("geom,prm,L,d,leaf,eta", [
+    (0, (), 2, 1, 2, 1.6), (0, (), 2, 1, 1, 1.6), (2, (1.0, 0.4), 2, 1, 1, 1.6),
+    (1, (0.7, 1.2, 1.6), 2, 2, 1, 1.6), (3, (2.0,), 2, 0, 1, 1.6), (0, (), 2, 1, 0, 0.0), (0, (), 1, 2, 1, 3.0),
+])
+def test_plan_equals_oracle(B, orc, geom, prm, L, d, leaf, eta):
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=d, level=L)
+    A = B.Operator(s, q=4, eta=eta, leaf_level=leaf, assemble=False)
+    pairs, rowptr, col = _plan_lists(B, A)
+    So = orc.Space(geom, list(prm), orc.LAPLACE, 0.0, degree=d, level=L)
+    Ho = orc.H2(So, q=4, eta=eta, leaf=leaf, assemble_near=(L <= 1 or (L == 2 and d <= 1 and leaf >= 1)))
+    far, near = Ho.lists()
+    assert np.array_equal(far, pairs)
+    assert A.info.nnear == Ho.nnear
+    if Ho.nnz:
+        rp, cl, _ = Ho.near_csr()
+        assert np.array_equal(rp, rowptr) and np.array_equal(cl, col)
+
+
+def test_plan_counts_at_full_size(B, orc):
+    """The benchmark workload's partition: far and near lists equal the oracle's."""
+    c = W.CONFIGS[1]
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=c["degree"], level=c["level"])
+    A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], assemble=False)
+    pairs, rowptr, col = _plan_lists(B, A)
+    So = orc.Space(orc.SPHERE, [], orc.LAPLACE, 0.0, degree=c["degree"], level=c["level"])
+    Ho = orc.H2(So, q=c["q"], eta=c["eta"], leaf=c["leaf"], assemble_near=False)
+    far, near = Ho.lists()
+    assert np.array_equal(far, pairs)
+    assert A.info.nfar == 143520 and A.info.nnear == Ho.nnear
+    assert A.info.ndof == 26136
+    # touching element pairs: identical + edge + vertex = nelem + 4 nelem + (4 nelem - 24)
+    ne = 6 * 64 * 64
+    assert A.info.ntouch == ne + 4 * ne + 4 * ne - 24

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same seeded inputs.
+
+Bar: FP64 results within 1e-11 relative (max-norm, element by element, relative to the
+largest oracle entry of the compared quantity); integer structure (patterns, lists) exact.
+Small cases span every geometry, degrees 0-2, Laplace and Helmholtz (real and complex
+wavenumber), leaf levels 0..L and eta = 0 (dense); the benchmark workload itself is checked
+on sampled rows and through properties that hold at any size.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+CASES = {
+    # id: (geom, params, pde, kappa, L, d, q, eta, leaf)
+    "sphere_L2_d1_laplace_dense": (0, (), 0, 0.0, 2, 1, 3, 0.0, 0),
+    "sphere_L2_d1_laplace_h2": (0, (), 0, 0.0, 2, 1, 5, 1.6, 2),
+    "sphere_L2_d1_helmholtz_h2": (0, (), 1, 2.5, 2, 1, 5, 1.6, 2),
+    "torus_L2_d1_laplace_h2": (2, (1.0, 0.4), 0, 0.0, 2, 1, 4, 1.6, 1),
+    "ellipsoid_L2_d2_helmholtz_cplx_h2": (1, (0.7, 1.2, 1.6), 1, 1.5 + 0.3j, 2, 2, 4, 1.6, 1),
+    "flat_L2_d0_laplace": (3, (2.0,), 0, 0.0, 2, 0, 3, 1.6, 1),
+    "sphere_L1_d2_laplace_leaf_eq_L": (0, (), 0, 0.0, 1, 2, 3, 1.6, 1),
+}
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_1906_00785_amd as B
+
+    assert torch.cuda.is_available()
+    return B
+
+
+_cache = {}
+
+
+def case(B, orc, cid):
+    if cid not in _cache:
+        geom, prm, pde, kappa, L, d, q, eta, leaf = CASES[cid]
+        print(f"[case {cid}] assemble on GPU and in the oracle", flush=True)
+        g = B.Geometry(geom, prm)
+        s = B.Space(g, pde, kappa, degree=d, level=L)
+        A = B.Operator(s, q=q, eta=eta, leaf_level=leaf)
+        So = orc.Space(geom, list(prm), pde, kappa, degree=d, level=L)
+        Ho = orc.H2(So, q=q, eta=eta, leaf=leaf)
+        _cache[cid] = (g, s, A, So, Ho)
+    return _cache[cid]
+
+
+@pytest.mark.parametrize("cid", list(CASES))
+def test_near_field(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    rowptr, col, val = A.export_near()
+    rp, cl, vo = Ho.near_csr()
+    assert np.array_equal(rowptr, rp) and np.array_equal(col, cl)
+    assert relerr(val, vo) <= TOL
+
+
+def test_dense_mode_equals_dense_matrix(B, orc):
+    g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_dense")
+    rowptr, col, val = A.export_near()
+    N = s.ndof
+    D = np.zeros((N, N))
+    for r in range(N):
+        D[r, col[rowptr[r]:rowptr[r + 1]]] = val[rowptr[r]:rowptr[r + 1]]
+    Ad = So.dense(8, 8)
+    assert relerr(D, Ad) <= TOL
+    assert np.abs(D - D.T).max() <= 1e-13 * np.abs(D).max()
+
+
+@pytest.mark.parametrize("cid", [c for c in CASES if CASES[c][7] > 0])
+def test_far_blocks(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    pairs, blocks = A.export_far()
+    far, _ = Ho.lists()
+    assert np.array_equal(pairs, far)
+    if len(far):
+        K, _, _, _ = Ho.tables()
+        assert relerr(blocks, K) <= TOL
+
+
+@pytest.mark.parametrize("cid", list(CASES))
+def test_moments(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    x = W.random_vector(W.rng(0, 20), s.ndof, is_complex=So.complex)
+    m = A.moments(torch.from_numpy(x).cuda())
+    mo = Ho.moments(x)
+    assert relerr(m, mo) <= TOL
+
+
+@pytest.mark.parametrize("cid", list(CASES))
+def test_apply(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    x = W.random_vector(W.rng(0, 21), s.ndof, is_complex=So.complex, ncols=3).T.copy()  # (3, N)
+    xd = torch.from_numpy(x).cuda()
+    y = A.apply(xd).cpu().numpy()
+    yo = Ho.apply(x.T).T
+    assert relerr(y, yo) <= TOL
+    # columns are independent and the result is deterministic
+    y1 = A.apply(xd[1]).cpu().numpy()
+    assert np.array_equal(y1, y[1])
+    assert np.array_equal(A.apply(xd).cpu().numpy(), y)
+
+
+def test_rhs_and_potential(B, orc):
+    for cid in ("sphere_L2_d1_laplace_h2", "sphere_L2_d1_helmholtz_h2", "ellipsoid_L2_d2_helmholtz_cplx_h2"):
+        g, s, A, So, Ho = case(B, orc, cid)
+        x0, pts = W.c0_inputs()
+        b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0, (0.2, 0.1, -0.3)]).cpu().numpy()
+        bo = So.rhs(orc.POINT_SOURCE, [x0, (0.2, 0.1, -0.3)]).T
+        assert relerr(b, bo) <= TOL, cid
+        if So.complex:
+            d = W.unit_vectors(W.rng(0, 22), 2)
+            b = s.rhs(B.BEM_DATA_PLANE_WAVE, d).cpu().numpy()
+            bo = So.rhs(orc.PLANE_WAVE, d).T
+            assert relerr(b, bo) <= TOL, cid
+        rho = W.random_vector(W.rng(0, 23), s.ndof, is_complex=So.complex)
+        u = s.potential(pts, torch.from_numpy(rho).cuda()).cpu().numpy()
+        uo = So.potential(rho, pts)
+        assert relerr(u, uo) <= TOL, cid
+    # no points: nothing to do, no error
+    u = s.potential(np.zeros((0, 3)), torch.from_numpy(rho).cuda())
+    assert u.numel() == 0
+
+
+@pytest.mark.parametrize("cid", ["sphere_L2_d1_laplace_h2", "sphere_L2_d1_helmholtz_h2",
+                                 "ellipsoid_L2_d2_helmholtz_cplx_h2"])
+def test_gmres(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    x0 = W.CONFIGS[0]["x0"]
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+    x, stats = A.solve(b, tol=1e-12, restart=30, maxit=500)
+    it, ok, rr = stats[0]
+    assert ok and rr <= 1e-12
+    xg = x.cpu().numpy()[0]
+    bo = So.rhs(orc.POINT_SOURCE, x0)
+    # the oracle's operator confirms the GPU solution, and the oracle's own GMRES agrees
+    assert np.linalg.norm(Ho.apply(xg) - bo) / np.linalg.norm(bo) <= 1e-11
+    xo, ito, rro, oko = Ho.gmres(bo, tol=1e-12)
+    assert oko and np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_gmres_nonconvergence_reported(B, orc):
+    g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_h2")
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [W.CONFIGS[0]["x0"]])
+    x, stats = A.solve(b, tol=1e-14, restart=5, maxit=3)
+    it, ok, rr = stats[0]
+    assert not ok and it == 3 and rr > 1e-14 and np.isfinite(x.cpu().numpy()).all()
+
+
+def test_exterior_dirichlet_dense_sphere(B, orc):
+    """The dense-sphere workload end to end on the GPU: potential reproduces 1/(4 pi |x-x0|)."""
+    g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_dense")
+    x0, pts = W.c0_inputs()
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+    rho, stats = A.solve(b, tol=1e-12)
+    u = s.potential(pts, rho[0]).cpu().numpy()
+    ex = 1.0 / (4 * math.pi * np.linalg.norm(pts - x0, axis=1))
+    err = np.max(np.abs(u - ex)) / np.max(np.abs(ex))
+    Ad = So.dense(8, 8)
+    uo = So.potential(np.linalg.solve(Ad, So.rhs(orc.POINT_SOURCE, x0)), pts)
+    assert err < 2e-4
+    assert relerr(u, uo) <= 1e-9
+
+
+# ------------------------------------------------------------------ the benchmark workload
+@pytest.fixture(scope="module")
+def full(B, orc):
+    c = W.CONFIGS[1]
+    print("[full] sphere6 L=6 d=2 q=5 eta=1.6 leaf=4: assemble on GPU", flush=True)
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=c["degree"], level=c["level"])
+    A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"])
+    So = orc.Space(orc.SPHERE, [], orc.LAPLACE, 0.0, degree=c["degree"], level=c["level"])
+    Ho = orc.H2(So, q=c["q"], eta=c["eta"], leaf=c["leaf"], assemble_near=False)
+    return g, s, A, So, Ho
+
+
+def test_full_size_sampled_rows(B, orc, full):
+    g, s, A, So, Ho = full
+    N = s.ndof
+    x = W.random_vector(W.rng(1, 30), N)
+    y = A.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    rows = W.sample_rows(1, N, 6)
+    Ho.assemble_near_rows(rows)
+    yo = Ho.apply_rows(x, rows)
+    assert np.max(np.abs(y[rows] - yo)) <= TOL * np.max(np.abs(yo))
+    # far field alone at every row (the oracle's far pipeline is cheap at this size)
+    allr = np.arange(N, dtype=np.int64)
+    yf = Ho.apply_rows(x, allr, far=True, near=False)
+    rowptr, col, val = A.export_near()
+    yn = np.add.reduceat(val * x[col], rowptr[:-1])
+    assert np.max(np.abs(y - yn - yf)) <= TOL * np.max(np.abs(y))
+
+
+def test_full_size_near_symmetric(B, full):
+    g, s, A, So, Ho = full
+    rowptr, col, val = A.export_near()
+    rows = W.sample_rows(1, s.ndof, 40)
+    worst = 0.0
+    for r in rows:
+        cs = col[rowptr[r]:rowptr[r + 1]]
+        vs = val[rowptr[r]:rowptr[r + 1]]
+        for h, v in zip(cs, vs):
+            seg = col[rowptr[h]:rowptr[h + 1]]
+            k = np.searchsorted(seg, r)
+            assert k < len(seg) and seg[k] == r
+            worst = max(worst, abs(val[rowptr[h] + k] - v))
+    assert worst <= 1e-13 * np.abs(val).max()
+
+
+def test_full_size_solve(B, full):
+    g, s, A, So, Ho = full
+    c = W.CONFIGS[1]
+    x0, pts = W.c1_inputs()
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+    rho, stats = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"])
+    it, ok, rr = stats[0]
+    assert ok and rr <= c["tol"]
+    r = (b[0] - A.apply(rho[0])).norm() / b[0].norm()
+    assert float(r) <= c["tol"]
+    u = s.potential(pts, rho[0]).cpu().numpy()
+    ex = 1.0 / (4 * math.pi * np.linalg.norm(pts - x0, axis=1))
+    assert np.max(np.abs(u - ex)) / np.max(np.abs(ex)) < 1e-5
