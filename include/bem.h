@@ -83,7 +83,8 @@ typedef struct bem_h2_params {
     int leaf_level;   /* cluster-tree leaf level, 0..L; -1 picks max(L-2, 0)             */
     int qg;           /* Gauss points per direction on each element of a regular pair   */
     int qs;           /* Gauss points per dimension of each Duffy cube (touching pairs)  */
-    int reserved[4];  /* must be zero */
+    int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 256     */
+    int reserved[3];  /* must be zero */
 } bem_h2_params;
 
 /* Sizes and counts of an operator, filled by bem_assemble_plan. */
@@ -97,8 +98,11 @@ typedef struct bem_operator_info {
     int64_t leaf_level;      /* leaf level actually used */
     size_t op_bytes;         /* persistent device workspace for bem_assemble */
     size_t tmp_bytes;        /* temporary device workspace, free after bem_assemble */
-    double far_bytes;        /* bytes of stored coupling blocks */
+    double far_bytes;        /* bytes of stored coupling blocks (each pair stored once) */
     double near_bytes;       /* bytes of near-field values + column indices */
+    int64_t nstored;         /* stored coupling blocks (= nfar / 2) */
+    int64_t nchunks;         /* work chunks of the coupling kernel */
+    double transposed_bytes; /* bytes of the per-column transposed products */
 } bem_operator_info;
 
 /* GMRES(m) parameters (reading: restart 30, x0 = 0, relative residual tolerance). */
@@ -187,7 +191,8 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
 /* Potential u(x) = int_Gamma k(x, y) rho(y) dsigma_y at npts points (Sec. 4 "Evaluation of
  * the Solution"; App. B (LS)/(HS)), Gauss with 8 points per direction per element.
  * pts_dev: device, npts x 3 row-major.  rho_dev: device N x nrhs (leading dim ldr).
- * u_dev: device npts x nrhs column-major (leading dim ldu >= npts), overwritten. */
+ * u_dev: device npts x nrhs column-major (leading dim ldu >= npts), overwritten.
+ * With npts == 0 nothing is done and pts_dev, u_dev may be NULL. */
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev,
                        int64_t ldr, int nrhs, void* u_dev, int64_t ldu, hipStream_t stream);
 

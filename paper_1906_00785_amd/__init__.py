@@ -85,9 +85,9 @@ class Operator:
     """Compressed single-layer operator: plan on the host, assemble on the GPU."""
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
-                 assemble: bool = True):
+                 assemble: bool = True, chunk_cols: int = 0):
         self.space = space
-        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs)
+        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols)
         self.q = q
         self.ndof = self.info.ndof
         self.op_ws = None

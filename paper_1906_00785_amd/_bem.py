@@ -21,13 +21,14 @@ _c_int, _c_dbl, _c_i64, _c_sz, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int
 
 class bem_h2_params(ctypes.Structure):
     _fields_ = [("q", _c_int), ("eta", _c_dbl), ("leaf_level", _c_int), ("qg", _c_int), ("qs", _c_int),
-                ("reserved", _c_int * 4)]
+                ("chunk_cols", _c_int), ("reserved", _c_int * 3)]
 
 
 class bem_operator_info(ctypes.Structure):
     _fields_ = [("ndof", _c_i64), ("nclusters", _c_i64), ("nfar", _c_i64), ("nnear", _c_i64), ("ntouch", _c_i64),
                 ("near_nnz", _c_i64), ("leaf_level", _c_i64), ("op_bytes", _c_sz), ("tmp_bytes", _c_sz),
-                ("far_bytes", _c_dbl), ("near_bytes", _c_dbl)]
+                ("far_bytes", _c_dbl), ("near_bytes", _c_dbl), ("nstored", _c_i64), ("nchunks", _c_i64),
+                ("transposed_bytes", _c_dbl)]
 
 
 class bem_solve_params(ctypes.Structure):
@@ -135,8 +136,8 @@ def bem_rhs(s: int, data_kind: int, data_params, nrhs: int, b_ptr: int, ldb: int
     check(lib.bem_rhs(s, data_kind, _dbl_array(flat), nrhs, b_ptr, ldb, stream))
 
 
-def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int):
-    p = bem_h2_params(q, eta, leaf_level, qg, qs, (_c_int * 4)(0, 0, 0, 0))
+def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int, chunk_cols: int = 0):
+    p = bem_h2_params(q, eta, leaf_level, qg, qs, chunk_cols, (_c_int * 3)(0, 0, 0))
     h = _vp()
     info = bem_operator_info()
     check(lib.bem_assemble_plan(s, ctypes.byref(p), ctypes.byref(h), ctypes.byref(info)))

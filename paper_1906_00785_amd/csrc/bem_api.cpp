@@ -76,6 +76,9 @@ struct bem_operator_s {
     }
 };
 
+// root level of the subtrees summed by one block each in the upward pass (depth <= 2)
+static int up_root_of(const Plan& p) { return std::max(p.leaf - 2, 0); }
+
 static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     const Plan& p = A.plan;
     Bump b(base);
@@ -84,15 +87,25 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     o.rowptr = b.take<int64_t>(p.rowptr.size());
     o.col = b.take<int32_t>(p.col.size());
     o.val = b.take<char>(p.col.size() * A.scal);
-    o.far_rowptr = b.take<int64_t>(p.far_rowptr.size());
-    o.far_s = b.take<int32_t>(p.far_s.size());
+    o.own_rowptr = b.take<int64_t>(p.own_rowptr.size());
+    o.own_src = b.take<int32_t>(p.own_src.size());
     o.koff = b.take<int64_t>(p.koff.size());
     o.krs = b.take<int32_t>(p.krs.size());
     o.K = b.take<char>((size_t)p.ktotal * A.scal);
+    o.pcol = b.take<int64_t>(p.pcol.size());
+    o.P = b.take<char>((size_t)p.ptotal * A.scal);
+    o.tr_rowptr = b.take<int64_t>(p.tr_rowptr.size());
+    o.tr_off = b.take<int64_t>(p.tr_off.size());
+    o.ch_t = b.take<int32_t>(p.ch_t.size());
+    o.ch_k0 = b.take<int32_t>(p.ch_k0.size());
+    o.ch_k1 = b.take<int32_t>(p.ch_k1.size());
+    o.cl_chunk = b.take<int64_t>(p.cl_chunk.size());
+    o.partial = b.take<char>(p.ch_t.size() * p.q2 * A.scal);
     o.V1 = b.take<double>(p.V1.size());
     o.E = b.take<double>(p.E.size());
     o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
     o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+    o.up_count = b.take<int>((size_t)std::max<int64_t>(1, p.lev_off[up_root_of(p)]));
     if (d) *d = o;
     return b.off + 256;
 }
@@ -117,7 +130,7 @@ static size_t tmp_layout(const bem_operator_s& A, void* base, AsmDev* d) {
     a.sx = b.take<double>(p.sx.size());
     a.sw = b.take<double>(p.sw.size());
     a.cheb = b.take<double>(p.cheb.size());
-    a.far_t = b.take<int32_t>(p.far_t.size());
+    a.own_t = b.take<int32_t>(p.own_t.size());
     a.xc = b.take<double>((size_t)p.ncl * p.q2 * 3);
     a.lb = b.take<char>((size_t)p.near_t.size() * p.nloc * p.nloc * p.nloc * p.nloc * A.scal);
     if (d) *d = a;
@@ -384,8 +397,9 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
 
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr, int nrhs,
                        void* u_dev, int64_t ldu, hipStream_t stream) {
-    if (!s || !rho_dev || !u_dev || (npts > 0 && !pts_dev)) return fail(BEM_EINVAL, "NULL argument");
+    if (!s || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
+    if (npts == 0) return BEM_OK;
     if (ldr < s->S.ndof || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
     if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
     const Gauss8 g8 = gauss8();
@@ -398,9 +412,10 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
 
 int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
     H2Params P;
+    P.chunk = p->chunk_cols == 0 ? 256 : p->chunk_cols;
     P.q = p->q;
     P.eta = p->eta;
     P.leaf = p->leaf_level;
@@ -436,6 +451,9 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     I.tmp_bytes = tmp_layout(*A, nullptr, nullptr);
     I.far_bytes = (double)pl.ktotal * A->scal;
     I.near_bytes = (double)pl.col.size() * (A->scal + 4) + (double)pl.rowptr.size() * 8;
+    I.nstored = (int64_t)pl.own_src.size();
+    I.nchunks = (int64_t)pl.ch_t.size();
+    I.transposed_bytes = (double)pl.ptotal * A->scal;
     if (info) *info = I;
     *out = A;
     return BEM_OK;
@@ -478,6 +496,11 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     d.ncl = p.ncl;
     d.nleaves = p.nleaves;
     d.nfar = (int64_t)p.far_t.size();
+    d.nstored = (int64_t)p.own_src.size();
+    d.up_root = up_root_of(p);
+    d.up_depth = p.leaf - d.up_root;
+    d.tile = std::min(p.nleaf1, 4);
+    d.nchunks = (int64_t)p.ch_t.size();
     d.nnear = (int64_t)p.near_t.size();
     d.ntouch = (int64_t)(p.touch.size() / 5);
     d.nnz = (int64_t)p.col.size();
@@ -489,10 +512,17 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(d.lev_off, p.lev_off.data(), p.lev_off.size() * 8));
     HIP_CHECK(up(d.rowptr, p.rowptr.data(), p.rowptr.size() * 8));
     HIP_CHECK(up(d.col, p.col.data(), p.col.size() * 4));
-    HIP_CHECK(up(d.far_rowptr, p.far_rowptr.data(), p.far_rowptr.size() * 8));
-    HIP_CHECK(up(d.far_s, p.far_s.data(), p.far_s.size() * 4));
+    HIP_CHECK(up(d.own_rowptr, p.own_rowptr.data(), p.own_rowptr.size() * 8));
+    HIP_CHECK(up(d.own_src, p.own_src.data(), p.own_src.size() * 4));
     HIP_CHECK(up(d.koff, p.koff.data(), p.koff.size() * 8));
     HIP_CHECK(up(d.krs, p.krs.data(), p.krs.size() * 4));
+    HIP_CHECK(up(d.pcol, p.pcol.data(), p.pcol.size() * 8));
+    HIP_CHECK(up(d.tr_rowptr, p.tr_rowptr.data(), p.tr_rowptr.size() * 8));
+    HIP_CHECK(up(d.tr_off, p.tr_off.data(), p.tr_off.size() * 8));
+    HIP_CHECK(up(d.ch_t, p.ch_t.data(), p.ch_t.size() * 4));
+    HIP_CHECK(up(d.ch_k0, p.ch_k0.data(), p.ch_k0.size() * 4));
+    HIP_CHECK(up(d.ch_k1, p.ch_k1.data(), p.ch_k1.size() * 4));
+    HIP_CHECK(up(d.cl_chunk, p.cl_chunk.data(), p.cl_chunk.size() * 8));
     HIP_CHECK(up(d.V1, p.V1.data(), p.V1.size() * 8));
     HIP_CHECK(up(d.E, p.E.data(), p.E.size() * 8));
     HIP_CHECK(up(as.near_t, p.near_t.data(), p.near_t.size() * 4));
@@ -508,9 +538,11 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(as.sx, p.sx.data(), p.sx.size() * 8));
     HIP_CHECK(up(as.sw, p.sw.data(), p.sw.size() * 8));
     HIP_CHECK(up(as.cheb, p.cheb.data(), p.cheb.size() * 8));
-    HIP_CHECK(up(as.far_t, p.far_t.data(), p.far_t.size() * 4));
+    HIP_CHECK(up(as.own_t, p.own_t.data(), p.own_t.size() * 4));
     // coupling rows are padded to even length: clear them before the blocks are written
     if (p.ktotal > 0) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
+    // upward-pass counters start at zero; each matvec leaves them at zero
+    HIP_CHECK(hipMemsetAsync(d.up_count, 0, (size_t)std::max<int64_t>(1, p.lev_off[d.up_root]) * sizeof(int), stream));
     HIP_CHECK(launch_gauss_points(d, as, stream));
     HIP_CHECK(launch_near_regular(d, as, stream));
     HIP_CHECK(launch_near_singular(d, as, stream));
@@ -647,12 +679,21 @@ int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t s
         HIP_CHECK(hipMemcpyAsync(K.data(), A->dev.K, K.size(), hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
         const int q2 = p.q2;
+        const size_t sc = A->scal;
         for (size_t i = 0; i < nf; ++i) {
-            const int t = p.far_t[i];
-            const int64_t slot = (int64_t)i - p.far_rowptr[t];
+            const int t = p.far_t[i], s = p.far_s[i];
+            // the pair is stored in the row of its owner; the partner sees the transpose
+            const int lo = std::min(t, s), hi = std::max(t, s);
+            const int owner = ((lo + hi) & 1) ? lo : hi, other = owner == t ? s : t;
+            auto first = p.own_src.begin() + p.own_rowptr[owner], last = p.own_src.begin() + p.own_rowptr[owner + 1];
+            const int64_t slot = std::lower_bound(first, last, other) - first;
+            const char* rows = K.data() + p.koff[owner] * sc;
             for (int a = 0; a < q2; ++a)
-                std::memcpy((char*)blocks + ((i * q2 + a) * q2) * A->scal,
-                            K.data() + (p.koff[t] + (int64_t)a * p.krs[t] + slot * q2) * A->scal, q2 * A->scal);
+                for (int b = 0; b < q2; ++b) {
+                    const int ra = owner == t ? a : b, cb = owner == t ? b : a;
+                    std::memcpy((char*)blocks + ((i * q2 + a) * q2 + b) * sc,
+                                rows + ((int64_t)ra * p.krs[owner] + slot * q2 + cb) * sc, sc);
+                }
         }
     }
     return BEM_OK;

@@ -45,18 +45,34 @@ struct OpDev {
     const int64_t* rowptr;
     const int32_t* col;
     void* val;
-    // far field
-    const int64_t* far_rowptr;
-    const int32_t* far_s;
+    // far field: stored blocks in owner rows (see the host plan)
+    const int64_t* own_rowptr;
+    const int32_t* own_src;
     const int64_t* koff;
     const int32_t* krs;
     void* K;
+    const int64_t* pcol;       // owner row -> start in P
+    void* P;                   // transposed products, one scalar per stored column
+    const int64_t* tr_rowptr;  // per cluster: its entries in tr_off
+    const int64_t* tr_off;     // start of a q*q column group in P
+    int64_t nchunks, nstored;
+    const int32_t* ch_t;
+    const int32_t* ch_k0;
+    const int32_t* ch_k1;
+    const int64_t* cl_chunk;   // per cluster: its chunks
+    void* partial;             // per chunk: q*q row sums
     // transforms
     const double* V1;  // [nleaf1][q][nloc]
     const double* E;   // [2][q][q]
     // matvec scratch: moments and local expansions of all clusters (one RHS)
     void* mom;
     void* lv;
+    // upward pass: subtrees rooted at level up_root are summed by one block each; the
+    // clusters above are completed by the last of their four children's blocks
+    int up_root, up_depth;
+    int* up_count;  // per cluster above up_root: children finished in this matvec (reset to 0)
+    // downward pass + backward transform: square tiles of leaves per block
+    int tile;
 };
 
 // Temporary arrays used only during assembly.
@@ -76,7 +92,7 @@ struct AsmDev {
     const double* sx;     // [qs]
     const double* sw;     // [qs]
     const double* cheb;   // [q]
-    const int32_t* far_t; // target of each far block
+    const int32_t* own_t; // owner of each stored block
     double* xc;           // [ncl][q2][3] Chebyshev points on the surface
     void* lb;             // [nnear][nloc^2][nloc^2] leaf-pair blocks
 };
@@ -87,8 +103,9 @@ hipError_t launch_near_singular(const OpDev& op, const AsmDev& as, hipStream_t s
 hipError_t launch_near_gather(const OpDev& op, const AsmDev& as, hipStream_t st);
 hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st);
 
-// y = A x for one RHS column, as four stages: 0 forward transform + upward transfer,
-// 1 far-field coupling, 2 downward transfer, 3 backward transform + near field
+// y = A x for one RHS column, as four stages: 0 near-field product with the forward
+// transform + upward transfer beside it, 1 far-field coupling, 2 gather of the local
+// expansions, 3 downward transfer + backward transform added to y
 constexpr int kApplyStages = 4;
 hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, hipStream_t st);
 hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st);

@@ -23,6 +23,11 @@ __device__ inline double wave_sum(double v) {
 }
 __device__ inline cdbl wave_sum(cdbl v) { return {wave_sum(v.re), wave_sum(v.im)}; }
 
+__device__ inline double shfl_xor_t(double v, int off) { return __shfl_xor(v, off, kWave); }
+__device__ inline cdbl shfl_xor_t(cdbl v, int off) { return {__shfl_xor(v.re, off, kWave), __shfl_xor(v.im, off, kWave)}; }
+__device__ inline double shfl_t(double v, int src) { return __shfl(v, src, kWave); }
+__device__ inline cdbl shfl_t(cdbl v, int src) { return {__shfl(v.re, src, kWave), __shfl(v.im, src, kWave)}; }
+
 // leaf-local index -> (patch, i, j)
 __device__ inline void leaf_decode(int l, int n1, int& f, int& i, int& j) {
     j = l % n1;
@@ -375,11 +380,11 @@ __global__ void k_far_assemble(OpDev op, AsmDev as) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q2 = op.q2;
     const int64_t per = (int64_t)q2 * q2;
-    if (idx >= op.nfar * per) return;
+    if (idx >= op.nstored * per) return;
     const int64_t blk = idx / per;
     const int rem = (int)(idx - blk * per), a = rem / q2, b = rem % q2;
-    const int t = as.far_t[blk], s = op.far_s[blk];
-    const int64_t slot = blk - op.far_rowptr[t];
+    const int t = as.own_t[blk], s = op.own_src[blk];
+    const int64_t slot = blk - op.own_rowptr[t];
     const double* x = as.xc + ((int64_t)t * q2 + a) * 3;
     const double* y = as.xc + ((int64_t)s * q2 + b) * 3;
     const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
@@ -387,139 +392,353 @@ __global__ void k_far_assemble(OpDev op, AsmDev as) {
 }
 
 // ------------------------------------------------------------------ H^2 matvec
-// forward transform: moments of every leaf, m[a1,a2] = sum V1_i[a1,m1] V1_j[a2,m2] x[...]
-template <class T>
-__global__ void k_forward(OpDev op, const T* __restrict__ x) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= op.nleaves * op.q2) return;
-    const int a = (int)(idx % op.q2);
-    const int l = (int)(idx / op.q2);
-    const int q = op.q, nloc = op.nloc, stride = op.m * op.S.r;
-    int f, i, j;
-    leaf_decode(l, op.nleaf1, f, i, j);
-    const int a1 = a / q, a2 = a % q;
-    const double* Vi = op.V1 + ((int64_t)i * q + a1) * nloc;
-    const double* Vj = op.V1 + ((int64_t)j * q + a2) * nloc;
-    T acc = zero<T>();
-    for (int m1 = 0; m1 < nloc; ++m1) {
-        T in = zero<T>();
-        const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
-        for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
-        acc += Vi[m1] * in;
-    }
-    ((T*)op.mom)[(op.lev_off[op.leaf] + l) * op.q2 + a] = acc;
-}
-
-// upward transfer at level lev: m_P = sum_children (E_b1 (x) E_b2)^T m_child
-template <class T>
-__global__ void k_upward(OpDev op, int lev) {
-    const int n = 1 << lev;
-    const int64_t ncl = (int64_t)op.S.geom.npatch * n * n;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ncl * op.q2) return;
-    const int q = op.q, q2 = op.q2;
-    const int a = (int)(idx % q2);
-    const int64_t loc = idx / q2;
-    const int j = (int)(loc % n), i = (int)((loc / n) % n), f = (int)(loc / ((int64_t)n * n));
-    const int a1 = a / q, a2 = a % q;
-    const T* mom = (const T*)op.mom;
-    T acc = zero<T>();
-    for (int b1 = 0; b1 < 2; ++b1)
-        for (int b2 = 0; b2 < 2; ++b2) {
-            const int64_t c = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
-            const T* mc = mom + c * q2;
-            for (int p1 = 0; p1 < q; ++p1) {
-                T in = zero<T>();
-                for (int p2 = 0; p2 < q; ++p2) in += op.E[(b2 * q + p2) * q + a2] * mc[p1 * q + p2];
-                acc += op.E[(b1 * q + p1) * q + a1] * in;
-            }
+// Stage 0.  Blocks [0, nup): forward transform of the leaves of one subtree rooted at level
+// up_root and upward transfer inside it (LDS); the clusters above up_root are completed
+// by the last block (of four siblings) to finish, chained up to the patch, with device-
+// scope fences around the counter.  No block ever waits for another.
+// Blocks [nup, ...): near-field product, one wave per row, overwriting y.
+template <class T, int Q>
+__device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict__ x) {
+    constexpr int Q2 = Q * Q;
+    __shared__ double Es[2 * Q * Q];
+    __shared__ T tree[21][Q2];  // levels below the root: 16 + 4 + 1 clusters at most
+    __shared__ int last;
+    for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
+    T* mom = (T*)op.mom;
+    const int r0 = op.up_root, s = op.up_depth, leaf = op.leaf;
+    const int nr = 1 << r0, w = 1 << s;  // roots per direction, leaves per root direction
+    const int f = blk / (nr * nr), loc = blk % (nr * nr), ri = loc / nr, rj = loc % nr;
+    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
+    (void)n1;
+    // LDS slots of the subtree: depth-2 clusters (16) at 0, depth-1 (4) at 16, root at 20
+    const int lb = s == 2 ? 0 : (s == 1 ? 16 : 20);
+    // leaves of this subtree
+    for (int idx = threadIdx.x; idx < w * w * Q2; idx += blockDim.x) {
+        const int a = idx % Q2, l = idx / Q2;
+        const int i = ri * w + l / w, j = rj * w + l % w, a1 = a / Q, a2 = a % Q;
+        const double* Vi = op.V1 + ((int64_t)i * Q + a1) * nloc;
+        const double* Vj = op.V1 + ((int64_t)j * Q + a2) * nloc;
+        T acc = zero<T>();
+#pragma unroll 2
+        for (int m1 = 0; m1 < nloc; ++m1) {
+            const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
+            T in = zero<T>();
+#pragma unroll 6
+            for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
+            acc += Vi[m1] * in;
         }
-    ((T*)op.mom)[(op.lev_off[lev] + loc) * q2 + a] = acc;
+        mom[(op.lev_off[leaf] + ((int64_t)f * n1 + i) * n1 + j) * Q2 + a] = acc;
+        tree[lb + l][a] = acc;
+    }
+    // upward inside the subtree, depth s-1 .. 0 (level r0 + depth)
+    for (int d = s - 1; d >= 0; --d) {
+        __syncthreads();
+        const int cw = 1 << d, lev = r0 + d;
+        const int cb = (d + 1 == s) ? lb : 16, ob = d == 1 ? 16 : 20;
+        for (int idx = threadIdx.x; idx < cw * cw * Q2; idx += blockDim.x) {
+            const int a = idx % Q2, l = idx / Q2, u = l / cw, v = l % cw, a1 = a / Q, a2 = a % Q;
+            T acc = zero<T>();
+#pragma unroll
+            for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    const T* mc = tree[cb + (2 * u + b1) * (2 * cw) + 2 * v + b2];
+#pragma unroll
+                    for (int p1 = 0; p1 < Q; ++p1) {
+                        T in = zero<T>();
+#pragma unroll
+                        for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
+                        acc += Es[(b1 * Q + p1) * Q + a1] * in;
+                    }
+                }
+            tree[ob + l][a] = acc;
+            const int gi = ri * cw + u, gj = rj * cw + v;
+            mom[(op.lev_off[lev] + ((int64_t)f * (nr * cw) + gi) * (nr * cw) + gj) * Q2 + a] = acc;
+        }
+    }
+    // clusters above the root: the last of four siblings completes the parent
+    int lev = r0, ci = ri, cj = rj;
+    while (lev > 0) {
+        __threadfence();
+        __syncthreads();
+        const int pn = 1 << (lev - 1), pi = ci >> 1, pj = cj >> 1;
+        const int64_t parent = op.lev_off[lev - 1] + ((int64_t)f * pn + pi) * pn + pj;
+        if (threadIdx.x == 0) last = atomicAdd(&op.up_count[parent], 1) == 3;
+        __syncthreads();
+        if (!last) return;
+        __threadfence();
+        const int n = 1 << lev;
+        if (threadIdx.x < Q2) {
+            const int a = threadIdx.x, a1 = a / Q, a2 = a % Q;
+            T acc = zero<T>();
+#pragma unroll
+            for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    const int64_t c = op.lev_off[lev] + ((int64_t)f * n + 2 * pi + b1) * n + 2 * pj + b2;
+                    const T* mc = mom + c * Q2;
+#pragma unroll
+                    for (int p1 = 0; p1 < Q; ++p1) {
+                        T in = zero<T>();
+#pragma unroll
+                        for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
+                        acc += Es[(b1 * Q + p1) * Q + a1] * in;
+                    }
+                }
+            mom[parent * Q2 + a] = acc;
+        }
+        if (threadIdx.x == 0) op.up_count[parent] = 0;  // ready for the next matvec
+        lev -= 1;
+        ci = pi;
+        cj = pj;
+    }
 }
 
-// coupling: lv_tau = sum over admissible sigma of K_tau,sigma m_sigma.  One wave per target;
-// the target's coupling rows are stored contiguously (row a = all its blocks' row a), each
-// lane streams columns k and keeps the Q*Q row sums, reduced across the wave at the end.
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    const int nup = op.S.geom.npatch << (2 * op.up_root);
+    if ((int)blockIdx.x < nup) {
+        up_subtree<T, Q>(op, blockIdx.x, x);
+        return;
+    }
+    const int64_t g = (int64_t)(blockIdx.x - nup) * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= op.S.ndof) return;
+    const T* __restrict__ val = (const T*)op.val;
+    const int32_t* __restrict__ col = op.col;
+    const int64_t k0 = op.rowptr[g], k1 = op.rowptr[g + 1];
+    T acc0 = zero<T>(), acc1 = zero<T>();
+    int64_t k = k0 + lane;
+    for (; k + kWave < k1; k += 2 * kWave) {
+        const int c0 = col[k], c1 = col[k + kWave];
+        const T v0 = val[k], v1 = val[k + kWave];
+        acc0 += v0 * x[c0];
+        acc1 += v1 * x[c1];
+    }
+    if (k < k1) acc0 += val[k] * x[col[k]];
+    const T s = wave_sum(acc0 + acc1);
+    if (lane == 0) y[g] = s;
+}
+
+// Reduce-scatter of Q2 per-lane values across the wave: after the six butterfly steps
+// lane l holds the wave sum of one index (returned in `idx`, valid if `ok`).
+template <class T, int C>
+__device__ inline void rs_step(T* v, bool upper, int off) {
+    constexpr int H = (C + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const T lo = v[i];
+        const T hi = (i + H < C) ? v[i + H] : zero<T>();
+        const T send = upper ? lo : hi;
+        const T keep = upper ? hi : lo;
+        v[i] = keep + shfl_xor_t(send, off);
+    }
+}
+
+template <int C>
+__device__ inline void rs_index(int lane, int off, int& base, int& real) {
+    constexpr int H = (C + 1) / 2;
+    if (lane & off) {
+        base += H;
+        real = real > H ? real - H : 0;
+    } else {
+        real = real < H ? real : H;
+    }
+}
+
+template <class T, int Q2>
+__device__ inline void wave_reduce_scatter(T* v, int lane, int& idx, bool& ok) {
+    constexpr int C1 = Q2, C2 = (C1 + 1) / 2, C3 = (C2 + 1) / 2, C4 = (C3 + 1) / 2, C5 = (C4 + 1) / 2,
+                  C6 = (C5 + 1) / 2;
+    rs_step<T, C1>(v, lane & 32, 32);
+    rs_step<T, C2>(v, lane & 16, 16);
+    rs_step<T, C3>(v, lane & 8, 8);
+    rs_step<T, C4>(v, lane & 4, 4);
+    rs_step<T, C5>(v, lane & 2, 2);
+    rs_step<T, C6>(v, lane & 1, 1);
+    int base = 0, real = Q2;
+    rs_index<C1>(lane, 32, base, real);
+    rs_index<C2>(lane, 16, base, real);
+    rs_index<C3>(lane, 8, base, real);
+    rs_index<C4>(lane, 4, base, real);
+    rs_index<C5>(lane, 2, base, real);
+    rs_index<C6>(lane, 1, base, real);
+    idx = base;
+    ok = real > 0;
+}
+
+template <class T>
+struct Pair {
+    T x, y;
+};
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// two adjacent scalars of a stream that is read once per matvec (non-temporal hint)
+__device__ inline Pair<double> load_stream(const double* p) {
+    const dvec2 v = __builtin_nontemporal_load((const dvec2*)p);
+    return {v.x, v.y};
+}
+__device__ inline Pair<cdbl> load_stream(const cdbl* p) {
+    const dvec2 a = __builtin_nontemporal_load((const dvec2*)p);
+    const dvec2 b = __builtin_nontemporal_load((const dvec2*)p + 1);
+    return {{a.x, a.y}, {b.x, b.y}};
+}
+
+// Stage 1.  Far-field coupling over the stored blocks, one wave per chunk of an owner's
+// row-concatenated coupling rows.  Each lane takes two adjacent columns (sigma, b) per
+// step: it loads the owner's Q2 row entries of both (16-byte loads, coalesced across the
+// wave), accumulates K m_sigma into Q2 row sums, and forms the transposed product
+// (K^T m_owner) of its columns, stored once per column.  Row sums are reduce-scattered
+// across the wave into the chunk's partial sums.
 template <class T, int Q>
 __global__ __launch_bounds__(256) void k_coupling(OpDev op) {
     constexpr int Q2 = Q * Q;
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (t >= op.ncl) return;
-    const int64_t beg = op.far_rowptr[t], n = op.far_rowptr[t + 1] - beg;
+    if (c >= op.nchunks) return;
+    const int t = op.ch_t[c], k0 = op.ch_k0[c], k1 = op.ch_k1[c];
     const int64_t rs = op.krs[t];
-    const T* base = (const T*)op.K + op.koff[t];
-    const T* mom = (const T*)op.mom;
+    const int64_t beg = op.own_rowptr[t];
+    const int ncols = (int)(op.own_rowptr[t + 1] - beg) * Q2;
+    const T* __restrict__ base = (const T*)op.K + op.koff[t];
+    const int32_t* __restrict__ src = op.own_src + beg;
+    const T* __restrict__ mom = (const T*)op.mom;
+    T* __restrict__ P = (T*)op.P + op.pcol[t];
+    T mown[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) mown[a] = mom[(int64_t)t * Q2 + a];
     T acc[Q2];
 #pragma unroll
     for (int a = 0; a < Q2; ++a) acc[a] = zero<T>();
-    for (int64_t k = lane; k < n * Q2; k += kWave) {
-        const int64_t s = k / Q2;
-        const int b = (int)(k - s * Q2);
-        const T mv = mom[(int64_t)op.far_s[beg + s] * Q2 + b];
+    for (int k = k0 + 2 * lane; k < k1; k += 2 * kWave) {
+        const int s0 = k / Q2, b0 = k - s0 * Q2;
+        const T m0 = mom[(int64_t)src[s0] * Q2 + b0];
+        T m1 = zero<T>();
+        if (k + 1 < ncols) {
+            const int s1 = (k + 1) / Q2, b1 = (k + 1) - s1 * Q2;
+            m1 = mom[(int64_t)src[s1] * Q2 + b1];
+        }
+        T p0 = zero<T>(), p1 = zero<T>();
 #pragma unroll
-        for (int a = 0; a < Q2; ++a) acc[a] += base[a * rs + k] * mv;
+        for (int a = 0; a < Q2; ++a) {
+            const Pair<T> kv = load_stream(base + a * rs + k);
+            acc[a] += kv.x * m0 + kv.y * m1;
+            p0 += kv.x * mown[a];
+            p1 += kv.y * mown[a];
+        }
+        *(Pair<T>*)(P + k) = Pair<T>{p0, p1};
     }
-    T* lv = (T*)op.lv + t * Q2;
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) {
-        const T s = wave_sum(acc[a]);
-        if (lane == 0) lv[a] = s;
-    }
+    int idx;
+    bool ok;
+    wave_reduce_scatter<T, Q2>(acc, lane, idx, ok);
+    if (ok) ((T*)op.partial)[c * Q2 + idx] = acc[0];
 }
 
-// downward transfer at level lev >= 1: lv_c += (E_b1 (x) E_b2) lv_parent
-template <class T>
-__global__ void k_downward(OpDev op, int lev) {
-    const int n = 1 << lev;
-    const int64_t ncl = (int64_t)op.S.geom.npatch * n * n;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ncl * op.q2) return;
-    const int q = op.q, q2 = op.q2;
-    const int p = (int)(idx % q2);
-    const int64_t loc = idx / q2;
-    const int j = (int)(loc % n), i = (int)((loc / n) % n), f = (int)(loc / ((int64_t)n * n));
-    const int p1 = p / q, p2 = p % q, b1 = i & 1, b2 = j & 1;
-    const int64_t P = op.lev_off[lev - 1] + ((int64_t)f * (n / 2) + i / 2) * (n / 2) + j / 2;
-    T* lv = (T*)op.lv;
-    const T* lp = lv + P * q2;
-    T acc = zero<T>();
-    for (int a1 = 0; a1 < q; ++a1) {
-        T in = zero<T>();
-        for (int a2 = 0; a2 < q; ++a2) in += op.E[(b2 * q + p2) * q + a2] * lp[a1 * q + a2];
-        acc += op.E[(b1 * q + p1) * q + a1] * in;
-    }
-    lv[(op.lev_off[lev] + loc) * q2 + p] += acc;
-}
-
-// backward transform plus near field: y_g = sum_tau (V_tau^T lv_tau)_g + sum_h A_near[g,h] x_h.
-// One wave per row.
-template <class T>
-__global__ __launch_bounds__(256) void k_back_near(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
-    const SpaceDesc S = op.S;
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// Stage 2a.  Local expansion of every cluster: its chunks' row sums plus the transposed
+// products of the blocks stored in its partners' rows.  One wave per cluster; the two
+// half-waves take alternate entries (lane & 31 = component), then add.
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_lv_gather(OpDev op) {
+    constexpr int Q2 = Q * Q;
+    static_assert(Q2 <= 64, "q <= 8");
+    const int64_t t = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (g >= S.ndof) return;
-    const T* val = (const T*)op.val;
-    T acc = zero<T>();
-    for (int64_t k = op.rowptr[g] + lane; k < op.rowptr[g + 1]; k += kWave) acc += val[k] * x[op.col[k]];
-    const int nb = S.nb, n1 = op.nleaf1, nloc = op.nloc, stride = op.m * S.r, q = op.q, q2 = op.q2;
-    const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
-    int lo1, hi1, lo2, hi2;
-    leaf_range(j1, stride, nloc, n1, lo1, hi1);
-    leaf_range(j2, stride, nloc, n1, lo2, hi2);
-    const int nl_a = hi1 - lo1 + 1, nl_b = hi2 - lo2 + 1;
-    const T* lv = (const T*)op.lv + op.lev_off[op.leaf] * q2;
-    for (int t = lane; t < nl_a * nl_b * q2; t += kWave) {
-        const int a = t % q2, lf = t / q2;
-        const int li = lo1 + lf / nl_b, lj = lo2 + lf % nl_b;
-        const int a1 = a / q, a2 = a % q;
-        const double c = op.V1[((int64_t)li * q + a1) * nloc + (j1 - li * stride)] *
-                         op.V1[((int64_t)lj * q + a2) * nloc + (j2 - lj * stride)];
-        acc += c * lv[((int64_t)(f * n1 + li) * n1 + lj) * q2 + a];
+    if (t >= op.ncl) return;
+    const T* __restrict__ partial = (const T*)op.partial;
+    const T* __restrict__ P = (const T*)op.P;
+    T v = zero<T>();
+    if (Q2 <= 32) {
+        const int a = lane & 31, h = lane >> 5;
+        if (a < Q2) {
+            for (int64_t c = op.cl_chunk[t] + h; c < op.cl_chunk[t + 1]; c += 2) v += partial[c * Q2 + a];
+            const int64_t e0 = op.tr_rowptr[t], e1 = op.tr_rowptr[t + 1];
+#pragma unroll 4
+            for (int64_t e = e0 + h; e < e1; e += 2) v += P[op.tr_off[e] + a];
+        }
+        v += shfl_xor_t(v, 32);
+        if (lane < Q2) ((T*)op.lv)[t * Q2 + lane] = v;
+    } else {
+        if (lane < Q2) {
+            for (int64_t c = op.cl_chunk[t]; c < op.cl_chunk[t + 1]; ++c) v += partial[c * Q2 + lane];
+#pragma unroll 4
+            for (int64_t e = op.tr_rowptr[t]; e < op.tr_rowptr[t + 1]; ++e) v += P[op.tr_off[e] + lane];
+            ((T*)op.lv)[t * Q2 + lane] = v;
+        }
     }
-    const T s = wave_sum(acc);
-    if (lane == 0) y[g] = s;
+}
+
+// Stage 2b + 3.  Downward transfer and backward transform per tile of TxT leaves: every
+// leaf of the tile and of a one-leaf halo gets its total local expansion along its
+// ancestor chain (v_0 = lv(patch), v_l = (E_b1 (x) E_b2) v_{l-1} + lv(ancestor at level
+// l)) in LDS; then every DOF whose first B-spline lies in the tile adds
+// sum over its leaves of (V_tau^T v_tau) to y.
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_down_back(OpDev op, T* __restrict__ y) {
+    constexpr int Q2 = Q * Q;
+    constexpr int TMAX = 4, HW = TMAX + 2;  // tile and tile + halo (leaves per direction)
+    __shared__ double Es[2 * Q * Q];
+    __shared__ T vbuf[2][HW * HW][Q2];
+    for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
+    const int T1 = op.tile, n1 = op.nleaf1, nt = n1 / T1;
+    const int f = blockIdx.x / (nt * nt), loc = blockIdx.x % (nt * nt);
+    const int ti = (loc / nt) * T1, tj = (loc % nt) * T1;
+    // halo-extended leaf range, clamped to the patch
+    const int i0 = max(ti - 1, 0), i1 = min(ti + T1, n1 - 1), j0 = max(tj - 1, 0), j1 = min(tj + T1, n1 - 1);
+    const int wi = i1 - i0 + 1, wj = j1 - j0 + 1, nl = wi * wj;
+    const T* lv = (const T*)op.lv;
+    int cur = 0;
+    // level 0: the patch's own expansion for every leaf
+    for (int idx = threadIdx.x; idx < nl * Q2; idx += blockDim.x)
+        vbuf[0][idx / Q2][idx % Q2] = lv[(op.lev_off[0] + f) * Q2 + idx % Q2];
+    for (int lev = 1; lev <= op.leaf; ++lev) {
+        __syncthreads();
+        const int sh = op.leaf - lev, n = 1 << lev;
+        for (int idx = threadIdx.x; idx < nl * Q2; idx += blockDim.x) {
+            const int p = idx % Q2, l = idx / Q2, p1 = p / Q, p2 = p % Q;
+            const int li = i0 + l / wj, lj = j0 + l % wj;
+            const int ai = li >> sh, aj = lj >> sh, b1 = ai & 1, b2 = aj & 1;
+            const T* v = vbuf[cur][l];
+            T acc = zero<T>();
+#pragma unroll
+            for (int a1 = 0; a1 < Q; ++a1) {
+                T in = zero<T>();
+#pragma unroll
+                for (int a2 = 0; a2 < Q; ++a2) in += Es[(b2 * Q + p2) * Q + a2] * v[a1 * Q + a2];
+                acc += Es[(b1 * Q + p1) * Q + a1] * in;
+            }
+            vbuf[cur ^ 1][l][p] = acc + lv[(op.lev_off[lev] + ((int64_t)f * n + ai) * n + aj) * Q2 + p];
+        }
+        cur ^= 1;
+    }
+    __syncthreads();
+    // DOFs owned by the tile: first B-spline index in [ti*stride, (ti+T1)*stride), the last
+    // tile also owning the trailing ones
+    const int nb = op.S.nb, nloc = op.nloc, stride = op.m * op.S.r;
+    const int g1a = ti * stride, g1b = (ti + T1 >= n1) ? nb : (ti + T1) * stride;
+    const int g2a = tj * stride, g2b = (tj + T1 >= n1) ? nb : (tj + T1) * stride;
+    const int nw = g2b - g2a;
+    for (int idx = threadIdx.x; idx < (g1b - g1a) * nw; idx += blockDim.x) {
+        const int jj1 = g1a + idx / nw, jj2 = g2a + idx % nw;
+        int lo1, hi1, lo2, hi2;
+        leaf_range(jj1, stride, nloc, n1, lo1, hi1);
+        leaf_range(jj2, stride, nloc, n1, lo2, hi2);
+        T acc = zero<T>();
+        for (int li = lo1; li <= hi1; ++li)
+            for (int lj = lo2; lj <= hi2; ++lj) {
+                const T* L = vbuf[cur][(li - i0) * wj + (lj - j0)];
+                const double* Vi = op.V1 + (int64_t)li * Q * nloc + (jj1 - li * stride);
+                const double* Vj = op.V1 + (int64_t)lj * Q * nloc + (jj2 - lj * stride);
+#pragma unroll
+                for (int a1 = 0; a1 < Q; ++a1) {
+                    T in = zero<T>();
+#pragma unroll
+                    for (int a2 = 0; a2 < Q; ++a2) in += Vj[a2 * nloc] * L[a1 * Q + a2];
+                    acc += Vi[a1 * nloc] * in;
+                }
+            }
+        y[dof_id(op.S, f, jj1, jj2)] += acc;
+    }
 }
 
 // ------------------------------------------------------------------ load vector and potential
@@ -763,8 +982,9 @@ hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st
     const int64_t np = op.ncl * op.q2;
     hipLaunchKernelGGL(k_cluster_points, dim3(nblk(np, 256)), dim3(256), 0, st, op, as);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || op.nfar == 0) return e;
-    const int64_t n = op.nfar * op.q2 * op.q2;
+    if (e != hipSuccess) return e;
+    const int64_t n = op.nstored * op.q2 * op.q2;
+    if (n == 0) return hipSuccess;
     if (op.cplx)
         hipLaunchKernelGGL(k_far_assemble<cdbl>, dim3(nblk(n, 256)), dim3(256), 0, st, op, as);
     else
@@ -772,55 +992,49 @@ hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st
     return hipGetLastError();
 }
 
-template <class T>
-static hipError_t moments_t(const OpDev& op, const T* x, hipStream_t st) {
-    const int64_t n = op.nleaves * op.q2;
-    hipLaunchKernelGGL(k_forward<T>, dim3(nblk(n, 256)), dim3(256), 0, st, op, x);
-    for (int lev = op.leaf - 1; lev >= 0; --lev) {
-        const int64_t nc = (int64_t)op.S.geom.npatch * (1LL << (2 * lev)) * op.q2;
-        hipLaunchKernelGGL(k_upward<T>, dim3(nblk(nc, 256)), dim3(256), 0, st, op, lev);
-    }
-    return hipGetLastError();
-}
-
-template <class T>
-static hipError_t coupling_t(const OpDev& op, hipStream_t st) {
-    const dim3 g(nblk(op.ncl, 4)), b(256);
-    switch (op.q) {
-        case 1: hipLaunchKernelGGL((k_coupling<T, 1>), g, b, 0, st, op); break;
-        case 2: hipLaunchKernelGGL((k_coupling<T, 2>), g, b, 0, st, op); break;
-        case 3: hipLaunchKernelGGL((k_coupling<T, 3>), g, b, 0, st, op); break;
-        case 4: hipLaunchKernelGGL((k_coupling<T, 4>), g, b, 0, st, op); break;
-        case 5: hipLaunchKernelGGL((k_coupling<T, 5>), g, b, 0, st, op); break;
-        case 6: hipLaunchKernelGGL((k_coupling<T, 6>), g, b, 0, st, op); break;
-        case 7: hipLaunchKernelGGL((k_coupling<T, 7>), g, b, 0, st, op); break;
-        default: hipLaunchKernelGGL((k_coupling<T, 8>), g, b, 0, st, op); break;
-    }
-    return hipGetLastError();
-}
-
-template <class T>
-static hipError_t apply_stage_t(const OpDev& op, int stage, const T* x, T* y, hipStream_t st) {
+template <class T, int Q>
+static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, bool with_near, hipStream_t st) {
     switch (stage) {
-        case 0:
-            return moments_t<T>(op, x, st);
+        case 0: {
+            const unsigned nup = (unsigned)op.S.geom.npatch << (2 * op.up_root);
+            const unsigned nb = nup + (with_near ? nblk(op.S.ndof, 4) : 0u);
+            hipLaunchKernelGGL((k_near_up<T, Q>), dim3(nb), dim3(256), 0, st, op, x, y);
+            break;
+        }
         case 1:
-            return coupling_t<T>(op, st);
+            if (op.nchunks > 0) hipLaunchKernelGGL((k_coupling<T, Q>), dim3(nblk(op.nchunks, 4)), dim3(256), 0, st, op);
+            break;
         case 2:
-            for (int lev = 1; lev <= op.leaf; ++lev) {
-                const int64_t nc = (int64_t)op.S.geom.npatch * (1LL << (2 * lev)) * op.q2;
-                hipLaunchKernelGGL(k_downward<T>, dim3(nblk(nc, 256)), dim3(256), 0, st, op, lev);
-            }
-            return hipGetLastError();
+            if (op.nstored > 0) hipLaunchKernelGGL((k_lv_gather<T, Q>), dim3(nblk(op.ncl, 4)), dim3(256), 0, st, op);
+            break;
         default:
-            hipLaunchKernelGGL(k_back_near<T>, dim3(nblk(op.S.ndof, 4)), dim3(256), 0, st, op, x, y);
-            return hipGetLastError();
+            if (op.nstored > 0) {
+                const int nt = op.nleaf1 / op.tile;
+                hipLaunchKernelGGL((k_down_back<T, Q>), dim3((unsigned)(op.S.geom.npatch * nt * nt)), dim3(256), 0, st,
+                                   op, y);
+            }
+            break;
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t apply_stage_t(const OpDev& op, int stage, const T* x, T* y, bool with_near, hipStream_t st) {
+    switch (op.q) {
+        case 1: return apply_stage_tq<T, 1>(op, stage, x, y, with_near, st);
+        case 2: return apply_stage_tq<T, 2>(op, stage, x, y, with_near, st);
+        case 3: return apply_stage_tq<T, 3>(op, stage, x, y, with_near, st);
+        case 4: return apply_stage_tq<T, 4>(op, stage, x, y, with_near, st);
+        case 5: return apply_stage_tq<T, 5>(op, stage, x, y, with_near, st);
+        case 6: return apply_stage_tq<T, 6>(op, stage, x, y, with_near, st);
+        case 7: return apply_stage_tq<T, 7>(op, stage, x, y, with_near, st);
+        default: return apply_stage_tq<T, 8>(op, stage, x, y, with_near, st);
     }
 }
 
 hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, hipStream_t st) {
-    if (op.cplx) return apply_stage_t<cdbl>(op, stage, (const cdbl*)x, (cdbl*)y, st);
-    return apply_stage_t<double>(op, stage, (const double*)x, (double*)y, st);
+    if (op.cplx) return apply_stage_t<cdbl>(op, stage, (const cdbl*)x, (cdbl*)y, true, st);
+    return apply_stage_t<double>(op, stage, (const double*)x, (double*)y, true, st);
 }
 
 hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st) {
@@ -832,8 +1046,8 @@ hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st)
 }
 
 hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st) {
-    if (op.cplx) return moments_t<cdbl>(op, (const cdbl*)x, st);
-    return moments_t<double>(op, (const double*)x, st);
+    if (op.cplx) return apply_stage_t<cdbl>(op, 0, (const cdbl*)x, nullptr, false, st);
+    return apply_stage_t<double>(op, 0, (const double*)x, nullptr, false, st);
 }
 
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,

@@ -390,6 +390,10 @@ bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& p, std::string& err
         err = "eta must be finite and >= 0";
         return false;
     }
+    if (P.chunk < 128 || P.chunk % 128 != 0 || P.chunk > (1 << 20)) {
+        err = "chunk_cols must be a positive multiple of 128";
+        return false;
+    }
     if (P.qg < 1 || P.qg > 16 || P.qs < 1 || P.qs > 16) {
         err = "qg and qs must lie in [1, 16]";
         return false;
@@ -422,17 +426,52 @@ bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& p, std::string& err
     p.far_rowptr.assign(p.ncl + 1, 0);
     for (auto& f : far) p.far_rowptr[f.first + 1]++;
     for (int64_t c = 0; c < p.ncl; ++c) p.far_rowptr[c + 1] += p.far_rowptr[c];
+    // stored blocks: each unordered pair once, in its owner's rows
+    std::vector<std::vector<int32_t>> own(p.ncl), tr(p.ncl);
+    for (auto& f : far) {
+        const int32_t a = std::min(f.first, f.second), b = std::max(f.first, f.second);
+        if (f.first != a) continue;  // visit each unordered pair once
+        const int32_t owner = ((a + b) & 1) ? a : b, other = owner == a ? b : a;
+        own[owner].push_back(other);
+    }
+    p.own_rowptr.assign(p.ncl + 1, 0);
     p.koff.assign(p.ncl, 0);
     p.krs.assign(p.ncl, 0);
-    int64_t off = 0;
+    p.pcol.assign(p.ncl, 0);
+    p.cl_chunk.assign(p.ncl + 1, 0);
+    int64_t off = 0, poff = 0;
     for (int64_t c = 0; c < p.ncl; ++c) {
-        const int64_t n = p.far_rowptr[c + 1] - p.far_rowptr[c];
+        std::sort(own[c].begin(), own[c].end());
+        const int64_t n = (int64_t)own[c].size();
         const int64_t rs = ((n * p.q2) + 1) / 2 * 2;  // even row length for paired loads
         p.koff[c] = off;
         p.krs[c] = (int32_t)rs;
+        p.pcol[c] = poff;
+        for (int64_t s = 0; s < n; ++s) {
+            p.own_src.push_back(own[c][s]);
+            p.own_t.push_back((int32_t)c);
+            tr[own[c][s]].push_back(0);  // counted below
+        }
+        p.own_rowptr[c + 1] = p.own_rowptr[c] + n;
+        for (int64_t k0 = 0; k0 < rs; k0 += P.chunk) {
+            p.ch_t.push_back((int32_t)c);
+            p.ch_k0.push_back((int32_t)k0);
+            p.ch_k1.push_back((int32_t)std::min<int64_t>(rs, k0 + P.chunk));
+        }
+        p.cl_chunk[c + 1] = (int64_t)p.ch_t.size();
         off += rs * p.q2;
+        poff += rs;
     }
     p.ktotal = off;
+    p.ptotal = poff;
+    // transposed lists: for each partner, the offsets of its columns in the owners' rows
+    p.tr_rowptr.assign(p.ncl + 1, 0);
+    for (int64_t c = 0; c < p.ncl; ++c) p.tr_rowptr[c + 1] = p.tr_rowptr[c] + (int64_t)tr[c].size();
+    p.tr_off.assign(p.tr_rowptr[p.ncl], 0);
+    std::vector<int64_t> fill(p.tr_rowptr.begin(), p.tr_rowptr.end() - 1);
+    for (int64_t c = 0; c < p.ncl; ++c)
+        for (int64_t s = p.own_rowptr[c]; s < p.own_rowptr[c + 1]; ++s)
+            p.tr_off[fill[p.own_src[s]]++] = p.pcol[c] + (s - p.own_rowptr[c]) * p.q2;
 
     p.near_t.resize(nearp.size());
     p.near_s.resize(nearp.size());

@@ -28,6 +28,7 @@ struct H2Params {
     int leaf = -1;
     int qg = 8;
     int qs = 8;
+    int chunk = 256;  // columns per coupling work chunk (multiple of 128)
 };
 
 struct Plan {
@@ -43,12 +44,28 @@ struct Plan {
     std::vector<int64_t> lev_off;  // first cluster of each level (size leaf+2)
     std::vector<double> ball;      // centre xyz + radius per cluster
 
-    // far field: both orientations, sorted by (target, source)
+    // far field: all admissible pairs in both orientations, sorted by (target, source)
     std::vector<int32_t> far_t, far_s;
     std::vector<int64_t> far_rowptr;  // per cluster
-    std::vector<int64_t> koff;        // start of each target's coupling rows (scalars)
-    std::vector<int32_t> krs;         // row stride of each target's coupling rows
+
+    // Stored coupling blocks.  K_st = K_ts^T, so every unordered admissible pair is stored
+    // once, in the rows of its owner: the smaller index if the index sum is odd, else the
+    // larger (this splits each cluster's partners about evenly between the two roles).
+    std::vector<int64_t> own_rowptr;  // per cluster: range of its stored blocks
+    std::vector<int32_t> own_src;     // the partner of each stored block
+    std::vector<int32_t> own_t;       // the owner of each stored block
+    std::vector<int64_t> koff;        // start of each owner's coupling rows (scalars)
+    std::vector<int32_t> krs;         // row stride of each owner's rows (even)
     int64_t ktotal = 0;               // scalars in all coupling rows
+    // transposed products: one scalar per stored column, owner rows laid out like K's row 0
+    std::vector<int64_t> pcol;        // start of each owner's columns in that buffer
+    int64_t ptotal = 0;
+    std::vector<int64_t> tr_rowptr;   // per cluster: stored blocks in which it is the partner
+    std::vector<int64_t> tr_off;      // ... as offsets of their q*q columns in the buffer
+    // work chunks of the coupling kernel: (owner, first column, end column), per owner
+    // contiguous; every chunk but an owner's last has P.chunk columns
+    std::vector<int32_t> ch_t, ch_k0, ch_k1;
+    std::vector<int64_t> cl_chunk;    // per cluster: its chunk range
 
     // near field: leaf pairs (leaf-local indices), sorted
     std::vector<int32_t> near_t, near_s;
