@@ -83,7 +83,7 @@ typedef struct bem_h2_params {
     int leaf_level;   /* cluster-tree leaf level, 0..L; -1 picks max(L-2, 0)             */
     int qg;           /* Gauss points per direction on each element of a regular pair   */
     int qs;           /* Gauss points per dimension of each Duffy cube (touching pairs)  */
-    int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 256     */
+    int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 128     */
     int reserved[3];  /* must be zero */
 } bem_h2_params;
 
@@ -179,11 +179,14 @@ int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64
 int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes);
 
 /* Restarted GMRES(m) on A (Sec. 4 "Solution of the System of Linear Equations"), x0 = 0,
- * classical Gram-Schmidt with reorthogonalisation, Givens rotations, stop on the true
- * relative residual.  b_dev, x_dev: device N x nrhs column-major; x is overwritten with the
- * best iterate.  stats: host array of nrhs entries.  ws: device workspace of >= the bytes
- * from bem_solve_plan.  Synchronises the stream.  Returns ENOCONV (stats and x still
- * written) if some right-hand side misses the tolerance within maxit steps. */
+ * classical Gram-Schmidt with one reorthogonalisation, Givens rotations and the triangular
+ * solve on the device; a cycle ends early when the rotated residual estimate of a step
+ * reaches tol, and convergence is decided on the true relative residual computed at the
+ * start of the next cycle.  1 <= restart <= 64.  b_dev, x_dev: device N x nrhs
+ * column-major; x is overwritten with the last iterate.  stats: host array of nrhs
+ * entries.  ws: device workspace of >= the bytes from bem_solve_plan.  Blocks the calling
+ * thread until the solve is done.  Returns ENOCONV (stats and x still written) if some
+ * right-hand side misses the tolerance within maxit steps. */
 int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64_t ldx, int nrhs,
               const bem_solve_params* p, bem_solve_stats* stats, void* ws, size_t ws_bytes,
               hipStream_t stream);

@@ -14,6 +14,7 @@
 
 #include "bem_kernels.h"
 #include "bem_plan.h"
+#include "bem_solve.h"
 
 using namespace bem;
 
@@ -71,8 +72,13 @@ struct bem_operator_s {
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kApplyStages + 1 events per recorded apply
     size_t ev_used = 0;
+    // GMRES: pinned status words and per-step events
+    double* pinned = nullptr;
+    std::vector<hipEvent_t> sev;
     ~bem_operator_s() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : sev) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 
@@ -87,6 +93,9 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     o.rowptr = b.take<int64_t>(p.rowptr.size());
     o.col = b.take<int32_t>(p.col.size());
     o.val = b.take<char>(p.col.size() * A.scal);
+    o.grp_rowptr = b.take<int64_t>(p.grp_rowptr.size());
+    o.grp_rows = b.take<int32_t>(p.grp_rows.size());
+    o.grp_voff = b.take<int64_t>(p.grp_voff.size());
     o.own_rowptr = b.take<int64_t>(p.own_rowptr.size());
     o.own_src = b.take<int32_t>(p.own_src.size());
     o.koff = b.take<int64_t>(p.koff.size());
@@ -105,7 +114,6 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     o.E = b.take<double>(p.E.size());
     o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
     o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
-    o.up_count = b.take<int>((size_t)std::max<int64_t>(1, p.lev_off[up_root_of(p)]));
     if (d) *d = o;
     return b.off + 256;
 }
@@ -121,6 +129,8 @@ static size_t tmp_layout(const bem_operator_s& A, void* base, AsmDev* d) {
     a.touch_rowptr = b.take<int32_t>(p.touch_rowptr.size());
     a.touch = b.take<int32_t>(p.touch.size());
     a.touch_lp = b.take<int32_t>(A.touch_lp.size());
+    a.row_grp = b.take<int32_t>(p.row_grp.size());
+    a.row_pos = b.take<int32_t>(p.row_pos.size());
     a.ntouch_lp = (int64_t)A.touch_lp.size();
     a.vid = b.take<int32_t>(p.vid.size());
     a.gx = b.take<double>(p.gx.size());
@@ -176,117 +186,105 @@ static Gauss8 gauss8() {
 }
 
 // ------------------------------------------------------------------------------ GMRES
-static inline double conj_h(double v) { return v; }
-static inline std::complex<double> conj_h(const std::complex<double>& v) { return std::conj(v); }
+struct SolveWs {
+    char* V;       // (m+1) x N Krylov basis
+    char* w;       // N
+    char* partA;   // kSolveBlocks x (m+1) partial sums
+    char* partB;
+    double* npart; // kSolveBlocks partial squared norms
+    GmresState st;
+};
 
-static size_t solve_layout(int64_t N, int m, size_t sc, void* base, char** ptrs) {
+static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws) {
     Bump b(base);
-    ptrs[0] = b.take<char>((size_t)(m + 1) * N * sc);           // Krylov basis V
-    ptrs[1] = b.take<char>((size_t)N * sc);                     // w
-    ptrs[2] = b.take<char>((size_t)kDotBlocks * (m + 1) * sc);  // partial sums
-    ptrs[3] = b.take<char>((size_t)(m + 1) * sc);               // h, first pass
-    ptrs[4] = b.take<char>((size_t)(m + 1) * sc);               // h, second pass
-    ptrs[5] = b.take<char>((size_t)(m + 1) * sc);               // update coefficients
-    ptrs[6] = b.take<char>(2 * sizeof(double));                 // norms
+    SolveWs w{};
+    w.V = b.take<char>((size_t)(m + 1) * N * sc);
+    w.w = b.take<char>((size_t)N * sc);
+    w.partA = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
+    w.partB = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
+    w.npart = b.take<double>(kSolveBlocks);
+    w.st.m = m;
+    w.st.H = b.take<char>((size_t)(m + 1) * m * sc);
+    w.st.cs = b.take<double>(m);
+    w.st.sn = b.take<char>((size_t)m * sc);
+    w.st.g = b.take<char>((size_t)(m + 1) * sc);
+    w.st.y = b.take<char>((size_t)m * sc);
+    w.st.h1 = b.take<char>((size_t)(m + 1) * sc);
+    w.st.h2 = b.take<char>((size_t)(m + 1) * sc);
+    w.st.scal = b.take<double>(m + 2);
+    if (ws) *ws = w;
     return b.off + 256;
 }
 
-template <class H>
-static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* st,
-                     char** W, hipStream_t stream) {
+// One right-hand side.  Within a cycle the host enqueues Arnoldi step j and then waits
+// only for the event of step j-1 (its residual estimate, copied to pinned memory), so the
+// device always has the next step queued; the true residual is read once per cycle.
+static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* out,
+                     SolveWs& W, hipStream_t stream) {
     const int64_t N = A->info.ndof;
     const int m = p->restart;
     const int cp = A->cplx ? 1 : 0;
     const size_t sc = A->scal;
-    char* V = W[0];
-    char* w = W[1];
-    char* part = W[2];
-    char* hd1 = W[3];
-    char* hd2 = W[4];
-    char* yc = W[5];
-    double* nrm = (double*)W[6];
-    auto Vj = [&](int j) { return V + (size_t)j * N * sc; };
-    std::vector<H> Hm((size_t)(m + 1) * m), g(m + 1), sn(m), y(m), h1(m + 1), h2(m + 1);
-    std::vector<double> cs(m);
-    double hn = 0.0;
+    auto Vj = [&](int j) { return W.V + (size_t)j * N * sc; };
+    if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
+    while ((int)A->sev.size() < kMaxRestart) {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        A->sev.push_back(e);
+    }
+    double* pin = A->pinned;
+    out->iterations = 0;
+    out->converged = 0;
+    out->relres = 0.0;
     HIP_CHECK(hipMemsetAsync(x, 0, N * sc, stream));
-    HIP_CHECK(launch_norm(cp, N, b, part, nrm, stream));
-    double bnorm = 0.0;
-    HIP_CHECK(hipMemcpyAsync(&bnorm, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
+    // ||b||: squared-norm partials of b, summed on the host in the device's order
+    HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 1, stream));
+    HIP_CHECK(hipMemcpyAsync(pin + kMaxRestart + 2, W.npart, sizeof(double) * kSolveBlocks, hipMemcpyDeviceToHost,
+                             stream));
     HIP_CHECK(hipStreamSynchronize(stream));
-    st->iterations = 0;
-    st->converged = 0;
-    st->relres = 0.0;
+    double bb = 0.0;
+    for (int i = 0; i < kSolveBlocks; ++i) bb += pin[kMaxRestart + 2 + i];
+    const double bnorm = std::sqrt(bb);
     if (bnorm == 0.0) {
-        st->converged = 1;
+        out->converged = 1;
         return BEM_OK;
     }
     int total = 0;
     double relres = 1.0;
-    for (;;) {
-        // true residual r = b - A x into w
-        HIP_CHECK(launch_apply(A->dev, x, w, stream));
-        HIP_CHECK(launch_axpby(cp, N, 1.0, b, -1.0, w, stream));
-        HIP_CHECK(launch_norm(cp, N, w, part, nrm, stream));
-        double beta = 0.0;
-        HIP_CHECK(hipMemcpyAsync(&beta, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
+    for (int cycle = 0;; ++cycle) {
+        if (cycle > 0) {
+            HIP_CHECK(launch_apply(A->dev, x, W.w, stream));
+            HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
+        }  // in the first cycle x = 0 and w already holds b
+        HIP_CHECK(solve_start(cp, N, W.npart, W.w, Vj(0), W.st, stream));
+        HIP_CHECK(hipMemcpyAsync(pin, W.st.scal + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
-        relres = beta / bnorm;
+        relres = pin[0] / bnorm;
         if (relres <= p->tol || total >= p->maxit || !std::isfinite(relres)) break;
-        HIP_CHECK(launch_scale(cp, N, w, nrm, Vj(0), stream));
-        std::fill(g.begin(), g.end(), H(0));
-        g[0] = beta;
         int k = 0;
-        for (int j = 0; j < m && total < p->maxit; ++j) {
-            HIP_CHECK(launch_apply(A->dev, Vj(j), w, stream));
-            // classical Gram-Schmidt, twice
-            HIP_CHECK(launch_dots(cp, N, j + 1, V, N, w, part, hd1, stream));
-            HIP_CHECK(launch_update(cp, N, j + 1, V, N, hd1, -1.0, w, stream));
-            HIP_CHECK(launch_dots(cp, N, j + 1, V, N, w, part, hd2, stream));
-            HIP_CHECK(launch_update(cp, N, j + 1, V, N, hd2, -1.0, w, stream));
-            HIP_CHECK(launch_norm(cp, N, w, part, nrm, stream));
-            HIP_CHECK(launch_scale(cp, N, w, nrm, Vj(j + 1), stream));
-            HIP_CHECK(hipMemcpyAsync(h1.data(), hd1, (j + 1) * sc, hipMemcpyDeviceToHost, stream));
-            HIP_CHECK(hipMemcpyAsync(h2.data(), hd2, (j + 1) * sc, hipMemcpyDeviceToHost, stream));
-            HIP_CHECK(hipMemcpyAsync(&hn, nrm, sizeof(double), hipMemcpyDeviceToHost, stream));
-            HIP_CHECK(hipStreamSynchronize(stream));
-            for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h1[i] + h2[i];
-            Hm[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const H a = Hm[(size_t)i * m + j], c = Hm[(size_t)(i + 1) * m + j];
-                Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                Hm[(size_t)(i + 1) * m + j] = -conj_h(sn[i]) * a + cs[i] * c;
-            }
-            const H a = Hm[(size_t)j * m + j], c = Hm[(size_t)(j + 1) * m + j];
-            const double na = std::abs(a), nc = std::abs(c), nu = std::sqrt(na * na + nc * nc);
-            if (na == 0.0) {
-                cs[j] = 0.0;
-                sn[j] = H(1);
-            } else {
-                cs[j] = na / nu;
-                sn[j] = (a / na) * conj_h(c) / nu;
-            }
-            Hm[(size_t)j * m + j] = cs[j] * a + sn[j] * c;
-            Hm[(size_t)(j + 1) * m + j] = H(0);
-            const H gj = g[j];
-            g[j] = cs[j] * gj;
-            g[j + 1] = -conj_h(sn[j]) * gj;
-            ++total;
+        for (int j = 0; j < m && total + j < p->maxit; ++j) {
+            HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, stream));
+            HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, stream));
+            HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partA, W.st.h1, W.w, W.partB, W.npart, 0, stream));
+            HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partB, W.st.h2, W.w, W.partA, W.npart, 1, stream));
+            HIP_CHECK(solve_scale_givens(cp, N, j, W.npart, W.w, Vj(j + 1), W.st, stream));
+            HIP_CHECK(hipMemcpyAsync(pin + 2 + j, W.st.scal + 2 + j, sizeof(double), hipMemcpyDeviceToHost, stream));
+            HIP_CHECK(hipEventRecord(A->sev[j], stream));
             k = j + 1;
-            if (std::abs(g[j + 1]) / bnorm <= p->tol || hn == 0.0) break;
+            if (j >= 1) {
+                HIP_CHECK(hipEventSynchronize(A->sev[j - 1]));
+                if (pin[2 + j - 1] <= p->tol * bnorm || !std::isfinite(pin[2 + j - 1])) {
+                    k = j;  // converged after step j-1; step j's column is not used
+                    break;
+                }
+            }
         }
-        for (int i = k - 1; i >= 0; --i) {
-            H s = g[i];
-            for (int l = i + 1; l < k; ++l) s -= Hm[(size_t)i * m + l] * y[l];
-            y[i] = s / Hm[(size_t)i * m + i];
-        }
-        HIP_CHECK(hipMemcpyAsync(yc, y.data(), k * sc, hipMemcpyHostToDevice, stream));
-        HIP_CHECK(launch_update(cp, N, k, V, N, yc, 1.0, x, stream));
-        HIP_CHECK(hipStreamSynchronize(stream));
+        total += k;
+        HIP_CHECK(solve_backsolve_update(cp, N, k, W.V, x, W.st, stream));
     }
-    st->iterations = total;
-    st->relres = relres;
-    st->converged = relres <= p->tol ? 1 : 0;
+    out->iterations = total;
+    out->relres = relres;
+    out->converged = relres <= p->tol ? 1 : 0;
     return BEM_OK;
 }
 
@@ -415,7 +413,7 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
     H2Params P;
-    P.chunk = p->chunk_cols == 0 ? 256 : p->chunk_cols;
+    P.chunk = p->chunk_cols == 0 ? 128 : p->chunk_cols;
     P.q = p->q;
     P.eta = p->eta;
     P.leaf = p->leaf_level;
@@ -499,11 +497,12 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     d.nstored = (int64_t)p.own_src.size();
     d.up_root = up_root_of(p);
     d.up_depth = p.leaf - d.up_root;
-    d.tile = std::min(p.nleaf1, 4);
+    d.tile = std::min(p.nleaf1, 2);
     d.nchunks = (int64_t)p.ch_t.size();
     d.nnear = (int64_t)p.near_t.size();
     d.ntouch = (int64_t)(p.touch.size() / 5);
     d.nnz = (int64_t)p.col.size();
+    d.ngroups = (int64_t)p.grp_rowptr.size() - 1;
     d.cplx = A->cplx ? 1 : 0;
     auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
         if (bytes == 0) return hipSuccess;
@@ -512,6 +511,11 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(d.lev_off, p.lev_off.data(), p.lev_off.size() * 8));
     HIP_CHECK(up(d.rowptr, p.rowptr.data(), p.rowptr.size() * 8));
     HIP_CHECK(up(d.col, p.col.data(), p.col.size() * 4));
+    HIP_CHECK(up(d.grp_rowptr, p.grp_rowptr.data(), p.grp_rowptr.size() * 8));
+    HIP_CHECK(up(d.grp_rows, p.grp_rows.data(), p.grp_rows.size() * 4));
+    HIP_CHECK(up(d.grp_voff, p.grp_voff.data(), p.grp_voff.size() * 8));
+    HIP_CHECK(up(as.row_grp, p.row_grp.data(), p.row_grp.size() * 4));
+    HIP_CHECK(up(as.row_pos, p.row_pos.data(), p.row_pos.size() * 4));
     HIP_CHECK(up(d.own_rowptr, p.own_rowptr.data(), p.own_rowptr.size() * 8));
     HIP_CHECK(up(d.own_src, p.own_src.data(), p.own_src.size() * 4));
     HIP_CHECK(up(d.koff, p.koff.data(), p.koff.size() * 8));
@@ -541,8 +545,6 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(as.own_t, p.own_t.data(), p.own_t.size() * 4));
     // coupling rows are padded to even length: clear them before the blocks are written
     if (p.ktotal > 0) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
-    // upward-pass counters start at zero; each matvec leaves them at zero
-    HIP_CHECK(hipMemsetAsync(d.up_count, 0, (size_t)std::max<int64_t>(1, p.lev_off[d.up_root]) * sizeof(int), stream));
     HIP_CHECK(launch_gauss_points(d, as, stream));
     HIP_CHECK(launch_near_regular(d, as, stream));
     HIP_CHECK(launch_near_singular(d, as, stream));
@@ -619,9 +621,9 @@ void bem_operator_destroy(bem_operator A) { delete A; }
 
 int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes) {
     if (!A || !p || !bytes) return fail(BEM_EINVAL, "NULL argument");
-    if (nrhs < 1 || p->restart < 1) return fail(BEM_EINVAL, "nrhs and restart must be >= 1");
-    char* ptrs[7];
-    *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, ptrs);
+    if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart)
+        return fail(BEM_EINVAL, "nrhs must be >= 1 and restart in [1, 64]");
+    *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, nullptr);
     return BEM_OK;
 }
 
@@ -629,20 +631,22 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
               const bem_solve_params* p, bem_solve_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!A || !b_dev || !x_dev || !p || !stats || !ws) return fail(BEM_EINVAL, "NULL argument");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
-    if (nrhs < 1 || p->restart < 1 || p->maxit < 1 || !(p->tol > 0.0)) return fail(BEM_EINVAL, "bad solver parameters");
+    if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart || p->maxit < 1 || !(p->tol > 0.0))
+        return fail(BEM_EINVAL, "bad solver parameters (restart must lie in [1, 64])");
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
     const int64_t N = A->info.ndof;
     if (ldb < N || ldx < N) return fail(BEM_EINVAL, "leading dimension too small");
-    char* ptrs[7];
-    const size_t need = solve_layout(N, p->restart, A->scal, nullptr, ptrs);
+    const size_t need = solve_layout(N, p->restart, A->scal, nullptr, nullptr);
     if (ws_bytes < need) return fail(BEM_ENOMEM, "solver workspace too small");
     char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
-    solve_layout(N, p->restart, A->scal, base, ptrs);
+    SolveWs W;
+    solve_layout(N, p->restart, A->scal, base, &W);
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
         const void* b = (const char*)b_dev + (size_t)r * ldb * A->scal;
         void* x = (char*)x_dev + (size_t)r * ldx * A->scal;
-        int rc = A->cplx ? gmres_one<std::complex<double>>(A, b, x, p, &stats[r], ptrs, stream)
-                         : gmres_one<double>(A, b, x, p, &stats[r], ptrs, stream);
+        const int rc = gmres_one(A, b, x, p, &stats[r], W, stream);
         if (rc != BEM_OK) return rc;
         all = all && stats[r].converged;
     }
@@ -658,8 +662,16 @@ int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, 
     if (rowptr) std::memcpy(rowptr, p.rowptr.data(), p.rowptr.size() * 8);
     if (col) std::memcpy(col, p.col.data(), p.col.size() * 4);
     if (val) {
-        HIP_CHECK(hipMemcpyAsync(val, A->dev.val, p.col.size() * A->scal, hipMemcpyDeviceToHost, stream));
+        // values are stored by row groups; return them in CSR order
+        std::vector<char> gv(p.col.size() * A->scal);
+        HIP_CHECK(hipMemcpyAsync(gv.data(), A->dev.val, gv.size(), hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
+        const size_t sc = A->scal;
+        for (size_t g = 0; g + 1 < p.rowptr.size(); ++g) {
+            const int64_t nc = p.rowptr[g + 1] - p.rowptr[g];
+            const int64_t src = p.grp_voff[p.row_grp[g]] + (int64_t)p.row_pos[g] * nc;
+            std::memcpy((char*)val + p.rowptr[g] * sc, gv.data() + src * sc, nc * sc);
+        }
     }
     return BEM_OK;
 }

@@ -41,10 +41,14 @@ struct OpDev {
     int64_t ncl, nleaves, nfar, nnear, ntouch, nnz;
     int cplx;
     const int64_t* lev_off;  // device copy (leaf+2)
-    // near field
+    // near field: CSR pattern; values stored by row groups (see the host plan)
     const int64_t* rowptr;
     const int32_t* col;
     void* val;
+    int64_t ngroups;
+    const int64_t* grp_rowptr;
+    const int32_t* grp_rows;
+    const int64_t* grp_voff;
     // far field: stored blocks in owner rows (see the host plan)
     const int64_t* own_rowptr;
     const int32_t* own_src;
@@ -68,9 +72,8 @@ struct OpDev {
     void* mom;
     void* lv;
     // upward pass: subtrees rooted at level up_root are summed by one block each; the
-    // clusters above are completed by the last of their four children's blocks
+    // levels above follow per patch
     int up_root, up_depth;
-    int* up_count;  // per cluster above up_root: children finished in this matvec (reset to 0)
     // downward pass + backward transform: square tiles of leaves per block
     int tile;
 };
@@ -83,6 +86,8 @@ struct AsmDev {
     const int32_t* touch_rowptr;
     const int32_t* touch;
     const int32_t* touch_lp;  // near leaf pairs that contain touching pairs
+    const int32_t* row_grp;   // row group of every row
+    const int32_t* row_pos;   // position of every row in its group
     int64_t ntouch_lp;
     const int32_t* vid;
     const double* gx;     // [qg]
@@ -117,20 +122,5 @@ hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, 
                       void* b, hipStream_t st);
 hipError_t launch_potential(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const double* pts,
                             int64_t npts, const void* rho, void* u, hipStream_t st);
-
-// GMRES building blocks.  Vectors of n scalars; V holds k vectors with leading dim ldv.
-// dots:   out[i] = sum_t conj(V_i[t]) w[t], i < k (partials per block, then reduced in
-//         a fixed order into out; deterministic)
-// update: w[t] += alpha * sum_i c[i] V_i[t]   (c on the device)
-// scale:  v[t] = w[t] * (1 / *nrm)            (nrm on the device, a real scalar)
-// axpby:  y[t] = a x[t] + b y[t]              (real a, b)
-constexpr int kDotBlocks = 240;
-hipError_t launch_dots(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* w, void* partial,
-                       void* out, hipStream_t st);
-hipError_t launch_update(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* c, double alpha,
-                         void* w, hipStream_t st);
-hipError_t launch_norm(int cplx, int64_t n, const void* w, void* partial, double* out, hipStream_t st);
-hipError_t launch_scale(int cplx, int64_t n, const void* w, const double* nrm, void* v, hipStream_t st);
-hipError_t launch_axpby(int cplx, int64_t n, double a, const void* x, double b, void* y, hipStream_t st);
 
 }  // namespace bem

@@ -7,6 +7,7 @@ namespace bem {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kGroupRowsDev = 16;  // rows per near-field row group at most (host: kGroupRows)
 
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -317,7 +318,9 @@ __global__ __launch_bounds__(256) void k_near_gather(OpDev op, AsmDev as) {
     leaf_range(j1, stride, nloc, n1, lo1, hi1);
     leaf_range(j2, stride, nloc, n1, lo2, hi2);
     const T* lb = (const T*)as.lb;
-    T* val = (T*)op.val;
+    const int64_t grp = as.row_grp[g];
+    const int64_t rbeg = op.rowptr[g], ncol = op.rowptr[g + 1] - rbeg;
+    T* val = (T*)op.val + op.grp_voff[grp] + as.row_pos[g] * ncol - rbeg;
     for (int64_t k = op.rowptr[g] + lane; k < op.rowptr[g + 1]; k += kWave) {
         const int h = op.col[k];
         const int h2 = h % nb, h1 = (h / nb) % nb, hf = h / (nb * nb);
@@ -391,135 +394,6 @@ __global__ void k_far_assemble(OpDev op, AsmDev as) {
     ((T*)op.K)[op.koff[t] + (int64_t)a * op.krs[t] + slot * q2 + b] = kernel_val(op.S.ker, dx * dx + dy * dy + dz * dz, T());
 }
 
-// ------------------------------------------------------------------ H^2 matvec
-// Stage 0.  Blocks [0, nup): forward transform of the leaves of one subtree rooted at level
-// up_root and upward transfer inside it (LDS); the clusters above up_root are completed
-// by the last block (of four siblings) to finish, chained up to the patch, with device-
-// scope fences around the counter.  No block ever waits for another.
-// Blocks [nup, ...): near-field product, one wave per row, overwriting y.
-template <class T, int Q>
-__device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict__ x) {
-    constexpr int Q2 = Q * Q;
-    __shared__ double Es[2 * Q * Q];
-    __shared__ T tree[21][Q2];  // levels below the root: 16 + 4 + 1 clusters at most
-    __shared__ int last;
-    for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
-    T* mom = (T*)op.mom;
-    const int r0 = op.up_root, s = op.up_depth, leaf = op.leaf;
-    const int nr = 1 << r0, w = 1 << s;  // roots per direction, leaves per root direction
-    const int f = blk / (nr * nr), loc = blk % (nr * nr), ri = loc / nr, rj = loc % nr;
-    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
-    (void)n1;
-    // LDS slots of the subtree: depth-2 clusters (16) at 0, depth-1 (4) at 16, root at 20
-    const int lb = s == 2 ? 0 : (s == 1 ? 16 : 20);
-    // leaves of this subtree
-    for (int idx = threadIdx.x; idx < w * w * Q2; idx += blockDim.x) {
-        const int a = idx % Q2, l = idx / Q2;
-        const int i = ri * w + l / w, j = rj * w + l % w, a1 = a / Q, a2 = a % Q;
-        const double* Vi = op.V1 + ((int64_t)i * Q + a1) * nloc;
-        const double* Vj = op.V1 + ((int64_t)j * Q + a2) * nloc;
-        T acc = zero<T>();
-#pragma unroll 2
-        for (int m1 = 0; m1 < nloc; ++m1) {
-            const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
-            T in = zero<T>();
-#pragma unroll 6
-            for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
-            acc += Vi[m1] * in;
-        }
-        mom[(op.lev_off[leaf] + ((int64_t)f * n1 + i) * n1 + j) * Q2 + a] = acc;
-        tree[lb + l][a] = acc;
-    }
-    // upward inside the subtree, depth s-1 .. 0 (level r0 + depth)
-    for (int d = s - 1; d >= 0; --d) {
-        __syncthreads();
-        const int cw = 1 << d, lev = r0 + d;
-        const int cb = (d + 1 == s) ? lb : 16, ob = d == 1 ? 16 : 20;
-        for (int idx = threadIdx.x; idx < cw * cw * Q2; idx += blockDim.x) {
-            const int a = idx % Q2, l = idx / Q2, u = l / cw, v = l % cw, a1 = a / Q, a2 = a % Q;
-            T acc = zero<T>();
-#pragma unroll
-            for (int b1 = 0; b1 < 2; ++b1)
-#pragma unroll
-                for (int b2 = 0; b2 < 2; ++b2) {
-                    const T* mc = tree[cb + (2 * u + b1) * (2 * cw) + 2 * v + b2];
-#pragma unroll
-                    for (int p1 = 0; p1 < Q; ++p1) {
-                        T in = zero<T>();
-#pragma unroll
-                        for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
-                        acc += Es[(b1 * Q + p1) * Q + a1] * in;
-                    }
-                }
-            tree[ob + l][a] = acc;
-            const int gi = ri * cw + u, gj = rj * cw + v;
-            mom[(op.lev_off[lev] + ((int64_t)f * (nr * cw) + gi) * (nr * cw) + gj) * Q2 + a] = acc;
-        }
-    }
-    // clusters above the root: the last of four siblings completes the parent
-    int lev = r0, ci = ri, cj = rj;
-    while (lev > 0) {
-        __threadfence();
-        __syncthreads();
-        const int pn = 1 << (lev - 1), pi = ci >> 1, pj = cj >> 1;
-        const int64_t parent = op.lev_off[lev - 1] + ((int64_t)f * pn + pi) * pn + pj;
-        if (threadIdx.x == 0) last = atomicAdd(&op.up_count[parent], 1) == 3;
-        __syncthreads();
-        if (!last) return;
-        __threadfence();
-        const int n = 1 << lev;
-        if (threadIdx.x < Q2) {
-            const int a = threadIdx.x, a1 = a / Q, a2 = a % Q;
-            T acc = zero<T>();
-#pragma unroll
-            for (int b1 = 0; b1 < 2; ++b1)
-#pragma unroll
-                for (int b2 = 0; b2 < 2; ++b2) {
-                    const int64_t c = op.lev_off[lev] + ((int64_t)f * n + 2 * pi + b1) * n + 2 * pj + b2;
-                    const T* mc = mom + c * Q2;
-#pragma unroll
-                    for (int p1 = 0; p1 < Q; ++p1) {
-                        T in = zero<T>();
-#pragma unroll
-                        for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
-                        acc += Es[(b1 * Q + p1) * Q + a1] * in;
-                    }
-                }
-            mom[parent * Q2 + a] = acc;
-        }
-        if (threadIdx.x == 0) op.up_count[parent] = 0;  // ready for the next matvec
-        lev -= 1;
-        ci = pi;
-        cj = pj;
-    }
-}
-
-template <class T, int Q>
-__global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
-    const int nup = op.S.geom.npatch << (2 * op.up_root);
-    if ((int)blockIdx.x < nup) {
-        up_subtree<T, Q>(op, blockIdx.x, x);
-        return;
-    }
-    const int64_t g = (int64_t)(blockIdx.x - nup) * 4 + uniform_int(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= op.S.ndof) return;
-    const T* __restrict__ val = (const T*)op.val;
-    const int32_t* __restrict__ col = op.col;
-    const int64_t k0 = op.rowptr[g], k1 = op.rowptr[g + 1];
-    T acc0 = zero<T>(), acc1 = zero<T>();
-    int64_t k = k0 + lane;
-    for (; k + kWave < k1; k += 2 * kWave) {
-        const int c0 = col[k], c1 = col[k + kWave];
-        const T v0 = val[k], v1 = val[k + kWave];
-        acc0 += v0 * x[c0];
-        acc1 += v1 * x[c1];
-    }
-    if (k < k1) acc0 += val[k] * x[col[k]];
-    const T s = wave_sum(acc0 + acc1);
-    if (lane == 0) y[g] = s;
-}
-
 // Reduce-scatter of Q2 per-lane values across the wave: after the six butterfly steps
 // lane l holds the wave sum of one index (returned in `idx`, valid if `ok`).
 template <class T, int C>
@@ -565,6 +439,165 @@ __device__ inline void wave_reduce_scatter(T* v, int lane, int& idx, bool& ok) {
     rs_index<C6>(lane, 1, base, real);
     idx = base;
     ok = real > 0;
+}
+
+// ------------------------------------------------------------------ H^2 matvec
+// Stage 0.  Blocks [0, nup): forward transform of the leaves of one subtree rooted at level
+// up_root and upward transfer inside it (LDS).  Blocks [nup, ...): near-field product
+// by row groups, overwriting y.  The levels above up_root follow in k_up_top.
+template <class T, int Q>
+__device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict__ x) {
+    constexpr int Q2 = Q * Q;
+    __shared__ double Es[2 * Q * Q];
+    __shared__ T tree[21][Q2];  // levels below the root: 16 + 4 + 1 clusters at most
+    for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
+    T* mom = (T*)op.mom;
+    const int r0 = op.up_root, s = op.up_depth, leaf = op.leaf;
+    const int nr = 1 << r0, w = 1 << s;  // roots per direction, leaves per root direction
+    const int f = blk / (nr * nr), loc = blk % (nr * nr), ri = loc / nr, rj = loc % nr;
+    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
+    (void)n1;
+    // LDS slots of the subtree: depth-2 clusters (16) at 0, depth-1 (4) at 16, root at 20
+    const int lb = s == 2 ? 0 : (s == 1 ? 16 : 20);
+    // leaves of this subtree
+    for (int idx = threadIdx.x; idx < w * w * Q2; idx += blockDim.x) {
+        const int a = idx % Q2, l = idx / Q2;
+        const int i = ri * w + l / w, j = rj * w + l % w, a1 = a / Q, a2 = a % Q;
+        const double* Vi = op.V1 + ((int64_t)i * Q + a1) * nloc;
+        const double* Vj = op.V1 + ((int64_t)j * Q + a2) * nloc;
+        T acc = zero<T>();
+#pragma unroll 2
+        for (int m1 = 0; m1 < nloc; ++m1) {
+            const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
+            T in = zero<T>();
+#pragma unroll 6
+            for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
+            acc += Vi[m1] * in;
+        }
+        mom[(op.lev_off[leaf] + ((int64_t)f * n1 + i) * n1 + j) * Q2 + a] = acc;
+        tree[lb + l][a] = acc;
+    }
+    // upward inside the subtree, depth s-1 .. 0 (level r0 + depth)
+    for (int d = s - 1; d >= 0; --d) {
+        __syncthreads();
+        const int cw = 1 << d, lev = r0 + d;
+        const int cb = (d + 1 == s) ? lb : 16, ob = d == 1 ? 16 : 20;
+        for (int idx = threadIdx.x; idx < cw * cw * Q2; idx += blockDim.x) {
+            const int a = idx % Q2, l = idx / Q2, u = l / cw, v = l % cw, a1 = a / Q, a2 = a % Q;
+            T acc = zero<T>();
+#pragma unroll 1
+            for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll 1
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    const T* mc = tree[cb + (2 * u + b1) * (2 * cw) + 2 * v + b2];
+#pragma unroll 1
+                    for (int p1 = 0; p1 < Q; ++p1) {
+                        T in = zero<T>();
+#pragma unroll
+                        for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
+                        acc += Es[(b1 * Q + p1) * Q + a1] * in;
+                    }
+                }
+            tree[ob + l][a] = acc;
+            const int gi = ri * cw + u, gj = rj * cw + v;
+            mom[(op.lev_off[lev] + ((int64_t)f * (nr * cw) + gi) * (nr * cw) + gj) * Q2 + a] = acc;
+        }
+    }
+}
+
+// Stage 0b.  Upper levels of one patch's tree (levels up_root-1 .. 0), one block per
+// patch, level by level from the moments written by stage 0.
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_up_top(OpDev op) {
+    constexpr int Q2 = Q * Q;
+    __shared__ double Es[2 * Q * Q];
+    for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
+    T* mom = (T*)op.mom;
+    const int f = blockIdx.x;
+    for (int lev = op.up_root - 1; lev >= 0; --lev) {
+        __syncthreads();
+        const int n = 1 << lev, nc = n * n;
+        for (int idx = threadIdx.x; idx < nc * Q2; idx += blockDim.x) {
+            const int a = idx % Q2, loc = idx / Q2, i = loc / n, j = loc % n, a1 = a / Q, a2 = a % Q;
+            T acc = zero<T>();
+#pragma unroll 1
+            for (int ch = 0; ch < 4; ++ch) {
+                const int b1 = ch >> 1, b2 = ch & 1;
+                const int64_t c = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
+                const T* mc = mom + c * Q2;
+#pragma unroll
+                for (int p1 = 0; p1 < Q; ++p1) {
+                    T in = zero<T>();
+#pragma unroll
+                    for (int p2 = 0; p2 < Q; ++p2) in += Es[(b2 * Q + p2) * Q + a2] * mc[p1 * Q + p2];
+                    acc += Es[(b1 * Q + p1) * Q + a1] * in;
+                }
+            }
+            mom[(op.lev_off[lev] + (int64_t)f * nc + loc) * Q2 + a] = acc;
+        }
+    }
+}
+
+// rows of one near-field row group (R <= RMAX rows sharing C columns), see k_near_up.
+// Columns are taken in blocks of U*64: per block every lane first issues its U column
+// indices, then its U gathers of x, then the values of all rows, so that a block costs
+// about two dependent memory round trips.
+template <class T, int RMAX>
+__device__ inline void near_group_rows(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                       const T* __restrict__ x, T* __restrict__ y, const int32_t* rows, int R, int C,
+                                       int lane) {
+    constexpr int U = RMAX <= 4 ? (sizeof(T) == 8 ? 8 : 4) : (sizeof(T) == 8 ? 4 : 2);
+    T acc[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) acc[r] = zero<T>();
+    for (int c0 = lane; c0 < C; c0 += U * kWave) {
+        int cc[U];
+        T xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = c0 + u * kWave < C ? col[c0 + u * kWave] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = cc[u] >= 0 ? x[cc[u]] : zero<T>();
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+                T vv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) vv[u] = cc[u] >= 0 ? val[(int64_t)r * C + c0 + u * kWave] : zero<T>();
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[r] += vv[u] * xv[u];
+            }
+        }
+    }
+    int idx;
+    bool ok;
+    wave_reduce_scatter<T, RMAX>(acc, lane, idx, ok);
+    if (ok && idx < R) y[rows[idx]] = acc[0];
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    const int nup = op.S.geom.npatch << (2 * op.up_root);
+    if ((int)blockIdx.x < nup) {
+        up_subtree<T, Q>(op, blockIdx.x, x);
+        return;
+    }
+    // near-field product of one row group: every lane takes columns c, c+64, ...; per
+    // step it issues 4 column indices, then the 4 gathers of x, then the values of all the
+    // group's rows (row-major, so each row's loads are coalesced across the wave)
+    const int64_t G = (int64_t)(blockIdx.x - nup) * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (G >= op.ngroups) return;
+    const int64_t rb = op.grp_rowptr[G];
+    const int R = (int)(op.grp_rowptr[G + 1] - rb);
+    const int64_t first = op.grp_rows[rb];
+    const int64_t cb = op.rowptr[first];
+    const int C = (int)(op.rowptr[first + 1] - cb);
+    const int32_t* __restrict__ col = op.col + cb;
+    const T* __restrict__ val = (const T*)op.val + op.grp_voff[G];
+    if (R <= 4)
+        near_group_rows<T, 4>(col, val, x, y, op.grp_rows + rb, R, C, lane);
+    else
+        near_group_rows<T, kGroupRowsDev>(col, val, x, y, op.grp_rows + rb, R, C, lane);
 }
 
 template <class T>
@@ -825,89 +858,6 @@ __global__ __launch_bounds__(256) void k_potential(SpaceDesc S, BasisTab bt, Gau
     if (threadIdx.x == 0) u[p] = red[0] + red[1] + red[2] + red[3];
 }
 
-// ------------------------------------------------------------------ GMRES vector operations
-// partial[blk][i] = sum over the block's slice of conj(V_i) w, 8 vectors per pass
-template <class T>
-__global__ __launch_bounds__(256) void k_dots(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
-                                              const T* __restrict__ w, T* partial) {
-    __shared__ T red[4][8];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i0 = 0; i0 < k; i0 += 8) {
-        T acc[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = zero<T>();
-        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-            const T wv = w[t];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i0 + u < k) acc[u] += conj_(V[(int64_t)(i0 + u) * ldv + t]) * wv;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const T s = wave_sum(acc[u]);
-            if (lane == 0) red[wave][u] = s;
-        }
-        __syncthreads();
-        if (threadIdx.x < 8 && i0 + (int)threadIdx.x < k) {
-            const int u = threadIdx.x;
-            partial[(int64_t)blockIdx.x * k + i0 + u] = red[0][u] + red[1][u] + red[2][u] + red[3][u];
-        }
-        __syncthreads();
-    }
-}
-
-template <class T>
-__global__ void k_reduce_partials(int k, int nblocks, const T* partial, T* out) {
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-        T s = zero<T>();
-        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * k + i];
-        out[i] = s;
-    }
-}
-
-template <class T>
-__global__ void k_update(int64_t n, int k, const T* __restrict__ V, int64_t ldv, const T* __restrict__ c, double alpha,
-                         T* w) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    T s = zero<T>();
-    for (int i = 0; i < k; ++i) s += c[i] * V[(int64_t)i * ldv + t];
-    w[t] += alpha * s;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_norm_partial(int64_t n, const T* __restrict__ w, double* partial) {
-    __shared__ double red[4];
-    double acc = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        acc += abs2(w[t]);
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void k_norm_final(int nblocks, const double* partial, double* out) {
-    if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[b];
-    *out = sqrt(s);
-}
-
-template <class T>
-__global__ void k_scale(int64_t n, const T* __restrict__ w, const double* nrm, T* v) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    v[t] = w[t] * (1.0 / *nrm);
-}
-
-template <class T>
-__global__ void k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    y[t] = a * x[t] + b * y[t];
-}
-
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -997,8 +947,10 @@ static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, b
     switch (stage) {
         case 0: {
             const unsigned nup = (unsigned)op.S.geom.npatch << (2 * op.up_root);
-            const unsigned nb = nup + (with_near ? nblk(op.S.ndof, 4) : 0u);
+            const unsigned nb = nup + (with_near ? nblk(op.ngroups, 4) : 0u);
             hipLaunchKernelGGL((k_near_up<T, Q>), dim3(nb), dim3(256), 0, st, op, x, y);
+            if (op.up_root > 0)
+                hipLaunchKernelGGL((k_up_top<T, Q>), dim3((unsigned)op.S.geom.npatch), dim3(256), 0, st, op);
             break;
         }
         case 1:
@@ -1069,62 +1021,6 @@ hipError_t launch_potential(const SpaceDesc& S, const BasisTab& bt, const Gauss8
     else
         hipLaunchKernelGGL(k_potential<double>, dim3((unsigned)npts), dim3(256), 0, st, S, bt, g8, pts,
                            (const double*)rho, (double*)u);
-    return hipGetLastError();
-}
-
-hipError_t launch_dots(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* w, void* partial,
-                       void* out, hipStream_t st) {
-    if (cplx) {
-        hipLaunchKernelGGL(k_dots<cdbl>, dim3(kDotBlocks), dim3(256), 0, st, n, k, (const cdbl*)V, ldv,
-                           (const cdbl*)w, (cdbl*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<cdbl>, dim3(1), dim3(64), 0, st, k, kDotBlocks, (const cdbl*)partial,
-                           (cdbl*)out);
-    } else {
-        hipLaunchKernelGGL(k_dots<double>, dim3(kDotBlocks), dim3(256), 0, st, n, k, (const double*)V, ldv,
-                           (const double*)w, (double*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<double>, dim3(1), dim3(64), 0, st, k, kDotBlocks,
-                           (const double*)partial, (double*)out);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_update(int cplx, int64_t n, int k, const void* V, int64_t ldv, const void* c, double alpha,
-                         void* w, hipStream_t st) {
-    if (cplx)
-        hipLaunchKernelGGL(k_update<cdbl>, dim3(nblk(n, 256)), dim3(256), 0, st, n, k, (const cdbl*)V, ldv,
-                           (const cdbl*)c, alpha, (cdbl*)w);
-    else
-        hipLaunchKernelGGL(k_update<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, k, (const double*)V, ldv,
-                           (const double*)c, alpha, (double*)w);
-    return hipGetLastError();
-}
-
-hipError_t launch_norm(int cplx, int64_t n, const void* w, void* partial, double* out, hipStream_t st) {
-    if (cplx)
-        hipLaunchKernelGGL(k_norm_partial<cdbl>, dim3(kDotBlocks), dim3(256), 0, st, n, (const cdbl*)w,
-                           (double*)partial);
-    else
-        hipLaunchKernelGGL(k_norm_partial<double>, dim3(kDotBlocks), dim3(256), 0, st, n, (const double*)w,
-                           (double*)partial);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, kDotBlocks, (const double*)partial, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale(int cplx, int64_t n, const void* w, const double* nrm, void* v, hipStream_t st) {
-    if (cplx)
-        hipLaunchKernelGGL(k_scale<cdbl>, dim3(nblk(n, 256)), dim3(256), 0, st, n, (const cdbl*)w, nrm, (cdbl*)v);
-    else
-        hipLaunchKernelGGL(k_scale<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, (const double*)w, nrm,
-                           (double*)v);
-    return hipGetLastError();
-}
-
-hipError_t launch_axpby(int cplx, int64_t n, double a, const void* x, double b, void* y, hipStream_t st) {
-    if (cplx)
-        hipLaunchKernelGGL(k_axpby<cdbl>, dim3(nblk(n, 256)), dim3(256), 0, st, n, a, (const cdbl*)x, b, (cdbl*)y);
-    else
-        hipLaunchKernelGGL(k_axpby<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, a, (const double*)x, b,
-                           (double*)y);
     return hipGetLastError();
 }
 

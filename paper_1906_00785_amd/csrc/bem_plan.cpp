@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
+#include <map>
 #include <unordered_map>
 
 namespace bem {
@@ -374,6 +376,43 @@ struct Builder {
             p.rowptr[g + 1] = (int64_t)p.col.size();
         }
     }
+
+    // rows with the same patch and leaf ranges share their columns
+    void near_groups() {
+        const SpaceDesc& S = p.S;
+        const int64_t N = S.ndof;
+        std::map<std::array<int, 5>, int32_t> open;  // key -> open group
+        std::vector<std::vector<int32_t>> rows;
+        p.row_grp.assign(N, 0);
+        p.row_pos.assign(N, 0);
+        for (int64_t g = 0; g < N; ++g) {
+            const int j2 = (int)(g % S.nb), j1 = (int)((g / S.nb) % S.nb), f = (int)(g / ((int64_t)S.nb * S.nb));
+            std::array<int, 5> key;
+            key[0] = f;
+            leaves_of_basis(p, j1, key[1], key[2]);
+            leaves_of_basis(p, j2, key[3], key[4]);
+            auto it = open.find(key);
+            if (it == open.end() || (int)rows[it->second].size() >= kGroupRows) {
+                rows.emplace_back();
+                open[key] = (int32_t)(rows.size() - 1);
+                it = open.find(key);
+            }
+            p.row_grp[g] = it->second;
+            p.row_pos[g] = (int32_t)rows[it->second].size();
+            rows[it->second].push_back((int32_t)g);
+        }
+        const size_t ng = rows.size();
+        p.grp_rowptr.assign(ng + 1, 0);
+        p.grp_voff.assign(ng + 1, 0);
+        p.grp_rows.clear();
+        for (size_t G = 0; G < ng; ++G) {
+            p.grp_rows.insert(p.grp_rows.end(), rows[G].begin(), rows[G].end());
+            p.grp_rowptr[G + 1] = (int64_t)p.grp_rows.size();
+            const int64_t first = rows[G][0];
+            const int64_t nc = p.rowptr[first + 1] - p.rowptr[first];
+            p.grp_voff[G + 1] = p.grp_voff[G] + nc * (int64_t)rows[G].size();
+        }
+    }
 };
 
 }  // namespace
@@ -488,6 +527,7 @@ bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& p, std::string& err
     B.touching(ok, err);
     if (!ok) return false;
     B.near_pattern();
+    B.near_groups();
 
     // tables
     gauss_legendre01(P.qg, p.gx, p.gw);

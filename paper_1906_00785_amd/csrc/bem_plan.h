@@ -22,13 +22,15 @@ void bspline_local_polys(int d, int r, int L, std::vector<double>& out);
 // Lagrange basis polynomial a of the nodes xs evaluated at y (barycentric form)
 double lagrange_bary(const std::vector<double>& xs, int a, double y);
 
+constexpr int kGroupRows = 16;  // rows per near-field row group at most
+
 struct H2Params {
     int q = 5;
     double eta = 1.6;
     int leaf = -1;
     int qg = 8;
     int qs = 8;
-    int chunk = 256;  // columns per coupling work chunk (multiple of 128)
+    int chunk = 128;  // columns per coupling work chunk (multiple of 128)
 };
 
 struct Plan {
@@ -78,6 +80,14 @@ struct Plan {
     // near-field sparsity pattern in the B-spline basis
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col;
+    // Row groups: rows whose supports meet the same leaves have the same columns; up to
+    // kGroupRows of them form a group whose values are stored row-major after each other
+    // (value (r, c) of group G at grp_voff[G] + r * ncols(G) + c).  The columns of a group
+    // are those of its first row in the pattern above.
+    std::vector<int64_t> grp_rowptr;  // per group: range in grp_rows
+    std::vector<int32_t> grp_rows;    // rows of each group, ascending
+    std::vector<int64_t> grp_voff;    // per group: first value (size ngroups+1)
+    std::vector<int32_t> row_grp, row_pos;  // group and position of every row
 
     // tables
     std::vector<double> gx, gw;   // qg-point rule

@@ -1,0 +1,39 @@
+// GMRES(m) device kernels (bem_solve.hip) and the device state they share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bem_core.h"
+
+namespace bem {
+
+constexpr int kSolveBlocks = 128;  // slices of every vector kernel
+constexpr int kMaxRestart = 64;    // Krylov dimension per cycle at most
+
+// Device-resident state of one GMRES cycle (pointers into the solver workspace).
+struct GmresState {
+    int m;
+    void* H;       // (m+1) x m rotated Hessenberg matrix, row-major
+    double* cs;    // m cosines
+    void* sn;      // m sines
+    void* g;       // m+1 rotated right-hand side
+    void* y;       // m coefficients of the update
+    void* h1;      // m+1 first Gram-Schmidt coefficients
+    void* h2;      // m+1 second Gram-Schmidt coefficients
+    double* scal;  // [0] unused, [1] beta of the cycle, [2 + j] residual estimate after step j
+};
+
+hipError_t solve_dots(int cplx, int64_t n, int k, const void* V, const void* w, void* part, hipStream_t s);
+hipError_t solve_update(int cplx, int64_t n, int k, const void* V, const void* part_in, void* hout, void* w,
+                        void* part_out, double* npart, int mode, hipStream_t s);
+hipError_t solve_scale_givens(int cplx, int64_t n, int j, const double* npart, const void* w, void* vnext,
+                              const GmresState& st, hipStream_t s);
+hipError_t solve_residual(int cplx, int64_t n, const void* b, void* w, double* npart, int copy_b, hipStream_t s);
+hipError_t solve_start(int cplx, int64_t n, const double* npart, const void* w, void* v0, const GmresState& st,
+                       hipStream_t s);
+hipError_t solve_backsolve_update(int cplx, int64_t n, int k, const void* V, void* x, const GmresState& st,
+                                  hipStream_t s);
+
+}  // namespace bem
