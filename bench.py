@@ -82,7 +82,8 @@ def main():
     g = B.Geometry(B.BEM_GEOM_SPHERE6)
     s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=cfg["degree"], level=cfg["level"])
     t0 = time.perf_counter()
-    A = B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble=False)
+    A = B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble=False,
+                   far_low=B.BEM_PREC_FP32)
     t_plan = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -129,7 +130,37 @@ def main():
           f"near {near_bytes/(stage_ms[0]*1e-3)/1e9:.0f} GB/s; matvec {matvec_bytes/(ms*1e-3)/1e9:.0f} GB/s",
           file=sys.stderr, flush=True)
 
+    def time_apply(op, prec, steps):
+        for _ in range(3):
+            op.apply(x, out=y, prec=prec)
+        torch.cuda.synchronize()
+        a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            op.apply(x, out=y, prec=prec)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b_) / steps
+        op.profile(True)
+        for _ in range(steps):
+            op.apply(x, out=y, prec=prec)
+        st_ms, _ = op.profile_read()
+        op.profile(False)
+        return t, st_ms
+
     extra = {}
+    # mixed precision: FP32 and BF16 copies of the coupling blocks (FP32 accumulation)
+    A16 = B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"],
+                     far_low=B.BEM_PREC_BF16)
+    mixed = {}
+    for name, op, prec in (("fp32", A, B.BEM_PREC_FP32), ("bf16", A16, B.BEM_PREC_BF16)):
+        t, st_ms = time_apply(op, prec, args.steps)
+        low_bytes = info.far_bytes / 8 * (4 if prec == B.BEM_PREC_FP32 else 2)
+        cb = low_bytes + info.transposed_bytes + info.nchunks * q2 * 8 + info.nstored * 4 + info.nclusters * q2 * 8
+        mixed[name] = {"matvec_us": t * 1e3, "dof_per_s": N / (t * 1e-3), "coupling_us": st_ms[1] * 1e3,
+                       "coupling_gbs": cb / (st_ms[1] * 1e-3) / 1e9}
+        print(f"bench: {name} matvec {t*1e3:.1f} us, coupling {st_ms[1]*1e3:.1f} us "
+              f"({cb/(st_ms[1]*1e-3)/1e9:.0f} GB/s)", file=sys.stderr, flush=True)
     if not args.no_gmres:
         x0 = cfg["x0"]
         b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
@@ -138,7 +169,7 @@ def main():
         rho, stats = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"])
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
-        it, ok, rr = stats[0]
+        it, ok, rr, _ = stats[0]
         _, pts = W.c1_inputs()
         u = s.potential(pts, rho[0]).cpu().numpy()
         ex = 1.0 / (4 * np.pi * np.linalg.norm(pts - np.array(x0), axis=1))
@@ -147,6 +178,19 @@ def main():
                           "tol": cfg["tol"], "restart": cfg["restart"], "potential_max_rel_err": perr}
         print(f"bench: GMRES {it} its {t_solve:.3f}s relres {rr:.2e} potential err {perr:.2e}", file=sys.stderr,
               flush=True)
+        for name, op in (("fp32", A), ("bf16", A16)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xm, stm = op.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], refine=True)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t0
+            itm, okm, rrm, outm = stm[0]
+            dx = float((xm - rho).norm() / rho.norm())
+            mixed[name].update({"time_to_tol_s": tm, "iterations": itm, "outer": outm, "converged": okm,
+                                "relres": rrm, "rel_diff_to_fp64_solution": dx})
+            print(f"bench: {name} refined GMRES {itm} its / {outm} outer {tm:.3f}s relres {rrm:.2e} "
+                  f"diff to FP64 solution {dx:.1e}", file=sys.stderr, flush=True)
+    extra["mixed"] = mixed
 
     cpu = None
     if not args.no_cpu_baseline:

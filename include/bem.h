@@ -84,8 +84,15 @@ typedef struct bem_h2_params {
     int qg;           /* Gauss points per direction on each element of a regular pair   */
     int qs;           /* Gauss points per dimension of each Duffy cube (touching pairs)  */
     int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 128     */
-    int reserved[3];  /* must be zero */
+    int far_low;      /* extra low-precision copy of the coupling blocks for mixed-precision
+                         applies and solves: 0 none, BEM_PREC_FP32 or BEM_PREC_BF16      */
+    int reserved[2];  /* must be zero */
 } bem_h2_params;
+
+/* arithmetic of the far-field coupling in bem_apply_ex / refined solves */
+#define BEM_PREC_FP64 0
+#define BEM_PREC_FP32 1 /* blocks stored in FP32, products accumulated in FP32 */
+#define BEM_PREC_BF16 2 /* blocks stored in BF16, products accumulated in FP32 */
 
 /* Sizes and counts of an operator, filled by bem_assemble_plan. */
 typedef struct bem_operator_info {
@@ -107,17 +114,25 @@ typedef struct bem_operator_info {
 
 /* GMRES(m) parameters (reading: restart 30, x0 = 0, relative residual tolerance). */
 typedef struct bem_solve_params {
-    int restart;      /* Krylov dimension m per cycle, >= 1 */
-    int maxit;        /* total Arnoldi steps over all cycles, >= 1 */
-    double tol;       /* stop when ||b - A x|| <= tol ||b|| (true residual, checked) */
+    int restart;      /* Krylov dimension m per cycle, 1..64 */
+    int maxit;        /* total Arnoldi steps over all cycles (and refinement steps), >= 1 */
+    double tol;       /* stop when ||b - A x|| <= tol ||b|| (true FP64 residual, checked) */
+    int refine;       /* 0: GMRES on the FP64 operator.  1: FP64 iterative refinement:
+                         r = b - A x with the FP64 operator, inner GMRES on the operator
+                         with the low-precision far field (far_low at assembly) to
+                         inner_tol, x += delta, until the FP64 residual meets tol */
+    int max_outer;    /* refinement steps at most (0 = 20) */
+    double inner_tol; /* relative tolerance of each inner solve (0 = 1e-4) */
     int reserved[4];  /* must be zero */
 } bem_solve_params;
 
 /* per-RHS solver statistics */
 typedef struct bem_solve_stats {
-    int iterations;       /* Arnoldi steps taken */
+    int iterations;       /* Arnoldi steps taken (all inner solves) */
     int converged;        /* 1 if the true relative residual is <= tol */
-    double relres;        /* true relative residual ||b - A x|| / ||b|| at exit */
+    double relres;        /* true relative FP64 residual ||b - A x|| / ||b|| at exit */
+    int outer;            /* refinement steps (0 without refinement) */
+    int reserved;
 } bem_solve_stats;
 
 /* Message of the last failed call on this thread (never NULL). */
@@ -174,6 +189,12 @@ int bem_operator_dims(bem_operator A, int64_t* rows, int64_t* cols);
  * ldx, ldy >= N, must not overlap.  y is overwritten.  nrhs >= 1. */
 int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy, int nrhs,
               hipStream_t stream);
+
+/* y = A x like bem_apply with the far-field coupling in the given precision:
+ * BEM_PREC_FP64, or the low precision the operator was assembled with (far_low); EINVAL
+ * if that copy does not exist.  Near field, transforms and transfers stay FP64. */
+int bem_apply_ex(bem_operator A, int precision, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy,
+                 int nrhs, hipStream_t stream);
 
 /* Device workspace bytes bem_solve needs for nrhs right-hand sides. */
 int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes);

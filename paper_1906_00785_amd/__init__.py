@@ -17,11 +17,12 @@ import torch
 
 from . import _bem as C
 from ._bem import (BEM_DATA_PLANE_WAVE, BEM_DATA_POINT_SOURCE, BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1,
-                   BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16, BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BemError)
+                   BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16, BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BEM_PREC_BF16,
+                   BEM_PREC_FP32, BEM_PREC_FP64, BemError)
 
 __all__ = ["Geometry", "Space", "Operator", "BemError", "BEM_GEOM_SPHERE6", "BEM_GEOM_ELLIPSOID6",
            "BEM_GEOM_TORUS16", "BEM_GEOM_FLAT1", "BEM_LAPLACE_SINGLE", "BEM_HELMHOLTZ_SINGLE",
-           "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE"]
+           "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE", "BEM_PREC_FP64", "BEM_PREC_FP32", "BEM_PREC_BF16"]
 
 
 def _stream() -> int:
@@ -85,9 +86,10 @@ class Operator:
     """Compressed single-layer operator: plan on the host, assemble on the GPU."""
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
-                 assemble: bool = True, chunk_cols: int = 0):
+                 assemble: bool = True, chunk_cols: int = 0, far_low: int = 0):
         self.space = space
-        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols)
+        self.far_low = far_low
+        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low)
         self.q = q
         self.ndof = self.info.ndof
         self.op_ws = None
@@ -111,21 +113,24 @@ class Operator:
         torch.cuda.current_stream().synchronize()
         del tmp
 
-    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        """y = A x for x of shape (N,) or (nrhs, N)."""
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None, prec: int = BEM_PREC_FP64) -> torch.Tensor:
+        """y = A x for x of shape (N,) or (nrhs, N); prec selects the far-field coupling's
+        precision (BEM_PREC_FP64 or the far_low the operator was assembled with)."""
         xx = x.reshape(-1, self.ndof).contiguous()
         y = out if out is not None else torch.empty_like(xx)
-        C.bem_apply(self.h, xx.data_ptr(), self.ndof, y.data_ptr(), self.ndof, xx.shape[0], _stream())
+        C.bem_apply_ex(self.h, prec, xx.data_ptr(), self.ndof, y.data_ptr(), self.ndof, xx.shape[0], _stream())
         return y.reshape(x.shape)
 
-    def solve(self, b: torch.Tensor, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
-        """GMRES(restart); returns (x, [(iterations, converged, relres)] per RHS)."""
+    def solve(self, b: torch.Tensor, tol: float = 1e-8, restart: int = 30, maxit: int = 2000, refine: bool = False,
+              inner_tol: float = 0.0, max_outer: int = 0):
+        """GMRES(restart), optionally inside FP64 iterative refinement with the
+        low-precision far field; returns (x, [(iterations, converged, relres, outer)])."""
         bb = b.reshape(-1, self.ndof).contiguous()
         x = torch.empty_like(bb)
         nbytes = C.bem_solve_plan(self.h, bb.shape[0], restart, maxit, tol)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=bb.device)
         _, stats = C.bem_solve(self.h, bb.data_ptr(), self.ndof, x.data_ptr(), self.ndof, bb.shape[0], restart, maxit,
-                               tol, ws.data_ptr(), nbytes, _stream())
+                               tol, ws.data_ptr(), nbytes, _stream(), int(refine), max_outer, inner_tol)
         return x.reshape(b.shape), stats
 
     def profile(self, on: bool):

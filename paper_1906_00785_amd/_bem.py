@@ -15,13 +15,14 @@ BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, 
 BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
 BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1 = 0, 1, 2, 3
 BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
+BEM_PREC_FP64, BEM_PREC_FP32, BEM_PREC_BF16 = 0, 1, 2
 
 _c_int, _c_dbl, _c_i64, _c_sz, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
 
 class bem_h2_params(ctypes.Structure):
     _fields_ = [("q", _c_int), ("eta", _c_dbl), ("leaf_level", _c_int), ("qg", _c_int), ("qs", _c_int),
-                ("chunk_cols", _c_int), ("reserved", _c_int * 3)]
+                ("chunk_cols", _c_int), ("far_low", _c_int), ("reserved", _c_int * 2)]
 
 
 class bem_operator_info(ctypes.Structure):
@@ -32,11 +33,13 @@ class bem_operator_info(ctypes.Structure):
 
 
 class bem_solve_params(ctypes.Structure):
-    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("tol", _c_dbl), ("reserved", _c_int * 4)]
+    _fields_ = [("restart", _c_int), ("maxit", _c_int), ("tol", _c_dbl), ("refine", _c_int), ("max_outer", _c_int),
+                ("inner_tol", _c_dbl), ("reserved", _c_int * 4)]
 
 
 class bem_solve_stats(ctypes.Structure):
-    _fields_ = [("iterations", _c_int), ("converged", _c_int), ("relres", _c_dbl)]
+    _fields_ = [("iterations", _c_int), ("converged", _c_int), ("relres", _c_dbl), ("outer", _c_int),
+                ("reserved", _c_int)]
 
 
 class BemError(RuntimeError):
@@ -59,6 +62,7 @@ _SIGNATURES = {
     "bem_operator_info_get": (_c_int, [_vp, _P(bem_operator_info)]),
     "bem_operator_dims": (_c_int, [_vp, _P(_c_i64), _P(_c_i64)]),
     "bem_apply": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _vp]),
+    "bem_apply_ex": (_c_int, [_vp, _c_int, _vp, _c_i64, _vp, _c_i64, _c_int, _vp]),
     "bem_solve_plan": (_c_int, [_vp, _c_int, _P(bem_solve_params), _P(_c_sz)]),
     "bem_solve": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _P(bem_solve_params), _P(bem_solve_stats), _vp,
                            _c_sz, _vp]),
@@ -136,8 +140,9 @@ def bem_rhs(s: int, data_kind: int, data_params, nrhs: int, b_ptr: int, ldb: int
     check(lib.bem_rhs(s, data_kind, _dbl_array(flat), nrhs, b_ptr, ldb, stream))
 
 
-def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int, chunk_cols: int = 0):
-    p = bem_h2_params(q, eta, leaf_level, qg, qs, chunk_cols, (_c_int * 3)(0, 0, 0))
+def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int, chunk_cols: int = 0,
+                      far_low: int = 0):
+    p = bem_h2_params(q, eta, leaf_level, qg, qs, chunk_cols, far_low, (_c_int * 2)(0, 0))
     h = _vp()
     info = bem_operator_info()
     check(lib.bem_assemble_plan(s, ctypes.byref(p), ctypes.byref(h), ctypes.byref(info)))
@@ -164,22 +169,30 @@ def bem_apply(A: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, str
     check(lib.bem_apply(A, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
 
 
+def _solve_params(restart, maxit, tol, refine=0, max_outer=0, inner_tol=0.0):
+    return bem_solve_params(restart, maxit, tol, int(refine), max_outer, inner_tol, (_c_int * 4)(0, 0, 0, 0))
+
+
+def bem_apply_ex(A: int, prec: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, stream: int):
+    check(lib.bem_apply_ex(A, prec, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
+
+
 def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float) -> int:
-    p = bem_solve_params(restart, maxit, tol, (_c_int * 4)(0, 0, 0, 0))
+    p = _solve_params(restart, maxit, tol)
     n = _c_sz()
     check(lib.bem_solve_plan(A, nrhs, ctypes.byref(p), ctypes.byref(n)))
     return n.value
 
 
 def bem_solve(A: int, b_ptr: int, ldb: int, x_ptr: int, ldx: int, nrhs: int, restart: int, maxit: int, tol: float,
-              ws_ptr: int, ws_bytes: int, stream: int):
+              ws_ptr: int, ws_bytes: int, stream: int, refine: int = 0, max_outer: int = 0, inner_tol: float = 0.0):
     """Returns (rc, stats list); rc is BEM_OK or BEM_ENOCONV (other codes raise)."""
-    p = bem_solve_params(restart, maxit, tol, (_c_int * 4)(0, 0, 0, 0))
+    p = _solve_params(restart, maxit, tol, refine, max_outer, inner_tol)
     st = (bem_solve_stats * nrhs)()
     rc = lib.bem_solve(A, b_ptr, ldb, x_ptr, ldx, nrhs, ctypes.byref(p), st, ws_ptr, ws_bytes, stream)
     if rc not in (BEM_OK, BEM_ENOCONV):
         check(rc)
-    return rc, [(s.iterations, bool(s.converged), s.relres) for s in st]
+    return rc, [(s.iterations, bool(s.converged), s.relres, s.outer) for s in st]
 
 
 def bem_eval_potential(s: int, pts_ptr: int, npts: int, rho_ptr: int, ldr: int, nrhs: int, u_ptr: int, ldu: int,

@@ -68,6 +68,7 @@ struct bem_operator_s {
     std::vector<int32_t> touch_lp;
     OpDev dev{};
     size_t scal = 8;  // bytes per scalar
+    int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
     // stage timing of bem_apply (bem_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kApplyStages + 1 events per recorded apply
@@ -110,6 +111,9 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     o.ch_k1 = b.take<int32_t>(p.ch_k1.size());
     o.cl_chunk = b.take<int64_t>(p.cl_chunk.size());
     o.partial = b.take<char>(p.ch_t.size() * p.q2 * A.scal);
+    o.low = A.far_low;
+    o.ktotal_scalars = p.ktotal * (A.cplx ? 2 : 1);
+    o.Klow = A.far_low ? b.take<char>((size_t)o.ktotal_scalars * (A.far_low == 1 ? 4 : 2)) : nullptr;
     o.V1 = b.take<double>(p.V1.size());
     o.E = b.take<double>(p.E.size());
     o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
@@ -189,6 +193,8 @@ static Gauss8 gauss8() {
 struct SolveWs {
     char* V;       // (m+1) x N Krylov basis
     char* w;       // N
+    char* r;       // N  (refinement: FP64 residual)
+    char* d;       // N  (refinement: correction)
     char* partA;   // kSolveBlocks x (m+1) partial sums
     char* partB;
     double* npart; // kSolveBlocks partial squared norms
@@ -200,6 +206,8 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
     SolveWs w{};
     w.V = b.take<char>((size_t)(m + 1) * N * sc);
     w.w = b.take<char>((size_t)N * sc);
+    w.r = b.take<char>((size_t)N * sc);
+    w.d = b.take<char>((size_t)N * sc);
     w.partA = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
     w.partB = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
     w.npart = b.take<double>(kSolveBlocks);
@@ -219,10 +227,9 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
 // One right-hand side.  Within a cycle the host enqueues Arnoldi step j and then waits
 // only for the event of step j-1 (its residual estimate, copied to pinned memory), so the
 // device always has the next step queued; the true residual is read once per cycle.
-static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* out,
-                     SolveWs& W, hipStream_t stream) {
+static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, int maxit, double tol,
+                     bem_solve_stats* out, SolveWs& W, hipStream_t stream) {
     const int64_t N = A->info.ndof;
-    const int m = p->restart;
     const int cp = A->cplx ? 1 : 0;
     const size_t sc = A->scal;
     auto Vj = [&](int j) { return W.V + (size_t)j * N * sc; };
@@ -253,17 +260,17 @@ static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_par
     double relres = 1.0;
     for (int cycle = 0;; ++cycle) {
         if (cycle > 0) {
-            HIP_CHECK(launch_apply(A->dev, x, W.w, stream));
+            HIP_CHECK(launch_apply(A->dev, x, W.w, prec, stream));
             HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
         }  // in the first cycle x = 0 and w already holds b
         HIP_CHECK(solve_start(cp, N, W.npart, W.w, Vj(0), W.st, stream));
         HIP_CHECK(hipMemcpyAsync(pin, W.st.scal + 1, sizeof(double), hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
         relres = pin[0] / bnorm;
-        if (relres <= p->tol || total >= p->maxit || !std::isfinite(relres)) break;
+        if (relres <= tol || total >= maxit || !std::isfinite(relres)) break;
         int k = 0;
-        for (int j = 0; j < m && total + j < p->maxit; ++j) {
-            HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, stream));
+        for (int j = 0; j < m && total + j < maxit; ++j) {
+            HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, prec, stream));
             HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partA, W.st.h1, W.w, W.partB, W.npart, 0, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partB, W.st.h2, W.w, W.partA, W.npart, 1, stream));
@@ -273,7 +280,7 @@ static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_par
             k = j + 1;
             if (j >= 1) {
                 HIP_CHECK(hipEventSynchronize(A->sev[j - 1]));
-                if (pin[2 + j - 1] <= p->tol * bnorm || !std::isfinite(pin[2 + j - 1])) {
+                if (pin[2 + j - 1] <= tol * bnorm || !std::isfinite(pin[2 + j - 1])) {
                     k = j;  // converged after step j-1; step j's column is not used
                     break;
                 }
@@ -284,7 +291,54 @@ static int gmres_one(bem_operator A, const void* b, void* x, const bem_solve_par
     }
     out->iterations = total;
     out->relres = relres;
-    out->converged = relres <= p->tol ? 1 : 0;
+    out->converged = relres <= tol ? 1 : 0;
+    out->outer = 0;
+    return BEM_OK;
+}
+
+// FP64 iterative refinement around GMRES on the operator with the low-precision far field:
+// r = b - A x (FP64), inner solve A_low d = r to inner_tol, x += d, until ||r|| <= tol ||b||.
+static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* out,
+                      SolveWs& W, hipStream_t stream) {
+    const int64_t N = A->info.ndof;
+    const int cp = A->cplx ? 1 : 0;
+    const size_t sc = A->scal;
+    const int max_outer = p->max_outer > 0 ? p->max_outer : 20;
+    const double inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
+    double* pin = A->pinned;
+    HIP_CHECK(hipMemsetAsync(x, 0, N * sc, stream));
+    HIP_CHECK(hipMemcpyAsync(W.r, b, N * sc, hipMemcpyDeviceToDevice, stream));
+    HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 1, stream));
+    auto host_norm = [&](double& v) -> int {
+        HIP_CHECK(hipMemcpyAsync(pin + kMaxRestart + 2, W.npart, sizeof(double) * kSolveBlocks,
+                                 hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        double s2 = 0.0;
+        for (int i = 0; i < kSolveBlocks; ++i) s2 += pin[kMaxRestart + 2 + i];
+        v = std::sqrt(s2);
+        return BEM_OK;
+    };
+    double bnorm = 0.0, rnorm = 0.0;
+    if (host_norm(bnorm) != BEM_OK) return BEM_EDEVICE;
+    rnorm = bnorm;
+    int total = 0, outer = 0;
+    while (bnorm > 0.0 && rnorm > p->tol * bnorm && outer < max_outer && total < p->maxit && std::isfinite(rnorm)) {
+        bem_solve_stats in{};
+        const int rc = gmres_one(A, A->far_low, W.r, W.d, p->restart, p->maxit - total, inner_tol, &in, W, stream);
+        if (rc != BEM_OK) return rc;
+        total += in.iterations;
+        ++outer;
+        HIP_CHECK(solve_axpy(cp, N, 1.0, W.d, x, stream));
+        HIP_CHECK(launch_apply(A->dev, x, W.w, 0, stream));
+        HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
+        HIP_CHECK(hipMemcpyAsync(W.r, W.w, N * sc, hipMemcpyDeviceToDevice, stream));
+        if (host_norm(rnorm) != BEM_OK) return BEM_EDEVICE;
+        if (in.iterations == 0) break;  // no progress possible
+    }
+    out->iterations = total;
+    out->outer = outer;
+    out->relres = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+    out->converged = out->relres <= p->tol ? 1 : 0;
     return BEM_OK;
 }
 
@@ -410,8 +464,9 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
 
 int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    if (p->far_low < 0 || p->far_low > 2) return fail(BEM_EINVAL, "far_low must be 0, BEM_PREC_FP32 or BEM_PREC_BF16");
     H2Params P;
     P.chunk = p->chunk_cols == 0 ? 128 : p->chunk_cols;
     P.q = p->q;
@@ -434,6 +489,7 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     A->sp = s;
     A->cplx = s->S.ker.pde == PDE_HELMHOLTZ;
     A->scal = A->cplx ? 16 : 8;
+    A->far_low = p->far_low;
     const Plan& pl = A->plan;
     for (size_t lp = 0; lp + 1 < pl.touch_rowptr.size(); ++lp)
         if (pl.touch_rowptr[lp + 1] > pl.touch_rowptr[lp]) A->touch_lp.push_back((int32_t)lp);
@@ -550,6 +606,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(launch_near_singular(d, as, stream));
     HIP_CHECK(launch_near_gather(d, as, stream));
     HIP_CHECK(launch_far_assemble(d, as, stream));
+    HIP_CHECK(launch_cast_low(d, stream));
     // the host tables above are copied from pageable memory; make sure they have been read
     // before the caller may free the temporary workspace (the plan itself stays alive)
     A->dev = d;
@@ -558,7 +615,14 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
 }
 
 int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy, int nrhs, hipStream_t stream) {
+    return bem_apply_ex(A, BEM_PREC_FP64, x_dev, ldx, y_dev, ldy, nrhs, stream);
+}
+
+int bem_apply_ex(bem_operator A, int prec, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy, int nrhs,
+                 hipStream_t stream) {
     if (!A || !x_dev || !y_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (prec != BEM_PREC_FP64 && prec != A->far_low)
+        return fail(BEM_EINVAL, "precision not available (assemble with far_low set to it)");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
     const int64_t N = A->info.ndof;
@@ -571,7 +635,7 @@ int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64
         const void* xr = xb + (size_t)r * ldx * A->scal;
         void* yr = yb + (size_t)r * ldy * A->scal;
         if (!A->prof) {
-            HIP_CHECK(launch_apply(A->dev, xr, yr, stream));
+            HIP_CHECK(launch_apply(A->dev, xr, yr, prec, stream));
             continue;
         }
         const size_t need = A->ev_used + kApplyStages + 1;
@@ -582,7 +646,7 @@ int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64
         }
         HIP_CHECK(hipEventRecord(A->ev[A->ev_used], stream));
         for (int s = 0; s < kApplyStages; ++s) {
-            HIP_CHECK(launch_apply_stage(A->dev, s, xr, yr, stream));
+            HIP_CHECK(launch_apply_stage(A->dev, s, xr, yr, prec, stream));
             HIP_CHECK(hipEventRecord(A->ev[A->ev_used + 1 + s], stream));
         }
         A->ev_used = need;
@@ -637,6 +701,10 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
     const int64_t N = A->info.ndof;
     if (ldb < N || ldx < N) return fail(BEM_EINVAL, "leading dimension too small");
+    if (p->refine != 0 && p->refine != 1) return fail(BEM_EINVAL, "refine must be 0 or 1");
+    if (p->refine && A->far_low == 0) return fail(BEM_EINVAL, "refinement needs far_low set at assembly");
+    if (p->max_outer < 0 || p->inner_tol < 0.0) return fail(BEM_EINVAL, "max_outer and inner_tol must be >= 0");
+    if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
     const size_t need = solve_layout(N, p->restart, A->scal, nullptr, nullptr);
     if (ws_bytes < need) return fail(BEM_ENOMEM, "solver workspace too small");
     char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
@@ -646,7 +714,8 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
     for (int r = 0; r < nrhs; ++r) {
         const void* b = (const char*)b_dev + (size_t)r * ldb * A->scal;
         void* x = (char*)x_dev + (size_t)r * ldx * A->scal;
-        const int rc = gmres_one(A, b, x, p, &stats[r], W, stream);
+        const int rc = p->refine ? refine_one(A, b, x, p, &stats[r], W, stream)
+                                 : gmres_one(A, 0, b, x, p->restart, p->maxit, p->tol, &stats[r], W, stream);
         if (rc != BEM_OK) return rc;
         all = all && stats[r].converged;
     }

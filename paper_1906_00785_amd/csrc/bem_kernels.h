@@ -65,6 +65,9 @@ struct OpDev {
     const int32_t* ch_k1;
     const int64_t* cl_chunk;   // per cluster: its chunks
     void* partial;             // per chunk: q*q row sums
+    void* Klow;                // optional low-precision copy of K (same layout), see low
+    int low;                   // 0 none, 1 FP32, 2 BF16
+    int64_t ktotal_scalars;    // real scalars in K (2 per complex entry)
     // transforms
     const double* V1;  // [nleaf1][q][nloc]
     const double* E;   // [2][q][q]
@@ -111,9 +114,12 @@ hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st
 // y = A x for one RHS column, as four stages: 0 near-field product with the forward
 // transform + upward transfer beside it, 1 far-field coupling, 2 gather of the local
 // expansions, 3 downward transfer + backward transform added to y
+// prec: 0 FP64 coupling, otherwise the low-precision copy (op.low must be set)
 constexpr int kApplyStages = 4;
-hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, hipStream_t st);
-hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st);
+hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, int prec, hipStream_t st);
+hipError_t launch_apply(const OpDev& op, const void* x, void* y, int prec, hipStream_t st);
+// low-precision copy of the stored coupling blocks
+hipError_t launch_cast_low(const OpDev& op, hipStream_t st);
 // moments of all clusters for x (forward + upward) into op.mom
 hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st);
 

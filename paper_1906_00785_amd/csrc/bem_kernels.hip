@@ -2,6 +2,8 @@
 // blocks, the H^2 matvec, load vector, potential and the GMRES vector operations.
 #include "bem_kernels.h"
 
+#include <type_traits>
+
 namespace bem {
 
 namespace {
@@ -402,7 +404,7 @@ __device__ inline void rs_step(T* v, bool upper, int off) {
 #pragma unroll
     for (int i = 0; i < H; ++i) {
         const T lo = v[i];
-        const T hi = (i + H < C) ? v[i + H] : zero<T>();
+        const T hi = (i + H < C) ? v[i + H] : T{};
         const T send = upper ? lo : hi;
         const T keep = upper ? hi : lo;
         v[i] = keep + shfl_xor_t(send, off);
@@ -666,6 +668,124 @@ __global__ __launch_bounds__(256) void k_coupling(OpDev op) {
     bool ok;
     wave_reduce_scatter<T, Q2>(acc, lane, idx, ok);
     if (ok) ((T*)op.partial)[c * Q2 + idx] = acc[0];
+}
+
+
+// ------------------------------------------------------------------ low-precision far field
+struct cflt {
+    float re, im;
+};
+__device__ inline cflt operator+(cflt a, cflt b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cflt operator*(cflt a, cflt b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cflt& operator+=(cflt& a, cflt b) {
+    a.re += b.re;
+    a.im += b.im;
+    return a;
+}
+template <class F>
+__device__ inline F zero_f();
+template <>
+__device__ inline float zero_f<float>() { return 0.0f; }
+template <>
+__device__ inline cflt zero_f<cflt>() { return {0.0f, 0.0f}; }
+__device__ inline float to_f(double v) { return (float)v; }
+__device__ inline cflt to_f(cdbl v) { return {(float)v.re, (float)v.im}; }
+__device__ inline double to_d(float v) { return (double)v; }
+__device__ inline cdbl to_d(cflt v) { return {(double)v.re, (double)v.im}; }
+__device__ inline float shfl_xor_t(float v, int off) { return __shfl_xor(v, off, kWave); }
+__device__ inline cflt shfl_xor_t(cflt v, int off) { return {__shfl_xor(v.re, off, kWave), __shfl_xor(v.im, off, kWave)}; }
+
+// BF16 by round-to-nearest-even of the FP32 value (finite inputs)
+__device__ inline uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf2f(uint32_t b) { return __uint_as_float(b << 16); }
+
+// storage types: FP32 (4 bytes per real scalar) or BF16 (2 bytes)
+struct StFp32 {};
+struct StBf16 {};
+
+// two adjacent columns of a coupling row, converted to FP32
+__device__ inline Pair<float> load_low(StFp32, const void* base, int64_t off) {
+    const float2 v = *((const float2*)base + off / 2);
+    return {v.x, v.y};
+}
+__device__ inline Pair<float> load_low(StBf16, const void* base, int64_t off) {
+    const uint32_t v = *((const uint32_t*)base + off / 2);
+    return {bf2f(v & 0xFFFFu), bf2f(v >> 16)};
+}
+__device__ inline Pair<cflt> load_low_c(StFp32, const void* base, int64_t off) {
+    const float4 v = *((const float4*)base + off / 2);
+    return {{v.x, v.y}, {v.z, v.w}};
+}
+__device__ inline Pair<cflt> load_low_c(StBf16, const void* base, int64_t off) {
+    const uint2 v = *((const uint2*)base + off / 2);
+    return {{bf2f(v.x & 0xFFFFu), bf2f(v.x >> 16)}, {bf2f(v.y & 0xFFFFu), bf2f(v.y >> 16)}};
+}
+template <class St>
+__device__ inline Pair<float> load_pair(St st, const void* base, int64_t off, float) {
+    return load_low(st, base, off);
+}
+template <class St>
+__device__ inline Pair<cflt> load_pair(St st, const void* base, int64_t off, cflt) {
+    return load_low_c(st, base, off);
+}
+
+__global__ void k_cast_low(int64_t n_scalars, const double* __restrict__ K, void* __restrict__ out, int kind) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_scalars) return;
+    if (kind == 1)
+        ((float*)out)[i] = (float)K[i];
+    else
+        ((uint16_t*)out)[i] = f2bf((float)K[i]);
+}
+
+// Stage 1 with the low-precision copy: as k_coupling, with the blocks and moments in
+// FP32 arithmetic (FP32 accumulation); the row sums and transposed products are written
+// back in FP64 for the rest of the pipeline.
+template <class T, class F, class St, int Q>
+__global__ __launch_bounds__(256) void k_coupling_low(OpDev op) {
+    constexpr int Q2 = Q * Q;
+    const int64_t c = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= op.nchunks) return;
+    const int t = op.ch_t[c], k0 = op.ch_k0[c], k1 = op.ch_k1[c];
+    const int64_t rs = op.krs[t];
+    const int64_t beg = op.own_rowptr[t];
+    const int ncols = (int)(op.own_rowptr[t + 1] - beg) * Q2;
+    const int64_t koff = op.koff[t];
+    const int32_t* __restrict__ src = op.own_src + beg;
+    const T* __restrict__ mom = (const T*)op.mom;
+    T* __restrict__ P = (T*)op.P + op.pcol[t];
+    F mown[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) mown[a] = to_f(mom[(int64_t)t * Q2 + a]);
+    F acc[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) acc[a] = zero_f<F>();
+    for (int k = k0 + 2 * lane; k < k1; k += 2 * kWave) {
+        const int s0 = k / Q2, b0 = k - s0 * Q2;
+        const F m0 = to_f(mom[(int64_t)src[s0] * Q2 + b0]);
+        F m1 = zero_f<F>();
+        if (k + 1 < ncols) {
+            const int s1 = (k + 1) / Q2, b1 = (k + 1) - s1 * Q2;
+            m1 = to_f(mom[(int64_t)src[s1] * Q2 + b1]);
+        }
+        F p0 = zero_f<F>(), p1 = zero_f<F>();
+#pragma unroll
+        for (int a = 0; a < Q2; ++a) {
+            const Pair<F> kv = load_pair(St(), op.Klow, koff + a * rs + k, F());
+            acc[a] += kv.x * m0 + kv.y * m1;
+            p0 += kv.x * mown[a];
+            p1 += kv.y * mown[a];
+        }
+        *(Pair<T>*)(P + k) = Pair<T>{to_d(p0), to_d(p1)};
+    }
+    int idx;
+    bool ok;
+    wave_reduce_scatter<F, Q2>(acc, lane, idx, ok);
+    if (ok) ((T*)op.partial)[c * Q2 + idx] = to_d(acc[0]);
 }
 
 // Stage 2a.  Local expansion of every cluster: its chunks' row sums plus the transposed
@@ -943,7 +1063,8 @@ hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st
 }
 
 template <class T, int Q>
-static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, bool with_near, hipStream_t st) {
+static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, bool with_near, int prec,
+                                 hipStream_t st) {
     switch (stage) {
         case 0: {
             const unsigned nup = (unsigned)op.S.geom.npatch << (2 * op.up_root);
@@ -953,9 +1074,18 @@ static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, b
                 hipLaunchKernelGGL((k_up_top<T, Q>), dim3((unsigned)op.S.geom.npatch), dim3(256), 0, st, op);
             break;
         }
-        case 1:
-            if (op.nchunks > 0) hipLaunchKernelGGL((k_coupling<T, Q>), dim3(nblk(op.nchunks, 4)), dim3(256), 0, st, op);
+        case 1: {
+            if (op.nchunks == 0) break;
+            const dim3 g(nblk(op.nchunks, 4)), b(256);
+            using F = typename std::conditional<std::is_same<T, double>::value, float, cflt>::type;
+            if (prec == 0)
+                hipLaunchKernelGGL((k_coupling<T, Q>), g, b, 0, st, op);
+            else if (op.low == 1)
+                hipLaunchKernelGGL((k_coupling_low<T, F, StFp32, Q>), g, b, 0, st, op);
+            else
+                hipLaunchKernelGGL((k_coupling_low<T, F, StBf16, Q>), g, b, 0, st, op);
             break;
+        }
         case 2:
             if (op.nstored > 0) hipLaunchKernelGGL((k_lv_gather<T, Q>), dim3(nblk(op.ncl, 4)), dim3(256), 0, st, op);
             break;
@@ -971,35 +1101,43 @@ static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, b
 }
 
 template <class T>
-static hipError_t apply_stage_t(const OpDev& op, int stage, const T* x, T* y, bool with_near, hipStream_t st) {
+static hipError_t apply_stage_t(const OpDev& op, int stage, const T* x, T* y, bool with_near, int prec,
+                                hipStream_t st) {
     switch (op.q) {
-        case 1: return apply_stage_tq<T, 1>(op, stage, x, y, with_near, st);
-        case 2: return apply_stage_tq<T, 2>(op, stage, x, y, with_near, st);
-        case 3: return apply_stage_tq<T, 3>(op, stage, x, y, with_near, st);
-        case 4: return apply_stage_tq<T, 4>(op, stage, x, y, with_near, st);
-        case 5: return apply_stage_tq<T, 5>(op, stage, x, y, with_near, st);
-        case 6: return apply_stage_tq<T, 6>(op, stage, x, y, with_near, st);
-        case 7: return apply_stage_tq<T, 7>(op, stage, x, y, with_near, st);
-        default: return apply_stage_tq<T, 8>(op, stage, x, y, with_near, st);
+        case 1: return apply_stage_tq<T, 1>(op, stage, x, y, with_near, prec, st);
+        case 2: return apply_stage_tq<T, 2>(op, stage, x, y, with_near, prec, st);
+        case 3: return apply_stage_tq<T, 3>(op, stage, x, y, with_near, prec, st);
+        case 4: return apply_stage_tq<T, 4>(op, stage, x, y, with_near, prec, st);
+        case 5: return apply_stage_tq<T, 5>(op, stage, x, y, with_near, prec, st);
+        case 6: return apply_stage_tq<T, 6>(op, stage, x, y, with_near, prec, st);
+        case 7: return apply_stage_tq<T, 7>(op, stage, x, y, with_near, prec, st);
+        default: return apply_stage_tq<T, 8>(op, stage, x, y, with_near, prec, st);
     }
 }
 
-hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, hipStream_t st) {
-    if (op.cplx) return apply_stage_t<cdbl>(op, stage, (const cdbl*)x, (cdbl*)y, true, st);
-    return apply_stage_t<double>(op, stage, (const double*)x, (double*)y, true, st);
+hipError_t launch_apply_stage(const OpDev& op, int stage, const void* x, void* y, int prec, hipStream_t st) {
+    if (op.cplx) return apply_stage_t<cdbl>(op, stage, (const cdbl*)x, (cdbl*)y, true, prec, st);
+    return apply_stage_t<double>(op, stage, (const double*)x, (double*)y, true, prec, st);
 }
 
-hipError_t launch_apply(const OpDev& op, const void* x, void* y, hipStream_t st) {
+hipError_t launch_apply(const OpDev& op, const void* x, void* y, int prec, hipStream_t st) {
     for (int s = 0; s < kApplyStages; ++s) {
-        hipError_t e = launch_apply_stage(op, s, x, y, st);
+        hipError_t e = launch_apply_stage(op, s, x, y, prec, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st) {
-    if (op.cplx) return apply_stage_t<cdbl>(op, 0, (const cdbl*)x, nullptr, false, st);
-    return apply_stage_t<double>(op, 0, (const double*)x, nullptr, false, st);
+    if (op.cplx) return apply_stage_t<cdbl>(op, 0, (const cdbl*)x, nullptr, false, 0, st);
+    return apply_stage_t<double>(op, 0, (const double*)x, nullptr, false, 0, st);
+}
+
+hipError_t launch_cast_low(const OpDev& op, hipStream_t st) {
+    const int64_t n = (int64_t)op.nchunks > 0 ? (int64_t)op.ktotal_scalars : 0;
+    if (n == 0 || op.low == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_low, dim3(nblk(n, 256)), dim3(256), 0, st, n, (const double*)op.K, op.Klow, op.low);
+    return hipGetLastError();
 }
 
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,

@@ -33,6 +33,7 @@ hipError_t solve_scale_givens(int cplx, int64_t n, int j, const double* npart, c
 hipError_t solve_residual(int cplx, int64_t n, const void* b, void* w, double* npart, int copy_b, hipStream_t s);
 hipError_t solve_start(int cplx, int64_t n, const double* npart, const void* w, void* v0, const GmresState& st,
                        hipStream_t s);
+hipError_t solve_axpy(int cplx, int64_t n, double a, const void* x, void* y, hipStream_t s);
 hipError_t solve_backsolve_update(int cplx, int64_t n, int k, const void* V, void* x, const GmresState& st,
                                   hipStream_t s);
 

@@ -215,6 +215,12 @@ __global__ __launch_bounds__(kThreads) void k_s_xupdate(int64_t n, int k, const 
 }
 
 template <class T>
+__global__ __launch_bounds__(kThreads) void k_s_axpy(int64_t n, double a, const T* __restrict__ x, T* y) {
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+
+template <class T>
 struct Launch {
     static hipError_t dots(int64_t n, int k, const void* V, const void* w, void* part, hipStream_t s) {
         hipLaunchKernelGGL(k_s_dots<T>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, k, (const T*)V, (const T*)w,
@@ -269,6 +275,15 @@ hipError_t solve_start(int cplx, int64_t n, const double* npart, const void* w, 
     else
         hipLaunchKernelGGL(k_s_start<double>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, npart, (const double*)w,
                            (double*)v0, st);
+    return hipGetLastError();
+}
+
+hipError_t solve_axpy(int cplx, int64_t n, double a, const void* x, void* y, hipStream_t s) {
+    const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+    if (cplx)
+        hipLaunchKernelGGL(k_s_axpy<cdbl>, dim3(nb), dim3(kThreads), 0, s, n, a, (const cdbl*)x, (cdbl*)y);
+    else
+        hipLaunchKernelGGL(k_s_axpy<double>, dim3(nb), dim3(kThreads), 0, s, n, a, (const double*)x, (double*)y);
     return hipGetLastError();
 }
 

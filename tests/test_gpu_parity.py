@@ -142,7 +142,7 @@ def test_gmres(B, orc, cid):
     x0 = W.CONFIGS[0]["x0"]
     b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
     x, stats = A.solve(b, tol=1e-12, restart=30, maxit=500)
-    it, ok, rr = stats[0]
+    it, ok, rr, _ = stats[0]
     assert ok and rr <= 1e-12
     xg = x.cpu().numpy()[0]
     bo = So.rhs(orc.POINT_SOURCE, x0)
@@ -156,7 +156,7 @@ def test_gmres_nonconvergence_reported(B, orc):
     g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_h2")
     b = s.rhs(B.BEM_DATA_POINT_SOURCE, [W.CONFIGS[0]["x0"]])
     x, stats = A.solve(b, tol=1e-14, restart=5, maxit=3)
-    it, ok, rr = stats[0]
+    it, ok, rr, _ = stats[0]
     assert not ok and it == 3 and rr > 1e-14 and np.isfinite(x.cpu().numpy()).all()
 
 
@@ -227,7 +227,7 @@ def test_full_size_solve(B, full):
     x0, pts = W.c1_inputs()
     b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
     rho, stats = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"])
-    it, ok, rr = stats[0]
+    it, ok, rr, _ = stats[0]
     assert ok and rr <= c["tol"]
     r = (b[0] - A.apply(rho[0])).norm() / b[0].norm()
     assert float(r) <= c["tol"]
