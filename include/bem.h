@@ -86,7 +86,12 @@ typedef struct bem_h2_params {
     int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 128     */
     int far_low;      /* extra low-precision copy of the coupling blocks for mixed-precision
                          applies and solves: 0 none, BEM_PREC_FP32 or BEM_PREC_BF16      */
-    int reserved[2];  /* must be zero */
+    int batch_rhs;    /* right-hand sides per batched apply: with batch_rhs > 1 the operator
+                         workspace holds slabs for that many columns and bem_apply /
+                         bem_apply_ex with nrhs > 1 run the many-RHS kernels on up to
+                         batch_rhs columns per pass (q <= 6; BEM_PREC_BF16 there needs
+                         q <= 5 and uses the matrix cores); 0 or 1: one column at a time */
+    int reserved[1];  /* must be zero */
 } bem_h2_params;
 
 /* arithmetic of the far-field coupling in bem_apply_ex / refined solves */
@@ -192,7 +197,10 @@ int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64
 
 /* y = A x like bem_apply with the far-field coupling in the given precision:
  * BEM_PREC_FP64, or the low precision the operator was assembled with (far_low); EINVAL
- * if that copy does not exist.  Near field, transforms and transfers stay FP64. */
+ * if that copy does not exist.  Near field, transforms and transfers stay FP64.  With
+ * batch_rhs > 1 at planning and nrhs > 1, columns go through the many-RHS kernels in
+ * passes of up to batch_rhs columns; BEM_PREC_BF16 there multiplies BF16 blocks and BF16
+ * moments on the matrix cores with FP32 accumulation. */
 int bem_apply_ex(bem_operator A, int precision, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy,
                  int nrhs, hipStream_t stream);
 

@@ -86,10 +86,11 @@ class Operator:
     """Compressed single-layer operator: plan on the host, assemble on the GPU."""
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
-                 assemble: bool = True, chunk_cols: int = 0, far_low: int = 0):
+                 assemble: bool = True, chunk_cols: int = 0, far_low: int = 0, batch_rhs: int = 0):
         self.space = space
         self.far_low = far_low
-        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low)
+        self.batch_rhs = batch_rhs
+        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs)
         self.q = q
         self.ndof = self.info.ndof
         self.op_ws = None
@@ -115,7 +116,8 @@ class Operator:
 
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None, prec: int = BEM_PREC_FP64) -> torch.Tensor:
         """y = A x for x of shape (N,) or (nrhs, N); prec selects the far-field coupling's
-        precision (BEM_PREC_FP64 or the far_low the operator was assembled with)."""
+        precision (BEM_PREC_FP64 or the far_low the operator was assembled with).  With
+        batch_rhs > 1 several columns go through the many-RHS kernels together."""
         xx = x.reshape(-1, self.ndof).contiguous()
         y = out if out is not None else torch.empty_like(xx)
         C.bem_apply_ex(self.h, prec, xx.data_ptr(), self.ndof, y.data_ptr(), self.ndof, xx.shape[0], _stream())

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "bem_batch.h"
 #include "bem_kernels.h"
 #include "bem_plan.h"
 #include "bem_solve.h"
@@ -66,9 +67,13 @@ struct bem_operator_s {
     bool assembled = false;
     bem_operator_info info{};
     std::vector<int32_t> touch_lp;
+    std::vector<int64_t> fb_off;  // host copies of the per-pair block table (kept until destroy,
+    std::vector<int32_t> fb_rs;   // the uploads above are asynchronous)
     OpDev dev{};
     size_t scal = 8;  // bytes per scalar
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
+    int batch_rhs = 0;  // columns per many-RHS pass (slabs in the operator workspace)
+    BatchDev bdev{};
     // stage timing of bem_apply (bem_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kApplyStages + 1 events per recorded apply
@@ -86,7 +91,7 @@ struct bem_operator_s {
 // root level of the subtrees summed by one block each in the upward pass (depth <= 2)
 static int up_root_of(const Plan& p) { return std::max(p.leaf - 2, 0); }
 
-static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
+static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev* bdo = nullptr) {
     const Plan& p = A.plan;
     Bump b(base);
     OpDev o{};
@@ -118,6 +123,27 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d) {
     o.E = b.take<double>(p.E.size());
     o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
     o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+    if (A.batch_rhs > 1) {
+        // many-RHS slabs and the per-pair block table
+        const size_t Rb = (size_t)A.batch_rhs, nch = (Rb + kBatchChunk - 1) / kBatchChunk, N = (size_t)p.S.ndof;
+        const size_t np = p.far_t.size();
+        BatchDev bd{};
+        bd.rmax = A.batch_rhs;
+        bd.far_rowptr = b.take<int64_t>(p.far_rowptr.size());
+        bd.far_s = b.take<int32_t>(np);
+        bd.fb_off = b.take<int64_t>(np);
+        bd.fb_rs = b.take<int32_t>(np);
+        bd.xs = b.take<char>(N * Rb * A.scal);
+        bd.ys = b.take<char>(N * Rb * A.scal);
+        bd.mom = b.take<char>((size_t)p.ncl * p.q2 * Rb * A.scal);
+        bd.lv = b.take<char>((size_t)p.ncl * p.q2 * Rb * A.scal);
+        bd.yl = b.take<char>((size_t)p.nleaves * p.nloc * p.nloc * Rb * A.scal);
+        if (A.far_low == 2) {
+            bd.Af = b.take<char>(np * bf_row_tiles(A.cplx) * kBatchChunk * 16);
+            bd.Bf = b.take<char>((size_t)p.ncl * nch * bf_col_tiles(A.cplx) * kBatchChunk * 16);
+        }
+        if (bdo) *bdo = bd;
+    }
     if (d) *d = o;
     return b.off + 256;
 }
@@ -464,9 +490,10 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
 
 int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
-    for (int i = 0; i < 2; ++i)
-        if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    if (p->reserved[0] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
     if (p->far_low < 0 || p->far_low > 2) return fail(BEM_EINVAL, "far_low must be 0, BEM_PREC_FP32 or BEM_PREC_BF16");
+    if (p->batch_rhs < 0 || p->batch_rhs > 4096) return fail(BEM_EINVAL, "batch_rhs must lie in [0, 4096]");
+    if (p->batch_rhs > 1 && p->q > 6) return fail(BEM_EUNSUPPORTED, "many-RHS kernels need q <= 6");
     H2Params P;
     P.chunk = p->chunk_cols == 0 ? 128 : p->chunk_cols;
     P.q = p->q;
@@ -490,6 +517,7 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     A->cplx = s->S.ker.pde == PDE_HELMHOLTZ;
     A->scal = A->cplx ? 16 : 8;
     A->far_low = p->far_low;
+    A->batch_rhs = p->batch_rhs > 1 ? p->batch_rhs : 0;
     const Plan& pl = A->plan;
     for (size_t lp = 0; lp + 1 < pl.touch_rowptr.size(); ++lp)
         if (pl.touch_rowptr[lp + 1] > pl.touch_rowptr[lp]) A->touch_lp.push_back((int32_t)lp);
@@ -535,7 +563,8 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     char* tb = (char*)(((uintptr_t)tmp_ws + 255) / 256 * 256);
     OpDev d;
     AsmDev as;
-    op_layout(*A, ob, &d);
+    BatchDev bd{};
+    op_layout(*A, ob, &d, &bd);
     tmp_layout(*A, tb, &as);
     d.S = p.S;
     d.bt = A->sp->bt;
@@ -607,6 +636,28 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(launch_near_gather(d, as, stream));
     HIP_CHECK(launch_far_assemble(d, as, stream));
     HIP_CHECK(launch_cast_low(d, stream));
+    if (A->batch_rhs > 1) {
+        // where each ordered far block sits in the stored rows (row 0 of the block, the
+        // owner's row stride, negative when the block is stored as its transpose)
+        const size_t np = p.far_t.size();
+        A->fb_off.resize(np);
+        A->fb_rs.resize(np);
+        for (size_t i = 0; i < np; ++i) {
+            const int t = p.far_t[i], s = p.far_s[i];
+            const int lo = std::min(t, s), hi = std::max(t, s);
+            const int owner = ((lo + hi) & 1) ? lo : hi, other = owner == t ? s : t;
+            auto first = p.own_src.begin() + p.own_rowptr[owner], last = p.own_src.begin() + p.own_rowptr[owner + 1];
+            const int64_t slot = std::lower_bound(first, last, other) - first;
+            A->fb_off[i] = p.koff[owner] + slot * p.q2;
+            A->fb_rs[i] = owner == t ? p.krs[owner] : -p.krs[owner];
+        }
+        HIP_CHECK(up(bd.far_rowptr, p.far_rowptr.data(), p.far_rowptr.size() * 8));
+        HIP_CHECK(up(bd.far_s, p.far_s.data(), np * 4));
+        HIP_CHECK(up(bd.fb_off, A->fb_off.data(), np * 8));
+        HIP_CHECK(up(bd.fb_rs, A->fb_rs.data(), np * 4));
+        if (A->far_low == 2 && p.P.q <= 5) HIP_CHECK(launch_build_bf_blocks(d, bd, (int64_t)np, stream));
+    }
+    A->bdev = bd;
     // the host tables above are copied from pageable memory; make sure they have been read
     // before the caller may free the temporary workspace (the plan itself stays alive)
     A->dev = d;
@@ -631,6 +682,32 @@ int bem_apply_ex(bem_operator A, int prec, const void* x_dev, int64_t ldx, void*
     char* yb = (char*)y_dev;
     const size_t span_x = ((size_t)(nrhs - 1) * ldx + N) * A->scal, span_y = ((size_t)(nrhs - 1) * ldy + N) * A->scal;
     if (!(xb + span_x <= yb || yb + span_y <= xb)) return fail(BEM_EINVAL, "x and y overlap");
+    if (nrhs > 1 && A->batch_rhs > 1) {
+        if (prec == BEM_PREC_BF16 && A->plan.P.q > 5) return fail(BEM_EUNSUPPORTED, "BF16 many-RHS coupling needs q <= 5");
+        for (int r0 = 0; r0 < nrhs; r0 += A->batch_rhs) {
+            BatchDev bd = A->bdev;
+            bd.R = std::min(A->batch_rhs, nrhs - r0);
+            const void* xr = xb + (size_t)r0 * ldx * A->scal;
+            void* yr = yb + (size_t)r0 * ldy * A->scal;
+            if (!A->prof) {
+                HIP_CHECK(launch_apply_batched(A->dev, bd, xr, ldx, yr, ldy, prec, stream));
+                continue;
+            }
+            const size_t need = A->ev_used + kBatchStages + 1;
+            while (A->ev.size() < need) {
+                hipEvent_t e;
+                HIP_CHECK(hipEventCreate(&e));
+                A->ev.push_back(e);
+            }
+            HIP_CHECK(hipEventRecord(A->ev[A->ev_used], stream));
+            for (int s = 0; s < kBatchStages; ++s) {
+                HIP_CHECK(launch_apply_batched_stage(A->dev, bd, s, xr, ldx, yr, ldy, prec, stream));
+                HIP_CHECK(hipEventRecord(A->ev[A->ev_used + 1 + s], stream));
+            }
+            A->ev_used = need;
+        }
+        return BEM_OK;
+    }
     for (int r = 0; r < nrhs; ++r) {
         const void* xr = xb + (size_t)r * ldx * A->scal;
         void* yr = yb + (size_t)r * ldy * A->scal;

@@ -1,0 +1,666 @@
+// gfx950 kernels of the H^2 matvec over many right-hand sides (see bem_batch.h).
+//
+// Stages of one batched product Y = A X (Sec. 2 "compressed system matrix", Sec. 4
+// "System Matrix"): column-major X to the slab layout, forward transform at the leaves,
+// upward transfer level by level, far-field coupling per target cluster, downward transfer
+// level by level, backward transform per leaf, then per near-field row group the near
+// product plus the gathered backward transforms, written back column-major.  Every kernel
+// is deterministic: no atomics, fixed summation order.
+#include "bem_batch.h"
+#include "bem_device.h"
+
+#include <type_traits>
+
+namespace bem {
+
+namespace {
+
+constexpr int kGroupRowsB = 16;  // rows per near-field row group at most (host: kGroupRows)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+__device__ inline int nchunks(int R) { return (R + kBatchChunk - 1) / kBatchChunk; }
+
+// conversions of a moment to the coupling's arithmetic type
+template <class F>
+__device__ inline F cvt(double v);
+template <>
+__device__ inline double cvt<double>(double v) { return v; }
+template <>
+__device__ inline float cvt<float>(double v) { return (float)v; }
+template <class F>
+__device__ inline F cvt(cdbl v);
+template <>
+__device__ inline cdbl cvt<cdbl>(cdbl v) { return v; }
+template <>
+__device__ inline cflt cvt<cflt>(cdbl v) { return {(float)v.re, (float)v.im}; }
+
+__device__ inline double part_re(double v) { return v; }
+__device__ inline double part_re(cdbl v) { return v.re; }
+__device__ inline double part_im(double) { return 0.0; }
+__device__ inline double part_im(cdbl v) { return v.im; }
+
+// ------------------------------------------------------------------ slab transposes
+// 64 DOFs x 32 right-hand sides per block through LDS
+template <class T>
+__global__ __launch_bounds__(256) void kb_to_slab(int64_t N, int R, const T* __restrict__ x, int64_t ldx,
+                                                  T* __restrict__ xs) {
+    __shared__ T tile[32][65];
+    const int64_t g0 = (int64_t)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 32;
+    {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int64_t g = g0 + tx;
+        for (int i = ty; i < 32; i += 4)
+            if (r0 + i < R && g < N) tile[i][tx] = x[g + (int64_t)(r0 + i) * ldx];
+    }
+    __syncthreads();
+    const int tr = threadIdx.x & 31, tg = threadIdx.x >> 5;
+    for (int i = tg; i < 64; i += 8)
+        if (r0 + tr < R && g0 + i < N) xs[(g0 + i) * R + r0 + tr] = tile[tr][i];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void kb_from_slab(int64_t N, int R, const T* __restrict__ ys, T* __restrict__ y,
+                                                    int64_t ldy) {
+    __shared__ T tile[32][65];
+    const int64_t g0 = (int64_t)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 32;
+    {
+        const int tr = threadIdx.x & 31, tg = threadIdx.x >> 5;
+        for (int i = tg; i < 64; i += 8)
+            if (r0 + tr < R && g0 + i < N) tile[tr][i] = ys[(g0 + i) * R + r0 + tr];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t g = g0 + tx;
+    for (int i = ty; i < 32; i += 4)
+        if (r0 + i < R && g < N) y[g + (int64_t)(r0 + i) * ldy] = tile[i][tx];
+}
+
+// ------------------------------------------------------------------ forward + upward
+// Leaf moments m_tau[a] = sum_g V_tau[a, g] x_g, with the 1-D moment tables of both
+// directions applied one after the other; one wave per (leaf, 64 right-hand sides).
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_leaf_moments(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q;
+    const int nch = nchunks(bd.R);
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= op.nleaves * nch) return;
+    const int l = (int)(item / nch), ch = (int)(item % nch);
+    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
+    const bool on = r < R;
+    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
+    const int j = l % n1, i = (l / n1) % n1, f = l / (n1 * n1);
+    const T* __restrict__ xs = (const T*)bd.xs;
+    const double* __restrict__ Vi = op.V1 + (int64_t)i * Q * nloc;
+    const double* __restrict__ Vj = op.V1 + (int64_t)j * Q * nloc;
+    T acc[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) acc[a] = zero<T>();
+    for (int m1 = 0; m1 < nloc; ++m1) {
+        const int64_t g0 = dof_id(op.S, f, i * stride + m1, j * stride);
+        T t[Q];
+#pragma unroll
+        for (int a2 = 0; a2 < Q; ++a2) t[a2] = zero<T>();
+        for (int m2 = 0; m2 < nloc; ++m2) {
+            const T xv = on ? xs[(g0 + m2) * R + r] : zero<T>();
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) t[a2] += Vj[a2 * nloc + m2] * xv;
+        }
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) {
+            const double w = Vi[a1 * nloc + m1];
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) acc[a1 * Q + a2] += w * t[a2];
+        }
+    }
+    if (!on) return;
+    T* mom = (T*)bd.mom + (op.lev_off[op.leaf] + l) * (int64_t)Q2 * R + r;
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) mom[(int64_t)a * R] = acc[a];
+}
+
+// Moments at level lev from the four children at lev + 1 (upward transfer):
+// m_P[a] = sum_children sum_p E_b1[p1][a1] E_b2[p2][a2] m_c[p].
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_upward(OpDev op, BatchDev bd, int lev) {
+    constexpr int Q2 = Q * Q;
+    const int nch = nchunks(bd.R);
+    const int n = 1 << lev;
+    const int64_t nl = (int64_t)op.S.geom.npatch * n * n;
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= nl * nch) return;
+    const int64_t loc = item / nch;
+    const int ch = (int)(item % nch);
+    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
+    const bool on = r < R;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    const double* __restrict__ E = op.E;
+    const T* __restrict__ mom = (const T*)bd.mom;
+    T acc[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) acc[a] = zero<T>();
+#pragma unroll 1
+    for (int c4 = 0; c4 < 4; ++c4) {
+        const int b1 = c4 >> 1, b2 = c4 & 1;
+        const int64_t c = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
+        const T* mc = mom + c * Q2 * R + r;
+#pragma unroll 1
+        for (int p1 = 0; p1 < Q; ++p1) {
+            T in[Q];
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) in[a2] = zero<T>();
+#pragma unroll
+            for (int p2 = 0; p2 < Q; ++p2) {
+                const T mv = on ? mc[(int64_t)(p1 * Q + p2) * R] : zero<T>();
+#pragma unroll
+                for (int a2 = 0; a2 < Q; ++a2) in[a2] += E[(b2 * Q + p2) * Q + a2] * mv;
+            }
+#pragma unroll
+            for (int a1 = 0; a1 < Q; ++a1) {
+                const double w = E[(b1 * Q + p1) * Q + a1];
+#pragma unroll
+                for (int a2 = 0; a2 < Q; ++a2) acc[a1 * Q + a2] += w * in[a2];
+            }
+        }
+    }
+    if (!on) return;
+    T* out = (T*)bd.mom + (op.lev_off[lev] + loc) * Q2 * R + r;
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) out[(int64_t)a * R] = acc[a];
+}
+
+// ------------------------------------------------------------------ coupling (vector units)
+// Local expansion of target cluster t for 64 right-hand sides: l_t = sum over its
+// admissible sources s of K_ts m_s, in the arithmetic type F (FP64, or FP32 from the FP32
+// copy).  The four waves of a block take every fourth source; each wave stages the block
+// K_ts (transposed when it is stored in the source's rows) in its LDS slice and every
+// lane applies it to its own right-hand side.  The four partial sums are added in wave
+// order.
+template <class T, class F, int Q>
+__global__ __launch_bounds__(256) void kb_coupling(OpDev op, BatchDev bd, const F* __restrict__ K) {
+    constexpr int Q2 = Q * Q;
+    __shared__ F Ks[4][Q2 * Q2];
+    __shared__ F red[Q2][kBatchChunk];
+    const int nch = nchunks(bd.R);
+    const int64_t t = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int R = bd.R, r = ch * kBatchChunk + lane;
+    const bool on = r < R;
+    const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
+    const T* __restrict__ mom = (const T*)bd.mom;
+    F* ks = Ks[w];
+    F acc[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) acc[a] = zero_f<F>();
+    for (int64_t p = beg + w; p < end; p += 4) {
+        const int s = bd.far_s[p];
+        const int64_t off = bd.fb_off[p];
+        const int rs = bd.fb_rs[p];
+        const bool tr = rs < 0;
+        const int ars = tr ? -rs : rs;
+        for (int idx = lane; idx < Q2 * Q2; idx += kWave) {
+            const int i = idx / Q2, jj = idx - i * Q2;
+            ks[tr ? jj * Q2 + i : idx] = K[off + (int64_t)i * ars + jj];
+        }
+        wave_sync();
+        const T* ms = mom + (int64_t)s * Q2 * R + r;
+#pragma unroll 1
+        for (int b0 = 0; b0 < Q2; b0 += Q) {
+            F mv[Q];
+#pragma unroll
+            for (int u = 0; u < Q; ++u) mv[u] = on ? cvt<F>(ms[(int64_t)(b0 + u) * R]) : zero_f<F>();
+#pragma unroll
+            for (int a = 0; a < Q2; ++a)
+#pragma unroll
+                for (int u = 0; u < Q; ++u) acc[a] += ks[a * Q2 + b0 + u] * mv[u];
+        }
+        wave_sync();
+    }
+    for (int step = 0; step < 4; ++step) {
+        if (w == step)
+#pragma unroll
+            for (int a = 0; a < Q2; ++a) red[a][lane] = step == 0 ? acc[a] : red[a][lane] + acc[a];
+        __syncthreads();
+    }
+    if (w == 0 && on) {
+        T* lv = (T*)bd.lv + t * Q2 * R + r;
+#pragma unroll
+        for (int a = 0; a < Q2; ++a) lv[(int64_t)a * R] = to_d(red[a][lane]);
+    }
+}
+
+// ------------------------------------------------------------------ coupling (matrix cores)
+// BF16 fragments.  v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16], e = 0..7, and receives C[4 (l / 16) + e][l % 16], e = 0..3.
+// A (one ordered block): rows = target nodes a (real), or [Re K; Im K] (complex), columns
+// = source nodes b, zero-padded to 32.  B (one cluster, 64 right-hand sides): rows =
+// source nodes b, columns = the right-hand sides (real) or [Re m | Im m] (complex).
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_bf_blocks(OpDev op, BatchDev bd, int64_t npairs) {
+    constexpr int Q2 = Q * Q;
+    constexpr bool CP = sizeof(T) == 16;
+    constexpr int RT = CP ? 4 : 2;
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (item >= npairs * RT) return;
+    const int64_t p = item / RT;
+    const int rt = (int)(item % RT);
+    const int64_t off = bd.fb_off[p];
+    const int rs = bd.fb_rs[p];
+    const bool tr = rs < 0;
+    const int ars = tr ? -rs : rs;
+    const T* __restrict__ K = (const T*)op.K;
+    const int row = 16 * rt + (lane & 15), k0 = 8 * (lane >> 4);
+    const int a = row < Q2 ? row : row - Q2;
+    const bool im = row >= Q2;
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int b = k0 + e;
+        float x = 0.0f;
+        if (b < Q2 && a < Q2 && (CP || !im)) {
+            const T kv = K[off + (tr ? (int64_t)b * ars + a : (int64_t)a * ars + b)];
+            x = (float)(im ? part_im(kv) : part_re(kv));
+        }
+        v[e] = f2bf(x);
+    }
+    ((u16x8*)bd.Af)[item * kWave + lane] = v;
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_bf_moments(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q;
+    constexpr bool CP = sizeof(T) == 16;
+    constexpr int NT = CP ? 8 : 4;
+    const int nch = nchunks(bd.R);
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= op.ncl * nch) return;
+    const int64_t c = item / nch;
+    const int ch = (int)(item % nch);
+    const int lane = threadIdx.x & 63, R = bd.R;
+    const T* __restrict__ mom = (const T*)bd.mom + c * Q2 * R;
+    const int k0 = 8 * (lane >> 4);
+#pragma unroll 1
+    for (int nt = 0; nt < NT; ++nt) {
+        const int col = 16 * nt + (lane & 15);
+        const bool im = CP && col >= kBatchChunk;
+        const int r = ch * kBatchChunk + (im ? col - kBatchChunk : col);
+        u16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int b = k0 + e;
+            float x = 0.0f;
+            if (b < Q2 && r < R) {
+                const T mv = mom[(int64_t)b * R + r];
+                x = (float)(im ? part_im(mv) : part_re(mv));
+            }
+            v[e] = f2bf(x);
+        }
+        ((u16x8*)bd.Bf)[(item * NT + nt) * kWave + lane] = v;
+    }
+}
+
+// l_t = sum_s K_ts m_s on the matrix cores for 64 right-hand sides: per source one row of
+// RT x NT MFMA tiles over a k-step of 32 (the q^2 <= 32 source nodes); the four waves of a
+// block take every fourth source and their FP32 tiles are added in wave order in LDS.
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_coupling_mfma(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q;
+    static_assert(Q2 <= 32, "one k-step of 32 per block");
+    constexpr bool CP = sizeof(T) == 16;
+    constexpr int RT = CP ? 4 : 2, NT = CP ? 8 : 4;
+    __shared__ float red[RT * 16][NT * 16 + 1];
+    const int nch = nchunks(bd.R);
+    const int64_t t = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
+    const u16x8* __restrict__ Af = (const u16x8*)bd.Af;
+    const u16x8* __restrict__ Bf = (const u16x8*)bd.Bf;
+    f32x4 acc[RT][NT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // fragments of the next source are loaded before the products of the current one
+    u16x8 a[RT], b[NT];
+    auto load = [&](int64_t p, u16x8* fa, u16x8* fb) {
+        const int64_t s = bd.far_s[p];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) fa[i] = Af[(p * RT + i) * kWave + lane];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) fb[j] = Bf[((s * nch + ch) * NT + j) * kWave + lane];
+    };
+    int64_t p = beg + w;
+    if (p < end) load(p, a, b);
+    while (p < end) {
+        const int64_t pn = p + 4;
+        u16x8 an[RT], bn[NT];
+        if (pn < end) load(pn, an, bn);
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[i]),
+                                                                    __builtin_bit_cast(bf16x8, b[j]), acc[i][j], 0, 0, 0);
+        if (pn < end) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) a[i] = an[i];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) b[j] = bn[j];
+        }
+        p = pn;
+    }
+    const int rq = 4 * (lane >> 4), cq = lane & 15;
+    for (int step = 0; step < 4; ++step) {
+        if (w == step)
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        float& dst = red[16 * i + rq + e][16 * j + cq];
+                        dst = step == 0 ? acc[i][j][e] : dst + acc[i][j][e];
+                    }
+        __syncthreads();
+    }
+    T* lv = (T*)bd.lv + t * Q2 * bd.R;
+    for (int idx = threadIdx.x; idx < Q2 * kBatchChunk; idx += blockDim.x) {
+        const int a = idx / kBatchChunk, rl = idx % kBatchChunk, r = ch * kBatchChunk + rl;
+        if (r >= bd.R) continue;
+        if constexpr (CP) {
+            // (Re K + i Im K)(Re m + i Im m)
+            const double re = (double)red[a][rl] - (double)red[Q2 + a][kBatchChunk + rl];
+            const double im = (double)red[a][kBatchChunk + rl] + (double)red[Q2 + a][rl];
+            ((cdbl*)lv)[(int64_t)a * bd.R + r] = cdbl{re, im};
+        } else {
+            ((double*)lv)[(int64_t)a * bd.R + r] = (double)red[a][rl];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ downward + backward
+// Local expansions at level lev >= 1 receive their parent's (complete) expansion:
+// l_c[p] += sum_a E_b1[p1][a1] E_b2[p2][a2] l_P[a].
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_downward(OpDev op, BatchDev bd, int lev) {
+    constexpr int Q2 = Q * Q;
+    const int nch = nchunks(bd.R);
+    const int n = 1 << lev, np = n >> 1;
+    const int64_t nl = (int64_t)op.S.geom.npatch * n * n;
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= nl * nch) return;
+    const int64_t loc = item / nch;
+    const int ch = (int)(item % nch);
+    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
+    if (r >= R) return;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    const int b1 = i & 1, b2 = j & 1;
+    const double* __restrict__ E = op.E;
+    const int64_t P = op.lev_off[lev - 1] + ((int64_t)f * np + (i >> 1)) * np + (j >> 1);
+    const T* vp = (const T*)bd.lv + P * Q2 * R + r;
+    T* vc = (T*)bd.lv + (op.lev_off[lev] + loc) * Q2 * R + r;
+    T acc[Q2];
+#pragma unroll
+    for (int p = 0; p < Q2; ++p) acc[p] = vc[(int64_t)p * R];
+#pragma unroll 1
+    for (int a1 = 0; a1 < Q; ++a1) {
+        T in[Q];
+#pragma unroll
+        for (int p2 = 0; p2 < Q; ++p2) in[p2] = zero<T>();
+#pragma unroll
+        for (int a2 = 0; a2 < Q; ++a2) {
+            const T v = vp[(int64_t)(a1 * Q + a2) * R];
+#pragma unroll
+            for (int p2 = 0; p2 < Q; ++p2) in[p2] += E[(b2 * Q + p2) * Q + a2] * v;
+        }
+#pragma unroll
+        for (int p1 = 0; p1 < Q; ++p1) {
+            const double w = E[(b1 * Q + p1) * Q + a1];
+#pragma unroll
+            for (int p2 = 0; p2 < Q; ++p2) acc[p1 * Q + p2] += w * in[p2];
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < Q2; ++p) vc[(int64_t)p * R] = acc[p];
+}
+
+// Backward transform of one leaf: its contribution V_tau^T l_tau to each of the nloc^2
+// B-splines that meet it, stored per leaf (added per DOF by the near-field kernel).
+template <class T, int Q>
+__global__ __launch_bounds__(256) void kb_leaf_back(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q;
+    const int nch = nchunks(bd.R);
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= op.nleaves * nch) return;
+    const int l = (int)(item / nch), ch = (int)(item % nch);
+    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
+    if (r >= R) return;
+    const int n1 = op.nleaf1, nloc = op.nloc;
+    const int j = l % n1, i = (l / n1) % n1;
+    const double* __restrict__ Vi = op.V1 + (int64_t)i * Q * nloc;
+    const double* __restrict__ Vj = op.V1 + (int64_t)j * Q * nloc;
+    const T* lvp = (const T*)bd.lv + (op.lev_off[op.leaf] + l) * Q2 * R + r;
+    T v[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) v[a] = lvp[(int64_t)a * R];
+    T* yl = (T*)bd.yl + (int64_t)l * nloc * nloc * R + r;
+    for (int m2 = 0; m2 < nloc; ++m2) {
+        T t[Q];
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) {
+            T s = zero<T>();
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) s += Vj[a2 * nloc + m2] * v[a1 * Q + a2];
+            t[a1] = s;
+        }
+        for (int m1 = 0; m1 < nloc; ++m1) {
+            T s = zero<T>();
+#pragma unroll
+            for (int a1 = 0; a1 < Q; ++a1) s += Vi[a1 * nloc + m1] * t[a1];
+            yl[(int64_t)(m1 * nloc + m2) * R] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ near field + output
+// One wave per (row group, 64 right-hand sides).  Columns are taken 64 at a time: the
+// wave stages the group's values of those columns in its LDS slice (row-major, coalesced)
+// and keeps the column indices in a register; then for every column it gathers x[h][r]
+// (coalesced across the wave) and updates all rows of the group.  Finally each row adds
+// the backward transforms of the leaves that meet its B-spline and is written to ys.
+template <class T, int RMAX>
+__device__ inline void kb_near_rows(const OpDev& op, const BatchDev& bd, T (*vs)[kBatchChunk], int64_t G, int lane,
+                                    int r, bool on) {
+    const int R = bd.R;
+    const int64_t rb = op.grp_rowptr[G];
+    const int Rg = (int)(op.grp_rowptr[G + 1] - rb);
+    const int32_t* rows = op.grp_rows + rb;
+    const int64_t first = rows[0];
+    const int64_t cb = op.rowptr[first];
+    const int C = (int)(op.rowptr[first + 1] - cb);
+    const int32_t* __restrict__ col = op.col + cb;
+    const T* __restrict__ val = (const T*)op.val + op.grp_voff[G];
+    const T* __restrict__ xs = (const T*)bd.xs;
+    T acc[RMAX];
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) acc[q] = zero<T>();
+    for (int c0 = 0; c0 < C; c0 += kBatchChunk) {
+        const int nc = min(kBatchChunk, C - c0);
+        const int ci = lane < nc ? col[c0 + lane] : 0;
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q)
+            if (q < Rg) vs[q][lane] = lane < nc ? val[(int64_t)q * C + c0 + lane] : zero<T>();
+        wave_sync();
+#pragma unroll 2
+        for (int u = 0; u < nc; ++u) {
+            const int h = __builtin_amdgcn_readlane(ci, u);
+            const T xv = on ? xs[(int64_t)h * R + r] : zero<T>();
+#pragma unroll
+            for (int q = 0; q < RMAX; ++q)
+                if (q < Rg) acc[q] += vs[q][u] * xv;
+        }
+        wave_sync();
+    }
+    // row sums go through the wave's LDS slice so that the loop below may index them
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q)
+        if (q < Rg) vs[q][lane] = acc[q];
+    wave_sync();
+    if (!on) return;
+    const SpaceDesc& S = op.S;
+    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * S.r, nb = S.nb;
+    const T* __restrict__ yl = (const T*)bd.yl;
+    for (int q = 0; q < Rg; ++q) {
+        const int64_t g = rows[q];
+        const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
+        int lo1, hi1, lo2, hi2;
+        leaf_range(j1, stride, nloc, n1, lo1, hi1);
+        leaf_range(j2, stride, nloc, n1, lo2, hi2);
+        T s = vs[q][lane];
+        for (int li = lo1; li <= hi1; ++li)
+            for (int lj = lo2; lj <= hi2; ++lj) {
+                const int64_t l = ((int64_t)f * n1 + li) * n1 + lj;
+                const int m1 = j1 - li * stride, m2 = j2 - lj * stride;
+                s += yl[((l * nloc + m1) * nloc + m2) * R + r];
+            }
+        ((T*)bd.ys)[g * R + r] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void kb_near(OpDev op, BatchDev bd) {
+    __shared__ T vs[4][kGroupRowsB][kBatchChunk];
+    const int nch = nchunks(bd.R);
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + w;
+    if (item >= op.ngroups * nch) return;
+    const int64_t G = item / nch;
+    const int ch = (int)(item % nch);
+    const int r = ch * kBatchChunk + lane;
+    const bool on = r < bd.R;
+    const int Rg = (int)(op.grp_rowptr[G + 1] - op.grp_rowptr[G]);
+    if (Rg <= 4)
+        kb_near_rows<T, 4>(op, bd, vs[w], G, lane, r, on);
+    else
+        kb_near_rows<T, kGroupRowsB>(op, bd, vs[w], G, lane, r, on);
+}
+
+// ------------------------------------------------------------------ launchers
+template <class T, int Q>
+hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* x, int64_t ldx, void* y, int64_t ldy,
+                    int prec, hipStream_t st) {
+    const int R = bd.R, nch = (R + kBatchChunk - 1) / kBatchChunk;
+    const int64_t N = op.S.ndof;
+    const int npatch = op.S.geom.npatch;
+    if (stage == 0) {
+        if (x)
+            hipLaunchKernelGGL(kb_to_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R, (const T*)x, ldx,
+                               (T*)bd.xs);
+        hipLaunchKernelGGL((kb_leaf_moments<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
+        for (int lev = op.leaf - 1; lev >= 0; --lev) {
+            const int64_t nl = (int64_t)npatch << (2 * lev);
+            hipLaunchKernelGGL((kb_upward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
+        }
+        if (prec == 2) hipLaunchKernelGGL((kb_bf_moments<T, Q>), dim3(nblk(op.ncl * nch, 4)), dim3(256), 0, st, op, bd);
+    } else if (stage == 1) {
+        const unsigned nb = (unsigned)(op.ncl * nch);
+        if (prec == 0) {
+            hipLaunchKernelGGL((kb_coupling<T, T, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const T*)op.K);
+        } else if (prec == 1) {
+            using F = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
+            hipLaunchKernelGGL((kb_coupling<T, F, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const F*)op.Klow);
+        } else {
+            if constexpr (Q * Q <= 32)
+                hipLaunchKernelGGL((kb_coupling_mfma<T, Q>), dim3(nb), dim3(256), 0, st, op, bd);
+            else
+                return hipErrorInvalidValue;
+        }
+    } else if (stage == 2) {
+        for (int lev = 1; lev <= op.leaf; ++lev) {
+            const int64_t nl = (int64_t)npatch << (2 * lev);
+            hipLaunchKernelGGL((kb_downward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
+        }
+        hipLaunchKernelGGL((kb_leaf_back<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
+    } else {
+        hipLaunchKernelGGL(kb_near<T>, dim3(nblk(op.ngroups * nch, 4)), dim3(256), 0, st, op, bd);
+        if (y)
+            hipLaunchKernelGGL(kb_from_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R,
+                               (const T*)bd.ys, (T*)y, ldy);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t stage_t(const OpDev& op, const BatchDev& bd, int stage, const void* x, int64_t ldx, void* y, int64_t ldy,
+                   int prec, hipStream_t st) {
+    switch (op.q) {
+        case 1: return stage_tq<T, 1>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        case 2: return stage_tq<T, 2>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        case 3: return stage_tq<T, 3>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        case 4: return stage_tq<T, 4>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        case 5: return stage_tq<T, 5>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        case 6: return stage_tq<T, 6>(op, bd, stage, x, ldx, y, ldy, prec, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, int Q>
+hipError_t bf_blocks_tq(const OpDev& op, const BatchDev& bd, int64_t npairs, hipStream_t st) {
+    if constexpr (Q * Q <= 32) {
+        const int RT = bf_row_tiles(sizeof(T) == 16);
+        hipLaunchKernelGGL((kb_bf_blocks<T, Q>), dim3(nblk(npairs * RT, 4)), dim3(256), 0, st, op, bd, npairs);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_apply_batched_stage(const OpDev& op, const BatchDev& bd, int stage, const void* x, int64_t ldx,
+                                      void* y, int64_t ldy, int prec, hipStream_t st) {
+    if (bd.R < 1 || bd.R > bd.rmax) return hipErrorInvalidValue;
+    return op.cplx ? stage_t<cdbl>(op, bd, stage, x, ldx, y, ldy, prec, st)
+                   : stage_t<double>(op, bd, stage, x, ldx, y, ldy, prec, st);
+}
+
+hipError_t launch_apply_batched(const OpDev& op, const BatchDev& bd, const void* x, int64_t ldx, void* y, int64_t ldy,
+                                int prec, hipStream_t st) {
+    for (int s = 0; s < kBatchStages; ++s) {
+        const hipError_t e = launch_apply_batched_stage(op, bd, s, x, ldx, y, ldy, prec, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_build_bf_blocks(const OpDev& op, const BatchDev& bd, int64_t npairs, hipStream_t st) {
+    if (npairs == 0) return hipSuccess;
+    if (op.cplx) {
+        switch (op.q) {
+            case 1: return bf_blocks_tq<cdbl, 1>(op, bd, npairs, st);
+            case 2: return bf_blocks_tq<cdbl, 2>(op, bd, npairs, st);
+            case 3: return bf_blocks_tq<cdbl, 3>(op, bd, npairs, st);
+            case 4: return bf_blocks_tq<cdbl, 4>(op, bd, npairs, st);
+            case 5: return bf_blocks_tq<cdbl, 5>(op, bd, npairs, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (op.q) {
+        case 1: return bf_blocks_tq<double, 1>(op, bd, npairs, st);
+        case 2: return bf_blocks_tq<double, 2>(op, bd, npairs, st);
+        case 3: return bf_blocks_tq<double, 3>(op, bd, npairs, st);
+        case 4: return bf_blocks_tq<double, 4>(op, bd, npairs, st);
+        case 5: return bf_blocks_tq<double, 5>(op, bd, npairs, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bem

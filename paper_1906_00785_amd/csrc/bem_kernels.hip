@@ -1,6 +1,7 @@
 // gfx950 kernels of the isogeometric Galerkin BEM hot path: near-field quadrature, coupling
 // blocks, the H^2 matvec, load vector, potential and the GMRES vector operations.
 #include "bem_kernels.h"
+#include "bem_device.h"
 
 #include <type_traits>
 
@@ -8,16 +9,7 @@ namespace bem {
 
 namespace {
 
-constexpr int kWave = 64;
 constexpr int kGroupRowsDev = 16;  // rows per near-field row group at most (host: kGroupRows)
-
-__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -28,6 +20,8 @@ __device__ inline cdbl wave_sum(cdbl v) { return {wave_sum(v.re), wave_sum(v.im)
 
 __device__ inline double shfl_xor_t(double v, int off) { return __shfl_xor(v, off, kWave); }
 __device__ inline cdbl shfl_xor_t(cdbl v, int off) { return {__shfl_xor(v.re, off, kWave), __shfl_xor(v.im, off, kWave)}; }
+__device__ inline float shfl_xor_t(float v, int off) { return __shfl_xor(v, off, kWave); }
+__device__ inline cflt shfl_xor_t(cflt v, int off) { return {__shfl_xor(v.re, off, kWave), __shfl_xor(v.im, off, kWave)}; }
 __device__ inline double shfl_t(double v, int src) { return __shfl(v, src, kWave); }
 __device__ inline cdbl shfl_t(cdbl v, int src) { return {__shfl(v.re, src, kWave), __shfl(v.im, src, kWave)}; }
 
@@ -300,12 +294,6 @@ __global__ __launch_bounds__(256) void k_near_singular(OpDev op, AsmDev as) {
 // ------------------------------------------------------------------ near field: CSR values
 // One wave per row g; each lane sums, for its column h, the leaf-pair blocks of every near
 // leaf pair (tau, sigma) with g in dofs(tau) and h in dofs(sigma), in a fixed order.
-__device__ inline void leaf_range(int j, int stride, int nloc, int nleaf1, int& lo, int& hi) {
-    hi = j / stride;
-    if (hi > nleaf1 - 1) hi = nleaf1 - 1;
-    const int l = j - nloc + 1;
-    lo = l <= 0 ? 0 : (l + stride - 1) / stride;
-}
 
 template <class T>
 __global__ __launch_bounds__(256) void k_near_gather(OpDev op, AsmDev as) {
@@ -672,35 +660,7 @@ __global__ __launch_bounds__(256) void k_coupling(OpDev op) {
 
 
 // ------------------------------------------------------------------ low-precision far field
-struct cflt {
-    float re, im;
-};
-__device__ inline cflt operator+(cflt a, cflt b) { return {a.re + b.re, a.im + b.im}; }
-__device__ inline cflt operator*(cflt a, cflt b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ inline cflt& operator+=(cflt& a, cflt b) {
-    a.re += b.re;
-    a.im += b.im;
-    return a;
-}
-template <class F>
-__device__ inline F zero_f();
-template <>
-__device__ inline float zero_f<float>() { return 0.0f; }
-template <>
-__device__ inline cflt zero_f<cflt>() { return {0.0f, 0.0f}; }
-__device__ inline float to_f(double v) { return (float)v; }
-__device__ inline cflt to_f(cdbl v) { return {(float)v.re, (float)v.im}; }
-__device__ inline double to_d(float v) { return (double)v; }
-__device__ inline cdbl to_d(cflt v) { return {(double)v.re, (double)v.im}; }
-__device__ inline float shfl_xor_t(float v, int off) { return __shfl_xor(v, off, kWave); }
-__device__ inline cflt shfl_xor_t(cflt v, int off) { return {__shfl_xor(v.re, off, kWave), __shfl_xor(v.im, off, kWave)}; }
 
-// BF16 by round-to-nearest-even of the FP32 value (finite inputs)
-__device__ inline uint16_t f2bf(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ inline float bf2f(uint32_t b) { return __uint_as_float(b << 16); }
 
 // storage types: FP32 (4 bytes per real scalar) or BF16 (2 bytes)
 struct StFp32 {};

@@ -1,0 +1,145 @@
+"""GPU: the many-RHS H^2 matvec (slab kernels, bem_apply with batch_rhs > 1) against the oracle.
+
+Bar: in FP64 every column within 1e-11 (max-norm, relative to the largest oracle entry) of
+the oracle's product, independent of how the columns are split into passes and bitwise
+repeatable.  The FP32 coupling (vector units) and the BF16 coupling (matrix cores: BF16
+blocks and BF16 moments, FP32 accumulation) are not parity quantities: their error against
+the FP64 product is stated and bounded.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+LOW_BOUND = {1: 1e-5, 2: 2e-2}
+
+CASES = {
+    # id: (geom, params, pde, kappa, L, d, q, eta, leaf)
+    "sphere_L2_d1_laplace_h2": (0, (), 0, 0.0, 2, 1, 5, 1.6, 2),
+    "sphere_L2_d1_helmholtz_h2": (0, (), 1, 2.5, 2, 1, 5, 1.6, 2),
+    "torus_L2_d1_laplace_h2": (2, (1.0, 0.4), 0, 0.0, 2, 1, 4, 1.6, 1),
+    "ellipsoid_L2_d2_helmholtz_cplx_h2": (1, (0.7, 1.2, 1.6), 1, 1.5 + 0.3j, 2, 2, 4, 1.6, 1),
+    "flat_L2_d0_laplace": (3, (2.0,), 0, 0.0, 2, 0, 3, 1.6, 1),
+    "sphere_L2_d1_laplace_dense": (0, (), 0, 0.0, 2, 1, 3, 0.0, 0),
+    "sphere_L3_d2_laplace_leaf0_q6": (0, (), 0, 0.0, 3, 2, 6, 1.6, 0),
+    "sphere_L1_d2_helmholtz_leaf_eq_L": (0, (), 1, 3.0, 1, 2, 3, 1.6, 1),
+}
+BATCH = 64
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_1906_00785_amd as B
+
+    return B
+
+
+_cache = {}
+
+
+def case(B, orc, cid, low=0):
+    key = (cid, low)
+    if key not in _cache:
+        geom, prm, pde, kappa, L, d, q, eta, leaf = CASES[cid]
+        print(f"[batch case {cid} far_low={low}] assemble", flush=True)
+        g = B.Geometry(geom, prm)
+        s = B.Space(g, pde, kappa, degree=d, level=L)
+        A = B.Operator(s, q=q, eta=eta, leaf_level=leaf, far_low=low, batch_rhs=BATCH)
+        if cid not in _cache:
+            So = orc.Space(geom, list(prm), pde, kappa, degree=d, level=L)
+            _cache[cid] = (So, orc.H2(So, q=q, eta=eta, leaf=leaf))
+        _cache[key] = (g, s, A)
+    return _cache[key] + _cache[cid]
+
+
+@pytest.mark.parametrize("cid", list(CASES))
+def test_batched_apply_matches_oracle(B, orc, cid):
+    g, s, A, So, Ho = case(B, orc, cid)
+    # 70 columns: one full pass of 64 and a ragged pass of 6 (a partly filled wave)
+    X = W.random_vector(W.rng(0, 50), s.ndof, is_complex=So.complex, ncols=70).T.copy()
+    Xd = torch.from_numpy(X).cuda()
+    Y = A.apply(Xd).cpu().numpy()
+    Yo = Ho.apply(X.T).T
+    assert relerr(Y, Yo) <= TOL
+    # bitwise repeatable, and a single column (one-column kernels) agrees to rounding
+    assert np.array_equal(A.apply(Xd).cpu().numpy(), Y)
+    y3 = A.apply(Xd[3]).cpu().numpy()
+    assert relerr(Y[3], y3) <= 1e-13
+    # grouping of columns into passes does not change the result beyond rounding
+    Y5 = A.apply(Xd[:5]).cpu().numpy()
+    assert relerr(Y5, Y[:5]) <= 1e-13
+
+
+@pytest.mark.parametrize("low", [1, 2])
+@pytest.mark.parametrize("cid", ["sphere_L2_d1_laplace_h2", "sphere_L2_d1_helmholtz_h2",
+                                 "ellipsoid_L2_d2_helmholtz_cplx_h2", "torus_L2_d1_laplace_h2"])
+def test_batched_low_precision_error_is_bounded(B, orc, cid, low):
+    g, s, A, So, Ho = case(B, orc, cid, low)
+    X = W.random_vector(W.rng(0, 51), s.ndof, is_complex=So.complex, ncols=70).T.copy()
+    Xd = torch.from_numpy(X).cuda()
+    Y64 = A.apply(Xd).cpu().numpy()
+    Ylo = A.apply(Xd, prec=low).cpu().numpy()
+    err = relerr(Ylo, Y64)
+    print(f"batched low-precision matvec error ({cid}, {'fp32' if low == 1 else 'bf16'}): {err:.2e}")
+    assert 0.0 < err <= LOW_BOUND[low]
+    assert relerr(Y64, Ho.apply(X.T).T) <= TOL
+
+
+def test_batched_bad_arguments(B, orc):
+    g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_h2")
+    X = torch.zeros((3, s.ndof), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BemError) as e:
+        A.apply(X, prec=1)  # no low-precision copy
+    assert e.value.code == B._bem.BEM_EINVAL
+    with pytest.raises(B.BemError) as e:
+        B.Operator(s, q=7, eta=1.6, leaf_level=2, batch_rhs=8, assemble=False)
+    assert e.value.code == B._bem.BEM_EUNSUPPORTED
+
+
+# ------------------------------------------------------------------ the many-RHS workload
+@pytest.fixture(scope="module")
+def c2(B, orc):
+    c = W.CONFIGS[2]
+    kappa, dirs = W.c2_inputs()
+    print(f"[c2] helmholtz sphere6 L={c['level']} d={c['degree']} kappa={kappa:.4f} leaf={c['leaf']}: assemble",
+          flush=True)
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, kappa, degree=c["degree"], level=c["level"])
+    A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_low=2, batch_rhs=c["nrhs"])
+    So = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, kappa, degree=c["degree"], level=c["level"])
+    Ho = orc.H2(So, q=c["q"], eta=c["eta"], leaf=c["leaf"], assemble_near=False)
+    return c, kappa, dirs, g, s, A, So, Ho
+
+
+def test_c2_batched_apply_full_size(B, orc, c2):
+    c, kappa, dirs, g, s, A, So, Ho = c2
+    N = s.ndof
+    b = s.rhs(B.BEM_DATA_PLANE_WAVE, dirs)  # (128, N): the plane-wave load vectors
+    assert b.shape == (c["nrhs"], N)
+    Y = A.apply(b).cpu().numpy()
+    # sampled rows of sampled columns against the oracle (near rows assembled on demand)
+    rows = W.sample_rows(2, N, 6)
+    Ho.assemble_near_rows(rows)
+    bh = b.cpu().numpy()
+    for col in (0, 63, 64, c["nrhs"] - 1):
+        yo = Ho.apply_rows(bh[col], rows)
+        assert np.max(np.abs(Y[col, rows] - yo)) <= TOL * np.max(np.abs(yo)), col
+        # the far field alone at every row of that column
+    yf = Ho.apply_rows(bh[5], np.arange(N, dtype=np.int64), far=True, near=False)
+    rowptr, cols, val = A.export_near()
+    yn = np.add.reduceat(val * bh[5][cols], rowptr[:-1])
+    assert np.max(np.abs(Y[5] - yn - yf)) <= TOL * np.max(np.abs(Y[5]))
+    # BF16 matrix-core coupling at full size: stated bound against the FP64 product
+    Yb = A.apply(b, prec=2).cpu().numpy()
+    err = relerr(Yb, Y)
+    print(f"c2 full size: bf16 matvec error {err:.2e}")
+    assert err <= LOW_BOUND[2]
