@@ -80,11 +80,14 @@ struct bem_operator_s {
     size_t ev_used = 0;
     // GMRES: pinned status words and per-step events
     double* pinned = nullptr;
+    double* bpin = nullptr;  // batched GMRES: per-RHS estimates, norms and step counts
+    size_t bpin_doubles = 0;
     std::vector<hipEvent_t> sev;
     ~bem_operator_s() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : sev) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
+        if (bpin) (void)hipHostFree(bpin);
     }
 };
 
@@ -365,6 +368,240 @@ static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_pa
     out->outer = outer;
     out->relres = bnorm > 0.0 ? rnorm / bnorm : 0.0;
     out->converged = out->relres <= p->tol ? 1 : 0;
+    return BEM_OK;
+}
+
+// ------------------------------------------------------------------ GMRES, many RHS
+struct BSolveWs {
+    char* V;        // (m+1) slabs [N][R]
+    char* w;        // slab
+    char* r;        // slab (refinement: FP64 residual)
+    char* d;        // slab (refinement: correction)
+    char* bs;       // slab of the right-hand sides
+    char* xs;       // slab of the solutions
+    char* part;     // [slices][m+1][R] partial inner products
+    char* h1;       // [m+1][R]
+    char* h2;       // [m+1][R]
+    double* npart;  // [slices][R]
+    int* flag;      // [R]
+    BGmresState st;
+};
+
+static size_t bsolve_layout(int64_t N, int m, int R, size_t sc, void* base, BSolveWs* ws) {
+    Bump b(base);
+    BSolveWs w{};
+    const size_t slab = (size_t)N * R * sc;
+    w.V = b.take<char>((size_t)(m + 1) * slab);
+    w.w = b.take<char>(slab);
+    w.r = b.take<char>(slab);
+    w.d = b.take<char>(slab);
+    w.bs = b.take<char>(slab);
+    w.xs = b.take<char>(slab);
+    w.part = b.take<char>((size_t)kBSolveSlices * (m + 1) * R * sc);
+    w.h1 = b.take<char>((size_t)(m + 1) * R * sc);
+    w.h2 = b.take<char>((size_t)(m + 1) * R * sc);
+    w.npart = b.take<double>((size_t)kBSolveSlices * R);
+    w.flag = b.take<int>(R);
+    w.st.m = m;
+    w.st.H = b.take<char>((size_t)R * (m + 1) * m * sc);
+    w.st.cs = b.take<double>((size_t)R * m);
+    w.st.sn = b.take<char>((size_t)R * m * sc);
+    w.st.g = b.take<char>((size_t)R * (m + 1) * sc);
+    w.st.y = b.take<char>((size_t)m * R * sc);
+    w.st.est = b.take<double>((size_t)m * R);
+    w.st.beta = b.take<double>(R);
+    w.st.sc = b.take<double>(R);
+    w.st.kr = b.take<int>(R);
+    if (ws) *ws = w;
+    return b.off + 256;
+}
+
+// y = A x on slabs of R columns (R <= batch_rhs)
+static int bapply(bem_operator A, int prec, const void* xs, void* ys, int R, hipStream_t stream) {
+    BatchDev bd = A->bdev;
+    bd.R = R;
+    bd.xs = (void*)xs;
+    bd.ys = ys;
+    HIP_CHECK(launch_apply_batched(A->dev, bd, nullptr, 0, nullptr, 0, prec, stream));
+    return BEM_OK;
+}
+
+static int ensure_bpin(bem_operator A, int R) {
+    const size_t need = (size_t)(kMaxRestart + 4) * R;
+    if (A->bpin && A->bpin_doubles >= need) return BEM_OK;
+    if (A->bpin) HIP_CHECK(hipHostFree(A->bpin));
+    A->bpin = nullptr;
+    HIP_CHECK(hipHostMalloc((void**)&A->bpin, sizeof(double) * need));
+    A->bpin_doubles = need;
+    while ((int)A->sev.size() < kMaxRestart) {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        A->sev.push_back(e);
+    }
+    return BEM_OK;
+}
+
+// R right-hand sides in lockstep (slabs b, x).  Each right-hand side stops on its own:
+// a cycle's Arnoldi steps go on while some active one has not reached tol on its rotated
+// residual estimate (checked one step late, as in the one-column solver), and each one
+// updates its iterate with the steps it needed.  Convergence is decided on the true
+// residual at the start of the next cycle.
+static int gmres_batched(bem_operator A, int prec, const void* b, void* x, int R, int m, int maxit, double tol,
+                         bem_solve_stats* out, BSolveWs& W, hipStream_t stream) {
+    const int64_t N = A->info.ndof;
+    const int cp = A->cplx ? 1 : 0;
+    const size_t sc = A->scal;
+    auto Vj = [&](int j) { return W.V + (size_t)j * N * R * sc; };
+    if (ensure_bpin(A, R) != BEM_OK) return BEM_EDEVICE;
+    double* est_h = A->bpin;                       // [kMaxRestart][R]
+    double* beta_h = est_h + (size_t)kMaxRestart * R;  // [R]
+    int* kr_h = (int*)(beta_h + R);               // [R]
+    auto read_beta = [&]() -> int {
+        HIP_CHECK(hipMemcpyAsync(beta_h, W.st.beta, sizeof(double) * R, hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        return BEM_OK;
+    };
+    HIP_CHECK(bsolve_zero(cp, N * R, x, stream));
+    HIP_CHECK(bsolve_residual(cp, N, R, b, W.w, W.npart, 1, stream));
+    HIP_CHECK(bsolve_start(cp, N, R, W.npart, W.w, Vj(0), W.st, stream));
+    if (read_beta() != BEM_OK) return BEM_EDEVICE;
+    std::vector<double> bnorm(beta_h, beta_h + R), rel(R, 0.0);
+    std::vector<int> total(R, 0);
+    std::vector<char> conv(R, 0), act(R, 0);
+    for (int cycle = 0;; ++cycle) {
+        if (cycle > 0) {
+            if (bapply(A, prec, x, W.w, R, stream) != BEM_OK) return BEM_EDEVICE;
+            HIP_CHECK(bsolve_residual(cp, N, R, b, W.w, W.npart, 0, stream));
+            HIP_CHECK(bsolve_start(cp, N, R, W.npart, W.w, Vj(0), W.st, stream));
+            if (read_beta() != BEM_OK) return BEM_EDEVICE;
+        }
+        bool any = false;
+        int room = 0;
+        for (int r = 0; r < R; ++r) {
+            rel[r] = bnorm[r] > 0.0 ? beta_h[r] / bnorm[r] : 0.0;
+            conv[r] = rel[r] <= tol;
+            act[r] = !conv[r] && total[r] < maxit && std::isfinite(rel[r]);
+            if (act[r]) {
+                any = true;
+                room = std::max(room, maxit - total[r]);
+            }
+        }
+        if (!any) break;
+        int k = 0;
+        for (int j = 0; j < m && j < room; ++j) {
+            if (bapply(A, prec, Vj(j), W.w, R, stream) != BEM_OK) return BEM_EDEVICE;
+            HIP_CHECK(bsolve_dots(cp, N, R, j + 1, W.V, W.w, W.part, W.h1, stream));
+            HIP_CHECK(bsolve_update(cp, N, R, j + 1, W.V, W.h1, W.w, W.npart, 0, stream));
+            HIP_CHECK(bsolve_dots(cp, N, R, j + 1, W.V, W.w, W.part, W.h2, stream));
+            HIP_CHECK(bsolve_update(cp, N, R, j + 1, W.V, W.h2, W.w, W.npart, 1, stream));
+            HIP_CHECK(bsolve_givens_scale(cp, N, R, j, W.npart, W.h1, W.h2, W.w, Vj(j + 1), W.st, stream));
+            HIP_CHECK(hipMemcpyAsync(est_h + (size_t)j * R, W.st.est + (size_t)j * R, sizeof(double) * R,
+                                     hipMemcpyDeviceToHost, stream));
+            HIP_CHECK(hipEventRecord(A->sev[j], stream));
+            k = j + 1;
+            if (j >= 1) {
+                HIP_CHECK(hipEventSynchronize(A->sev[j - 1]));
+                bool all = true;
+                for (int r = 0; r < R && all; ++r) {
+                    const double e = est_h[(size_t)(j - 1) * R + r];
+                    if (act[r] && e > tol * bnorm[r] && std::isfinite(e)) all = false;
+                }
+                if (all) {
+                    k = j;  // every active one converged after step j-1
+                    break;
+                }
+            }
+        }
+        if (k > 0) HIP_CHECK(hipEventSynchronize(A->sev[k - 1]));
+        for (int r = 0; r < R; ++r) {
+            int kr = 0;
+            if (act[r]) {
+                kr = std::min(k, maxit - total[r]);
+                for (int s2 = 0; s2 < kr; ++s2)
+                    if (!(est_h[(size_t)s2 * R + r] > tol * bnorm[r])) {
+                        kr = s2 + 1;
+                        break;
+                    }
+            }
+            kr_h[r] = kr;
+            total[r] += kr;
+        }
+        HIP_CHECK(hipMemcpyAsync(W.st.kr, kr_h, sizeof(int) * R, hipMemcpyHostToDevice, stream));
+        HIP_CHECK(bsolve_backsolve_update(cp, N, R, k, W.V, x, W.st, stream));
+    }
+    for (int r = 0; r < R; ++r) {
+        out[r].iterations = total[r];
+        out[r].relres = rel[r];
+        out[r].converged = conv[r] ? 1 : 0;
+        out[r].outer = 0;
+    }
+    return BEM_OK;
+}
+
+// FP64 iterative refinement around the lockstep GMRES on the low-precision operator;
+// right-hand sides that have met tol are masked out of further inner solves.
+static int refine_batched(bem_operator A, const void* b, void* x, int R, const bem_solve_params* p,
+                          bem_solve_stats* out, BSolveWs& W, hipStream_t stream) {
+    const int64_t N = A->info.ndof;
+    const int cp = A->cplx ? 1 : 0;
+    const int max_outer = p->max_outer > 0 ? p->max_outer : 20;
+    const double inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
+    if (ensure_bpin(A, R) != BEM_OK) return BEM_EDEVICE;
+    double* beta_h = A->bpin + (size_t)kMaxRestart * R;
+    int* flag_h = (int*)(beta_h + R);
+    auto norms = [&](std::vector<double>& v) -> int {
+        // norms of the slab in W.r (partials in W.npart) via the start kernel's reduction
+        HIP_CHECK(bsolve_start(cp, N, R, W.npart, W.r, W.V, W.st, stream));
+        HIP_CHECK(hipMemcpyAsync(beta_h, W.st.beta, sizeof(double) * R, hipMemcpyDeviceToHost, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        v.assign(beta_h, beta_h + R);
+        return BEM_OK;
+    };
+    HIP_CHECK(bsolve_zero(cp, N * R, x, stream));
+    HIP_CHECK(bsolve_residual(cp, N, R, b, W.r, W.npart, 1, stream));
+    std::vector<double> bnorm, rnorm;
+    if (norms(bnorm) != BEM_OK) return BEM_EDEVICE;
+    rnorm = bnorm;
+    std::vector<int> total(R, 0), outer(R, 0), done(R, 0);
+    std::vector<bem_solve_stats> in(R);
+    for (int it = 0; it < max_outer; ++it) {
+        bool any = false;
+        for (int r = 0; r < R; ++r) {
+            done[r] = bnorm[r] == 0.0 || rnorm[r] <= p->tol * bnorm[r] || total[r] >= p->maxit ||
+                      !std::isfinite(rnorm[r]);
+            flag_h[r] = done[r];
+            any = any || !done[r];
+        }
+        if (!any) break;
+        // (the pinned flags are read by the copy before the inner solve reuses that memory:
+        // the inner solve synchronises the stream before its first host write)
+        HIP_CHECK(hipMemcpyAsync(W.flag, flag_h, sizeof(int) * R, hipMemcpyHostToDevice, stream));
+        HIP_CHECK(bsolve_mask(cp, N, R, W.flag, W.r, stream));
+        // every inner solve stays within the budget of each right-hand side still iterating
+        int left = p->maxit;
+        for (int r = 0; r < R; ++r)
+            if (!done[r]) left = std::min(left, p->maxit - total[r]);
+        const int rc = gmres_batched(A, A->far_low, W.r, W.d, R, p->restart, left, inner_tol, in.data(), W, stream);
+        if (rc != BEM_OK) return rc;
+        int progress = 0;
+        for (int r = 0; r < R; ++r)
+            if (!done[r]) {
+                total[r] += in[r].iterations;
+                outer[r] += 1;
+                progress += in[r].iterations;
+            }
+        HIP_CHECK(bsolve_axpy(cp, N, R, W.d, x, stream));
+        if (bapply(A, 0, x, W.r, R, stream) != BEM_OK) return BEM_EDEVICE;
+        HIP_CHECK(bsolve_residual(cp, N, R, b, W.r, W.npart, 0, stream));
+        if (norms(rnorm) != BEM_OK) return BEM_EDEVICE;
+        if (progress == 0) break;
+    }
+    for (int r = 0; r < R; ++r) {
+        out[r].iterations = total[r];
+        out[r].outer = outer[r];
+        out[r].relres = bnorm[r] > 0.0 ? rnorm[r] / bnorm[r] : 0.0;
+        out[r].converged = out[r].relres <= p->tol ? 1 : 0;
+    }
     return BEM_OK;
 }
 
@@ -765,6 +1002,9 @@ int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* 
     if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart)
         return fail(BEM_EINVAL, "nrhs must be >= 1 and restart in [1, 64]");
     *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, nullptr);
+    if (nrhs > 1 && A->batch_rhs > 1)
+        *bytes = std::max(*bytes, bsolve_layout(A->info.ndof, p->restart, std::min(nrhs, A->batch_rhs), A->scal,
+                                                nullptr, nullptr));
     return BEM_OK;
 }
 
@@ -782,9 +1022,32 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
     if (p->refine && A->far_low == 0) return fail(BEM_EINVAL, "refinement needs far_low set at assembly");
     if (p->max_outer < 0 || p->inner_tol < 0.0) return fail(BEM_EINVAL, "max_outer and inner_tol must be >= 0");
     if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
+    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    if (nrhs > 1 && A->batch_rhs > 1) {
+        // many right-hand sides in lockstep, up to batch_rhs per pass
+        const int Rb = std::min(nrhs, A->batch_rhs);
+        if (ws_bytes < bsolve_layout(N, p->restart, Rb, A->scal, nullptr, nullptr))
+            return fail(BEM_ENOMEM, "solver workspace too small");
+        BSolveWs W;
+        bsolve_layout(N, p->restart, Rb, A->scal, base, &W);
+        bool all = true;
+        for (int r0 = 0; r0 < nrhs; r0 += Rb) {
+            const int R = std::min(Rb, nrhs - r0);
+            HIP_CHECK(launch_to_slab(A->cplx, N, R, (const char*)b_dev + (size_t)r0 * ldb * A->scal, ldb, W.bs,
+                                     stream));
+            const int rc = p->refine ? refine_batched(A, W.bs, W.xs, R, p, stats + r0, W, stream)
+                                     : gmres_batched(A, 0, W.bs, W.xs, R, p->restart, p->maxit, p->tol, stats + r0,
+                                                     W, stream);
+            if (rc != BEM_OK) return rc;
+            HIP_CHECK(launch_from_slab(A->cplx, N, R, W.xs, (char*)x_dev + (size_t)r0 * ldx * A->scal, ldx, stream));
+            for (int r = 0; r < R; ++r) all = all && stats[r0 + r].converged;
+        }
+        HIP_CHECK(hipStreamSynchronize(stream));
+        if (!all) return fail(BEM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
+        return BEM_OK;
+    }
     const size_t need = solve_layout(N, p->restart, A->scal, nullptr, nullptr);
     if (ws_bytes < need) return fail(BEM_ENOMEM, "solver workspace too small");
-    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
     SolveWs W;
     solve_layout(N, p->restart, A->scal, base, &W);
     bool all = true;

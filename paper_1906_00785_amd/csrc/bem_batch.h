@@ -54,6 +54,9 @@ hipError_t launch_apply_batched(const OpDev& op, const BatchDev& bd, const void*
 constexpr int kBatchStages = 4;
 hipError_t launch_apply_batched_stage(const OpDev& op, const BatchDev& bd, int stage, const void* x, int64_t ldx,
                                       void* y, int64_t ldy, int prec, hipStream_t st);
+// column-major (leading dimension ld) <-> slab [N][R]
+hipError_t launch_to_slab(int cplx, int64_t N, int R, const void* x, int64_t ldx, void* xs, hipStream_t st);
+hipError_t launch_from_slab(int cplx, int64_t N, int R, const void* ys, void* y, int64_t ldy, hipStream_t st);
 // BF16 fragments of every ordered far block (assembly, after the coupling blocks)
 hipError_t launch_build_bf_blocks(const OpDev& op, const BatchDev& bd, int64_t npairs, hipStream_t st);
 

@@ -641,6 +641,24 @@ hipError_t launch_apply_batched(const OpDev& op, const BatchDev& bd, const void*
     return hipSuccess;
 }
 
+hipError_t launch_to_slab(int cplx, int64_t N, int R, const void* x, int64_t ldx, void* xs, hipStream_t st) {
+    const dim3 g(nblk(N, 64), nblk(R, 32));
+    if (cplx)
+        hipLaunchKernelGGL(kb_to_slab<cdbl>, g, dim3(256), 0, st, N, R, (const cdbl*)x, ldx, (cdbl*)xs);
+    else
+        hipLaunchKernelGGL(kb_to_slab<double>, g, dim3(256), 0, st, N, R, (const double*)x, ldx, (double*)xs);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_slab(int cplx, int64_t N, int R, const void* ys, void* y, int64_t ldy, hipStream_t st) {
+    const dim3 g(nblk(N, 64), nblk(R, 32));
+    if (cplx)
+        hipLaunchKernelGGL(kb_from_slab<cdbl>, g, dim3(256), 0, st, N, R, (const cdbl*)ys, (cdbl*)y, ldy);
+    else
+        hipLaunchKernelGGL(kb_from_slab<double>, g, dim3(256), 0, st, N, R, (const double*)ys, (double*)y, ldy);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_bf_blocks(const OpDev& op, const BatchDev& bd, int64_t npairs, hipStream_t st) {
     if (npairs == 0) return hipSuccess;
     if (op.cplx) {

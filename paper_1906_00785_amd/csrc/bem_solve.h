@@ -37,4 +37,37 @@ hipError_t solve_axpy(int cplx, int64_t n, double a, const void* x, void* y, hip
 hipError_t solve_backsolve_update(int cplx, int64_t n, int k, const void* V, void* x, const GmresState& st,
                                   hipStream_t s);
 
+// ---- many right-hand sides in lockstep (bem_bsolve.hip): slab vectors v[g][r]
+constexpr int kBSolveSlices = 64;  // row slices of every slab kernel
+
+// Device-resident per-RHS state of one batched GMRES cycle.
+struct BGmresState {
+    int m;
+    void* H;      // [R][(m+1) x m]
+    double* cs;   // [R][m]
+    void* sn;     // [R][m]
+    void* g;      // [R][m+1]
+    void* y;      // [m][R]
+    double* est;  // [m][R] residual estimate after each step
+    double* beta; // [R] norm of the cycle's initial residual
+    double* sc;   // [R] scale of the next basis vector
+    int* kr;      // [R] steps of each right-hand side used for the update
+};
+
+hipError_t bsolve_dots(int cplx, int64_t n, int R, int k, const void* V, const void* w, void* part, void* h,
+                       hipStream_t s);
+hipError_t bsolve_update(int cplx, int64_t n, int R, int k, const void* V, const void* h, void* w, double* npart,
+                         int norm, hipStream_t s);
+hipError_t bsolve_residual(int cplx, int64_t n, int R, const void* b, void* w, double* npart, int copy_b,
+                           hipStream_t s);
+hipError_t bsolve_start(int cplx, int64_t n, int R, const double* npart, const void* w, void* v0,
+                        const BGmresState& st, hipStream_t s);
+hipError_t bsolve_givens_scale(int cplx, int64_t n, int R, int j, const double* npart, const void* h1, const void* h2,
+                               const void* w, void* vnext, const BGmresState& st, hipStream_t s);
+hipError_t bsolve_backsolve_update(int cplx, int64_t n, int R, int k, const void* V, void* x, const BGmresState& st,
+                                   hipStream_t s);
+hipError_t bsolve_axpy(int cplx, int64_t n, int R, const void* x, void* y, hipStream_t s);
+hipError_t bsolve_mask(int cplx, int64_t n, int R, const int* flag, void* y, hipStream_t s);
+hipError_t bsolve_zero(int cplx, int64_t n_scalars, void* y, hipStream_t s);
+
 }  // namespace bem
