@@ -31,6 +31,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the many-RHS Helmholtz workload")
     ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
     return ap.parse_args()
 
@@ -62,6 +63,74 @@ def cpu_baseline(cfg, x, nrows):
     return {"value": N / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"far field over all {N} rows timed in full ({t_far:.3f} s); near field timed over "
                       f"{rows.size} seeded rows and scaled to {N} rows ({t_near:.3f} s); serial FP64"}
+
+
+BF16_MFMA_PEAK = 2.5e15
+
+
+def bench_c2(B, W, torch, np, stream, args):
+    """Helmholtz single layer, sphere level 5, degree 2, 128 plane waves: the many-RHS
+    matvec (FP64, FP32 far field, BF16 far field on the matrix cores) and lockstep GMRES to
+    1e-8 in FP64 and with FP64 refinement around the FP32 far field."""
+    c = W.CONFIGS[2]
+    kappa, dirs = W.c2_inputs()
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, kappa, degree=c["degree"], level=c["level"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A16 = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_low=B.BEM_PREC_BF16, batch_rhs=c["nrhs"])
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    A32 = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_low=B.BEM_PREC_FP32, batch_rhs=c["nrhs"])
+    N, R, q2 = s.ndof, c["nrhs"], c["q"] ** 2
+    info = A16.info
+    b = s.rhs(B.BEM_DATA_PLANE_WAVE, dirs)
+    y = torch.empty_like(b)
+    steps = max(5, min(args.steps // 10, 30))
+    out = {"workload": c["name"], "ndof": N, "nrhs": R, "kappa": kappa, "leaf_level": c["leaf"], "nfar": info.nfar,
+           "near_nnz": info.near_nnz, "assembly_s": t_asm}
+    for name, op, prec in (("fp64", A16, 0), ("fp32", A32, B.BEM_PREC_FP32), ("bf16", A16, B.BEM_PREC_BF16)):
+        for _ in range(2):
+            op.apply(b, out=y, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            op.apply(b, out=y, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        op.profile(True)
+        for _ in range(steps):
+            op.apply(b, out=y, prec=prec)
+        st_ms, _ = op.profile_read()
+        op.profile(False)
+        # useful far-field flops: every ordered block applied to every column (complex: 8 per entry)
+        flops = info.nfar * q2 * q2 * 8.0 * R
+        ent = {"matvec_ms": ms, "dof_rhs_per_s": N * R / (ms * 1e-3),
+               "stages_ms": {"moments": st_ms[0], "coupling": st_ms[1], "down_back": st_ms[2], "near_out": st_ms[3]},
+               "coupling_useful_tflops": flops / (st_ms[1] * 1e-3) / 1e12}
+        if prec == B.BEM_PREC_BF16:
+            ent["coupling_mfma_frac_of_bf16_peak"] = flops / (st_ms[1] * 1e-3) / BF16_MFMA_PEAK
+        out[name] = ent
+        print(f"bench c2: {name} matvec {ms:.3f} ms ({N*R/(ms*1e-3):.3e} DOF*RHS/s); stages "
+              f"{st_ms[0]:.3f}/{st_ms[1]:.3f}/{st_ms[2]:.3f}/{st_ms[3]:.3f} ms; coupling "
+              f"{flops/(st_ms[1]*1e-3)/1e12:.1f} TFLOP/s useful", file=sys.stderr, flush=True)
+    if not args.no_gmres:
+        for name, op, refine in (("gmres_fp64", A16, False), ("gmres_fp32_refined", A32, True)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = op.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=refine)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            its = [v[0] for v in st]
+            res = float(((b - A16.apply(x)).norm(dim=1) / b.norm(dim=1)).max())
+            out[name] = {"time_to_tol_s": t, "iterations_min": min(its), "iterations_max": max(its),
+                         "converged": sum(bool(v[1]) for v in st), "max_true_relres": res,
+                         "outer_max": max(v[3] for v in st)}
+            print(f"bench c2: {name} {t:.3f}s its {min(its)}..{max(its)} converged {out[name]['converged']}/{R} "
+                  f"max relres {res:.2e}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -191,6 +260,8 @@ def main():
             print(f"bench: {name} refined GMRES {itm} its / {outm} outer {tm:.3f}s relres {rrm:.2e} "
                   f"diff to FP64 solution {dx:.1e}", file=sys.stderr, flush=True)
     extra["mixed"] = mixed
+    if not args.no_c2:
+        extra["many_rhs"] = bench_c2(B, W, torch, np, stream, args)
 
     cpu = None
     if not args.no_cpu_baseline:

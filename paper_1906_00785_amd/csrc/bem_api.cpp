@@ -69,6 +69,7 @@ struct bem_operator_s {
     std::vector<int32_t> touch_lp;
     std::vector<int64_t> fb_off;  // host copies of the per-pair block table (kept until destroy,
     std::vector<int32_t> fb_rs;   // the uploads above are asynchronous)
+    std::vector<int32_t> gsel;
     OpDev dev{};
     size_t scal = 8;  // bytes per scalar
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
@@ -132,6 +133,7 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
         const size_t np = p.far_t.size();
         BatchDev bd{};
         bd.rmax = A.batch_rhs;
+        bd.gsel = b.take<int32_t>(p.grp_rowptr.size() - 1);
         bd.far_rowptr = b.take<int64_t>(p.far_rowptr.size());
         bd.far_s = b.take<int32_t>(np);
         bd.fb_off = b.take<int64_t>(np);
@@ -888,6 +890,14 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
             A->fb_off[i] = p.koff[owner] + slot * p.q2;
             A->fb_rs[i] = owner == t ? p.krs[owner] : -p.krs[owner];
         }
+        const int64_t ng = (int64_t)p.grp_rowptr.size() - 1;
+        A->gsel.clear();
+        for (int64_t G = 0; G < ng; ++G)
+            if (p.grp_rowptr[G + 1] - p.grp_rowptr[G] <= 4) A->gsel.push_back((int32_t)G);
+        bd.nsmall = (int64_t)A->gsel.size();
+        for (int64_t G = 0; G < ng; ++G)
+            if (p.grp_rowptr[G + 1] - p.grp_rowptr[G] > 4) A->gsel.push_back((int32_t)G);
+        HIP_CHECK(up(bd.gsel, A->gsel.data(), ng * 4));
         HIP_CHECK(up(bd.far_rowptr, p.far_rowptr.data(), p.far_rowptr.size() * 8));
         HIP_CHECK(up(bd.far_s, p.far_s.data(), np * 4));
         HIP_CHECK(up(bd.fb_off, A->fb_off.data(), np * 8));

@@ -27,6 +27,8 @@ struct BatchDev {
     const int32_t* far_s;       // source of each ordered pair
     const int64_t* fb_off;      // first scalar of the block (row 0) in K
     const int32_t* fb_rs;       // row stride of the stored rows; negative: stored transposed
+    const int32_t* gsel;        // near-field row groups: those of <= 4 rows first, then the others
+    int64_t nsmall;             // number of groups of <= 4 rows
     void* xs;                   // [N][R] input slab
     void* ys;                   // [N][R] output slab
     void* mom;                  // [ncl][q2][R] moments

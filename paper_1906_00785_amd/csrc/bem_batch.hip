@@ -178,9 +178,9 @@ __global__ __launch_bounds__(256) void kb_upward(OpDev op, BatchDev bd, int lev)
 // Local expansion of target cluster t for 64 right-hand sides: l_t = sum over its
 // admissible sources s of K_ts m_s, in the arithmetic type F (FP64, or FP32 from the FP32
 // copy).  The four waves of a block take every fourth source; each wave stages the block
-// K_ts (transposed when it is stored in the source's rows) in its LDS slice and every
-// lane applies it to its own right-hand side.  The four partial sums are added in wave
-// order.
+// K_ts (transposed when it is stored in the source's rows) in its LDS slice, with the
+// next block already in flight in registers, and every lane applies it to its own
+// right-hand side.  The four partial sums are added in wave order.
 template <class T, class F, int Q>
 __global__ __launch_bounds__(256) void kb_coupling(OpDev op, BatchDev bd, const F* __restrict__ K) {
     constexpr int Q2 = Q * Q;
@@ -198,17 +198,33 @@ __global__ __launch_bounds__(256) void kb_coupling(OpDev op, BatchDev bd, const 
     F acc[Q2];
 #pragma unroll
     for (int a = 0; a < Q2; ++a) acc[a] = zero_f<F>();
-    for (int64_t p = beg + w; p < end; p += 4) {
-        const int s = bd.far_s[p];
+    // the next block's entries are loaded into registers while the current one is applied
+    constexpr int KR = (Q2 * Q2 + kWave - 1) / kWave;  // block entries per lane
+    F kreg[KR];
+    auto load_block = [&](int64_t p) {
         const int64_t off = bd.fb_off[p];
         const int rs = bd.fb_rs[p];
-        const bool tr = rs < 0;
-        const int ars = tr ? -rs : rs;
-        for (int idx = lane; idx < Q2 * Q2; idx += kWave) {
+        const int ars = rs < 0 ? -rs : rs;
+#pragma unroll
+        for (int u = 0; u < KR; ++u) {
+            const int idx = lane + u * kWave;
             const int i = idx / Q2, jj = idx - i * Q2;
-            ks[tr ? jj * Q2 + i : idx] = K[off + (int64_t)i * ars + jj];
+            kreg[u] = idx < Q2 * Q2 ? K[off + (int64_t)i * ars + jj] : zero_f<F>();
+        }
+    };
+    int64_t p = beg + w;
+    if (p < end) load_block(p);
+    for (; p < end; p += 4) {
+        const int s = bd.far_s[p];
+        const bool tr = bd.fb_rs[p] < 0;
+#pragma unroll
+        for (int u = 0; u < KR; ++u) {
+            const int idx = lane + u * kWave;
+            const int i = idx / Q2, jj = idx - i * Q2;
+            if (idx < Q2 * Q2) ks[tr ? jj * Q2 + i : idx] = kreg[u];
         }
         wave_sync();
+        if (p + 4 < end) load_block(p + 4);
         const T* ms = mom + (int64_t)s * Q2 * R + r;
 #pragma unroll 1
         for (int b0 = 0; b0 < Q2; b0 += Q) {
@@ -471,15 +487,22 @@ __global__ __launch_bounds__(256) void kb_leaf_back(OpDev op, BatchDev bd) {
 }
 
 // ------------------------------------------------------------------ near field + output
-// One wave per (row group, 64 right-hand sides).  Columns are taken 64 at a time: the
-// wave stages the group's values of those columns in its LDS slice (row-major, coalesced)
-// and keeps the column indices in a register; then for every column it gathers x[h][r]
-// (coalesced across the wave) and updates all rows of the group.  Finally each row adds
-// the backward transforms of the leaves that meet its B-spline and is written to ys.
-template <class T, int RMAX>
-__device__ inline void kb_near_rows(const OpDev& op, const BatchDev& bd, T (*vs)[kBatchChunk], int64_t G, int lane,
-                                    int r, bool on) {
-    const int R = bd.R;
+// One block per (row group, 64 right-hand sides); the four waves split the group's
+// columns into four ranges.  Column indices and values are the same for the whole wave
+// (uniform loads through the scalar cache); per U columns a wave issues the U gathers
+// x[h][r] (coalesced across the wave) before it updates the rows of the group.  The
+// four partial row sums are added in wave order in LDS; then each row adds the backward
+// transforms of the leaves that meet its B-spline and is written to ys.  Groups of at
+// most 4 rows and larger ones run as separate launches (list gsel).
+template <class T, int RMAX, int U>
+__global__ __launch_bounds__(256) void kb_near(OpDev op, BatchDev bd, int64_t g0, int64_t ng) {
+    __shared__ T red[RMAX][kBatchChunk];
+    const int nch = nchunks(bd.R);
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t G = bd.gsel[g0 + blockIdx.x / nch];
+    const int ch = (int)(blockIdx.x % nch);
+    const int R = bd.R, r = ch * kBatchChunk + lane;
+    const bool on = r < R;
     const int64_t rb = op.grp_rowptr[G];
     const int Rg = (int)(op.grp_rowptr[G + 1] - rb);
     const int32_t* rows = op.grp_rows + rb;
@@ -488,33 +511,33 @@ __device__ inline void kb_near_rows(const OpDev& op, const BatchDev& bd, T (*vs)
     const int C = (int)(op.rowptr[first + 1] - cb);
     const int32_t* __restrict__ col = op.col + cb;
     const T* __restrict__ val = (const T*)op.val + op.grp_voff[G];
-    const T* __restrict__ xs = (const T*)bd.xs;
+    const T* __restrict__ xs = (const T*)bd.xs + r;
+    const int c0 = (C * w) >> 2, c1 = (C * (w + 1)) >> 2;
     T acc[RMAX];
 #pragma unroll
     for (int q = 0; q < RMAX; ++q) acc[q] = zero<T>();
-    for (int c0 = 0; c0 < C; c0 += kBatchChunk) {
-        const int nc = min(kBatchChunk, C - c0);
-        const int ci = lane < nc ? col[c0 + lane] : 0;
+    for (int c = c0; c < c1; c += U) {
+        T xv[U];
 #pragma unroll
-        for (int q = 0; q < RMAX; ++q)
-            if (q < Rg) vs[q][lane] = lane < nc ? val[(int64_t)q * C + c0 + lane] : zero<T>();
-        wave_sync();
-#pragma unroll 2
-        for (int u = 0; u < nc; ++u) {
-            const int h = __builtin_amdgcn_readlane(ci, u);
-            const T xv = on ? xs[(int64_t)h * R + r] : zero<T>();
+        for (int uu = 0; uu < U; ++uu) {
+            const int h = col[c + uu < c1 ? c + uu : c0];
+            xv[uu] = on ? xs[(int64_t)h * R] : zero<T>();
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu)
+            if (c + uu < c1)
+#pragma unroll
+                for (int q = 0; q < RMAX; ++q)
+                    if (q < Rg) acc[q] += val[(int64_t)q * C + c + uu] * xv[uu];
+    }
+    for (int step = 0; step < 4; ++step) {
+        if (w == step)
 #pragma unroll
             for (int q = 0; q < RMAX; ++q)
-                if (q < Rg) acc[q] += vs[q][u] * xv;
-        }
-        wave_sync();
+                if (q < Rg) red[q][lane] = step == 0 ? acc[q] : red[q][lane] + acc[q];
+        __syncthreads();
     }
-    // row sums go through the wave's LDS slice so that the loop below may index them
-#pragma unroll
-    for (int q = 0; q < RMAX; ++q)
-        if (q < Rg) vs[q][lane] = acc[q];
-    wave_sync();
-    if (!on) return;
+    if (w != 0 || !on) return;
     const SpaceDesc& S = op.S;
     const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * S.r, nb = S.nb;
     const T* __restrict__ yl = (const T*)bd.yl;
@@ -524,33 +547,15 @@ __device__ inline void kb_near_rows(const OpDev& op, const BatchDev& bd, T (*vs)
         int lo1, hi1, lo2, hi2;
         leaf_range(j1, stride, nloc, n1, lo1, hi1);
         leaf_range(j2, stride, nloc, n1, lo2, hi2);
-        T s = vs[q][lane];
+        T sum = red[q][lane];
         for (int li = lo1; li <= hi1; ++li)
             for (int lj = lo2; lj <= hi2; ++lj) {
                 const int64_t l = ((int64_t)f * n1 + li) * n1 + lj;
                 const int m1 = j1 - li * stride, m2 = j2 - lj * stride;
-                s += yl[((l * nloc + m1) * nloc + m2) * R + r];
+                sum += yl[((l * nloc + m1) * nloc + m2) * R + r];
             }
-        ((T*)bd.ys)[g * R + r] = s;
+        ((T*)bd.ys)[g * R + r] = sum;
     }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void kb_near(OpDev op, BatchDev bd) {
-    __shared__ T vs[4][kGroupRowsB][kBatchChunk];
-    const int nch = nchunks(bd.R);
-    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t item = (int64_t)blockIdx.x * 4 + w;
-    if (item >= op.ngroups * nch) return;
-    const int64_t G = item / nch;
-    const int ch = (int)(item % nch);
-    const int r = ch * kBatchChunk + lane;
-    const bool on = r < bd.R;
-    const int Rg = (int)(op.grp_rowptr[G + 1] - op.grp_rowptr[G]);
-    if (Rg <= 4)
-        kb_near_rows<T, 4>(op, bd, vs[w], G, lane, r, on);
-    else
-        kb_near_rows<T, kGroupRowsB>(op, bd, vs[w], G, lane, r, on);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -590,7 +595,14 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
         }
         hipLaunchKernelGGL((kb_leaf_back<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
     } else {
-        hipLaunchKernelGGL(kb_near<T>, dim3(nblk(op.ngroups * nch, 4)), dim3(256), 0, st, op, bd);
+        constexpr int US = sizeof(T) == 16 ? 8 : 16, UB = sizeof(T) == 16 ? 4 : 8;
+        if (bd.nsmall > 0)
+            hipLaunchKernelGGL((kb_near<T, 4, US>), dim3((unsigned)(bd.nsmall * nch)), dim3(256), 0, st, op, bd,
+                               (int64_t)0, bd.nsmall);
+        const int64_t nbig = op.ngroups - bd.nsmall;
+        if (nbig > 0)
+            hipLaunchKernelGGL((kb_near<T, kGroupRowsB, UB>), dim3((unsigned)(nbig * nch)), dim3(256), 0, st, op, bd,
+                               bd.nsmall, nbig);
         if (y)
             hipLaunchKernelGGL(kb_from_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R,
                                (const T*)bd.ys, (T*)y, ldy);
