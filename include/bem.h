@@ -128,8 +128,13 @@ typedef struct bem_solve_params {
                          inner_tol, x += delta, until the FP64 residual meets tol */
     int max_outer;    /* refinement steps at most (0 = 20) */
     double inner_tol; /* relative tolerance of each inner solve (0 = 1e-4) */
-    int reserved[4];  /* must be zero */
+    int precond;      /* BEM_PRECOND_NONE, or BEM_PRECOND_BLOCK: right preconditioning with
+                         the operator's block preconditioner (bem_precond_build first) */
+    int reserved[3];  /* must be zero */
 } bem_solve_params;
+
+#define BEM_PRECOND_NONE 0
+#define BEM_PRECOND_BLOCK 1
 
 /* per-RHS solver statistics */
 typedef struct bem_solve_stats {
@@ -236,6 +241,57 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
  * stage_ms[0..3] (nstages >= 4), their number into *napplies, and clears the record. */
 int bem_profile_enable(bem_operator A, int on);
 int bem_profile_read(bem_operator A, double* stage_ms, int nstages, int* napplies);
+
+/* ---- block-Jacobi preconditioner with a learned low-rank correction -------------------
+ * Not part of the paper (its example program runs GMRES unpreconditioned); an addition to
+ * cut iterations on the first-kind single-layer systems.  Blocks are tiles of 8 x 8
+ * consecutive B-spline indices of a patch (64 DOFs, shorter at a patch's end; DOF
+ * (f, j1, j2) sits in slot (j1 % 8) * 8 + j2 % 8 of tile (f, j1 / 8, j2 / 8), tiles
+ * numbered (f * nt + j1 / 8) * nt + j2 / 8 with nt = ceil(nb / 8)).  D_b is the near-field
+ * part of A[b, b]; its inverse is formed by Gauss-Jordan elimination with partial pivoting
+ * (unused slots of short tiles carry identity).  GMRES uses M^{-1} as a right
+ * preconditioner (bem_solve_params.precond), so its residual is the true residual. */
+
+/* Number of tiles and bytes of the device workspace bem_precond_build needs. */
+int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes);
+
+/* Extracts and inverts every block (the plain inverse becomes the active one).  ws: device
+ * workspace of >= ws_bytes, owned by the caller, used until the operator is destroyed or
+ * the preconditioner is rebuilt.  EDEVICE if a block is singular. */
+int bem_precond_build(bem_operator A, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* z = M^{-1} r for nrhs columns (device, column-major, leading dimensions >= N). */
+int bem_precond_apply(bem_operator A, const void* r, int64_t ldr, void* z, int64_t ldz, int nrhs,
+                      hipStream_t stream);
+
+/* Host copy of the active (which = 0) or plain (which = 1) inverses: ntiles x 64 x 64
+ * scalars, row-major per tile, in slot order. */
+int bem_precond_export(bem_operator A, int which, double* inv_host, hipStream_t stream);
+
+/* Features of every tile for the correction network (device float, ntiles x 99): the
+ * Jacobian of the patch map at the 4 x 4 cell centres of the parameter box of the
+ * elements the tile's B-splines meet, with respect to box coordinates (d/ds x 3, d/dt x 3
+ * per point, points row by row), then Re kappa, Im kappa, level. */
+int bem_precond_features(bem_operator A, float* feats_dev, hipStream_t stream);
+
+/* Training targets of the correction network: for tiles [t0, t0 + nt), (C_b - D_b^{-1}) / s_b
+ * as device float ntiles x 64 x 64 (interleaved re, im for Helmholtz; written at tile
+ * index), where C_b = [(A_N)^{-1}]_{bb}, N(b) the tile extended by `ring` (0..8) B-spline
+ * indices per side inside the patch, A_N the near field on N(b) (reduced by Gauss-Jordan
+ * with partial pivoting), s_b = ||D_b^{-1}||_F / 64.  work: device scratch of >= the bytes
+ * from bem_precond_target_bytes(A, ring, nt). */
+int bem_precond_target_bytes(bem_operator A, int ring, int64_t nt, size_t* bytes);
+int bem_precond_targets(bem_operator A, int ring, int64_t t0, int64_t nt, void* work, size_t work_bytes,
+                        float* delta_dev, hipStream_t stream);
+
+/* Installs the learned correction M_b^{-1} = D_b^{-1} + s_b U_b V_b^T from the network output
+ * uv_dev (device float, ntiles x out; out = [U (64 x 8, row-major), V (64 x 8)] for Laplace,
+ * [Re U, Im U, Re V, Im V] for Helmholtz).  mode 2: keep it only for blocks where it lowers
+ * the residual of the near field on N(b) (ring as above) for each of 4 seeded probe
+ * vectors, else fall back to D_b^{-1}; mode 1: keep all; mode 0: plain block-Jacobi again.
+ * accepted_host (may be NULL): ntiles flags. */
+int bem_precond_correct(bem_operator A, const float* uv_dev, int mode, int ring, int* accepted_host,
+                        hipStream_t stream);
 
 /* Destroys the operator (its workspace stays with the caller). */
 void bem_operator_destroy(bem_operator A);

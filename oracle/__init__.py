@@ -78,6 +78,14 @@ def lib():
             "orc_h2_gmres": (I, [P, P, P, D, I, I, P]),
             "orc_h2_near_rows": (I, [P, P, I64]),
             "orc_dense_gmres": (I, [I64, I, P, P, P, D, I, I, P]),
+            "orc_bj_new": (I, [P, I, P]),
+            "orc_bj_free": (None, [P]),
+            "orc_bj_ntiles": (I64, [P]),
+            "orc_bj_tile": (I, [P, I64, P, P]),
+            "orc_bj_block": (I, [P, I64, P]),
+            "orc_bj_apply": (I, [P, P, P]),
+            "orc_bj_target": (I, [P, I64, I, P]),
+            "orc_h2_gmres_bj": (I, [P, P, P, P, D, I, I, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -296,3 +304,55 @@ def dense_gmres(A, b, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
     st = np.zeros(3)
     _check(lib().orc_dense_gmres(A.shape[0], int(cplx), _p(A), _p(b), _p(x), tol, restart, maxit, _p(st)))
     return x, int(st[0]), float(st[1]), bool(st[2])
+
+
+class BlockJacobi:
+    """Block-Jacobi preconditioner of an H2 oracle operator: tiles of `tile` x `tile`
+    B-spline indices per patch, blocks from the near field, LU with partial pivoting."""
+
+    def __init__(self, h2: "H2", tile: int = 8):
+        self.h2 = h2
+        h = ctypes.c_void_p()
+        _check(lib().orc_bj_new(h2._h, tile, ctypes.byref(h)))
+        self._h = h.value
+        self.ntiles = lib().orc_bj_ntiles(self._h)
+        self.dtype = h2.space.dtype
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_bj_free(self._h)
+            self._h = None
+
+    def tile(self, k: int):
+        t5 = np.zeros(5, dtype=np.int32)
+        _check(lib().orc_bj_tile(self._h, k, _p(t5), None))
+        n = int((t5[2] - t5[1]) * (t5[4] - t5[3]))
+        dofs = np.zeros(n, dtype=np.int64)
+        _check(lib().orc_bj_tile(self._h, k, _p(t5), _p(dofs)))
+        return tuple(int(v) for v in t5), dofs
+
+    def block(self, k: int) -> np.ndarray:
+        _, dofs = self.tile(k)
+        D = np.zeros((dofs.size, dofs.size), dtype=self.dtype)
+        _check(lib().orc_bj_block(self._h, k, _p(D)))
+        return D
+
+    def target(self, k: int, ring: int) -> np.ndarray:
+        _, dofs = self.tile(k)
+        C = np.zeros((dofs.size, dofs.size), dtype=self.dtype)
+        _check(lib().orc_bj_target(self._h, k, ring, _p(C)))
+        return C
+
+    def apply(self, r) -> np.ndarray:
+        r = np.ascontiguousarray(r, dtype=self.dtype)
+        z = np.zeros_like(r)
+        _check(lib().orc_bj_apply(self._h, _p(r), _p(z)))
+        return z
+
+    def gmres(self, b, tol: float = 1e-8, restart: int = 30, maxit: int = 2000):
+        """Right-preconditioned GMRES on the H2 operator; returns (x, iterations, relres, converged)."""
+        b = np.ascontiguousarray(b, dtype=self.dtype)
+        x = np.zeros_like(b)
+        st = np.zeros(3)
+        _check(lib().orc_h2_gmres_bj(self.h2._h, self._h, _p(b), _p(x), tol, restart, maxit, _p(st)))
+        return x, int(st[0]), float(st[1]), bool(st[2])

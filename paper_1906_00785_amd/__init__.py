@@ -124,16 +124,62 @@ class Operator:
         return y.reshape(x.shape)
 
     def solve(self, b: torch.Tensor, tol: float = 1e-8, restart: int = 30, maxit: int = 2000, refine: bool = False,
-              inner_tol: float = 0.0, max_outer: int = 0):
-        """GMRES(restart), optionally inside FP64 iterative refinement with the
+              inner_tol: float = 0.0, max_outer: int = 0, precond: bool = False):
+        """GMRES(restart), optionally right-preconditioned with the block preconditioner
+        (precond_build first) and/or inside FP64 iterative refinement with the
         low-precision far field; returns (x, [(iterations, converged, relres, outer)])."""
         bb = b.reshape(-1, self.ndof).contiguous()
         x = torch.empty_like(bb)
         nbytes = C.bem_solve_plan(self.h, bb.shape[0], restart, maxit, tol)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=bb.device)
         _, stats = C.bem_solve(self.h, bb.data_ptr(), self.ndof, x.data_ptr(), self.ndof, bb.shape[0], restart, maxit,
-                               tol, ws.data_ptr(), nbytes, _stream(), int(refine), max_outer, inner_tol)
+                               tol, ws.data_ptr(), nbytes, _stream(), int(refine), max_outer, inner_tol, int(precond))
         return x.reshape(b.shape), stats
+
+    # ---- block-Jacobi preconditioner and its learned correction
+    def precond_build(self):
+        """Extracts and inverts the 8 x 8-tile diagonal blocks of the near field."""
+        self.ntiles, nbytes = C.bem_precond_info(self.h)
+        self.prec_ws = torch.empty(nbytes, dtype=torch.uint8, device=_dev())
+        C.bem_precond_build(self.h, self.prec_ws.data_ptr(), nbytes, _stream())
+
+    def precond_apply(self, r: torch.Tensor) -> torch.Tensor:
+        rr = r.reshape(-1, self.ndof).contiguous()
+        z = torch.empty_like(rr)
+        C.bem_precond_apply(self.h, rr.data_ptr(), self.ndof, z.data_ptr(), self.ndof, rr.shape[0], _stream())
+        return z.reshape(r.shape)
+
+    def precond_export(self, which: int = 0) -> np.ndarray:
+        npdt = np.complex128 if self.space.dtype == torch.complex128 else np.float64
+        out = np.zeros((self.ntiles, 64, 64), dtype=npdt)
+        C.bem_precond_export(self.h, which, out.ctypes.data, _stream())
+        return out
+
+    def precond_features(self) -> torch.Tensor:
+        f = torch.empty((self.ntiles, 99), dtype=torch.float32, device=_dev())
+        C.bem_precond_features(self.h, f.data_ptr(), _stream())
+        return f
+
+    def precond_targets(self, ring: int = 2, per_pass: int = 256) -> torch.Tensor:
+        """(C_b - D_b^{-1}) / s_b for every tile, float (ntiles, 64, 64[, 2])."""
+        cplx = self.space.dtype == torch.complex128
+        shape = (self.ntiles, 64, 64, 2) if cplx else (self.ntiles, 64, 64)
+        delta = torch.empty(shape, dtype=torch.float32, device=_dev())
+        per_pass = max(1, min(per_pass, self.ntiles))
+        nbytes = C.bem_precond_target_bytes(self.h, ring, per_pass)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=_dev())
+        for t0 in range(0, self.ntiles, per_pass):
+            nt = min(per_pass, self.ntiles - t0)
+            C.bem_precond_targets(self.h, ring, t0, nt, work.data_ptr(), nbytes, delta.data_ptr(), _stream())
+        return delta
+
+    def precond_correct(self, uv: torch.Tensor | None, mode: int = 2, ring: int = 2) -> np.ndarray:
+        """Install the learned correction from the network output (mode 2: per-block probe
+        test, 1: keep all, 0: plain block-Jacobi); returns the accepted flags."""
+        acc = np.zeros(self.ntiles, dtype=np.int32)
+        ptr = uv.contiguous().data_ptr() if uv is not None else None
+        C.bem_precond_correct(self.h, ptr, mode, ring, acc.ctypes.data, _stream())
+        return acc
 
     def profile(self, on: bool):
         """Enable/disable HIP-event timing of the four apply stages."""

@@ -16,6 +16,7 @@ BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
 BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1 = 0, 1, 2, 3
 BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
 BEM_PREC_FP64, BEM_PREC_FP32, BEM_PREC_BF16 = 0, 1, 2
+BEM_PRECOND_NONE, BEM_PRECOND_BLOCK = 0, 1
 
 _c_int, _c_dbl, _c_i64, _c_sz, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
@@ -35,7 +36,7 @@ class bem_operator_info(ctypes.Structure):
 
 class bem_solve_params(ctypes.Structure):
     _fields_ = [("restart", _c_int), ("maxit", _c_int), ("tol", _c_dbl), ("refine", _c_int), ("max_outer", _c_int),
-                ("inner_tol", _c_dbl), ("reserved", _c_int * 4)]
+                ("inner_tol", _c_dbl), ("precond", _c_int), ("reserved", _c_int * 3)]
 
 
 class bem_solve_stats(ctypes.Structure):
@@ -74,6 +75,14 @@ _SIGNATURES = {
     "bem_export_near": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
     "bem_export_far": (_c_int, [_vp, _vp, _vp, _vp]),
     "bem_export_moments": (_c_int, [_vp, _vp, _vp, _vp]),
+    "bem_precond_info": (_c_int, [_vp, _P(_c_i64), _P(_c_sz)]),
+    "bem_precond_build": (_c_int, [_vp, _vp, _c_sz, _vp]),
+    "bem_precond_apply": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _vp]),
+    "bem_precond_export": (_c_int, [_vp, _c_int, _vp, _vp]),
+    "bem_precond_features": (_c_int, [_vp, _vp, _vp]),
+    "bem_precond_target_bytes": (_c_int, [_vp, _c_int, _c_i64, _P(_c_sz)]),
+    "bem_precond_targets": (_c_int, [_vp, _c_int, _c_i64, _c_i64, _vp, _c_sz, _vp, _vp]),
+    "bem_precond_correct": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _vp]),
 }
 
 
@@ -170,8 +179,8 @@ def bem_apply(A: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, str
     check(lib.bem_apply(A, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
 
 
-def _solve_params(restart, maxit, tol, refine=0, max_outer=0, inner_tol=0.0):
-    return bem_solve_params(restart, maxit, tol, int(refine), max_outer, inner_tol, (_c_int * 4)(0, 0, 0, 0))
+def _solve_params(restart, maxit, tol, refine=0, max_outer=0, inner_tol=0.0, precond=0):
+    return bem_solve_params(restart, maxit, tol, int(refine), max_outer, inner_tol, int(precond), (_c_int * 3)(0, 0, 0))
 
 
 def bem_apply_ex(A: int, prec: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, stream: int):
@@ -186,9 +195,10 @@ def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float) -> i
 
 
 def bem_solve(A: int, b_ptr: int, ldb: int, x_ptr: int, ldx: int, nrhs: int, restart: int, maxit: int, tol: float,
-              ws_ptr: int, ws_bytes: int, stream: int, refine: int = 0, max_outer: int = 0, inner_tol: float = 0.0):
+              ws_ptr: int, ws_bytes: int, stream: int, refine: int = 0, max_outer: int = 0, inner_tol: float = 0.0,
+              precond: int = 0):
     """Returns (rc, stats list); rc is BEM_OK or BEM_ENOCONV (other codes raise)."""
-    p = _solve_params(restart, maxit, tol, refine, max_outer, inner_tol)
+    p = _solve_params(restart, maxit, tol, refine, max_outer, inner_tol, precond)
     st = (bem_solve_stats * nrhs)()
     rc = lib.bem_solve(A, b_ptr, ldb, x_ptr, ldx, nrhs, ctypes.byref(p), st, ws_ptr, ws_bytes, stream)
     if rc not in (BEM_OK, BEM_ENOCONV):
@@ -227,3 +237,40 @@ def bem_export_far(A: int, pairs_ptr: int, blocks_ptr: int, stream: int):
 
 def bem_export_moments(A: int, x_ptr: int, mom_ptr: int, stream: int):
     check(lib.bem_export_moments(A, x_ptr, mom_ptr, stream))
+
+
+def bem_precond_info(A: int):
+    n, b = _c_i64(), _c_sz()
+    check(lib.bem_precond_info(A, ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
+
+
+def bem_precond_build(A: int, ws_ptr: int, ws_bytes: int, stream: int):
+    check(lib.bem_precond_build(A, ws_ptr, ws_bytes, stream))
+
+
+def bem_precond_apply(A: int, r_ptr: int, ldr: int, z_ptr: int, ldz: int, nrhs: int, stream: int):
+    check(lib.bem_precond_apply(A, r_ptr, ldr, z_ptr, ldz, nrhs, stream))
+
+
+def bem_precond_export(A: int, which: int, out_ptr: int, stream: int):
+    check(lib.bem_precond_export(A, which, out_ptr, stream))
+
+
+def bem_precond_features(A: int, feats_ptr: int, stream: int):
+    check(lib.bem_precond_features(A, feats_ptr, stream))
+
+
+def bem_precond_target_bytes(A: int, ring: int, nt: int) -> int:
+    b = _c_sz()
+    check(lib.bem_precond_target_bytes(A, ring, nt, ctypes.byref(b)))
+    return b.value
+
+
+def bem_precond_targets(A: int, ring: int, t0: int, nt: int, work_ptr: int, work_bytes: int, delta_ptr: int,
+                        stream: int):
+    check(lib.bem_precond_targets(A, ring, t0, nt, work_ptr, work_bytes, delta_ptr, stream))
+
+
+def bem_precond_correct(A: int, uv_ptr, mode: int, ring: int, accepted_ptr, stream: int):
+    check(lib.bem_precond_correct(A, uv_ptr, mode, ring, accepted_ptr, stream))

@@ -15,6 +15,7 @@
 #include "bem_batch.h"
 #include "bem_kernels.h"
 #include "bem_plan.h"
+#include "bem_precond.h"
 #include "bem_solve.h"
 
 using namespace bem;
@@ -75,6 +76,9 @@ struct bem_operator_s {
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
     int batch_rhs = 0;  // columns per many-RHS pass (slabs in the operator workspace)
     BatchDev bdev{};
+    // block preconditioner (bem_precond_*)
+    bool prec_built = false;
+    PrecDev pdev{};
     // stage timing of bem_apply (bem_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kApplyStages + 1 events per recorded apply
@@ -226,6 +230,7 @@ struct SolveWs {
     char* w;       // N
     char* r;       // N  (refinement: FP64 residual)
     char* d;       // N  (refinement: correction)
+    char* z;       // N  (preconditioned vector)
     char* partA;   // kSolveBlocks x (m+1) partial sums
     char* partB;
     double* npart; // kSolveBlocks partial squared norms
@@ -239,6 +244,7 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
     w.w = b.take<char>((size_t)N * sc);
     w.r = b.take<char>((size_t)N * sc);
     w.d = b.take<char>((size_t)N * sc);
+    w.z = b.take<char>((size_t)N * sc);
     w.partA = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
     w.partB = b.take<char>((size_t)kSolveBlocks * (m + 1) * sc);
     w.npart = b.take<double>(kSolveBlocks);
@@ -259,7 +265,7 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
 // only for the event of step j-1 (its residual estimate, copied to pinned memory), so the
 // device always has the next step queued; the true residual is read once per cycle.
 static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, int maxit, double tol,
-                     bem_solve_stats* out, SolveWs& W, hipStream_t stream) {
+                     bem_solve_stats* out, SolveWs& W, hipStream_t stream, bool pc = false) {
     const int64_t N = A->info.ndof;
     const int cp = A->cplx ? 1 : 0;
     const size_t sc = A->scal;
@@ -301,7 +307,12 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
         if (relres <= tol || total >= maxit || !std::isfinite(relres)) break;
         int k = 0;
         for (int j = 0; j < m && total + j < maxit; ++j) {
-            HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, prec, stream));
+            if (pc) {
+                HIP_CHECK(launch_prec_apply(A->dev, A->pdev, 1, Vj(j), W.z, stream));
+                HIP_CHECK(launch_apply(A->dev, W.z, W.w, prec, stream));
+            } else {
+                HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, prec, stream));
+            }
             HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partA, W.st.h1, W.w, W.partB, W.npart, 0, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partB, W.st.h2, W.w, W.partA, W.npart, 1, stream));
@@ -318,7 +329,17 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
             }
         }
         total += k;
-        HIP_CHECK(solve_backsolve_update(cp, N, k, W.V, x, W.st, stream));
+        if (pc) {
+            // x += M^{-1} (V y)
+            if (k > 0) {
+                HIP_CHECK(bsolve_zero(cp, N, W.z, stream));
+                HIP_CHECK(solve_backsolve_update(cp, N, k, W.V, W.z, W.st, stream));
+                HIP_CHECK(launch_prec_apply(A->dev, A->pdev, 1, W.z, W.w, stream));
+                HIP_CHECK(solve_axpy(cp, N, 1.0, W.w, x, stream));
+            }
+        } else {
+            HIP_CHECK(solve_backsolve_update(cp, N, k, W.V, x, W.st, stream));
+        }
     }
     out->iterations = total;
     out->relres = relres;
@@ -355,7 +376,8 @@ static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_pa
     int total = 0, outer = 0;
     while (bnorm > 0.0 && rnorm > p->tol * bnorm && outer < max_outer && total < p->maxit && std::isfinite(rnorm)) {
         bem_solve_stats in{};
-        const int rc = gmres_one(A, A->far_low, W.r, W.d, p->restart, p->maxit - total, inner_tol, &in, W, stream);
+        const int rc = gmres_one(A, A->far_low, W.r, W.d, p->restart, p->maxit - total, inner_tol, &in, W, stream,
+                                 p->precond != 0);
         if (rc != BEM_OK) return rc;
         total += in.iterations;
         ++outer;
@@ -381,6 +403,7 @@ struct BSolveWs {
     char* d;        // slab (refinement: correction)
     char* bs;       // slab of the right-hand sides
     char* xs;       // slab of the solutions
+    char* z;        // slab (preconditioned vectors)
     char* part;     // [slices][m+1][R] partial inner products
     char* h1;       // [m+1][R]
     char* h2;       // [m+1][R]
@@ -399,6 +422,7 @@ static size_t bsolve_layout(int64_t N, int m, int R, size_t sc, void* base, BSol
     w.d = b.take<char>(slab);
     w.bs = b.take<char>(slab);
     w.xs = b.take<char>(slab);
+    w.z = b.take<char>(slab);
     w.part = b.take<char>((size_t)kBSolveSlices * (m + 1) * R * sc);
     w.h1 = b.take<char>((size_t)(m + 1) * R * sc);
     w.h2 = b.take<char>((size_t)(m + 1) * R * sc);
@@ -449,7 +473,7 @@ static int ensure_bpin(bem_operator A, int R) {
 // updates its iterate with the steps it needed.  Convergence is decided on the true
 // residual at the start of the next cycle.
 static int gmres_batched(bem_operator A, int prec, const void* b, void* x, int R, int m, int maxit, double tol,
-                         bem_solve_stats* out, BSolveWs& W, hipStream_t stream) {
+                         bem_solve_stats* out, BSolveWs& W, hipStream_t stream, bool pc = false) {
     const int64_t N = A->info.ndof;
     const int cp = A->cplx ? 1 : 0;
     const size_t sc = A->scal;
@@ -491,7 +515,12 @@ static int gmres_batched(bem_operator A, int prec, const void* b, void* x, int R
         if (!any) break;
         int k = 0;
         for (int j = 0; j < m && j < room; ++j) {
-            if (bapply(A, prec, Vj(j), W.w, R, stream) != BEM_OK) return BEM_EDEVICE;
+            if (pc) {
+                HIP_CHECK(launch_prec_apply(A->dev, A->pdev, R, Vj(j), W.z, stream));
+                if (bapply(A, prec, W.z, W.w, R, stream) != BEM_OK) return BEM_EDEVICE;
+            } else if (bapply(A, prec, Vj(j), W.w, R, stream) != BEM_OK) {
+                return BEM_EDEVICE;
+            }
             HIP_CHECK(bsolve_dots(cp, N, R, j + 1, W.V, W.w, W.part, W.h1, stream));
             HIP_CHECK(bsolve_update(cp, N, R, j + 1, W.V, W.h1, W.w, W.npart, 0, stream));
             HIP_CHECK(bsolve_dots(cp, N, R, j + 1, W.V, W.w, W.part, W.h2, stream));
@@ -529,7 +558,16 @@ static int gmres_batched(bem_operator A, int prec, const void* b, void* x, int R
             total[r] += kr;
         }
         HIP_CHECK(hipMemcpyAsync(W.st.kr, kr_h, sizeof(int) * R, hipMemcpyHostToDevice, stream));
-        HIP_CHECK(bsolve_backsolve_update(cp, N, R, k, W.V, x, W.st, stream));
+        if (pc) {
+            if (k > 0) {
+                HIP_CHECK(bsolve_zero(cp, N * R, W.z, stream));
+                HIP_CHECK(bsolve_backsolve_update(cp, N, R, k, W.V, W.z, W.st, stream));
+                HIP_CHECK(launch_prec_apply(A->dev, A->pdev, R, W.z, W.w, stream));
+                HIP_CHECK(bsolve_axpy(cp, N, R, W.w, x, stream));
+            }
+        } else {
+            HIP_CHECK(bsolve_backsolve_update(cp, N, R, k, W.V, x, W.st, stream));
+        }
     }
     for (int r = 0; r < R; ++r) {
         out[r].iterations = total[r];
@@ -583,7 +621,8 @@ static int refine_batched(bem_operator A, const void* b, void* x, int R, const b
         int left = p->maxit;
         for (int r = 0; r < R; ++r)
             if (!done[r]) left = std::min(left, p->maxit - total[r]);
-        const int rc = gmres_batched(A, A->far_low, W.r, W.d, R, p->restart, left, inner_tol, in.data(), W, stream);
+        const int rc = gmres_batched(A, A->far_low, W.r, W.d, R, p->restart, left, inner_tol, in.data(), W, stream,
+                                     p->precond != 0);
         if (rc != BEM_OK) return rc;
         int progress = 0;
         for (int r = 0; r < R; ++r)
@@ -1007,6 +1046,118 @@ int bem_profile_read(bem_operator A, double* stage_ms, int nstages, int* napplie
 
 void bem_operator_destroy(bem_operator A) { delete A; }
 
+// ------------------------------------------------------------------------------ preconditioner
+static int64_t prec_tiles(const bem_operator_s& A, int* nt) {
+    const int t = (A.plan.S.nb + kTile - 1) / kTile;
+    if (nt) *nt = t;
+    return (int64_t)A.plan.S.geom.npatch * t * t;
+}
+
+int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes) {
+    if (!A || !ntiles || !ws_bytes) return fail(BEM_EINVAL, "NULL argument");
+    *ntiles = prec_tiles(*A, nullptr);
+    OpDev d{};
+    d.S = A->plan.S;
+    d.cplx = A->cplx ? 1 : 0;
+    *ws_bytes = prec_layout(d, *ntiles, nullptr, nullptr);
+    return BEM_OK;
+}
+
+int bem_precond_build(bem_operator A, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!A || !ws) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    int nt = 0;
+    const int64_t ntl = prec_tiles(*A, &nt);
+    if (ws_bytes < prec_layout(A->dev, ntl, nullptr, nullptr)) return fail(BEM_ENOMEM, "workspace too small");
+    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    PrecDev pc{};
+    prec_layout(A->dev, ntl, base, &pc);
+    pc.nt = nt;
+    HIP_CHECK(hipMemsetAsync(pc.status, 0, sizeof(int), stream));
+    HIP_CHECK(launch_prec_build(A->dev, pc, stream));
+    int st = 0;
+    HIP_CHECK(hipMemcpyAsync(&st, pc.status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    if (st != 0) return fail(BEM_EDEVICE, "a diagonal block of the near field is singular");
+    A->pdev = pc;
+    A->prec_built = true;
+    return BEM_OK;
+}
+
+int bem_precond_apply(bem_operator A, const void* r, int64_t ldr, void* z, int64_t ldz, int nrhs, hipStream_t stream) {
+    if (!A || !r || !z) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    const int64_t N = A->info.ndof;
+    if (nrhs < 1 || ldr < N || ldz < N) return fail(BEM_EINVAL, "nrhs >= 1 and leading dimensions >= N");
+    for (int c = 0; c < nrhs; ++c)
+        HIP_CHECK(launch_prec_apply(A->dev, A->pdev, 1, (const char*)r + (size_t)c * ldr * A->scal,
+                                    (char*)z + (size_t)c * ldz * A->scal, stream));
+    return BEM_OK;
+}
+
+int bem_precond_export(bem_operator A, int which, double* inv_host, hipStream_t stream) {
+    if (!A || !inv_host) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    const size_t bytes = (size_t)A->pdev.ntiles * kTileN * kTileN * A->scal;
+    HIP_CHECK(hipMemcpyAsync(inv_host, which ? A->pdev.D0inv : A->pdev.Dinv, bytes, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    return BEM_OK;
+}
+
+int bem_precond_features(bem_operator A, float* feats_dev, hipStream_t stream) {
+    if (!A || !feats_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    HIP_CHECK(launch_prec_features(A->dev, A->pdev, feats_dev, stream));
+    return BEM_OK;
+}
+
+int bem_precond_target_bytes(bem_operator A, int ring, int64_t nt, size_t* bytes) {
+    if (!A || !bytes) return fail(BEM_EINVAL, "NULL argument");
+    if (ring < 0 || ring > 8 || nt < 1) return fail(BEM_EINVAL, "ring in [0, 8] and nt >= 1");
+    OpDev d{};
+    d.S = A->plan.S;
+    d.cplx = A->cplx ? 1 : 0;
+    *bytes = prec_target_bytes(d, ring, nt) + 256;
+    return BEM_OK;
+}
+
+int bem_precond_targets(bem_operator A, int ring, int64_t t0, int64_t nt, void* work, size_t work_bytes,
+                        float* delta_dev, hipStream_t stream) {
+    if (!A || !work || !delta_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    if (ring < 0 || ring > 8 || nt < 1 || t0 < 0 || t0 + nt > A->pdev.ntiles)
+        return fail(BEM_EINVAL, "ring in [0, 8] and tiles inside [0, ntiles)");
+    if (work_bytes < prec_target_bytes(A->dev, ring, nt) + 256) return fail(BEM_ENOMEM, "work too small");
+    char* base = (char*)(((uintptr_t)work + 255) / 256 * 256);
+    HIP_CHECK(hipMemsetAsync(A->pdev.status, 0, sizeof(int), stream));
+    HIP_CHECK(launch_prec_targets(A->dev, A->pdev, ring, t0, nt, base, delta_dev, stream));
+    int st = 0;
+    HIP_CHECK(hipMemcpyAsync(&st, A->pdev.status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    if (st != 0) return fail(BEM_EDEVICE, "a neighbourhood system of the near field is singular");
+    return BEM_OK;
+}
+
+int bem_precond_correct(bem_operator A, const float* uv_dev, int mode, int ring, int* accepted_host,
+                        hipStream_t stream) {
+    if (!A || (!uv_dev && mode != 0)) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    if (mode < 0 || mode > 2 || ring < 0 || ring > 8) return fail(BEM_EINVAL, "mode in {0,1,2}, ring in [0, 8]");
+    const int64_t nt = A->pdev.ntiles;
+    if (mode == 0) {
+        HIP_CHECK(hipMemcpyAsync(A->pdev.Dinv, A->pdev.D0inv, (size_t)nt * kTileN * kTileN * A->scal,
+                                 hipMemcpyDeviceToDevice, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
+        if (accepted_host) std::memset(accepted_host, 0, sizeof(int) * nt);
+        return BEM_OK;
+    }
+    HIP_CHECK(launch_prec_correct(A->dev, A->pdev, uv_dev, mode, ring, A->pdev.accepted, stream));
+    if (accepted_host)
+        HIP_CHECK(hipMemcpyAsync(accepted_host, A->pdev.accepted, sizeof(int) * nt, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    return BEM_OK;
+}
+
 int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes) {
     if (!A || !p || !bytes) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart)
@@ -1024,8 +1175,11 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart || p->maxit < 1 || !(p->tol > 0.0))
         return fail(BEM_EINVAL, "bad solver parameters (restart must lie in [1, 64])");
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    if (p->precond != BEM_PRECOND_NONE && p->precond != BEM_PRECOND_BLOCK)
+        return fail(BEM_EINVAL, "precond must be BEM_PRECOND_NONE or BEM_PRECOND_BLOCK");
+    if (p->precond == BEM_PRECOND_BLOCK && !A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
     const int64_t N = A->info.ndof;
     if (ldb < N || ldx < N) return fail(BEM_EINVAL, "leading dimension too small");
     if (p->refine != 0 && p->refine != 1) return fail(BEM_EINVAL, "refine must be 0 or 1");
@@ -1047,7 +1201,7 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
                                      stream));
             const int rc = p->refine ? refine_batched(A, W.bs, W.xs, R, p, stats + r0, W, stream)
                                      : gmres_batched(A, 0, W.bs, W.xs, R, p->restart, p->maxit, p->tol, stats + r0,
-                                                     W, stream);
+                                                     W, stream, p->precond != 0);
             if (rc != BEM_OK) return rc;
             HIP_CHECK(launch_from_slab(A->cplx, N, R, W.xs, (char*)x_dev + (size_t)r0 * ldx * A->scal, ldx, stream));
             for (int r = 0; r < R; ++r) all = all && stats[r0 + r].converged;
@@ -1065,7 +1219,8 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
         const void* b = (const char*)b_dev + (size_t)r * ldb * A->scal;
         void* x = (char*)x_dev + (size_t)r * ldx * A->scal;
         const int rc = p->refine ? refine_one(A, b, x, p, &stats[r], W, stream)
-                                 : gmres_one(A, 0, b, x, p->restart, p->maxit, p->tol, &stats[r], W, stream);
+                                 : gmres_one(A, 0, b, x, p->restart, p->maxit, p->tol, &stats[r], W, stream,
+                                             p->precond != 0);
         if (rc != BEM_OK) return rc;
         all = all && stats[r].converged;
     }
