@@ -271,7 +271,7 @@ int bem_precond_export(bem_operator A, int which, double* inv_host, hipStream_t 
 /* Features of every tile for the correction network (device float, ntiles x 99): the
  * Jacobian of the patch map at the 4 x 4 cell centres of the parameter box of the
  * elements the tile's B-splines meet, with respect to box coordinates (d/ds x 3, d/dt x 3
- * per point, points row by row), then Re kappa, Im kappa, level. */
+ * per point, points row by row), then Re kappa / 10, Im kappa / 10, level / 8. */
 int bem_precond_features(bem_operator A, float* feats_dev, hipStream_t stream);
 
 /* Training targets of the correction network: for tiles [t0, t0 + nt), (C_b - D_b^{-1}) / s_b
@@ -292,6 +292,36 @@ int bem_precond_targets(bem_operator A, int ring, int64_t t0, int64_t nt, void* 
  * accepted_host (may be NULL): ntiles flags. */
 int bem_precond_correct(bem_operator A, const float* uv_dev, int mode, int ring, int* accepted_host,
                         hipStream_t stream);
+
+/* Keeps the learned correction (uv_dev as for bem_precond_correct, installed for every
+ * block) only if one GMRES(restart) cycle of the preconditioned true operator on b_dev
+ * (device, one column) ends with a lower residual than the same cycle with plain
+ * block-Jacobi; otherwise plain block-Jacobi is installed again.  ws: device workspace of
+ * >= the bytes from bem_solve_plan(A, 1, ...) plus N scalars.  *kept: 1 if the correction
+ * stays; relres2 (may be NULL): the two cycles' relative residuals (plain, learned). */
+int bem_precond_select(bem_operator A, const float* uv_dev, const void* b_dev, int restart, void* ws,
+                       size_t ws_bytes, int* kept, double* relres2, hipStream_t stream);
+
+/* ---- the correction network: in -> hidden -> hidden -> out, ReLU, trained on the device --
+ * Parameters: one FP32 device array, W1 [in][hidden], b1, W2 [hidden][hidden], b2,
+ * W3 [hidden][out], b3 (row-major).  precision 0: FP32 products; 1: BF16 operands on the
+ * matrix cores with FP32 accumulation.  ws: device workspace of >= ws_bytes for the batch. */
+int bem_mlp_sizes(int in, int hidden, int out, int batch, int64_t* nparams, size_t* ws_bytes);
+/* He-uniform weights from a counter-based generator (splitmix64 of seed and index), zero biases. */
+int bem_mlp_init(int in, int hidden, int out, uint64_t seed, float* params_dev, hipStream_t stream);
+/* Y [batch][out] = net(X [batch][in]) (device, row-major). */
+int bem_mlp_forward(int in, int hidden, int out, int batch, const float* params_dev, const float* X_dev, float* Y_dev,
+                    int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Loss of the rank-8 block correction and its gradient: the network output of sample b is
+ * U_b, V_b (64 x 8; out = 1024: [U | V] real, out = 2048: [Re U | Im U | Re V | Im V]);
+ * loss = mean_b ||T_b - U_b V_b^T||_F^2 / ||T_b||_F^2 with T (device float, batch x 64 x 64,
+ * interleaved complex if is_complex) into loss_dev[0], d loss / d params into grad_dev. */
+int bem_mlp_loss_grad(int in, int hidden, int out, int batch, int is_complex, const float* params_dev,
+                      const float* X_dev, const float* T_dev, float* grad_dev, float* loss_dev, int precision,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+/* One Adam step (bias-corrected moments m, v; step counts from 1). */
+int bem_mlp_adam(int64_t n, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int step, float lr,
+                 float beta1, float beta2, float eps, hipStream_t stream);
 
 /* Destroys the operator (its workspace stays with the caller). */
 void bem_operator_destroy(bem_operator A);

@@ -86,6 +86,7 @@ def lib():
             "orc_bj_apply": (I, [P, P, P]),
             "orc_bj_target": (I, [P, I64, I, P]),
             "orc_h2_gmres_bj": (I, [P, P, P, P, D, I, I, P]),
+            "orc_tile_features": (I, [P, I, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -356,3 +357,14 @@ class BlockJacobi:
         st = np.zeros(3)
         _check(lib().orc_h2_gmres_bj(self.h2._h, self._h, _p(b), _p(x), tol, restart, maxit, _p(st)))
         return x, int(st[0]), float(st[1]), bool(st[2])
+
+
+def tile_features(space: "Space", tile: int = 8) -> np.ndarray:
+    """Features of every tile of `tile` x `tile` B-spline indices (ntiles x 99), analytic
+    Jacobians of the patch maps (see bem_oracle.cpp, tile_features)."""
+    nb = space.degree + 1 + (2 ** space.level - 1) * space.knot_rep
+    npatch = {SPHERE: 6, ELLIPSOID: 6, TORUS: 16, FLAT: 1}[space.geom]
+    nt = -(-nb // tile)
+    out = np.zeros((npatch * nt * nt, 99))
+    _check(lib().orc_tile_features(space._h, tile, _p(out)))
+    return out

@@ -1418,6 +1418,37 @@ static std::vector<T> bj_target(const H2<T>& H, const Tile& t, int ring) {
     return C;
 }
 
+// Features of a tile for the correction network (reading, not in the paper): the parameter
+// box of the elements that the tile's B-splines meet; at the 4 x 4 cell centres of a
+// uniform grid of the box, the Jacobian of the patch map with respect to the box
+// coordinates (analytic derivatives): d/ds x, y, z then d/dt x, y, z per point, points row
+// by row; then Re kappa / 10, Im kappa / 10, level / 8.
+static void tile_features(const Space& S, const Tile& t, double* out) {
+    const int d = S.K.d, r = S.K.r, nel = 1 << S.K.L;
+    const double h = 1.0 / nel;
+    auto box = [&](int ja, int jb, double& lo, double& hi) {  // B-splines [ja, jb)
+        int elo = ja - d <= 0 ? 0 : (ja - d + r - 1) / r;
+        int ehi = std::min((jb - 1) / r, nel - 1);
+        lo = elo * h;
+        hi = (ehi + 1) * h;
+    };
+    double s0, s1, u0, u1;
+    box(t.j1a, t.j1b, s0, s1);
+    box(t.j2a, t.j2b, u0, u1);
+    for (int p = 0; p < 16; ++p) {
+        const double s = s0 + (p / 4 + 0.5) * 0.25 * (s1 - s0), u = u0 + (p % 4 + 0.5) * 0.25 * (u1 - u0);
+        double x[3], xs[3], xt[3];
+        gamma(S.G, t.f, s, u, x, xs, xt);
+        for (int k = 0; k < 3; ++k) {
+            out[p * 6 + k] = xs[k] * (s1 - s0);
+            out[p * 6 + 3 + k] = xt[k] * (u1 - u0);
+        }
+    }
+    out[96] = S.kappa.real() / 10.0;
+    out[97] = S.kappa.imag() / 10.0;
+    out[98] = S.K.L / 8.0;
+}
+
 }  // namespace orc
 
 // =======================================================================================
@@ -1916,6 +1947,15 @@ int orc_bj_target(void* bp, int64_t k, int ring, double* C) {
         }
     })
 }
+// features of every tile of T x T B-spline indices (ntiles x 99)
+int orc_tile_features(void* sp, int T, double* feats) {
+    ORC_TRY({
+        const Space& S = ((OrcSpace*)sp)->S;
+        const auto tiles = make_tiles(S, T);
+        for (size_t k = 0; k < tiles.size(); ++k) tile_features(S, tiles[k], feats + k * 99);
+    })
+}
+
 // right-preconditioned GMRES on the H^2 operator: GMRES on A M^{-1}, then x = M^{-1} u
 int orc_h2_gmres_bj(void* hp, void* bp, const double* b, double* x, double tol, int restart, int maxit,
                     double* stats) {

@@ -83,6 +83,14 @@ _SIGNATURES = {
     "bem_precond_target_bytes": (_c_int, [_vp, _c_int, _c_i64, _P(_c_sz)]),
     "bem_precond_targets": (_c_int, [_vp, _c_int, _c_i64, _c_i64, _vp, _c_sz, _vp, _vp]),
     "bem_precond_correct": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _vp]),
+    "bem_precond_select": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_sz, _P(_c_int), _P(_c_dbl), _vp]),
+    "bem_mlp_sizes": (_c_int, [_c_int, _c_int, _c_int, _c_int, _P(_c_i64), _P(_c_sz)]),
+    "bem_mlp_init": (_c_int, [_c_int, _c_int, _c_int, ctypes.c_uint64, _vp, _vp]),
+    "bem_mlp_forward": (_c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _c_int, _vp, _c_sz, _vp]),
+    "bem_mlp_loss_grad": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _vp, _vp, _c_int, _vp, _c_sz,
+                                   _vp]),
+    "bem_mlp_adam": (_c_int, [_c_i64, _vp, _vp, _vp, _vp, _c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, _vp]),
 }
 
 
@@ -274,3 +282,34 @@ def bem_precond_targets(A: int, ring: int, t0: int, nt: int, work_ptr: int, work
 
 def bem_precond_correct(A: int, uv_ptr, mode: int, ring: int, accepted_ptr, stream: int):
     check(lib.bem_precond_correct(A, uv_ptr, mode, ring, accepted_ptr, stream))
+
+
+def bem_precond_select(A: int, uv_ptr: int, b_ptr: int, restart: int, ws_ptr: int, ws_bytes: int, stream: int):
+    kept = _c_int()
+    rr = (_c_dbl * 2)()
+    check(lib.bem_precond_select(A, uv_ptr, b_ptr, restart, ws_ptr, ws_bytes, ctypes.byref(kept), rr, stream))
+    return bool(kept.value), (rr[0], rr[1])
+
+
+def bem_mlp_sizes(n_in: int, hidden: int, out: int, batch: int):
+    n, b = _c_i64(), _c_sz()
+    check(lib.bem_mlp_sizes(n_in, hidden, out, batch, ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
+
+
+def bem_mlp_init(n_in: int, hidden: int, out: int, seed: int, params_ptr: int, stream: int):
+    check(lib.bem_mlp_init(n_in, hidden, out, seed, params_ptr, stream))
+
+
+def bem_mlp_forward(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, ws_ptr, ws_bytes, stream):
+    check(lib.bem_mlp_forward(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, ws_ptr, ws_bytes, stream))
+
+
+def bem_mlp_loss_grad(n_in, hidden, out, batch, is_complex, params_ptr, x_ptr, t_ptr, grad_ptr, loss_ptr, precision,
+                      ws_ptr, ws_bytes, stream):
+    check(lib.bem_mlp_loss_grad(n_in, hidden, out, batch, is_complex, params_ptr, x_ptr, t_ptr, grad_ptr, loss_ptr,
+                                precision, ws_ptr, ws_bytes, stream))
+
+
+def bem_mlp_adam(n, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream):
+    check(lib.bem_mlp_adam(n, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream))

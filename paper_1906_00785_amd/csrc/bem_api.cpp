@@ -14,6 +14,7 @@
 
 #include "bem_batch.h"
 #include "bem_kernels.h"
+#include "bem_mlp.h"
 #include "bem_plan.h"
 #include "bem_precond.h"
 #include "bem_solve.h"
@@ -1225,6 +1226,87 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
         all = all && stats[r].converged;
     }
     if (!all) return fail(BEM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
+    return BEM_OK;
+}
+
+int bem_precond_select(bem_operator A, const float* uv_dev, const void* b_dev, int restart, void* ws,
+                       size_t ws_bytes, int* kept, double* relres2, hipStream_t stream) {
+    if (!A || !uv_dev || !b_dev || !ws || !kept) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
+    if (restart < 1 || restart > kMaxRestart) return fail(BEM_EINVAL, "restart in [1, 64]");
+    const int64_t N = A->info.ndof;
+    const size_t need = solve_layout(N, restart, A->scal, nullptr, nullptr);
+    if (ws_bytes < need + (size_t)N * A->scal + 512) return fail(BEM_ENOMEM, "workspace too small");
+    if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
+    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    SolveWs W;
+    solve_layout(N, restart, A->scal, base, &W);
+    char* x = base + (need + 255) / 256 * 256;
+    double rr[2] = {0.0, 0.0};
+    for (int c = 0; c < 2; ++c) {
+        const int rc = bem_precond_correct(A, c ? uv_dev : nullptr, c ? 1 : 0, 0, nullptr, stream);
+        if (rc != BEM_OK) return rc;
+        bem_solve_stats st{};
+        const int g = gmres_one(A, 0, b_dev, x, restart, restart, 1e-300, &st, W, stream, true);
+        if (g != BEM_OK) return g;
+        rr[c] = st.relres;
+    }
+    *kept = rr[1] < rr[0] ? 1 : 0;
+    if (!*kept) {
+        const int rc = bem_precond_correct(A, nullptr, 0, 0, nullptr, stream);
+        if (rc != BEM_OK) return rc;
+    }
+    if (relres2) {
+        relres2[0] = rr[0];
+        relres2[1] = rr[1];
+    }
+    return BEM_OK;
+}
+
+// ------------------------------------------------------------------------------ network
+int bem_mlp_sizes(int in, int hidden, int out, int batch, int64_t* nparams, size_t* ws_bytes) {
+    if (!nparams || !ws_bytes) return fail(BEM_EINVAL, "NULL argument");
+    if (in < 1 || hidden < 1 || out < 1 || batch < 1) return fail(BEM_EINVAL, "sizes must be >= 1");
+    *nparams = mlp_nparams(in, hidden, out);
+    *ws_bytes = mlp_ws_bytes(hidden, out, batch);
+    return BEM_OK;
+}
+
+int bem_mlp_init(int in, int hidden, int out, uint64_t seed, float* params_dev, hipStream_t stream) {
+    if (!params_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (in < 1 || hidden < 1 || out < 1) return fail(BEM_EINVAL, "sizes must be >= 1");
+    HIP_CHECK(mlp_init(in, hidden, out, seed, params_dev, stream));
+    return BEM_OK;
+}
+
+int bem_mlp_forward(int in, int hidden, int out, int batch, const float* params_dev, const float* X_dev, float* Y_dev,
+                    int precision, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!params_dev || !X_dev || !Y_dev || !ws) return fail(BEM_EINVAL, "NULL argument");
+    if (in < 1 || hidden < 1 || out < 1 || batch < 1 || (precision != 0 && precision != 1))
+        return fail(BEM_EINVAL, "sizes >= 1, precision 0 or 1");
+    if (ws_bytes < mlp_ws_bytes(hidden, out, batch)) return fail(BEM_ENOMEM, "workspace too small");
+    HIP_CHECK(mlp_forward(in, hidden, out, batch, params_dev, X_dev, Y_dev, precision, ws, stream));
+    return BEM_OK;
+}
+
+int bem_mlp_loss_grad(int in, int hidden, int out, int batch, int is_complex, const float* params_dev,
+                      const float* X_dev, const float* T_dev, float* grad_dev, float* loss_dev, int precision,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!params_dev || !X_dev || !T_dev || !grad_dev || !loss_dev || !ws) return fail(BEM_EINVAL, "NULL argument");
+    if (in < 1 || hidden < 1 || batch < 1 || (precision != 0 && precision != 1))
+        return fail(BEM_EINVAL, "sizes >= 1, precision 0 or 1");
+    if (out != (is_complex ? 4 : 2) * kMlpSlots * kMlpRank) return fail(BEM_EINVAL, "out must be 1024 (real) or 2048");
+    if (ws_bytes < mlp_ws_bytes(hidden, out, batch)) return fail(BEM_ENOMEM, "workspace too small");
+    HIP_CHECK(mlp_loss_grad(in, hidden, out, batch, is_complex ? 1 : 0, params_dev, X_dev, T_dev, grad_dev, loss_dev,
+                            precision, ws, stream));
+    return BEM_OK;
+}
+
+int bem_mlp_adam(int64_t n, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int step, float lr,
+                 float beta1, float beta2, float eps, hipStream_t stream) {
+    if (!params_dev || !grad_dev || !m_dev || !v_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (n < 1 || step < 1) return fail(BEM_EINVAL, "n >= 1 and step >= 1");
+    HIP_CHECK(mlp_adam(n, params_dev, grad_dev, m_dev, v_dev, step, lr, beta1, beta2, eps, stream));
     return BEM_OK;
 }
 

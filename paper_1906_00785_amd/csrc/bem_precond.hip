@@ -237,9 +237,9 @@ __global__ __launch_bounds__(64) void kp_features(OpDev op, PrecDev pc, float* f
         }
     }
     if (p == 16) {
-        out[96] = (float)S.ker.kre;
-        out[97] = (float)S.ker.kim;
-        out[98] = (float)S.L;
+        out[96] = (float)(S.ker.kre / 10.0);
+        out[97] = (float)(S.ker.kim / 10.0);
+        out[98] = (float)(S.L / 8.0);
     }
 }
 
