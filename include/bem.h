@@ -274,12 +274,13 @@ int bem_precond_export(bem_operator A, int which, double* inv_host, hipStream_t 
  * per point, points row by row), then Re kappa / 10, Im kappa / 10, level / 8. */
 int bem_precond_features(bem_operator A, float* feats_dev, hipStream_t stream);
 
-/* Training targets of the correction network: for tiles [t0, t0 + nt), (C_b - D_b^{-1}) / s_b
+/* Training targets of the correction network: for tiles [t0, t0 + nt), (X_b - D_b^{-1}) / s_b
  * as device float ntiles x 64 x 64 (interleaved re, im for Helmholtz; written at tile
- * index), where C_b = [(A_N)^{-1}]_{bb}, N(b) the tile extended by `ring` (0..8) B-spline
- * indices per side inside the patch, A_N the near field on N(b) (reduced by Gauss-Jordan
- * with partial pivoting), s_b = ||D_b^{-1}||_F / 64.  work: device scratch of >= the bytes
- * from bem_precond_target_bytes(A, ring, nt). */
+ * index), where X_b is the block least-squares approximate inverse
+ * X_b = argmin ||A[N(b), b] X - I[N(b), b]||_F = (A_Nb^H A_Nb)^{-1} D_b^H on N(b), the tile
+ * extended by `ring` (0..8) B-spline indices per side inside the patch, A_Nb the near field
+ * on the rows of N(b) and the columns of b, and s_b = ||D_b^{-1}||_F / 64.  work: device
+ * scratch of >= the bytes from bem_precond_target_bytes(A, ring, nt). */
 int bem_precond_target_bytes(bem_operator A, int ring, int64_t nt, size_t* bytes);
 int bem_precond_targets(bem_operator A, int ring, int64_t t0, int64_t nt, void* work, size_t work_bytes,
                         float* delta_dev, hipStream_t stream);
@@ -287,8 +288,9 @@ int bem_precond_targets(bem_operator A, int ring, int64_t t0, int64_t nt, void* 
 /* Installs the learned correction M_b^{-1} = D_b^{-1} + s_b U_b V_b^T from the network output
  * uv_dev (device float, ntiles x out; out = [U (64 x 8, row-major), V (64 x 8)] for Laplace,
  * [Re U, Im U, Re V, Im V] for Helmholtz).  mode 2: keep it only for blocks where it lowers
- * the residual of the near field on N(b) (ring as above) for each of 4 seeded probe
- * vectors, else fall back to D_b^{-1}; mode 1: keep all; mode 0: plain block-Jacobi again.
+ * the least-squares residual ||[p; 0] - A[N(b), b] z|| (the quantity X_b minimises) for each
+ * of 4 seeded probe vectors p, else fall back to D_b^{-1}; mode 1: keep all; mode 0: plain
+ * block-Jacobi again.
  * accepted_host (may be NULL): ntiles flags. */
 int bem_precond_correct(bem_operator A, const float* uv_dev, int mode, int ring, int* accepted_host,
                         hipStream_t stream);

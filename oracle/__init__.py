@@ -339,6 +339,7 @@ class BlockJacobi:
         return D
 
     def target(self, k: int, ring: int) -> np.ndarray:
+        """Block least-squares approximate inverse X_b of tile k on the tile extended by ring."""
         _, dofs = self.tile(k)
         C = np.zeros((dofs.size, dofs.size), dtype=self.dtype)
         _check(lib().orc_bj_target(self._h, k, ring, _p(C)))

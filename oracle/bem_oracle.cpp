@@ -1287,8 +1287,8 @@ static int gmres(int64_t n, MV matvec, const T* b, T* x, double tol, int m, int 
 // workloads here and checked by the tests through the dense operator).  D_b^{-1} is applied
 // by LU with partial pivoting.  Right preconditioning: GMRES on A M^{-1}, x = M^{-1} u, so
 // the residual GMRES sees is the true residual.
-// Learned-correction targets: C_b = [(A_N)^{-1}]_{bb}, where N(b) is the tile extended by
-// `ring` B-spline indices on each side inside the patch and A_N is the near field on N(b).
+// Learned-correction targets: the block least-squares approximate inverse on N(b), the tile
+// extended by `ring` B-spline indices on each side inside the patch (see bj_target).
 // ---------------------------------------------------------------------------------------
 struct Tile {
     int f, j1a, j1b, j2a, j2b;  // [j1a, j1b) x [j2a, j2b) of patch f
@@ -1396,26 +1396,34 @@ static void bj_apply(const BJ<T>& B, const T* r, T* z) {
     }
 }
 
-// C_b = [(A_N)^{-1}]_{bb}: solve A_N X = E_b by LU and keep the rows of b
+// Learned-correction target: the block least-squares approximate inverse of tile b,
+// X_b = argmin_X ||A[N(b), b] X - I[N(b), b]||_F = (A_Nb^H A_Nb)^{-1} A_bb^H, with A_Nb the
+// near-field rows of N(b) in the columns of b (the tile extended by `ring` indices per
+// side).  For ring 0 it is D_b^{-1}.
 template <class T>
 static std::vector<T> bj_target(const H2<T>& H, const Tile& t, int ring) {
     const auto gb = tile_dofs(*H.S, t, 0);
     const auto gn = tile_dofs(*H.S, t, ring);
     const int n = (int)gn.size(), nbk = (int)gb.size();
-    std::vector<T> AN = near_block(H, gn, gn);
+    const std::vector<T> ANb = near_block(H, gn, gb);  // n x nbk
+    std::vector<T> G((size_t)nbk * nbk, T(0));
+    for (int i = 0; i < nbk; ++i)
+        for (int j = 0; j < nbk; ++j) {
+            T s = T(0);
+            for (int k = 0; k < n; ++k) s += conjv(ANb[(size_t)k * nbk + i]) * ANb[(size_t)k * nbk + j];
+            G[(size_t)i * nbk + j] = s;
+        }
+    const std::vector<T> D = near_block(H, gb, gb);
     std::vector<int> piv;
-    lu_factor(AN, n, piv);
-    std::vector<int> pos(nbk);
-    for (int i = 0; i < nbk; ++i) pos[i] = (int)(std::find(gn.begin(), gn.end(), gb[i]) - gn.begin());
-    std::vector<T> C((size_t)nbk * nbk);
-    std::vector<T> e(n);
+    lu_factor(G, nbk, piv);
+    std::vector<T> X((size_t)nbk * nbk);
+    std::vector<T> col(nbk);
     for (int j = 0; j < nbk; ++j) {
-        std::fill(e.begin(), e.end(), T(0));
-        e[pos[j]] = T(1);
-        lu_solve(AN, n, piv, e.data());
-        for (int i = 0; i < nbk; ++i) C[(size_t)i * nbk + j] = e[pos[i]];
+        for (int i = 0; i < nbk; ++i) col[i] = conjv(D[(size_t)j * nbk + i]);  // column j of D^H
+        lu_solve(G, nbk, piv, col.data());
+        for (int i = 0; i < nbk; ++i) X[(size_t)i * nbk + j] = col[i];
     }
-    return C;
+    return X;
 }
 
 // Features of a tile for the correction network (reading, not in the paper): the parameter
@@ -1934,7 +1942,7 @@ int orc_bj_apply(void* bp, const double* r, double* z) {
             bj_apply(b->br, r, z);
     })
 }
-// learned-correction target C_b of tile k with the given ring (n_b x n_b row-major)
+// learned-correction target X_b of tile k with the given ring (n_b x n_b row-major)
 int orc_bj_target(void* bp, int64_t k, int ring, double* C) {
     ORC_TRY({
         OrcBJ* b = (OrcBJ*)bp;

@@ -7,7 +7,7 @@ vector, W1 [in][hid], b1, W2 [hid][hid], b2, W3 [hid][out], b3 (row-major).
 
 The loss of one sample: U, V (64 x 8, complex when the PDE is Helmholtz) are the network
 output ([U | V] real, [Re U | Im U | Re V | Im V] complex); E = T - U V^T with the target
-T = (C_b - D_b^{-1}) / s_b; L_b = ||E||_F^2 / ||T||_F^2; the batch loss is the mean.  By the
+T = (X_b - D_b^{-1}) / s_b; L_b = ||E||_F^2 / ||T||_F^2; the batch loss is the mean.  By the
 Eckart-Young theorem the minimiser over rank-8 U V^T is the rank-8 truncated SVD of T,
 so fitting T itself is the same as fitting that truncation.
 """

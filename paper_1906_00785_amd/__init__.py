@@ -161,7 +161,8 @@ class Operator:
         return f
 
     def precond_targets(self, ring: int = 2, per_pass: int = 256) -> torch.Tensor:
-        """(C_b - D_b^{-1}) / s_b for every tile, float (ntiles, 64, 64[, 2])."""
+        """(X_b - D_b^{-1}) / s_b for every tile, float (ntiles, 64, 64[, 2]), X_b the block
+        least-squares approximate inverse on the tile extended by `ring` indices."""
         cplx = self.space.dtype == torch.complex128
         shape = (self.ntiles, 64, 64, 2) if cplx else (self.ntiles, 64, 64)
         delta = torch.empty(shape, dtype=torch.float32, device=_dev())

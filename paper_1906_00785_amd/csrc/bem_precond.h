@@ -40,9 +40,10 @@ hipError_t launch_prec_build(const OpDev& op, const PrecDev& pc, hipStream_t st)
 hipError_t launch_prec_apply(const OpDev& op, const PrecDev& pc, int R, const void* r, void* z, hipStream_t st);
 // features of every tile (float, [ntiles][kFeat])
 hipError_t launch_prec_features(const OpDev& op, const PrecDev& pc, float* feats, hipStream_t st);
-// training targets: (C_b - D_b^{-1}) / s_b as float [ntiles][64][64] (x2 interleaved if
-// complex), C_b = [(A_N)^{-1}]_bb with N(b) the tile plus `ring` (<= 8) indices per side;
-// work: scratch of prec_target_bytes(); tiles [t0, t0 + nt) per launch
+// training targets: (X_b - D_b^{-1}) / s_b as float [ntiles][64][64] (x2 interleaved if
+// complex), X_b = (A_Nb^H A_Nb)^{-1} D_b^H the block least-squares approximate inverse on
+// N(b), the tile plus `ring` (<= 8) indices per side; work: scratch of
+// prec_target_bytes(); tiles [t0, t0 + nt) per launch
 size_t prec_target_bytes(const OpDev& op, int ring, int64_t ntiles_per_launch);
 hipError_t launch_prec_targets(const OpDev& op, const PrecDev& pc, int ring, int64_t t0, int64_t nt, void* work,
                                float* delta, hipStream_t st);

@@ -81,18 +81,11 @@ __global__ __launch_bounds__(256) void kp_extract(OpDev op, PrecDev pc) {
 }
 
 // ------------------------------------------------------------------ inversion
-// In-place Gauss-Jordan with partial pivoting (largest modulus in the column), one block
-// per tile; the row interchanges are undone as column interchanges in reverse order.
+// In-place Gauss-Jordan inversion of the 64 x 64 matrix a (LDS) with partial pivoting
+// (largest modulus in the column) by the whole block; the row interchanges are undone as
+// column interchanges in reverse order.  status[0] = 1 on a zero pivot.
 template <class T>
-__global__ __launch_bounds__(256) void kp_invert(PrecDev pc) {
-    __shared__ T a[kTileN][kTileN + 1];
-    __shared__ T colk[kTileN];
-    __shared__ int perm[kTileN];
-    __shared__ int piv_s;
-    const int64_t tb = blockIdx.x;
-    T* src = (T*)pc.D0inv + tb * kTileN * kTileN;
-    for (int i = threadIdx.x; i < kTileN * kTileN; i += 256) a[i / kTileN][i % kTileN] = src[i];
-    __syncthreads();
+__device__ void gj_invert(T (*a)[kTileN + 1], T* colk, int* perm, int* piv_s, int* status) {
     for (int k = 0; k < kTileN; ++k) {
         if (threadIdx.x < 64) {
             const int i = threadIdx.x;
@@ -108,15 +101,15 @@ __global__ __launch_bounds__(256) void kp_invert(PrecDev pc) {
                 }
             }
             if (i == 0) {
-                piv_s = p;
+                *piv_s = p;
                 perm[k] = p;
-                if (v == 0.0) pc.status[0] = 1;
+                if (v == 0.0) status[0] = 1;
             }
         }
         __syncthreads();
-        const int p = piv_s;
+        const int p = *piv_s;
         if (p != k)
-            for (int j = threadIdx.x; j < kTileN; j += 256) {
+            for (int j = threadIdx.x; j < kTileN; j += blockDim.x) {
                 const T tmp = a[k][j];
                 a[k][j] = a[p][j];
                 a[p][j] = tmp;
@@ -124,10 +117,10 @@ __global__ __launch_bounds__(256) void kp_invert(PrecDev pc) {
         __syncthreads();
         const T inv = inv_(a[k][k]);
         __syncthreads();
-        for (int j = threadIdx.x; j < kTileN; j += 256) a[k][j] = j == k ? inv : a[k][j] * inv;
-        for (int i = threadIdx.x; i < kTileN; i += 256) colk[i] = a[i][k];
+        for (int j = threadIdx.x; j < kTileN; j += blockDim.x) a[k][j] = j == k ? inv : a[k][j] * inv;
+        for (int i = threadIdx.x; i < kTileN; i += blockDim.x) colk[i] = a[i][k];
         __syncthreads();
-        for (int idx = threadIdx.x; idx < kTileN * kTileN; idx += 256) {
+        for (int idx = threadIdx.x; idx < kTileN * kTileN; idx += blockDim.x) {
             const int i = idx / kTileN, j = idx % kTileN;
             if (i == k) continue;
             if (j == k)
@@ -140,13 +133,26 @@ __global__ __launch_bounds__(256) void kp_invert(PrecDev pc) {
     for (int k = kTileN - 1; k >= 0; --k) {
         const int p = perm[k];
         if (p != k)
-            for (int i = threadIdx.x; i < kTileN; i += 256) {
+            for (int i = threadIdx.x; i < kTileN; i += blockDim.x) {
                 const T tmp = a[i][k];
                 a[i][k] = a[i][p];
                 a[i][p] = tmp;
             }
         __syncthreads();
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void kp_invert(PrecDev pc) {
+    __shared__ T a[kTileN][kTileN + 1];
+    __shared__ T colk[kTileN];
+    __shared__ int perm[kTileN];
+    __shared__ int piv_s;
+    const int64_t tb = blockIdx.x;
+    T* src = (T*)pc.D0inv + tb * kTileN * kTileN;
+    for (int i = threadIdx.x; i < kTileN * kTileN; i += 256) a[i / kTileN][i % kTileN] = src[i];
+    __syncthreads();
+    gj_invert<T>(a, colk, perm, &piv_s, pc.status);
     T* dst0 = (T*)pc.D0inv + tb * kTileN * kTileN;
     T* dst1 = (T*)pc.Dinv + tb * kTileN * kTileN;
     double fro = 0.0;
@@ -283,96 +289,61 @@ __device__ inline T near_entry(const OpDev& op, const int64_t* grp_of_row, const
     return ((const T*)op.val)[op.grp_voff[G] + (int64_t)pos_of_row[g] * (e - b) + (lo - b)];
 }
 
-// Augmented system [A_N | E_b] of one tile in `work` (n rows, n + 64 columns), reduced by
-// Gauss-Jordan with partial pivoting; C_b = rows of b of the right part.  One block per tile.
+__device__ inline double conj_(double v) { return v; }
+__device__ inline cdbl conj_(cdbl v) { return {v.re, -v.im}; }
+
+// Block least-squares approximate inverse of one tile (one block per tile):
+// X_b = argmin ||A[N(b), b] X - I[N(b), b]||_F = (A_Nb^H A_Nb)^{-1} D_b^H, with A_Nb the near
+// field on the rows of N(b) and the slots of b (in `work`, n x 64); unused slots of a short
+// tile keep identity.  Target: (X_b - D_b^{-1}) / s_b.
 template <class T>
 __global__ __launch_bounds__(256) void kp_targets(OpDev op, PrecDev pc, int ring, int64_t t0, T* work, int64_t wstride,
                                                   float* delta) {
+    __shared__ T G[kTileN][kTileN + 1];
+    __shared__ T colk[kTileN];
+    __shared__ int perm[kTileN];
+    __shared__ int piv_s;
     const int64_t* grp_of_row = pc.grp_of_row;
     const int32_t* pos_of_row = pc.pos_of_row;
-    __shared__ double vmax[256];
-    __shared__ int imax[256];
-    __shared__ T rowk[(kTile + 2 * 8) * (kTile + 2 * 8) + kTileN];
     const int64_t tb = t0 + blockIdx.x;
     const Nbhd N = nbhd_of(op.S, pc.nt, tb, ring);
-    const int n = N.n, nc = n + kTileN;
-    T* M = work + blockIdx.x * wstride;
-    // build [A_N | E_b]: column n + l is the unit vector of slot l of the tile (if used)
-    for (int64_t idx = threadIdx.x; idx < (int64_t)n * nc; idx += 256) {
-        const int i = (int)(idx / nc), j = (int)(idx % nc);
-        const int64_t g = N.dof(op.S, i);
+    const int n = N.n;
+    T* Anb = work + blockIdx.x * wstride;  // [n][64]
+    T* DH = Anb + (int64_t)n * kTileN;     // [64][64]: D_b^H (identity on unused slots)
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * kTileN; idx += 256) {
+        const int i = (int)(idx / kTileN), l = (int)(idx % kTileN);
+        const int64_t h = slot_dof(op.S, pc.nt, tb, l);
+        Anb[idx] = h >= 0 ? near_entry<T>(op, grp_of_row, pos_of_row, N.dof(op.S, i), h) : zero<T>();
+    }
+    for (int idx = threadIdx.x; idx < kTileN * kTileN; idx += 256) {
+        const int i = idx / kTileN, j = idx % kTileN;
+        const int64_t gi = slot_dof(op.S, pc.nt, tb, i), gj = slot_dof(op.S, pc.nt, tb, j);
         T v = zero<T>();
-        if (j < n) {
-            v = near_entry<T>(op, grp_of_row, pos_of_row, g, N.dof(op.S, j));
-        } else {
-            const int64_t h = slot_dof(op.S, pc.nt, tb, j - n);
-            if (h == g) v = one<T>();
-        }
-        M[idx] = v;
+        if (gi >= 0 && gj >= 0)
+            v = conj_(near_entry<T>(op, grp_of_row, pos_of_row, gj, gi));  // (D^H)_ij = conj(D_ji)
+        else if (i == j)
+            v = one<T>();
+        DH[idx] = v;
     }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        double v = -1.0;
-        int p = k;
-        for (int i = k + threadIdx.x; i < n; i += 256) {
-            const double a = absval(M[(int64_t)i * nc + k]);
-            if (a > v) {
-                v = a;
-                p = i;
-            }
-        }
-        vmax[threadIdx.x] = v;
-        imax[threadIdx.x] = p;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) {
-                const double v2 = vmax[threadIdx.x + o];
-                const int p2 = imax[threadIdx.x + o];
-                if (v2 > vmax[threadIdx.x] || (v2 == vmax[threadIdx.x] && p2 < imax[threadIdx.x])) {
-                    vmax[threadIdx.x] = v2;
-                    imax[threadIdx.x] = p2;
-                }
-            }
-            __syncthreads();
-        }
-        const int pr = imax[0];
-        if (threadIdx.x == 0 && vmax[0] == 0.0) pc.status[0] = 1;
-        // swap rows k and pr (columns >= k), scale row k, keep it in LDS
-        const T inv = inv_(M[(int64_t)pr * nc + k]);
-        __syncthreads();
-        for (int j = k + threadIdx.x; j < nc; j += 256) {
-            const T a = M[(int64_t)pr * nc + j];
-            if (pr != k) M[(int64_t)pr * nc + j] = M[(int64_t)k * nc + j];
-            const T s = a * inv;
-            M[(int64_t)k * nc + j] = s;
-            rowk[j - k] = s;
-        }
-        __syncthreads();
-        // eliminate column k from every other row
-        for (int64_t idx = threadIdx.x; idx < (int64_t)n * (nc - k - 1); idx += 256) {
-            const int i = (int)(idx / (nc - k - 1)), j = k + 1 + (int)(idx % (nc - k - 1));
-            if (i == k) continue;
-            const T f = M[(int64_t)i * nc + k];
-            M[(int64_t)i * nc + j] -= f * rowk[j - k];
-        }
-        __syncthreads();
+    for (int idx = threadIdx.x; idx < kTileN * kTileN; idx += 256) {
+        const int i = idx / kTileN, j = idx % kTileN;
+        T acc = zero<T>();
+        for (int k = 0; k < n; ++k) acc += conj_(Anb[(int64_t)k * kTileN + i]) * Anb[(int64_t)k * kTileN + j];
+        if (i == j && slot_dof(op.S, pc.nt, tb, i) < 0) acc = one<T>();
+        G[i][j] = acc;
     }
-    // Delta = (C_b - D_b^{-1}) / s_b for the used slots (unused slots: 0)
+    __syncthreads();
+    gj_invert<T>(G, colk, perm, &piv_s, pc.status);
     const T* Dinv = (const T*)pc.D0inv + tb * kTileN * kTileN;
     const double sinv = 1.0 / pc.scale[tb];
     constexpr int CPX = sizeof(T) == 16 ? 2 : 1;
     float* out = delta + tb * kTileN * kTileN * CPX;
     for (int idx = threadIdx.x; idx < kTileN * kTileN; idx += 256) {
-        const int li = idx / kTileN, lj = idx % kTileN;
-        const int64_t gi = slot_dof(op.S, pc.nt, tb, li), gj = slot_dof(op.S, pc.nt, tb, lj);
-        T d = zero<T>();
-        if (gi >= 0 && gj >= 0) {
-            // row of g_i in N(b)
-            const int w2 = N.j2b - N.j2a;
-            const int j1 = (int)((gi / op.S.nb) % op.S.nb), j2 = (int)(gi % op.S.nb);
-            const int row = (j1 - N.j1a) * w2 + (j2 - N.j2a);
-            d = M[(int64_t)row * nc + n + lj] - Dinv[idx];
-        }
+        const int i = idx / kTileN, j = idx % kTileN;
+        T x = zero<T>();
+        for (int k = 0; k < kTileN; ++k) x += G[i][k] * DH[k * kTileN + j];
+        const T d = x - Dinv[idx];
         if constexpr (CPX == 2) {
             const cdbl c = *(const cdbl*)&d;
             out[2 * idx] = (float)(c.re * sinv);
@@ -555,13 +526,13 @@ static int64_t nbhd_max(int ring) {
 size_t prec_target_bytes(const OpDev& op, int ring, int64_t ntiles_per_launch) {
     const int64_t n = nbhd_max(ring);
     const size_t sc = op.cplx ? 16 : 8;
-    return (size_t)ntiles_per_launch * n * (n + kTileN) * sc;
+    return (size_t)ntiles_per_launch * (n + kTileN) * kTileN * sc;
 }
 
 hipError_t launch_prec_targets(const OpDev& op, const PrecDev& pc, int ring, int64_t t0, int64_t nt, void* work,
                                float* delta, hipStream_t st) {
     if (ring < 0 || ring > 8 || nt <= 0) return hipErrorInvalidValue;
-    const int64_t n = nbhd_max(ring), ws = n * (n + kTileN);
+    const int64_t n = nbhd_max(ring), ws = (n + kTileN) * kTileN;
     if (op.cplx)
         hipLaunchKernelGGL(kp_targets<cdbl>, dim3((unsigned)nt), dim3(256), 0, st, op, pc, ring, t0, (cdbl*)work, ws,
                            delta);

@@ -85,17 +85,27 @@ def test_exact_preconditioner_converges_in_one_step(orc):
 
 
 def test_targets(orc):
-    # ring 0: N(b) = b, so C_b = D_b^{-1}
+    # ring 0: N(b) = b, so the least-squares inverse is D_b^{-1}
     S, H = _h2(orc, orc.SPHERE, (), orc.HELMHOLTZ, 2.5, 2, 1, 4, 1.6, 1)
     bj = orc.BlockJacobi(H, tile=3)
     for k in (0, 3):
         C = bj.target(k, 0)
         assert np.max(np.abs(C - np.linalg.inv(bj.block(k)))) <= 1e-10 * np.max(np.abs(C))
-    # one patch, dense mode, a ring that covers the patch: C_b = (A^{-1})[b, b]
-    S, H = _h2(orc, orc.FLAT, (1.0,), orc.LAPLACE, 0.0, 2, 1, 3, 0.0, 0)  # nb = 5: tiles 3 and 2
-    bj = orc.BlockJacobi(H, tile=3)
-    Ainv = np.linalg.inv(S.dense(8, 8))
-    for k in range(bj.ntiles):
-        _, dofs = bj.tile(k)
-        C = bj.target(k, 8)
-        assert np.max(np.abs(C - Ainv[np.ix_(dofs, dofs)])) <= 1e-9 * np.max(np.abs(Ainv))
+    # ring 2: numpy's least-squares solution of A[N(b), b] X = I[N(b), b] from the near field
+    rowptr, col, val = H.near_csr()
+    nb = 5
+    for k in (0, 4, 8):
+        (f, a1, b1, a2, b2), dofs = bj.tile(k)
+        nbh = [(f * nb + j1) * nb + j2 for j1 in range(max(0, a1 - 2), min(nb, b1 + 2))
+               for j2 in range(max(0, a2 - 2), min(nb, b2 + 2))]
+        Anb = np.zeros((len(nbh), len(dofs)), dtype=complex)
+        for i, g in enumerate(nbh):
+            cols = col[rowptr[g]:rowptr[g + 1]]
+            for j, h in enumerate(dofs):
+                hit = np.nonzero(cols == h)[0]
+                if hit.size:
+                    Anb[i, j] = val[rowptr[g] + hit[0]]
+        I = np.array([[1.0 if g == h else 0.0 for h in dofs] for g in nbh])
+        X = np.linalg.lstsq(Anb, I, rcond=None)[0]
+        C = bj.target(k, 2)
+        assert np.max(np.abs(C - X)) <= 1e-9 * np.max(np.abs(X)), k

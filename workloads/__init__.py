@@ -37,6 +37,17 @@ CONFIGS = {
     ),
 }
 
+CONFIGS[3] = dict(
+    name="batched_uneven_ellipsoid_torus_512",
+    ninst=512, levels=(2, 3, 4, 5), degrees=(1, 2), kappa_range=(1.0, 8.0), nrhs_range=(1, 16),
+    semiaxes=(0.5, 2.0), torus_R=1.0, torus_r=(0.2, 0.5), q=5, eta=1.6,
+)
+CONFIGS[4] = dict(
+    name="learned_precond_ellipsoid_torus_L5_d2_helmholtz",
+    level=5, degree=2, kappa_range=(4.0, 20.0), semiaxes=(0.5, 2.0), torus_R=1.0, torus_r=(0.2, 0.5),
+    q=5, eta=1.6, tol=1e-8, restart=30, maxit=2000, ring=2,
+)
+
 GEOM_KIND = {"sphere": 0, "ellipsoid": 1, "torus": 2, "flat": 3}
 PDE_KIND = {"laplace": 0, "helmholtz": 1}
 
@@ -126,3 +137,54 @@ def sample_rows(config_index: int, n: int, nrows: int) -> np.ndarray:
     rows.update({0, n - 1})
     return np.array(sorted(rows), dtype=np.int64)
 
+
+
+def shape_draw(g: np.random.Generator, cfg: dict):
+    """Ellipsoid (semi-axes uniform) or torus (R fixed, r uniform), 50/50."""
+    if g.uniform() < 0.5:
+        a = g.uniform(*cfg["semiaxes"], size=3)
+        return GEOM_KIND["ellipsoid"], tuple(float(v) for v in a)
+    return GEOM_KIND["torus"], (float(cfg["torus_R"]), float(g.uniform(*cfg["torus_r"])))
+
+
+def c4_instances(n: int, stream: int = 0, kappa_range=None):
+    """Instances of the learned-preconditioner family: (geom, params, kappa) with kappa
+    uniform in the configured range (or kappa_range); stream 0 trains, other streams are
+    held out."""
+    cfg = CONFIGS[4]
+    g = rng(4, stream)
+    out = []
+    for _ in range(n):
+        geom, prm = shape_draw(g, cfg)
+        out.append((geom, prm, float(g.uniform(*(kappa_range or cfg["kappa_range"])))))
+    return out
+
+
+def c3_instances(n: int | None = None):
+    """Instances of the batched uneven workload: geometry, level, degree, PDE, wavenumber,
+    number of right-hand sides, and one interior point source per right-hand side."""
+    cfg = CONFIGS[3]
+    n = cfg["ninst"] if n is None else n
+    g = rng(3)
+    out = []
+    for _ in range(n):
+        geom, prm = shape_draw(g, cfg)
+        L = int(g.choice(cfg["levels"]))
+        d = int(g.choice(cfg["degrees"]))
+        helm = bool(g.uniform() < 0.5)
+        kappa = float(g.uniform(*cfg["kappa_range"])) if helm else 0.0
+        nrhs = int(g.integers(cfg["nrhs_range"][0], cfg["nrhs_range"][1] + 1))
+        srcs = []
+        for _ in range(nrhs):
+            if geom == GEOM_KIND["ellipsoid"]:
+                u = unit_vectors(g, 1)[0] * g.uniform() ** (1 / 3)
+                srcs.append(tuple(0.5 * np.array(prm) * u))
+            else:
+                R, r = prm
+                phi = g.uniform(0, 2 * np.pi)
+                rho = 0.5 * r * np.sqrt(g.uniform())
+                th = g.uniform(0, 2 * np.pi)
+                rr = R + rho * np.cos(th)
+                srcs.append((rr * np.cos(phi), rr * np.sin(phi), rho * np.sin(th)))
+        out.append(dict(geom=geom, params=prm, level=L, degree=d, pde=1 if helm else 0, kappa=kappa, sources=srcs))
+    return out
