@@ -328,6 +328,34 @@ int bem_mlp_adam(int64_t n, float* params_dev, const float* grad_dev, float* m_d
 /* Destroys the operator (its workspace stays with the caller). */
 void bem_operator_destroy(bem_operator A);
 
+/* ---- many operators in one launch per stage, and captured launch sequences -----------
+ * A group binds columns of several assembled operators (uneven sizes, the same PDE kind and
+ * q) so that y = A x for all of them runs as one launch per matvec stage (five launches in
+ * all) instead of several launches per operator and column.  Each bound column gets its
+ * own scratch, so the group does not disturb the operators' own applies. */
+typedef struct bem_group_s* bem_group;
+
+/* ncols[i] >= 1 columns of ops[i]; all assembled, all Laplace or all Helmholtz, one q.
+ * *ws_bytes: device workspace bem_group_bind needs. */
+int bem_group_create(int nops, const bem_operator* ops, const int* ncols, bem_group* out, size_t* ws_bytes);
+/* Binds the columns: x_cols, y_cols are host arrays of sum(ncols) device pointers (column c
+ * of operator i at position ncols[0] + ... + ncols[i-1] + c), each an N_i-vector; y must not
+ * overlap x.  ws: device workspace of >= ws_bytes (caller-owned).  Synchronises the stream. */
+int bem_group_bind(bem_group G, void* ws, size_t ws_bytes, const void* const* x_cols, void* const* y_cols,
+                   hipStream_t stream);
+/* y = A x for every bound column (FP64), five launches on `stream`, nothing else (capturable). */
+int bem_group_apply(bem_group G, hipStream_t stream);
+void bem_group_destroy(bem_group G);
+
+/* Stream capture of a sequence of library calls that only launch kernels (bem_apply,
+ * bem_apply_ex, bem_group_apply, bem_precond_apply) into a HIP graph, replayed with one
+ * launch.  Between begin and end nothing may synchronise the stream. */
+typedef struct bem_graph_s* bem_graph;
+int bem_capture_begin(hipStream_t stream);
+int bem_capture_end(hipStream_t stream, bem_graph* out);
+int bem_graph_launch(bem_graph g, hipStream_t stream);
+void bem_graph_destroy(bem_graph g);
+
 /* ---- introspection for parity checks (host copies; each synchronises the stream) ----- */
 
 /* Near field in CSR form: rowptr (N+1, int64), col (nnz, int32), val (nnz scalars).

@@ -215,3 +215,59 @@ class Operator:
         xx = x.contiguous()
         C.bem_export_moments(self.h, xx.data_ptr(), m.ctypes.data, _stream())
         return m
+
+
+class Group:
+    """Columns of several operators (same PDE kind and q) applied with one launch per
+    matvec stage.  xs, ys: lists of (ncols_i, N_i) tensors (contiguous rows = columns)."""
+
+    def __init__(self, ops, xs, ys):
+        self.ops = list(ops)
+        ncols = [int(x.reshape(-1, op.ndof).shape[0]) for op, x in zip(self.ops, xs)]
+        self.h, nbytes = C.bem_group_create([op.h for op in self.ops], ncols)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=_dev())
+        xp, yp = [], []
+        for op, x, y in zip(self.ops, xs, ys):
+            xx, yy = x.reshape(-1, op.ndof), y.reshape(-1, op.ndof)
+            assert xx.is_contiguous() and yy.is_contiguous()
+            for c in range(xx.shape[0]):
+                xp.append(xx[c].data_ptr())
+                yp.append(yy[c].data_ptr())
+        self.xs, self.ys = xs, ys  # keep the bound buffers alive
+        C.bem_group_bind(self.h, self.ws.data_ptr(), nbytes, xp, yp, _stream())
+
+    def apply(self):
+        C.bem_group_apply(self.h, _stream())
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            C.bem_group_destroy(self.h)
+            self.h = None
+
+
+class Graph:
+    """Stream capture of library calls (kernel launches only), replayed with one launch.
+    Usage: g = Graph(); with g: ...calls...; g.launch()."""
+
+    def __init__(self):
+        self.h = None
+
+    def __enter__(self):
+        C.bem_capture_begin(_stream())
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = C.bem_capture_end(_stream())
+        if et is None:
+            self.h = h
+        else:
+            C.bem_graph_destroy(h)
+        return False
+
+    def launch(self):
+        C.bem_graph_launch(self.h, _stream())
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            C.bem_graph_destroy(self.h)
+            self.h = None

@@ -84,6 +84,14 @@ _SIGNATURES = {
     "bem_precond_targets": (_c_int, [_vp, _c_int, _c_i64, _c_i64, _vp, _c_sz, _vp, _vp]),
     "bem_precond_correct": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _vp]),
     "bem_precond_select": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_sz, _P(_c_int), _P(_c_dbl), _vp]),
+    "bem_group_create": (_c_int, [_c_int, _P(_vp), _P(_c_int), _P(_vp), _P(_c_sz)]),
+    "bem_group_bind": (_c_int, [_vp, _vp, _c_sz, _P(_vp), _P(_vp), _vp]),
+    "bem_group_apply": (_c_int, [_vp, _vp]),
+    "bem_group_destroy": (None, [_vp]),
+    "bem_capture_begin": (_c_int, [_vp]),
+    "bem_capture_end": (_c_int, [_vp, _P(_vp)]),
+    "bem_graph_launch": (_c_int, [_vp, _vp]),
+    "bem_graph_destroy": (None, [_vp]),
     "bem_mlp_sizes": (_c_int, [_c_int, _c_int, _c_int, _c_int, _P(_c_i64), _P(_c_sz)]),
     "bem_mlp_init": (_c_int, [_c_int, _c_int, _c_int, ctypes.c_uint64, _vp, _vp]),
     "bem_mlp_forward": (_c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _c_int, _vp, _c_sz, _vp]),
@@ -313,3 +321,42 @@ def bem_mlp_loss_grad(n_in, hidden, out, batch, is_complex, params_ptr, x_ptr, t
 
 def bem_mlp_adam(n, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream):
     check(lib.bem_mlp_adam(n, params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream))
+
+
+def bem_group_create(ops, ncols):
+    n = len(ops)
+    h = _vp()
+    b = _c_sz()
+    check(lib.bem_group_create(n, (_vp * n)(*ops), (_c_int * n)(*ncols), ctypes.byref(h), ctypes.byref(b)))
+    return h.value, b.value
+
+
+def bem_group_bind(G: int, ws_ptr: int, ws_bytes: int, x_ptrs, y_ptrs, stream: int):
+    n = len(x_ptrs)
+    check(lib.bem_group_bind(G, ws_ptr, ws_bytes, (_vp * n)(*x_ptrs), (_vp * n)(*y_ptrs), stream))
+
+
+def bem_group_apply(G: int, stream: int):
+    check(lib.bem_group_apply(G, stream))
+
+
+def bem_group_destroy(G: int):
+    lib.bem_group_destroy(G)
+
+
+def bem_capture_begin(stream: int):
+    check(lib.bem_capture_begin(stream))
+
+
+def bem_capture_end(stream: int) -> int:
+    g = _vp()
+    check(lib.bem_capture_end(stream, ctypes.byref(g)))
+    return g.value
+
+
+def bem_graph_launch(g: int, stream: int):
+    check(lib.bem_graph_launch(g, stream))
+
+
+def bem_graph_destroy(g: int):
+    lib.bem_graph_destroy(g)

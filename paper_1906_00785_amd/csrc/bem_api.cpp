@@ -1310,6 +1310,165 @@ int bem_mlp_adam(int64_t n, float* params_dev, const float* grad_dev, float* m_d
     return BEM_OK;
 }
 
+// ------------------------------------------------------------------------------ groups
+}  // extern "C"
+
+struct bem_group_s {
+    std::vector<bem_operator> ops;
+    std::vector<int> ncols;
+    int cplx = 0, q = 0;
+    int64_t napply = 0;
+    size_t ws_bytes = 0;
+    std::vector<OpDev> host_ops;
+    std::vector<int64_t> prefix;
+    std::vector<const void*> xs;
+    std::vector<void*> ys;
+    GroupDev dev{};
+    bool bound = false;
+};
+
+// group workspace: tables (OpDev per apply, x and y pointers, stage prefixes), then per
+// apply the one-column scratch (moments, local expansions, chunk sums, transposed products)
+static size_t group_layout(bem_group_s& G, char* base, std::vector<OpDev>* ops) {
+    Bump b(base);
+    const size_t n = (size_t)G.napply;
+    OpDev* d_ops = b.take<OpDev>(n);
+    const void** d_x = b.take<const void*>(n);
+    void** d_y = b.take<void*>(n);
+    int64_t* d_pre = b.take<int64_t>((size_t)kGroupStages * (n + 1));
+    if (ops) ops->clear();
+    for (size_t i = 0; i < G.ops.size(); ++i) {
+        const bem_operator_s& A = *G.ops[i];
+        const Plan& p = A.plan;
+        for (int c = 0; c < G.ncols[i]; ++c) {
+            OpDev o = A.dev;
+            o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+            o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+            o.partial = b.take<char>(p.ch_t.size() * p.q2 * A.scal);
+            o.P = b.take<char>((size_t)p.ptotal * A.scal);
+            if (ops) ops->push_back(o);
+        }
+    }
+    if (base) {
+        G.dev.ops = d_ops;
+        G.dev.x = d_x;
+        G.dev.y = d_y;
+        G.dev.prefix = d_pre;
+    }
+    return b.off + 256;
+}
+
+extern "C" {
+
+int bem_group_create(int nops, const bem_operator* ops, const int* ncols, bem_group* out, size_t* ws_bytes) {
+    if (!ops || !ncols || !out || !ws_bytes || nops < 1) return fail(BEM_EINVAL, "NULL argument or nops < 1");
+    bem_group_s* G = new (std::nothrow) bem_group_s;
+    if (!G) return fail(BEM_ENOMEM, "host allocation failed");
+    for (int i = 0; i < nops; ++i) {
+        if (!ops[i] || !ops[i]->assembled || ncols[i] < 1) {
+            delete G;
+            return fail(BEM_EINVAL, "every operator must be assembled and have >= 1 column");
+        }
+        const int c = ops[i]->cplx ? 1 : 0, q = ops[i]->plan.P.q;
+        if (i == 0) {
+            G->cplx = c;
+            G->q = q;
+        } else if (c != G->cplx || q != G->q) {
+            delete G;
+            return fail(BEM_EINVAL, "a group's operators share the PDE kind and q");
+        }
+        G->ops.push_back(ops[i]);
+        G->ncols.push_back(ncols[i]);
+        G->napply += ncols[i];
+    }
+    G->ws_bytes = group_layout(*G, nullptr, nullptr);
+    *ws_bytes = G->ws_bytes;
+    *out = G;
+    return BEM_OK;
+}
+
+int bem_group_bind(bem_group G, void* ws, size_t ws_bytes, const void* const* x_cols, void* const* y_cols,
+                   hipStream_t stream) {
+    if (!G || !ws || !x_cols || !y_cols) return fail(BEM_EINVAL, "NULL argument");
+    if (ws_bytes < G->ws_bytes) return fail(BEM_ENOMEM, "workspace too small");
+    char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    group_layout(*G, base, &G->host_ops);
+    const size_t n = (size_t)G->napply;
+    G->xs.assign(x_cols, x_cols + n);
+    G->ys.assign(y_cols, y_cols + n);
+    for (size_t a = 0; a < n; ++a)
+        if (!G->xs[a] || !G->ys[a]) return fail(BEM_EINVAL, "NULL column pointer");
+    G->prefix.assign((size_t)kGroupStages * (n + 1), 0);
+    for (size_t a = 0; a < n; ++a) {
+        int64_t nb[kGroupStages];
+        group_stage_blocks(G->host_ops[a], nb);
+        for (int s = 0; s < kGroupStages; ++s) G->prefix[s * (n + 1) + a + 1] = G->prefix[s * (n + 1) + a] + nb[s];
+    }
+    G->dev.napply = G->napply;
+    for (int s = 0; s < kGroupStages; ++s) {
+        G->dev.nblocks[s] = G->prefix[s * (n + 1) + n];
+        if (G->dev.nblocks[s] > 0x7fffffff) return fail(BEM_EUNSUPPORTED, "too many blocks in one launch");
+    }
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.ops, G->host_ops.data(), n * sizeof(OpDev), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.x, G->xs.data(), n * sizeof(void*), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.y, G->ys.data(), n * sizeof(void*), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.prefix, G->prefix.data(), G->prefix.size() * 8, hipMemcpyHostToDevice,
+                             stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    G->bound = true;
+    return BEM_OK;
+}
+
+int bem_group_apply(bem_group G, hipStream_t stream) {
+    if (!G) return fail(BEM_EINVAL, "NULL argument");
+    if (!G->bound) return fail(BEM_EINVAL, "group not bound");
+    HIP_CHECK(launch_group_apply(G->dev, G->cplx, G->q, stream));
+    return BEM_OK;
+}
+
+void bem_group_destroy(bem_group G) { delete G; }
+
+// ------------------------------------------------------------------------------ graphs
+}  // extern "C"
+
+struct bem_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~bem_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" {
+
+int bem_capture_begin(hipStream_t stream) {
+    HIP_CHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    return BEM_OK;
+}
+
+int bem_capture_end(hipStream_t stream, bem_graph* out) {
+    if (!out) return fail(BEM_EINVAL, "NULL argument");
+    bem_graph_s* g = new (std::nothrow) bem_graph_s;
+    if (!g) return fail(BEM_ENOMEM, "host allocation failed");
+    hipError_t e = hipStreamEndCapture(stream, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(BEM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return BEM_OK;
+}
+
+int bem_graph_launch(bem_graph g, hipStream_t stream) {
+    if (!g || !g->exec) return fail(BEM_EINVAL, "NULL graph");
+    HIP_CHECK(hipGraphLaunch(g->exec, stream));
+    return BEM_OK;
+}
+
+void bem_graph_destroy(bem_graph g) { delete g; }
+
 // ------------------------------------------------------------------------------ exports
 int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, hipStream_t stream) {
     if (!A) return fail(BEM_EINVAL, "NULL argument");

@@ -123,6 +123,24 @@ hipError_t launch_cast_low(const OpDev& op, hipStream_t st);
 // moments of all clusters for x (forward + upward) into op.mom
 hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st);
 
+// Many operators and columns in one launch per stage: apply a runs the one-column stages
+// of ops[a] (its own scratch) on x[a] -> y[a].  Stages: 0 near field + forward/upward
+// inside subtrees, 1 upper levels of the upward pass, 2 coupling, 3 gather of the local
+// expansions, 4 downward + backward.  prefix[s * (napply + 1) + a] = first block of apply a
+// in stage s's launch; nblocks[s] = blocks of that launch.  All operators share the scalar
+// type and q.
+constexpr int kGroupStages = 5;
+struct GroupDev {
+    int64_t napply;
+    const OpDev* ops;
+    const void* const* x;
+    void* const* y;
+    const int64_t* prefix;
+    int64_t nblocks[kGroupStages];
+};
+void group_stage_blocks(const OpDev& op, int64_t out[kGroupStages]);
+hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st);
+
 // load vector (one RHS) and potential (one RHS)
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,
                       void* b, hipStream_t st);

@@ -498,12 +498,12 @@ __device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict_
 // Stage 0b.  Upper levels of one patch's tree (levels up_root-1 .. 0), one block per
 // patch, level by level from the moments written by stage 0.
 template <class T, int Q>
-__global__ __launch_bounds__(256) void k_up_top(OpDev op) {
+__device__ inline void up_top_body(const OpDev& op, int64_t blk_) {
     constexpr int Q2 = Q * Q;
     __shared__ double Es[2 * Q * Q];
     for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
     T* mom = (T*)op.mom;
-    const int f = blockIdx.x;
+    const int f = blk_;
     for (int lev = op.up_root - 1; lev >= 0; --lev) {
         __syncthreads();
         const int n = 1 << lev, nc = n * n;
@@ -526,6 +526,11 @@ __global__ __launch_bounds__(256) void k_up_top(OpDev op) {
             mom[(op.lev_off[lev] + (int64_t)f * nc + loc) * Q2 + a] = acc;
         }
     }
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_up_top(OpDev op) {
+    up_top_body<T, Q>(op, blockIdx.x);
 }
 
 // rows of one near-field row group (R <= RMAX rows sharing C columns), see k_near_up.
@@ -565,16 +570,16 @@ __device__ inline void near_group_rows(const int32_t* __restrict__ col, const T*
 }
 
 template <class T, int Q>
-__global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+__device__ inline void near_up_body(const OpDev& op, int64_t blk_, const T* __restrict__ x, T* __restrict__ y) {
     const int nup = op.S.geom.npatch << (2 * op.up_root);
-    if ((int)blockIdx.x < nup) {
-        up_subtree<T, Q>(op, blockIdx.x, x);
+    if ((int)blk_ < nup) {
+        up_subtree<T, Q>(op, blk_, x);
         return;
     }
     // near-field product of one row group: every lane takes columns c, c+64, ...; per
     // step it issues 4 column indices, then the 4 gathers of x, then the values of all the
     // group's rows (row-major, so each row's loads are coalesced across the wave)
-    const int64_t G = (int64_t)(blockIdx.x - nup) * 4 + uniform_int(threadIdx.x >> 6);
+    const int64_t G = (int64_t)(blk_ - nup) * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (G >= op.ngroups) return;
     const int64_t rb = op.grp_rowptr[G];
@@ -588,6 +593,11 @@ __global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__
         near_group_rows<T, 4>(col, val, x, y, op.grp_rows + rb, R, C, lane);
     else
         near_group_rows<T, kGroupRowsDev>(col, val, x, y, op.grp_rows + rb, R, C, lane);
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    near_up_body<T, Q>(op, blockIdx.x, x, y);
 }
 
 template <class T>
@@ -615,9 +625,9 @@ __device__ inline Pair<cdbl> load_stream(const cdbl* p) {
 // (K^T m_owner) of its columns, stored once per column.  Row sums are reduce-scattered
 // across the wave into the chunk's partial sums.
 template <class T, int Q>
-__global__ __launch_bounds__(256) void k_coupling(OpDev op) {
+__device__ inline void coupling_body(const OpDev& op, int64_t blk_) {
     constexpr int Q2 = Q * Q;
-    const int64_t c = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int64_t c = (int64_t)blk_ * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (c >= op.nchunks) return;
     const int t = op.ch_t[c], k0 = op.ch_k0[c], k1 = op.ch_k1[c];
@@ -656,6 +666,11 @@ __global__ __launch_bounds__(256) void k_coupling(OpDev op) {
     bool ok;
     wave_reduce_scatter<T, Q2>(acc, lane, idx, ok);
     if (ok) ((T*)op.partial)[c * Q2 + idx] = acc[0];
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_coupling(OpDev op) {
+    coupling_body<T, Q>(op, blockIdx.x);
 }
 
 
@@ -752,10 +767,10 @@ __global__ __launch_bounds__(256) void k_coupling_low(OpDev op) {
 // products of the blocks stored in its partners' rows.  One wave per cluster; the two
 // half-waves take alternate entries (lane & 31 = component), then add.
 template <class T, int Q>
-__global__ __launch_bounds__(256) void k_lv_gather(OpDev op) {
+__device__ inline void lv_gather_body(const OpDev& op, int64_t blk_) {
     constexpr int Q2 = Q * Q;
     static_assert(Q2 <= 64, "q <= 8");
-    const int64_t t = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int64_t t = (int64_t)blk_ * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (t >= op.ncl) return;
     const T* __restrict__ partial = (const T*)op.partial;
@@ -781,20 +796,25 @@ __global__ __launch_bounds__(256) void k_lv_gather(OpDev op) {
     }
 }
 
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_lv_gather(OpDev op) {
+    lv_gather_body<T, Q>(op, blockIdx.x);
+}
+
 // Stage 2b + 3.  Downward transfer and backward transform per tile of TxT leaves: every
 // leaf of the tile and of a one-leaf halo gets its total local expansion along its
 // ancestor chain (v_0 = lv(patch), v_l = (E_b1 (x) E_b2) v_{l-1} + lv(ancestor at level
 // l)) in LDS; then every DOF whose first B-spline lies in the tile adds
 // sum over its leaves of (V_tau^T v_tau) to y.
 template <class T, int Q>
-__global__ __launch_bounds__(256) void k_down_back(OpDev op, T* __restrict__ y) {
+__device__ inline void down_back_body(const OpDev& op, int64_t blk_, T* __restrict__ y) {
     constexpr int Q2 = Q * Q;
     constexpr int TMAX = 4, HW = TMAX + 2;  // tile and tile + halo (leaves per direction)
     __shared__ double Es[2 * Q * Q];
     __shared__ T vbuf[2][HW * HW][Q2];
     for (int i = threadIdx.x; i < 2 * Q * Q; i += blockDim.x) Es[i] = op.E[i];
     const int T1 = op.tile, n1 = op.nleaf1, nt = n1 / T1;
-    const int f = blockIdx.x / (nt * nt), loc = blockIdx.x % (nt * nt);
+    const int f = blk_ / (nt * nt), loc = blk_ % (nt * nt);
     const int ti = (loc / nt) * T1, tj = (loc % nt) * T1;
     // halo-extended leaf range, clamped to the patch
     const int i0 = max(ti - 1, 0), i1 = min(ti + T1, n1 - 1), j0 = max(tj - 1, 0), j1 = min(tj + T1, n1 - 1);
@@ -852,6 +872,11 @@ __global__ __launch_bounds__(256) void k_down_back(OpDev op, T* __restrict__ y) 
             }
         y[dof_id(op.S, f, jj1, jj2)] += acc;
     }
+}
+
+template <class T, int Q>
+__global__ __launch_bounds__(256) void k_down_back(OpDev op, T* __restrict__ y) {
+    down_back_body<T, Q>(op, blockIdx.x, y);
 }
 
 // ------------------------------------------------------------------ load vector and potential
@@ -936,6 +961,62 @@ __global__ __launch_bounds__(256) void k_potential(SpaceDesc S, BasisTab bt, Gau
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) u[p] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ------------------------------------------------------------------ grouped launches
+// apply of block b: the largest a < napply with prefix[a] <= b (empty applies skipped)
+__device__ inline int64_t group_find(const int64_t* pre, int64_t napply, int64_t b) {
+    int64_t lo = 0, hi = napply;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <class T, int Q, int S>
+__global__ __launch_bounds__(256) void kg_stage(GroupDev g) {
+    const int64_t* pre = g.prefix + (int64_t)S * (g.napply + 1);
+    const int64_t a = group_find(pre, g.napply, blockIdx.x);
+    const int64_t blk = (int64_t)blockIdx.x - pre[a];
+    const OpDev& op = g.ops[a];
+    if constexpr (S == 0)
+        near_up_body<T, Q>(op, blk, (const T*)g.x[a], (T*)g.y[a]);
+    else if constexpr (S == 1)
+        up_top_body<T, Q>(op, blk);
+    else if constexpr (S == 2)
+        coupling_body<T, Q>(op, blk);
+    else if constexpr (S == 3)
+        lv_gather_body<T, Q>(op, blk);
+    else
+        down_back_body<T, Q>(op, blk, (T*)g.y[a]);
+}
+
+template <class T, int Q>
+hipError_t group_tq(const GroupDev& g, hipStream_t st) {
+    if (g.nblocks[0] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 0>), dim3((unsigned)g.nblocks[0]), dim3(256), 0, st, g);
+    if (g.nblocks[1] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 1>), dim3((unsigned)g.nblocks[1]), dim3(256), 0, st, g);
+    if (g.nblocks[2] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 2>), dim3((unsigned)g.nblocks[2]), dim3(256), 0, st, g);
+    if (g.nblocks[3] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 3>), dim3((unsigned)g.nblocks[3]), dim3(256), 0, st, g);
+    if (g.nblocks[4] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 4>), dim3((unsigned)g.nblocks[4]), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t group_t(const GroupDev& g, int q, hipStream_t st) {
+    switch (q) {
+        case 1: return group_tq<T, 1>(g, st);
+        case 2: return group_tq<T, 2>(g, st);
+        case 3: return group_tq<T, 3>(g, st);
+        case 4: return group_tq<T, 4>(g, st);
+        case 5: return group_tq<T, 5>(g, st);
+        case 6: return group_tq<T, 6>(g, st);
+        case 7: return group_tq<T, 7>(g, st);
+        default: return group_tq<T, 8>(g, st);
+    }
 }
 
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1098,6 +1179,21 @@ hipError_t launch_cast_low(const OpDev& op, hipStream_t st) {
     if (n == 0 || op.low == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cast_low, dim3(nblk(n, 256)), dim3(256), 0, st, n, (const double*)op.K, op.Klow, op.low);
     return hipGetLastError();
+}
+
+// blocks of each grouped stage for one operator (the one-column launch shapes)
+void group_stage_blocks(const OpDev& op, int64_t out[kGroupStages]) {
+    out[0] = ((int64_t)op.S.geom.npatch << (2 * op.up_root)) + (op.ngroups + 3) / 4;
+    out[1] = op.up_root > 0 ? op.S.geom.npatch : 0;
+    out[2] = op.nchunks > 0 ? (op.nchunks + 3) / 4 : 0;
+    out[3] = op.nstored > 0 ? (op.ncl + 3) / 4 : 0;
+    const int64_t nt = op.nleaf1 / op.tile;
+    out[4] = op.nstored > 0 ? (int64_t)op.S.geom.npatch * nt * nt : 0;
+}
+
+hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st) {
+    if (g.napply <= 0) return hipSuccess;
+    return cplx ? group_t<cdbl>(g, q, st) : group_t<double>(g, q, st);
 }
 
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,
