@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the many-RHS Helmholtz workload")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched uneven workload")
+    ap.add_argument("--c3-instances", type=int, default=512)
+    ap.add_argument("--no-c4", action="store_true", help="skip the learned-preconditioner workload")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner on the main workload")
     ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
     return ap.parse_args()
 
@@ -131,6 +135,124 @@ def bench_c2(B, W, torch, np, stream, args):
             print(f"bench c2: {name} {t:.3f}s its {min(its)}..{max(its)} converged {out[name]['converged']}/{R} "
                   f"max relres {res:.2e}", file=sys.stderr, flush=True)
     return out
+
+
+def bench_c3(B, W, torch, np, args):
+    """Batched uneven instances: per-instance applies vs one grouped launch per stage vs one
+    graph launch for the whole batch (every instance, every right-hand side, FP64)."""
+    insts = W.c3_instances(args.c3_instances)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    members = {0: [], 1: []}
+    for it in insts:
+        g = B.Geometry(it["geom"], it["params"])
+        s = B.Space(g, it["pde"], it["kappa"], degree=it["degree"], level=it["level"])
+        A = B.Operator(s, q=W.CONFIGS[3]["q"], eta=W.CONFIGS[3]["eta"], leaf_level=max(it["level"] - 2, 0))
+        x = s.rhs(B.BEM_DATA_POINT_SOURCE, it["sources"])
+        members[it["pde"]].append((s, A, x, torch.empty_like(x)))
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    dofrhs = sum(s.ndof * x.shape[0] for m in members.values() for s, _, x, _ in m)
+    groups = [B.Group([A for _, A, _, _ in m], [x for _, _, x, _ in m], [y for _, _, _, y in m])
+              for m in members.values() if m]
+    side = torch.cuda.Stream()
+    reps = 5
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def per_instance():
+        for m in members.values():
+            for s, A, x, y in m:
+                A.apply(x, out=y)
+
+    def grouped():
+        for G in groups:
+            G.apply()
+
+    t_each = timed(per_instance)
+    t_group = timed(grouped)
+    with torch.cuda.stream(side):
+        graph = B.Graph()
+        with graph:
+            grouped()
+        t_graph = timed(graph.launch)
+    torch.cuda.synchronize()
+    nrhs = sum(x.shape[0] for m in members.values() for _, _, x, _ in m)
+    out = {"workload": W.CONFIGS[3]["name"], "instances": len(insts), "columns": nrhs, "dof_rhs": dofrhs,
+           "assembly_s": t_asm, "per_instance_ms": t_each, "grouped_ms": t_group, "graph_ms": t_graph,
+           "dof_rhs_per_s_graph": dofrhs / (t_graph * 1e-3), "dof_rhs_per_s_per_instance": dofrhs / (t_each * 1e-3),
+           "launches_grouped": 5 * len(groups)}
+    print(f"bench c3: {len(insts)} instances, {nrhs} columns, {dofrhs} DOF*RHS; assembly {t_asm:.1f}s; matvec "
+          f"per-instance {t_each:.2f} ms, grouped {t_group:.2f} ms, graph {t_graph:.2f} ms "
+          f"({dofrhs/(t_graph*1e-3):.3e} DOF*RHS/s)", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_c4(B, W, torch, np, args):
+    """Learned block-Jacobi correction: train on solver-generated targets of the family,
+    compare preconditioned GMRES to 1e-8 (plain block-Jacobi vs learned with fallback) on
+    held-out instances.  Level 4 and the resolved wavenumber range (see the tests)."""
+    import paper_1906_00785_amd.learned as L
+
+    cfg = W.CONFIGS[4]
+    level, krange = 4, (4.0, 8.0)
+
+    def op_of(inst):
+        geom, prm, kappa = inst
+        g = B.Geometry(geom, prm)
+        s = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, kappa, degree=cfg["degree"], level=level)
+        A = B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=level - 2)
+        A.precond_build()
+        return s, A
+
+    t0 = time.perf_counter()
+    feats, targs = [], []
+    for inst in W.c4_instances(8, stream=0, kappa_range=krange):
+        s, A = op_of(inst)
+        f, t = L.training_data(A, ring=cfg["ring"])
+        feats.append(f)
+        targs.append(t)
+    X, T = torch.cat(feats), torch.cat(targs)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = L.CorrectionNet(cplx=True, hidden=256, seed=1906, precision=1)
+    t0 = time.perf_counter()
+    losses = net.train(X, T, steps=600, batch=64, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rows = []
+    for inst in W.c4_instances(3, stream=1, kappa_range=krange):
+        s, A = op_of(inst)
+        b = s.rhs(B.BEM_DATA_PLANE_WAVE, W.unit_vectors(W.rng(4, 103), 1))
+        res = {}
+        for name, pc in (("none", False), ("block_jacobi", True)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, st = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], precond=pc)
+            torch.cuda.synchronize()
+            res[name] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1]}
+        t1 = time.perf_counter()
+        kept, rr = L.install(A, net, b, restart=cfg["restart"])
+        _, st = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], precond=True)
+        torch.cuda.synchronize()
+        res["learned"] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1],
+                          "kept": kept, "cycle_relres_plain_learned": rr}
+        rows.append({"instance": [inst[0], list(inst[1]), inst[2]], **res})
+        print(f"bench c4: {inst}: none {res['none']['iterations']} its, block-Jacobi "
+              f"{res['block_jacobi']['iterations']} its, learned {res['learned']['iterations']} its "
+              f"(kept {kept})", file=sys.stderr, flush=True)
+    return {"workload": cfg["name"], "level": level, "kappa_range": list(krange), "train_blocks": int(X.shape[0]),
+            "data_s": t_data, "train_s": t_train, "train_steps": 600,
+            "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:])), "held_out": rows}
 
 
 def main():
@@ -262,6 +384,15 @@ def main():
     extra["mixed"] = mixed
     if not args.no_c2:
         extra["many_rhs"] = bench_c2(B, W, torch, np, stream, args)
+    if not args.no_c3:
+        extra["batched_uneven"] = bench_c3(B, W, torch, np, args)
+    if not args.no_c4:
+        extra["learned_precond"] = bench_c4(B, W, torch, np, args)
+    if args.tune:
+        import paper_1906_00785_amd.autotune as AT
+
+        extra["autotune"] = AT.tune(s, q=cfg["q"], eta=cfg["eta"], steps=20)
+        print(f"bench: autotune {extra['autotune']['table']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -53,6 +53,7 @@ class Space:
     def __init__(self, geom: Geometry, kernel: int = BEM_LAPLACE_SINGLE, kappa: complex = 0.0, degree: int = 1,
                  knot_repetition: int = 1, level: int = 0):
         self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level)
+        self.geom = geom
         self.kernel, self.kappa, self.degree, self.level = kernel, complex(kappa), degree, level
         self.ndof = C.bem_space_ndof(self.h)
         self.dtype = torch.complex128 if kernel == BEM_HELMHOLTZ_SINGLE else torch.float64
