@@ -143,10 +143,14 @@ def bench_c2(B, W, torch, np, stream, args):
               f"{st_ms[0]:.3f}/{st_ms[1]:.3f}/{st_ms[2]:.3f}/{st_ms[3]:.3f} ms; coupling "
               f"{flops/(st_ms[1]*1e-3)/1e12:.1f} TFLOP/s useful", file=sys.stderr, flush=True)
     if not args.no_gmres:
-        for name, op, refine in (("gmres_fp64", A16, False), ("gmres_fp32_refined", A32, True)):
+        A16.precond_build()
+        A32.precond_build()
+        for name, op, refine, pc in (("gmres_fp64", A16, False, False), ("gmres_fp32_refined", A32, True, False),
+                                     ("gmres_fp64_block_jacobi", A16, False, True),
+                                     ("gmres_fp32_refined_block_jacobi", A32, True, True)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x, st = op.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=refine)
+            x, st = op.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=refine, precond=pc)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             its = [v[0] for v in st]
@@ -400,6 +404,18 @@ def main():
         perr = float(np.max(np.abs(u - ex)) / np.max(np.abs(ex)))
         extra["gmres"] = {"time_to_tol_s": t_solve, "iterations": it, "converged": ok, "relres": rr,
                           "tol": cfg["tol"], "restart": cfg["restart"], "potential_max_rel_err": perr}
+        # block-Jacobi right preconditioning (build included in the time)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.precond_build()
+        rho_p, stp = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], precond=True)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
+        rr_true = float(((b[0] - A.apply(rho_p[0])).norm() / b[0].norm()))
+        extra["gmres_block_jacobi"] = {"time_to_tol_s": t_p, "iterations": stp[0][0], "converged": stp[0][1],
+                                       "relres": rr_true}
+        print(f"bench: block-Jacobi GMRES {stp[0][0]} its {t_p:.3f}s (build included) relres {rr_true:.2e}",
+              file=sys.stderr, flush=True)
         print(f"bench: GMRES {it} its {t_solve:.3f}s relres {rr:.2e} potential err {perr:.2e}", file=sys.stderr,
               flush=True)
         for name, op in (("fp32", A), ("bf16", A16)):
