@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <string>
 #include <vector>
@@ -71,7 +72,9 @@ struct bem_operator_s {
     std::vector<int32_t> touch_lp;
     std::vector<int64_t> fb_off;  // host copies of the per-pair block table (kept until destroy,
     std::vector<int32_t> fb_rs;   // the uploads above are asynchronous)
-    std::vector<int32_t> gsel;
+    // dense near-field tiles of the many-RHS path (see BatchDev)
+    std::vector<int64_t> tile_rowptr, tile_colptr, tile_voff;
+    std::vector<int32_t> tile_rows, tile_cols;
     OpDev dev{};
     size_t scal = 8;  // bytes per scalar
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
@@ -138,7 +141,15 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
         const size_t np = p.far_t.size();
         BatchDev bd{};
         bd.rmax = A.batch_rhs;
-        bd.gsel = b.take<int32_t>(p.grp_rowptr.size() - 1);
+        bd.ntiles = (int64_t)A.tile_rowptr.size() - 1;
+        bd.tile_rowptr = b.take<int64_t>(A.tile_rowptr.size());
+        bd.tile_rows = b.take<int32_t>(A.tile_rows.size());
+        bd.tile_colptr = b.take<int64_t>(A.tile_colptr.size());
+        bd.tile_cols = b.take<int32_t>(A.tile_cols.size());
+        bd.tile_voff = b.take<int64_t>(A.tile_voff.size());
+        bd.tile_val = b.take<char>((size_t)A.tile_voff.back() * A.scal);
+        bd.row_grp = b.take<int32_t>(p.row_grp.size());
+        bd.row_pos = b.take<int32_t>(p.row_pos.size());
         bd.far_rowptr = b.take<int64_t>(p.far_rowptr.size());
         bd.far_s = b.take<int32_t>(np);
         bd.fb_off = b.take<int64_t>(np);
@@ -798,6 +809,33 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     A->far_low = p->far_low;
     A->batch_rhs = p->batch_rhs > 1 ? p->batch_rhs : 0;
     const Plan& pl = A->plan;
+    if (A->batch_rhs > 1) {
+        // dense near-field tiles: rows of 4 x 4 blocks of B-spline indices, columns the union
+        // of their patterns, values padded to whole steps of 4 columns (64 per step)
+        const int nb = pl.S.nb, nbt = (nb + 3) / 4;
+        A->tile_rowptr.assign(1, 0);
+        A->tile_colptr.assign(1, 0);
+        A->tile_voff.assign(1, 0);
+        std::vector<int32_t> uni, tmp;
+        for (int f = 0; f < pl.S.geom.npatch; ++f)
+            for (int a1 = 0; a1 < nbt; ++a1)
+                for (int a2 = 0; a2 < nbt; ++a2) {
+                    uni.clear();
+                    for (int j1 = 4 * a1; j1 < std::min(4 * a1 + 4, nb); ++j1)
+                        for (int j2 = 4 * a2; j2 < std::min(4 * a2 + 4, nb); ++j2) {
+                            const int64_t g = dof_id(pl.S, f, j1, j2);
+                            A->tile_rows.push_back((int32_t)g);
+                            tmp.clear();
+                            std::set_union(uni.begin(), uni.end(), pl.col.begin() + pl.rowptr[g],
+                                           pl.col.begin() + pl.rowptr[g + 1], std::back_inserter(tmp));
+                            uni.swap(tmp);
+                        }
+                    A->tile_cols.insert(A->tile_cols.end(), uni.begin(), uni.end());
+                    A->tile_rowptr.push_back((int64_t)A->tile_rows.size());
+                    A->tile_colptr.push_back((int64_t)A->tile_cols.size());
+                    A->tile_voff.push_back(A->tile_voff.back() + (int64_t)((uni.size() + 3) / 4) * 64);
+                }
+    }
     for (size_t lp = 0; lp + 1 < pl.touch_rowptr.size(); ++lp)
         if (pl.touch_rowptr[lp + 1] > pl.touch_rowptr[lp]) A->touch_lp.push_back((int32_t)lp);
     bem_operator_info& I = A->info;
@@ -930,14 +968,14 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
             A->fb_off[i] = p.koff[owner] + slot * p.q2;
             A->fb_rs[i] = owner == t ? p.krs[owner] : -p.krs[owner];
         }
-        const int64_t ng = (int64_t)p.grp_rowptr.size() - 1;
-        A->gsel.clear();
-        for (int64_t G = 0; G < ng; ++G)
-            if (p.grp_rowptr[G + 1] - p.grp_rowptr[G] <= 4) A->gsel.push_back((int32_t)G);
-        bd.nsmall = (int64_t)A->gsel.size();
-        for (int64_t G = 0; G < ng; ++G)
-            if (p.grp_rowptr[G + 1] - p.grp_rowptr[G] > 4) A->gsel.push_back((int32_t)G);
-        HIP_CHECK(up(bd.gsel, A->gsel.data(), ng * 4));
+        HIP_CHECK(up(bd.tile_rowptr, A->tile_rowptr.data(), A->tile_rowptr.size() * 8));
+        HIP_CHECK(up(bd.tile_rows, A->tile_rows.data(), A->tile_rows.size() * 4));
+        HIP_CHECK(up(bd.tile_colptr, A->tile_colptr.data(), A->tile_colptr.size() * 8));
+        HIP_CHECK(up(bd.tile_cols, A->tile_cols.data(), A->tile_cols.size() * 4));
+        HIP_CHECK(up(bd.tile_voff, A->tile_voff.data(), A->tile_voff.size() * 8));
+        HIP_CHECK(up(bd.row_grp, p.row_grp.data(), p.row_grp.size() * 4));
+        HIP_CHECK(up(bd.row_pos, p.row_pos.data(), p.row_pos.size() * 4));
+        HIP_CHECK(launch_tile_fill(d, bd, stream));
         HIP_CHECK(up(bd.far_rowptr, p.far_rowptr.data(), p.far_rowptr.size() * 8));
         HIP_CHECK(up(bd.far_s, p.far_s.data(), np * 4));
         HIP_CHECK(up(bd.fb_off, A->fb_off.data(), np * 8));

@@ -27,8 +27,18 @@ struct BatchDev {
     const int32_t* far_s;       // source of each ordered pair
     const int64_t* fb_off;      // first scalar of the block (row 0) in K
     const int32_t* fb_rs;       // row stride of the stored rows; negative: stored transposed
-    const int32_t* gsel;        // near-field row groups: those of <= 4 rows first, then the others
-    int64_t nsmall;             // number of groups of <= 4 rows
+    // near field as dense tiles for the matrix cores: rows of a 4 x 4 block of B-spline
+    // indices of a patch, columns the union of their patterns; values in FP64 MFMA
+    // fragment order (per step of 4 columns, lane l: row l % 16, column 4 step + l / 16)
+    int64_t ntiles;
+    const int64_t* tile_rowptr;  // [ntiles + 1] into tile_rows
+    const int32_t* tile_rows;
+    const int64_t* tile_colptr;  // [ntiles + 1] into tile_cols
+    const int32_t* tile_cols;
+    const int64_t* tile_voff;    // [ntiles + 1] first value (multiple of 64)
+    void* tile_val;
+    const int32_t* row_grp;      // near-field row group and position of every row
+    const int32_t* row_pos;
     void* xs;                   // [N][R] input slab
     void* ys;                   // [N][R] output slab
     void* mom;                  // [ncl][q2][R] moments
@@ -59,6 +69,8 @@ hipError_t launch_apply_batched_stage(const OpDev& op, const BatchDev& bd, int s
 // column-major (leading dimension ld) <-> slab [N][R]
 hipError_t launch_to_slab(int cplx, int64_t N, int R, const void* x, int64_t ldx, void* xs, hipStream_t st);
 hipError_t launch_from_slab(int cplx, int64_t N, int R, const void* ys, void* y, int64_t ldy, hipStream_t st);
+// dense near-field tile values (assembly, after the near field)
+hipError_t launch_tile_fill(const OpDev& op, const BatchDev& bd, hipStream_t st);
 // BF16 fragments of every ordered far block (assembly, after the coupling blocks)
 hipError_t launch_build_bf_blocks(const OpDev& op, const BatchDev& bd, int64_t npairs, hipStream_t st);
 

@@ -15,8 +15,6 @@ namespace bem {
 
 namespace {
 
-constexpr int kGroupRowsB = 16;  // rows per near-field row group at most (host: kGroupRows)
-
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -487,67 +485,113 @@ __global__ __launch_bounds__(256) void kb_leaf_back(OpDev op, BatchDev bd) {
 }
 
 // ------------------------------------------------------------------ near field + output
-// One block per (row group, 64 right-hand sides); the four waves split the group's
-// columns into four ranges.  Column indices and values are the same for the whole wave
-// (uniform loads through the scalar cache); per U columns a wave issues the U gathers
-// x[h][r] (coalesced across the wave) before it updates the rows of the group.  The
-// four partial row sums are added in wave order in LDS; then each row adds the backward
-// transforms of the leaves that meet its B-spline and is written to ys.  Groups of at
-// most 4 rows and larger ones run as separate launches (list gsel).
-template <class T, int RMAX, int U>
-__global__ __launch_bounds__(256) void kb_near(OpDev op, BatchDev bd, int64_t g0, int64_t ng) {
-    __shared__ T red[RMAX][kBatchChunk];
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// value of the near field at (g, h), 0 outside the pattern (binary search in row g)
+template <class T>
+__device__ inline T near_at(const OpDev& op, const BatchDev& bd, int64_t g, int64_t h) {
+    const int64_t b = op.rowptr[g], e = op.rowptr[g + 1];
+    int64_t lo = b, hi = e;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (op.col[mid] < h)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo >= e || op.col[lo] != h) return zero<T>();
+    const int64_t G = bd.row_grp[g];
+    return ((const T*)op.val)[op.grp_voff[G] + (int64_t)bd.row_pos[g] * (e - b) + (lo - b)];
+}
+
+// dense tile values in fragment order (assembly; one block per tile)
+template <class T>
+__global__ __launch_bounds__(256) void kb_tile_fill(OpDev op, BatchDev bd) {
+    const int64_t t = blockIdx.x;
+    const int64_t rb = bd.tile_rowptr[t], cb = bd.tile_colptr[t];
+    const int nr = (int)(bd.tile_rowptr[t + 1] - rb), C = (int)(bd.tile_colptr[t + 1] - cb);
+    const int64_t v0 = bd.tile_voff[t], nv = bd.tile_voff[t + 1] - v0;
+    T* out = (T*)bd.tile_val + v0;
+    for (int64_t idx = threadIdx.x; idx < nv; idx += blockDim.x) {
+        const int l = (int)(idx % kWave);
+        const int row = l % 16, kc = (int)(idx / kWave) * 4 + l / 16;
+        out[idx] = (row < nr && kc < C) ? near_at<T>(op, bd, bd.tile_rows[rb + row], bd.tile_cols[cb + kc]) : zero<T>();
+    }
+}
+
+// Near field on the matrix cores (v_mfma_f64_16x16x4f64): one block per (tile, 64
+// right-hand sides), wave w takes 16 of them.  Per step of 4 columns, lane l holds the tile
+// value A[l % 16][l / 16] and x[column l / 16][rhs l % 16]; a complex product is four real
+// products (Re, Im of A times Re, Im of x).  The fragments of the next step are loaded
+// before the products of the current one.  Epilogue: lane l holds rows l / 16 + 4 i,
+// right-hand side l % 16; each adds the backward transforms of the leaves that meet its
+// B-spline and is written to ys.
+template <class T>
+__global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
+    constexpr bool CP = sizeof(T) == 16;
     const int nch = nchunks(bd.R);
+    const int64_t t = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t G = bd.gsel[g0 + blockIdx.x / nch];
-    const int ch = (int)(blockIdx.x % nch);
-    const int R = bd.R, r = ch * kBatchChunk + lane;
+    const int R = bd.R;
+    const int rb_n = ch * kBatchChunk + 16 * w;  // first right-hand side of this wave
+    const int r = rb_n + (lane & 15);
     const bool on = r < R;
-    const int64_t rb = op.grp_rowptr[G];
-    const int Rg = (int)(op.grp_rowptr[G + 1] - rb);
-    const int32_t* rows = op.grp_rows + rb;
-    const int64_t first = rows[0];
-    const int64_t cb = op.rowptr[first];
-    const int C = (int)(op.rowptr[first + 1] - cb);
-    const int32_t* __restrict__ col = op.col + cb;
-    const T* __restrict__ val = (const T*)op.val + op.grp_voff[G];
-    const T* __restrict__ xs = (const T*)bd.xs + r;
-    const int c0 = (C * w) >> 2, c1 = (C * (w + 1)) >> 2;
-    T acc[RMAX];
-#pragma unroll
-    for (int q = 0; q < RMAX; ++q) acc[q] = zero<T>();
-    for (int c = c0; c < c1; c += U) {
-        T xv[U];
-#pragma unroll
-        for (int uu = 0; uu < U; ++uu) {
-            const int h = col[c + uu < c1 ? c + uu : c0];
-            xv[uu] = on ? xs[(int64_t)h * R] : zero<T>();
+    const int64_t rb = bd.tile_rowptr[t], cb = bd.tile_colptr[t];
+    const int nr = (int)(bd.tile_rowptr[t + 1] - rb), C = (int)(bd.tile_colptr[t + 1] - cb);
+    const int nsteps = (C + 3) / 4;
+    const T* __restrict__ val = (const T*)bd.tile_val + bd.tile_voff[t] + lane;
+    const int32_t* __restrict__ cols = bd.tile_cols + cb;
+    const T* __restrict__ xs = (const T*)bd.xs;
+    const int kk = lane >> 4;
+    f64x4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int step, T& a, T& xv) {
+        a = val[(int64_t)step * kWave];
+        const int kc = step * 4 + kk;
+        const int64_t h = cols[kc < C ? kc : 0];
+        xv = on ? xs[h * R + r] : zero<T>();
+    };
+    T a, xv;
+    if (nsteps > 0) load(0, a, xv);
+    for (int step = 0; step < nsteps; ++step) {
+        T an, xn;
+        if (step + 1 < nsteps) load(step + 1, an, xn);
+        if constexpr (CP) {
+            const cdbl ac = *(const cdbl*)&a, xc = *(const cdbl*)&xv;
+            ar = mfma64(ac.re, xc.re, ar);
+            ar = mfma64(-ac.im, xc.im, ar);
+            ai = mfma64(ac.re, xc.im, ai);
+            ai = mfma64(ac.im, xc.re, ai);
+        } else {
+            ar = mfma64(*(const double*)&a, *(const double*)&xv, ar);
         }
-#pragma unroll
-        for (int uu = 0; uu < U; ++uu)
-            if (c + uu < c1)
-#pragma unroll
-                for (int q = 0; q < RMAX; ++q)
-                    if (q < Rg) acc[q] += val[(int64_t)q * C + c + uu] * xv[uu];
+        if (step + 1 < nsteps) {
+            a = an;
+            xv = xn;
+        }
     }
-    for (int step = 0; step < 4; ++step) {
-        if (w == step)
-#pragma unroll
-            for (int q = 0; q < RMAX; ++q)
-                if (q < Rg) red[q][lane] = step == 0 ? acc[q] : red[q][lane] + acc[q];
-        __syncthreads();
-    }
-    if (w != 0 || !on) return;
+    if (!on) return;
     const SpaceDesc& S = op.S;
     const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * S.r, nb = S.nb;
     const T* __restrict__ yl = (const T*)bd.yl;
-    for (int q = 0; q < Rg; ++q) {
-        const int64_t g = rows[q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = kk + 4 * i;  // v_mfma_f64_16x16x4f64: lane l holds rows l / 16 + 4 i
+        if (q >= nr) continue;
+        const int64_t g = bd.tile_rows[rb + q];
         const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
         int lo1, hi1, lo2, hi2;
         leaf_range(j1, stride, nloc, n1, lo1, hi1);
         leaf_range(j2, stride, nloc, n1, lo2, hi2);
-        T sum = red[q][lane];
+        T sum;
+        if constexpr (CP)
+            *(cdbl*)&sum = cdbl{ar[i], ai[i]};
+        else
+            *(double*)&sum = ar[i];
         for (int li = lo1; li <= hi1; ++li)
             for (int lj = lo2; lj <= hi2; ++lj) {
                 const int64_t l = ((int64_t)f * n1 + li) * n1 + lj;
@@ -595,14 +639,7 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
         }
         hipLaunchKernelGGL((kb_leaf_back<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
     } else {
-        constexpr int US = sizeof(T) == 16 ? 8 : 16, UB = sizeof(T) == 16 ? 4 : 8;
-        if (bd.nsmall > 0)
-            hipLaunchKernelGGL((kb_near<T, 4, US>), dim3((unsigned)(bd.nsmall * nch)), dim3(256), 0, st, op, bd,
-                               (int64_t)0, bd.nsmall);
-        const int64_t nbig = op.ngroups - bd.nsmall;
-        if (nbig > 0)
-            hipLaunchKernelGGL((kb_near<T, kGroupRowsB, UB>), dim3((unsigned)(nbig * nch)), dim3(256), 0, st, op, bd,
-                               bd.nsmall, nbig);
+        hipLaunchKernelGGL(kb_near_mfma<T>, dim3((unsigned)(bd.ntiles * nch)), dim3(256), 0, st, op, bd);
         if (y)
             hipLaunchKernelGGL(kb_from_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R,
                                (const T*)bd.ys, (T*)y, ldy);
@@ -668,6 +705,15 @@ hipError_t launch_from_slab(int cplx, int64_t N, int R, const void* ys, void* y,
         hipLaunchKernelGGL(kb_from_slab<cdbl>, g, dim3(256), 0, st, N, R, (const cdbl*)ys, (cdbl*)y, ldy);
     else
         hipLaunchKernelGGL(kb_from_slab<double>, g, dim3(256), 0, st, N, R, (const double*)ys, (double*)y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_fill(const OpDev& op, const BatchDev& bd, hipStream_t st) {
+    if (bd.ntiles == 0) return hipSuccess;
+    if (op.cplx)
+        hipLaunchKernelGGL(kb_tile_fill<cdbl>, dim3((unsigned)bd.ntiles), dim3(256), 0, st, op, bd);
+    else
+        hipLaunchKernelGGL(kb_tile_fill<double>, dim3((unsigned)bd.ntiles), dim3(256), 0, st, op, bd);
     return hipGetLastError();
 }
 
