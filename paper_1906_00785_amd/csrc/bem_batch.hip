@@ -147,14 +147,18 @@ __global__ __launch_bounds__(256) void kb_upward(OpDev op, BatchDev bd, int lev)
         const int b1 = c4 >> 1, b2 = c4 & 1;
         const int64_t c = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
         const T* mc = mom + c * Q2 * R + r;
-#pragma unroll 1
+        // all of the child's moments first (independent loads), then the transfer
+        T mall[Q2];
+#pragma unroll
+        for (int p = 0; p < Q2; ++p) mall[p] = on ? mc[(int64_t)p * R] : zero<T>();
+#pragma unroll
         for (int p1 = 0; p1 < Q; ++p1) {
             T in[Q];
 #pragma unroll
             for (int a2 = 0; a2 < Q; ++a2) in[a2] = zero<T>();
 #pragma unroll
             for (int p2 = 0; p2 < Q; ++p2) {
-                const T mv = on ? mc[(int64_t)(p1 * Q + p2) * R] : zero<T>();
+                const T mv = mall[p1 * Q + p2];
 #pragma unroll
                 for (int a2 = 0; a2 < Q; ++a2) in[a2] += E[(b2 * Q + p2) * Q + a2] * mv;
             }
@@ -424,14 +428,17 @@ __global__ __launch_bounds__(256) void kb_downward(OpDev op, BatchDev bd, int le
     T acc[Q2];
 #pragma unroll
     for (int p = 0; p < Q2; ++p) acc[p] = vc[(int64_t)p * R];
-#pragma unroll 1
+    T vall[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) vall[a] = vp[(int64_t)a * R];
+#pragma unroll
     for (int a1 = 0; a1 < Q; ++a1) {
         T in[Q];
 #pragma unroll
         for (int p2 = 0; p2 < Q; ++p2) in[p2] = zero<T>();
 #pragma unroll
         for (int a2 = 0; a2 < Q; ++a2) {
-            const T v = vp[(int64_t)(a1 * Q + a2) * R];
+            const T v = vall[a1 * Q + a2];
 #pragma unroll
             for (int p2 = 0; p2 < Q; ++p2) in[p2] += E[(b2 * Q + p2) * Q + a2] * v;
         }
@@ -526,8 +533,8 @@ __global__ __launch_bounds__(256) void kb_tile_fill(OpDev op, BatchDev bd) {
 // Near field on the matrix cores (v_mfma_f64_16x16x4f64): one block per (tile, 64
 // right-hand sides), wave w takes 16 of them.  Per step of 4 columns, lane l holds the tile
 // value A[l % 16][l / 16] and x[column l / 16][rhs l % 16]; a complex product is four real
-// products (Re, Im of A times Re, Im of x).  The fragments of the next step are loaded
-// before the products of the current one.  Epilogue: lane l holds rows l / 16 + 4 i,
+// products (Re, Im of A times Re, Im of x).  Four steps' fragments are loaded before their
+// products.  Epilogue: lane l holds rows l / 16 + 4 i,
 // right-hand side l % 16; each adds the backward transforms of the leaves that meet its
 // B-spline and is written to ys.
 template <class T>
@@ -549,29 +556,33 @@ __global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
     const T* __restrict__ xs = (const T*)bd.xs;
     const int kk = lane >> 4;
     f64x4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int step, T& a, T& xv) {
-        a = val[(int64_t)step * kWave];
-        const int kc = step * 4 + kk;
-        const int64_t h = cols[kc < C ? kc : 0];
-        xv = on ? xs[h * R + r] : zero<T>();
-    };
-    T a, xv;
-    if (nsteps > 0) load(0, a, xv);
-    for (int step = 0; step < nsteps; ++step) {
-        T an, xn;
-        if (step + 1 < nsteps) load(step + 1, an, xn);
-        if constexpr (CP) {
-            const cdbl ac = *(const cdbl*)&a, xc = *(const cdbl*)&xv;
-            ar = mfma64(ac.re, xc.re, ar);
-            ar = mfma64(-ac.im, xc.im, ar);
-            ai = mfma64(ac.re, xc.im, ai);
-            ai = mfma64(ac.im, xc.re, ai);
-        } else {
-            ar = mfma64(*(const double*)&a, *(const double*)&xv, ar);
+    // DEPTH steps per round: all their column indices, then all value and x loads, then
+    // the products (steps past the end carry zero values and a valid column)
+    constexpr int DEPTH = 4;
+    for (int s0 = 0; s0 < nsteps; s0 += DEPTH) {
+        int64_t h[DEPTH];
+        T a[DEPTH], xv[DEPTH];
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int kc = (s0 + u) * 4 + kk;
+            h[u] = cols[kc < C ? kc : 0];
         }
-        if (step + 1 < nsteps) {
-            a = an;
-            xv = xn;
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            a[u] = s0 + u < nsteps ? val[(int64_t)(s0 + u) * kWave] : zero<T>();
+            xv[u] = on ? xs[h[u] * R + r] : zero<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            if constexpr (CP) {
+                const cdbl ac = *(const cdbl*)&a[u], xc = *(const cdbl*)&xv[u];
+                ar = mfma64(ac.re, xc.re, ar);
+                ar = mfma64(-ac.im, xc.im, ar);
+                ai = mfma64(ac.re, xc.im, ai);
+                ai = mfma64(ac.im, xc.re, ai);
+            } else {
+                ar = mfma64(*(const double*)&a[u], *(const double*)&xv[u], ar);
+            }
         }
     }
     if (!on) return;
