@@ -83,7 +83,8 @@ typedef struct bem_h2_params {
     int leaf_level;   /* cluster-tree leaf level, 0..L; -1 picks max(L-2, 0)             */
     int qg;           /* Gauss points per direction on each element of a regular pair   */
     int qs;           /* Gauss points per dimension of each Duffy cube (touching pairs)  */
-    int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 128     */
+    int chunk_cols;   /* coupling columns per work chunk, a multiple of 128; 0 = 128 (256
+                         with far_eval)                                                 */
     int far_low;      /* extra low-precision copy of the coupling blocks for mixed-precision
                          applies and solves: 0 none, BEM_PREC_FP32 or BEM_PREC_BF16      */
     int batch_rhs;    /* right-hand sides per batched apply: with batch_rhs > 1 the operator
@@ -91,7 +92,12 @@ typedef struct bem_h2_params {
                          bem_apply_ex with nrhs > 1 run the many-RHS kernels on up to
                          batch_rhs columns per pass (q <= 6; BEM_PREC_BF16 there needs
                          q <= 5 and uses the matrix cores); 0 or 1: one column at a time */
-    int reserved[1];  /* must be zero */
+    int far_eval;     /* 1: no stored coupling blocks; every apply evaluates the kernel at the
+                         clusters' Chebyshev points where the blocks are used (same entries
+                         as the stored blocks, Sec. 4: the coupling matrices are the kernel
+                         sampled at the interpolation points).  Needs far_low = 0 and
+                         batch_rhs <= 1; bem_export_far then returns BEM_EUNSUPPORTED.
+                         0: blocks computed once at assembly and stored               */
 } bem_h2_params;
 
 /* arithmetic of the far-field coupling in bem_apply_ex / refined solves */

@@ -87,11 +87,14 @@ class Operator:
     """Compressed single-layer operator: plan on the host, assemble on the GPU."""
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
-                 assemble: bool = True, chunk_cols: int = 0, far_low: int = 0, batch_rhs: int = 0):
+                 assemble: bool = True, chunk_cols: int = 0, far_low: int = 0, batch_rhs: int = 0,
+                 far_eval: bool = False):
         self.space = space
         self.far_low = far_low
         self.batch_rhs = batch_rhs
-        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs)
+        self.far_eval = bool(far_eval)
+        self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs,
+                                                int(far_eval))
         self.q = q
         self.ndof = self.info.ndof
         self.op_ws = None

@@ -79,6 +79,7 @@ struct bem_operator_s {
     size_t scal = 8;  // bytes per scalar
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
     int batch_rhs = 0;  // columns per many-RHS pass (slabs in the operator workspace)
+    bool far_eval = false;  // coupling evaluated in every apply (no stored blocks)
     BatchDev bdev{};
     // block preconditioner (bem_precond_*)
     bool prec_built = false;
@@ -118,7 +119,10 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
     o.own_src = b.take<int32_t>(p.own_src.size());
     o.koff = b.take<int64_t>(p.koff.size());
     o.krs = b.take<int32_t>(p.krs.size());
-    o.K = b.take<char>((size_t)p.ktotal * A.scal);
+    o.K = A.far_eval ? nullptr : b.take<char>((size_t)p.ktotal * A.scal);
+    o.otf = A.far_eval ? 1 : 0;
+    o.otf_wide = p.P.chunk >= 512 ? 1 : 0;
+    o.xc = A.far_eval ? b.take<double>((size_t)p.ncl * p.q2 * 3) : nullptr;
     o.pcol = b.take<int64_t>(p.pcol.size());
     o.P = b.take<char>((size_t)p.ptotal * A.scal);
     o.tr_rowptr = b.take<int64_t>(p.tr_rowptr.size());
@@ -780,12 +784,14 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
 
 int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
-    if (p->reserved[0] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    if (p->far_eval != 0 && p->far_eval != 1) return fail(BEM_EINVAL, "far_eval must be 0 or 1");
+    if (p->far_eval && (p->far_low != 0 || p->batch_rhs > 1))
+        return fail(BEM_EUNSUPPORTED, "far_eval needs far_low = 0 and batch_rhs <= 1");
     if (p->far_low < 0 || p->far_low > 2) return fail(BEM_EINVAL, "far_low must be 0, BEM_PREC_FP32 or BEM_PREC_BF16");
     if (p->batch_rhs < 0 || p->batch_rhs > 4096) return fail(BEM_EINVAL, "batch_rhs must lie in [0, 4096]");
     if (p->batch_rhs > 1 && p->q > 6) return fail(BEM_EUNSUPPORTED, "many-RHS kernels need q <= 6");
     H2Params P;
-    P.chunk = p->chunk_cols == 0 ? 128 : p->chunk_cols;
+    P.chunk = p->chunk_cols != 0 ? p->chunk_cols : (p->far_eval ? 256 : 128);
     P.q = p->q;
     P.eta = p->eta;
     P.leaf = p->leaf_level;
@@ -808,6 +814,7 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     A->scal = A->cplx ? 16 : 8;
     A->far_low = p->far_low;
     A->batch_rhs = p->batch_rhs > 1 ? p->batch_rhs : 0;
+    A->far_eval = p->far_eval == 1;
     const Plan& pl = A->plan;
     if (A->batch_rhs > 1) {
         // dense near-field tiles: rows of 4 x 4 blocks of B-spline indices, columns the union
@@ -848,7 +855,7 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     I.leaf_level = pl.leaf;
     I.op_bytes = op_layout(*A, nullptr, nullptr);
     I.tmp_bytes = tmp_layout(*A, nullptr, nullptr);
-    I.far_bytes = (double)pl.ktotal * A->scal;
+    I.far_bytes = A->far_eval ? 0.0 : (double)pl.ktotal * A->scal;
     I.near_bytes = (double)pl.col.size() * (A->scal + 4) + (double)pl.rowptr.size() * 8;
     I.nstored = (int64_t)pl.own_src.size();
     I.nchunks = (int64_t)pl.ch_t.size();
@@ -883,6 +890,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     BatchDev bd{};
     op_layout(*A, ob, &d, &bd);
     tmp_layout(*A, tb, &as);
+    if (A->far_eval) as.xc = const_cast<double*>(d.xc);  // the cluster points stay with the operator
     d.S = p.S;
     d.bt = A->sp->bt;
     d.q = p.P.q;
@@ -946,7 +954,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(as.cheb, p.cheb.data(), p.cheb.size() * 8));
     HIP_CHECK(up(as.own_t, p.own_t.data(), p.own_t.size() * 4));
     // coupling rows are padded to even length: clear them before the blocks are written
-    if (p.ktotal > 0) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
+    if (p.ktotal > 0 && d.K) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
     HIP_CHECK(launch_gauss_points(d, as, stream));
     HIP_CHECK(launch_near_regular(d, as, stream));
     HIP_CHECK(launch_near_singular(d, as, stream));
@@ -1539,6 +1547,7 @@ int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t s
             pairs[2 * i] = p.far_t[i];
             pairs[2 * i + 1] = p.far_s[i];
         }
+    if (blocks && A->far_eval) return fail(BEM_EUNSUPPORTED, "no stored coupling blocks (far_eval)");
     if (blocks && nf > 0) {
         std::vector<char> K((size_t)p.ktotal * A->scal);
         HIP_CHECK(hipMemcpyAsync(K.data(), A->dev.K, K.size(), hipMemcpyDeviceToHost, stream));

@@ -68,6 +68,11 @@ struct OpDev {
     void* Klow;                // optional low-precision copy of K (same layout), see low
     int low;                   // 0 none, 1 FP32, 2 BF16
     int64_t ktotal_scalars;    // real scalars in K (2 per complex entry)
+    // coupling evaluated in every apply instead of stored (K unused): the clusters'
+    // Chebyshev points on the surface, [ncl][q2][3]
+    int otf;
+    int otf_wide;  // chunks of at least 512 columns (8 real columns per lane and pass)
+    const double* xc;
     // transforms
     const double* V1;  // [nleaf1][q][nloc]
     const double* E;   // [2][q][q]

@@ -668,9 +668,144 @@ __device__ inline void coupling_body(const OpDev& op, int64_t blk_) {
     if (ok) ((T*)op.partial)[c * Q2 + idx] = acc[0];
 }
 
+// 1/r for NS values r^2 > 0 (finite).  From the hardware estimate y (relative error
+// about 5e-8), e = 1 - r^2 y^2 and the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// give y (1 + e/2 + 3e^2/8), whose truncation error (5e^3/16) lies far below FP64
+// rounding; the NS chains are interleaved step by step.
+template <int NS>
+__device__ inline void rinv_nr(const double* r2, double* y) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) y[u] = __builtin_amdgcn_rsq(r2[u]);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const double e = __builtin_fma(-(r2[u] * y[u]), y[u], 1.0);
+        const double c = __builtin_fma(e, 0.375, 0.5);
+        y[u] = __builtin_fma(y[u] * e, c, y[u]);
+    }
+}
+
+// the single-layer kernel without its constant factor 1/(4 pi), at NS distances r^2 > 0
+template <int NS>
+__device__ inline void kernel_unscaled(const KernelDesc&, const double* r2, double* kv) {
+    rinv_nr<NS>(r2, kv);
+}
+template <int NS>
+__device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cdbl* kv) {
+    double ir[NS];
+    rinv_nr<NS>(r2, ir);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const double r = r2[u] * ir[u];
+        double sn, cs;
+        sincos(k.kre * r, &sn, &cs);
+        const double mag = k.kim != 0.0 ? ir[u] * exp(k.kim * r) : ir[u];
+        kv[u] = {mag * cs, -mag * sn};
+    }
+}
+
+// Stage 1 without stored blocks: every coupling entry is the kernel at a pair of the
+// clusters' Chebyshev points on the surface, evaluated where it is used (the stored
+// blocks hold the same values).  Same chunks, row sums and transposed products as
+// coupling_body.  Each lane takes NS columns (sigma, b) of a pass and keeps their points
+// and moments in registers.  The owner's rows a are visited G at a time (uniform points
+// and moments, scalar loads): every lane adds k * m_owner[a] to its columns' transposed
+// products, and the G row sums of the pass are reduce-scattered across the wave and
+// added to the wave's row accumulators in LDS.  Columns past the row (its padding) or the
+// chunk get a distant point and a zero moment.
+template <class T, int Q, int NS>
+__device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
+    constexpr int Q2 = Q * Q;
+    static_assert(Q2 <= kWave, "one lane per row of the owner");
+    constexpr int G = Q < 5 ? Q : 5;
+    __shared__ T racc[4][Q2];
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t c = (int64_t)blk_ * 4 + w;
+    const int lane = threadIdx.x & 63;
+    if (c >= op.nchunks) return;
+    const int t = uniform_int(op.ch_t[c]), k0 = uniform_int(op.ch_k0[c]), k1 = uniform_int(op.ch_k1[c]);
+    const int64_t beg = op.own_rowptr[t];
+    const int32_t* __restrict__ src = op.own_src + beg;
+    const int ncols = (int)(op.own_rowptr[t + 1] - beg) * Q2;  // rows are padded past this
+    const int kend = k1 < ncols ? k1 : ncols;                   // last real column of the chunk
+    const T* __restrict__ mom = (const T*)op.mom;
+    const double* __restrict__ xc = op.xc;
+    const double* __restrict__ xt = xc + (int64_t)t * Q2 * 3;
+    const T* __restrict__ mt = mom + (int64_t)t * Q2;
+    T* __restrict__ P = (T*)op.P + op.pcol[t];
+    const KernelDesc kd = op.S.ker;
+    if (lane < Q2) racc[w][lane] = zero<T>();
+    for (int kb = k0; kb < k1; kb += NS * kWave) {
+        double y0[NS], y1[NS], y2[NS];
+        T ms[NS], p[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int k = kb + u * kWave + lane;
+            p[u] = zero<T>();
+            if (k < kend) {
+                const int sl = k / Q2, b = k - sl * Q2;
+                const int64_t g = (int64_t)src[sl] * Q2 + b;
+                y0[u] = xc[3 * g];
+                y1[u] = xc[3 * g + 1];
+                y2[u] = xc[3 * g + 2];
+                ms[u] = mom[g];
+            } else {
+                y0[u] = y1[u] = y2[u] = 64.0;
+                ms[u] = zero<T>();
+            }
+        }
+#pragma unroll 1
+        for (int a0 = 0; a0 < Q2; a0 += G) {
+            T sa[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                sa[g] = zero<T>();
+                const int a = a0 + g;
+                if (Q2 % G != 0 && a >= Q2) continue;
+                const double x0 = xt[3 * a], x1 = xt[3 * a + 1], x2 = xt[3 * a + 2];
+                const T ma = mt[a];
+                double r2[NS];
+                T kv[NS];
+#pragma unroll
+                for (int u = 0; u < NS; ++u) {
+                    const double dx = x0 - y0[u], dy = x1 - y1[u], dz = x2 - y2[u];
+                    r2[u] = dx * dx + dy * dy + dz * dz;
+                }
+                kernel_unscaled<NS>(kd, r2, kv);
+#pragma unroll
+                for (int u = 0; u < NS; ++u) {
+                    sa[g] += kv[u] * ms[u];
+                    p[u] += kv[u] * ma;
+                }
+            }
+            int idx;
+            bool ok;
+            wave_reduce_scatter<T, G>(sa, lane, idx, ok);
+            if (ok && a0 + idx < Q2) racc[w][a0 + idx] += sa[0];
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int k = kb + u * kWave + lane;
+            if (k < k1) P[k] = p[u] * kInv4Pi;
+        }
+    }
+    if (lane < Q2) ((T*)op.partial)[c * Q2 + lane] = racc[w][lane] * kInv4Pi;
+}
+
+// columns per lane and pass: 8 real (2 complex), or 4 real when the chunks are
+// narrower than 512 columns
+template <class T>
+__host__ __device__ constexpr int otf_ns(bool wide) {
+    return sizeof(T) == 16 ? 2 : (wide ? 8 : 4);
+}
+
 template <class T, int Q>
 __global__ __launch_bounds__(256) void k_coupling(OpDev op) {
     coupling_body<T, Q>(op, blockIdx.x);
+}
+
+template <class T, int Q, int NS>
+__global__ __launch_bounds__(256) void k_coupling_otf(OpDev op) {
+    coupling_otf_body<T, Q, NS>(op, blockIdx.x);
 }
 
 
@@ -987,8 +1122,15 @@ __global__ __launch_bounds__(256) void kg_stage(GroupDev g) {
         near_up_body<T, Q>(op, blk, (const T*)g.x[a], (T*)g.y[a]);
     else if constexpr (S == 1)
         up_top_body<T, Q>(op, blk);
-    else if constexpr (S == 2)
-        coupling_body<T, Q>(op, blk);
+    else if constexpr (S == 2) {
+        // the operator's own pass width, so that the sums match its one-operator apply
+        if (op.otf && op.otf_wide)
+            coupling_otf_body<T, Q, otf_ns<T>(true)>(op, blk);
+        else if (op.otf)
+            coupling_otf_body<T, Q, otf_ns<T>(false)>(op, blk);
+        else
+            coupling_body<T, Q>(op, blk);
+    }
     else if constexpr (S == 3)
         lv_gather_body<T, Q>(op, blk);
     else
@@ -1095,7 +1237,7 @@ hipError_t launch_far_assemble(const OpDev& op, const AsmDev& as, hipStream_t st
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = op.nstored * op.q2 * op.q2;
-    if (n == 0) return hipSuccess;
+    if (n == 0 || op.otf) return hipSuccess;
     if (op.cplx)
         hipLaunchKernelGGL(k_far_assemble<cdbl>, dim3(nblk(n, 256)), dim3(256), 0, st, op, as);
     else
@@ -1119,7 +1261,11 @@ static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, b
             if (op.nchunks == 0) break;
             const dim3 g(nblk(op.nchunks, 4)), b(256);
             using F = typename std::conditional<std::is_same<T, double>::value, float, cflt>::type;
-            if (prec == 0)
+            if (op.otf && op.otf_wide)
+                hipLaunchKernelGGL((k_coupling_otf<T, Q, otf_ns<T>(true)>), g, b, 0, st, op);
+            else if (op.otf)
+                hipLaunchKernelGGL((k_coupling_otf<T, Q, otf_ns<T>(false)>), g, b, 0, st, op);
+            else if (prec == 0)
                 hipLaunchKernelGGL((k_coupling<T, Q>), g, b, 0, st, op);
             else if (op.low == 1)
                 hipLaunchKernelGGL((k_coupling_low<T, F, StFp32, Q>), g, b, 0, st, op);

@@ -47,6 +47,16 @@ def test_argument_validation(B):
         with pytest.raises(C.BemError) as e:
             B.Operator(s, q=q, eta=eta, leaf_level=leaf, assemble=False)
         assert e.value.code == C.BEM_EINVAL
+    # on-the-fly coupling excludes the stored low-precision copy and the many-RHS slabs
+    for kw, code in [(dict(far_eval=True, far_low=1), C.BEM_EUNSUPPORTED),
+                     (dict(far_eval=True, batch_rhs=8), C.BEM_EUNSUPPORTED)]:
+        with pytest.raises(C.BemError) as e:
+            B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False, **kw)
+        assert e.value.code == code, kw
+    Ao = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False, far_eval=True)
+    Ast = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False)
+    assert Ao.info.far_bytes == 0.0 and Ast.info.far_bytes > 0.0
+    assert Ao.info.op_bytes < Ast.info.op_bytes
     A = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False)
     with pytest.raises(C.BemError):  # not assembled yet
         C.bem_apply(A.h, 1, A.ndof, 2, A.ndof, 1, 0)

@@ -1,0 +1,163 @@
+"""GPU: the far-field coupling evaluated in every apply (no stored blocks).
+
+The coupling matrices are the kernel sampled at the clusters' Chebyshev points (Sec. 4), so
+an operator that evaluates them where they are used computes the same H^2 matvec as one that
+stores them.  Bars: against the oracle, FP64 within 1e-11 relative (max-norm over all
+entries, as the stored path); against the stored path on the same inputs, within 1e-13
+relative (only the summation order and the reciprocal square root's rounding differ); at
+the benchmark size, sampled rows against the oracle and the far field at every row;
+grouped launches over operators of both kinds bitwise equal to their own applies.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+CASES = {
+    # id: (geom, params, pde, kappa, L, d, q, leaf)
+    "sphere_L2_d1_laplace": (0, (), 0, 0.0, 2, 1, 5, 2),
+    "sphere_L3_d2_helmholtz": (0, (), 1, 2.5, 3, 2, 4, 2),
+    "torus_L2_d1_laplace_q4": (2, (1.0, 0.4), 0, 0.0, 2, 1, 4, 1),
+    "ellipsoid_L2_d2_helmholtz_cplx": (1, (0.7, 1.2, 1.6), 1, 1.5 + 0.3j, 2, 2, 4, 1),
+    "sphere_L3_d0_laplace_q8": (0, (), 0, 0.0, 3, 0, 8, 1),
+    "flat_L3_d1_laplace_q1": (3, (2.0,), 0, 0.0, 3, 1, 1, 3),
+}
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_1906_00785_amd as B
+
+    return B
+
+
+_cache = {}
+
+
+def ops(B, orc, cid):
+    if cid not in _cache:
+        geom, prm, pde, kappa, L, d, q, leaf = CASES[cid]
+        print(f"[far_eval {cid}] assemble stored and on-the-fly operators", flush=True)
+        g = B.Geometry(geom, prm)
+        s = B.Space(g, pde, kappa, degree=d, level=L)
+        Ast = B.Operator(s, q=q, eta=1.6, leaf_level=leaf)
+        Aot = B.Operator(s, q=q, eta=1.6, leaf_level=leaf, far_eval=True)
+        So = orc.Space(geom, list(prm), pde, kappa, degree=d, level=L)
+        Ho = orc.H2(So, q=q, eta=1.6, leaf=leaf)
+        _cache[cid] = (s, Ast, Aot, So, Ho)
+    return _cache[cid]
+
+
+@pytest.mark.parametrize("cid", list(CASES))
+def test_apply_matches_oracle_and_stored(B, orc, cid):
+    s, Ast, Aot, So, Ho = ops(B, orc, cid)
+    assert Aot.info.nfar > 0 and Aot.info.far_bytes == 0.0
+    x = W.random_vector(W.rng(7, 10), s.ndof, is_complex=So.complex, ncols=3).T.copy()
+    xd = torch.from_numpy(x).cuda()
+    y = Aot.apply(xd).cpu().numpy()
+    assert relerr(y, Ho.apply(x.T).T) <= TOL
+    assert relerr(y, Ast.apply(xd).cpu().numpy()) <= 1e-13
+    # deterministic, columns independent
+    assert np.array_equal(Aot.apply(xd[2]).cpu().numpy(), y[2])
+    assert np.array_equal(Aot.apply(xd).cpu().numpy(), y)
+
+
+def test_chunk_widths_agree(B, orc):
+    """Chunks of one pass, of several passes and ragged row ends give the same result."""
+    cid = "sphere_L3_d2_helmholtz"
+    s, Ast, Aot, So, Ho = ops(B, orc, cid)
+    geom, prm, pde, kappa, L, d, q, leaf = CASES[cid]
+    x = torch.from_numpy(W.random_vector(W.rng(7, 11), s.ndof, is_complex=True)).cuda()
+    y = Aot.apply(x).cpu().numpy()
+    for chunk in (128, 384, 512, 2048):
+        A = B.Operator(s, q=q, eta=1.6, leaf_level=leaf, far_eval=True, chunk_cols=chunk)
+        assert relerr(A.apply(x).cpu().numpy(), y) <= 1e-13, chunk
+
+
+def test_export_far_unsupported(B, orc):
+    s, Ast, Aot, So, Ho = ops(B, orc, "sphere_L2_d1_laplace")
+    with pytest.raises(B._bem.BemError) as e:
+        Aot.export_far()
+    assert e.value.code == B._bem.BEM_EUNSUPPORTED
+
+
+def test_solve(B, orc):
+    s, Ast, Aot, So, Ho = ops(B, orc, "sphere_L3_d2_helmholtz")
+    d = W.unit_vectors(W.rng(7, 12), 2)
+    b = s.rhs(B.BEM_DATA_PLANE_WAVE, d)
+    x, st = Aot.solve(b, tol=1e-10, restart=60, maxit=400)
+    xs, sts = Ast.solve(b, tol=1e-10, restart=60, maxit=400)
+    for k in range(2):
+        assert st[k][1] and st[k][2] <= 1e-10
+        r = (b[k] - Aot.apply(x[k])).norm() / b[k].norm()
+        assert float(r) <= 1e-10
+        # both operators define the same system: the solutions agree to the solver tolerance
+        assert float((x[k] - xs[k]).norm() / xs[k].norm()) <= 1e-7
+
+
+def test_group_mixes_stored_and_on_the_fly(B, orc):
+    members = []
+    for cid in ("sphere_L2_d1_laplace", "torus_L2_d1_laplace_q4"):
+        s, Ast, Aot, So, Ho = ops(B, orc, cid)
+        if CASES[cid][6] != 5:
+            continue  # a group shares q
+        for A in (Ast, Aot):
+            x = torch.from_numpy(W.random_vector(W.rng(7, 13), s.ndof, ncols=2).T.copy()).cuda()
+            members.append((A, x))
+    s, Ast, Aot, So, Ho = ops(B, orc, "sphere_L2_d1_laplace")
+    x = torch.from_numpy(W.random_vector(W.rng(7, 14), s.ndof, ncols=3).T.copy()).cuda()
+    members.append((Aot, x))
+    ys = [torch.empty_like(x) for _, x in members]
+    G = B.Group([A for A, _ in members], [x for _, x in members], ys)
+    G.apply()
+    for (A, x), y in zip(members, ys):
+        assert torch.equal(y, A.apply(x))
+
+
+@pytest.fixture(scope="module")
+def full(B, orc):
+    c = W.CONFIGS[1]
+    print("[far_eval full] sphere6 L=6 d=2 q=5 eta=1.6 leaf=4: assemble on GPU", flush=True)
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=c["degree"], level=c["level"])
+    A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_eval=True)
+    So = orc.Space(orc.SPHERE, [], orc.LAPLACE, 0.0, degree=c["degree"], level=c["level"])
+    Ho = orc.H2(So, q=c["q"], eta=c["eta"], leaf=c["leaf"], assemble_near=False)
+    return s, A, Ho
+
+
+def test_full_size_sampled_rows_and_far_field(B, orc, full):
+    s, A, Ho = full
+    N = s.ndof
+    x = W.random_vector(W.rng(7, 15), N)
+    y = A.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    rows = W.sample_rows(7, N, 6)
+    Ho.assemble_near_rows(rows)
+    yo = Ho.apply_rows(x, rows)
+    assert np.max(np.abs(y[rows] - yo)) <= TOL * np.max(np.abs(yo))
+    yf = Ho.apply_rows(x, np.arange(N, dtype=np.int64), far=True, near=False)
+    rowptr, col, val = A.export_near()
+    yn = np.add.reduceat(val * x[col], rowptr[:-1])
+    assert np.max(np.abs(y - yn - yf)) <= TOL * np.max(np.abs(y))
+
+
+def test_full_size_solve(B, full):
+    s, A, Ho = full
+    c = W.CONFIGS[1]
+    x0, pts = W.c1_inputs()
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+    rho, stats = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"])
+    it, ok, rr, _ = stats[0]
+    assert ok and rr <= c["tol"]
+    r = (b[0] - A.apply(rho[0])).norm() / b[0].norm()
+    assert float(r) <= c["tol"]
