@@ -449,6 +449,21 @@ __device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict_
     (void)n1;
     // LDS slots of the subtree: depth-2 clusters (16) at 0, depth-1 (4) at 16, root at 20
     const int lb = s == 2 ? 0 : (s == 1 ? 16 : 20);
+    // the coefficients under the subtree's leaves form an E x E square; when it fits, it
+    // is staged in LDS with coalesced loads, so that the transforms below read LDS instead
+    // of issuing dependent global loads
+    constexpr int kStage = 24;
+    __shared__ T xs[kStage * kStage];
+    const int E = (w - 1) * stride + nloc;
+    const bool staged = E <= kStage;
+    if (staged) {
+        const int b1 = ri * w * stride, b2 = rj * w * stride;
+        for (int idx = threadIdx.x; idx < E * E; idx += blockDim.x) {
+            const int e1 = idx / E, e2 = idx - e1 * E;
+            xs[idx] = x[dof_id(op.S, f, b1 + e1, b2 + e2)];
+        }
+        __syncthreads();
+    }
     // leaves of this subtree
     for (int idx = threadIdx.x; idx < w * w * Q2; idx += blockDim.x) {
         const int a = idx % Q2, l = idx / Q2;
@@ -456,13 +471,24 @@ __device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict_
         const double* Vi = op.V1 + ((int64_t)i * Q + a1) * nloc;
         const double* Vj = op.V1 + ((int64_t)j * Q + a2) * nloc;
         T acc = zero<T>();
+        if (staged) {
+            const T* xl = xs + (l / w) * stride * E + (l % w) * stride;
 #pragma unroll 2
-        for (int m1 = 0; m1 < nloc; ++m1) {
-            const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
-            T in = zero<T>();
+            for (int m1 = 0; m1 < nloc; ++m1) {
+                T in = zero<T>();
 #pragma unroll 6
-            for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
-            acc += Vi[m1] * in;
+                for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xl[m1 * E + m2];
+                acc += Vi[m1] * in;
+            }
+        } else {
+#pragma unroll 2
+            for (int m1 = 0; m1 < nloc; ++m1) {
+                const T* xr = x + dof_id(op.S, f, i * stride + m1, j * stride);
+                T in = zero<T>();
+#pragma unroll 6
+                for (int m2 = 0; m2 < nloc; ++m2) in += Vj[m2] * xr[m2];
+                acc += Vi[m1] * in;
+            }
         }
         mom[(op.lev_off[leaf] + ((int64_t)f * n1 + i) * n1 + j) * Q2 + a] = acc;
         tree[lb + l][a] = acc;
@@ -707,8 +733,8 @@ __device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cd
 // clusters' Chebyshev points on the surface, evaluated where it is used (the stored
 // blocks hold the same values).  Same chunks, row sums and transposed products as
 // coupling_body.  Each lane takes NS columns (sigma, b) of a pass and keeps their points
-// and moments in registers.  The owner's rows a are visited G at a time (uniform points
-// and moments, scalar loads): every lane adds k * m_owner[a] to its columns' transposed
+// and moments in registers.  The owner's rows a are visited G at a time (points and
+// moments staged in LDS per chunk): every lane adds k * m_owner[a] to its columns' transposed
 // products, and the G row sums of the pass are reduce-scattered across the wave and
 // added to the wave's row accumulators in LDS.  Columns past the row (its padding) or the
 // chunk get a distant point and a zero moment.
@@ -733,9 +759,24 @@ __device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
     const T* __restrict__ mt = mom + (int64_t)t * Q2;
     T* __restrict__ P = (T*)op.P + op.pcol[t];
     const KernelDesc kd = op.S.ker;
-    if (lane < Q2) racc[w][lane] = zero<T>();
+    // the owner's points and moments, staged once per chunk: the row loop reads them from
+    // LDS (all lanes the same address) instead of waiting on global loads
+    // Coordinates are taken relative to the owner's first point o, and the squared
+    // distance is expanded as |x'|^2 + |y'|^2 - 2 x'.y' (three multiply-adds per entry).
+    // For an admissible pair |x'|, |y'| and r are of one order, so the expansion loses
+    // only a few units of rounding.  Staged per owner row: (-2 x', |x'|^2).
+    __shared__ double4 opt[4][Q2];
+    __shared__ T omo[4][Q2];
+    const double o0 = xt[0], o1 = xt[1], o2 = xt[2];
+    if (lane < Q2) {
+        racc[w][lane] = zero<T>();
+        const double d0 = xt[3 * lane] - o0, d1 = xt[3 * lane + 1] - o1, d2 = xt[3 * lane + 2] - o2;
+        opt[w][lane] = double4{-2.0 * d0, -2.0 * d1, -2.0 * d2, d0 * d0 + d1 * d1 + d2 * d2};
+        omo[w][lane] = mt[lane];
+    }
+    wave_sync();
     for (int kb = k0; kb < k1; kb += NS * kWave) {
-        double y0[NS], y1[NS], y2[NS];
+        double y0[NS], y1[NS], y2[NS], yy[NS];
         T ms[NS], p[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
@@ -744,14 +785,15 @@ __device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
             if (k < kend) {
                 const int sl = k / Q2, b = k - sl * Q2;
                 const int64_t g = (int64_t)src[sl] * Q2 + b;
-                y0[u] = xc[3 * g];
-                y1[u] = xc[3 * g + 1];
-                y2[u] = xc[3 * g + 2];
+                y0[u] = xc[3 * g] - o0;
+                y1[u] = xc[3 * g + 1] - o1;
+                y2[u] = xc[3 * g + 2] - o2;
                 ms[u] = mom[g];
             } else {
                 y0[u] = y1[u] = y2[u] = 64.0;
                 ms[u] = zero<T>();
             }
+            yy[u] = y0[u] * y0[u] + y1[u] * y1[u] + y2[u] * y2[u];
         }
 #pragma unroll 1
         for (int a0 = 0; a0 < Q2; a0 += G) {
@@ -761,15 +803,13 @@ __device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
                 sa[g] = zero<T>();
                 const int a = a0 + g;
                 if (Q2 % G != 0 && a >= Q2) continue;
-                const double x0 = xt[3 * a], x1 = xt[3 * a + 1], x2 = xt[3 * a + 2];
-                const T ma = mt[a];
+                const double4 pa = opt[w][a];
+                const T ma = omo[w][a];
                 double r2[NS];
                 T kv[NS];
 #pragma unroll
-                for (int u = 0; u < NS; ++u) {
-                    const double dx = x0 - y0[u], dy = x1 - y1[u], dz = x2 - y2[u];
-                    r2[u] = dx * dx + dy * dy + dz * dz;
-                }
+                for (int u = 0; u < NS; ++u)
+                    r2[u] = __builtin_fma(pa.x, y0[u], __builtin_fma(pa.y, y1[u], __builtin_fma(pa.z, y2[u], pa.w + yy[u])));
                 kernel_unscaled<NS>(kd, r2, kv);
 #pragma unroll
                 for (int u = 0; u < NS; ++u) {
