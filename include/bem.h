@@ -239,14 +239,27 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev,
                        int64_t ldr, int nrhs, void* u_dev, int64_t ldu, hipStream_t stream);
 
-/* Stage timing of bem_apply (tracing).  While enabled (on != 0), every bem_apply records
- * HIP events on its stream around its four stages: 0 forward transform + upward transfer,
- * 1 far-field coupling, 2 downward transfer, 3 backward transform + near-field product.
- * Enabling or disabling clears the record.  bem_profile_read waits for the last recorded
- * event, writes the mean milliseconds of each stage over the recorded applies into
- * stage_ms[0..3] (nstages >= 4), their number into *napplies, and clears the record. */
+/* Stage timing of bem_apply (tracing).  While enabled (on != 0), every one-column apply
+ * records HIP events on its stream around its four stages: 0 near-field product (y
+ * overwritten) beside the forward transform and upward transfer (Sec. 4: moments of every
+ * cluster), 1 far-field coupling, 2 gather of the local expansions, 3 downward transfer +
+ * backward transform added to y.  Many-RHS applies (batch_rhs > 1) record their own five
+ * stages.  Enabling or disabling clears the record.  bem_profile_read waits for the last
+ * recorded event, writes the mean milliseconds of each stage over the recorded applies
+ * into stage_ms[0..nstages-1] (nstages >= 4), their number into *napplies, and clears the
+ * record. */
 int bem_profile_enable(bem_operator A, int on);
 int bem_profile_read(bem_operator A, double* stage_ms, int nstages, int* napplies);
+
+/* Profiling aid: launch stage `stage` (0..3 as above) of a one-column apply of x into y
+ * on `stream`, alone.  The stages pass their results through the operator's scratch
+ * (moments, transposed products, row sums, local expansions), so a stage computes from
+ * what the previous stages of the last apply left there; stages 0-2 are idempotent when
+ * repeated, stage 3 adds to y again.  Back-to-back launches of one stage time its kernel
+ * without the launch gaps that the stage events include.  prec as in bem_apply_ex.
+ * x_dev, y_dev: device, N scalars each (stage 0 reads x and writes y; 3 adds to y).
+ * EINVAL: bad stage, precision not available, operator not assembled. */
+int bem_apply_stage(bem_operator A, int prec, int stage, const void* x_dev, void* y_dev, hipStream_t stream);
 
 /* ---- block-Jacobi preconditioner with a learned low-rank correction -------------------
  * Not part of the paper (its example program runs GMRES unpreconditioned); an addition to

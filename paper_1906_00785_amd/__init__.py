@@ -191,8 +191,15 @@ class Operator:
         C.bem_profile_enable(self.h, on)
 
     def profile_read(self):
-        """(mean ms per stage [fwd+up, coupling, down, back+near], number of applies)."""
+        """(mean ms per stage [near + forward/upward, coupling, gather, downward/backward],
+        number of applies)."""
         return C.bem_profile_read(self.h)
+
+    def apply_stage(self, stage: int, x: torch.Tensor, y: torch.Tensor, prec: int = BEM_PREC_FP64):
+        """Launch one stage of a one-column apply alone (profiling aid; see bem_apply_stage)."""
+        assert x.is_cuda and y.is_cuda and x.numel() >= self.ndof and y.numel() >= self.ndof
+        assert x.dtype == self.space.dtype and y.dtype == self.space.dtype and x.is_contiguous() and y.is_contiguous()
+        C.bem_apply_stage(self.h, prec, stage, x.data_ptr(), y.data_ptr(), _stream())
 
     # ---- parity exports
     def export_near(self):

@@ -72,6 +72,7 @@ _SIGNATURES = {
     "bem_operator_destroy": (None, [_vp]),
     "bem_profile_enable": (_c_int, [_vp, _c_int]),
     "bem_profile_read": (_c_int, [_vp, _P(_c_dbl), _c_int, _P(_c_int)]),
+    "bem_apply_stage": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp]),
     "bem_export_near": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
     "bem_export_far": (_c_int, [_vp, _vp, _vp, _vp]),
     "bem_export_moments": (_c_int, [_vp, _vp, _vp, _vp]),
@@ -241,6 +242,10 @@ def bem_profile_read(A: int):
     n = _c_int()
     check(lib.bem_profile_read(A, ms, 4, ctypes.byref(n)))
     return list(ms), n.value
+
+
+def bem_apply_stage(A: int, prec: int, stage: int, x_ptr: int, y_ptr: int, stream: int):
+    check(lib.bem_apply_stage(A, prec, stage, x_ptr, y_ptr, stream))
 
 
 def bem_export_near(A: int, rowptr_ptr: int, col_ptr: int, val_ptr: int, stream: int):

@@ -1064,6 +1064,16 @@ int bem_apply_ex(bem_operator A, int prec, const void* x_dev, int64_t ldx, void*
     return BEM_OK;
 }
 
+int bem_apply_stage(bem_operator A, int prec, int stage, const void* x_dev, void* y_dev, hipStream_t stream) {
+    if (!A || !x_dev || !y_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    if (prec != BEM_PREC_FP64 && prec != A->far_low)
+        return fail(BEM_EINVAL, "precision not available (assemble with far_low set to it)");
+    if (stage < 0 || stage >= kApplyStages) return fail(BEM_EINVAL, "stage must lie in [0, 4)");
+    HIP_CHECK(launch_apply_stage(A->dev, stage, x_dev, y_dev, prec, stream));
+    return BEM_OK;
+}
+
 int bem_profile_enable(bem_operator A, int on) {
     if (!A) return fail(BEM_EINVAL, "NULL argument");
     A->prof = on != 0;

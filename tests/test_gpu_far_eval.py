@@ -161,3 +161,22 @@ def test_full_size_solve(B, full):
     assert ok and rr <= c["tol"]
     r = (b[0] - A.apply(rho[0])).norm() / b[0].norm()
     assert float(r) <= c["tol"]
+
+
+@pytest.mark.parametrize("cid", ["sphere_L2_d1_laplace", "ellipsoid_L2_d2_helmholtz_cplx"])
+def test_stage_launches_compose_to_apply(B, orc, cid):
+    """The four stages launched one by one (bem_apply_stage) give the apply bitwise, and a
+    repeated coupling stage (idempotent) leaves the result unchanged."""
+    s, Ast, Aot, So, Ho = ops(B, orc, cid)
+    x = torch.from_numpy(W.random_vector(W.rng(7, 16), s.ndof, is_complex=So.complex)).cuda()
+    for A in (Ast, Aot):
+        y = A.apply(x)
+        y2 = torch.empty_like(x)
+        for st in range(4):
+            A.apply_stage(st, x, y2)
+            if st == 1:
+                A.apply_stage(1, x, y2)
+        assert torch.equal(y, y2)
+        with pytest.raises(B._bem.BemError) as e:
+            A.apply_stage(4, x, y2)
+        assert e.value.code == B._bem.BEM_EINVAL
