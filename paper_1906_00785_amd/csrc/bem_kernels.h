@@ -130,11 +130,12 @@ hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st);
 
 // Many operators and columns in one launch per stage: apply a runs the one-column stages
 // of ops[a] (its own scratch) on x[a] -> y[a].  Stages: 0 near field + forward/upward
-// inside subtrees, 1 upper levels of the upward pass, 2 coupling, 3 gather of the local
-// expansions, 4 downward + backward.  prefix[s * (napply + 1) + a] = first block of apply a
-// in stage s's launch; nblocks[s] = blocks of that launch.  All operators share the scalar
-// type and q.
-constexpr int kGroupStages = 5;
+// inside subtrees, 1 upper levels of the upward pass, 2 coupling of the operators with
+// stored blocks, 5 coupling of those evaluating it on the fly (launched right after 2, so
+// that neither launch carries the other's registers), 3 gather of the local expansions,
+// 4 downward + backward.  prefix[s * (napply + 1) + a] = first block of apply a in stage
+// s's launch; nblocks[s] = blocks of that launch.  All operators share the scalar type and q.
+constexpr int kGroupStages = 6;
 struct GroupDev {
     int64_t napply;
     const OpDev* ops;

@@ -1162,14 +1162,14 @@ __global__ __launch_bounds__(256) void kg_stage(GroupDev g) {
         near_up_body<T, Q>(op, blk, (const T*)g.x[a], (T*)g.y[a]);
     else if constexpr (S == 1)
         up_top_body<T, Q>(op, blk);
-    else if constexpr (S == 2) {
+    else if constexpr (S == 2)
+        coupling_body<T, Q>(op, blk);
+    else if constexpr (S == 5) {
         // the operator's own pass width, so that the sums match its one-operator apply
-        if (op.otf && op.otf_wide)
+        if (op.otf_wide)
             coupling_otf_body<T, Q, otf_ns<T>(true)>(op, blk);
-        else if (op.otf)
-            coupling_otf_body<T, Q, otf_ns<T>(false)>(op, blk);
         else
-            coupling_body<T, Q>(op, blk);
+            coupling_otf_body<T, Q, otf_ns<T>(false)>(op, blk);
     }
     else if constexpr (S == 3)
         lv_gather_body<T, Q>(op, blk);
@@ -1182,6 +1182,7 @@ hipError_t group_tq(const GroupDev& g, hipStream_t st) {
     if (g.nblocks[0] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 0>), dim3((unsigned)g.nblocks[0]), dim3(256), 0, st, g);
     if (g.nblocks[1] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 1>), dim3((unsigned)g.nblocks[1]), dim3(256), 0, st, g);
     if (g.nblocks[2] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 2>), dim3((unsigned)g.nblocks[2]), dim3(256), 0, st, g);
+    if (g.nblocks[5] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 5>), dim3((unsigned)g.nblocks[5]), dim3(256), 0, st, g);
     if (g.nblocks[3] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 3>), dim3((unsigned)g.nblocks[3]), dim3(256), 0, st, g);
     if (g.nblocks[4] > 0) hipLaunchKernelGGL((kg_stage<T, Q, 4>), dim3((unsigned)g.nblocks[4]), dim3(256), 0, st, g);
     return hipGetLastError();
@@ -1371,7 +1372,9 @@ hipError_t launch_cast_low(const OpDev& op, hipStream_t st) {
 void group_stage_blocks(const OpDev& op, int64_t out[kGroupStages]) {
     out[0] = ((int64_t)op.S.geom.npatch << (2 * op.up_root)) + (op.ngroups + 3) / 4;
     out[1] = op.up_root > 0 ? op.S.geom.npatch : 0;
-    out[2] = op.nchunks > 0 ? (op.nchunks + 3) / 4 : 0;
+    const int64_t nc = op.nchunks > 0 ? (op.nchunks + 3) / 4 : 0;
+    out[2] = op.otf ? 0 : nc;
+    out[5] = op.otf ? nc : 0;
     out[3] = op.nstored > 0 ? (op.ncl + 3) / 4 : 0;
     const int64_t nt = op.nleaf1 / op.tile;
     out[4] = op.nstored > 0 ? (int64_t)op.S.geom.npatch * nt * nt : 0;
