@@ -613,6 +613,123 @@ __global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
     }
 }
 
+// ------------------------------------------------------------------ coupling (FP64 matrix cores)
+// l_t = sum_s K_ts m_s in FP64 on v_mfma_f64_16x16x4f64 for 64 NTW right-hand sides.  The
+// block walks the sources of t in order; every source's block K_ts is staged once in LDS
+// (transposed when it is stored in the source's rows; double buffered, the next block in
+// flight in registers during the products) and wave w takes NTW column tiles of 16
+// right-hand sides.  Per step of 4 source nodes b, lane l takes A[16 i + l % 16][b] from
+// the staged block and B[b][l % 16] of each column tile from the moments' slab (zero past
+// q^2); a complex product is four real products.  Lane l receives rows 16 i + l / 16 + 4 e
+// of its columns.
+template <class T, int Q, int NTW>
+__global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q;
+    constexpr bool CP = sizeof(T) == 16;
+    constexpr int RT = (Q2 + 15) / 16, KS = (Q2 + 3) / 4, CW = 64 * NTW;
+    constexpr int KR = (Q2 * Q2 + 255) / 256;  // block entries per thread
+    __shared__ T ks[2][Q2 * Q2];
+    const int nch = (bd.R + CW - 1) / CW;
+    const int64_t t = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int R = bd.R, kq = lane >> 4, rl = lane & 15;
+    int rr[NTW];
+    bool on[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        rr[j] = ch * CW + 16 * (w * NTW + j) + rl;  // this lane's right-hand sides
+        on[j] = rr[j] < R;
+    }
+    const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
+    const T* __restrict__ mom = (const T*)bd.mom;
+    const T* __restrict__ K = (const T*)op.K;
+    f64x4 ar[RT][NTW], ai[RT][NTW];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) ar[i][j] = ai[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    T kreg[KR];
+    auto load_block = [&](int64_t p) {
+        const int64_t off = bd.fb_off[p];
+        const int rs = bd.fb_rs[p];
+        const int ars = rs < 0 ? -rs : rs;
+#pragma unroll
+        for (int u = 0; u < KR; ++u) {
+            const int idx = threadIdx.x + u * 256;
+            const int i = idx / Q2, jj = idx - i * Q2;
+            kreg[u] = idx < Q2 * Q2 ? K[off + (int64_t)i * ars + jj] : zero<T>();
+        }
+    };
+    auto store_block = [&](int64_t p, T* dst) {
+        const bool tr = bd.fb_rs[p] < 0;
+#pragma unroll
+        for (int u = 0; u < KR; ++u) {
+            const int idx = threadIdx.x + u * 256;
+            const int i = idx / Q2, jj = idx - i * Q2;
+            if (idx < Q2 * Q2) dst[tr ? jj * Q2 + i : idx] = kreg[u];
+        }
+    };
+    int buf = 0;
+    if (beg < end) {
+        load_block(beg);
+        store_block(beg, ks[0]);
+    }
+    __syncthreads();
+    for (int64_t p = beg; p < end; ++p) {
+        if (p + 1 < end) load_block(p + 1);
+        const T* __restrict__ ms = mom + (int64_t)bd.far_s[p] * Q2 * R;
+        const T* kb = ks[buf];
+        T bv[KS][NTW];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int b = 4 * k + kq;
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) bv[k][j] = (b < Q2 && on[j]) ? ms[(int64_t)b * R + rr[j]] : zero<T>();
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int b = 4 * k + kq;
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int a = 16 * i + rl;
+                const T av = (a < Q2 && b < Q2) ? kb[a * Q2 + b] : zero<T>();
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) {
+                    if constexpr (CP) {
+                        const cdbl ac = *(const cdbl*)&av, bc = *(const cdbl*)&bv[k][j];
+                        ar[i][j] = mfma64(ac.re, bc.re, ar[i][j]);
+                        ar[i][j] = mfma64(-ac.im, bc.im, ar[i][j]);
+                        ai[i][j] = mfma64(ac.re, bc.im, ai[i][j]);
+                        ai[i][j] = mfma64(ac.im, bc.re, ai[i][j]);
+                    } else {
+                        ar[i][j] = mfma64(*(const double*)&av, *(const double*)&bv[k][j], ar[i][j]);
+                    }
+                }
+            }
+        }
+        if (p + 1 < end) store_block(p + 1, ks[buf ^ 1]);
+        __syncthreads();
+        buf ^= 1;
+    }
+    T* lv = (T*)bd.lv + t * Q2 * R;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        if (!on[j]) continue;
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = 16 * i + kq + 4 * e;
+                if (a >= Q2) continue;
+                if constexpr (CP)
+                    ((cdbl*)lv)[(int64_t)a * R + rr[j]] = cdbl{ar[i][j][e], ai[i][j][e]};
+                else
+                    ((double*)lv)[(int64_t)a * R + rr[j]] = ar[i][j][e];
+            }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 template <class T, int Q>
 hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* x, int64_t ldx, void* y, int64_t ldy,
@@ -633,7 +750,16 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
     } else if (stage == 1) {
         const unsigned nb = (unsigned)(op.ncl * nch);
         if (prec == 0) {
-            hipLaunchKernelGGL((kb_coupling<T, T, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const T*)op.K);
+            if constexpr (Q * Q <= 28) {
+                // 128 right-hand sides per block once there are more than 64
+                if (R > kBatchChunk)
+                    hipLaunchKernelGGL((kb_coupling_mfma64<T, Q, 2>), dim3((unsigned)(op.ncl * ((R + 127) / 128))),
+                                       dim3(256), 0, st, op, bd);
+                else
+                    hipLaunchKernelGGL((kb_coupling_mfma64<T, Q, 1>), dim3(nb), dim3(256), 0, st, op, bd);
+            } else {
+                hipLaunchKernelGGL((kb_coupling<T, T, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const T*)op.K);
+            }
         } else if (prec == 1) {
             using F = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
             hipLaunchKernelGGL((kb_coupling<T, F, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const F*)op.Klow);
