@@ -90,8 +90,10 @@ typedef struct bem_h2_params {
     int batch_rhs;    /* right-hand sides per batched apply: with batch_rhs > 1 the operator
                          workspace holds slabs for that many columns and bem_apply /
                          bem_apply_ex with nrhs > 1 run the many-RHS kernels on up to
-                         batch_rhs columns per pass (q <= 6; BEM_PREC_BF16 there needs
-                         q <= 5 and uses the matrix cores); 0 or 1: one column at a time */
+                         batch_rhs columns per pass (q <= 6; with q <= 5 the coupling
+                         runs on the matrix cores in FP64, FP32 or BF16 and the near field
+                         in FP64; BEM_PREC_BF16 there needs q <= 5); 0 or 1: one column
+                         at a time                                                        */
     int far_eval;     /* 1: no stored coupling blocks; every apply evaluates the kernel at the
                          clusters' Chebyshev points where the blocks are used (same entries
                          as the stored blocks, Sec. 4: the coupling matrices are the kernel

@@ -335,8 +335,9 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma(OpDev op, BatchDev bd) {
     constexpr int RT = CP ? 4 : 2, NT = CP ? 8 : 4;
     __shared__ float red[RT * 16][NT * 16 + 1];
     const int nch = nchunks(bd.R);
-    const int64_t t = blockIdx.x / nch;
-    const int ch = blockIdx.x % nch;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);  // neighbouring blocks on one XCD
+    const int64_t t = lb / nch;
+    const int ch = (int)(lb % nch);
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
     const u16x8* __restrict__ Af = (const u16x8*)bd.Af;
@@ -541,8 +542,9 @@ template <class T>
 __global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
     constexpr bool CP = sizeof(T) == 16;
     const int nch = nchunks(bd.R);
-    const int64_t t = blockIdx.x / nch;
-    const int ch = blockIdx.x % nch;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);  // neighbouring blocks on one XCD
+    const int64_t t = lb / nch;
+    const int ch = (int)(lb % nch);
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int R = bd.R;
     const int rb_n = ch * kBatchChunk + 16 * w;  // first right-hand side of this wave
@@ -613,25 +615,48 @@ __global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
     }
 }
 
-// ------------------------------------------------------------------ coupling (FP64 matrix cores)
-// l_t = sum_s K_ts m_s in FP64 on v_mfma_f64_16x16x4f64 for 64 NTW right-hand sides.  The
-// block walks the sources of t in order; every source's block K_ts is staged once in LDS
-// (transposed when it is stored in the source's rows; double buffered, the next block in
-// flight in registers during the products) and wave w takes NTW column tiles of 16
-// right-hand sides.  Per step of 4 source nodes b, lane l takes A[16 i + l % 16][b] from
-// the staged block and B[b][l % 16] of each column tile from the moments' slab (zero past
-// q^2); a complex product is four real products.  Lane l receives rows 16 i + l / 16 + 4 e
-// of its columns.
-template <class T, int Q, int NTW>
-__global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd) {
+// ------------------------------------------------------------------ coupling (matrix cores, FP64 / FP32)
+// One real MFMA step per arithmetic: v_mfma_f64_16x16x4f64 (lane l receives rows
+// l / 16 + 4 e of column l % 16) or v_mfma_f32_16x16x4f32 (rows 4 (l / 16) + e); both take
+// A[l % 16][l / 16] and B[l / 16][l % 16].
+template <class Bt>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    using acc = f64x4;
+    __device__ static acc step(double a, double b, acc c) { return mfma64(a, b, c); }
+    __device__ static int row(int kq, int e) { return kq + 4 * e; }
+};
+template <>
+struct Mfma16<float> {
+    using acc = f32x4;
+    __device__ static acc step(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int kq, int e) { return 4 * kq + e; }
+};
+
+// l_t = sum_s K_ts m_s on the matrix cores for 64 NTW right-hand sides, in FP64 (F = T,
+// the stored blocks) or FP32 (F = float / cflt, the FP32 copy; moments rounded to FP32,
+// FP32 accumulation).  The block walks the sources of t in order; every source's block
+// K_ts is staged once in LDS (transposed when it is stored in the source's rows; double
+// buffered, the next block in flight in registers during the products) and wave w takes
+// NTW column tiles of 16 right-hand sides.  Per step of 4 source nodes b, lane l takes
+// A[16 i + l % 16][b] from the staged block and B[b][l % 16] of each column tile from the
+// moments' slab (zero past q^2); a complex product is four real products.
+template <class T, class F, int Q, int NTW>
+__global__ __launch_bounds__(256) void kb_coupling_mx(OpDev op, BatchDev bd, const F* __restrict__ K) {
     constexpr int Q2 = Q * Q;
     constexpr bool CP = sizeof(T) == 16;
+    using Bt = typename std::conditional<sizeof(F) == 4 || (sizeof(F) == 8 && CP), float, double>::type;
+    using M = Mfma16<Bt>;
+    using A4 = typename M::acc;
     constexpr int RT = (Q2 + 15) / 16, KS = (Q2 + 3) / 4, CW = 64 * NTW;
     constexpr int KR = (Q2 * Q2 + 255) / 256;  // block entries per thread
-    __shared__ T ks[2][Q2 * Q2];
+    __shared__ F ks[2][Q2 * Q2];
     const int nch = (bd.R + CW - 1) / CW;
-    const int64_t t = blockIdx.x / nch;
-    const int ch = blockIdx.x % nch;
+    // consecutive targets (siblings, sharing most of their sources' moments) on one XCD
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t = lb / nch;
+    const int ch = (int)(lb % nch);
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int R = bd.R, kq = lane >> 4, rl = lane & 15;
     int rr[NTW];
@@ -643,13 +668,12 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd)
     }
     const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
     const T* __restrict__ mom = (const T*)bd.mom;
-    const T* __restrict__ K = (const T*)op.K;
-    f64x4 ar[RT][NTW], ai[RT][NTW];
+    A4 ar[RT][NTW], ai[RT][NTW];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) ar[i][j] = ai[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    T kreg[KR];
+        for (int j = 0; j < NTW; ++j) ar[i][j] = ai[i][j] = A4{0, 0, 0, 0};
+    F kreg[KR];
     auto load_block = [&](int64_t p) {
         const int64_t off = bd.fb_off[p];
         const int rs = bd.fb_rs[p];
@@ -658,10 +682,10 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd)
         for (int u = 0; u < KR; ++u) {
             const int idx = threadIdx.x + u * 256;
             const int i = idx / Q2, jj = idx - i * Q2;
-            kreg[u] = idx < Q2 * Q2 ? K[off + (int64_t)i * ars + jj] : zero<T>();
+            kreg[u] = idx < Q2 * Q2 ? K[off + (int64_t)i * ars + jj] : zero_f<F>();
         }
     };
-    auto store_block = [&](int64_t p, T* dst) {
+    auto store_block = [&](int64_t p, F* dst) {
         const bool tr = bd.fb_rs[p] < 0;
 #pragma unroll
         for (int u = 0; u < KR; ++u) {
@@ -679,13 +703,14 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd)
     for (int64_t p = beg; p < end; ++p) {
         if (p + 1 < end) load_block(p + 1);
         const T* __restrict__ ms = mom + (int64_t)bd.far_s[p] * Q2 * R;
-        const T* kb = ks[buf];
-        T bv[KS][NTW];
+        const F* kb = ks[buf];
+        F bv[KS][NTW];
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int b = 4 * k + kq;
 #pragma unroll
-            for (int j = 0; j < NTW; ++j) bv[k][j] = (b < Q2 && on[j]) ? ms[(int64_t)b * R + rr[j]] : zero<T>();
+            for (int j = 0; j < NTW; ++j)
+                bv[k][j] = (b < Q2 && on[j]) ? cvt<F>(ms[(int64_t)b * R + rr[j]]) : zero_f<F>();
         }
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
@@ -693,17 +718,16 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd)
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 const int a = 16 * i + rl;
-                const T av = (a < Q2 && b < Q2) ? kb[a * Q2 + b] : zero<T>();
+                const F av = (a < Q2 && b < Q2) ? kb[a * Q2 + b] : zero_f<F>();
 #pragma unroll
                 for (int j = 0; j < NTW; ++j) {
                     if constexpr (CP) {
-                        const cdbl ac = *(const cdbl*)&av, bc = *(const cdbl*)&bv[k][j];
-                        ar[i][j] = mfma64(ac.re, bc.re, ar[i][j]);
-                        ar[i][j] = mfma64(-ac.im, bc.im, ar[i][j]);
-                        ai[i][j] = mfma64(ac.re, bc.im, ai[i][j]);
-                        ai[i][j] = mfma64(ac.im, bc.re, ai[i][j]);
+                        ar[i][j] = M::step(av.re, bv[k][j].re, ar[i][j]);
+                        ar[i][j] = M::step(-av.im, bv[k][j].im, ar[i][j]);
+                        ai[i][j] = M::step(av.re, bv[k][j].im, ai[i][j]);
+                        ai[i][j] = M::step(av.im, bv[k][j].re, ai[i][j]);
                     } else {
-                        ar[i][j] = mfma64(*(const double*)&av, *(const double*)&bv[k][j], ar[i][j]);
+                        ar[i][j] = M::step(av, bv[k][j], ar[i][j]);
                     }
                 }
             }
@@ -720,12 +744,12 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma64(OpDev op, BatchDev bd)
         for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int a = 16 * i + kq + 4 * e;
+                const int a = 16 * i + M::row(kq, e);
                 if (a >= Q2) continue;
                 if constexpr (CP)
-                    ((cdbl*)lv)[(int64_t)a * R + rr[j]] = cdbl{ar[i][j][e], ai[i][j][e]};
+                    ((cdbl*)lv)[(int64_t)a * R + rr[j]] = cdbl{(double)ar[i][j][e], (double)ai[i][j][e]};
                 else
-                    ((double*)lv)[(int64_t)a * R + rr[j]] = ar[i][j][e];
+                    ((double*)lv)[(int64_t)a * R + rr[j]] = (double)ar[i][j][e];
             }
     }
 }
@@ -749,20 +773,29 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
         if (prec == 2) hipLaunchKernelGGL((kb_bf_moments<T, Q>), dim3(nblk(op.ncl * nch, 4)), dim3(256), 0, st, op, bd);
     } else if (stage == 1) {
         const unsigned nb = (unsigned)(op.ncl * nch);
+        using F32 = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
+        // 128 right-hand sides per block once there are more than 64
+        const unsigned nb2 = (unsigned)(op.ncl * ((R + 127) / 128));
         if (prec == 0) {
             if constexpr (Q * Q <= 28) {
-                // 128 right-hand sides per block once there are more than 64
                 if (R > kBatchChunk)
-                    hipLaunchKernelGGL((kb_coupling_mfma64<T, Q, 2>), dim3((unsigned)(op.ncl * ((R + 127) / 128))),
-                                       dim3(256), 0, st, op, bd);
+                    hipLaunchKernelGGL((kb_coupling_mx<T, T, Q, 2>), dim3(nb2), dim3(256), 0, st, op, bd, (const T*)op.K);
                 else
-                    hipLaunchKernelGGL((kb_coupling_mfma64<T, Q, 1>), dim3(nb), dim3(256), 0, st, op, bd);
+                    hipLaunchKernelGGL((kb_coupling_mx<T, T, Q, 1>), dim3(nb), dim3(256), 0, st, op, bd, (const T*)op.K);
             } else {
                 hipLaunchKernelGGL((kb_coupling<T, T, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const T*)op.K);
             }
         } else if (prec == 1) {
-            using F = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
-            hipLaunchKernelGGL((kb_coupling<T, F, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const F*)op.Klow);
+            if constexpr (Q * Q <= 28) {
+                if (R > kBatchChunk)
+                    hipLaunchKernelGGL((kb_coupling_mx<T, F32, Q, 2>), dim3(nb2), dim3(256), 0, st, op, bd,
+                                       (const F32*)op.Klow);
+                else
+                    hipLaunchKernelGGL((kb_coupling_mx<T, F32, Q, 1>), dim3(nb), dim3(256), 0, st, op, bd,
+                                       (const F32*)op.Klow);
+            } else {
+                hipLaunchKernelGGL((kb_coupling<T, F32, Q>), dim3(nb), dim3(256), 0, st, op, bd, (const F32*)op.Klow);
+            }
         } else {
             if constexpr (Q * Q <= 32)
                 hipLaunchKernelGGL((kb_coupling_mfma<T, Q>), dim3(nb), dim3(256), 0, st, op, bd);

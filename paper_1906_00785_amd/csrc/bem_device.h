@@ -14,6 +14,16 @@ constexpr int kWave = 64;
 
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b to XCD b % 8), and each XCD
+// has its own L2.  Renumbering so that XCD x runs a contiguous range of logical blocks
+// lets neighbouring blocks (which read overlapping data) share an L2.  A bijection of
+// [0, n).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+    const int64_t x = b % kXcds, i = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // orders the wave's LDS accesses before and after this point
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
