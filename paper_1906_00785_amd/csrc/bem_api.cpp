@@ -1376,7 +1376,8 @@ struct bem_group_s {
     int64_t napply = 0;
     size_t ws_bytes = 0;
     std::vector<OpDev> host_ops;
-    std::vector<int64_t> prefix;
+    std::vector<int64_t> prefix, first;
+    std::vector<int32_t> ncol32;
     std::vector<const void*> xs;
     std::vector<void*> ys;
     GroupDev dev{};
@@ -1391,7 +1392,10 @@ static size_t group_layout(bem_group_s& G, char* base, std::vector<OpDev>* ops) 
     OpDev* d_ops = b.take<OpDev>(n);
     const void** d_x = b.take<const void*>(n);
     void** d_y = b.take<void*>(n);
-    int64_t* d_pre = b.take<int64_t>((size_t)kGroupStages * (n + 1));
+    const size_t nop = G.ops.size();
+    int64_t* d_pre = b.take<int64_t>((size_t)kGroupStages * (nop + 1));
+    int64_t* d_first = b.take<int64_t>(nop);
+    int32_t* d_ncol = b.take<int32_t>(nop);
     if (ops) ops->clear();
     for (size_t i = 0; i < G.ops.size(); ++i) {
         const bem_operator_s& A = *G.ops[i];
@@ -1410,6 +1414,8 @@ static size_t group_layout(bem_group_s& G, char* base, std::vector<OpDev>* ops) 
         G.dev.x = d_x;
         G.dev.y = d_y;
         G.dev.prefix = d_pre;
+        G.dev.first = d_first;
+        G.dev.ncol = d_ncol;
     }
     return b.off + 256;
 }
@@ -1454,15 +1460,23 @@ int bem_group_bind(bem_group G, void* ws, size_t ws_bytes, const void* const* x_
     G->ys.assign(y_cols, y_cols + n);
     for (size_t a = 0; a < n; ++a)
         if (!G->xs[a] || !G->ys[a]) return fail(BEM_EINVAL, "NULL column pointer");
-    G->prefix.assign((size_t)kGroupStages * (n + 1), 0);
-    for (size_t a = 0; a < n; ++a) {
+    // per operator: the blocks of all its columns in each stage (see group_stage_blocks;
+    // every column of an operator has the block counts of the operator's first apply)
+    const size_t nop = G->ops.size();
+    G->prefix.assign((size_t)kGroupStages * (nop + 1), 0);
+    G->first.assign(nop, 0);
+    G->ncol32.assign(nop, 0);
+    for (size_t i = 0, a = 0; i < nop; a += (size_t)G->ncols[i], ++i) {
+        G->first[i] = (int64_t)a;
+        G->ncol32[i] = G->ncols[i];
         int64_t nb[kGroupStages];
-        group_stage_blocks(G->host_ops[a], nb);
-        for (int s = 0; s < kGroupStages; ++s) G->prefix[s * (n + 1) + a + 1] = G->prefix[s * (n + 1) + a] + nb[s];
+        group_stage_blocks(G->host_ops[a], G->ncols[i], nb);
+        for (int s = 0; s < kGroupStages; ++s) G->prefix[s * (nop + 1) + i + 1] = G->prefix[s * (nop + 1) + i] + nb[s];
     }
     G->dev.napply = G->napply;
+    G->dev.nop = (int64_t)nop;
     for (int s = 0; s < kGroupStages; ++s) {
-        G->dev.nblocks[s] = G->prefix[s * (n + 1) + n];
+        G->dev.nblocks[s] = G->prefix[s * (nop + 1) + nop];
         if (G->dev.nblocks[s] > 0x7fffffff) return fail(BEM_EUNSUPPORTED, "too many blocks in one launch");
     }
     HIP_CHECK(hipMemcpyAsync((void*)G->dev.ops, G->host_ops.data(), n * sizeof(OpDev), hipMemcpyHostToDevice, stream));
@@ -1470,6 +1484,8 @@ int bem_group_bind(bem_group G, void* ws, size_t ws_bytes, const void* const* x_
     HIP_CHECK(hipMemcpyAsync((void*)G->dev.y, G->ys.data(), n * sizeof(void*), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync((void*)G->dev.prefix, G->prefix.data(), G->prefix.size() * 8, hipMemcpyHostToDevice,
                              stream));
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.first, G->first.data(), nop * 8, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)G->dev.ncol, G->ncol32.data(), nop * 4, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
     G->bound = true;
     return BEM_OK;

@@ -133,18 +133,25 @@ hipError_t launch_moments(const OpDev& op, const void* x, hipStream_t st);
 // inside subtrees, 1 upper levels of the upward pass, 2 coupling of the operators with
 // stored blocks, 5 coupling of those evaluating it on the fly (launched right after 2, so
 // that neither launch carries the other's registers), 3 gather of the local expansions,
-// 4 downward + backward.  prefix[s * (napply + 1) + a] = first block of apply a in stage
-// s's launch; nblocks[s] = blocks of that launch.  All operators share the scalar type and q.
+// 4 downward + backward.  Within a launch the blocks of one operator's columns are
+// interleaved (block j of the operator's range is block j / ncol of its column j % ncol),
+// so that its columns read the same stored values one after the other.
+// prefix[s * (nop + 1) + i] = first block of operator i in stage s's launch; first[i] =
+// its first apply, ncol[i] its columns; nblocks[s] = blocks of that launch.  All operators
+// share the scalar type and q.
 constexpr int kGroupStages = 6;
 struct GroupDev {
-    int64_t napply;
-    const OpDev* ops;
+    int64_t napply, nop;
+    const OpDev* ops;  // per apply
     const void* const* x;
     void* const* y;
     const int64_t* prefix;
+    const int64_t* first;
+    const int32_t* ncol;
     int64_t nblocks[kGroupStages];
 };
-void group_stage_blocks(const OpDev& op, int64_t out[kGroupStages]);
+// blocks of each grouped stage for one operator with ncols columns
+void group_stage_blocks(const OpDev& op, int ncols, int64_t out[kGroupStages]);
 hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st);
 
 // load vector (one RHS) and potential (one RHS)

@@ -643,6 +643,16 @@ __device__ inline Pair<cdbl> load_stream(const cdbl* p) {
     const dvec2 b = __builtin_nontemporal_load((const dvec2*)p + 1);
     return {{a.x, a.y}, {b.x, b.y}};
 }
+// the same pairs with ordinary (cached) loads, for blocks that other blocks read again
+__device__ inline Pair<double> load_cached(const double* p) {
+    const dvec2 v = *(const dvec2*)p;
+    return {v.x, v.y};
+}
+__device__ inline Pair<cdbl> load_cached(const cdbl* p) {
+    const dvec2 a = *(const dvec2*)p;
+    const dvec2 b = *((const dvec2*)p + 1);
+    return {{a.x, a.y}, {b.x, b.y}};
+}
 
 // Stage 1.  Far-field coupling over the stored blocks, one wave per chunk of an owner's
 // row-concatenated coupling rows.  Each lane takes two adjacent columns (sigma, b) per
@@ -650,7 +660,7 @@ __device__ inline Pair<cdbl> load_stream(const cdbl* p) {
 // wave), accumulates K m_sigma into Q2 row sums, and forms the transposed product
 // (K^T m_owner) of its columns, stored once per column.  Row sums are reduce-scattered
 // across the wave into the chunk's partial sums.
-template <class T, int Q>
+template <class T, int Q, bool kStream = true>
 __device__ inline void coupling_body(const OpDev& op, int64_t blk_) {
     constexpr int Q2 = Q * Q;
     const int64_t c = (int64_t)blk_ * 4 + uniform_int(threadIdx.x >> 6);
@@ -681,7 +691,7 @@ __device__ inline void coupling_body(const OpDev& op, int64_t blk_) {
         T p0 = zero<T>(), p1 = zero<T>();
 #pragma unroll
         for (int a = 0; a < Q2; ++a) {
-            const Pair<T> kv = load_stream(base + a * rs + k);
+            const Pair<T> kv = kStream ? load_stream(base + a * rs + k) : load_cached(base + a * rs + k);
             acc[a] += kv.x * m0 + kv.y * m1;
             p0 += kv.x * mown[a];
             p1 += kv.y * mown[a];
@@ -1154,16 +1164,21 @@ __device__ inline int64_t group_find(const int64_t* pre, int64_t napply, int64_t
 
 template <class T, int Q, int S>
 __global__ __launch_bounds__(256) void kg_stage(GroupDev g) {
-    const int64_t* pre = g.prefix + (int64_t)S * (g.napply + 1);
-    const int64_t a = group_find(pre, g.napply, blockIdx.x);
-    const int64_t blk = (int64_t)blockIdx.x - pre[a];
+    const int64_t* pre = g.prefix + (int64_t)S * (g.nop + 1);
+    // consecutive logical blocks on one XCD, where an operator's columns share its data
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t o = group_find(pre, g.nop, b);
+    const int64_t j = b - pre[o];
+    const int nc = g.ncol[o];
+    const int64_t a = g.first[o] + j % nc;
+    const int64_t blk = j / nc;
     const OpDev& op = g.ops[a];
     if constexpr (S == 0)
         near_up_body<T, Q>(op, blk, (const T*)g.x[a], (T*)g.y[a]);
     else if constexpr (S == 1)
         up_top_body<T, Q>(op, blk);
     else if constexpr (S == 2)
-        coupling_body<T, Q>(op, blk);
+        coupling_body<T, Q, false>(op, blk);  // the operator's other columns read the same blocks
     else if constexpr (S == 5) {
         // the operator's own pass width, so that the sums match its one-operator apply
         if (op.otf_wide)
@@ -1369,15 +1384,16 @@ hipError_t launch_cast_low(const OpDev& op, hipStream_t st) {
 }
 
 // blocks of each grouped stage for one operator (the one-column launch shapes)
-void group_stage_blocks(const OpDev& op, int64_t out[kGroupStages]) {
+void group_stage_blocks(const OpDev& op, int ncols, int64_t out[kGroupStages]) {
+    const int64_t nc = op.nchunks > 0 ? (op.nchunks + 3) / 4 : 0;
+    const int64_t nt = op.nleaf1 / op.tile;
     out[0] = ((int64_t)op.S.geom.npatch << (2 * op.up_root)) + (op.ngroups + 3) / 4;
     out[1] = op.up_root > 0 ? op.S.geom.npatch : 0;
-    const int64_t nc = op.nchunks > 0 ? (op.nchunks + 3) / 4 : 0;
     out[2] = op.otf ? 0 : nc;
     out[5] = op.otf ? nc : 0;
     out[3] = op.nstored > 0 ? (op.ncl + 3) / 4 : 0;
-    const int64_t nt = op.nleaf1 / op.tile;
     out[4] = op.nstored > 0 ? (int64_t)op.S.geom.npatch * nt * nt : 0;
+    for (int s = 0; s < kGroupStages; ++s) out[s] *= ncols;
 }
 
 hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st) {
