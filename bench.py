@@ -175,8 +175,9 @@ def bench_c2(B, W, torch, np, stream, args):
 def bench_c3(B, W, torch, np, args):
     """Batched uneven instances, every instance and right-hand side in FP64: per-column
     applies, one grouped launch per stage over every instance and column, and the grouped
-    launches captured into one graph.  Each instance uses the faster far field for its
-    kernel: evaluated on the fly for Laplace, stored blocks for Helmholtz."""
+    launches captured into one graph.  Laplace instances evaluate the coupling on the fly,
+    Helmholtz instances stream their stored blocks (measured faster in grouped launches,
+    where an operator's columns read them one after the other)."""
     insts = W.c3_instances(args.c3_instances)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -787,6 +787,13 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     if (p->far_eval != 0 && p->far_eval != 1) return fail(BEM_EINVAL, "far_eval must be 0 or 1");
     if (p->far_eval && (p->far_low != 0 || p->batch_rhs > 1))
         return fail(BEM_EUNSUPPORTED, "far_eval needs far_low = 0 and batch_rhs <= 1");
+    if (p->far_eval && s->S.ker.pde == PDE_HELMHOLTZ) {
+        // the on-the-fly sine and cosine take arguments Re(kappa) r below 2^20
+        const GeomDesc& gd = s->S.geom;
+        const double diam = 2.0 * (std::fabs(gd.a) + std::fabs(gd.b) + std::fabs(gd.c) + 1.0);
+        if (std::fabs(s->S.ker.kre) * diam >= 1048576.0)
+            return fail(BEM_EUNSUPPORTED, "far_eval: Re(kappa) times the surface diameter must stay below 2^20");
+    }
     if (p->far_low < 0 || p->far_low > 2) return fail(BEM_EINVAL, "far_low must be 0, BEM_PREC_FP32 or BEM_PREC_BF16");
     if (p->batch_rhs < 0 || p->batch_rhs > 4096) return fail(BEM_EINVAL, "batch_rhs must lie in [0, 4096]");
     if (p->batch_rhs > 1 && p->q > 6) return fail(BEM_EUNSUPPORTED, "many-RHS kernels need q <= 6");

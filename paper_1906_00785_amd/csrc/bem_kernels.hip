@@ -720,6 +720,41 @@ __device__ inline void rinv_nr(const double* r2, double* y) {
     }
 }
 
+// sin x and cos x for 0 <= x < 2^20: x = k pi/2 + y with |y| <= pi/4 (pi/2 split into three
+// doubles, each product subtracted with one rounding), then the Taylor series of sin and
+// cos about 0 through y^17 and y^18 (truncation below 1e-19 at pi/4) and the quadrant k mod 4.
+__device__ inline void sincos_reduced(double x, double* sn, double* cs) {
+    const double k = __builtin_rint(x * 0.6366197723675814);  // 2 / pi
+    double y = __builtin_fma(-k, 1.5707963267948966, x);
+    y = __builtin_fma(-k, 6.123233995736766e-17, y);
+    y = __builtin_fma(-k, -1.4973849048591698e-33, y);
+    const double z = y * y;
+    // coefficients (-1)^m / (2m+1)! and (-1)^m / (2m)!
+    double ps = 2.8114572543455206e-15;
+    ps = __builtin_fma(ps, z, -7.647163731819816e-13);
+    ps = __builtin_fma(ps, z, 1.6059043836821613e-10);
+    ps = __builtin_fma(ps, z, -2.505210838544172e-08);
+    ps = __builtin_fma(ps, z, 2.7557319223985893e-06);
+    ps = __builtin_fma(ps, z, -0.0001984126984126984);
+    ps = __builtin_fma(ps, z, 0.008333333333333333);
+    ps = __builtin_fma(ps, z, -0.16666666666666666);
+    const double s = __builtin_fma(ps * z, y, y);
+    double pc = -1.5619206968586225e-16;
+    pc = __builtin_fma(pc, z, 4.779477332387385e-14);
+    pc = __builtin_fma(pc, z, -1.1470745597729725e-11);
+    pc = __builtin_fma(pc, z, 2.08767569878681e-09);
+    pc = __builtin_fma(pc, z, -2.755731922398589e-07);
+    pc = __builtin_fma(pc, z, 2.48015873015873e-05);
+    pc = __builtin_fma(pc, z, -0.001388888888888889);
+    pc = __builtin_fma(pc, z, 0.041666666666666664);
+    pc = __builtin_fma(pc, z, -0.5);
+    const double c = __builtin_fma(pc, z, 1.0);
+    const int q = (int)k & 3;
+    const double s1 = (q & 1) ? c : s, c1 = (q & 1) ? s : c;
+    *sn = (q & 2) ? -s1 : s1;
+    *cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
 // the single-layer kernel without its constant factor 1/(4 pi), at NS distances r^2 > 0
 template <int NS>
 __device__ inline void kernel_unscaled(const KernelDesc&, const double* r2, double* kv) {
@@ -733,7 +768,7 @@ __device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cd
     for (int u = 0; u < NS; ++u) {
         const double r = r2[u] * ir[u];
         double sn, cs;
-        sincos(k.kre * r, &sn, &cs);
+        sincos_reduced(k.kre * r, &sn, &cs);  // 0 <= Re kappa r < 2^20, checked at planning
         const double mag = k.kim != 0.0 ? ir[u] * exp(k.kim * r) : ir[u];
         kv[u] = {mag * cs, -mag * sn};
     }
