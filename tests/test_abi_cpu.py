@@ -53,6 +53,12 @@ def test_argument_validation(B):
         with pytest.raises(C.BemError) as e:
             B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False, **kw)
         assert e.value.code == code, kw
+    # the on-the-fly sine and cosine take Re(kappa) r < 2^20
+    sh = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, 5e5, degree=1, level=2)
+    with pytest.raises(C.BemError) as e:
+        B.Operator(sh, q=5, eta=1.6, leaf_level=2, assemble=False, far_eval=True)
+    assert e.value.code == C.BEM_EUNSUPPORTED
+    B.Operator(sh, q=5, eta=1.6, leaf_level=2, assemble=False)  # stored blocks: no bound
     Ao = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False, far_eval=True)
     Ast = B.Operator(s, q=5, eta=1.6, leaf_level=2, assemble=False)
     assert Ao.info.far_bytes == 0.0 and Ast.info.far_bytes > 0.0
