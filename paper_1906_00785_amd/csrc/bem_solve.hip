@@ -47,19 +47,27 @@ __device__ inline T block_sum(T v, T* red) {
     return s;
 }
 
-// part[b][i] = sum over slice b of conj(V_i) w, i < k
+// part[b][i] = sum over slice b of conj(V_i) w, i < k: wave v of the block takes the
+// vectors i = v, v + 4, ..., each lane every 64th entry of the slice, then a butterfly
+// (no block barrier per vector)
+template <class T>
+__device__ inline void slice_dots(int64_t n, int k, const T* __restrict__ V, const T* w, int64_t t0, int64_t t1,
+                                  T* __restrict__ part) {
+    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = v; i < k; i += kThreads / 64) {
+        T acc = zero<T>();
+        for (int64_t t = t0 + lane; t < t1; t += 64) acc += conj_(V[(int64_t)i * n + t]) * w[t];
+        acc = wsum(acc);
+        if (lane == 0) part[(int64_t)blockIdx.x * k + i] = acc;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_s_dots(int64_t n, int k, const T* __restrict__ V, const T* __restrict__ w,
                                                      T* __restrict__ part) {
-    __shared__ T red[4];
     int64_t t0, t1;
     slice(n, t0, t1);
-    for (int i = 0; i < k; ++i) {
-        T acc = zero<T>();
-        for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) acc += conj_(V[(int64_t)i * n + t]) * w[t];
-        const T s = block_sum(acc, red);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + i] = s;
-    }
+    slice_dots(n, k, V, w, t0, t1, part);
 }
 
 // h = sum of the partials (k values) -> w -= V h over the slice -> partials of the next
@@ -69,13 +77,20 @@ __global__ __launch_bounds__(kThreads) void k_s_update(int64_t n, int k, const T
                                                        const T* __restrict__ part_in, T* __restrict__ hout, T* w,
                                                        T* __restrict__ part_out, double* __restrict__ npart, int mode) {
     __shared__ T h[65];
-    __shared__ T red[4];
     __shared__ double redd[4];
-    for (int i = threadIdx.x; i < k; i += kThreads) {
-        T s = zero<T>();
-        for (int b = 0; b < (int)gridDim.x; ++b) s += part_in[(int64_t)b * k + i];
-        h[i] = s;
-        if (blockIdx.x == 0) hout[i] = s;
+    {
+        // h_i = sum over the blocks' partials: wave v takes i = v, v + 4, ..., each lane
+        // every 64th block, then a butterfly (fixed order)
+        const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int i = v; i < k; i += kThreads / 64) {
+            T s = zero<T>();
+            for (int b = lane; b < (int)gridDim.x; b += 64) s += part_in[(int64_t)b * k + i];
+            s = wsum(s);
+            if (lane == 0) {
+                h[i] = s;
+                if (blockIdx.x == 0) hout[i] = s;
+            }
+        }
     }
     __syncthreads();
     int64_t t0, t1;
@@ -87,12 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_s_update(int64_t n, int k, const T
     }
     __syncthreads();
     if (mode == 0) {
-        for (int i = 0; i < k; ++i) {
-            T acc = zero<T>();
-            for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) acc += conj_(V[(int64_t)i * n + t]) * w[t];
-            const T s = block_sum(acc, red);
-            if (threadIdx.x == 0) part_out[(int64_t)blockIdx.x * k + i] = s;
-        }
+        slice_dots(n, k, V, w, t0, t1, part_out);
     } else {
         double acc = 0.0;
         for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) acc += abs2(w[t]);
@@ -101,10 +111,12 @@ __global__ __launch_bounds__(kThreads) void k_s_update(int64_t n, int k, const T
     }
 }
 
+// sqrt of the sum of the nb per-block squared-norm partials, computed by every wave in the
+// same fixed order (each lane every 64th partial, then a butterfly)
 __device__ inline double reduce_npart(const double* npart, int nb) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += npart[b];
-    return sqrt(s);
+    for (int b = threadIdx.x & 63; b < nb; b += 64) s += npart[b];
+    return sqrt(wsum(s));
 }
 
 // v_{j+1} = w / ||w|| over the slice; block 0 applies the Givens rotations to the new
