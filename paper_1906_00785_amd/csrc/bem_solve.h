@@ -9,7 +9,7 @@
 
 namespace bem {
 
-constexpr int kSolveBlocks = 128;  // slices of every vector kernel
+constexpr int kSolveBlocks = 256;  // slices of every vector kernel
 constexpr int kMaxRestart = 64;    // Krylov dimension per cycle at most
 
 // Device-resident state of one GMRES cycle (pointers into the solver workspace).

@@ -54,6 +54,7 @@ template <class T>
 __device__ inline void slice_dots(int64_t n, int k, const T* __restrict__ V, const T* w, int64_t t0, int64_t t1,
                                   T* __restrict__ part) {
     const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll 4
     for (int i = v; i < k; i += kThreads / 64) {
         T acc = zero<T>();
         for (int64_t t = t0 + lane; t < t1; t += 64) acc += conj_(V[(int64_t)i * n + t]) * w[t];
@@ -131,34 +132,52 @@ __global__ __launch_bounds__(kThreads) void k_s_scale_givens(int64_t n, int j, c
     slice(n, t0, t1);
     const double inv = 1.0 / nrm;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) vnext[t] = w[t] * inv;
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    // block 0: the new column and the rotations so far are staged in LDS by all threads,
+    // then one thread applies the rotations (a serial chain, now on LDS)
+    __shared__ T col[66];
+    __shared__ T snl[64];
+    __shared__ double csl[64];
     const int m = st.m;
     T* H = (T*)st.H;
     T* sn = (T*)st.sn;
     T* g = (T*)st.g;
     const T* h1 = (const T*)st.h1;
     const T* h2 = (const T*)st.h2;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
-    H[(j + 1) * m + j] = from_real(nrm, T());
+    for (int i = threadIdx.x; i <= j; i += kThreads) {
+        col[i] = h1[i] + h2[i];
+        if (i < j) {
+            snl[i] = sn[i];
+            csl[i] = st.cs[i];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    col[j + 1] = from_real(nrm, T());
     for (int i = 0; i < j; ++i) {
-        const T a = H[i * m + j], c = H[(i + 1) * m + j];
-        H[i * m + j] = st.cs[i] * a + sn[i] * c;
-        H[(i + 1) * m + j] = st.cs[i] * c - conj_(sn[i]) * a;
+        const T a = col[i], c = col[i + 1];
+        col[i] = csl[i] * a + snl[i] * c;
+        col[i + 1] = csl[i] * c - conj_(snl[i]) * a;
     }
-    const T a = H[j * m + j], c = H[(j + 1) * m + j];
+    const T a = col[j], c = col[j + 1];
     const double na = absval(a), nc = absval(c), nu = sqrt(na * na + nc * nc);
+    double cj;
+    T sj;
     if (na == 0.0) {
-        st.cs[j] = 0.0;
-        sn[j] = from_real(1.0, T());
+        cj = 0.0;
+        sj = from_real(1.0, T());
     } else {
-        st.cs[j] = na / nu;
-        sn[j] = (a * (1.0 / na)) * conj_(c) * (1.0 / nu);
+        cj = na / nu;
+        sj = (a * (1.0 / na)) * conj_(c) * (1.0 / nu);
     }
-    H[j * m + j] = st.cs[j] * a + sn[j] * c;
+    st.cs[j] = cj;
+    sn[j] = sj;
+    col[j] = cj * a + sj * c;
+    for (int i = 0; i <= j; ++i) H[i * m + j] = col[i];
     H[(j + 1) * m + j] = zero<T>();
     const T gj = g[j];
-    g[j] = st.cs[j] * gj;
-    g[j + 1] = zero<T>() - conj_(sn[j]) * gj;
+    g[j] = cj * gj;
+    g[j + 1] = zero<T>() - conj_(sj) * gj;
     st.scal[2 + j] = absval(g[j + 1]);
 }
 
