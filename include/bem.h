@@ -181,6 +181,19 @@ void bem_space_destroy(bem_space s);
 int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, void* b_dev,
             int64_t ldb, hipStream_t stream);
 
+/* Load vectors from user data (Sec. 4 "Boundary Values" takes the Dirichlet data as a
+ * function; here it is sampled where the quadrature needs it).  bem_rhs_quadpoints writes
+ * the number of quadrature points, nelem * 64, to *npts and, if xyz_dev is not NULL, the
+ * points themselves (device, npts x 3 row-major; point e * 64 + 8 a1 + a2 is Gauss point
+ * (a1, a2) of element e = (patch, i1, i2), the rule of bem_rhs).  bem_rhs_from_samples
+ * computes b_g = int_Gamma g psi_g by that rule from g_dev (device, npts x nrhs
+ * column-major, leading dimension ldg >= npts; FP64, interleaved complex for Helmholtz)
+ * into b_dev (N x nrhs, ldb >= N, written).  With samples of a built-in data function it
+ * reproduces bem_rhs. */
+int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t stream);
+int bem_rhs_from_samples(bem_space s, const void* g_dev, int64_t ldg, int nrhs, void* b_dev, int64_t ldb,
+                         hipStream_t stream);
+
 /* Host plan of the compressed system matrix (Sec. 4 "System Matrix"): cluster tree on the
  * patches' parameter squares, block partition into admissible (far) cluster pairs and
  * near leaf pairs, near-field sparsity pattern, touching element pairs.  Creates *out (no

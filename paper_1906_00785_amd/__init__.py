@@ -73,6 +73,21 @@ class Space:
         C.bem_rhs(self.h, data_kind, params, len(params), b.data_ptr(), self.ndof, _stream())
         return b
 
+    def quadpoints(self) -> torch.Tensor:
+        """The load vector's quadrature points, tensor (npts, 3) on the GPU."""
+        n = C.bem_rhs_quadpoints(self.h, None, _stream())
+        xyz = torch.empty((n, 3), dtype=torch.float64, device=_dev())
+        C.bem_rhs_quadpoints(self.h, xyz.data_ptr(), _stream())
+        return xyz
+
+    def rhs_from_samples(self, g: torch.Tensor) -> torch.Tensor:
+        """Load vectors from data sampled at quadpoints(): g of shape (nrhs, npts) or (npts,)."""
+        gg = g.reshape(-1, g.shape[-1]).to(self.dtype).contiguous()
+        assert gg.is_cuda
+        b = torch.empty((gg.shape[0], self.ndof), dtype=self.dtype, device=_dev())
+        C.bem_rhs_from_samples(self.h, gg.data_ptr(), gg.shape[1], gg.shape[0], b.data_ptr(), self.ndof, _stream())
+        return b if g.dim() > 1 else b[0]
+
     def potential(self, pts, rho: torch.Tensor) -> torch.Tensor:
         """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,)."""
         pts = torch.as_tensor(np.asarray(pts, dtype=np.float64)).to(_dev()).contiguous()

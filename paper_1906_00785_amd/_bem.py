@@ -59,6 +59,8 @@ _SIGNATURES = {
     "bem_space_ndof": (_c_int, [_vp, _P(_c_i64)]),
     "bem_space_destroy": (None, [_vp]),
     "bem_rhs": (_c_int, [_vp, _c_int, _P(_c_dbl), _c_int, _vp, _c_i64, _vp]),
+    "bem_rhs_quadpoints": (_c_int, [_vp, _vp, _P(_c_i64), _vp]),
+    "bem_rhs_from_samples": (_c_int, [_vp, _vp, _c_i64, _c_int, _vp, _c_i64, _vp]),
     "bem_assemble_plan": (_c_int, [_vp, _P(bem_h2_params), _P(_vp), _P(bem_operator_info)]),
     "bem_assemble": (_c_int, [_vp, _vp, _c_sz, _vp, _c_sz, _vp]),
     "bem_operator_info_get": (_c_int, [_vp, _P(bem_operator_info)]),
@@ -165,6 +167,16 @@ def bem_space_destroy(s: int):
 def bem_rhs(s: int, data_kind: int, data_params, nrhs: int, b_ptr: int, ldb: int, stream: int):
     flat = [float(v) for row in data_params for v in row]
     check(lib.bem_rhs(s, data_kind, _dbl_array(flat), nrhs, b_ptr, ldb, stream))
+
+
+def bem_rhs_quadpoints(s: int, xyz_ptr, stream: int) -> int:
+    n = ctypes.c_int64()
+    check(lib.bem_rhs_quadpoints(s, xyz_ptr, ctypes.byref(n), stream))
+    return n.value
+
+
+def bem_rhs_from_samples(s: int, g_ptr: int, ldg: int, nrhs: int, b_ptr: int, ldb: int, stream: int):
+    check(lib.bem_rhs_from_samples(s, g_ptr, ldg, nrhs, b_ptr, ldb, stream))
 
 
 def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int, chunk_cols: int = 0,

@@ -767,6 +767,27 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
     return BEM_OK;
 }
 
+int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t stream) {
+    if (!s || !npts) return fail(BEM_EINVAL, "NULL argument");
+    *npts = s->S.nelem * 64;
+    if (xyz_dev) HIP_CHECK(launch_quadpoints(s->S, gauss8(), xyz_dev, stream));
+    return BEM_OK;
+}
+
+int bem_rhs_from_samples(bem_space s, const void* g_dev, int64_t ldg, int nrhs, void* b_dev, int64_t ldb,
+                         hipStream_t stream) {
+    if (!s || !g_dev || !b_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
+    if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
+    if (ldg < s->S.nelem * 64) return fail(BEM_EINVAL, "ldg must be >= the number of quadrature points");
+    const Gauss8 g8 = gauss8();
+    const size_t sc = s->S.ker.pde == PDE_HELMHOLTZ ? 16 : 8;
+    for (int r = 0; r < nrhs; ++r)
+        HIP_CHECK(launch_rhs_samples(s->S, s->bt, g8, (const char*)g_dev + r * ldg * sc, (char*)b_dev + r * ldb * sc,
+                                     stream));
+    return BEM_OK;
+}
+
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr, int nrhs,
                        void* u_dev, int64_t ldu, hipStream_t stream) {
     if (!s || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");

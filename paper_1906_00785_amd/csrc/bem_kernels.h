@@ -157,6 +157,10 @@ hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st
 // load vector (one RHS) and potential (one RHS)
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,
                       void* b, hipStream_t st);
+// the load vector's quadrature points (nelem * 64 x 3) and the load vector from data sampled there
+hipError_t launch_quadpoints(const SpaceDesc& S, const Gauss8& g8, double* xyz, hipStream_t st);
+hipError_t launch_rhs_samples(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const void* gv, void* b,
+                              hipStream_t st);
 hipError_t launch_potential(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const double* pts,
                             int64_t npts, const void* rho, void* u, hipStream_t st);
 

@@ -1150,6 +1150,47 @@ __global__ __launch_bounds__(256) void k_rhs(SpaceDesc S, BasisTab bt, Gauss8 g8
     if (lane == 0) b[g] = s;
 }
 
+// The load vector's quadrature points: point e * 64 + 8 a1 + a2 is the Gauss point (a1, a2)
+// of element e = (patch, i1, i2), as used by k_rhs.
+__global__ __launch_bounds__(256) void k_quadpoints(SpaceDesc S, Gauss8 g8, double* xyz) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= S.nelem * 64) return;
+    const int64_t e = p / 64;
+    const int q = (int)(p % 64), a1 = q >> 3, a2 = q & 7;
+    const int i2 = (int)(e % S.nel), i1 = (int)((e / S.nel) % S.nel), f = (int)(e / ((int64_t)S.nel * S.nel));
+    double x[3];
+    patch_point(S.geom, f, (i1 + g8.x[a1]) * S.h, (i2 + g8.x[a2]) * S.h, x);
+    xyz[3 * p] = x[0];
+    xyz[3 * p + 1] = x[1];
+    xyz[3 * p + 2] = x[2];
+}
+
+// b_g from data sampled at those points (gv[e * 64 + q]): the quadrature of k_rhs with
+// the samples in place of the built-in data
+template <class T>
+__global__ __launch_bounds__(256) void k_rhs_samples(SpaceDesc S, BasisTab bt, Gauss8 g8, const T* __restrict__ gv,
+                                                     T* b) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= S.ndof) return;
+    const int nb = S.nb, d = S.d, r = S.r;
+    const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
+    const int a1 = lane >> 3, a2 = lane & 7;
+    T acc = zero<T>();
+    const int i1lo = j1 - d <= 0 ? 0 : (j1 - d + r - 1) / r, i1hi = min(j1 / r, S.nel - 1);
+    const int i2lo = j2 - d <= 0 ? 0 : (j2 - d + r - 1) / r, i2hi = min(j2 / r, S.nel - 1);
+    for (int i1 = i1lo; i1 <= i1hi; ++i1)
+        for (int i2 = i2lo; i2 <= i2hi; ++i2) {
+            const int l1 = j1 - i1 * r, l2 = j2 - i2 * r;
+            if (l1 > d || l2 > d) continue;
+            const double phi = basis_eval(bt, basis_class(bt, i1), l1, g8.x[a1]) *
+                               basis_eval(bt, basis_class(bt, i2), l2, g8.x[a2]);
+            acc += gv[elem_id(S, f, i1, i2) * 64 + lane] * (g8.w[a1] * g8.w[a2] * S.h * S.h * phi);
+        }
+    const T s = wave_sum(acc);
+    if (lane == 0) b[g] = s;
+}
+
 // u(x_p) = sum_e 8x8 Gauss sum of k(x_p, y) rho_hat(y); one workgroup per point
 template <class T>
 __global__ __launch_bounds__(256) void k_potential(SpaceDesc S, BasisTab bt, Gauss8 g8, const double* pts,
@@ -1443,6 +1484,23 @@ hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, 
         hipLaunchKernelGGL(k_rhs<cdbl>, g, blk, 0, st, S, bt, g8, kind, prm[0], prm[1], prm[2], (cdbl*)b);
     else
         hipLaunchKernelGGL(k_rhs<double>, g, blk, 0, st, S, bt, g8, kind, prm[0], prm[1], prm[2], (double*)b);
+    return hipGetLastError();
+}
+
+hipError_t launch_quadpoints(const SpaceDesc& S, const Gauss8& g8, double* xyz, hipStream_t st) {
+    const int64_t n = S.nelem * 64;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_quadpoints, dim3(nblk(n, 256)), dim3(256), 0, st, S, g8, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_samples(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const void* gv, void* b,
+                              hipStream_t st) {
+    const dim3 g(nblk(S.ndof, 4)), blk(256);
+    if (S.ker.pde == PDE_HELMHOLTZ)
+        hipLaunchKernelGGL(k_rhs_samples<cdbl>, g, blk, 0, st, S, bt, g8, (const cdbl*)gv, (cdbl*)b);
+    else
+        hipLaunchKernelGGL(k_rhs_samples<double>, g, blk, 0, st, S, bt, g8, (const double*)gv, (double*)b);
     return hipGetLastError();
 }
 

@@ -135,6 +135,30 @@ def test_rhs_and_potential(B, orc):
     assert u.numel() == 0
 
 
+@pytest.mark.parametrize("geom,prm,pde,kappa,kind", [
+    (0, (), 0, 0.0, 0), (1, (0.7, 1.2, 1.6), 1, 2.5, 1), (2, (1.0, 0.4), 1, 1.5 + 0.3j, 0), (3, (2.0,), 0, 0.0, 0)])
+def test_rhs_from_samples(B, geom, prm, pde, kappa, kind):
+    """Data sampled at the exported quadrature points gives the built-in load vector (the
+    same rule; only the data's rounding differs), and the points lie on the surface."""
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, pde, kappa, degree=2, level=2)
+    pts = s.quadpoints()
+    assert pts.shape[1] == 3 and pts.shape[0] % 64 == 0 and pts.shape[0] >= s.ndof
+    p = W.CONFIGS[0]["x0"] if kind == 0 else (0.6, 0.0, 0.8)
+    pt = torch.tensor(p, dtype=torch.float64, device=pts.device)
+    kap = complex(kappa)
+    if kind == 0:
+        r = (pts - pt).norm(dim=1)
+        gv = (torch.exp(-1j * kap * r.to(torch.complex128)) if pde else torch.ones_like(r)) / (4 * math.pi * r)
+    else:
+        gv = torch.exp(-1j * kap * (pts @ pt).to(torch.complex128))
+    b = s.rhs_from_samples(gv if pde else gv.real)
+    bref = s.rhs(B.BEM_DATA_POINT_SOURCE if kind == 0 else B.BEM_DATA_PLANE_WAVE, [p])[0]
+    assert relerr(b.cpu().numpy(), bref.cpu().numpy()) <= 1e-13
+    if geom == 0:
+        assert float((pts.norm(dim=1) - 1.0).abs().max()) <= 1e-14
+
+
 @pytest.mark.parametrize("cid", ["sphere_L2_d1_laplace_h2", "sphere_L2_d1_helmholtz_h2",
                                  "ellipsoid_L2_d2_helmholtz_cplx_h2"])
 def test_gmres(B, orc, cid):
