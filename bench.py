@@ -420,6 +420,24 @@ def main():
         return t, st_ms
 
     extra = {}
+    # plain device copy of 1 GiB (read + write): the attainable streaming bandwidth
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del src, dst
+    roof_st["frac_of_copy"] = achieved_st / copy_gbs
+    extra["copy_gbs"] = copy_gbs
+    print(f"bench: 1 GiB device copy {copy_gbs:.0f} GB/s; stored-block coupling at {achieved_st / copy_gbs:.2f} of it",
+          file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)  # 1 GiB
         dst = torch.empty_like(src)

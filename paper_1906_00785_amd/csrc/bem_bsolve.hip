@@ -13,6 +13,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kC = 64;  // right-hand sides per wave
 constexpr int kJT = 4;  // inner products per block of the dots kernel
+constexpr int kGivensThreads = 16;  // right-hand sides per block of the rotation kernel (LDS)
 
 __device__ inline double absval(double v) { return fabs(v); }
 __device__ inline double absval(cdbl v) { return sqrt(v.re * v.re + v.im * v.im); }
@@ -71,9 +72,16 @@ template <class T>
 __global__ __launch_bounds__(kT) void kbs_reduce(int S, int R, int k, const T* __restrict__ part, T* __restrict__ h) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= (int64_t)k * R) return;
-    T s = zero<T>();
-    for (int b = 0; b < S; ++b) s += part[(int64_t)b * k * R + i];
-    h[i] = s;
+    // eight interleaved partial sums (independent loads in flight), added in a fixed order
+    T s8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] = zero<T>();
+    int b = 0;
+    for (; b + 8 <= S; b += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += part[(int64_t)(b + u) * k * R + i];
+    for (; b < S; ++b) s8[0] += part[(int64_t)b * k * R + i];
+    h[i] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
 }
 
 // w[g][r] -= sum_{j<k} V_j[g][r] h[j][r] over the slice; with norm != 0 also the partial
@@ -131,9 +139,13 @@ __global__ __launch_bounds__(kT) void kbs_residual(int64_t n, int R, const T* __
 }
 
 __device__ inline double norm_of(const double* npart, int S, int R, int r) {
-    double s = 0.0;
-    for (int b = 0; b < S; ++b) s += npart[(int64_t)b * R + r];
-    return sqrt(s);
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 8 <= S; b += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += npart[(int64_t)(b + u) * R + r];
+    for (; b < S; ++b) s8[0] += npart[(int64_t)b * R + r];
+    return sqrt(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
 }
 
 // per right-hand side: beta = ||w||, g = beta e_1, sc = 1/beta (0 if beta = 0)
@@ -161,36 +173,53 @@ __global__ __launch_bounds__(kT) void kbs_scale(int64_t n, int R, const T* __res
 // the previous rotations, a new rotation, the rotated right-hand side g, the residual
 // estimate est[j][r] = |g_{j+1}| and the scale 1/||w|| of the next basis vector
 template <class T>
-__global__ void kbs_givens(int S, int R, int m, int j, const double* __restrict__ npart, const T* __restrict__ h1,
-                           const T* __restrict__ h2, BGmresState st) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kGivensThreads) void kbs_givens(int S, int R, int m, int j, const double* __restrict__ npart,
+                                                           const T* __restrict__ h1, const T* __restrict__ h2,
+                                                           BGmresState st) {
+    // the new column and the previous rotations of each right-hand side staged in LDS
+    // (one column of kGivensThreads right-hand sides per block), then the serial rotation
+    // chain on LDS
+    __shared__ T col[kMaxRestart + 1][kGivensThreads];
+    __shared__ T snl[kMaxRestart][kGivensThreads];
+    __shared__ double csl[kMaxRestart][kGivensThreads];
+    const int tl = threadIdx.x;
+    const int r = blockIdx.x * kGivensThreads + tl;
     if (r >= R) return;
     const double nrm = norm_of(npart, S, R, r);
     T* H = (T*)st.H + (int64_t)r * (m + 1) * m;
     double* cs = st.cs + (int64_t)r * m;
     T* sn = (T*)st.sn + (int64_t)r * m;
     T* g = (T*)st.g + (int64_t)r * (m + 1);
-    for (int i = 0; i <= j; ++i) H[i * m + j] = h1[(int64_t)i * R + r] + h2[(int64_t)i * R + r];
-    H[(j + 1) * m + j] = from_real(nrm, T());
+    for (int i = 0; i <= j; ++i) col[i][tl] = h1[(int64_t)i * R + r] + h2[(int64_t)i * R + r];
     for (int i = 0; i < j; ++i) {
-        const T a = H[i * m + j], c = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * c;
-        H[(i + 1) * m + j] = cs[i] * c - conj_(sn[i]) * a;
+        csl[i][tl] = cs[i];
+        snl[i][tl] = sn[i];
     }
-    const T a = H[j * m + j], c = H[(j + 1) * m + j];
+    col[j + 1][tl] = from_real(nrm, T());
+    for (int i = 0; i < j; ++i) {
+        const T a = col[i][tl], c = col[i + 1][tl];
+        col[i][tl] = csl[i][tl] * a + snl[i][tl] * c;
+        col[i + 1][tl] = csl[i][tl] * c - conj_(snl[i][tl]) * a;
+    }
+    const T a = col[j][tl], c = col[j + 1][tl];
     const double na = absval(a), nc = absval(c), nu = sqrt(na * na + nc * nc);
+    double cj;
+    T sj;
     if (na == 0.0) {
-        cs[j] = 0.0;
-        sn[j] = from_real(1.0, T());
+        cj = 0.0;
+        sj = from_real(1.0, T());
     } else {
-        cs[j] = na / nu;
-        sn[j] = (a * (1.0 / na)) * conj_(c) * (1.0 / nu);
+        cj = na / nu;
+        sj = (a * (1.0 / na)) * conj_(c) * (1.0 / nu);
     }
-    H[j * m + j] = cs[j] * a + sn[j] * c;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j][tl] = cj * a + sj * c;
+    for (int i = 0; i <= j; ++i) H[i * m + j] = col[i][tl];
     H[(j + 1) * m + j] = zero<T>();
     const T gj = g[j];
-    g[j] = cs[j] * gj;
-    g[j + 1] = zero<T>() - conj_(sn[j]) * gj;
+    g[j] = cj * gj;
+    g[j + 1] = zero<T>() - conj_(sj) * gj;
     st.est[(int64_t)j * R + r] = absval(g[j + 1]);
     st.sc[r] = nrm > 0.0 ? 1.0 / nrm : 0.0;
 }
@@ -313,12 +342,12 @@ hipError_t bsolve_start(int cplx, int64_t n, int R, const double* npart, const v
 hipError_t bsolve_givens_scale(int cplx, int64_t n, int R, int j, const double* npart, const void* h1, const void* h2,
                                const void* w, void* vnext, const BGmresState& st, hipStream_t s) {
     if (cplx) {
-        hipLaunchKernelGGL(kbs_givens<cdbl>, dim3(nb(R, 64)), dim3(64), 0, s, kBSolveSlices, R, st.m, j, npart,
+        hipLaunchKernelGGL(kbs_givens<cdbl>, dim3(nb(R, kGivensThreads)), dim3(kGivensThreads), 0, s, kBSolveSlices, R, st.m, j, npart,
                            (const cdbl*)h1, (const cdbl*)h2, st);
         hipLaunchKernelGGL(kbs_scale<cdbl>, dim3(nb(n * R, kT)), dim3(kT), 0, s, n, R, (const cdbl*)w, st.sc,
                            (cdbl*)vnext);
     } else {
-        hipLaunchKernelGGL(kbs_givens<double>, dim3(nb(R, 64)), dim3(64), 0, s, kBSolveSlices, R, st.m, j, npart,
+        hipLaunchKernelGGL(kbs_givens<double>, dim3(nb(R, kGivensThreads)), dim3(kGivensThreads), 0, s, kBSolveSlices, R, st.m, j, npart,
                            (const double*)h1, (const double*)h2, st);
         hipLaunchKernelGGL(kbs_scale<double>, dim3(nb(n * R, kT)), dim3(kT), 0, s, n, R, (const double*)w, st.sc,
                            (double*)vnext);
