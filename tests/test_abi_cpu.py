@@ -2,6 +2,7 @@
 declares, validates its arguments, and its host plan (cluster tree, block partition, near
 pattern) equals the oracle's.  No compute call touches a GPU here."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -125,3 +126,14 @@ def test_plan_counts_at_full_size(B, orc):
     # touching element pairs: identical + edge + vertex = nelem + 4 nelem + (4 nelem - 24)
     ne = 6 * 64 * 64
     assert A.info.ntouch == ne + 4 * ne + 4 * ne - 24
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before touching a GPU."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
