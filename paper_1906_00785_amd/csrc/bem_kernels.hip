@@ -720,7 +720,7 @@ __device__ inline void rinv_nr(const double* r2, double* y) {
     }
 }
 
-// sin x and cos x for 0 <= x < 2^20: x = k pi/2 + y with |y| <= pi/4 (pi/2 split into three
+// sin x and cos x for |x| < 2^20: x = k pi/2 + y with |y| <= pi/4 (pi/2 split into three
 // doubles, each product subtracted with one rounding), then the Taylor series of sin and
 // cos about 0 through y^17 and y^18 (truncation below 1e-19 at pi/4) and the quadrant k mod 4.
 __device__ inline void sincos_reduced(double x, double* sn, double* cs) {
@@ -768,7 +768,7 @@ __device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cd
     for (int u = 0; u < NS; ++u) {
         const double r = r2[u] * ir[u];
         double sn, cs;
-        sincos_reduced(k.kre * r, &sn, &cs);  // 0 <= Re kappa r < 2^20, checked at planning
+        sincos_reduced(k.kre * r, &sn, &cs);  // |Re kappa| r < 2^20, checked at planning
         const double mag = k.kim != 0.0 ? ir[u] * exp(k.kim * r) : ir[u];
         kv[u] = {mag * cs, -mag * sn};
     }

@@ -26,6 +26,7 @@ CASES = {
     "ellipsoid_L2_d2_helmholtz_cplx": (1, (0.7, 1.2, 1.6), 1, 1.5 + 0.3j, 2, 2, 4, 1),
     "sphere_L3_d0_laplace_q8": (0, (), 0, 0.0, 3, 0, 8, 1),
     "flat_L3_d1_laplace_q1": (3, (2.0,), 0, 0.0, 3, 1, 1, 3),
+    "torus_L2_d1_helmholtz_negative_kappa": (2, (1.0, 0.4), 1, -2.0, 2, 1, 4, 1),
 }
 
 
