@@ -181,3 +181,21 @@ def test_stage_launches_compose_to_apply(B, orc, cid):
         with pytest.raises(B._bem.BemError) as e:
             A.apply_stage(4, x, y2)
         assert e.value.code == B._bem.BEM_EINVAL
+
+
+def test_block_jacobi_solve(B, orc):
+    """Block-Jacobi right preconditioning on the on-the-fly operator (its blocks come from
+    the near field only): same iteration count as on the stored operator to within one, and
+    the true residual meets the tolerance."""
+    s, Ast, Aot, So, Ho = ops(B, orc, "sphere_L3_d2_helmholtz")
+    d = W.unit_vectors(W.rng(7, 17), 1)
+    b = s.rhs(B.BEM_DATA_PLANE_WAVE, d)
+    res = []
+    for A in (Ast, Aot):
+        A.precond_build()
+        x, st = A.solve(b, tol=1e-10, restart=30, maxit=400, precond=True)
+        assert st[0][1]
+        r = (b[0] - A.apply(x[0])).norm() / b[0].norm()
+        assert float(r) <= 1e-10
+        res.append(st[0][0])
+    assert abs(res[0] - res[1]) <= 1
