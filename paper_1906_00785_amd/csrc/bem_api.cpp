@@ -167,6 +167,7 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
             bd.Af = b.take<char>(np * bf_row_tiles(A.cplx) * kBatchChunk * 16);
             bd.Bf = b.take<char>((size_t)p.ncl * nch * bf_col_tiles(A.cplx) * kBatchChunk * 16);
         }
+        if (A.far_low == 1) bd.mlow = b.take<char>((size_t)p.ncl * p.q2 * Rb * (A.scal / 2));
         if (bdo) *bdo = bd;
     }
     if (d) *d = o;

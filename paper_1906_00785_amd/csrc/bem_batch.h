@@ -48,6 +48,7 @@ struct BatchDev {
     // moments of every cluster
     void* Af;                   // [npairs][RT][64 lanes] x 8 bf16
     void* Bf;                   // [ncl][nchunks][NT][64 lanes] x 8 bf16
+    void* mlow;                 // FP32 copy of the moments' slab (FP32 coupling), or null
 };
 
 // fragment counts of the BF16 coupling: row tiles of 16 (real: K padded to 32 rows;

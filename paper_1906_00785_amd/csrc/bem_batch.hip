@@ -642,6 +642,13 @@ struct Mfma16<float> {
 // NTW column tiles of 16 right-hand sides.  Per step of 4 source nodes b, lane l takes
 // A[16 i + l % 16][b] from the staged block and B[b][l % 16] of each column tile from the
 // moments' slab (zero past q^2); a complex product is four real products.
+// the moments' slab rounded to FP32 (read by the FP32 coupling at half the bytes)
+template <class T, class F>
+__global__ __launch_bounds__(256) void kb_moments_low(int64_t n, const T* __restrict__ m, F* __restrict__ ml) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) ml[i] = cvt<F>(m[i]);
+}
+
 template <class T, class F, int Q, int NTW>
 __global__ __launch_bounds__(256) void kb_coupling_mx(OpDev op, BatchDev bd, const F* __restrict__ K) {
     constexpr int Q2 = Q * Q;
@@ -667,7 +674,10 @@ __global__ __launch_bounds__(256) void kb_coupling_mx(OpDev op, BatchDev bd, con
         on[j] = rr[j] < R;
     }
     const int64_t beg = bd.far_rowptr[t], end = bd.far_rowptr[t + 1];
+    // FP32 arithmetic reads the FP32 copy of the moments when there is one
+    constexpr bool kLow = sizeof(F) < sizeof(T);
     const T* __restrict__ mom = (const T*)bd.mom;
+    const F* __restrict__ moml = (const F*)bd.mlow;
     A4 ar[RT][NTW], ai[RT][NTW];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -702,15 +712,17 @@ __global__ __launch_bounds__(256) void kb_coupling_mx(OpDev op, BatchDev bd, con
     __syncthreads();
     for (int64_t p = beg; p < end; ++p) {
         if (p + 1 < end) load_block(p + 1);
-        const T* __restrict__ ms = mom + (int64_t)bd.far_s[p] * Q2 * R;
+        const int64_t mo = (int64_t)bd.far_s[p] * Q2 * R;
         const F* kb = ks[buf];
         F bv[KS][NTW];
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int b = 4 * k + kq;
 #pragma unroll
-            for (int j = 0; j < NTW; ++j)
-                bv[k][j] = (b < Q2 && on[j]) ? cvt<F>(ms[(int64_t)b * R + rr[j]]) : zero_f<F>();
+            for (int j = 0; j < NTW; ++j) {
+                const int64_t idx = mo + (int64_t)b * R + rr[j];
+                bv[k][j] = !(b < Q2 && on[j]) ? zero_f<F>() : (kLow && moml ? moml[idx] : cvt<F>(mom[idx]));
+            }
         }
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
@@ -771,6 +783,12 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
             hipLaunchKernelGGL((kb_upward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
         }
         if (prec == 2) hipLaunchKernelGGL((kb_bf_moments<T, Q>), dim3(nblk(op.ncl * nch, 4)), dim3(256), 0, st, op, bd);
+        if (prec == 1 && bd.mlow) {
+            using F32 = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
+            const int64_t nm = op.ncl * op.q2 * (int64_t)R;
+            hipLaunchKernelGGL((kb_moments_low<T, F32>), dim3(nblk(nm, 256)), dim3(256), 0, st, nm, (const T*)bd.mom,
+                               (F32*)bd.mlow);
+        }
     } else if (stage == 1) {
         const unsigned nb = (unsigned)(op.ncl * nch);
         using F32 = typename std::conditional<sizeof(T) == 16, cflt, float>::type;
