@@ -100,6 +100,10 @@ typedef struct bem_h2_params {
                          sampled at the interpolation points).  Needs far_low = 0 and
                          batch_rhs <= 1; bem_export_far then returns BEM_EUNSUPPORTED.
                          0: blocks computed once at assembly and stored               */
+    double kappa_adm; /* Helmholtz: a far pair also needs |kappa| * 2 max(r_t, r_s) <= kappa_adm,
+                         so that q nodes resolve the kernel's oscillation over the clusters
+                         (survey reading of the paper's silence on large wavenumbers); 0: no
+                         such bound.  Ignored for Laplace. */
 } bem_h2_params;
 
 /* arithmetic of the far-field coupling in bem_apply_ex / refined solves */

@@ -65,7 +65,7 @@ def lib():
             "orc_density_pairing": (I, [P, I, I, I, I, P]),
             "orc_rhs": (I, [P, I, P, I, I, P]),
             "orc_potential": (I, [P, I, P, I64, P, P]),
-            "orc_h2_new": (I, [P, I, D, I, I, I, I, P]),
+            "orc_h2_new": (I, [P, I, D, I, I, I, I, D, P]),
             "orc_h2_free": (None, [P]),
             "orc_h2_info": (I, [P, P]),
             "orc_h2_lists": (I, [P, P, P]),
@@ -212,10 +212,11 @@ class H2:
     """H^2 operator of a Space (near field optional: assemble_near=False keeps it lazy)."""
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf: int = 0, qg: int = 8,
-                 qs: int = 8, assemble_near: bool = True):
+                 qs: int = 8, assemble_near: bool = True, kappa_adm: float = 0.0):
         self.space = space
         h = ctypes.c_void_p()
-        _check(lib().orc_h2_new(space._h, q, eta, leaf, qg, qs, int(assemble_near), ctypes.byref(h)))
+        _check(lib().orc_h2_new(space._h, q, eta, leaf, qg, qs, int(assemble_near), float(kappa_adm),
+                                ctypes.byref(h)))
         self._h = h
         self.q, self.eta, self.leaf = q, eta, leaf
         info = np.zeros(6, dtype=np.int64)

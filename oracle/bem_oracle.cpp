@@ -712,6 +712,7 @@ struct H2 {
     const Space* S = nullptr;
     int q = 5, leaf = 0, qg = 8, qs = 8, qm = 1;
     double eta = 1.6;
+    double kadm = 0.0;  // reading A12: |kappa| 2 max(r) <= kadm for a far pair (0: no bound)
     std::vector<int64_t> lev_off;  // first cluster index of every level, plus the total
     std::vector<Cluster> cl;
     std::vector<std::pair<int64_t, int64_t>> far;   // (target, source), sorted
@@ -759,11 +760,21 @@ static bool admissible(const Cluster& A, const Cluster& B, double eta) {
     return lhs <= rhs;
 }
 
+// reading A12: the interpolation degree resolves the kernel's oscillation only while the
+// wavenumber times the larger cluster diameter stays below kadm (ties inadmissible)
+static bool resolved(const Cluster& A, const Cluster& B, double kabs, double kadm) {
+    if (!(kadm > 0.0) || kabs == 0.0) return true;
+    const double lhs = kabs * 2.0 * std::max(A.rad, B.rad);
+    if (std::fabs(lhs - kadm) <= 1e-12 * kadm) return false;
+    return lhs <= kadm;
+}
+
 template <class T>
 static void h2_partition(H2<T>& H, int64_t t, int64_t s) {
     const Cluster& A = H.cl[t];
     const Cluster& B = H.cl[s];
-    if (admissible(A, B, H.eta)) {
+    const double kabs = H.S->pde == PDE_HELMHOLTZ ? std::abs(H.S->kappa) : 0.0;
+    if (admissible(A, B, H.eta) && resolved(A, B, kabs, H.kadm)) {
         H.far.push_back({t, s});
         return;
     }
@@ -798,12 +809,13 @@ static void leaf_elements(const H2<T>& H, int64_t c, std::vector<int64_t>& els) 
 
 template <class T>
 static void h2_build(H2<T>& H, const Space& S, int q, double eta, int leaf, int qg, int qs,
-                     bool assemble_near) {
+                     bool assemble_near, double kadm) {
     if (leaf < 0 || leaf > S.K.L) throw std::runtime_error("leaf level must lie in [0, L]");
     if (q < 1) throw std::runtime_error("q must be positive");
     H.S = &S;
     H.q = q;
     H.eta = eta;
+    H.kadm = kadm;
     H.leaf = leaf;
     H.qg = qg;
     H.qs = qs;
@@ -1650,7 +1662,7 @@ int orc_potential(void* sp, int q, const double* rho, int64_t npts, const double
     })
 }
 
-int orc_h2_new(void* sp, int q, double eta, int leaf, int qg, int qs, int assemble_near, void** out) {
+int orc_h2_new(void* sp, int q, double eta, int leaf, int qg, int qs, int assemble_near, double kadm, void** out) {
     ORC_TRY({
         OrcH2* h = new OrcH2;
         h->sp = (OrcSpace*)sp;
@@ -1658,9 +1670,9 @@ int orc_h2_new(void* sp, int q, double eta, int leaf, int qg, int qs, int assemb
         h->cplx_ = is_cplx(S);
         try {
             if (h->cplx_)
-                h2_build(h->hc, S, q, eta, leaf, qg, qs, assemble_near != 0);
+                h2_build(h->hc, S, q, eta, leaf, qg, qs, assemble_near != 0, kadm);
             else
-                h2_build(h->hr, S, q, eta, leaf, qg, qs, assemble_near != 0);
+                h2_build(h->hr, S, q, eta, leaf, qg, qs, assemble_near != 0, kadm);
         } catch (...) {
             delete h;
             throw;

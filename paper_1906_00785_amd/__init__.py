@@ -103,13 +103,13 @@ class Operator:
 
     def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
                  assemble: bool = True, chunk_cols: int = 0, far_low: int = 0, batch_rhs: int = 0,
-                 far_eval: bool = False):
+                 far_eval: bool = False, kappa_adm: float = 0.0):
         self.space = space
         self.far_low = far_low
         self.batch_rhs = batch_rhs
         self.far_eval = bool(far_eval)
         self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs,
-                                                int(far_eval))
+                                                int(far_eval), float(kappa_adm))
         self.q = q
         self.ndof = self.info.ndof
         self.op_ws = None

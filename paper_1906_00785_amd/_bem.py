@@ -24,7 +24,7 @@ _c_int, _c_dbl, _c_i64, _c_sz, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int
 class bem_h2_params(ctypes.Structure):
     _fields_ = [("q", _c_int), ("eta", _c_dbl), ("leaf_level", _c_int), ("qg", _c_int), ("qs", _c_int),
                 ("chunk_cols", _c_int), ("far_low", _c_int), ("batch_rhs", _c_int),
-                ("far_eval", _c_int)]
+                ("far_eval", _c_int), ("kappa_adm", _c_dbl)]
 
 
 class bem_operator_info(ctypes.Structure):
@@ -180,8 +180,8 @@ def bem_rhs_from_samples(s: int, g_ptr: int, ldg: int, nrhs: int, b_ptr: int, ld
 
 
 def bem_assemble_plan(s: int, q: int, eta: float, leaf_level: int, qg: int, qs: int, chunk_cols: int = 0,
-                      far_low: int = 0, batch_rhs: int = 0, far_eval: int = 0):
-    p = bem_h2_params(q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs, far_eval)
+                      far_low: int = 0, batch_rhs: int = 0, far_eval: int = 0, kappa_adm: float = 0.0):
+    p = bem_h2_params(q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs, far_eval, kappa_adm)
     h = _vp()
     info = bem_operator_info()
     check(lib.bem_assemble_plan(s, ctypes.byref(p), ctypes.byref(h), ctypes.byref(info)))

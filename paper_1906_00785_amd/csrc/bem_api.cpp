@@ -826,6 +826,8 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     P.leaf = p->leaf_level;
     P.qg = p->qg;
     P.qs = p->qs;
+    if (!(p->kappa_adm >= 0.0) || !std::isfinite(p->kappa_adm)) return fail(BEM_EINVAL, "kappa_adm must be finite and >= 0");
+    P.kadm = p->kappa_adm;
     bem_operator_s* A = new (std::nothrow) bem_operator_s;
     if (!A) return fail(BEM_ENOMEM, "host allocation failed");
     std::string err;

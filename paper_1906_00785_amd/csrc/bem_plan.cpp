@@ -181,7 +181,14 @@ struct Builder {
         const double lhs = 2.0 * std::max(A[3], B[3]);
         const double rhs = p.P.eta * gap;
         if (std::fabs(lhs - rhs) <= 1e-12 * gap) return false;  // ties are inadmissible
-        return lhs <= rhs;
+        if (!(lhs <= rhs)) return false;
+        // the interpolation resolves the oscillating kernel only while |kappa| times the
+        // larger diameter stays below kadm (ties inadmissible)
+        if (p.P.kadm > 0.0 && p.S.ker.pde == PDE_HELMHOLTZ) {
+            const double kd = std::hypot(p.S.ker.kre, p.S.ker.kim) * lhs;
+            if (std::fabs(kd - p.P.kadm) <= 1e-12 * p.P.kadm || kd > p.P.kadm) return false;
+        }
+        return true;
     }
 
     void partition(std::vector<std::pair<int32_t, int32_t>>& far,

@@ -31,6 +31,7 @@ struct H2Params {
     int qg = 8;
     int qs = 8;
     int chunk = 128;  // columns per coupling work chunk (multiple of 128)
+    double kadm = 0.0;  // far pairs also need |kappa| 2 max(r) <= kadm (Helmholtz; 0: no bound)
 };
 
 struct Plan {

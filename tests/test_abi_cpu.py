@@ -137,3 +137,27 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("kappa,kadm", [(4.0, 4.0), (12.0, 3.0), (6.0 + 1.0j, 2.5), (4.0, 0.0)])
+def test_plan_equals_oracle_wavenumber_bound(B, orc, kappa, kadm):
+    """Reading A12: with the wavenumber bound the far list equals the oracle's and is a
+    subset of the unbounded one (pairs too wide for the wavenumber are refined)."""
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, kappa, degree=1, level=3)
+    A = B.Operator(s, q=4, eta=1.6, leaf_level=3, assemble=False, kappa_adm=kadm)
+    pairs, _, _ = _plan_lists(B, A)
+    So = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, kappa, degree=1, level=3)
+    Ho = orc.H2(So, q=4, eta=1.6, leaf=3, assemble_near=False, kappa_adm=kadm)
+    far, _ = Ho.lists()
+    assert np.array_equal(far, pairs)
+    A0 = B.Operator(s, q=4, eta=1.6, leaf_level=3, assemble=False)
+    if kadm > 0:
+        assert A.info.nnear >= A0.info.nnear
+        # every far pair satisfies the bound: |kappa| times the larger cluster diameter; the
+        # clusters of a level-l pair have diameters of order 2^-l, so the coarsest far level
+        # moves down as the bound tightens
+        lev_of = lambda c: int(np.searchsorted(np.cumsum([6 * 4 ** l for l in range(4)]), c, side="right"))
+        assert min(lev_of(t) for t, _ in pairs) >= min(lev_of(t) for t, _ in _plan_lists(B, A0)[0])
+    else:
+        assert A.info.nfar == A0.info.nfar

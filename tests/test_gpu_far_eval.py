@@ -199,3 +199,28 @@ def test_block_jacobi_solve(B, orc):
         assert float(r) <= 1e-10
         res.append(st[0][0])
     assert abs(res[0] - res[1]) <= 1
+
+
+def test_wavenumber_bound_matches_oracle(B, orc):
+    """With the Helmholtz cluster-size bound |kappa| 2 max(r_t, r_s) < c (kappa_adm), the
+    device partition equals the oracle's and both kinds of far field apply the oracle's
+    operator; at kappa = 12 and c = 8 the bound turns about half the far pairs near."""
+    kappa, ka = 12.0, 8.0
+    print(f"[far_eval wavenumber bound kappa={kappa} c={ka}] assemble", flush=True)
+    g = B.Geometry(0)
+    s = B.Space(g, 1, kappa, degree=1, level=2)
+    So = orc.Space(0, [], 1, kappa, degree=1, level=2)
+    Ho = orc.H2(So, q=4, eta=1.6, leaf=2, kappa_adm=ka)
+    far, near = Ho.lists()
+    far0, _ = orc.H2(So, q=4, eta=1.6, leaf=2, assemble_near=False).lists()
+    assert 0 < len(far) < len(far0)
+    x = W.random_vector(W.rng(7, 30), s.ndof, is_complex=True, ncols=2).T.copy()
+    xd = torch.from_numpy(x).cuda()
+    yo = Ho.apply(x.T).T
+    for far_eval in (False, True):
+        A = B.Operator(s, q=4, eta=1.6, leaf_level=2, far_eval=far_eval, kappa_adm=ka)
+        assert (A.info.nfar, A.info.nnear) == (len(far), len(near))
+        if not far_eval:
+            pairs, _ = A.export_far()
+            assert np.array_equal(pairs, far)
+        assert relerr(A.apply(xd).cpu().numpy(), yo) <= TOL
