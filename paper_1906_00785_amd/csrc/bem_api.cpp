@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -90,6 +92,8 @@ struct bem_operator_s {
     size_t ev_used = 0;
     // GMRES: pinned status words and per-step events
     double* pinned = nullptr;
+    double* hstat = nullptr;  // coherent host-mapped estimates and stamps (GmresState::hest)
+    unsigned stamp = 0;
     double* bpin = nullptr;  // batched GMRES: per-RHS estimates, norms and step counts
     size_t bpin_doubles = 0;
     std::vector<hipEvent_t> sev;
@@ -97,6 +101,7 @@ struct bem_operator_s {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : sev) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
+        if (hstat) (void)hipHostFree(hstat);
         if (bpin) (void)hipHostFree(bpin);
     }
 };
@@ -278,9 +283,12 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
     return b.off + 256;
 }
 
-// One right-hand side.  Within a cycle the host enqueues Arnoldi step j and then waits
-// only for the event of step j-1 (its residual estimate, copied to pinned memory), so the
-// device always has the next step queued; the true residual is read once per cycle.
+// One right-hand side.  The Givens step of Arnoldi step j runs inside step j+1's
+// dot-product kernel and writes its residual estimate straight to coherent host memory,
+// with a stamp (no copy, no event in the stream); having enqueued step j the host waits
+// only for the estimate of step j-2, so the device always has more than a step queued.  Convergence is therefore seen up to two steps
+// late; those steps' columns are dropped, so the iterate is that of the step that
+// converged.  The true residual is read once per cycle.
 static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, int maxit, double tol,
                      bem_solve_stats* out, SolveWs& W, hipStream_t stream, bool pc = false) {
     const int64_t N = A->info.ndof;
@@ -293,6 +301,35 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
         HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         A->sev.push_back(e);
     }
+    if (!A->hstat) {
+        HIP_CHECK(hipHostMalloc((void**)&A->hstat, (sizeof(double) + sizeof(unsigned)) * kMaxRestart,
+                                hipHostMallocMapped | hipHostMallocCoherent));
+        std::memset(A->hstat, 0, (sizeof(double) + sizeof(unsigned)) * kMaxRestart);
+        A->stamp = 0;
+    }
+    {
+        void* dp = nullptr;
+        HIP_CHECK(hipHostGetDevicePointer(&dp, A->hstat, 0));
+        W.st.hest = (double*)dp;
+        W.st.hseq = (unsigned*)((double*)dp + kMaxRestart);
+    }
+    const volatile double* hest = A->hstat;
+    const volatile unsigned* hseq = (const volatile unsigned*)(A->hstat + kMaxRestart);
+    // residual estimate of step jj of the current cycle: spin on its stamp; should it not
+    // arrive within seconds (not expected), wait for the stream and copy the device value
+    auto estimate = [&](int jj, double& e) -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 1; hseq[jj] != W.st.stamp; ++spin) {
+            if ((spin & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5)) {
+                HIP_CHECK(hipStreamSynchronize(stream));
+                HIP_CHECK(hipMemcpy(&e, W.st.scal + 2 + jj, sizeof(double), hipMemcpyDeviceToHost));
+                return BEM_OK;
+            }
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        e = hest[jj];
+        return BEM_OK;
+    };
     double* pin = A->pinned;
     out->iterations = 0;
     out->converged = 0;
@@ -313,6 +350,7 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
     int total = 0;
     double relres = 1.0;
     for (int cycle = 0;; ++cycle) {
+        W.st.stamp = ++A->stamp;
         if (cycle > 0) {
             HIP_CHECK(launch_apply(A->dev, x, W.w, prec, stream));
             HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
@@ -323,6 +361,7 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
         relres = pin[0] / bnorm;
         if (relres <= tol || total >= maxit || !std::isfinite(relres)) break;
         int k = 0;
+        bool done = false;  // convergence seen: the Givens steps of columns 0..k-1 have run
         for (int j = 0; j < m && total + j < maxit; ++j) {
             if (pc) {
                 HIP_CHECK(launch_prec_apply(A->dev, A->pdev, 1, Vj(j), W.z, stream));
@@ -330,17 +369,32 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
             } else {
                 HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, prec, stream));
             }
-            HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, stream));
+            // the dot products of step j and the Givens step of step j-1
+            HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, j - 1, W.npart, W.st, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partA, W.st.h1, W.w, W.partB, W.npart, 0, stream));
             HIP_CHECK(solve_update(cp, N, j + 1, W.V, W.partB, W.st.h2, W.w, W.partA, W.npart, 1, stream));
-            HIP_CHECK(solve_scale_givens(cp, N, j, W.npart, W.w, Vj(j + 1), W.st, stream));
-            HIP_CHECK(hipMemcpyAsync(pin + 2 + j, W.st.scal + 2 + j, sizeof(double), hipMemcpyDeviceToHost, stream));
-            HIP_CHECK(hipEventRecord(A->sev[j], stream));
+            HIP_CHECK(solve_scale(cp, N, W.npart, W.w, Vj(j + 1), stream));
             k = j + 1;
-            if (j >= 1) {
-                HIP_CHECK(hipEventSynchronize(A->sev[j - 1]));
-                if (pin[2 + j - 1] <= tol * bnorm || !std::isfinite(pin[2 + j - 1])) {
-                    k = j;  // converged after step j-1; step j's column is not used
+            if (j >= 2) {
+                double e;
+                const int rc = estimate(j - 2, e);
+                if (rc != BEM_OK) return rc;
+                if (e <= tol * bnorm || !std::isfinite(e)) {
+                    k = j - 1;  // converged after step j-2; the columns of steps j-1 and j are not used
+                    done = true;
+                    break;
+                }
+            }
+        }
+        // the last step's Givens step, and the convergence check of the steps not yet read
+        if (k > 0 && !done) {
+            HIP_CHECK(solve_givens(cp, k - 1, W.npart, W.st, stream));
+            for (int j = k >= 2 ? k - 2 : 0; j < k; ++j) {
+                double e;
+                const int rc = estimate(j, e);
+                if (rc != BEM_OK) return rc;
+                if (e <= tol * bnorm || !std::isfinite(e)) {
+                    k = j + 1;
                     break;
                 }
             }

@@ -23,13 +23,20 @@ struct GmresState {
     void* h1;      // m+1 first Gram-Schmidt coefficients
     void* h2;      // m+1 second Gram-Schmidt coefficients
     double* scal;  // [0] unused, [1] beta of the cycle, [2 + j] residual estimate after step j
+    // optional host-mapped status (coherent pinned memory): after Givens step j the estimate
+    // goes to hest[j] and then stamp to hseq[j], so the host can read it without a copy
+    double* hest = nullptr;
+    unsigned* hseq = nullptr;
+    unsigned stamp = 0;
 };
 
-hipError_t solve_dots(int cplx, int64_t n, int k, const void* V, const void* w, void* part, hipStream_t s);
+// dot products of the new vector against V (k vectors); gj >= 0 also runs Givens step gj
+hipError_t solve_dots(int cplx, int64_t n, int k, const void* V, const void* w, void* part, int gj,
+                      const double* npart, const GmresState& st, hipStream_t s);
+hipError_t solve_givens(int cplx, int j, const double* npart, const GmresState& st, hipStream_t s);
+hipError_t solve_scale(int cplx, int64_t n, const double* npart, const void* w, void* vnext, hipStream_t s);
 hipError_t solve_update(int cplx, int64_t n, int k, const void* V, const void* part_in, void* hout, void* w,
                         void* part_out, double* npart, int mode, hipStream_t s);
-hipError_t solve_scale_givens(int cplx, int64_t n, int j, const double* npart, const void* w, void* vnext,
-                              const GmresState& st, hipStream_t s);
 hipError_t solve_residual(int cplx, int64_t n, const void* b, void* w, double* npart, int copy_b, hipStream_t s);
 hipError_t solve_start(int cplx, int64_t n, const double* npart, const void* w, void* v0, const GmresState& st,
                        hipStream_t s);

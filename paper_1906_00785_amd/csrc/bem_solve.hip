@@ -2,7 +2,9 @@
 // rotations and the triangular solve on the device.  Every vector kernel splits the
 // N entries into kSolveBlocks contiguous slices, one per block, and writes its per-block
 // partial sums; the next kernel reduces those partials in its prologue (fixed order, so
-// results are deterministic).
+// results are deterministic).  The Givens rotations of step j run in one extra block of
+// step j+1's dot-product kernel, beside the slices, so that their serial chain is off the
+// path from one matrix-vector product to the next.
 #include "bem_solve.h"
 
 namespace bem {
@@ -63,13 +65,6 @@ __device__ inline void slice_dots(int64_t n, int k, const T* __restrict__ V, con
     }
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_s_dots(int64_t n, int k, const T* __restrict__ V, const T* __restrict__ w,
-                                                     T* __restrict__ part) {
-    int64_t t0, t1;
-    slice(n, t0, t1);
-    slice_dots(n, k, V, w, t0, t1, part);
-}
 
 // h = sum of the partials (k values) -> w -= V h over the slice -> partials of the next
 // reduction of the updated slice: mode 0 -> V^H w (k values), mode 1 -> ||w||^2
@@ -120,21 +115,14 @@ __device__ inline double reduce_npart(const double* npart, int nb) {
     return sqrt(wsum(s));
 }
 
-// v_{j+1} = w / ||w|| over the slice; block 0 applies the Givens rotations to the new
-// Hessenberg column j (h1 + h2 above the diagonal, ||w|| below) and records the residual
-// estimate |g_{j+1}| in scal[2 + j]
+// Givens step j: the new Hessenberg column (h1 + h2 above the diagonal, ||w|| from the
+// squared-norm partials below it) is rotated by the rotations so far, the new rotation
+// annihilates its subdiagonal entry, and the residual estimate |g_{j+1}| goes to
+// scal[2 + j].  One block: the column and the rotations are staged in LDS by all threads,
+// then one thread applies the rotations (a serial chain).
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_s_scale_givens(int64_t n, int j, const double* __restrict__ npart,
-                                                             const T* __restrict__ w, T* __restrict__ vnext,
-                                                             GmresState st) {
-    const double nrm = reduce_npart(npart, gridDim.x);
-    int64_t t0, t1;
-    slice(n, t0, t1);
-    const double inv = 1.0 / nrm;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) vnext[t] = w[t] * inv;
-    if (blockIdx.x != 0) return;
-    // block 0: the new column and the rotations so far are staged in LDS by all threads,
-    // then one thread applies the rotations (a serial chain, now on LDS)
+__device__ inline void givens_body(int j, const double* __restrict__ npart, const GmresState& st) {
+    const double nrm = reduce_npart(npart, kSolveBlocks);
     __shared__ T col[66];
     __shared__ T snl[64];
     __shared__ double csl[64];
@@ -177,8 +165,48 @@ __global__ __launch_bounds__(kThreads) void k_s_scale_givens(int64_t n, int j, c
     H[(j + 1) * m + j] = zero<T>();
     const T gj = g[j];
     g[j] = cj * gj;
-    g[j + 1] = zero<T>() - conj_(sj) * gj;
-    st.scal[2 + j] = absval(g[j + 1]);
+    const T gn = zero<T>() - conj_(sj) * gj;
+    g[j + 1] = gn;
+    const double est = absval(gn);
+    st.scal[2 + j] = est;
+    if (st.hest) {
+        st.hest[j] = est;
+        __threadfence_system();  // the estimate is visible to the host before its stamp
+        *(volatile unsigned*)(st.hseq + j) = st.stamp;
+    }
+}
+
+// Dot products of step j+1 (blocks 0 .. kSolveBlocks-1, see slice_dots) and, when
+// gj >= 0, the Givens step gj in block kSolveBlocks.  The inputs of Givens step gj (h1,
+// h2, the squared-norm partials) are rewritten only by the update kernels that follow.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_s_dots(int64_t n, int k, const T* __restrict__ V, const T* __restrict__ w,
+                                                     T* __restrict__ part, int gj, const double* __restrict__ npart,
+                                                     GmresState st) {
+    if ((int)blockIdx.x == kSolveBlocks) {
+        if (gj >= 0) givens_body<T>(gj, npart, st);
+        return;
+    }
+    const int64_t len = (n + kSolveBlocks - 1) / kSolveBlocks;
+    const int64_t t0 = (int64_t)blockIdx.x * len, t1 = t0 + len < n ? t0 + len : n;
+    slice_dots(n, k, V, w, t0, t1, part);
+}
+
+// the Givens step on its own (the last step of a cycle)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_s_givens(int j, const double* __restrict__ npart, GmresState st) {
+    givens_body<T>(j, npart, st);
+}
+
+// v_{j+1} = w / ||w|| over the slice
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_s_scale(int64_t n, const double* __restrict__ npart,
+                                                      const T* __restrict__ w, T* __restrict__ vnext) {
+    const double nrm = reduce_npart(npart, gridDim.x);
+    int64_t t0, t1;
+    slice(n, t0, t1);
+    const double inv = 1.0 / nrm;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) vnext[t] = w[t] * inv;
 }
 
 // w = b - w (residual of the current iterate) and its squared-norm partials
@@ -214,18 +242,29 @@ __global__ __launch_bounds__(kThreads) void k_s_start(int64_t n, const double* _
     }
 }
 
-// y = H_k^{-1} g_k (upper triangular, k <= m), one thread
+// y = H_k^{-1} g_k (upper triangular, k <= m <= 64), one wave by columns: lane i holds the
+// running right-hand side of row i; for l = k-1 down to 0 lane l divides by H_ll and every
+// lane above the diagonal subtracts H_il y_l (its next H entry is loaded a column ahead)
 template <class T>
-__global__ void k_s_backsolve(int k, GmresState st) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_s_backsolve(int k, GmresState st) {
+    const int i = threadIdx.x;
     const int m = st.m;
     const T* H = (const T*)st.H;
-    const T* g = (const T*)st.g;
     T* y = (T*)st.y;
-    for (int i = k - 1; i >= 0; --i) {
-        T s = g[i];
-        for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
-        y[i] = div_(s, H[i * m + i]);
+    __shared__ T yl;
+    T r = i < k ? ((const T*)st.g)[i] : zero<T>();
+    T h = k >= 1 && i < k - 1 ? H[i * m + k - 1] : zero<T>();
+    for (int l = k - 1; l >= 0; --l) {
+        const T hn = l >= 1 && i < l - 1 ? H[i * m + l - 1] : zero<T>();
+        if (i == l) {
+            const T v = div_(r, H[l * m + l]);
+            y[l] = v;
+            yl = v;
+        }
+        __syncthreads();
+        if (i < l) r -= h * yl;
+        __syncthreads();
+        h = hn;
     }
 }
 
@@ -253,17 +292,38 @@ __global__ __launch_bounds__(kThreads) void k_s_axpy(int64_t n, double a, const 
 
 template <class T>
 struct Launch {
-    static hipError_t dots(int64_t n, int k, const void* V, const void* w, void* part, hipStream_t s) {
-        hipLaunchKernelGGL(k_s_dots<T>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, k, (const T*)V, (const T*)w,
-                           (T*)part);
+    static hipError_t dots(int64_t n, int k, const void* V, const void* w, void* part, int gj, const double* npart,
+                           const GmresState& st, hipStream_t s) {
+        hipLaunchKernelGGL(k_s_dots<T>, dim3(kSolveBlocks + (gj >= 0 ? 1 : 0)), dim3(kThreads), 0, s, n, k,
+                           (const T*)V, (const T*)w, (T*)part, gj, npart, st);
+        return hipGetLastError();
+    }
+    static hipError_t givens(int j, const double* npart, const GmresState& st, hipStream_t s) {
+        hipLaunchKernelGGL(k_s_givens<T>, dim3(1), dim3(kThreads), 0, s, j, npart, st);
+        return hipGetLastError();
+    }
+    static hipError_t scale(int64_t n, const double* npart, const void* w, void* vnext, hipStream_t s) {
+        hipLaunchKernelGGL(k_s_scale<T>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, npart, (const T*)w, (T*)vnext);
         return hipGetLastError();
     }
 };
 
 }  // namespace
 
-hipError_t solve_dots(int cplx, int64_t n, int k, const void* V, const void* w, void* part, hipStream_t s) {
-    return cplx ? Launch<cdbl>::dots(n, k, V, w, part, s) : Launch<double>::dots(n, k, V, w, part, s);
+hipError_t solve_dots(int cplx, int64_t n, int k, const void* V, const void* w, void* part, int gj,
+                      const double* npart, const GmresState& st, hipStream_t s) {
+    if (gj >= st.m) return hipErrorInvalidValue;
+    return cplx ? Launch<cdbl>::dots(n, k, V, w, part, gj, npart, st, s)
+                : Launch<double>::dots(n, k, V, w, part, gj, npart, st, s);
+}
+
+hipError_t solve_givens(int cplx, int j, const double* npart, const GmresState& st, hipStream_t s) {
+    if (j < 0 || j >= st.m) return hipErrorInvalidValue;
+    return cplx ? Launch<cdbl>::givens(j, npart, st, s) : Launch<double>::givens(j, npart, st, s);
+}
+
+hipError_t solve_scale(int cplx, int64_t n, const double* npart, const void* w, void* vnext, hipStream_t s) {
+    return cplx ? Launch<cdbl>::scale(n, npart, w, vnext, s) : Launch<double>::scale(n, npart, w, vnext, s);
 }
 
 hipError_t solve_update(int cplx, int64_t n, int k, const void* V, const void* part_in, void* hout, void* w,
@@ -274,17 +334,6 @@ hipError_t solve_update(int cplx, int64_t n, int k, const void* V, const void* p
     else
         hipLaunchKernelGGL(k_s_update<double>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, k, (const double*)V,
                            (const double*)part_in, (double*)hout, (double*)w, (double*)part_out, npart, mode);
-    return hipGetLastError();
-}
-
-hipError_t solve_scale_givens(int cplx, int64_t n, int j, const double* npart, const void* w, void* vnext,
-                              const GmresState& st, hipStream_t s) {
-    if (cplx)
-        hipLaunchKernelGGL(k_s_scale_givens<cdbl>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, j, npart,
-                           (const cdbl*)w, (cdbl*)vnext, st);
-    else
-        hipLaunchKernelGGL(k_s_scale_givens<double>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, j, npart,
-                           (const double*)w, (double*)vnext, st);
     return hipGetLastError();
 }
 
