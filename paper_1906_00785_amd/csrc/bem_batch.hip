@@ -535,7 +535,9 @@ __global__ __launch_bounds__(256) void kb_tile_fill(OpDev op, BatchDev bd) {
 // right-hand sides), wave w takes 16 of them.  Per step of 4 columns, lane l holds the tile
 // value A[l % 16][l / 16] and x[column l / 16][rhs l % 16]; a complex product is four real
 // products (Re, Im of A times Re, Im of x).  Four steps' fragments are loaded before their
-// products.  Epilogue: lane l holds rows l / 16 + 4 i,
+// products; the tile's column indices are staged in LDS (up to kColStage at a time), so
+// the x gathers of a round wait on one memory round trip, not two.  Epilogue: lane l
+// holds rows l / 16 + 4 i,
 // right-hand side l % 16; each adds the backward transforms of the leaves that meet its
 // B-spline and is written to ys.
 template <class T>
@@ -552,38 +554,42 @@ __global__ __launch_bounds__(256) void kb_near_mfma(OpDev op, BatchDev bd) {
     const bool on = r < R;
     const int64_t rb = bd.tile_rowptr[t], cb = bd.tile_colptr[t];
     const int nr = (int)(bd.tile_rowptr[t + 1] - rb), C = (int)(bd.tile_colptr[t + 1] - cb);
-    const int nsteps = (C + 3) / 4;
     const T* __restrict__ val = (const T*)bd.tile_val + bd.tile_voff[t] + lane;
     const int32_t* __restrict__ cols = bd.tile_cols + cb;
     const T* __restrict__ xs = (const T*)bd.xs;
     const int kk = lane >> 4;
     f64x4 ar = {0.0, 0.0, 0.0, 0.0}, ai = {0.0, 0.0, 0.0, 0.0};
-    // DEPTH steps per round: all their column indices, then all value and x loads, then
-    // the products (steps past the end carry zero values and a valid column)
-    constexpr int DEPTH = 4;
-    for (int s0 = 0; s0 < nsteps; s0 += DEPTH) {
-        int64_t h[DEPTH];
-        T a[DEPTH], xv[DEPTH];
+    // DEPTH steps per round: all their value and x loads, then the products (steps past
+    // the end carry zero values and a valid column)
+    constexpr int DEPTH = 8;
+    constexpr int kColStage = 1024;  // multiple of 4 DEPTH: a round never crosses a stage
+    static_assert(kColStage % (4 * DEPTH) == 0, "whole rounds per stage");
+    __shared__ int32_t cst[kColStage];
+    for (int c0 = 0; c0 < C; c0 += kColStage) {
+        const int cn = C - c0 < kColStage ? C - c0 : kColStage;
+        __syncthreads();  // the previous stage's columns are no longer read
+        for (int i = threadIdx.x; i < kColStage; i += blockDim.x) cst[i] = cols[c0 + (i < cn ? i : 0)];
+        __syncthreads();
+        const int sb = c0 / 4, se = (c0 + cn + 3) / 4;  // steps of this stage
+        for (int s0 = sb; s0 < se; s0 += DEPTH) {
+            T a[DEPTH], xv[DEPTH];
 #pragma unroll
-        for (int u = 0; u < DEPTH; ++u) {
-            const int kc = (s0 + u) * 4 + kk;
-            h[u] = cols[kc < C ? kc : 0];
-        }
+            for (int u = 0; u < DEPTH; ++u) {
+                const int64_t h = cst[(s0 + u - sb) * 4 + kk];
+                a[u] = s0 + u < se ? val[(int64_t)(s0 + u) * kWave] : zero<T>();
+                xv[u] = on ? xs[h * R + r] : zero<T>();
+            }
 #pragma unroll
-        for (int u = 0; u < DEPTH; ++u) {
-            a[u] = s0 + u < nsteps ? val[(int64_t)(s0 + u) * kWave] : zero<T>();
-            xv[u] = on ? xs[h[u] * R + r] : zero<T>();
-        }
-#pragma unroll
-        for (int u = 0; u < DEPTH; ++u) {
-            if constexpr (CP) {
-                const cdbl ac = *(const cdbl*)&a[u], xc = *(const cdbl*)&xv[u];
-                ar = mfma64(ac.re, xc.re, ar);
-                ar = mfma64(-ac.im, xc.im, ar);
-                ai = mfma64(ac.re, xc.im, ai);
-                ai = mfma64(ac.im, xc.re, ai);
-            } else {
-                ar = mfma64(*(const double*)&a[u], *(const double*)&xv[u], ar);
+            for (int u = 0; u < DEPTH; ++u) {
+                if constexpr (CP) {
+                    const cdbl ac = *(const cdbl*)&a[u], xc = *(const cdbl*)&xv[u];
+                    ar = mfma64(ac.re, xc.re, ar);
+                    ar = mfma64(-ac.im, xc.im, ar);
+                    ai = mfma64(ac.re, xc.im, ai);
+                    ai = mfma64(ac.im, xc.re, ai);
+                } else {
+                    ar = mfma64(*(const double*)&a[u], *(const double*)&xv[u], ar);
+                }
             }
         }
     }
