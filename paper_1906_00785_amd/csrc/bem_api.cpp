@@ -286,9 +286,10 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
 // One right-hand side.  The Givens step of Arnoldi step j runs inside step j+1's
 // dot-product kernel and writes its residual estimate straight to coherent host memory,
 // with a stamp (no copy, no event in the stream); having enqueued step j the host waits
-// only for the estimate of step j-2, so the device always has more than a step queued.  Convergence is therefore seen up to two steps
-// late; those steps' columns are dropped, so the iterate is that of the step that
-// converged.  The true residual is read once per cycle.
+// only for the estimate of step j-2, so the device always has more than a step queued.
+// Convergence is therefore seen up to two steps late; those steps' columns are dropped,
+// so the iterate is that of the step that converged.  The true residual is read once per
+// cycle.
 static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, int maxit, double tol,
                      bem_solve_stats* out, SolveWs& W, hipStream_t stream, bool pc = false) {
     const int64_t N = A->info.ndof;
@@ -296,11 +297,6 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
     const size_t sc = A->scal;
     auto Vj = [&](int j) { return W.V + (size_t)j * N * sc; };
     if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
-    while ((int)A->sev.size() < kMaxRestart) {
-        hipEvent_t e;
-        HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        A->sev.push_back(e);
-    }
     if (!A->hstat) {
         HIP_CHECK(hipHostMalloc((void**)&A->hstat, (sizeof(double) + sizeof(unsigned)) * kMaxRestart,
                                 hipHostMallocMapped | hipHostMallocCoherent));
