@@ -176,6 +176,29 @@ def test_gmres(B, orc, cid):
     assert oko and np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-8
 
 
+@pytest.mark.parametrize("restart", [2, 3, 4, 7, 30])
+def test_gmres_cycle_lengths(B, orc, restart):
+    """The device solver reads its residual estimates two steps late and drops the steps
+    past convergence; at every cycle length (also cycles shorter than that lag) it meets
+    the tolerance and stops no later than the oracle's GMRES (within one step, or 2 % after
+    hundreds of short cycles whose rounding drifts apart).  It may stop a few steps
+    earlier: it orthogonalises with classical Gram-Schmidt and a second pass, the oracle
+    with one pass of modified Gram-Schmidt, whose basis loses more orthogonality."""
+    g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_h2")
+    x0 = W.CONFIGS[0]["x0"]
+    b = s.rhs(B.BEM_DATA_POINT_SOURCE, [x0])
+    print(f"[gmres restart={restart}]", flush=True)
+    x, stats = A.solve(b, tol=1e-10, restart=restart, maxit=3000)
+    it, ok, rr, _ = stats[0]
+    bo = So.rhs(orc.POINT_SOURCE, x0)
+    xo, ito, rro, oko = Ho.gmres(bo, tol=1e-10, restart=restart, maxit=3000)
+    assert ok and oko and rr <= 1e-10
+    assert 0.9 * ito <= it <= ito + max(1, 0.02 * ito), (it, ito)
+    xg = x.cpu().numpy()[0]
+    assert np.linalg.norm(Ho.apply(xg) - bo) / np.linalg.norm(bo) <= 1e-9
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-6
+
+
 def test_gmres_nonconvergence_reported(B, orc):
     g, s, A, So, Ho = case(B, orc, "sphere_L2_d1_laplace_h2")
     b = s.rhs(B.BEM_DATA_POINT_SOURCE, [W.CONFIGS[0]["x0"]])
