@@ -17,9 +17,10 @@
 // each is named in the function that takes it.
 //
 // Parity status: every function here is pinned by a CPU test (tests/test_oracle_*.py)
-// against a closed form, an invariant, a library routine or brute force, except
-//   * the value of the H^2 compression error itself (only its monotone decay in q and the
-//     eta -> 0 limit are pinned): "parity unpinned" for that number.
+// against a closed form, an invariant, a library routine or brute force.  The compressed
+// operator itself is pinned three ways: eta -> 0 gives the dense matrix, the error decays
+// geometrically in q, and its matvec equals the operator written out from the definition
+// (interpolated kernel on every far pair, scipy B-splines and Gauss rules; flat square).
 #include <algorithm>
 #include <cmath>
 #include <complex>
