@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "bem_oracle.cpp")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 # geometry kinds, PDEs and data kinds (same numbering as the C code)
-SPHERE, ELLIPSOID, TORUS, FLAT = 0, 1, 2, 3
+SPHERE, ELLIPSOID, TORUS, FLAT, NURBS = 0, 1, 2, 3, 4
 LAPLACE, HELMHOLTZ = 0, 1
 POINT_SOURCE, PLANE_WAVE = 0, 1
 
@@ -54,6 +54,7 @@ def lib():
             "orc_bspline": (I, [I, I, I, I, I64, P, P]),
             "orc_bspline_count": (I, [I, I, I]),
             "orc_space_new": (I, [I, P, I, I, D, D, I, I, I, P]),
+            "orc_space_new_nurbs": (I, [I, P, P, P, I, D, D, I, I, I, P]),
             "orc_space_free": (None, [P]),
             "orc_space_ndof": (I64, [P]),
             "orc_space_nelem": (I64, [P]),
@@ -128,12 +129,29 @@ class Space:
 
     def __init__(self, geom: int, gparams=(), pde: int = LAPLACE, kappa: complex = 0.0,
                  degree: int = 1, knot_rep: int = 1, level: int = 0):
-        gp = np.ascontiguousarray(np.asarray(gparams, dtype=np.float64).reshape(-1))
-        if gp.size == 0:
-            gp = np.zeros(1)
+        """geom: an analytic kind with its parameters, or NURBS with gparams a list of patches,
+        each a dict with "degree" (p1, p2), "knots" (Xi_1, Xi_2) and "cw", an array
+        (k1, k2, 4) of control points and weights (App. C)."""
         h = ctypes.c_void_p()
-        _check(lib().orc_space_new(geom, _p(gp), int(len(gparams)), pde, float(np.real(kappa)),
-                                   float(np.imag(kappa)), degree, knot_rep, level, ctypes.byref(h)))
+        if geom == NURBS:
+            meta, knots, cw = [], [], []
+            for P in gparams:
+                c = np.asarray(P["cw"], dtype=np.float64)
+                meta += [int(P["degree"][0]), int(P["degree"][1]), c.shape[0], c.shape[1]]
+                knots += [np.asarray(P["knots"][0], dtype=np.float64), np.asarray(P["knots"][1], dtype=np.float64)]
+                cw.append(c.reshape(-1))
+            m = np.ascontiguousarray(meta, dtype=np.int32)
+            kn = np.ascontiguousarray(np.concatenate(knots))
+            cc = np.ascontiguousarray(np.concatenate(cw))
+            _check(lib().orc_space_new_nurbs(len(gparams), m.ctypes.data, _p(kn), _p(cc), pde,
+                                             float(np.real(kappa)), float(np.imag(kappa)), degree, knot_rep, level,
+                                             ctypes.byref(h)))
+        else:
+            gp = np.ascontiguousarray(np.asarray(gparams, dtype=np.float64).reshape(-1))
+            if gp.size == 0:
+                gp = np.zeros(1)
+            _check(lib().orc_space_new(geom, _p(gp), int(len(gparams)), pde, float(np.real(kappa)),
+                                       float(np.imag(kappa)), degree, knot_rep, level, ctypes.byref(h)))
         self._h = h
         self.pde = pde
         self.complex = pde == HELMHOLTZ
@@ -369,4 +387,33 @@ def tile_features(space: "Space", tile: int = 8) -> np.ndarray:
     nt = -(-nb // tile)
     out = np.zeros((npatch * nt * nt, 99))
     _check(lib().orc_tile_features(space._h, tile, _p(out)))
+    return out
+
+
+def user_map_patches(fn, npatch: int, degree: int = 5, intervals: int = 8):
+    """Reading of a user-supplied patch map (Sec. 4 "Geometry" allows arbitrary smooth
+    maps): each patch map is replaced by its tensor B-spline interpolant of `degree` on
+    `intervals` (a power of two) uniform intervals per direction, interpolating at the
+    Greville abscissae of the clamped knot vector; the result is a set of NURBS patches
+    with unit weights.  fn(patch, st) -> xyz for st an (n, 2) array of parameter points.
+    The collocation matrices use the oracle's own B-splines (App. C recursion)."""
+    L = int(round(np.log2(intervals)))
+    if 1 << L != intervals:
+        raise ValueError("intervals must be a power of two")
+    k = bspline_count(degree, 1, L)
+    knots = [0.0] * (degree + 1) + [j / intervals for j in range(1, intervals)] + [1.0] * (degree + 1)
+    kn = np.asarray(knots)
+    grev = np.array([kn[j + 1:j + degree + 1].mean() for j in range(k)]) if degree > 0 else \
+        0.5 * (kn[:k] + kn[1:k + 1])
+    B = np.stack([bspline(degree, 1, L, j, grev) for j in range(k)], axis=1)  # B[i, j] = b_j(x_i)
+    s1, s2 = np.meshgrid(grev, grev, indexing="ij")
+    st = np.stack([s1.ravel(), s2.ravel()], axis=1)
+    out = []
+    for f in range(npatch):
+        F = np.asarray(fn(f, st), dtype=np.float64).reshape(k, k, 3)
+        C = np.empty_like(F)
+        for d in range(3):  # B C_d B^T = F_d
+            C[:, :, d] = np.linalg.solve(B, np.linalg.solve(B, F[:, :, d]).T).T
+        cw = np.concatenate([C, np.ones((k, k, 1))], axis=2)
+        out.append({"degree": (degree, degree), "knots": (knots, knots), "cw": cw})
     return out

@@ -135,12 +135,23 @@ static int find_span(const Knots& K, double x) {
 // Geometry, App. D: Gamma is the union of patches gamma_f([0,1]^2) with outward normal and
 // matching parametrisations on shared edges.  The analytic maps are reading A1.
 // ---------------------------------------------------------------------------------------
-enum { G_SPHERE = 0, G_ELLIPSOID = 1, G_TORUS = 2, G_FLAT = 3 };
+enum { G_SPHERE = 0, G_ELLIPSOID = 1, G_TORUS = 2, G_FLAT = 3, G_NURBS = 4 };
+
+// One NURBS patch of App. C: degrees p_1, p_2, knot vectors Xi_1, Xi_2 on [0, 1] with
+// k_1, k_2 basis functions, control points c_{j1 j2} and weights w_{j1 j2} (stored
+// x, y, z, w per control point, j1 outer).
+struct NurbsPatch {
+    int p[2] = {0, 0};
+    int k[2] = {1, 1};
+    std::vector<double> xi[2];
+    std::vector<double> cw;
+};
 
 struct Geom {
     int kind = G_SPHERE;
     double p[3] = {1.0, 1.0, 1.0};
     int npatch = 6;
+    std::vector<NurbsPatch> nurbs;  // G_NURBS only
 };
 
 static Geom make_geom(int kind, const double* params, int nparams) {
@@ -163,6 +174,110 @@ static Geom make_geom(int kind, const double* params, int nparams) {
         G.p[0] = params[0];
     } else {
         throw std::runtime_error("unknown geometry kind");
+    }
+    return G;
+}
+
+// All k B-splines of degree p over the knot vector xi at x (App. C recursion), and their
+// derivatives.  The recursion is evaluated degree by degree over every index (the same
+// formula as the recursive definition, each b_j^{p-1} computed once); the degree-0
+// indicators take the half-open span [xi_j, xi_{j+1}) that contains x, and at x = 1 the
+// last non-empty span.  Quotients with a zero denominator are taken as 0.  Derivative:
+// d/dx b_j^p = p b_j^{p-1} / (xi_{j+p} - xi_j) - p b_{j+1}^{p-1} / (xi_{j+p+1} - xi_{j+1}).
+static void nurbs_basis(const std::vector<double>& xi, int p, int k, double x, std::vector<double>& b,
+                        std::vector<double>& db) {
+    const int nk = (int)xi.size();
+    int span = -1;
+    for (int j = 0; j + 1 < nk; ++j)
+        if (xi[j] < xi[j + 1] && xi[j] <= x && (x < xi[j + 1] || (xi[j + 1] >= xi[nk - 1] && x <= xi[j + 1])))
+            span = j;
+    if (span < 0) throw std::runtime_error("point outside the knot vector");
+    // (work arrays kept per thread so that repeated calls do not allocate)
+    thread_local std::vector<double> cur, prev;
+    cur.assign(nk - 1, 0.0);
+    cur[span] = 1.0;
+    for (int q = 1; q <= p; ++q) {
+        prev.swap(cur);
+        const int cnt = nk - 1 - q;
+        cur.assign(cnt, 0.0);
+        for (int j = 0; j < cnt; ++j) {
+            double v = 0.0;
+            const double d1 = xi[j + q] - xi[j];
+            if (d1 > 0.0) v += (x - xi[j]) / d1 * prev[j];
+            const double d2 = xi[j + q + 1] - xi[j + 1];
+            if (d2 > 0.0) v += (xi[j + q + 1] - x) / d2 * prev[j + 1];
+            cur[j] = v;
+        }
+        if (q == p) {
+            db.assign(k, 0.0);
+            for (int j = 0; j < k; ++j) {
+                double v = 0.0;
+                const double d1 = xi[j + p] - xi[j];
+                if (d1 > 0.0) v += p * prev[j] / d1;
+                const double d2 = xi[j + p + 1] - xi[j + 1];
+                if (d2 > 0.0) v -= p * prev[j + 1] / d2;
+                db[j] = v;
+            }
+        }
+    }
+    if (p == 0) db.assign(k, 0.0);
+    b.assign(cur.begin(), cur.begin() + k);
+}
+
+// NURBS map of App. C and its partial derivatives (quotient rule)
+static void nurbs_point(const NurbsPatch& P, double s, double t, double x[3], double xs[3], double xt[3]) {
+    thread_local std::vector<double> b1, db1, b2, db2;
+    nurbs_basis(P.xi[0], P.p[0], P.k[0], s, b1, db1);
+    nurbs_basis(P.xi[1], P.p[1], P.k[1], t, b2, db2);
+    double A[3] = {0, 0, 0}, As[3] = {0, 0, 0}, At[3] = {0, 0, 0}, W = 0, Ws = 0, Wt = 0;
+    for (int j1 = 0; j1 < P.k[0]; ++j1)
+        for (int j2 = 0; j2 < P.k[1]; ++j2) {
+            const double* c = &P.cw[4 * ((size_t)j1 * P.k[1] + j2)];
+            const double w = c[3];
+            const double v = b1[j1] * b2[j2] * w, vs = db1[j1] * b2[j2] * w, vt = b1[j1] * db2[j2] * w;
+            for (int d = 0; d < 3; ++d) {
+                A[d] += v * c[d];
+                As[d] += vs * c[d];
+                At[d] += vt * c[d];
+            }
+            W += v;
+            Ws += vs;
+            Wt += vt;
+        }
+    for (int d = 0; d < 3; ++d) {
+        x[d] = A[d] / W;
+        if (xs) xs[d] = (As[d] - x[d] * Ws) / W;
+        if (xt) xt[d] = (At[d] - x[d] * Wt) / W;
+    }
+}
+
+static Geom make_nurbs_geom(int npatch, const int* meta, const double* knots, const double* cw) {
+    if (npatch < 1) throw std::runtime_error("need at least one patch");
+    Geom G;
+    G.kind = G_NURBS;
+    G.npatch = npatch;
+    size_t ko = 0, co = 0;
+    for (int f = 0; f < npatch; ++f) {
+        NurbsPatch P;
+        for (int d = 0; d < 2; ++d) {
+            P.p[d] = meta[4 * f + d];
+            P.k[d] = meta[4 * f + 2 + d];
+            if (P.p[d] < 0 || P.k[d] <= P.p[d]) throw std::runtime_error("bad NURBS degree or count");
+        }
+        for (int d = 0; d < 2; ++d) {
+            const int nk = P.k[d] + P.p[d] + 1;
+            P.xi[d].assign(knots + ko, knots + ko + nk);
+            ko += nk;
+            for (int i = 0; i + 1 < nk; ++i)
+                if (P.xi[d][i + 1] < P.xi[d][i]) throw std::runtime_error("knots must not decrease");
+            if (P.xi[d].front() != 0.0 || P.xi[d].back() != 1.0) throw std::runtime_error("knots must span [0,1]");
+        }
+        const size_t n = (size_t)P.k[0] * P.k[1] * 4;
+        P.cw.assign(cw + co, cw + co + n);
+        co += n;
+        for (size_t i = 3; i < n; i += 4)
+            if (!(P.cw[i] > 0.0)) throw std::runtime_error("weights must be positive");
+        G.nurbs.push_back(std::move(P));
     }
     return G;
 }
@@ -222,6 +337,8 @@ static void gamma(const Geom& G, int f, double s, double t, double x[3], double 
             xt[1] = -r * std::sin(v) * std::sin(u) * dv;
             xt[2] = r * std::cos(v) * dv;
         }
+    } else if (G.kind == G_NURBS) {
+        nurbs_point(G.nurbs[f], s, t, x, xs, xt);
     } else {  // flat square of side a in the plane z = 0
         const double a = G.p[0];
         x[0] = a * s;
@@ -1545,6 +1662,23 @@ int orc_space_new(int gkind, const double* gparams, int nparams, int pde, double
         try {
             s->S = make_space(make_geom(gkind, gparams, nparams), pde, cplx(kre, kim), degree,
                               knot_rep, level);
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = s;
+    })
+}
+
+// space on NURBS patches: meta = (p1, p2, k1, k2) per patch, knots = Xi_1 then Xi_2 of each
+// patch in turn, cw = (x, y, z, w) per control point of each patch in turn (j1 outer)
+int orc_space_new_nurbs(int npatch, const int* meta, const double* knots, const double* cw, int pde, double kre,
+                        double kim, int degree, int knot_rep, int level, void** out) {
+    ORC_TRY({
+        OrcSpace* s = new OrcSpace;
+        try {
+            s->S = make_space(make_nurbs_geom(npatch, meta, knots, cw), pde, cplx(kre, kim), degree, knot_rep,
+                              level);
         } catch (...) {
             delete s;
             throw;

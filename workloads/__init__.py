@@ -188,3 +188,85 @@ def c3_instances(n: int | None = None):
                 srcs.append((rr * np.cos(phi), rr * np.sin(phi), rho * np.sin(th)))
         out.append(dict(geom=geom, params=prm, level=L, degree=d, pde=1 if helm else 0, kappa=kappa, sources=srcs))
     return out
+
+
+# ------------------------------------------------------------------ NURBS patch sets
+# Geometry inputs given as NURBS patches (control points and weights): each patch is a dict
+# {"degree": (p1, p2), "knots": (Xi_1, Xi_2), "cw": array (k1, k2, 4) of x, y, z, w}.
+
+def _quarter_arc(k: int):
+    """The unit circle over the angles [k pi/2, (k+1) pi/2] as a rational quadratic Bezier
+    arc: control points (end, corner of the end tangents, end) and weights (1, 1/sqrt 2, 1)."""
+    t0 = 0.5 * np.pi * k
+    c, s = np.cos(t0), np.sin(t0)
+    pts = np.array([[c, s], [c - s, s + c], [-s, c]])
+    w = np.array([1.0, np.sqrt(0.5), 1.0])
+    return pts, w
+
+
+def nurbs_torus(R: float, r: float):
+    """The torus of radii R > r as 16 biquadratic rational patches, patch 4 a + b covering
+    the quarter turns a (around the z axis) and b (around the tube), oriented like the
+    analytic torus patches (outward normal); control points are the products of the two
+    circles' arc control points."""
+    knots = [0.0, 0.0, 0.0, 1.0, 1.0, 1.0]
+    out = []
+    for a in range(4):
+        P, wP = _quarter_arc(a)
+        for b in range(4):
+            Q, wQ = _quarter_arc(b)
+            cw = np.zeros((3, 3, 4))
+            for i in range(3):
+                for j in range(3):
+                    rad = R + r * Q[j, 0]
+                    cw[i, j] = (rad * P[i, 0], rad * P[i, 1], r * Q[j, 1], wP[i] * wQ[j])
+            out.append({"degree": (2, 2), "knots": (knots, knots), "cw": cw})
+    return out
+
+
+def greville(knots, p: int) -> np.ndarray:
+    """Greville abscissae of a knot vector (averages of p consecutive interior knots)."""
+    kn = np.asarray(knots, dtype=np.float64)
+    k = kn.size - p - 1
+    if p == 0:
+        return 0.5 * (kn[:k] + kn[1:k + 1])
+    return np.array([kn[j + 1:j + p + 1].mean() for j in range(k)])
+
+
+def nurbs_flat(a: float, degree=(2, 3), knots=None, weight: float = 2.5):
+    """The square [0, a]^2 x {0} as one NURBS patch whose map is (a s, a t, 0): control
+    points at the Greville abscissae (linear precision of B-splines), every weight equal.
+    knots: (Xi_1, Xi_2), default non-uniform open knot vectors."""
+    if knots is None:
+        knots = ([0.0] * (degree[0] + 1) + [0.2, 0.45, 0.5] + [1.0] * (degree[0] + 1),
+                 [0.0] * (degree[1] + 1) + [0.3, 0.7] + [1.0] * (degree[1] + 1))
+    g1, g2 = greville(knots[0], degree[0]), greville(knots[1], degree[1])
+    cw = np.zeros((g1.size, g2.size, 4))
+    for i, u in enumerate(g1):
+        for j, v in enumerate(g2):
+            cw[i, j] = (a * u, a * v, 0.0, weight)
+    return [{"degree": tuple(degree), "knots": (list(knots[0]), list(knots[1])), "cw": cw}]
+
+
+def sphere6_map(f: int, st) -> np.ndarray:
+    """The unit sphere's patch f (cube face projected radially, faces +z, -z, +x, -x, +y, -y
+    with u = 2s - 1, v = 2t - 1 placed as (u,v,1), (v,u,-1), (1,u,v), (-1,v,u), (v,1,u),
+    (u,-1,v)), as a user-supplied map: xyz for an (n, 2) array of parameter points."""
+    st = np.asarray(st, dtype=np.float64).reshape(-1, 2)
+    u, v = 2.0 * st[:, 0] - 1.0, 2.0 * st[:, 1] - 1.0
+    one = np.ones_like(u)
+    c = [np.stack([u, v, one], 1), np.stack([v, u, -one], 1), np.stack([one, u, v], 1),
+         np.stack([-one, v, u], 1), np.stack([v, one, u], 1), np.stack([u, -one, v], 1)][f]
+    return c / np.linalg.norm(c, axis=1, keepdims=True)
+
+
+def torus16_map(R: float, r: float):
+    """The torus's 16 quarter-turn patches as a user-supplied map (same parametrisation as
+    the analytic torus)."""
+    def fn(f: int, st):
+        st = np.asarray(st, dtype=np.float64).reshape(-1, 2)
+        u = 0.5 * np.pi * ((f >> 2) + st[:, 0])
+        v = 0.5 * np.pi * ((f & 3) + st[:, 1])
+        rr = R + r * np.cos(v)
+        return np.stack([rr * np.cos(u), rr * np.sin(u), r * np.sin(v)], 1)
+    return fn
