@@ -55,6 +55,7 @@ def lib():
             "orc_bspline_count": (I, [I, I, I]),
             "orc_space_new": (I, [I, P, I, I, D, D, I, I, I, P]),
             "orc_space_new_nurbs": (I, [I, P, P, P, I, D, D, I, I, I, P]),
+            "orc_h2_potential": (I, [P, P, I64, P, D, P]),
             "orc_space_free": (None, [P]),
             "orc_space_ndof": (I64, [P]),
             "orc_space_nelem": (I64, [P]),
@@ -300,6 +301,17 @@ class H2:
         parts = (1 if far else 0) | (2 if near else 0)
         _check(lib().orc_h2_apply_rows(self._h, _p(x), _p(rows), rows.size, parts, _p(y)))
         return y
+
+    def potential(self, rho, pts, eta: float | None = None) -> np.ndarray:
+        """Potential at points (n, 3) by the cluster tree: admissible clusters through their
+        moments and Chebyshev points, near leaves by 8x8 Gauss (eta: admissibility of
+        point and cluster; default the operator's; 0 gives the plain quadrature)."""
+        rho = np.ascontiguousarray(rho, dtype=self.space.dtype)
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        u = np.zeros(pts.shape[0], dtype=self.space.dtype)
+        _check(lib().orc_h2_potential(self._h, _p(rho), pts.shape[0], _p(pts), float(self.eta if eta is None else eta),
+                                      _p(u)))
+        return u
 
     def assemble_near_rows(self, rows):
         """Assemble and keep the near-field rows of a subset of DOFs (lazy operators)."""

@@ -1630,6 +1630,67 @@ static void h2_info(const H2<T>& H, int64_t* info) {
     info[5] = H.qm;
 }
 
+// Potential accelerated by the cluster tree (Sec. 4 "Evaluation of the Solution" evaluated
+// with the compression of Sec. 2 on the source side only): for each point x, the clusters of
+// every patch are visited from the root; a cluster whose ball is admissible for the point
+// (reading A10 with a target radius of 0: dist = |x - c| - r > 0 and 2 r <= eta dist, ties
+// within 1e-12 dist inadmissible) contributes sum_a k(x, gamma(xi_a)) m_a, with the moments m
+// of rho (forward + upward transform); an inadmissible leaf contributes the plain quadrature
+// of its elements (q points per direction, as the dense potential); an inadmissible cluster
+// above the leaves passes the point to its four children.
+template <class T>
+static void h2_potential(const H2<T>& H, const T* rho, int64_t npts, const double* pts, double eta, int qp, T* u) {
+    const Space& S = *H.S;
+    std::vector<T> mom(H.cl.size() * H.q * H.q, T(0));
+    h2_forward(H, rho, mom);
+    h2_upward(H, mom);
+    const int q = H.q, q2 = q * q;
+    const Rule g = gauss01(qp);
+    const int nb = (S.K.d + 1) * (S.K.d + 1);
+    std::vector<double> ph(nb);
+    for (int64_t p = 0; p < npts; ++p) {
+        const double* x = &pts[3 * p];
+        T acc = T(0);
+        std::vector<int64_t> todo;
+        for (int f = S.G.npatch - 1; f >= 0; --f) todo.push_back(H.cluster_index(0, f, 0, 0));
+        while (!todo.empty()) {
+            const int64_t c = todo.back();
+            todo.pop_back();
+            const Cluster& C = H.cl[c];
+            const double dist = dist3(x, C.c) - C.rad;
+            const double lhs = 2.0 * C.rad, rhs = eta * dist;
+            const bool adm = dist > 0.0 && !(std::fabs(lhs - rhs) <= 1e-12 * dist) && lhs <= rhs;
+            if (adm) {
+                for (int a = 0; a < q2; ++a) {
+                    double y[3];
+                    cluster_node(S.G, C, H.xi, a / q, a % q, y);
+                    acc += kernel_r<T>(S.pde, S.kappa, dist3(x, y)) * mom[(size_t)c * q2 + a];
+                }
+            } else if (C.lev == H.leaf) {
+                std::vector<int64_t> els;
+                leaf_elements(H, c, els);
+                for (int64_t e : els) {
+                    const Elem E = elem_of(S, e);
+                    for (int a1 = 0; a1 < qp; ++a1)
+                        for (int a2 = 0; a2 < qp; ++a2) {
+                            double s, t, y[3];
+                            elem_param(S, E, 0, g.x[a1], g.x[a2], s, t);
+                            gamma(S.G, E.f, s, t, y);
+                            elem_basis(S, E, s, t, ph.data());
+                            T rv = T(0);
+                            for (int l = 0; l < nb; ++l) rv += rho[local_dof(S, E, l)] * ph[l];
+                            acc += kernel_r<T>(S.pde, S.kappa, dist3(x, y)) * rv * (g.w[a1] * g.w[a2] * S.h * S.h);
+                        }
+                }
+            } else {
+                for (int k = 3; k >= 0; --k)
+                    todo.push_back(H.cluster_index(C.lev + 1, C.f, 2 * C.i + (k >> 1), 2 * C.j + (k & 1)));
+            }
+        }
+        u[p] = acc;
+    }
+}
+
 extern "C" {
 
 const char* orc_last_error() { return g_err.c_str(); }
@@ -1935,6 +1996,16 @@ int orc_h2_moments(void* hp, const double* x, int direct, double* mom) {
 }
 
 // y = A x for nrhs columns (column-major, leading dimension N)
+int orc_h2_potential(void* hp, const double* rho, int64_t npts, const double* pts, double eta, double* u) {
+    ORC_TRY({
+        OrcH2* h = (OrcH2*)hp;
+        if (h->cplx_)
+            h2_potential(h->hc, (const cplx*)rho, npts, pts, eta, 8, (cplx*)u);
+        else
+            h2_potential(h->hr, rho, npts, pts, eta, 8, u);
+    })
+}
+
 int orc_h2_apply(void* hp, const double* x, double* y, int nrhs) {
     ORC_TRY({
         OrcH2* h = (OrcH2*)hp;
