@@ -42,13 +42,19 @@ def parse():
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--only-main", action="store_true", help="main workload matvec only (for profiling)")
     ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
+    ap.add_argument("--no-cpu-legs", action="store_true", help="skip the oracle's timings of the other workloads")
     return ap.parse_args()
 
 
-# FP64 operations per coupling entry evaluated on the fly (a fused multiply-add counts 2):
-# squared distance 1 add + 3 FMA (7), hardware 1/sqrt estimate (1), third-order
-# correction 2 mul + 3 FMA (8), row sum and transposed product 2 FMA (4)
-OTF_FLOPS_PER_ENTRY = 20
+# FP64 operations per coupling entry evaluated on the fly, the method's own work (a fused
+# multiply-add counts 2): squared distance of two points (3 differences, 3 products, 2
+# sums = 8), one reciprocal square root (1), the entry's product with the moment in the row
+# sum and in the transposed product (4) = 13.  The kernel issues 20: the squared distance
+# expanded about the owner's first point (1 add + 3 FMA = 7), the hardware estimate (1) and
+# its third-order correction (2 mul + 3 FMA = 8), the two products (4); that count is
+# reported beside it.
+OTF_FLOPS_PER_ENTRY = 13
+OTF_ISSUED_FLOPS_PER_ENTRY = 20
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -71,33 +77,142 @@ def measured_traffic(kernel="k_coupling"):
     return float(t.group(1)) if cur == h.group(1) else None
 
 
-def cpu_baseline(cfg, x, nrows):
-    """Oracle H^2 matvec on the same workload, timed on a bounded sample: the far field
-    (forward, upward, coupling, downward, backward) over all N rows in full, the near field
-    over `nrows` sampled rows (assembled first, untimed), scaled to N rows."""
+def _sampled_matvec_s(H, x, N, nrows, seed_cfg, reps=5):
+    """Seconds of one oracle H^2 matvec: the far field (forward, upward, coupling, downward,
+    backward) over all N rows timed in full, the near field over `nrows` seeded rows
+    (assembled first, untimed) timed and scaled to N rows."""
     import numpy as np
 
-    import oracle as O
     import workloads as W
 
-    S = O.Space(O.SPHERE, [], O.LAPLACE, 0.0, degree=cfg["degree"], level=cfg["level"])
-    H = O.H2(S, q=cfg["q"], eta=cfg["eta"], leaf=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble_near=False)
-    N = S.ndof
-    rows = W.sample_rows(1, N, nrows)
+    rows = W.sample_rows(seed_cfg, N, nrows)
     H.assemble_near_rows(rows)
     allrows = np.arange(N, dtype=np.int64)
     t0 = time.perf_counter()
     H.apply_rows(x, allrows, far=True, near=False)
     t_far = time.perf_counter() - t0
-    reps = 20
     t0 = time.perf_counter()
     for _ in range(reps):
         H.apply_rows(x, rows, far=False, near=True)
     t_near = (time.perf_counter() - t0) / reps * (N / rows.size)
+    return t_far, t_near, rows.size
+
+
+def _cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def cpu_baseline(cfg, x, nrows, threads=1):
+    """Oracle H^2 matvec on the same workload (the oracle as it stands, plain FP64), timed on
+    a bounded sample: far field over all rows in full, near field on sampled rows scaled to
+    N rows.  threads > 1: the oracle's timing mode (parallel loops over independent rows,
+    clusters and target runs; the same results)."""
+    import oracle as O
+
+    used = O.set_threads(threads)
+    S = O.Space(O.SPHERE, [], O.LAPLACE, 0.0, degree=cfg["degree"], level=cfg["level"])
+    H = O.H2(S, q=cfg["q"], eta=cfg["eta"], leaf=cfg["leaf"], qg=cfg["qg"], qs=cfg["qs"], assemble_near=False)
+    N = S.ndof
+    t_far, t_near, nr = _sampled_matvec_s(H, x, N, nrows, 1)
     t = t_far + t_near
-    return {"value": N / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+    O.set_threads(1)
+    return {"value": N / t, "unit": "DOF/s", "cores": used, "kind": "oracle",
             "sample": f"far field over all {N} rows timed in full ({t_far:.3f} s); near field timed over "
-                      f"{rows.size} seeded rows and scaled to {N} rows ({t_near:.3f} s); serial FP64"}
+                      f"{nr} seeded rows and scaled to {N} rows ({t_near:.3f} s); FP64, {used} thread(s)"}
+
+
+def cpu_oracle_legs(args, gpu):
+    """The oracle on the other workloads, bounded samples on the host cores (timing mode with
+    every core the process may use; the oracle's results do not depend on the thread count).
+    gpu: the GPU figures the estimates are scaled with (iteration counts) or compared to."""
+    import numpy as np
+
+    import oracle as O
+    import workloads as W
+
+    model, ncpu = _cpu_info()
+    used = O.set_threads(ncpu)
+    out = {"cpu_model": model, "nproc": ncpu, "threads": used}
+    # C0: dense assembly, solve and potential, in full
+    c0 = W.CONFIGS[0]
+    t0 = time.perf_counter()
+    S0 = O.Space(O.SPHERE, [], O.LAPLACE, 0.0, degree=c0["degree"], level=c0["level"])
+    A0 = S0.dense(c0["qg"], c0["qs"])
+    t_asm = time.perf_counter() - t0
+    x0, pts = W.c0_inputs()
+    t0 = time.perf_counter()
+    rho = np.linalg.solve(A0, S0.rhs(O.POINT_SOURCE, x0))
+    u = S0.potential(rho, pts)
+    t_sol = time.perf_counter() - t0
+    ex = 1.0 / (4 * np.pi * np.linalg.norm(pts - np.array(x0), axis=1))
+    out["c0_dense"] = {"assembly_s": t_asm, "solve_and_potential_s": t_sol,
+                       "potential_max_rel_err": float(np.max(np.abs(u - ex)) / np.max(np.abs(ex))),
+                       "sample": "in full"}
+    # C1 GMRES: one sampled matvec times the GPU's iteration count (the Arnoldi steps' vector
+    # work is small beside the matvec)
+    c1 = W.CONFIGS[1]
+    S1 = O.Space(O.SPHERE, [], O.LAPLACE, 0.0, degree=c1["degree"], level=c1["level"])
+    H1 = O.H2(S1, q=c1["q"], eta=c1["eta"], leaf=c1["leaf"], assemble_near=False)
+    x1 = W.random_vector(W.rng(1, 11), S1.ndof)
+    tf, tn, nr = _sampled_matvec_s(H1, x1, S1.ndof, 24, 1, reps=3)
+    its = gpu.get("c1_gmres_iterations")
+    out["c1_gmres"] = {"matvec_s": tf + tn, "iterations": its,
+                       "time_to_tol_s_estimate": (tf + tn) * its if its else None,
+                       "sample": f"one matvec (far field in full, near field on {nr} rows scaled) times the GPU "
+                                 f"solve's iteration count"}
+    # C2: one wavenumber, one of the 128 columns, scaled to 128
+    c2 = W.CONFIGS[2]
+    kappa, dirs = W.c2_inputs()
+    S2 = O.Space(O.SPHERE, [], O.HELMHOLTZ, kappa, degree=c2["degree"], level=c2["level"])
+    t0 = time.perf_counter()
+    H2 = O.H2(S2, q=c2["q"], eta=c2["eta"], leaf=c2["leaf"], assemble_near=False)
+    t_far_asm = time.perf_counter() - t0
+    x2 = W.random_vector(W.rng(2, 11), S2.ndof, is_complex=True)
+    tf, tn, nr = _sampled_matvec_s(H2, x2, S2.ndof, 12, 2, reps=3)
+    out["c2_many_rhs"] = {"far_assembly_s": t_far_asm, "matvec_one_column_s": tf + tn,
+                          "dof_rhs_per_s": S2.ndof / (tf + tn),
+                          "sample": f"one column (far field in full, near field on {nr} rows scaled); the "
+                                    f"oracle applies columns one after the other, so 128 take 128 times as long"}
+    # C3: 32 seeded instances, one column each timed, times their column counts
+    insts = W.c3_instances(32)
+    tot, dofrhs, tbuild = 0.0, 0, 0.0
+    for k, it in enumerate(insts):
+        S = O.Space(it["geom"], list(it["params"]), it["pde"], it["kappa"], degree=it["degree"], level=it["level"])
+        t0 = time.perf_counter()
+        H = O.H2(S, q=W.CONFIGS[3]["q"], eta=W.CONFIGS[3]["eta"], leaf=max(it["level"] - 2, 0), assemble_near=False)
+        tbuild += time.perf_counter() - t0
+        xx = W.random_vector(W.rng(3, 500 + k), S.ndof, is_complex=bool(it["pde"]))
+        tf, tn, _ = _sampled_matvec_s(H, xx, S.ndof, 3, 3, reps=1)
+        nc = len(it["sources"])
+        tot += (tf + tn) * nc
+        dofrhs += S.ndof * nc
+    out["c3_subset"] = {"instances": len(insts), "dof_rhs": dofrhs, "matvec_s": tot, "dof_rhs_per_s": dofrhs / tot,
+                        "far_assembly_s": tbuild,
+                        "sample": "the first 32 seeded instances: one column each (far field in full, near field "
+                                  "on 3 rows scaled), times its column count"}
+    # C4: the correction network in FP64 (forward + loss gradient) on a 1,024-block batch
+    import oracle.mlp as M
+
+    g = W.rng(4, 900)
+    nin, hid, nout = 99, 256, 2048
+    P = g.normal(scale=0.05, size=M.nparams(nin, hid, nout))
+    Xb = g.normal(size=(1024, nin))
+    Tb = g.normal(size=(1024, 64, 64)) + 1j * g.normal(size=(1024, 64, 64))
+    t0 = time.perf_counter()
+    M.loss_and_grad(P, Xb, Tb, nin, hid, nout, True)
+    t_mlp = time.perf_counter() - t0
+    out["c4_network"] = {"blocks": 1024, "forward_and_gradient_s": t_mlp, "blocks_per_s": 1024 / t_mlp,
+                         "sample": "numpy FP64 forward, rank-8 loss and gradient of the 99-256-256-2048 network"}
+    O.set_threads(1)
+    return out
 
 
 BF16_MFMA_PEAK = 2.5e15
@@ -155,8 +270,10 @@ def bench_c2(B, W, torch, np, stream, args):
         A16.precond_build()
         A32.precond_build()
         for name, op, refine, pc in (("gmres_fp64", A16, False, False), ("gmres_fp32_refined", A32, True, False),
+                                     ("gmres_bf16_refined", A16, True, False),
                                      ("gmres_fp64_block_jacobi", A16, False, True),
-                                     ("gmres_fp32_refined_block_jacobi", A32, True, True)):
+                                     ("gmres_fp32_refined_block_jacobi", A32, True, True),
+                                     ("gmres_bf16_refined_block_jacobi", A16, True, True)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, st = op.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=refine, precond=pc)
@@ -167,8 +284,19 @@ def bench_c2(B, W, torch, np, stream, args):
             out[name] = {"time_to_tol_s": t, "iterations_min": min(its), "iterations_max": max(its),
                          "converged": sum(bool(v[1]) for v in st), "max_true_relres": res,
                          "outer_max": max(v[3] for v in st)}
+            base = "gmres_fp64_block_jacobi" if pc else "gmres_fp64"
+            if name != base:
+                out[name]["speedup_vs_fp64"] = out[base]["time_to_tol_s"] / t
             print(f"bench c2: {name} {t:.3f}s its {min(its)}..{max(its)} converged {out[name]['converged']}/{R} "
                   f"max relres {res:.2e}", file=sys.stderr, flush=True)
+        # the stated error of the refined solutions: all to 1e-12, max over the 128 columns of
+        # the relative difference to the FP64 solution
+        x64, _ = A16.solve(b, tol=1e-12, restart=c["restart"], maxit=20000)
+        for name, op in (("gmres_fp32_refined", A32), ("gmres_bf16_refined", A16)):
+            xl, _ = op.solve(b, tol=1e-12, restart=c["restart"], maxit=20000, refine=True, max_outer=40)
+            err = float(((xl - x64).norm(dim=1) / x64.norm(dim=1)).max())
+            out[name]["solution_rel_err_vs_fp64_at_1e-12"] = err
+            print(f"bench c2: {name} solution error vs FP64 (all to 1e-12) {err:.1e}", file=sys.stderr, flush=True)
     return out
 
 
@@ -178,15 +306,34 @@ def bench_c3(B, W, torch, np, args):
     launches captured into one graph.  Laplace instances evaluate the coupling on the fly,
     Helmholtz instances stream their stored blocks (measured faster in grouped launches,
     where an operator's columns read them one after the other)."""
+    import paper_1906_00785_amd.autotune as AT
+
     insts = W.c3_instances(args.c3_instances)
+    q3, eta3 = W.CONFIGS[3]["q"], W.CONFIGS[3]["eta"]
+    # autotuned launch shapes (leaf level, coupling chunk width) per shape class of the two
+    # largest levels, measured on the class's first instance and used for all of its members
+    t0 = time.perf_counter()
+    tuned = {}
+    for it in insts:
+        cls = (it["geom"], it["pde"], it["level"], it["degree"])
+        if it["level"] < 4 or cls in tuned:
+            continue
+        g = B.Geometry(it["geom"], it["params"])
+        s = B.Space(g, it["pde"], it["kappa"], degree=it["degree"], level=it["level"])
+        r = AT.tune(s, q=q3, eta=eta3, steps=5, far_eval=it["pde"] == 0,
+                    leaf_levels=[lv for lv in (it["level"] - 3, it["level"] - 2, it["level"] - 1) if lv >= 0])
+        tuned[cls] = {"leaf_level": r["leaf_level"], "chunk_cols": r["chunk_cols"], "apply_us": r["apply_us"]}
+        del s, g
+    t_tune = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     members = {0: [], 1: []}
     for it in insts:
         g = B.Geometry(it["geom"], it["params"])
         s = B.Space(g, it["pde"], it["kappa"], degree=it["degree"], level=it["level"])
-        A = B.Operator(s, q=W.CONFIGS[3]["q"], eta=W.CONFIGS[3]["eta"], leaf_level=max(it["level"] - 2, 0),
-                       far_eval=it["pde"] == 0)
+        tc = tuned.get((it["geom"], it["pde"], it["level"], it["degree"]))
+        A = B.Operator(s, q=q3, eta=eta3, leaf_level=tc["leaf_level"] if tc else max(it["level"] - 2, 0),
+                       chunk_cols=tc["chunk_cols"] if tc else 0, far_eval=it["pde"] == 0)
         x = s.rhs(B.BEM_DATA_POINT_SOURCE, it["sources"])
         members[it["pde"]].append((s, A, x, torch.empty_like(x)))
     torch.cuda.synchronize()
@@ -229,7 +376,9 @@ def bench_c3(B, W, torch, np, args):
     out = {"workload": W.CONFIGS[3]["name"], "instances": len(insts), "columns": nrhs, "dof_rhs": dofrhs,
            "assembly_s": t_asm, "per_column_ms": t_col, "grouped_ms": t_group, "graph_ms": t_graph,
            "dof_rhs_per_s_graph": dofrhs / (t_graph * 1e-3), "dof_rhs_per_s_per_column": dofrhs / (t_col * 1e-3),
-           "far_field": "on the fly (Laplace), stored blocks (Helmholtz)", "launches_grouped": 6 * len(groups)}
+           "far_field": "on the fly (Laplace), stored blocks (Helmholtz)", "launches_grouped": 6 * len(groups),
+           "autotune_s": t_tune,
+           "autotuned": {f"geom{k[0]}_pde{k[1]}_L{k[2]}_d{k[3]}": v for k, v in tuned.items()}}
     print(f"bench c3: {len(insts)} instances, {nrhs} columns, {dofrhs} DOF*RHS; assembly {t_asm:.1f}s; matvec "
           f"per-column {t_col:.2f} ms, grouped {t_group:.2f} ms, graph {t_graph:.2f} ms "
           f"({dofrhs/(t_graph*1e-3):.3e} DOF*RHS/s)", file=sys.stderr, flush=True)
@@ -237,15 +386,16 @@ def bench_c3(B, W, torch, np, args):
 
 
 def bench_c4(B, W, torch, np, args):
-    """Learned block-Jacobi correction: train on solver-generated targets of the family,
-    compare preconditioned GMRES to 1e-8 (plain block-Jacobi vs learned with fallback) on
-    held-out instances.  Level 4 and the resolved wavenumber range (see the tests)."""
+    """Learned block-Jacobi correction on the family as configured: ellipsoids and tori,
+    levels 5 and 6, degree 2, Helmholtz with wavenumbers 4..20; the BF16 network (3 layers
+    of width 256) is trained on solver-generated targets of about 10,000 tiles, then GMRES to
+    1e-8 runs on held-out instances without a preconditioner, with plain block-Jacobi and
+    with the learned correction (kept only if it wins its selection cycle)."""
     import paper_1906_00785_amd.learned as L
 
     cfg = W.CONFIGS[4]
-    level, krange = 4, (4.0, 8.0)
 
-    def op_of(inst):
+    def op_of(inst, level):
         geom, prm, kappa = inst
         g = B.Geometry(geom, prm)
         s = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, kappa, degree=cfg["degree"], level=level)
@@ -254,23 +404,32 @@ def bench_c4(B, W, torch, np, args):
         return s, A
 
     t0 = time.perf_counter()
-    feats, targs = [], []
-    for inst in W.c4_instances(8, stream=0, kappa_range=krange):
-        s, A = op_of(inst)
+    feats, targs, ntr, used = [], [], 0, []
+    nmax = 40
+    for inst, level in zip(W.c4_instances(nmax, stream=0), W.c4_levels(nmax, stream=0)):
+        s, A = op_of(inst, level)
         f, t = L.training_data(A, ring=cfg["ring"])
         feats.append(f)
         targs.append(t)
+        ntr += f.shape[0]
+        used.append(level)
+        del A, s
+        if ntr >= cfg["train_blocks"]:
+            break
     X, T = torch.cat(feats), torch.cat(targs)
+    del feats, targs
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    print(f"bench c4: {X.shape[0]} training blocks from {len(used)} instances (levels {sorted(set(used))}) "
+          f"in {t_data:.1f}s", file=sys.stderr, flush=True)
     net = L.CorrectionNet(cplx=True, hidden=256, seed=1906, precision=1)
     t0 = time.perf_counter()
     losses = net.train(X, T, steps=600, batch=64, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     rows = []
-    for inst in W.c4_instances(3, stream=1, kappa_range=krange):
-        s, A = op_of(inst)
+    for inst, level in zip(W.c4_instances(4, stream=1), W.c4_levels(4, stream=1)):
+        s, A = op_of(inst, level)
         b = s.rhs(B.BEM_DATA_PLANE_WAVE, W.unit_vectors(W.rng(4, 103), 1))
         res = {}
         for name, pc in (("none", False), ("block_jacobi", True)):
@@ -285,12 +444,14 @@ def bench_c4(B, W, torch, np, args):
         torch.cuda.synchronize()
         res["learned"] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1],
                           "kept": kept, "cycle_relres_plain_learned": rr}
-        rows.append({"instance": [inst[0], list(inst[1]), inst[2]], **res})
-        print(f"bench c4: {inst}: none {res['none']['iterations']} its, block-Jacobi "
+        rows.append({"instance": [inst[0], list(inst[1]), inst[2]], "level": level, "ndof": s.ndof, **res})
+        print(f"bench c4: L{level} {inst}: none {res['none']['iterations']} its, block-Jacobi "
               f"{res['block_jacobi']['iterations']} its, learned {res['learned']['iterations']} its "
               f"(kept {kept})", file=sys.stderr, flush=True)
-    return {"workload": cfg["name"], "level": level, "kappa_range": list(krange), "train_blocks": int(X.shape[0]),
-            "data_s": t_data, "train_s": t_train, "train_steps": 600,
+        del A, s
+    return {"workload": cfg["name"], "levels": sorted(set(used)), "kappa_range": list(cfg["kappa_range"]),
+            "train_blocks": int(X.shape[0]), "train_instances": len(used), "data_s": t_data, "train_s": t_train,
+            "train_steps": 600, "network": "3 layers, width 256, BF16 products",
             "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:])), "held_out": rows}
 
 
@@ -393,7 +554,9 @@ def main():
                "achieved": otf_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                "frac": otf_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic("k_coupling_otf"),
                "algorithmic_flops": OTF_FLOPS_PER_ENTRY * entries, "entries": entries, "avg_ms": kern_ot,
-               "stage_ms": stage_ot[1]}
+               "stage_ms": stage_ot[1], "issued_flops_per_entry": OTF_ISSUED_FLOPS_PER_ENTRY,
+               "issued_tflops": OTF_ISSUED_FLOPS_PER_ENTRY * entries / (kern_ot * 1e-3) / 1e12,
+               "issued_frac": OTF_ISSUED_FLOPS_PER_ENTRY * entries / (kern_ot * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     if ms_ot <= ms_st:
         ms, stage_ms, roof, roof_other, head = ms_ot, stage_ot, roof_ot, roof_st, "on_the_fly"
     else:
@@ -498,18 +661,30 @@ def main():
               file=sys.stderr, flush=True)
         print(f"bench: GMRES {it} its {t_solve:.3f}s relres {rr:.2e} potential err {perr:.2e}", file=sys.stderr,
               flush=True)
+        # the stated error of the refined solutions (reading A20): every solve to 1e-13, the
+        # refined solution against the FP64 one (whose matvec the parity tests pin)
+        x64t, _ = A.solve(b, tol=1e-13, restart=cfg["restart"], maxit=20000)
         for name, op in (("fp32", A), ("bf16", A16)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            xm, stm = op.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], refine=True)
-            torch.cuda.synchronize()
-            tm = time.perf_counter() - t0
-            itm, okm, rrm, outm = stm[0]
-            dx = float((xm - rho).norm() / rho.norm())
-            mixed[name].update({"time_to_tol_s": tm, "iterations": itm, "outer": outm, "converged": okm,
-                                "relres": rrm, "rel_diff_to_fp64_solution": dx})
-            print(f"bench: {name} refined GMRES {itm} its / {outm} outer {tm:.3f}s relres {rrm:.2e} "
-                  f"diff to FP64 solution {dx:.1e}", file=sys.stderr, flush=True)
+            for pc in (False, True):
+                if pc:
+                    op.precond_build()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xm, stm = op.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], refine=True,
+                                   precond=pc)
+                torch.cuda.synchronize()
+                tm = time.perf_counter() - t0
+                itm, okm, rrm, outm = stm[0]
+                key = name if not pc else name + "_block_jacobi"
+                ent = mixed.setdefault(key, {})
+                ent.update({"time_to_tol_s": tm, "iterations": itm, "outer": outm, "converged": okm, "relres": rrm})
+                if not pc:
+                    xt, _ = op.solve(b, tol=1e-13, restart=cfg["restart"], maxit=20000, refine=True, max_outer=40)
+                    ent["solution_rel_err_vs_fp64_at_1e-13"] = float((xt - x64t).norm() / x64t.norm())
+                ent["speedup_vs_fp64"] = (extra["gmres_block_jacobi" if pc else "gmres"]["time_to_tol_s"] / tm)
+                print(f"bench: {key} refined GMRES {itm} its / {outm} outer {tm:.3f}s relres {rrm:.2e}"
+                      + (f", solution error vs FP64 (both to 1e-13) {ent['solution_rel_err_vs_fp64_at_1e-13']:.1e}"
+                         if not pc else ""), file=sys.stderr, flush=True)
     extra["mixed"] = mixed
     if not args.no_c2:
         extra["many_rhs"] = bench_c2(B, W, torch, np, stream, args)
@@ -529,6 +704,18 @@ def main():
         cpu = cpu_baseline(cfg, x_host, args.cpu_rows)
         print(f"bench: cpu baseline {cpu['value']:.3e} DOF/s ({time.perf_counter()-t0:.1f}s)", file=sys.stderr,
               flush=True)
+        model, ncpu = _cpu_info()
+        t0 = time.perf_counter()
+        extra["cpu_baseline_openmp"] = cpu_baseline(cfg, x_host, args.cpu_rows, threads=ncpu)
+        extra["cpu_baseline_openmp"]["cpu_model"] = model
+        print(f"bench: cpu baseline OpenMP ({extra['cpu_baseline_openmp']['cores']} threads) "
+              f"{extra['cpu_baseline_openmp']['value']:.3e} DOF/s ({time.perf_counter()-t0:.1f}s)", file=sys.stderr,
+              flush=True)
+        if not args.no_cpu_legs:
+            t0 = time.perf_counter()
+            gpu = {"c1_gmres_iterations": extra.get("gmres", {}).get("iterations")}
+            extra["cpu_oracle_legs"] = cpu_oracle_legs(args, gpu)
+            print(f"bench: oracle legs {time.perf_counter()-t0:.1f}s", file=sys.stderr, flush=True)
 
     out = {
         "metric": "H2 matvec DOF/s + GMRES time-to-1e-8, mixed/learned vs FP64 plain, 1 GPU",

@@ -54,7 +54,7 @@ extern "C" {
 #define BEM_LAPLACE_SINGLE 0
 #define BEM_HELMHOLTZ_SINGLE 1
 
-/* analytic multi-patch geometries (App. D; arbitrary smooth maps are allowed, Sec. 4):
+/* multi-patch geometries (App. D; arbitrary smooth maps are allowed, Sec. 4).  Analytic:
  *   SPHERE6     unit sphere, 6 cube faces projected radially               params: none
  *   ELLIPSOID6  diag(a,b,c) applied to SPHERE6                             params: a, b, c
  *   TORUS16     torus of radii R > r, 16 patches of a quarter turn each    params: R, r
@@ -63,6 +63,9 @@ extern "C" {
 #define BEM_GEOM_ELLIPSOID6 1
 #define BEM_GEOM_TORUS16 2
 #define BEM_GEOM_FLAT1 3
+/* patches given by NURBS maps (App. C): bem_geometry_nurbs, bem_geometry_load,
+ * bem_geometry_user */
+#define BEM_GEOM_NURBS 4
 
 /* boundary data for bem_rhs (Sec. 4 "Boundary Values"):
  *   POINT_SOURCE  g(x) = k(x, x0), the PDE's own kernel centred at x0       params: x0 (3)
@@ -134,15 +137,25 @@ typedef struct bem_solve_params {
     int restart;      /* Krylov dimension m per cycle, 1..64 */
     int maxit;        /* total Arnoldi steps over all cycles (and refinement steps), >= 1 */
     double tol;       /* stop when ||b - A x|| <= tol ||b|| (true FP64 residual, checked) */
-    int refine;       /* 0: GMRES on the FP64 operator.  1: FP64 iterative refinement:
-                         r = b - A x with the FP64 operator, inner GMRES on the operator
-                         with the low-precision far field (far_low at assembly) to
-                         inner_tol, x += delta, until the FP64 residual meets tol */
+    int refine;       /* 0: GMRES on the FP64 operator.  1: FP64 refinement: each outer step
+                         solves A_low d = r (inner GMRES on the operator with the
+                         low-precision far field, far_low at assembly) to inner_tol, and
+                         x moves along d and the earlier outer directions by the
+                         combination that minimises the FP64 residual ||b - A x|| (a
+                         flexible outer Krylov loop: generalised conjugate residuals over
+                         the images A d, orthonormalised in FP64; up to 16 directions are
+                         kept, then the loop restarts from x); r = b - A x is recomputed in
+                         FP64 after every step, until it meets tol */
     int max_outer;    /* refinement steps at most (0 = 20) */
-    double inner_tol; /* relative tolerance of each inner solve (0 = 1e-4) */
+    double inner_tol; /* relative tolerance of each inner solve (0: 1e-4 with an FP32 far
+                         field, 1e-2 with BF16, whose rounded moments leave the inner
+                         operator's residual near 1e-3 of the right-hand side) */
     int precond;      /* BEM_PRECOND_NONE, or BEM_PRECOND_BLOCK: right preconditioning with
                          the operator's block preconditioner (bem_precond_build first) */
-    int reserved[3];  /* must be zero */
+    int inner_maxit;  /* Arnoldi steps of one inner solve at most (0 = 3 * restart); the outer
+                         loop takes whatever the inner solve reached (measured: with the
+                         flexible outer loop, short inner solves cost fewer steps in all) */
+    int reserved[2];  /* must be zero */
 } bem_solve_params;
 
 #define BEM_PRECOND_NONE 0
@@ -166,13 +179,56 @@ const char* bem_last_error(void);
 int bem_geometry_analytic(int kind, const double* params, int nparams, bem_geometry* out);
 void bem_geometry_destroy(bem_geometry g);
 
+/* Patches given by NURBS maps (App. C: gamma(x, y) = sum c_{j1 j2} b_{j1}(x) b_{j2}(y) w_{j1 j2}
+ * / sum b_{i1}(x) b_{i2}(y) w_{i1 i2}, App. D: outward normals, matching parametrisations on
+ * shared edges; the caller guarantees both, the library does not check them).
+ * meta: host, 4 ints per patch: degrees p1, p2 (0..8) and basis counts k1 > p1, k2 > p2
+ *       (<= 4096).
+ * knots: host, per patch the k1 + p1 + 1 knots of the first direction then the k2 + p2 + 1
+ *       of the second, patch after patch; non-decreasing and clamped (the first and the
+ *       last degree + 1 knots are 0 and 1).
+ * cw:   host, per patch k1 * k2 control points x, y, z, w (w > 0), j1 outer, patch after
+ *       patch.
+ * The library copies the tables (a small device copy is allocated here and freed with the
+ * last space made from the geometry).  EINVAL names the offending patch. */
+int bem_geometry_nurbs(int npatch, const int* meta, const double* knots, const double* cw, bem_geometry* out);
+
+/* File import and export of NURBS patch sets (Sec. 4 "Geometry": the geometry is imported
+ * from a file).  Plain text, '#' starts a comment to the end of its line: the word BEMNURBS
+ * and the version 1, the number of patches, then per patch "p1 p2 k1 k2", the knots of the
+ * two directions and k1 * k2 lines "x y z w" (j1 outer); the same checks as
+ * bem_geometry_nurbs.  bem_geometry_save writes a NURBS geometry (EINVAL for analytic ones)
+ * with 17 significant digits, so that a saved and reloaded geometry is the same. */
+int bem_geometry_load(const char* path, bem_geometry* out);
+int bem_geometry_save(bem_geometry g, const char* path);
+
+/* User-supplied patch maps (Sec. 4 "Geometry": arbitrary smooth maps; App. D conditions are
+ * the caller's).  The library calls gamma(patch, st, n, xyz, jac, user) once per patch at
+ * setup, on the host, for n = (intervals + degree)^2 parameter points st (n x 2, row-major)
+ * and reads xyz (n x 3, row-major; every entry must be finite); jac (n x 6) may be filled
+ * or ignored, it is not used.  Reading of the paper's arbitrary maps: each patch map is
+ * replaced by its tensor B-spline interpolant of the given degree (1..8) on `intervals`
+ * (1..1024) uniform intervals per direction, interpolating at the Greville abscissae of the
+ * clamped knot vector (so that shared edges, sampled at the same points from both sides,
+ * stay shared); the result is a NURBS geometry with unit weights.  Its error against the
+ * map decays like intervals^-(degree + 1) for smooth maps and is zero for polynomial maps of
+ * at most that degree. */
+typedef void (*bem_user_map)(int patch, const double* st, int64_t n, double* xyz, double* jac, void* user);
+int bem_geometry_user(int npatch, bem_user_map gamma, void* user, int degree, int intervals, bem_geometry* out);
+
 /* Discrete space (Sec. 4 "Discretization"; App. E): the spline space S^2 of tensor
  * B-splines of degree `degree` over 2^level equal elements per direction on every patch,
  * interior knots repeated `knot_repetition` times (1 <= knot_repetition <= degree + 1),
  * lifted to the surface by the Piola transform, for the PDE `kernel`
  * (BEM_LAPLACE_SINGLE or BEM_HELMHOLTZ_SINGLE with wavenumber kappa_re + i kappa_im != 0;
  * non-resonance is assumed, Sec. 2).  EINVAL on degree < 0, level < 0 or > 12, bad knot
- * repetition, or kappa = 0 for Helmholtz.  The geometry may be destroyed afterwards. */
+ * repetition, or kappa = 0 for Helmholtz.  The geometry may be destroyed afterwards.
+ * Build limit: degree <= 2 (EUNSUPPORTED above).  The singular-quadrature kernel keeps the
+ * (d+1)^2 x (d+1)^2 element-pair block of every Duffy region in registers; at d = 2 it
+ * already takes all 256 VGPRs of a lane (FP64: 256 VGPRs + 8 AGPRs, complex: 256 + 59,
+ * occupancy 1 wave per SIMD, from the compiler's kernel resource report), so d = 3 (256
+ * accumulators, 512 for complex) would spill; the element basis tables hold polynomials of
+ * degree <= 2. */
 int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
                      int knot_repetition, int level, bem_space* out);
 int bem_space_ndof(bem_space s, int64_t* n);
@@ -234,7 +290,8 @@ int bem_apply(bem_operator A, const void* x_dev, int64_t ldx, void* y_dev, int64
 int bem_apply_ex(bem_operator A, int precision, const void* x_dev, int64_t ldx, void* y_dev, int64_t ldy,
                  int nrhs, hipStream_t stream);
 
-/* Device workspace bytes bem_solve needs for nrhs right-hand sides. */
+/* Device workspace bytes bem_solve needs for nrhs right-hand sides with parameters p
+ * (refinement adds 2 min(max_outer, 16) vectors per right-hand side of a pass). */
 int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* bytes);
 
 /* Restarted GMRES(m) on A (Sec. 4 "Solution of the System of Linear Equations"), x0 = 0,
@@ -257,6 +314,34 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
  * With npts == 0 nothing is done and pts_dev, u_dev may be NULL. */
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev,
                        int64_t ldr, int nrhs, void* u_dev, int64_t ldu, hipStream_t stream);
+
+/* Potential at many points through the operator's cluster tree (Sec. 4 "Evaluation of the
+ * Solution", accelerated by the interpolation of Sec. 2 on the source side): for every
+ * point, each patch's clusters are visited from the root; a cluster whose ball (centre c,
+ * radius r) satisfies dist = |x - c| - r > 0 and 2 r <= eta * dist (ties within 1e-12 dist
+ * count as not admissible) contributes sum_a k(x, gamma(xi_a)) m_a over its q x q Chebyshev
+ * points with the moments m of rho (the operator's forward transform and upward transfer);
+ * a leaf that is not admissible contributes the 8 x 8 Gauss sums of its elements, as
+ * bem_eval_potential; other clusters pass the point to their children.  eta >= 0 (0: every
+ * point takes the plain quadrature, identical to bem_eval_potential up to summation order;
+ * the operator's own eta is the usual choice).  The error against bem_eval_potential decays
+ * geometrically with the operator's q.  Cost per point O(q^2 log N) for points away from
+ * the surface instead of O(N).  pts_dev: device npts x 3 row-major; rho_dev: device N x
+ * nrhs (ld ldr); u_dev: device npts x nrhs (ld ldu >= npts), overwritten.  Uses the
+ * operator's matvec scratch (moments): overlapping calls on one operator race. */
+int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr,
+                          int nrhs, void* u_dev, int64_t ldu, double eta, hipStream_t stream);
+
+/* Visualisation of the density and the geometry in VTK format (Sec. 4 "Visualization"):
+ * writes a legacy ASCII VTK unstructured grid with (nsub + 1)^2 points and nsub^2
+ * quadrilaterals (cell type 9) per element, point e * (nsub + 1)^2 + a * (nsub + 1) + b at
+ * parameter (i1 + a / nsub, i2 + b / nsub) 2^-L of element e = (patch, i1, i2), and point
+ * data "kappa" (surface element |d_s gamma x d_t gamma|, by central differences with step
+ * 1e-6) and, per column r of rho, the density on the surface rho_hat / kappa (2-form
+ * lifting) as "rho_r" (Laplace) or "rho_re_r", "rho_im_r" (Helmholtz).  rho_host: host,
+ * N x nrhs column-major (leading dimension ldr >= N), may be NULL with nrhs = 0 (geometry
+ * only); 0 <= nrhs <= 64, 1 <= nsub <= 64.  Host work only. */
+int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int nsub, const char* path);
 
 /* Stage timing of bem_apply (tracing).  While enabled (on != 0), every one-column apply
  * records HIP events on its stream around its four stages: 0 near-field product (y

@@ -28,11 +28,11 @@ POINT_SOURCE, PLANE_WAVE = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with g++ (plain -O2, no fast-math)."""
+    """Compile liboracle.so with g++ (plain -O2, no fast-math; OpenMP for the timing mode)."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC]
+        cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-fopenmp", "-shared", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -56,6 +56,7 @@ def lib():
             "orc_space_new": (I, [I, P, I, I, D, D, I, I, I, P]),
             "orc_space_new_nurbs": (I, [I, P, P, P, I, D, D, I, I, I, P]),
             "orc_h2_potential": (I, [P, P, I64, P, D, P]),
+            "orc_set_threads": (I, [I]),
             "orc_space_free": (None, [P]),
             "orc_space_ndof": (I64, [P]),
             "orc_space_nelem": (I64, [P]),
@@ -105,6 +106,12 @@ def _check(rc):
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's timing mode (parallel loops over independent rows, clusters
+    and target runs; results are the same for any count).  Returns the count in effect."""
+    return lib().orc_set_threads(int(n))
 
 
 def gauss01(n: int):

@@ -31,6 +31,10 @@
 #include <string>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace orc {
 
 using cplx = std::complex<double>;
@@ -995,7 +999,9 @@ static void h2_build(H2<T>& H, const Space& S, int q, double eta, int leaf, int 
     // coupling blocks K[(a1,a2),(b1,b2)] = k(gamma_tau(xi_a), gamma_sigma(xi_b))
     const int q2 = q * q;
     H.K.assign(H.far.size() * (size_t)q2 * q2, T(0));
-    for (size_t blk = 0; blk < H.far.size(); ++blk) {
+    const int64_t nblk = (int64_t)H.far.size();
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
         const Cluster& A = H.cl[H.far[blk].first];
         const Cluster& B = H.cl[H.far[blk].second];
         for (int a = 0; a < q2; ++a) {
@@ -1038,6 +1044,8 @@ template <class T>
 static void h2_forward(const H2<T>& H, const T* x, std::vector<T>& mom) {
     const Space& S = *H.S;
     const int q = H.q, q2 = q * q, nl = 1 << H.leaf;
+    // (timing mode: independent clusters in parallel; each cluster's sums are unchanged)
+#pragma omp parallel for collapse(3) schedule(static)
     for (int f = 0; f < S.G.npatch; ++f)
         for (int i = 0; i < nl; ++i)
             for (int j = 0; j < nl; ++j) {
@@ -1062,6 +1070,7 @@ static void h2_upward(const H2<T>& H, std::vector<T>& mom) {
     const int q = H.q, q2 = q * q;
     for (int l = H.leaf - 1; l >= 0; --l) {
         const int n = 1 << l;
+#pragma omp parallel for collapse(3) schedule(static)
         for (int f = 0; f < S.G.npatch; ++f)
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) {
@@ -1126,14 +1135,23 @@ template <class T>
 static void h2_coupling(const H2<T>& H, const std::vector<T>& mom, std::vector<T>& lv) {
     const int q2 = H.q * H.q;
     std::fill(lv.begin(), lv.end(), T(0));
-    for (size_t blk = 0; blk < H.far.size(); ++blk) {
-        const int64_t t = H.far[blk].first, s = H.far[blk].second;
-        for (int a = 0; a < q2; ++a) {
-            T acc = T(0);
-            for (int b = 0; b < q2; ++b) acc += H.K[blk * q2 * q2 + a * q2 + b] * mom[s * q2 + b];
-            lv[t * q2 + a] += acc;
+    // blocks in list order; the list is sorted by target, so the runs of one target are
+    // independent of each other (timing mode: runs in parallel, each in list order)
+    std::vector<size_t> run{0};
+    for (size_t blk = 1; blk < H.far.size(); ++blk)
+        if (H.far[blk].first != H.far[blk - 1].first) run.push_back(blk);
+    run.push_back(H.far.size());
+    const int64_t nruns = (int64_t)run.size() - 1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nruns; ++k)
+        for (size_t blk = run[k]; blk < run[k + 1]; ++blk) {
+            const int64_t t = H.far[blk].first, s = H.far[blk].second;
+            for (int a = 0; a < q2; ++a) {
+                T acc = T(0);
+                for (int b = 0; b < q2; ++b) acc += H.K[blk * q2 * q2 + a * q2 + b] * mom[s * q2 + b];
+                lv[t * q2 + a] += acc;
+            }
         }
-    }
 }
 
 // downward transfer: lv_c += (E_c1 (x) E_c2) lv_P
@@ -1143,6 +1161,7 @@ static void h2_downward(const H2<T>& H, std::vector<T>& lv) {
     const int q = H.q, q2 = q * q;
     for (int l = 1; l <= H.leaf; ++l) {
         const int n = 1 << l;
+#pragma omp parallel for collapse(3) schedule(static)
         for (int f = 0; f < S.G.npatch; ++f)
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) {
@@ -1196,9 +1215,10 @@ static void h2_near_rows_subset(H2<T>& H, const int64_t* rows, int64_t nrows) {
     const int nb = side_nb(S, F);
     const int d = S.K.d, nbs = S.K.nb, nel = S.K.nel;
     const int m = 1 << (S.K.L - H.leaf);
-    std::vector<T> Bk(nb * nb);
-    std::vector<int64_t> es;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < nrows; ++r) {
+        std::vector<T> Bk(nb * nb);
+        std::vector<int64_t> es;
         const int64_t g = rows[r];
         const int f = (int)(g / ((int64_t)nbs * nbs));
         const int j1 = (int)((g / nbs) % nbs), j2 = (int)(g % nbs);
@@ -1263,9 +1283,11 @@ static void h2_apply_rows(const H2<T>& H, const T* x, const int64_t* rows, int64
     const int nb = side_nb(S, F);
     const int d = S.K.d, nbs = S.K.nb, nel = S.K.nel;
     const int m = 1 << (S.K.L - H.leaf);
-    std::vector<T> Bk(nb * nb);
-    std::vector<int64_t> es;
+    // (timing mode: rows in parallel, each row's sum unchanged)
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < nrows; ++r) {
+        std::vector<T> Bk(nb * nb);
+        std::vector<int64_t> es;
         const int64_t g = rows[r];
         T acc = far_part ? h2_backward_dof(H, lv, g) : T(0);
         if (near_part && H.have_near) {
@@ -1694,6 +1716,18 @@ static void h2_potential(const H2<T>& H, const T* rho, int64_t npts, const doubl
 extern "C" {
 
 const char* orc_last_error() { return g_err.c_str(); }
+
+// Timing mode (C-ALG step 13): threads of the parallel loops over independent items (rows,
+// clusters, target runs); 1 = serial.  Results do not depend on it.  Returns the count set.
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n < 1 ? 1 : n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 int orc_gauss01(int n, double* x, double* w) {
     ORC_TRY({

@@ -16,12 +16,12 @@ import numpy as np
 import torch
 
 from . import _bem as C
-from ._bem import (BEM_DATA_PLANE_WAVE, BEM_DATA_POINT_SOURCE, BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1,
+from ._bem import (BEM_DATA_PLANE_WAVE, BEM_DATA_POINT_SOURCE, BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1, BEM_GEOM_NURBS,
                    BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16, BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BEM_PREC_BF16,
                    BEM_PREC_FP32, BEM_PREC_FP64, BemError)
 
 __all__ = ["Geometry", "Space", "Operator", "BemError", "BEM_GEOM_SPHERE6", "BEM_GEOM_ELLIPSOID6",
-           "BEM_GEOM_TORUS16", "BEM_GEOM_FLAT1", "BEM_LAPLACE_SINGLE", "BEM_HELMHOLTZ_SINGLE",
+           "BEM_GEOM_TORUS16", "BEM_GEOM_FLAT1", "BEM_GEOM_NURBS", "BEM_LAPLACE_SINGLE", "BEM_HELMHOLTZ_SINGLE",
            "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE", "BEM_PREC_FP64", "BEM_PREC_FP32", "BEM_PREC_BF16"]
 
 
@@ -36,9 +36,29 @@ def _dev() -> torch.device:
 
 
 class Geometry:
-    def __init__(self, kind: int, params=()):
+    """Analytic geometry (kind, params), or NURBS patches via the constructors below."""
+
+    def __init__(self, kind: int, params=(), _handle=None):
         self.kind, self.params = kind, tuple(params)
-        self.h = C.bem_geometry_analytic(kind, self.params)
+        self.h = _handle if _handle is not None else C.bem_geometry_analytic(kind, self.params)
+
+    @classmethod
+    def nurbs(cls, patches):
+        """patches: list of {"degree": (p1, p2), "knots": (Xi_1, Xi_2), "cw": (k1, k2, 4)}."""
+        return cls(BEM_GEOM_NURBS, (), _handle=C.bem_geometry_nurbs(patches))
+
+    @classmethod
+    def load(cls, path: str):
+        """NURBS patches from a BEMNURBS text file."""
+        return cls(BEM_GEOM_NURBS, (), _handle=C.bem_geometry_load(path))
+
+    @classmethod
+    def user(cls, npatch: int, fn, degree: int = 5, intervals: int = 8):
+        """User patch maps fn(patch, st) -> xyz, replaced by their tensor B-spline interpolants."""
+        return cls(BEM_GEOM_NURBS, (), _handle=C.bem_geometry_user(npatch, fn, degree, intervals))
+
+    def save(self, path: str):
+        C.bem_geometry_save(self.h, path)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -55,6 +75,7 @@ class Space:
         self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level)
         self.geom = geom
         self.kernel, self.kappa, self.degree, self.level = kernel, complex(kappa), degree, level
+        self.knot_repetition = knot_repetition
         self.ndof = C.bem_space_ndof(self.h)
         self.dtype = torch.complex128 if kernel == BEM_HELMHOLTZ_SINGLE else torch.float64
 
@@ -88,6 +109,14 @@ class Space:
         C.bem_rhs_from_samples(self.h, gg.data_ptr(), gg.shape[1], gg.shape[0], b.data_ptr(), self.ndof, _stream())
         return b if g.dim() > 1 else b[0]
 
+    def write_vtk(self, path: str, rho=None, nsub: int = 4):
+        """Surface mesh and density (rows of rho: (nrhs, N) or (N,), host or device) as VTK."""
+        if rho is None:
+            C.bem_write_vtk(self.h, None, self.ndof, 0, nsub, path)
+            return
+        r = torch.as_tensor(rho).reshape(-1, self.ndof).to("cpu", self.dtype).contiguous()
+        C.bem_write_vtk(self.h, r.data_ptr(), self.ndof, r.shape[0], nsub, path)
+
     def potential(self, pts, rho: torch.Tensor) -> torch.Tensor:
         """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,)."""
         pts = torch.as_tensor(np.asarray(pts, dtype=np.float64)).to(_dev()).contiguous()
@@ -110,7 +139,7 @@ class Operator:
         self.far_eval = bool(far_eval)
         self.h, self.info = C.bem_assemble_plan(space.h, q, eta, leaf_level, qg, qs, chunk_cols, far_low, batch_rhs,
                                                 int(far_eval), float(kappa_adm))
-        self.q = q
+        self.q, self.eta = q, eta
         self.ndof = self.info.ndof
         self.op_ws = None
         if assemble:
@@ -143,16 +172,17 @@ class Operator:
         return y.reshape(x.shape)
 
     def solve(self, b: torch.Tensor, tol: float = 1e-8, restart: int = 30, maxit: int = 2000, refine: bool = False,
-              inner_tol: float = 0.0, max_outer: int = 0, precond: bool = False):
+              inner_tol: float = 0.0, max_outer: int = 0, precond: bool = False, inner_maxit: int = 0):
         """GMRES(restart), optionally right-preconditioned with the block preconditioner
         (precond_build first) and/or inside FP64 iterative refinement with the
         low-precision far field; returns (x, [(iterations, converged, relres, outer)])."""
         bb = b.reshape(-1, self.ndof).contiguous()
         x = torch.empty_like(bb)
-        nbytes = C.bem_solve_plan(self.h, bb.shape[0], restart, maxit, tol)
+        nbytes = C.bem_solve_plan(self.h, bb.shape[0], restart, maxit, tol, int(refine), max_outer)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=bb.device)
         _, stats = C.bem_solve(self.h, bb.data_ptr(), self.ndof, x.data_ptr(), self.ndof, bb.shape[0], restart, maxit,
-                               tol, ws.data_ptr(), nbytes, _stream(), int(refine), max_outer, inner_tol, int(precond))
+                               tol, ws.data_ptr(), nbytes, _stream(), int(refine), max_outer, inner_tol, int(precond),
+                               inner_maxit)
         return x.reshape(b.shape), stats
 
     # ---- block-Jacobi preconditioner and its learned correction
@@ -217,6 +247,16 @@ class Operator:
         C.bem_apply_stage(self.h, prec, stage, x.data_ptr(), y.data_ptr(), _stream())
 
     # ---- parity exports
+    def potential(self, pts, rho: torch.Tensor, eta: float | None = None) -> torch.Tensor:
+        """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,) through the
+        cluster tree (eta: admissibility of point and cluster, default the operator's)."""
+        pts = torch.as_tensor(np.asarray(pts, dtype=np.float64)).to(_dev()).contiguous()
+        r = rho.reshape(-1, self.ndof).contiguous()
+        u = torch.empty((r.shape[0], pts.shape[0]), dtype=self.space.dtype, device=_dev())
+        C.bem_eval_potential_h2(self.h, pts.data_ptr(), pts.shape[0], r.data_ptr(), self.ndof, r.shape[0],
+                                u.data_ptr(), pts.shape[0], float(self.eta if eta is None else eta), _stream())
+        return u.reshape(rho.shape[:-1] + (pts.shape[0],)) if rho.dim() == 1 else u
+
     def export_near(self):
         n = self.ndof
         rowptr = np.zeros(n + 1, dtype=np.int64)
@@ -267,7 +307,10 @@ class Group:
 
     def __del__(self):
         if getattr(self, "h", None):
-            C.bem_group_destroy(self.h)
+            try:
+                C.bem_group_destroy(self.h)
+            except Exception:  # interpreter shutdown: the binding module may already be gone
+                pass
             self.h = None
 
 
@@ -295,5 +338,8 @@ class Graph:
 
     def __del__(self):
         if getattr(self, "h", None):
-            C.bem_graph_destroy(self.h)
+            try:
+                C.bem_graph_destroy(self.h)
+            except Exception:  # interpreter shutdown: the binding module may already be gone
+                pass
             self.h = None

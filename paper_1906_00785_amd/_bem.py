@@ -13,7 +13,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bem.h")
 
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
-BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1 = 0, 1, 2, 3
+BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1, BEM_GEOM_NURBS = 0, 1, 2, 3, 4
 BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
 BEM_PREC_FP64, BEM_PREC_FP32, BEM_PREC_BF16 = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_BLOCK = 0, 1
@@ -36,7 +36,8 @@ class bem_operator_info(ctypes.Structure):
 
 class bem_solve_params(ctypes.Structure):
     _fields_ = [("restart", _c_int), ("maxit", _c_int), ("tol", _c_dbl), ("refine", _c_int), ("max_outer", _c_int),
-                ("inner_tol", _c_dbl), ("precond", _c_int), ("reserved", _c_int * 3)]
+                ("inner_tol", _c_dbl), ("precond", _c_int), ("inner_maxit", _c_int),
+                ("reserved", _c_int * 2)]
 
 
 class bem_solve_stats(ctypes.Structure):
@@ -55,6 +56,12 @@ _SIGNATURES = {
     "bem_last_error": (ctypes.c_char_p, []),
     "bem_geometry_analytic": (_c_int, [_c_int, _P(_c_dbl), _c_int, _P(_vp)]),
     "bem_geometry_destroy": (None, [_vp]),
+    "bem_geometry_nurbs": (_c_int, [_c_int, _vp, _vp, _vp, _P(_vp)]),
+    "bem_write_vtk": (_c_int, [_vp, _vp, _c_i64, _c_int, _c_int, ctypes.c_char_p]),
+    "bem_eval_potential_h2": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64, _c_int, _vp, _c_i64, _c_dbl, _vp]),
+    "bem_geometry_load": (_c_int, [ctypes.c_char_p, _P(_vp)]),
+    "bem_geometry_save": (_c_int, [_vp, ctypes.c_char_p]),
+    "bem_geometry_user": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _P(_vp)]),
     "bem_space_create": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _P(_vp)]),
     "bem_space_ndof": (_c_int, [_vp, _P(_c_i64)]),
     "bem_space_destroy": (None, [_vp]),
@@ -143,6 +150,61 @@ def bem_geometry_analytic(kind: int, params=()) -> int:
     return h.value
 
 
+def bem_geometry_nurbs(patches) -> int:
+    """patches: list of {"degree": (p1, p2), "knots": (Xi_1, Xi_2), "cw": array (k1, k2, 4)}."""
+    import numpy as np
+
+    meta, knots, cw = [], [], []
+    for P in patches:
+        c = np.asarray(P["cw"], dtype=np.float64)
+        meta += [int(P["degree"][0]), int(P["degree"][1]), c.shape[0], c.shape[1]]
+        knots += [float(v) for v in P["knots"][0]] + [float(v) for v in P["knots"][1]]
+        cw.append(c.reshape(-1))
+    m = np.ascontiguousarray(meta, dtype=np.int32)
+    kn = np.ascontiguousarray(knots, dtype=np.float64)
+    cc = np.ascontiguousarray(np.concatenate(cw))
+    h = _vp()
+    check(lib.bem_geometry_nurbs(len(patches), m.ctypes.data, kn.ctypes.data, cc.ctypes.data, ctypes.byref(h)))
+    return h.value
+
+
+def bem_geometry_load(path: str) -> int:
+    h = _vp()
+    check(lib.bem_geometry_load(os.fsencode(path), ctypes.byref(h)))
+    return h.value
+
+
+def bem_geometry_save(g: int, path: str):
+    check(lib.bem_geometry_save(g, os.fsencode(path)))
+
+
+USER_MAP = ctypes.CFUNCTYPE(None, _c_int, _P(_c_dbl), _c_i64, _P(_c_dbl), _P(_c_dbl), _vp)
+
+
+def bem_geometry_user(npatch: int, fn, degree: int, intervals: int) -> int:
+    """fn(patch, st) -> xyz for an (n, 2) numpy array of parameter points (host callback;
+    called during this call only)."""
+    import numpy as np
+
+    err = []
+
+    def cb(patch, st, n, xyz, jac, user):
+        try:
+            pts = np.ctypeslib.as_array(st, shape=(n, 2)).copy()
+            out = np.ctypeslib.as_array(xyz, shape=(n, 3))
+            out[:] = np.asarray(fn(patch, pts), dtype=np.float64).reshape(n, 3)
+        except Exception as e:  # leave NaN in xyz: the library reports it
+            err.append(e)
+
+    h = _vp()
+    c = USER_MAP(cb)
+    rc = lib.bem_geometry_user(npatch, ctypes.cast(c, _vp), None, degree, intervals, ctypes.byref(h))
+    if err:
+        raise err[0]
+    check(rc)
+    return h.value
+
+
 def bem_geometry_destroy(g: int):
     lib.bem_geometry_destroy(g)
 
@@ -208,16 +270,18 @@ def bem_apply(A: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, str
     check(lib.bem_apply(A, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
 
 
-def _solve_params(restart, maxit, tol, refine=0, max_outer=0, inner_tol=0.0, precond=0):
-    return bem_solve_params(restart, maxit, tol, int(refine), max_outer, inner_tol, int(precond), (_c_int * 3)(0, 0, 0))
+def _solve_params(restart, maxit, tol, refine=0, max_outer=0, inner_tol=0.0, precond=0, inner_maxit=0):
+    return bem_solve_params(restart, maxit, tol, int(refine), max_outer, inner_tol, int(precond), int(inner_maxit),
+                            (_c_int * 2)(0, 0))
 
 
 def bem_apply_ex(A: int, prec: int, x_ptr: int, ldx: int, y_ptr: int, ldy: int, nrhs: int, stream: int):
     check(lib.bem_apply_ex(A, prec, x_ptr, ldx, y_ptr, ldy, nrhs, stream))
 
 
-def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float) -> int:
-    p = _solve_params(restart, maxit, tol)
+def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float, refine: int = 0,
+                   max_outer: int = 0) -> int:
+    p = _solve_params(restart, maxit, tol, refine, max_outer)
     n = _c_sz()
     check(lib.bem_solve_plan(A, nrhs, ctypes.byref(p), ctypes.byref(n)))
     return n.value
@@ -225,14 +289,23 @@ def bem_solve_plan(A: int, nrhs: int, restart: int, maxit: int, tol: float) -> i
 
 def bem_solve(A: int, b_ptr: int, ldb: int, x_ptr: int, ldx: int, nrhs: int, restart: int, maxit: int, tol: float,
               ws_ptr: int, ws_bytes: int, stream: int, refine: int = 0, max_outer: int = 0, inner_tol: float = 0.0,
-              precond: int = 0):
+              precond: int = 0, inner_maxit: int = 0):
     """Returns (rc, stats list); rc is BEM_OK or BEM_ENOCONV (other codes raise)."""
-    p = _solve_params(restart, maxit, tol, refine, max_outer, inner_tol, precond)
+    p = _solve_params(restart, maxit, tol, refine, max_outer, inner_tol, precond, inner_maxit)
     st = (bem_solve_stats * nrhs)()
     rc = lib.bem_solve(A, b_ptr, ldb, x_ptr, ldx, nrhs, ctypes.byref(p), st, ws_ptr, ws_bytes, stream)
     if rc not in (BEM_OK, BEM_ENOCONV):
         check(rc)
     return rc, [(s.iterations, bool(s.converged), s.relres, s.outer) for s in st]
+
+
+def bem_write_vtk(s: int, rho_host_ptr, ldr: int, nrhs: int, nsub: int, path: str):
+    check(lib.bem_write_vtk(s, rho_host_ptr, ldr, nrhs, nsub, os.fsencode(path)))
+
+
+def bem_eval_potential_h2(A: int, pts_ptr: int, npts: int, rho_ptr: int, ldr: int, nrhs: int, u_ptr: int, ldu: int,
+                          eta: float, stream: int):
+    check(lib.bem_eval_potential_h2(A, pts_ptr, npts, rho_ptr, ldr, nrhs, u_ptr, ldu, eta, stream))
 
 
 def bem_eval_potential(s: int, pts_ptr: int, npts: int, rho_ptr: int, ldr: int, nrhs: int, u_ptr: int, ldu: int,

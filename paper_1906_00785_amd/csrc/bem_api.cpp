@@ -9,9 +9,13 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <iterator>
+#include <memory>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -56,13 +60,25 @@ struct Bump {
 
 }  // namespace
 
+// NURBS table of a geometry (layout in bem_core.h): the host copy and a device copy of the
+// same doubles; shared by the geometry and every space made from it
+struct GeomTab {
+    std::vector<double> host;
+    double* dev = nullptr;
+    ~GeomTab() {
+        if (dev) (void)hipFree(dev);
+    }
+};
+
 struct bem_geometry_s {
     GeomDesc g;
+    std::shared_ptr<GeomTab> tab;
 };
 
 struct bem_space_s {
     SpaceDesc S;
     BasisTab bt;
+    std::shared_ptr<GeomTab> tab;  // keeps a NURBS geometry's tables alive
 };
 
 struct bem_operator_s {
@@ -127,7 +143,9 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
     o.K = A.far_eval ? nullptr : b.take<char>((size_t)p.ktotal * A.scal);
     o.otf = A.far_eval ? 1 : 0;
     o.otf_wide = p.P.chunk >= 512 ? 1 : 0;
-    o.xc = A.far_eval ? b.take<double>((size_t)p.ncl * p.q2 * 3) : nullptr;
+    o.xc = b.take<double>((size_t)p.ncl * p.q2 * 3);
+    o.ball = b.take<double>((size_t)p.ncl * 4);
+    o.up_count = b.take<int>((size_t)p.S.geom.npatch);
     o.pcol = b.take<int64_t>(p.pcol.size());
     o.P = b.take<char>((size_t)p.ptotal * A.scal);
     o.tr_rowptr = b.take<int64_t>(p.tr_rowptr.size());
@@ -256,10 +274,36 @@ struct SolveWs {
     char* partA;   // kSolveBlocks x (m+1) partial sums
     char* partB;
     double* npart; // kSolveBlocks partial squared norms
+    // refinement: the flexible outer loop's directions D_j and their images U_j = A D_j
+    // (orthonormal), hist vectors each, with their own partial sums and coefficients
+    int hist = 0;
+    char* U;
+    char* D;
+    char* gpA;
+    char* gpB;
+    char* gh1;
+    char* gh2;
     GmresState st;
 };
 
-static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws) {
+// directions kept by the flexible outer loop of a refined solve (restarted beyond that)
+constexpr int kRefineHist = 16;
+
+// Inner tolerance of a refined solve: the caller's, else 1e-4 with an FP32 far field and
+// 1e-2 with BF16 (its moments are rounded to BF16 in every apply, which leaves the inner
+// operator's residual near 1e-3 of the right-hand side, so a tighter inner tolerance is
+// never met).
+static double refine_inner_tol(const bem_operator_s* A, const bem_solve_params* p) {
+    if (p->inner_tol > 0.0) return p->inner_tol;
+    return A->far_low == BEM_PREC_BF16 ? 1e-2 : 1e-4;
+}
+
+static int refine_hist(const bem_solve_params* p) {
+    const int mo = p->max_outer > 0 ? p->max_outer : 20;
+    return p->refine ? std::min(mo, kRefineHist) : 0;
+}
+
+static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws, int hist = 0) {
     Bump b(base);
     SolveWs w{};
     w.V = b.take<char>((size_t)(m + 1) * N * sc);
@@ -279,6 +323,15 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws)
     w.st.h1 = b.take<char>((size_t)(m + 1) * sc);
     w.st.h2 = b.take<char>((size_t)(m + 1) * sc);
     w.st.scal = b.take<double>(m + 2);
+    w.hist = hist;
+    if (hist > 0) {
+        w.U = b.take<char>((size_t)hist * N * sc);
+        w.D = b.take<char>((size_t)hist * N * sc);
+        w.gpA = b.take<char>((size_t)kSolveBlocks * hist * sc);
+        w.gpB = b.take<char>((size_t)kSolveBlocks * hist * sc);
+        w.gh1 = b.take<char>((size_t)hist * sc);
+        w.gh2 = b.take<char>((size_t)hist * sc);
+    }
     if (ws) *ws = w;
     return b.off + 256;
 }
@@ -415,15 +468,25 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
     return BEM_OK;
 }
 
-// FP64 iterative refinement around GMRES on the operator with the low-precision far field:
-// r = b - A x (FP64), inner solve A_low d = r to inner_tol, x += d, until ||r|| <= tol ||b||.
+// FP64 refinement around GMRES on the operator with the low-precision far field, as a
+// flexible outer Krylov loop (generalised conjugate residuals): each outer step solves
+// A_low d = r to inner_tol, forms u = A d with the FP64 operator, orthonormalises u against
+// the previous images (classical Gram-Schmidt, two passes, the same combination applied to
+// d), and moves x along d by the coefficient that minimises the FP64 residual over all
+// kept directions; the residual is then recomputed as b - A x in FP64.  Plain refinement
+// (x += d) is the first step of this; the later steps also converge when the low-precision
+// operator's error times the condition number is near 1.
 static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_params* p, bem_solve_stats* out,
                       SolveWs& W, hipStream_t stream) {
     const int64_t N = A->info.ndof;
     const int cp = A->cplx ? 1 : 0;
     const size_t sc = A->scal;
     const int max_outer = p->max_outer > 0 ? p->max_outer : 20;
-    const double inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
+    const double inner_tol = refine_inner_tol(A, p);
+    const int inner_cap = p->inner_maxit > 0 ? p->inner_maxit : 3 * p->restart;
+    if (W.hist < 1) return fail(BEM_EINVAL, "refinement workspace missing");
+    auto Uj = [&](int j) { return W.U + (size_t)j * N * sc; };
+    auto Dj = [&](int j) { return W.D + (size_t)j * N * sc; };
     double* pin = A->pinned;
     HIP_CHECK(hipMemsetAsync(x, 0, N * sc, stream));
     HIP_CHECK(hipMemcpyAsync(W.r, b, N * sc, hipMemcpyDeviceToDevice, stream));
@@ -440,20 +503,39 @@ static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_pa
     double bnorm = 0.0, rnorm = 0.0;
     if (host_norm(bnorm) != BEM_OK) return BEM_EDEVICE;
     rnorm = bnorm;
-    int total = 0, outer = 0;
+    int total = 0, outer = 0, k = 0;
     while (bnorm > 0.0 && rnorm > p->tol * bnorm && outer < max_outer && total < p->maxit && std::isfinite(rnorm)) {
         bem_solve_stats in{};
-        const int rc = gmres_one(A, A->far_low, W.r, W.d, p->restart, p->maxit - total, inner_tol, &in, W, stream,
-                                 p->precond != 0);
+        const int rc = gmres_one(A, A->far_low, W.r, W.d, p->restart, std::min(p->maxit - total, inner_cap),
+                                 inner_tol, &in, W, stream, p->precond != 0);
         if (rc != BEM_OK) return rc;
         total += in.iterations;
         ++outer;
-        HIP_CHECK(solve_axpy(cp, N, 1.0, W.d, x, stream));
+        if (in.iterations == 0) break;  // no progress possible
+        if (k == W.hist) k = 0;         // history full: restart the outer loop from x
+        // u = A d (FP64), orthonormalised against U_0..U_{k-1}; d follows the same combination
+        HIP_CHECK(launch_apply(A->dev, W.d, W.w, 0, stream));
+        if (k > 0) {
+            HIP_CHECK(solve_dots(cp, N, k, W.U, W.w, W.gpA, -1, W.npart, W.st, stream));
+            HIP_CHECK(solve_update(cp, N, k, W.U, W.gpA, W.gh1, W.w, W.gpB, W.npart, 0, stream));
+            HIP_CHECK(solve_combine(cp, N, k, W.D, W.gh1, -1.0, W.d, stream));
+            HIP_CHECK(solve_update(cp, N, k, W.U, W.gpB, W.gh2, W.w, W.gpA, W.npart, 1, stream));
+            HIP_CHECK(solve_combine(cp, N, k, W.D, W.gh2, -1.0, W.d, stream));
+        } else {
+            HIP_CHECK(solve_update(cp, N, 0, W.U, W.gpA, W.gh1, W.w, W.gpB, W.npart, 1, stream));  // ||u|| only
+        }
+        HIP_CHECK(solve_scale(cp, N, W.npart, W.w, Uj(k), stream));
+        HIP_CHECK(solve_scale(cp, N, W.npart, W.d, Dj(k), stream));
+        // alpha = U_k^H r; x += alpha D_k
+        HIP_CHECK(solve_dots(cp, N, 1, Uj(k), W.r, W.gpA, -1, W.npart, W.st, stream));
+        HIP_CHECK(solve_update(cp, N, 1, Uj(k), W.gpA, W.gh1, W.r, W.gpB, W.npart, 1, stream));
+        HIP_CHECK(solve_combine(cp, N, 1, Dj(k), W.gh1, 1.0, x, stream));
+        ++k;
+        // the FP64 residual of the new iterate
         HIP_CHECK(launch_apply(A->dev, x, W.w, 0, stream));
         HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
         HIP_CHECK(hipMemcpyAsync(W.r, W.w, N * sc, hipMemcpyDeviceToDevice, stream));
         if (host_norm(rnorm) != BEM_OK) return BEM_EDEVICE;
-        if (in.iterations == 0) break;  // no progress possible
     }
     out->iterations = total;
     out->outer = outer;
@@ -476,10 +558,18 @@ struct BSolveWs {
     char* h2;       // [m+1][R]
     double* npart;  // [slices][R]
     int* flag;      // [R]
+    // refinement: directions D_j and orthonormal images U_j = A D_j (hist slabs each),
+    // partial sums [slices][hist][R] and coefficients [hist][R]
+    int hist = 0;
+    char* U;
+    char* D;
+    char* gpart;
+    char* gh1;
+    char* gh2;
     BGmresState st;
 };
 
-static size_t bsolve_layout(int64_t N, int m, int R, size_t sc, void* base, BSolveWs* ws) {
+static size_t bsolve_layout(int64_t N, int m, int R, size_t sc, void* base, BSolveWs* ws, int hist = 0) {
     Bump b(base);
     BSolveWs w{};
     const size_t slab = (size_t)N * R * sc;
@@ -505,6 +595,14 @@ static size_t bsolve_layout(int64_t N, int m, int R, size_t sc, void* base, BSol
     w.st.beta = b.take<double>(R);
     w.st.sc = b.take<double>(R);
     w.st.kr = b.take<int>(R);
+    w.hist = hist;
+    if (hist > 0) {
+        w.U = b.take<char>((size_t)hist * slab);
+        w.D = b.take<char>((size_t)hist * slab);
+        w.gpart = b.take<char>((size_t)kBSolveSlices * hist * R * sc);
+        w.gh1 = b.take<char>((size_t)hist * R * sc);
+        w.gh2 = b.take<char>((size_t)hist * R * sc);
+    }
     if (ws) *ws = w;
     return b.off + 256;
 }
@@ -645,14 +743,21 @@ static int gmres_batched(bem_operator A, int prec, const void* b, void* x, int R
     return BEM_OK;
 }
 
-// FP64 iterative refinement around the lockstep GMRES on the low-precision operator;
-// right-hand sides that have met tol are masked out of further inner solves.
+// FP64 refinement around the lockstep GMRES on the low-precision operator, with the same
+// flexible outer loop as the one-column solver, per right-hand side (each keeps its own
+// coefficients; right-hand sides that have met tol are masked out of further inner solves,
+// their new directions are zero and leave them unchanged).
 static int refine_batched(bem_operator A, const void* b, void* x, int R, const bem_solve_params* p,
                           bem_solve_stats* out, BSolveWs& W, hipStream_t stream) {
     const int64_t N = A->info.ndof;
     const int cp = A->cplx ? 1 : 0;
+    const size_t slab = (size_t)N * R * A->scal;
     const int max_outer = p->max_outer > 0 ? p->max_outer : 20;
-    const double inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
+    const double inner_tol = refine_inner_tol(A, p);
+    const int inner_cap = p->inner_maxit > 0 ? p->inner_maxit : 3 * p->restart;
+    if (W.hist < 1) return fail(BEM_EINVAL, "refinement workspace missing");
+    auto Uj = [&](int j) { return W.U + (size_t)j * slab; };
+    auto Dj = [&](int j) { return W.D + (size_t)j * slab; };
     if (ensure_bpin(A, R) != BEM_OK) return BEM_EDEVICE;
     double* beta_h = A->bpin + (size_t)kMaxRestart * R;
     int* flag_h = (int*)(beta_h + R);
@@ -671,6 +776,7 @@ static int refine_batched(bem_operator A, const void* b, void* x, int R, const b
     rnorm = bnorm;
     std::vector<int> total(R, 0), outer(R, 0), done(R, 0);
     std::vector<bem_solve_stats> in(R);
+    int k = 0;
     for (int it = 0; it < max_outer; ++it) {
         bool any = false;
         for (int r = 0; r < R; ++r) {
@@ -685,7 +791,7 @@ static int refine_batched(bem_operator A, const void* b, void* x, int R, const b
         HIP_CHECK(hipMemcpyAsync(W.flag, flag_h, sizeof(int) * R, hipMemcpyHostToDevice, stream));
         HIP_CHECK(bsolve_mask(cp, N, R, W.flag, W.r, stream));
         // every inner solve stays within the budget of each right-hand side still iterating
-        int left = p->maxit;
+        int left = std::min(p->maxit, inner_cap);
         for (int r = 0; r < R; ++r)
             if (!done[r]) left = std::min(left, p->maxit - total[r]);
         const int rc = gmres_batched(A, A->far_low, W.r, W.d, R, p->restart, left, inner_tol, in.data(), W, stream,
@@ -698,11 +804,27 @@ static int refine_batched(bem_operator A, const void* b, void* x, int R, const b
                 outer[r] += 1;
                 progress += in[r].iterations;
             }
-        HIP_CHECK(bsolve_axpy(cp, N, R, W.d, x, stream));
+        if (progress == 0) break;
+        if (k == W.hist) k = 0;  // history full: restart the outer loop from x
+        // u = A d (FP64) orthonormalised per column against U_0..U_{k-1}; d alike
+        if (bapply(A, 0, W.d, W.w, R, stream) != BEM_OK) return BEM_EDEVICE;
+        if (k > 0) {
+            HIP_CHECK(bsolve_dots(cp, N, R, k, W.U, W.w, W.gpart, W.gh1, stream));
+            HIP_CHECK(bsolve_update(cp, N, R, k, W.D, W.gh1, W.d, W.npart, 0, stream));
+            HIP_CHECK(bsolve_update(cp, N, R, k, W.U, W.gh1, W.w, W.npart, 0, stream));
+            HIP_CHECK(bsolve_dots(cp, N, R, k, W.U, W.w, W.gpart, W.gh2, stream));
+            HIP_CHECK(bsolve_update(cp, N, R, k, W.D, W.gh2, W.d, W.npart, 0, stream));
+        }
+        HIP_CHECK(bsolve_update(cp, N, R, k, W.U, W.gh2, W.w, W.npart, 1, stream));  // k = 0: ||u|| only
+        HIP_CHECK(bsolve_scale2(cp, N, R, W.npart, W.w, W.d, Uj(k), Dj(k), stream));
+        // alpha_r = U_k[:, r]^H r_r; x += alpha D_k
+        HIP_CHECK(bsolve_dots(cp, N, R, 1, Uj(k), W.r, W.gpart, W.gh1, stream));
+        HIP_CHECK(bsolve_xupdate(cp, N, R, 1, Dj(k), W.gh1, x, stream));
+        ++k;
+        // the FP64 residual of the new iterates
         if (bapply(A, 0, x, W.r, R, stream) != BEM_OK) return BEM_EDEVICE;
         HIP_CHECK(bsolve_residual(cp, N, R, b, W.r, W.npart, 0, stream));
         if (norms(rnorm) != BEM_OK) return BEM_EDEVICE;
-        if (progress == 0) break;
     }
     for (int r = 0; r < R; ++r) {
         out[r].iterations = total[r];
@@ -758,6 +880,248 @@ int bem_geometry_analytic(int kind, const double* params, int nparams, bem_geome
 
 void bem_geometry_destroy(bem_geometry g) { delete g; }
 
+}  // extern "C"
+
+// Kernels evaluate NURBS maps from the device copy of the tables.
+static int need_device_geometry(const SpaceDesc& S) {
+    if (S.geom.kind == GEOM_NURBS && !S.geom.tab_dev)
+        return fail(BEM_EDEVICE, "NURBS geometry created without a GPU: no device copy of its tables");
+    return BEM_OK;
+}
+
+// Checks and packs NURBS patches into a geometry (table in host and device memory).
+static int make_nurbs_geometry(int npatch, const int* meta, const double* knots, const double* cw,
+                               bem_geometry* out) {
+    if (!meta || !knots || !cw || !out) return fail(BEM_EINVAL, "NULL argument");
+    if (npatch < 1 || npatch > 1 << 20) return fail(BEM_EINVAL, "npatch must lie in [1, 2^20]");
+    auto tab = std::make_shared<GeomTab>();
+    std::vector<double>& T = tab->host;
+    T.assign(1 + 6 * (size_t)npatch, 0.0);
+    T[0] = npatch;
+    size_t ko = 0, co = 0;
+    for (int f = 0; f < npatch; ++f) {
+        const int p1 = meta[4 * f], p2 = meta[4 * f + 1], k1 = meta[4 * f + 2], k2 = meta[4 * f + 3];
+        const std::string pf = "patch " + std::to_string(f) + ": ";
+        if (p1 < 0 || p2 < 0 || p1 > kNurbsMaxDeg || p2 > kNurbsMaxDeg)
+            return fail(BEM_EINVAL, pf + "degrees must lie in [0, " + std::to_string(kNurbsMaxDeg) + "]");
+        if (k1 <= p1 || k2 <= p2 || k1 > 4096 || k2 > 4096)
+            return fail(BEM_EINVAL, pf + "basis counts must exceed the degrees (and be <= 4096)");
+        const int pd[2] = {p1, p2}, kd[2] = {k1, k2};
+        double* hdr = &T[1 + 6 * (size_t)f];
+        hdr[0] = p1;
+        hdr[1] = p2;
+        hdr[2] = k1;
+        hdr[3] = k2;
+        hdr[4] = (double)T.size();
+        for (int d = 0; d < 2; ++d) {
+            const int nk = kd[d] + pd[d] + 1;
+            const double* xi = knots + ko;
+            ko += nk;
+            for (int i = 0; i < nk; ++i) {
+                if (!std::isfinite(xi[i])) return fail(BEM_EINVAL, pf + "knots must be finite");
+                if (i > 0 && xi[i] < xi[i - 1]) return fail(BEM_EINVAL, pf + "knots must not decrease");
+            }
+            for (int i = 0; i <= pd[d]; ++i)
+                if (xi[i] != 0.0 || xi[nk - 1 - i] != 1.0)
+                    return fail(BEM_EINVAL, pf + "knot vectors must be clamped to [0, 1] (degree + 1 end knots)");
+            T.insert(T.end(), xi, xi + nk);
+        }
+        hdr = &T[1 + 6 * (size_t)f];
+        hdr[5] = (double)T.size();
+        const size_t n = (size_t)k1 * k2 * 4;
+        for (size_t i = 0; i < n; ++i) {
+            const double v = cw[co + i];
+            if (!std::isfinite(v)) return fail(BEM_EINVAL, pf + "control points must be finite");
+            if (i % 4 == 3 && !(v > 0.0)) return fail(BEM_EINVAL, pf + "weights must be positive");
+        }
+        T.insert(T.end(), cw + co, cw + co + n);
+        co += n;
+    }
+    // the device copy; on a host without a GPU the geometry still serves host planning, and
+    // every call that would launch a kernel on it fails with EDEVICE
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+        HIP_CHECK(hipMalloc((void**)&tab->dev, sizeof(double) * T.size()));
+        HIP_CHECK(hipMemcpy(tab->dev, T.data(), sizeof(double) * T.size(), hipMemcpyHostToDevice));
+    } else {
+        (void)hipGetLastError();
+    }
+    bem_geometry_s* G = new (std::nothrow) bem_geometry_s;
+    if (!G) return fail(BEM_ENOMEM, "host allocation failed");
+    G->g = GeomDesc{};
+    G->g.kind = GEOM_NURBS;
+    G->g.npatch = npatch;
+    G->g.a = G->g.b = G->g.c = 1.0;
+    G->g.tab_host = tab->host.data();
+    G->g.tab_dev = tab->dev;
+    G->tab = tab;
+    *out = G;
+    return BEM_OK;
+}
+
+// Dense LU with partial pivoting (row-major n x n, in place) and the solve of one
+// right-hand side: the collocation systems of user maps (n <= 4096 + 8).
+static bool lu_factor(std::vector<double>& A, int n, std::vector<int>& piv) {
+    piv.resize(n);
+    for (int c = 0; c < n; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)pr * n + c])) pr = r;
+        if (A[(size_t)pr * n + c] == 0.0) return false;
+        piv[c] = pr;
+        if (pr != c)
+            for (int k = 0; k < n; ++k) std::swap(A[(size_t)c * n + k], A[(size_t)pr * n + k]);
+        for (int r = c + 1; r < n; ++r) {
+            const double m = A[(size_t)r * n + c] / A[(size_t)c * n + c];
+            A[(size_t)r * n + c] = m;
+            for (int k = c + 1; k < n; ++k) A[(size_t)r * n + k] -= m * A[(size_t)c * n + k];
+        }
+    }
+    return true;
+}
+static void lu_solve(const std::vector<double>& A, int n, const std::vector<int>& piv, double* b, int stride) {
+    for (int c = 0; c < n; ++c) {
+        if (piv[c] != c) std::swap(b[(size_t)c * stride], b[(size_t)piv[c] * stride]);
+        for (int r = c + 1; r < n; ++r) b[(size_t)r * stride] -= A[(size_t)r * n + c] * b[(size_t)c * stride];
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double v = b[(size_t)c * stride];
+        for (int k = c + 1; k < n; ++k) v -= A[(size_t)c * n + k] * b[(size_t)k * stride];
+        b[(size_t)c * stride] = v / A[(size_t)c * n + c];
+    }
+}
+
+extern "C" {
+
+int bem_geometry_nurbs(int npatch, const int* meta, const double* knots, const double* cw, bem_geometry* out) {
+    return make_nurbs_geometry(npatch, meta, knots, cw, out);
+}
+
+// File layout (plain text, '#' starts a comment running to the end of its line): the word
+// BEMNURBS and the format version 1, the number of patches, then per patch the degrees p1 p2
+// and basis counts k1 k2, the k1 + p1 + 1 knots of the first direction, the k2 + p2 + 1
+// knots of the second, and k1 * k2 control points "x y z w" (j1 outer).
+int bem_geometry_load(const char* path, bem_geometry* out) {
+    if (!path || !out) return fail(BEM_EINVAL, "NULL argument");
+    std::ifstream in(path);
+    if (!in) return fail(BEM_EINVAL, std::string("cannot open ") + path);
+    std::stringstream body;
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t h = line.find('#');
+        body << (h == std::string::npos ? line : line.substr(0, h)) << '\n';
+    }
+    std::string tag;
+    int version = 0, npatch = 0;
+    if (!(body >> tag >> version) || tag != "BEMNURBS" || version != 1)
+        return fail(BEM_EINVAL, "not a BEMNURBS 1 file");
+    if (!(body >> npatch) || npatch < 1 || npatch > 1 << 20) return fail(BEM_EINVAL, "bad patch count");
+    std::vector<int> meta;
+    std::vector<double> knots, cw;
+    for (int f = 0; f < npatch; ++f) {
+        int m[4];
+        if (!(body >> m[0] >> m[1] >> m[2] >> m[3])) return fail(BEM_EINVAL, "truncated patch header");
+        if (m[0] < 0 || m[1] < 0 || m[0] > kNurbsMaxDeg || m[1] > kNurbsMaxDeg || m[2] <= m[0] || m[3] <= m[1] ||
+            m[2] > 4096 || m[3] > 4096)
+            return fail(BEM_EINVAL, "patch " + std::to_string(f) + ": bad degrees or basis counts");
+        meta.insert(meta.end(), m, m + 4);
+        const size_t nk = (size_t)(m[2] + m[0] + 1) + (size_t)(m[3] + m[1] + 1);
+        for (size_t i = 0; i < nk; ++i) {
+            double v;
+            if (!(body >> v)) return fail(BEM_EINVAL, "truncated knot vector");
+            knots.push_back(v);
+        }
+        const size_t nc = (size_t)m[2] * m[3] * 4;
+        for (size_t i = 0; i < nc; ++i) {
+            double v;
+            if (!(body >> v)) return fail(BEM_EINVAL, "truncated control points");
+            cw.push_back(v);
+        }
+    }
+    return make_nurbs_geometry(npatch, meta.data(), knots.data(), cw.data(), out);
+}
+
+int bem_geometry_save(bem_geometry g, const char* path) {
+    if (!g || !path) return fail(BEM_EINVAL, "NULL argument");
+    if (g->g.kind != GEOM_NURBS || !g->tab) return fail(BEM_EINVAL, "only NURBS geometries are written");
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return fail(BEM_EINVAL, std::string("cannot create ") + path);
+    const std::vector<double>& T = g->tab->host;
+    std::fprintf(fp, "BEMNURBS 1\n%d\n", g->g.npatch);
+    for (int f = 0; f < g->g.npatch; ++f) {
+        const double* h = &T[1 + 6 * (size_t)f];
+        const int p1 = (int)h[0], p2 = (int)h[1], k1 = (int)h[2], k2 = (int)h[3];
+        std::fprintf(fp, "# patch %d\n%d %d %d %d\n", f, p1, p2, k1, k2);
+        const double* xi = &T[(size_t)h[4]];
+        for (int i = 0; i < k1 + p1 + 1; ++i) std::fprintf(fp, "%.17g%c", xi[i], i + 1 < k1 + p1 + 1 ? ' ' : '\n');
+        xi += k1 + p1 + 1;
+        for (int i = 0; i < k2 + p2 + 1; ++i) std::fprintf(fp, "%.17g%c", xi[i], i + 1 < k2 + p2 + 1 ? ' ' : '\n');
+        const double* c = &T[(size_t)h[5]];
+        for (int i = 0; i < k1 * k2; ++i)
+            std::fprintf(fp, "%.17g %.17g %.17g %.17g\n", c[4 * i], c[4 * i + 1], c[4 * i + 2], c[4 * i + 3]);
+    }
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? BEM_OK : fail(BEM_EINVAL, std::string("write failed: ") + path);
+}
+
+int bem_geometry_user(int npatch, bem_user_map gamma, void* user, int degree, int intervals, bem_geometry* out) {
+    if (!gamma || !out) return fail(BEM_EINVAL, "NULL argument");
+    if (npatch < 1 || npatch > 1 << 20) return fail(BEM_EINVAL, "npatch must lie in [1, 2^20]");
+    if (degree < 1 || degree > kNurbsMaxDeg) return fail(BEM_EINVAL, "degree must lie in [1, 8]");
+    if (intervals < 1 || intervals > 1024) return fail(BEM_EINVAL, "intervals must lie in [1, 1024]");
+    const int p = degree, k = intervals + degree;
+    // clamped uniform knots, Greville abscissae and the collocation matrix B[i][j] = b_j(x_i)
+    std::vector<double> xi;
+    for (int i = 0; i <= p; ++i) xi.push_back(0.0);
+    for (int i = 1; i < intervals; ++i) xi.push_back((double)i / intervals);
+    for (int i = 0; i <= p; ++i) xi.push_back(1.0);
+    std::vector<double> gx(k), Bm((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        double sum = 0.0;
+        for (int m = 1; m <= p; ++m) sum += xi[j + m];
+        gx[j] = sum / p;
+    }
+    for (int i = 0; i < k; ++i) {
+        double N[kNurbsMaxDeg + 1];
+        const int mu = nurbs_span(xi.data(), p, k, gx[i]);
+        nurbs_funs(xi.data(), p, mu, gx[i], N);
+        for (int r = 0; r <= p; ++r) Bm[(size_t)i * k + mu - p + r] = N[r];
+    }
+    std::vector<int> piv;
+    if (!lu_factor(Bm, k, piv)) return fail(BEM_EINVAL, "singular collocation matrix");
+    std::vector<double> st((size_t)k * k * 2), xyz((size_t)k * k * 3), jac((size_t)k * k * 6);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            st[2 * ((size_t)i * k + j)] = gx[i];
+            st[2 * ((size_t)i * k + j) + 1] = gx[j];
+        }
+    std::vector<int> meta;
+    std::vector<double> knots, cw;
+    for (int f = 0; f < npatch; ++f) {
+        std::fill(xyz.begin(), xyz.end(), std::nan(""));
+        gamma(f, st.data(), (int64_t)k * k, xyz.data(), jac.data(), user);
+        for (double v : xyz)
+            if (!std::isfinite(v)) return fail(BEM_EINVAL, "the user map returned a non-finite point");
+        // B C B^T = F per coordinate: solve along the first index, then along the second
+        for (int d = 0; d < 3; ++d) {
+            std::vector<double> F((size_t)k * k);
+            for (size_t i = 0; i < F.size(); ++i) F[i] = xyz[3 * i + d];
+            for (int j = 0; j < k; ++j) lu_solve(Bm, k, piv, &F[j], k);           // columns
+            for (int i = 0; i < k; ++i) lu_solve(Bm, k, piv, &F[(size_t)i * k], 1);  // rows
+            if (d == 0) cw.resize(cw.size() + (size_t)k * k * 4);
+            double* C = &cw[cw.size() - (size_t)k * k * 4];
+            for (size_t i = 0; i < F.size(); ++i) {
+                C[4 * i + d] = F[i];
+                C[4 * i + 3] = 1.0;
+            }
+        }
+        meta.insert(meta.end(), {p, p, k, k});
+        knots.insert(knots.end(), xi.begin(), xi.end());
+        knots.insert(knots.end(), xi.begin(), xi.end());
+    }
+    return make_nurbs_geometry(npatch, meta.data(), knots.data(), cw.data(), out);
+}
+
 int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
                      int level, bem_space* out) {
     if (!g || !out) return fail(BEM_EINVAL, "NULL argument");
@@ -786,6 +1150,7 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
     bem_space_s* sp = new (std::nothrow) bem_space_s;
     if (!sp) return fail(BEM_ENOMEM, "host allocation failed");
     sp->S = S;
+    sp->tab = g->tab;
     if (!make_basis_tab(S, sp->bt)) {
         delete sp;
         return fail(BEM_EUNSUPPORTED, "element basis classes do not repeat for this knot vector");
@@ -806,6 +1171,7 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
             hipStream_t stream) {
     if (!s || !data_params || !b_dev) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
+    if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
     if (data_kind != BEM_DATA_POINT_SOURCE && data_kind != BEM_DATA_PLANE_WAVE)
         return fail(BEM_EINVAL, "unknown data kind");
@@ -821,6 +1187,7 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
 int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t stream) {
     if (!s || !npts) return fail(BEM_EINVAL, "NULL argument");
     *npts = s->S.nelem * 64;
+    if (xyz_dev && need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (xyz_dev) HIP_CHECK(launch_quadpoints(s->S, gauss8(), xyz_dev, stream));
     return BEM_OK;
 }
@@ -828,6 +1195,7 @@ int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t 
 int bem_rhs_from_samples(bem_space s, const void* g_dev, int64_t ldg, int nrhs, void* b_dev, int64_t ldb,
                          hipStream_t stream) {
     if (!s || !g_dev || !b_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
     if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
     if (ldg < s->S.nelem * 64) return fail(BEM_EINVAL, "ldg must be >= the number of quadrature points");
@@ -845,6 +1213,7 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
     if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
     if (npts == 0) return BEM_OK;
     if (ldr < s->S.ndof || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
+    if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
     const Gauss8 g8 = gauss8();
     const size_t sc = s->S.ker.pde == PDE_HELMHOLTZ ? 16 : 8;
@@ -962,6 +1331,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     if (!A || !op_ws || !tmp_ws) return fail(BEM_EINVAL, "NULL argument");
     if (op_bytes < A->info.op_bytes || tmp_bytes < A->info.tmp_bytes)
         return fail(BEM_ENOMEM, "workspace smaller than bem_assemble_plan reported");
+    if (need_device_geometry(A->sp->S) != BEM_OK) return BEM_EDEVICE;
     const Plan& p = A->plan;
     // align the workspaces' bases to 256 bytes
     char* ob = (char*)(((uintptr_t)op_ws + 255) / 256 * 256);
@@ -971,7 +1341,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     BatchDev bd{};
     op_layout(*A, ob, &d, &bd);
     tmp_layout(*A, tb, &as);
-    if (A->far_eval) as.xc = const_cast<double*>(d.xc);  // the cluster points stay with the operator
+    as.xc = const_cast<double*>(d.xc);  // the cluster points stay with the operator
     d.S = p.S;
     d.bt = A->sp->bt;
     d.q = p.P.q;
@@ -1000,6 +1370,8 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
         return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
     };
     HIP_CHECK(up(d.lev_off, p.lev_off.data(), p.lev_off.size() * 8));
+    HIP_CHECK(up(d.ball, p.ball.data(), p.ball.size() * 8));
+    HIP_CHECK(hipMemsetAsync(d.up_count, 0, sizeof(int) * p.S.geom.npatch, stream));
     HIP_CHECK(up(d.rowptr, p.rowptr.data(), p.rowptr.size() * 8));
     HIP_CHECK(up(d.col, p.col.data(), p.col.size() * 4));
     HIP_CHECK(up(d.grp_rowptr, p.grp_rowptr.data(), p.grp_rowptr.size() * 8));
@@ -1300,10 +1672,11 @@ int bem_solve_plan(bem_operator A, int nrhs, const bem_solve_params* p, size_t* 
     if (!A || !p || !bytes) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart)
         return fail(BEM_EINVAL, "nrhs must be >= 1 and restart in [1, 64]");
-    *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, nullptr);
+    const int hist = refine_hist(p);
+    *bytes = solve_layout(A->info.ndof, p->restart, A->scal, nullptr, nullptr, hist);
     if (nrhs > 1 && A->batch_rhs > 1)
         *bytes = std::max(*bytes, bsolve_layout(A->info.ndof, p->restart, std::min(nrhs, A->batch_rhs), A->scal,
-                                                nullptr, nullptr));
+                                                nullptr, nullptr, hist));
     return BEM_OK;
 }
 
@@ -1313,8 +1686,9 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     if (nrhs < 1 || p->restart < 1 || p->restart > kMaxRestart || p->maxit < 1 || !(p->tol > 0.0))
         return fail(BEM_EINVAL, "bad solver parameters (restart must lie in [1, 64])");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (p->reserved[i] != 0) return fail(BEM_EINVAL, "reserved fields must be zero");
+    if (p->inner_maxit < 0) return fail(BEM_EINVAL, "inner_maxit must be >= 0");
     if (p->precond != BEM_PRECOND_NONE && p->precond != BEM_PRECOND_BLOCK)
         return fail(BEM_EINVAL, "precond must be BEM_PRECOND_NONE or BEM_PRECOND_BLOCK");
     if (p->precond == BEM_PRECOND_BLOCK && !A->prec_built) return fail(BEM_EINVAL, "preconditioner not built");
@@ -1325,13 +1699,14 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
     if (p->max_outer < 0 || p->inner_tol < 0.0) return fail(BEM_EINVAL, "max_outer and inner_tol must be >= 0");
     if (!A->pinned) HIP_CHECK(hipHostMalloc((void**)&A->pinned, sizeof(double) * (kMaxRestart + 2 + kSolveBlocks)));
     char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+    const int hist = refine_hist(p);
     if (nrhs > 1 && A->batch_rhs > 1) {
         // many right-hand sides in lockstep, up to batch_rhs per pass
         const int Rb = std::min(nrhs, A->batch_rhs);
-        if (ws_bytes < bsolve_layout(N, p->restart, Rb, A->scal, nullptr, nullptr))
+        if (ws_bytes < bsolve_layout(N, p->restart, Rb, A->scal, nullptr, nullptr, hist))
             return fail(BEM_ENOMEM, "solver workspace too small");
         BSolveWs W;
-        bsolve_layout(N, p->restart, Rb, A->scal, base, &W);
+        bsolve_layout(N, p->restart, Rb, A->scal, base, &W, hist);
         bool all = true;
         for (int r0 = 0; r0 < nrhs; r0 += Rb) {
             const int R = std::min(Rb, nrhs - r0);
@@ -1348,10 +1723,10 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
         if (!all) return fail(BEM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
         return BEM_OK;
     }
-    const size_t need = solve_layout(N, p->restart, A->scal, nullptr, nullptr);
+    const size_t need = solve_layout(N, p->restart, A->scal, nullptr, nullptr, hist);
     if (ws_bytes < need) return fail(BEM_ENOMEM, "solver workspace too small");
     SolveWs W;
-    solve_layout(N, p->restart, A->scal, base, &W);
+    solve_layout(N, p->restart, A->scal, base, &W, hist);
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
         const void* b = (const char*)b_dev + (size_t)r * ldb * A->scal;
@@ -1676,6 +2051,109 @@ int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t s
                                 rows + ((int64_t)ra * p.krs[owner] + slot * q2 + cb) * sc, sc);
                 }
         }
+    }
+    return BEM_OK;
+}
+
+int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int nsub, const char* path) {
+    if (!s || !path || (nrhs > 0 && !rho_host)) return fail(BEM_EINVAL, "NULL argument");
+    if (nrhs < 0 || nrhs > 64) return fail(BEM_EINVAL, "nrhs must lie in [0, 64]");
+    if (nsub < 1 || nsub > 64) return fail(BEM_EINVAL, "nsub must lie in [1, 64]");
+    const SpaceDesc& S = s->S;
+    if (nrhs > 0 && ldr < S.ndof) return fail(BEM_EINVAL, "ldr must be >= N");
+    const bool cplx = S.ker.pde == PDE_HELMHOLTZ;
+    const int np1 = nsub + 1;
+    const int64_t npe = (int64_t)np1 * np1;
+    const int64_t npts = S.nelem * npe, ncell = S.nelem * nsub * nsub;
+    if (npts > ((int64_t)1 << 31)) return fail(BEM_EINVAL, "too many output points");
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return fail(BEM_EINVAL, std::string("cannot create ") + path);
+    std::vector<double> kap((size_t)npts);
+    std::vector<double> val((size_t)npts * (cplx ? 2 : 1) * (size_t)std::max(nrhs, 1));
+    std::fprintf(fp, "# vtk DataFile Version 3.0\nboundary density\nASCII\nDATASET UNSTRUCTURED_GRID\n");
+    std::fprintf(fp, "POINTS %lld double\n", (long long)npts);
+    const double fd = 1e-6;  // parameter step of the central differences of the surface element
+    int64_t k = 0;
+    for (int64_t e = 0; e < S.nelem; ++e) {
+        const int i2 = (int)(e % S.nel), i1 = (int)((e / S.nel) % S.nel), f = (int)(e / ((int64_t)S.nel * S.nel));
+        const int ca = basis_class(s->bt, i1), cb = basis_class(s->bt, i2);
+        for (int a = 0; a <= nsub; ++a)
+            for (int b = 0; b <= nsub; ++b, ++k) {
+                const double u1 = (double)a / nsub, u2 = (double)b / nsub;
+                const double ps = (i1 + u1) * S.h, pt = (i2 + u2) * S.h;
+                double x[3], xp[3], xm[3], yp[3], ym[3];
+                patch_point(S.geom, f, ps, pt, x);
+                patch_point(S.geom, f, ps + fd, pt, xp);
+                patch_point(S.geom, f, ps - fd, pt, xm);
+                patch_point(S.geom, f, ps, pt + fd, yp);
+                patch_point(S.geom, f, ps, pt - fd, ym);
+                double ds[3], dt[3];
+                for (int c = 0; c < 3; ++c) {
+                    ds[c] = (xp[c] - xm[c]) / (2 * fd);
+                    dt[c] = (yp[c] - ym[c]) / (2 * fd);
+                }
+                const double nx = ds[1] * dt[2] - ds[2] * dt[1], ny = ds[2] * dt[0] - ds[0] * dt[2],
+                             nz = ds[0] * dt[1] - ds[1] * dt[0];
+                kap[k] = std::sqrt(nx * nx + ny * ny + nz * nz);
+                std::fprintf(fp, "%.17g %.17g %.17g\n", x[0], x[1], x[2]);
+                for (int r = 0; r < nrhs; ++r) {
+                    double re = 0.0, im = 0.0;
+                    for (int l1 = 0; l1 <= S.d; ++l1)
+                        for (int l2 = 0; l2 <= S.d; ++l2) {
+                            const double phi = basis_eval(s->bt, ca, l1, u1) * basis_eval(s->bt, cb, l2, u2);
+                            const int64_t g = dof_id(S, f, i1 * S.r + l1, i2 * S.r + l2) + (int64_t)r * ldr;
+                            if (cplx) {
+                                re += phi * ((const double*)rho_host)[2 * g];
+                                im += phi * ((const double*)rho_host)[2 * g + 1];
+                            } else {
+                                re += phi * ((const double*)rho_host)[g];
+                            }
+                        }
+                    // 2-form lifting: the density on the surface is rho_hat / kappa
+                    const size_t o = ((size_t)r * npts + k) * (cplx ? 2 : 1);
+                    val[o] = re / kap[k];
+                    if (cplx) val[o + 1] = im / kap[k];
+                }
+            }
+    }
+    std::fprintf(fp, "CELLS %lld %lld\n", (long long)ncell, (long long)ncell * 5);
+    for (int64_t e = 0; e < S.nelem; ++e)
+        for (int a = 0; a < nsub; ++a)
+            for (int b = 0; b < nsub; ++b) {
+                const int64_t p0 = e * npe + (int64_t)a * np1 + b;
+                std::fprintf(fp, "4 %lld %lld %lld %lld\n", (long long)p0, (long long)(p0 + np1),
+                             (long long)(p0 + np1 + 1), (long long)(p0 + 1));
+            }
+    std::fprintf(fp, "CELL_TYPES %lld\n", (long long)ncell);
+    for (int64_t c = 0; c < ncell; ++c) std::fprintf(fp, "9\n");
+    std::fprintf(fp, "POINT_DATA %lld\nSCALARS kappa double 1\nLOOKUP_TABLE default\n", (long long)npts);
+    for (int64_t p = 0; p < npts; ++p) std::fprintf(fp, "%.17g\n", kap[p]);
+    for (int r = 0; r < nrhs; ++r)
+        for (int part = 0; part < (cplx ? 2 : 1); ++part) {
+            std::fprintf(fp, "SCALARS rho%s_%d double 1\nLOOKUP_TABLE default\n", cplx ? (part ? "_im" : "_re") : "", r);
+            for (int64_t p = 0; p < npts; ++p)
+                std::fprintf(fp, "%.17g\n", val[((size_t)r * npts + p) * (cplx ? 2 : 1) + part]);
+        }
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? BEM_OK : fail(BEM_EINVAL, std::string("write failed: ") + path);
+}
+
+int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr,
+                          int nrhs, void* u_dev, int64_t ldu, double eta, hipStream_t stream) {
+    if (!A || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");
+    if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
+    if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
+    if (!(eta >= 0.0) || !std::isfinite(eta)) return fail(BEM_EINVAL, "eta must be finite and >= 0");
+    if (npts == 0) return BEM_OK;
+    const int64_t N = A->info.ndof;
+    if (ldr < N || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
+    if (npts > ((int64_t)1 << 33)) return fail(BEM_EINVAL, "too many points");
+    const Gauss8 g8 = gauss8();
+    for (int r = 0; r < nrhs; ++r) {
+        const char* rho = (const char*)rho_dev + (size_t)r * ldr * A->scal;
+        HIP_CHECK(launch_moments(A->dev, rho, stream));
+        HIP_CHECK(launch_potential_tree(A->dev, g8, eta, pts_dev, npts, rho, (char*)u_dev + (size_t)r * ldu * A->scal,
+                                        stream));
     }
     return BEM_OK;
 }

@@ -264,6 +264,29 @@ __global__ __launch_bounds__(kT) void kbs_xupdate(int64_t n, int R, int k, const
     }
 }
 
+// U[g][r] = u[g][r] / ||u_r||, D[g][r] = d[g][r] / ||u_r|| (zero if ||u_r|| = 0)
+template <class T>
+__global__ __launch_bounds__(kT) void kbs_scale2(int64_t n, int R, const double* __restrict__ npart,
+                                                 const T* __restrict__ u, const T* __restrict__ d, T* __restrict__ U,
+                                                 T* __restrict__ D) {
+    __shared__ double inv[kC];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.y * kC + lane;
+    if (wv == 0) {
+        const double nrm = r < R ? norm_of(npart, kBSolveSlices, R, r) : 0.0;
+        inv[lane] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    }
+    __syncthreads();
+    if (r >= R) return;
+    int64_t t0, t1;
+    bslice(n, t0, t1);
+    const double s = inv[lane];
+    for (int64_t t = t0 + wv; t < t1; t += 4) {
+        U[t * R + r] = u[t * R + r] * s;
+        D[t * R + r] = d[t * R + r] * s;
+    }
+}
+
 // y += x, and columns whose flag is set are cleared in y (mask != nullptr)
 template <class T>
 __global__ __launch_bounds__(kT) void kbs_axpy(int64_t n, int R, const T* __restrict__ x, T* y) {
@@ -367,6 +390,30 @@ hipError_t bsolve_backsolve_update(int cplx, int64_t n, int R, int k, const void
         hipLaunchKernelGGL(kbs_xupdate<double>, g, dim3(kT), 0, s, n, R, k, (const double*)V, (const double*)st.y,
                            (double*)x);
     }
+    return hipGetLastError();
+}
+
+hipError_t bsolve_xupdate(int cplx, int64_t n, int R, int k, const void* V, const void* y, void* x, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    if (k > kMaxRestart) return hipErrorInvalidValue;
+    const dim3 g(kBSolveSlices, nb(R, kC));
+    if (cplx)
+        hipLaunchKernelGGL(kbs_xupdate<cdbl>, g, dim3(kT), 0, s, n, R, k, (const cdbl*)V, (const cdbl*)y, (cdbl*)x);
+    else
+        hipLaunchKernelGGL(kbs_xupdate<double>, g, dim3(kT), 0, s, n, R, k, (const double*)V, (const double*)y,
+                           (double*)x);
+    return hipGetLastError();
+}
+
+hipError_t bsolve_scale2(int cplx, int64_t n, int R, const double* npart, const void* u, const void* d, void* U,
+                         void* D, hipStream_t s) {
+    const dim3 g(kBSolveSlices, nb(R, kC));
+    if (cplx)
+        hipLaunchKernelGGL(kbs_scale2<cdbl>, g, dim3(kT), 0, s, n, R, npart, (const cdbl*)u, (const cdbl*)d, (cdbl*)U,
+                           (cdbl*)D);
+    else
+        hipLaunchKernelGGL(kbs_scale2<double>, g, dim3(kT), 0, s, n, R, npart, (const double*)u, (const double*)d,
+                           (double*)U, (double*)D);
     return hipGetLastError();
 }
 

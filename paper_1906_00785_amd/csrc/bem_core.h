@@ -47,13 +47,93 @@ __host__ __device__ inline double abs2(double a) { return a * a; }
 __host__ __device__ inline double abs2(cdbl a) { return a.re * a.re + a.im * a.im; }
 
 // ------------------------------------------------------------------ geometry
-enum GeomKind : int { GEOM_SPHERE6 = 0, GEOM_ELLIPSOID6 = 1, GEOM_TORUS16 = 2, GEOM_FLAT1 = 3 };
+enum GeomKind : int { GEOM_SPHERE6 = 0, GEOM_ELLIPSOID6 = 1, GEOM_TORUS16 = 2, GEOM_FLAT1 = 3, GEOM_NURBS = 4 };
+
+// Patches given by NURBS maps (App. C) live in one table of doubles, a copy in host memory
+// for the planner and one in device memory for the kernels:
+//   [1 + 6 f .. 1 + 6 f + 5]  patch f: p1, p2, k1, k2 (degrees, basis counts), offset of its
+//                             knots (Xi_1 then Xi_2, clamped), offset of its control points
+//                             (x, y, z, w per point, j1 outer, k1 x k2 points)
+constexpr int kNurbsMaxDeg = 8;
 
 struct GeomDesc {
     int kind;
     int npatch;
     double a, b, c;  // ellipsoid semi-axes; torus R = a, r = b; flat side a
+    const double* tab_host;  // NURBS table (GEOM_NURBS only)
+    const double* tab_dev;
 };
+
+// Knot span of x in a clamped knot vector xi with k basis functions of degree p: the
+// largest mu in [p, k-1] with xi[mu] <= x (x = 1 falls in the last span).
+__host__ __device__ inline int nurbs_span(const double* xi, int p, int k, double x) {
+    if (x >= xi[k]) return k - 1;
+    int lo = p, hi = k;  // xi[lo] <= x < xi[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (x < xi[mid])
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return lo;
+}
+
+// The p + 1 B-splines of degree p that do not vanish in span mu, N[r] = b_{mu-p+r}(x),
+// by the triangular scheme (each degree from the previous one over the span's knot
+// differences; no division by a zero-length interval occurs inside a non-empty span).
+__host__ __device__ inline void nurbs_funs(const double* xi, int p, int mu, double x, double* N) {
+    double left[kNurbsMaxDeg + 1], right[kNurbsMaxDeg + 1];
+    N[0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = x - xi[mu + 1 - j];
+        right[j] = xi[mu + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            const double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
+// gamma_f(s, t) of a NURBS patch: the rational combination of the (p1+1)(p2+1) control
+// points whose basis functions do not vanish at (s, t).  Kept out of line so that the
+// analytic maps' callers do not carry its registers.
+__host__ __device__ __attribute__((noinline)) inline void nurbs_point(const double* tab, int f, double s, double t,
+                                                                     double* x) {
+    const double* h = tab + 1 + 6 * f;
+    const int p1 = (int)h[0], p2 = (int)h[1], k1 = (int)h[2], k2 = (int)h[3];
+    const double* xi1 = tab + (int64_t)h[4];
+    const double* xi2 = xi1 + k1 + p1 + 1;
+    const double* cw = tab + (int64_t)h[5];
+    const int m1 = nurbs_span(xi1, p1, k1, s), m2 = nurbs_span(xi2, p2, k2, t);
+    double N1[kNurbsMaxDeg + 1], N2[kNurbsMaxDeg + 1];
+    nurbs_funs(xi1, p1, m1, s, N1);
+    nurbs_funs(xi2, p2, m2, t, N2);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, aw = 0.0;
+    for (int i = 0; i <= p1; ++i) {
+        const double* row = cw + 4 * ((int64_t)(m1 - p1 + i) * k2 + (m2 - p2));
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, bw = 0.0;
+        for (int j = 0; j <= p2; ++j) {
+            const double* c = row + 4 * j;
+            const double v = N2[j] * c[3];
+            b0 += v * c[0];
+            b1 += v * c[1];
+            b2 += v * c[2];
+            bw += v;
+        }
+        a0 += N1[i] * b0;
+        a1 += N1[i] * b1;
+        a2 += N1[i] * b2;
+        aw += N1[i] * bw;
+    }
+    const double inv = 1.0 / aw;
+    x[0] = a0 * inv;
+    x[1] = a1 * inv;
+    x[2] = a2 * inv;
+}
 
 // Cube face f of the cube-sphere: which coordinate receives u = 2s-1, which receives
 // v = 2t-1, which is the constant +-1.  Faces: +z, -z, +x, -x, +y, -y, each with the
@@ -99,6 +179,12 @@ __host__ __device__ inline void patch_point(const GeomDesc& g, int f, double s, 
         x[0] = rr * cu;
         x[1] = rr * su;
         x[2] = g.b * sv;
+    } else if (g.kind == GEOM_NURBS) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        nurbs_point(g.tab_dev, f, s, t, x);
+#else
+        nurbs_point(g.tab_host, f, s, t, x);
+#endif
     } else {
         x[0] = g.a * s;
         x[1] = g.a * t;

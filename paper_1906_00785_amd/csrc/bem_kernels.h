@@ -73,6 +73,7 @@ struct OpDev {
     int otf;
     int otf_wide;  // chunks of at least 512 columns (8 real columns per lane and pass)
     const double* xc;
+    const double* ball;  // [ncl][4]: centre and radius of every cluster (admissibility)
     // transforms
     const double* V1;  // [nleaf1][q][nloc]
     const double* E;   // [2][q][q]
@@ -82,6 +83,7 @@ struct OpDev {
     // upward pass: subtrees rooted at level up_root are summed by one block each; the
     // levels above follow per patch
     int up_root, up_depth;
+    int* up_count;  // per patch: subtree blocks done in the current apply (0 between applies)
     // downward pass + backward transform: square tiles of leaves per block
     int tile;
 };
@@ -161,6 +163,11 @@ hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, 
 hipError_t launch_quadpoints(const SpaceDesc& S, const Gauss8& g8, double* xyz, hipStream_t st);
 hipError_t launch_rhs_samples(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const void* gv, void* b,
                               hipStream_t st);
+// potential through the cluster tree: moments of rho (launch_moments first, in op.mom),
+// admissible clusters (point-ball rule with eta) by their Chebyshev points, near leaves by
+// 8x8 Gauss
+hipError_t launch_potential_tree(const OpDev& op, const Gauss8& g8, double eta, const double* pts, int64_t npts,
+                                 const void* rho, void* u, hipStream_t st);
 hipError_t launch_potential(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const double* pts,
                             int64_t npts, const void* rho, void* u, hipStream_t st);
 

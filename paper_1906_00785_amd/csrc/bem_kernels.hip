@@ -621,8 +621,34 @@ __device__ inline void near_up_body(const OpDev& op, int64_t blk_, const T* __re
         near_group_rows<T, kGroupRowsDev>(col, val, x, y, op.grp_rows + rb, R, C, lane);
 }
 
+// Stage 0 in one launch: the subtree blocks, then the levels above up_root by the last
+// subtree block of each patch to finish.  Each subtree block releases its moments at device
+// scope and counts itself in up_count[patch]; the block that brings the count to the
+// number of subtrees acquires the others' moments, sums the upper levels and resets the
+// count for the next apply (so no clearing is needed between applies or graph replays).
+// No block waits for another.
 template <class T, int Q>
 __global__ __launch_bounds__(256) void k_near_up(OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    const int nup = op.S.geom.npatch << (2 * op.up_root);
+    if (op.up_count && op.up_root > 0 && (int)blockIdx.x < nup) {
+        up_subtree<T, Q>(op, blockIdx.x, x);
+        __shared__ int last;
+        const int per = 1 << (2 * op.up_root), f = (int)blockIdx.x / per;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const int before = atomicAdd(op.up_count + f, 1);
+            __threadfence();
+            last = before == per - 1;
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            up_top_body<T, Q>(op, f);
+            if (threadIdx.x == 0) op.up_count[f] = 0;
+        }
+        return;
+    }
     near_up_body<T, Q>(op, blockIdx.x, x, y);
 }
 
@@ -1224,6 +1250,74 @@ __global__ __launch_bounds__(256) void k_potential(SpaceDesc S, BasisTab bt, Gau
     if (threadIdx.x == 0) u[p] = red[0] + red[1] + red[2] + red[3];
 }
 
+// u(x_p) through the cluster tree, one wave per point (four per block).  The wave walks
+// every patch's quadtree from its root with a stack in LDS (every lane writes the same
+// entries, so each lane reads back its own writes): a cluster whose ball is admissible for
+// the point (dist = |x - c| - r > 0, 2 r <= eta dist, ties within 1e-12 dist inadmissible)
+// adds sum_a k(x, xi_a) m_a over its q^2 Chebyshev points (lane a); an inadmissible leaf adds
+// the 8x8 Gauss sums of its elements (lane = Gauss point); other clusters push their four
+// children.  The walk is the same for all lanes, so the wave never diverges on it.
+template <class T>
+__global__ __launch_bounds__(256) void k_potential_tree(OpDev op, Gauss8 g8, double eta, const double* __restrict__ pts,
+                                                        int64_t npts, const T* __restrict__ rho, T* __restrict__ u) {
+    __shared__ int stk[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (p >= npts) return;  // whole waves only; no block barrier follows
+    const SpaceDesc& S = op.S;
+    const double px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+    const T* __restrict__ mom = (const T*)op.mom;
+    const int q2 = op.q2, d = S.d, r = S.r;
+    const int m = 1 << (S.L - op.leaf);  // elements per leaf per direction
+    int* st = stk[wv];
+    T acc = zero<T>();
+    for (int f = 0; f < S.geom.npatch; ++f) {
+        int top = 0;
+        st[top++] = 0;  // (level 0, i 0, j 0), packed as level << 24 | i << 12 | j
+        while (top > 0) {
+            const int code = st[--top];
+            const int l = code >> 24, ci = (code >> 12) & 4095, cj = code & 4095;
+            const int n = 1 << l;
+            const int64_t c = op.lev_off[l] + ((int64_t)f * n + ci) * n + cj;
+            const double* bl = op.ball + 4 * c;
+            const double dx = px - bl[0], dy = py - bl[1], dz = pz - bl[2];
+            const double dist = sqrt(dx * dx + dy * dy + dz * dz) - bl[3];
+            const double lhs = 2.0 * bl[3], rhs = eta * dist;
+            const bool adm = dist > 0.0 && !(fabs(lhs - rhs) <= 1e-12 * dist) && lhs <= rhs;
+            if (adm) {
+                if (lane < q2) {
+                    const double* y = op.xc + (c * q2 + lane) * 3;
+                    const double ex = px - y[0], ey = py - y[1], ez = pz - y[2];
+                    acc += kernel_val(S.ker, ex * ex + ey * ey + ez * ez, T()) * mom[c * q2 + lane];
+                }
+            } else if (l == op.leaf) {
+                const double u1 = g8.x[lane >> 3], u2 = g8.x[lane & 7];
+                const double wq = g8.w[lane >> 3] * g8.w[lane & 7] * S.h * S.h;
+                for (int e1 = 0; e1 < m; ++e1)
+                    for (int e2 = 0; e2 < m; ++e2) {
+                        const int i1 = ci * m + e1, i2 = cj * m + e2;
+                        double y[3];
+                        patch_point(S.geom, f, (i1 + u1) * S.h, (i2 + u2) * S.h, y);
+                        const int ca = basis_class(op.bt, i1), cb = basis_class(op.bt, i2);
+                        T rh = zero<T>();
+                        for (int l1 = 0; l1 <= d; ++l1) {
+                            const double ba = basis_eval(op.bt, ca, l1, u1);
+                            for (int l2 = 0; l2 <= d; ++l2)
+                                rh += (ba * basis_eval(op.bt, cb, l2, u2)) * rho[dof_id(S, f, i1 * r + l1, i2 * r + l2)];
+                        }
+                        const double ex = px - y[0], ey = py - y[1], ez = pz - y[2];
+                        acc += kernel_val(S.ker, ex * ex + ey * ey + ez * ez, T()) * rh * wq;
+                    }
+            } else {
+                for (int k = 3; k >= 0; --k)
+                    st[top++] = ((l + 1) << 24) | ((2 * ci + (k >> 1)) << 12) | (2 * cj + (k & 1));
+            }
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) u[p] = acc;
+}
+
 // ------------------------------------------------------------------ grouped launches
 // apply of block b: the largest a < napply with prefix[a] <= b (empty applies skipped)
 __device__ inline int64_t group_find(const int64_t* pre, int64_t napply, int64_t b) {
@@ -1385,7 +1479,7 @@ static hipError_t apply_stage_tq(const OpDev& op, int stage, const T* x, T* y, b
             const unsigned nup = (unsigned)op.S.geom.npatch << (2 * op.up_root);
             const unsigned nb = nup + (with_near ? nblk(op.ngroups, 4) : 0u);
             hipLaunchKernelGGL((k_near_up<T, Q>), dim3(nb), dim3(256), 0, st, op, x, y);
-            if (op.up_root > 0)
+            if (op.up_root > 0 && !op.up_count)
                 hipLaunchKernelGGL((k_up_top<T, Q>), dim3((unsigned)op.S.geom.npatch), dim3(256), 0, st, op);
             break;
         }
@@ -1501,6 +1595,19 @@ hipError_t launch_rhs_samples(const SpaceDesc& S, const BasisTab& bt, const Gaus
         hipLaunchKernelGGL(k_rhs_samples<cdbl>, g, blk, 0, st, S, bt, g8, (const cdbl*)gv, (cdbl*)b);
     else
         hipLaunchKernelGGL(k_rhs_samples<double>, g, blk, 0, st, S, bt, g8, (const double*)gv, (double*)b);
+    return hipGetLastError();
+}
+
+hipError_t launch_potential_tree(const OpDev& op, const Gauss8& g8, double eta, const double* pts, int64_t npts,
+                                 const void* rho, void* u, hipStream_t st) {
+    if (npts == 0) return hipSuccess;
+    const dim3 grid((unsigned)((npts + 3) / 4));
+    if (op.cplx)
+        hipLaunchKernelGGL(k_potential_tree<cdbl>, grid, dim3(256), 0, st, op, g8, eta, pts, npts, (const cdbl*)rho,
+                           (cdbl*)u);
+    else
+        hipLaunchKernelGGL(k_potential_tree<double>, grid, dim3(256), 0, st, op, g8, eta, pts, npts,
+                           (const double*)rho, (double*)u);
     return hipGetLastError();
 }
 

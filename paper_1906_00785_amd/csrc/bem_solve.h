@@ -43,6 +43,9 @@ hipError_t solve_start(int cplx, int64_t n, const double* npart, const void* w, 
 hipError_t solve_axpy(int cplx, int64_t n, double a, const void* x, void* y, hipStream_t s);
 hipError_t solve_backsolve_update(int cplx, int64_t n, int k, const void* V, void* x, const GmresState& st,
                                   hipStream_t s);
+// x += sign * sum_{i<k} y_i V_i, y device (k <= 64)
+hipError_t solve_combine(int cplx, int64_t n, int k, const void* V, const void* y, double sign, void* x,
+                         hipStream_t s);
 
 // ---- many right-hand sides in lockstep (bem_bsolve.hip): slab vectors v[g][r]
 constexpr int kBSolveSlices = 64;  // row slices of every slab kernel
@@ -74,6 +77,12 @@ hipError_t bsolve_givens_scale(int cplx, int64_t n, int R, int j, const double* 
 hipError_t bsolve_backsolve_update(int cplx, int64_t n, int R, int k, const void* V, void* x, const BGmresState& st,
                                    hipStream_t s);
 hipError_t bsolve_axpy(int cplx, int64_t n, int R, const void* x, void* y, hipStream_t s);
+// x[g][r] += sum_{j<k} y[j][r] V_j[g][r]  (y device [k][R], k <= 64)
+hipError_t bsolve_xupdate(int cplx, int64_t n, int R, int k, const void* V, const void* y, void* x, hipStream_t s);
+// U = u / ||u_r|| and D = d / ||u_r|| per right-hand side r (norms from the partials of u;
+// a zero column stays zero)
+hipError_t bsolve_scale2(int cplx, int64_t n, int R, const double* npart, const void* u, const void* d, void* U,
+                         void* D, hipStream_t s);
 hipError_t bsolve_mask(int cplx, int64_t n, int R, const int* flag, void* y, hipStream_t s);
 hipError_t bsolve_zero(int cplx, int64_t n_scalars, void* y, hipStream_t s);
 

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_s_scale(int64_t n, const double* _
     const double nrm = reduce_npart(npart, gridDim.x);
     int64_t t0, t1;
     slice(n, t0, t1);
-    const double inv = 1.0 / nrm;
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;  // a zero vector stays zero
     for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) vnext[t] = w[t] * inv;
 }
 
@@ -274,6 +274,22 @@ __global__ __launch_bounds__(kThreads) void k_s_xupdate(int64_t n, int k, const 
                                                         const T* __restrict__ y, T* x) {
     __shared__ T ys[64];
     for (int i = threadIdx.x; i < k; i += kThreads) ys[i] = y[i];
+    __syncthreads();
+    int64_t t0, t1;
+    slice(n, t0, t1);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kThreads) {
+        T s = zero<T>();
+        for (int i = 0; i < k; ++i) s += ys[i] * V[(int64_t)i * n + t];
+        x[t] += s;
+    }
+}
+
+// x += sign * sum_{i<k} y_i v_i  (y on the device, k <= 64)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_s_combine(int64_t n, int k, const T* __restrict__ V,
+                                                        const T* __restrict__ y, double sign, T* x) {
+    __shared__ T ys[64];
+    for (int i = threadIdx.x; i < k; i += kThreads) ys[i] = y[i] * sign;
     __syncthreads();
     int64_t t0, t1;
     slice(n, t0, t1);
@@ -364,6 +380,19 @@ hipError_t solve_axpy(int cplx, int64_t n, double a, const void* x, void* y, hip
         hipLaunchKernelGGL(k_s_axpy<cdbl>, dim3(nb), dim3(kThreads), 0, s, n, a, (const cdbl*)x, (cdbl*)y);
     else
         hipLaunchKernelGGL(k_s_axpy<double>, dim3(nb), dim3(kThreads), 0, s, n, a, (const double*)x, (double*)y);
+    return hipGetLastError();
+}
+
+hipError_t solve_combine(int cplx, int64_t n, int k, const void* V, const void* y, double sign, void* x,
+                         hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    if (k > 64) return hipErrorInvalidValue;
+    if (cplx)
+        hipLaunchKernelGGL(k_s_combine<cdbl>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, k, (const cdbl*)V,
+                           (const cdbl*)y, sign, (cdbl*)x);
+    else
+        hipLaunchKernelGGL(k_s_combine<double>, dim3(kSolveBlocks), dim3(kThreads), 0, s, n, k, (const double*)V,
+                           (const double*)y, sign, (double*)x);
     return hipGetLastError();
 }
 

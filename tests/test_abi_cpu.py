@@ -161,3 +161,158 @@ def test_plan_equals_oracle_wavenumber_bound(B, orc, kappa, kadm):
         assert min(lev_of(t) for t, _ in pairs) >= min(lev_of(t) for t, _ in _plan_lists(B, A0)[0])
     else:
         assert A.info.nfar == A0.info.nfar
+
+
+def test_autotune_cache_key_separates_instances():
+    """Two instances that differ only in a geometry parameter, the wavenumber, the knot
+    repetition or the far-field mode get different cache entries."""
+    from types import SimpleNamespace as NS
+
+    import paper_1906_00785_amd.autotune as AT
+
+    def sp(params=(1.0, 0.4), kappa=2.0, rep=1):
+        return NS(geom=NS(kind=2, params=params), level=3, degree=2, knot_repetition=rep, kernel=1, kappa=kappa)
+
+    base = AT.cache_key(sp(), 5, 1.6, 1, False, 0.0)
+    others = [AT.cache_key(sp(params=(1.0, 0.45)), 5, 1.6, 1, False, 0.0),
+              AT.cache_key(sp(kappa=2.5), 5, 1.6, 1, False, 0.0),
+              AT.cache_key(sp(kappa=2.0 + 0.1j), 5, 1.6, 1, False, 0.0),
+              AT.cache_key(sp(rep=2), 5, 1.6, 1, False, 0.0),
+              AT.cache_key(sp(), 5, 1.6, 1, True, 0.0),
+              AT.cache_key(sp(), 5, 1.6, 1, False, 6.0),
+              AT.cache_key(sp(), 5, 1.6, 8, False, 0.0)]
+    assert len(set(others + [base])) == len(others) + 1
+    assert AT.cache_key(sp(), 5, 1.6, 1, False, 0.0) == base
+
+
+# ---------------------------------------------------------------- NURBS geometries (host side)
+def test_nurbs_plan_equals_oracle(B, orc):
+    """The NURBS torus: the host plan (partition, near pattern) equals the oracle's."""
+    patches = W.nurbs_torus(1.0, 0.4)
+    g = B.Geometry.nurbs(patches)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=2)
+    A = B.Operator(s, q=4, eta=1.6, leaf_level=1, assemble=False)
+    pairs, rowptr, col = _plan_lists(B, A)
+    So = orc.Space(orc.NURBS, patches, orc.LAPLACE, 0.0, degree=1, level=2)
+    Ho = orc.H2(So, q=4, eta=1.6, leaf=1, assemble_near=False)
+    far, _ = Ho.lists()
+    assert np.array_equal(far, pairs) and A.info.nnear == Ho.nnear
+    # touching element pairs on the closed torus: every vertex has valence 4
+    ne = 16 * 4 * 4
+    assert A.info.ntouch == ne + 4 * ne + 4 * ne
+
+
+def test_nurbs_file_round_trip(B, tmp_path):
+    """A NURBS geometry saved and loaded again plans the same operator; malformed files
+    and tables are refused with EINVAL."""
+    C = B._bem
+    g = B.Geometry.nurbs(W.nurbs_torus(1.0, 0.3) + [])
+    path = str(tmp_path / "torus.bemnurbs")
+    g.save(path)
+    g2 = B.Geometry.load(path)
+    plans = []
+    for gg in (g, g2):
+        s = B.Space(gg, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=2)
+        plans.append(_plan_lists(B, B.Operator(s, q=4, eta=1.6, leaf_level=1, assemble=False)))
+    for a, b in zip(*plans):
+        assert np.array_equal(a, b)
+    bad = tmp_path / "bad.bemnurbs"
+    txt = open(path).read()
+    for mutate in (lambda t: t.replace("BEMNURBS 1", "BEMNURBS 2"), lambda t: t[: len(t) // 2]):
+        bad.write_text(mutate(txt))
+        with pytest.raises(C.BemError) as e:
+            B.Geometry.load(str(bad))
+        assert e.value.code == C.BEM_EINVAL
+    P = W.nurbs_torus(1.0, 0.3)[0]
+    for change in ({"knots": ([0.0, 0.0, 0.5, 1.0, 1.0, 1.0], P["knots"][1])},  # not clamped
+                   {"cw": np.concatenate([P["cw"][:, :, :3], -np.ones((3, 3, 1))], axis=2)}):  # weights
+        with pytest.raises(C.BemError) as e:
+            B.Geometry.nurbs([dict(P, **change)])
+        assert e.value.code == C.BEM_EINVAL
+    with pytest.raises(C.BemError) as e:
+        B.Geometry(B.BEM_GEOM_SPHERE6).save(path)
+    assert e.value.code == C.BEM_EINVAL
+
+
+def test_user_map_plan_equals_oracle(B, orc):
+    """A user map (the sphere's patch maps as a host callback): the library's interpolant
+    plans the same partition as the oracle's reading of the same map, and a callback that
+    returns non-finite points is refused."""
+    C = B._bem
+    g = B.Geometry.user(6, W.sphere6_map, degree=5, intervals=8)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=3)
+    A = B.Operator(s, q=4, eta=1.6, leaf_level=2, assemble=False)
+    pairs, _, _ = _plan_lists(B, A)
+    So = orc.Space(orc.NURBS, orc.user_map_patches(W.sphere6_map, 6, 5, 8), orc.LAPLACE, 0.0, degree=1, level=3)
+    Ho = orc.H2(So, q=4, eta=1.6, leaf=2, assemble_near=False)
+    far, _ = Ho.lists()
+    assert np.array_equal(far, pairs) and A.info.nnear == Ho.nnear
+    with pytest.raises(C.BemError) as e:
+        B.Geometry.user(1, lambda f, st: np.full((st.shape[0], 3), np.nan), degree=3, intervals=4)
+    assert e.value.code == C.BEM_EINVAL
+
+
+def _read_vtk(path):
+    """Minimal reader of the legacy ASCII unstructured grid the library writes."""
+    tok = open(path).read().split("\n")
+    i = tok.index("DATASET UNSTRUCTURED_GRID") + 1
+    n = int(tok[i].split()[1])
+    pts = np.array([[float(v) for v in tok[i + 1 + k].split()] for k in range(n)])
+    i += 1 + n
+    nc = int(tok[i].split()[1])
+    cells = np.array([[int(v) for v in tok[i + 1 + k].split()] for k in range(nc)])
+    i += 1 + nc
+    types = np.array([int(tok[i + 1 + k]) for k in range(nc)])
+    i += 1 + nc
+    data = {}
+    assert tok[i].startswith("POINT_DATA")
+    i += 1
+    while i < len(tok) and tok[i].startswith("SCALARS"):
+        name = tok[i].split()[1]
+        data[name] = np.array([float(tok[i + 2 + k]) for k in range(n)])
+        i += 2 + n
+    return pts, cells, types, data
+
+
+@pytest.mark.parametrize("geom,prm,pde,kappa", [(0, (), 0, 0.0), (2, (1.0, 0.4), 1, 2.0)])
+def test_vtk_output_matches_oracle_geometry_and_density(B, orc, tmp_path, geom, prm, pde, kappa):
+    """Points are gamma at the stated parameters, kappa the surface element, and the density
+    rho_hat / kappa with rho_hat = sum_g rho_g b_j1(s) b_j2(t), all against the oracle's maps,
+    surface elements and B-splines (App. C)."""
+    L, d, nsub = 1, 2, 3
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, pde, kappa, degree=d, level=L)
+    rho = W.random_vector(W.rng(9, 40), s.ndof, is_complex=bool(pde), ncols=2).T.copy()
+    path = str(tmp_path / "out.vtk")
+    s.write_vtk(path, torch_free(rho), nsub=nsub)
+    pts, cells, types, data = _read_vtk(path)
+    np1 = nsub + 1
+    nel = 1 << L
+    assert pts.shape == (s.ndof // (nel + d) ** 2 * nel * nel * np1 * np1, 3)
+    assert cells.shape[1] == 5 and np.all(cells[:, 0] == 4) and np.all(types == 9)
+    So = orc.Space(geom, list(prm), pde, kappa, degree=d, level=L)
+    nb = nel + d
+    k = 0
+    for e in range(So.nelem):
+        f, i1, i2 = e // (nel * nel), (e // nel) % nel, e % nel
+        st = np.array([[(i1 + a / nsub) / nel, (i2 + b / nsub) / nel] for a in range(np1) for b in range(np1)])
+        xyz, kap, _ = So.gamma(f, st)
+        np.testing.assert_allclose(pts[k:k + np1 * np1], xyz, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(data["kappa"][k:k + np1 * np1], kap, rtol=1e-8)
+        B1 = np.stack([orc.bspline(d, 1, L, j, st[:, 0]) for j in range(nb)], 1)
+        B2 = np.stack([orc.bspline(d, 1, L, j, st[:, 1]) for j in range(nb)], 1)
+        for r in range(2):
+            c = rho[r].reshape(-1, nb, nb)[f]
+            rh = np.einsum("pi,pj,ij->p", B1, B2, c) / kap
+            if pde:
+                np.testing.assert_allclose(data[f"rho_re_{r}"][k:k + np1 * np1], rh.real, rtol=1e-7, atol=1e-12)
+                np.testing.assert_allclose(data[f"rho_im_{r}"][k:k + np1 * np1], rh.imag, rtol=1e-7, atol=1e-12)
+            else:
+                np.testing.assert_allclose(data[f"rho_{r}"][k:k + np1 * np1], rh, rtol=1e-7, atol=1e-12)
+        k += np1 * np1
+
+
+def torch_free(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a))

@@ -208,35 +208,26 @@ def test_batched_gmres_edge_cases(B, orc):
 
 
 def test_c2_batched_solve_full_size(B, orc, c2):
-    """The many-RHS workload end to end: 128 plane waves in lockstep GMRES(30) to 1e-8, in
-    FP64 and with FP64 refinement around the FP32 far field; the BF16 far field with
-    refinement is run and its outcome reported (on this first-kind Helmholtz system the
-    BF16 coupling error times the condition number is close to 1, so refinement may stall;
-    its stats must then say so)."""
+    """The many-RHS workload end to end: 128 plane waves in lockstep GMRES(30), FP64 to a
+    relative residual of 1e-12 (the reference), and FP64 refinement around the FP32 and the
+    BF16 far field (flexible outer loop) to 1e-12: every right-hand side converges, and its
+    solution lies within 1e-8 (relative) of the FP64 one."""
     c, kappa, dirs, g, s, A, So, Ho = c2
     b = s.rhs(B.BEM_DATA_PLANE_WAVE, dirs)
-    x64, st64 = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"])
+    x64, st64 = A.solve(b, tol=1e-12, restart=c["restart"], maxit=20000)
     its64 = [t[0] for t in st64]
-    print(f"c2 full size: FP64 lockstep GMRES its {min(its64)}..{max(its64)}", flush=True)
-    assert all(t[1] and t[2] <= c["tol"] for t in st64)
-    A32 = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_low=1, batch_rhs=c["nrhs"])
-    x32, st32 = A32.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=True)
-    its32 = [t[0] for t in st32]
-    print(f"c2 full size: fp32-refined its {min(its32)}..{max(its32)} outer {max(t[3] for t in st32)}", flush=True)
-    assert all(t[1] and t[2] <= c["tol"] for t in st32)
-    for X in (x64, x32):
-        res = (b - A.apply(X)).norm(dim=1) / b.norm(dim=1)
-        assert float(res.max()) <= c["tol"]
-    # the two solutions give the same scattered field away from the surface
-    pts = W.exterior_points(W.rng(2, 60), 16, 2.0, 4.0)
-    u64 = s.potential(pts, x64).cpu().numpy()
-    u32 = s.potential(pts, x32).cpu().numpy()
-    du = float(np.max(np.abs(u32 - u64)) / np.max(np.abs(u64)))
-    print(f"c2 full size: potential difference FP64 vs fp32-refined {du:.2e}")
-    assert du <= 1e-6
-    xb, stb = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"], refine=True, max_outer=3)
-    res = ((b - A.apply(xb)).norm(dim=1) / b.norm(dim=1)).cpu().numpy()
-    print(f"c2 full size: bf16-refined (3 outer steps at most): converged {sum(t[1] for t in stb)}/{len(stb)}, "
-          f"residual {res.min():.2e}..{res.max():.2e}")
-    for t, rr in zip(stb, res):
-        assert t[1] == (rr <= c["tol"] * (1 + 1e-6)) and abs(t[2] - rr) <= 1e-3 * rr + 1e-15
+    print(f"c2 full size: FP64 lockstep GMRES to 1e-12 its {min(its64)}..{max(its64)}", flush=True)
+    assert all(t[1] and t[2] <= 1e-12 for t in st64)
+    res = (b - A.apply(x64)).norm(dim=1) / b.norm(dim=1)
+    assert float(res.max()) <= 1e-12 * (1 + 1e-6)
+    for low in (B.BEM_PREC_FP32, B.BEM_PREC_BF16):
+        Al = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["leaf"], far_low=low, batch_rhs=c["nrhs"])
+        xl, stl = Al.solve(b, tol=1e-12, restart=c["restart"], maxit=20000, refine=True, max_outer=40)
+        its = [t[0] for t in stl]
+        d = ((xl - x64).norm(dim=1) / x64.norm(dim=1)).cpu().numpy()
+        print(f"c2 full size: {'fp32' if low == 1 else 'bf16'}-refined its {min(its)}..{max(its)} outer "
+              f"{max(t[3] for t in stl)}, solution difference to FP64 max {d.max():.2e}", flush=True)
+        assert all(t[1] and t[2] <= 1e-12 for t in stl)
+        res = (b - A.apply(xl)).norm(dim=1) / b.norm(dim=1)
+        assert float(res.max()) <= 1e-12 * (1 + 1e-6)
+        assert d.max() <= 1e-8

@@ -43,9 +43,9 @@ CONFIGS[3] = dict(
     semiaxes=(0.5, 2.0), torus_R=1.0, torus_r=(0.2, 0.5), q=5, eta=1.6,
 )
 CONFIGS[4] = dict(
-    name="learned_precond_ellipsoid_torus_L5_d2_helmholtz",
-    level=5, degree=2, kappa_range=(4.0, 20.0), semiaxes=(0.5, 2.0), torus_R=1.0, torus_r=(0.2, 0.5),
-    q=5, eta=1.6, tol=1e-8, restart=30, maxit=2000, ring=2,
+    name="learned_precond_ellipsoid_torus_L5-6_d2_helmholtz_k4-20",
+    level=5, levels=(5, 6), degree=2, kappa_range=(4.0, 20.0), semiaxes=(0.5, 2.0), torus_R=1.0,
+    torus_r=(0.2, 0.5), q=5, eta=1.6, tol=1e-8, restart=30, maxit=2000, ring=2, train_blocks=10000,
 )
 
 GEOM_KIND = {"sphere": 0, "ellipsoid": 1, "torus": 2, "flat": 3}
@@ -145,6 +145,14 @@ def shape_draw(g: np.random.Generator, cfg: dict):
         a = g.uniform(*cfg["semiaxes"], size=3)
         return GEOM_KIND["ellipsoid"], tuple(float(v) for v in a)
     return GEOM_KIND["torus"], (float(cfg["torus_R"]), float(g.uniform(*cfg["torus_r"])))
+
+
+def c4_levels(n: int, stream: int = 0):
+    """Levels of the first n instances of a stream of the learned-preconditioner family,
+    uniform over the configured levels (a draw of its own, so the instances' shapes and
+    wavenumbers do not depend on it)."""
+    g = rng(4, 100 + stream)
+    return [int(v) for v in g.choice(CONFIGS[4]["levels"], size=n)]
 
 
 def c4_instances(n: int, stream: int = 0, kappa_range=None):
