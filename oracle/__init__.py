@@ -56,6 +56,8 @@ def lib():
             "orc_space_new": (I, [I, P, I, I, D, D, I, I, I, P]),
             "orc_space_new_nurbs": (I, [I, P, P, P, I, D, D, I, I, I, P]),
             "orc_h2_potential": (I, [P, P, I64, P, D, P]),
+            "orc_space_set_form": (I, [P, I]),
+            "orc_space_glue": (I, [P, P, P]),
             "orc_set_threads": (I, [I]),
             "orc_space_free": (None, [P]),
             "orc_space_ndof": (I64, [P]),
@@ -136,7 +138,7 @@ class Space:
     """Discrete space S^2 on an analytic multi-patch geometry, with its PDE."""
 
     def __init__(self, geom: int, gparams=(), pde: int = LAPLACE, kappa: complex = 0.0,
-                 degree: int = 1, knot_rep: int = 1, level: int = 0):
+                 degree: int = 1, knot_rep: int = 1, level: int = 0, form: int = 2):
         """geom: an analytic kind with its parameters, or NURBS with gparams a list of patches,
         each a dict with "degree" (p1, p2), "knots" (Xi_1, Xi_2) and "cw", an array
         (k1, k2, 4) of control points and weights (App. C)."""
@@ -161,6 +163,9 @@ class Space:
             _check(lib().orc_space_new(geom, _p(gp), int(len(gparams)), pde, float(np.real(kappa)),
                                        float(np.imag(kappa)), degree, knot_rep, level, ctypes.byref(h)))
         self._h = h
+        self.form = form
+        if form != 2:
+            _check(lib().orc_space_set_form(self._h, form))
         self.pde = pde
         self.complex = pde == HELMHOLTZ
         self.degree, self.level, self.knot_rep = degree, level, knot_rep
@@ -177,7 +182,15 @@ class Space:
 
     @property
     def ndof(self) -> int:
+        """Local functions (patch by patch); the glued space has glue()[1] of them."""
         return lib().orc_space_ndof(self._h)
+
+    def glue(self):
+        """S^0 continuity: (map local -> global, number of global functions)."""
+        m = np.zeros(self.ndof, dtype=np.int64)
+        n = ctypes.c_int64()
+        _check(lib().orc_space_glue(self._h, _p(m), ctypes.byref(n)))
+        return m, int(n.value)
 
     @property
     def nelem(self) -> int:

@@ -22,6 +22,7 @@
 // geometrically in q, and its matvec equals the operator written out from the definition
 // (interpolated kernel on every far pair, scipy B-splines and Gauss rules; flat square).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -402,6 +403,10 @@ struct Space {
     Knots K;
     int64_t nelem = 0, ndof = 0;
     double h = 1.0;
+    // lifting of the reference functions to the surface (App. E "Piola transform"): 2 for
+    // the 2-form lifting of S^2 (the surface element cancels, reading A3), 0 for the 0-form
+    // lifting of S^0 (phi = phi_hat o gamma^-1: every surface integral carries kappa)
+    int form = 2;
 };
 
 static Space make_space(const Geom& G, int pde, cplx kappa, int d, int r, int L) {
@@ -431,6 +436,63 @@ static Elem elem_of(const Space& S, int64_t e) {
 static int64_t dof_index(const Space& S, int f, int j1, int j2) {
     return ((int64_t)f * S.K.nb + j1) * S.K.nb + j2;
 }
+
+// S^0 continuity across patch boundaries (App. E: continuity conditions give the conforming
+// space S^0(Gamma) in H^1/2).  Each local B-spline b_j1 b_j2 of a patch is anchored at the
+// image of its Greville point (xi*_j1, xi*_j2), xi*_j = (xi_{j+1} + ... + xi_{j+d}) / d; with
+// clamped knots the anchors of the functions that do not vanish on the patch boundary lie on
+// it, and by the matching condition (App. D) the functions of two patches that agree on a
+// shared edge or vertex have the same anchor.  Those are identified (anchors within 1e-10
+// of the largest anchor coordinate), every other function is its own.  Global indices are
+// numbered in the order of their first local function.  Returns the local -> global map.
+static std::vector<int64_t> glue_map(const Space& S, int64_t* nglob) {
+    const Knots& K = S.K;
+    if (K.d < 1) throw std::runtime_error("continuous spaces need degree >= 1");
+    const int nb = K.nb;
+    std::vector<double> gr(nb);
+    for (int j = 0; j < nb; ++j) {
+        double a = 0.0;
+        for (int k = 1; k <= K.d; ++k) a += K.xi[j + k];
+        gr[j] = a / K.d;
+    }
+    std::vector<int64_t> bidx;
+    std::vector<std::array<double, 3>> anc;
+    double scale = 0.0;
+    for (int f = 0; f < S.G.npatch; ++f)
+        for (int j1 = 0; j1 < nb; ++j1)
+            for (int j2 = 0; j2 < nb; ++j2) {
+                if (j1 != 0 && j1 != nb - 1 && j2 != 0 && j2 != nb - 1) continue;
+                std::array<double, 3> x;
+                gamma(S.G, f, gr[j1], gr[j2], x.data());
+                for (double v : x) scale = std::max(scale, std::fabs(v));
+                bidx.push_back(dof_index(S, f, j1, j2));
+                anc.push_back(x);
+            }
+    std::vector<int64_t> parent(S.ndof);
+    for (int64_t g = 0; g < S.ndof; ++g) parent[g] = g;
+    auto root = [&](int64_t g) {
+        while (parent[g] != g) g = parent[g] = parent[parent[g]];
+        return g;
+    };
+    const double tol = 1e-10 * std::max(scale, 1e-300);
+    for (size_t a = 0; a < bidx.size(); ++a)
+        for (size_t b = a + 1; b < bidx.size(); ++b)
+            if (std::fabs(anc[a][0] - anc[b][0]) <= tol && std::fabs(anc[a][1] - anc[b][1]) <= tol &&
+                std::fabs(anc[a][2] - anc[b][2]) <= tol) {
+                const int64_t ra = root(bidx[a]), rb = root(bidx[b]);
+                if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+            }
+    std::vector<int64_t> gid(S.ndof, -1), map(S.ndof);
+    int64_t n = 0;
+    for (int64_t g = 0; g < S.ndof; ++g) {
+        const int64_t r = root(g);
+        if (gid[r] < 0) gid[r] = n++;
+        map[g] = gid[r];
+    }
+    *nglob = n;
+    return map;
+}
+
 
 // D4 symmetries of the unit square, fixed enumeration (reading A8): identity, flip first,
 // flip second, flip both; then the same four applied after swapping the coordinates.
@@ -504,6 +566,10 @@ static void side_eval(const Space& S, const SideFn& F, const Elem& E, int k, dou
     gamma(S.G, E.f, s, t, x);
     if (F.mode == SIDE_SPLINE) {
         elem_basis(S, E, s, t, vals);
+        if (S.form == 0) {
+            const double k = surf_elem(S.G, E.f, s, t);
+            for (int l = 0; l < side_nb(S, F); ++l) vals[l] *= k;
+        }
     } else {
         vals[0] = density_fn(F.fid, x) * surf_elem(S.G, E.f, s, t);
     }
@@ -767,7 +833,8 @@ static void load_vector(const Space& S, int kind, const double* prm, int q, T* b
                 elem_param(S, E, 0, g.x[a1], g.x[a2], s, t);
                 gamma(S.G, E.f, s, t, x);
                 elem_basis(S, E, s, t, ph.data());
-                const T gv = data_value<T>(S, kind, prm, x) * (g.w[a1] * g.w[a2] * S.h * S.h);
+                const double lift = S.form == 0 ? surf_elem(S.G, E.f, s, t) : 1.0;
+                const T gv = data_value<T>(S, kind, prm, x) * (g.w[a1] * g.w[a2] * S.h * S.h * lift);
                 for (int l = 0; l < nb; ++l) b[local_dof(S, E, l)] += gv * ph[l];
             }
     }
@@ -791,7 +858,7 @@ static void potential(const Space& S, int q, const T* rho, int64_t npts, const d
                 elem_basis(S, E, s, t, ph.data());
                 T rv = T(0);
                 for (int l = 0; l < nb; ++l) rv += rho[local_dof(S, E, l)] * ph[l];
-                rv *= g.w[a1] * g.w[a2] * S.h * S.h;
+                rv *= g.w[a1] * g.w[a2] * S.h * S.h * (S.form == 0 ? surf_elem(S.G, E.f, s, t) : 1.0);
                 for (int64_t p = 0; p < npts; ++p)
                     u[p] += kernel_r<T>(S.pde, S.kappa, dist3(&pts[3 * p], y)) * rv;
             }
@@ -845,6 +912,7 @@ struct H2 {
     // 1-D moments per leaf index i along one direction: V1[i][a*nloc + m] =
     //   int over leaf interval i of L_a(s) b_{first(i)+m}(s) ds
     std::vector<std::vector<double>> V1;
+    std::vector<std::vector<double>> Vd;  // 0-form lifting: full leaf tables (see h2_build)
     int nloc = 0;  // B-splines overlapping one leaf interval
     bool have_near = false;
     std::vector<std::map<int64_t, T>> near_rows;  // near field, one sorted map per row
@@ -996,6 +1064,41 @@ static void h2_build(H2<T>& H, const Space& S, int q, double eta, int leaf, int 
             }
         }
     }
+    // 0-form lifting: the moments carry the surface element, so a leaf's table is no longer
+    // a product of 1-D tables; Vd[leaf][(a1 q + a2) nloc^2 + m1 nloc + m2] is the integral over
+    // the leaf of L_a1 L_a2 b_{first1+m1} b_{first2+m2} kappa by qg x qg Gauss points per element
+    if (S.form == 0) {
+        const Rule gq = gauss01(qg);
+        const int nl2 = H.nloc * H.nloc, nbl = (S.K.d + 1) * (S.K.d + 1);
+        H.Vd.assign((size_t)S.G.npatch * nleaf1 * nleaf1, std::vector<double>((size_t)q * q * nl2, 0.0));
+        std::vector<double> ph(nbl);
+        for (int f = 0; f < S.G.npatch; ++f)
+            for (int i = 0; i < nleaf1; ++i)
+                for (int j = 0; j < nleaf1; ++j) {
+                    std::vector<double>& V = H.Vd[((size_t)f * nleaf1 + i) * nleaf1 + j];
+                    const int fi = H.leaf_first_basis(i), fj = H.leaf_first_basis(j);
+                    for (int e1 = i * m; e1 < (i + 1) * m; ++e1)
+                        for (int e2 = j * m; e2 < (j + 1) * m; ++e2) {
+                            const Elem E{f, e1, e2};
+                            for (int k1 = 0; k1 < qg; ++k1)
+                                for (int k2 = 0; k2 < qg; ++k2) {
+                                    const double s = (e1 + gq.x[k1]) * S.h, t = (e2 + gq.x[k2]) * S.h;
+                                    elem_basis(S, E, s, t, ph.data());
+                                    const double w = gq.w[k1] * gq.w[k2] * S.h * S.h * surf_elem(S.G, f, s, t);
+                                    const double sl = s * nleaf1 - i, tl = t * nleaf1 - j;
+                                    for (int a1 = 0; a1 < q; ++a1)
+                                        for (int a2 = 0; a2 < q; ++a2) {
+                                            const double La = lagrange(H.xi, a1, sl) * lagrange(H.xi, a2, tl) * w;
+                                            for (int l = 0; l < nbl; ++l) {
+                                                const int m1 = elem_first_basis(S.K, e1) + l / (S.K.d + 1) - fi;
+                                                const int m2 = elem_first_basis(S.K, e2) + l % (S.K.d + 1) - fj;
+                                                V[(size_t)(a1 * q + a2) * nl2 + m1 * H.nloc + m2] += La * ph[l];
+                                            }
+                                        }
+                                }
+                        }
+                }
+    }
     // coupling blocks K[(a1,a2),(b1,b2)] = k(gamma_tau(xi_a), gamma_sigma(xi_b))
     const int q2 = q * q;
     H.K.assign(H.far.size() * (size_t)q2 * q2, T(0));
@@ -1055,9 +1158,13 @@ static void h2_forward(const H2<T>& H, const T* x, std::vector<T>& mom) {
                     for (int a2 = 0; a2 < q; ++a2) {
                         T acc = T(0);
                         for (int m1 = 0; m1 < H.nloc; ++m1)
-                            for (int m2 = 0; m2 < H.nloc; ++m2)
-                                acc += H.V1[i][a1 * H.nloc + m1] * H.V1[j][a2 * H.nloc + m2] *
-                                       x[dof_index(S, f, fi + m1, fj + m2)];
+                            for (int m2 = 0; m2 < H.nloc; ++m2) {
+                                const double v = S.form == 0
+                                                     ? H.Vd[((size_t)f * nl + i) * nl + j][(size_t)(a1 * q + a2) * H.nloc * H.nloc +
+                                                                                           m1 * H.nloc + m2]
+                                                     : H.V1[i][a1 * H.nloc + m1] * H.V1[j][a2 * H.nloc + m2];
+                                acc += v * x[dof_index(S, f, fi + m1, fj + m2)];
+                            }
                         mom[c * q2 + a1 * q + a2] = acc;
                     }
             }
@@ -1098,7 +1205,8 @@ template <class T>
 static void h2_direct_moments(const H2<T>& H, const T* x, std::vector<T>& mom) {
     const Space& S = *H.S;
     const int q = H.q, q2 = q * q;
-    const Rule g = gauss01(H.qm);
+    const int nq = S.form == 0 ? H.qg : H.qm;  // 0-form: the leaf tables' rule
+    const Rule g = gauss01(nq);
     const int nb = (S.K.d + 1) * (S.K.d + 1);
     std::vector<double> ph(nb);
     std::fill(mom.begin(), mom.end(), T(0));
@@ -1112,13 +1220,13 @@ static void h2_direct_moments(const H2<T>& H, const T* x, std::vector<T>& mom) {
                     for (int ei = i * m; ei < (i + 1) * m; ++ei)
                         for (int ej = j * m; ej < (j + 1) * m; ++ej) {
                             Elem E{f, ei, ej};
-                            for (int k1 = 0; k1 < H.qm; ++k1)
-                                for (int k2 = 0; k2 < H.qm; ++k2) {
+                            for (int k1 = 0; k1 < nq; ++k1)
+                                for (int k2 = 0; k2 < nq; ++k2) {
                                     const double s = (ei + g.x[k1]) * S.h, t = (ej + g.x[k2]) * S.h;
                                     elem_basis(S, E, s, t, ph.data());
                                     T xv = T(0);
                                     for (int lb = 0; lb < nb; ++lb) xv += ph[lb] * x[local_dof(S, E, lb)];
-                                    const double w = g.w[k1] * g.w[k2] * S.h * S.h;
+                                    const double w = g.w[k1] * g.w[k2] * S.h * S.h * (S.form == 0 ? surf_elem(S.G, f, s, t) : 1.0);
                                     const double sl = s * n - i, tl = t * n - j;
                                     for (int a1 = 0; a1 < q; ++a1)
                                         for (int a2 = 0; a2 < q; ++a2)
@@ -1198,8 +1306,13 @@ static T h2_backward_dof(const H2<T>& H, const std::vector<T>& lv, int64_t g) {
             if (m2 < 0 || m2 >= H.nloc) continue;
             const int64_t c = H.cluster_index(H.leaf, f, i, j);
             for (int a1 = 0; a1 < q; ++a1)
-                for (int a2 = 0; a2 < q; ++a2)
-                    acc += H.V1[i][a1 * H.nloc + m1] * H.V1[j][a2 * H.nloc + m2] * lv[c * q2 + a1 * q + a2];
+                for (int a2 = 0; a2 < q; ++a2) {
+                    const double v = S.form == 0
+                                         ? H.Vd[((size_t)f * nl + i) * nl + j][(size_t)(a1 * q + a2) * H.nloc * H.nloc +
+                                                                               m1 * H.nloc + m2]
+                                         : H.V1[i][a1 * H.nloc + m1] * H.V1[j][a2 * H.nloc + m2];
+                    acc += v * lv[c * q2 + a1 * q + a2];
+                }
         }
     }
     return acc;
@@ -1701,6 +1814,7 @@ static void h2_potential(const H2<T>& H, const T* rho, int64_t npts, const doubl
                             elem_basis(S, E, s, t, ph.data());
                             T rv = T(0);
                             for (int l = 0; l < nb; ++l) rv += rho[local_dof(S, E, l)] * ph[l];
+                            if (S.form == 0) rv *= surf_elem(S.G, E.f, s, t);
                             acc += kernel_r<T>(S.pde, S.kappa, dist3(x, y)) * rv * (g.w[a1] * g.w[a2] * S.h * S.h);
                         }
                 }
@@ -1779,6 +1893,24 @@ int orc_space_new_nurbs(int npatch, const int* meta, const double* knots, const 
             throw;
         }
         *out = s;
+    })
+}
+
+// lifting of the space: 2 (S^2, default) or 0 (S^0: surface integrals carry kappa); set
+// before any operator is built on the space
+int orc_space_set_form(void* sp, int form) {
+    ORC_TRY({
+        if (form != 0 && form != 2) throw std::runtime_error("form must be 0 or 2");
+        ((OrcSpace*)sp)->S.form = form;
+    })
+}
+
+// S^0 gluing: local -> global index of every local B-spline (map, ndof entries) and the
+// number of global functions
+int orc_space_glue(void* sp, int64_t* map, int64_t* nglob) {
+    ORC_TRY({
+        const std::vector<int64_t> m = glue_map(((OrcSpace*)sp)->S, nglob);
+        std::copy(m.begin(), m.end(), map);
     })
 }
 
