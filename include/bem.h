@@ -437,6 +437,17 @@ int bem_mlp_init(int in, int hidden, int out, uint64_t seed, float* params_dev, 
 /* Y [batch][out] = net(X [batch][in]) (device, row-major). */
 int bem_mlp_forward(int in, int hidden, int out, int batch, const float* params_dev, const float* X_dev, float* Y_dev,
                     int precision, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Y = net(X) like bem_mlp_forward, for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): no workspace argument
+ * and no allocation of any kind.  The hidden activations (2 * batch * hidden floats) live in a
+ * fixed 32 MiB device array of the library, one per GPU, held until the process ends; its
+ * address is looked up on the first call on each device.  EINVAL if 8 * batch * hidden
+ * exceeds 32 MiB (33554432 bytes) or batch > 1048576, as for bad sizes.  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one device (different streams
+ * or threads) race and must be serialised by the caller.  Same kernels and results as
+ * bem_mlp_forward. */
+int bem_mlp_forward_noalloc(int in, int hidden, int out, int batch, const float* params_dev, const float* X_dev,
+                            float* Y_dev, int precision, hipStream_t stream);
 /* Loss of the rank-8 block correction and its gradient: the network output of sample b is
  * U_b, V_b (64 x 8; out = 1024: [U | V] real, out = 2048: [Re U | Im U | Re V | Im V]);
  * loss = mean_b ||T_b - U_b V_b^T||_F^2 / ||T_b||_F^2 with T (device float, batch x 64 x 64,

@@ -105,6 +105,7 @@ _SIGNATURES = {
     "bem_mlp_sizes": (_c_int, [_c_int, _c_int, _c_int, _c_int, _P(_c_i64), _P(_c_sz)]),
     "bem_mlp_init": (_c_int, [_c_int, _c_int, _c_int, ctypes.c_uint64, _vp, _vp]),
     "bem_mlp_forward": (_c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _c_int, _vp, _c_sz, _vp]),
+    "bem_mlp_forward_noalloc": (_c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _c_int, _vp]),
     "bem_mlp_loss_grad": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _vp, _vp, _c_int, _vp, _c_sz,
                                    _vp]),
     "bem_mlp_adam": (_c_int, [_c_i64, _vp, _vp, _vp, _vp, _c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -401,6 +402,10 @@ def bem_mlp_init(n_in: int, hidden: int, out: int, seed: int, params_ptr: int, s
 
 def bem_mlp_forward(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, ws_ptr, ws_bytes, stream):
     check(lib.bem_mlp_forward(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, ws_ptr, ws_bytes, stream))
+
+
+def bem_mlp_forward_noalloc(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, stream):
+    check(lib.bem_mlp_forward_noalloc(n_in, hidden, out, batch, params_ptr, x_ptr, y_ptr, precision, stream))
 
 
 def bem_mlp_loss_grad(n_in, hidden, out, batch, is_complex, params_ptr, x_ptr, t_ptr, grad_ptr, loss_ptr, precision,

@@ -1796,8 +1796,25 @@ int bem_mlp_forward(int in, int hidden, int out, int batch, const float* params_
     if (!params_dev || !X_dev || !Y_dev || !ws) return fail(BEM_EINVAL, "NULL argument");
     if (in < 1 || hidden < 1 || out < 1 || batch < 1 || (precision != 0 && precision != 1))
         return fail(BEM_EINVAL, "sizes >= 1, precision 0 or 1");
+    if (batch > kMlpMaxBatch) return fail(BEM_EINVAL, "batch above " + std::to_string(kMlpMaxBatch));
     if (ws_bytes < mlp_ws_bytes(hidden, out, batch)) return fail(BEM_ENOMEM, "workspace too small");
     HIP_CHECK(mlp_forward(in, hidden, out, batch, params_dev, X_dev, Y_dev, precision, ws, stream));
+    return BEM_OK;
+}
+
+int bem_mlp_forward_noalloc(int in, int hidden, int out, int batch, const float* params_dev, const float* X_dev,
+                            float* Y_dev, int precision, hipStream_t stream) {
+    if (!params_dev || !X_dev || !Y_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (in < 1 || hidden < 1 || out < 1 || batch < 1 || (precision != 0 && precision != 1))
+        return fail(BEM_EINVAL, "sizes >= 1, precision 0 or 1");
+    if (batch > kMlpMaxBatch) return fail(BEM_EINVAL, "batch above " + std::to_string(kMlpMaxBatch));
+    const size_t need = mlp_forward_scratch_bytes(hidden, batch);
+    if (need > kMlpScratchBytes)
+        return fail(BEM_EINVAL, "batch * hidden too large for the fixed scratch: needs " + std::to_string(need) +
+                                    " bytes, the limit is " + std::to_string(kMlpScratchBytes));
+    void* scr = nullptr;
+    HIP_CHECK(mlp_scratch(&scr));
+    HIP_CHECK(mlp_forward_noalloc(in, hidden, out, batch, params_dev, X_dev, Y_dev, precision, scr, stream));
     return BEM_OK;
 }
 

@@ -8,6 +8,8 @@
 // (precision 1, v_mfma_f32_16x16x32_bf16).
 #include "bem_mlp.h"
 
+#include <mutex>
+
 #include "bem_device.h"
 
 namespace bem {
@@ -348,6 +350,47 @@ hipError_t mlp_forward(int in, int hid, int out, int batch, const float* params,
                        int precision, void* ws, hipStream_t st) {
     const Net n = net_of(in, hid, out, params);
     return forward(n, batch, X, Y, ws_of(hid, out, batch, ws), precision, st);
+}
+
+// Forward pass with its hidden activations in a fixed device array instead of a caller
+// workspace, for callers that cannot allocate (graph capture, serving loops).  The array is
+// a file-scope device variable; its address differs per device and is looked up once per
+// device with hipGetSymbolAddress (the variable's name in host code is only a stand-in).
+// Every call on a device shares that device's array, so calls that overlap in time on one
+// device race.  Nothing in the array needs clearing: the forward pass writes H1 and H2 in
+// full before reading them.
+static __device__ __align__(256) char scratch[kMlpScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMlpMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMlpMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t mlp_forward_scratch_bytes(int hid, int batch) { return sizeof(float) * 2 * (size_t)batch * (size_t)hid; }
+
+hipError_t mlp_forward_noalloc(int in, int hid, int out, int batch, const float* params, const float* X, float* Y,
+                               int precision, void* scratch_ptr, hipStream_t st) {
+    const Net n = net_of(in, hid, out, params);
+    MlpWs w{};
+    w.H1 = (float*)scratch_ptr;
+    w.H2 = w.H1 + (size_t)batch * hid;
+    return forward(n, batch, X, Y, w, precision, st);
 }
 
 hipError_t mlp_loss_grad(int in, int hid, int out, int batch, int cplx, const float* params, const float* X,
