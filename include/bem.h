@@ -130,6 +130,7 @@ typedef struct bem_operator_info {
     int64_t nstored;         /* stored coupling blocks (= nfar / 2) */
     int64_t nchunks;         /* work chunks of the coupling kernel */
     double transposed_bytes; /* bytes of the per-column transposed products */
+    int64_t nlocal;          /* local functions (patch by patch); = ndof except on S^0 spaces */
 } bem_operator_info;
 
 /* GMRES(m) parameters (reading: restart 30, x0 = 0, relative residual tolerance). */
@@ -231,7 +232,29 @@ int bem_geometry_user(int npatch, bem_user_map gamma, void* user, int degree, in
  * degree <= 2. */
 int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
                      int knot_repetition, int level, bem_space* out);
+
+/* The spline spaces of App. E on the patches: */
+#define BEM_SPACE_S2 2 /* S^2: discontinuous across patches, 2-form (Piola) lifting (default) */
+#define BEM_SPACE_S0 0 /* S^0: continuous across patch boundaries, 0-form lifting */
+/* bem_space_create with the space kind.  S^0 (conforming in H^1/2; degree >= 1): the local
+ * B-splines of a patch are lifted as phi = phi_hat o gamma^-1, so every surface integral
+ * (Galerkin entries, moments, load vector, potential) carries the surface element kappa;
+ * the local functions that do not vanish on a shared edge or vertex are glued into one
+ * global function (reading: functions whose Greville-point images coincide within 1e-10 of
+ * the largest coordinate are the same; the matching condition of App. D makes these the
+ * traces that agree).  Global functions are numbered in the order of their first local
+ * function (patch, j1, j2).  Every vector over the DOFs of an S^0 space (load vectors,
+ * densities, products, solutions) has the global length bem_space_ndof returns.  Operators
+ * on S^0 spaces: FP64, one column per pass (far_low = 0, batch_rhs <= 1), no block
+ * preconditioner, no grouped launches, no stage timing (EUNSUPPORTED). */
+int bem_space_create_ex(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
+                        int knot_repetition, int level, int space_kind, bem_space* out);
+/* N: the space's functions (S^0: global, glued ones). */
 int bem_space_ndof(bem_space s, int64_t* n);
+/* Local functions (patch by patch, the numbering of the near field's CSR export) into
+ * *nlocal and, if glue_host is not NULL, the global function of each (host, nlocal entries;
+ * the identity for S^2). */
+int bem_space_glue(bem_space s, int64_t* nlocal, int32_t* glue_host);
 void bem_space_destroy(bem_space s);
 
 /* Load vectors (Sec. 4 "Boundary Values"): b_g = int_Gamma g psi_g for nrhs data sets.
@@ -337,8 +360,9 @@ int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, c
  * quadrilaterals (cell type 9) per element, point e * (nsub + 1)^2 + a * (nsub + 1) + b at
  * parameter (i1 + a / nsub, i2 + b / nsub) 2^-L of element e = (patch, i1, i2), and point
  * data "kappa" (surface element |d_s gamma x d_t gamma|, by central differences with step
- * 1e-6) and, per column r of rho, the density on the surface rho_hat / kappa (2-form
- * lifting) as "rho_r" (Laplace) or "rho_re_r", "rho_im_r" (Helmholtz).  rho_host: host,
+ * 1e-6) and, per column r of rho, the density on the surface, rho_hat / kappa (2-form
+ * lifting, S^2) or rho_hat (0-form, S^0, coefficients of the global functions), as "rho_r"
+ * (Laplace) or "rho_re_r", "rho_im_r" (Helmholtz).  rho_host: host,
  * N x nrhs column-major (leading dimension ldr >= N), may be NULL with nrhs = 0 (geometry
  * only); 0 <= nrhs <= 64, 1 <= nsub <= 64.  Host work only. */
 int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int nsub, const char* path);

@@ -71,13 +71,20 @@ class Geometry:
 
 class Space:
     def __init__(self, geom: Geometry, kernel: int = BEM_LAPLACE_SINGLE, kappa: complex = 0.0, degree: int = 1,
-                 knot_repetition: int = 1, level: int = 0):
-        self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level)
+                 knot_repetition: int = 1, level: int = 0, continuous: bool = False):
+        """continuous=True: the S^0 space (glued across patches, 0-form lifting); else S^2."""
+        self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level,
+                                    C.BEM_SPACE_S0 if continuous else C.BEM_SPACE_S2)
+        self.continuous = bool(continuous)
         self.geom = geom
         self.kernel, self.kappa, self.degree, self.level = kernel, complex(kappa), degree, level
         self.knot_repetition = knot_repetition
         self.ndof = C.bem_space_ndof(self.h)
         self.dtype = torch.complex128 if kernel == BEM_HELMHOLTZ_SINGLE else torch.float64
+
+    def glue(self) -> np.ndarray:
+        """Global function of every local function (the identity for S^2)."""
+        return C.bem_space_glue(self.h)[1]
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -258,7 +265,8 @@ class Operator:
         return u.reshape(rho.shape[:-1] + (pts.shape[0],)) if rho.dim() == 1 else u
 
     def export_near(self):
-        n = self.ndof
+        """Near field on the local functions (patch by patch), CSR."""
+        n = self.info.nlocal
         rowptr = np.zeros(n + 1, dtype=np.int64)
         col = np.zeros(self.info.near_nnz, dtype=np.int32)
         npdt = np.complex128 if self.space.dtype == torch.complex128 else np.float64

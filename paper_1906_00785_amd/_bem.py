@@ -14,6 +14,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bem.h")
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
 BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1, BEM_GEOM_NURBS = 0, 1, 2, 3, 4
+BEM_SPACE_S2, BEM_SPACE_S0 = 2, 0
 BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
 BEM_PREC_FP64, BEM_PREC_FP32, BEM_PREC_BF16 = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_BLOCK = 0, 1
@@ -31,7 +32,7 @@ class bem_operator_info(ctypes.Structure):
     _fields_ = [("ndof", _c_i64), ("nclusters", _c_i64), ("nfar", _c_i64), ("nnear", _c_i64), ("ntouch", _c_i64),
                 ("near_nnz", _c_i64), ("leaf_level", _c_i64), ("op_bytes", _c_sz), ("tmp_bytes", _c_sz),
                 ("far_bytes", _c_dbl), ("near_bytes", _c_dbl), ("nstored", _c_i64), ("nchunks", _c_i64),
-                ("transposed_bytes", _c_dbl)]
+                ("transposed_bytes", _c_dbl), ("nlocal", _c_i64)]
 
 
 class bem_solve_params(ctypes.Structure):
@@ -63,6 +64,8 @@ _SIGNATURES = {
     "bem_geometry_save": (_c_int, [_vp, ctypes.c_char_p]),
     "bem_geometry_user": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _P(_vp)]),
     "bem_space_create": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _P(_vp)]),
+    "bem_space_create_ex": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _c_int, _P(_vp)]),
+    "bem_space_glue": (_c_int, [_vp, _P(_c_i64), _vp]),
     "bem_space_ndof": (_c_int, [_vp, _P(_c_i64)]),
     "bem_space_destroy": (None, [_vp]),
     "bem_rhs": (_c_int, [_vp, _c_int, _P(_c_dbl), _c_int, _vp, _c_i64, _vp]),
@@ -210,11 +213,24 @@ def bem_geometry_destroy(g: int):
     lib.bem_geometry_destroy(g)
 
 
-def bem_space_create(g: int, kernel: int, kappa: complex, degree: int, knot_repetition: int, level: int) -> int:
+def bem_space_create(g: int, kernel: int, kappa: complex, degree: int, knot_repetition: int, level: int,
+                     space_kind: int = BEM_SPACE_S2) -> int:
     h = _vp()
     kappa = complex(kappa)
-    check(lib.bem_space_create(g, kernel, kappa.real, kappa.imag, degree, knot_repetition, level, ctypes.byref(h)))
+    check(lib.bem_space_create_ex(g, kernel, kappa.real, kappa.imag, degree, knot_repetition, level, space_kind,
+                                  ctypes.byref(h)))
     return h.value
+
+
+def bem_space_glue(s: int):
+    """(number of local functions, int32 array of their global functions)."""
+    import numpy as np
+
+    n = _c_i64()
+    check(lib.bem_space_glue(s, ctypes.byref(n), None))
+    m = np.zeros(n.value, dtype=np.int32)
+    check(lib.bem_space_glue(s, ctypes.byref(n), m.ctypes.data))
+    return n.value, m
 
 
 def bem_space_ndof(s: int) -> int:

@@ -75,10 +75,25 @@ struct bem_geometry_s {
     std::shared_ptr<GeomTab> tab;
 };
 
+// S^0 gluing of a space: local -> global map and the inverse in CSR form, host and device
+struct GlueTab {
+    std::vector<int32_t> glue, ginv_idx;
+    std::vector<int64_t> ginv_ptr;
+    int32_t* d_glue = nullptr;
+    int64_t* d_ptr = nullptr;
+    int32_t* d_idx = nullptr;
+    ~GlueTab() {
+        if (d_glue) (void)hipFree(d_glue);
+        if (d_ptr) (void)hipFree(d_ptr);
+        if (d_idx) (void)hipFree(d_idx);
+    }
+};
+
 struct bem_space_s {
     SpaceDesc S;
     BasisTab bt;
-    std::shared_ptr<GeomTab> tab;  // keeps a NURBS geometry's tables alive
+    std::shared_ptr<GeomTab> tab;    // keeps a NURBS geometry's tables alive
+    std::shared_ptr<GlueTab> glue;   // S^0 only
 };
 
 struct bem_operator_s {
@@ -162,6 +177,12 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
     o.E = b.take<double>(p.E.size());
     o.mom = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
     o.lv = b.take<char>((size_t)p.ncl * p.q2 * A.scal);
+    if (p.S.form == 0) {
+        // 0-form lifting: full leaf tables; S^0: local copies of the applied vectors
+        o.Vd = b.take<double>((size_t)p.nleaves * p.q2 * p.nloc * p.nloc);
+        o.xl = b.take<char>((size_t)p.S.ndof * A.scal);
+        o.yl = b.take<char>((size_t)p.S.ndof * A.scal);
+    }
     if (A.batch_rhs > 1) {
         // many-RHS slabs and the per-pair block table
         const size_t Rb = (size_t)A.batch_rhs, nch = (Rb + kBatchChunk - 1) / kBatchChunk, N = (size_t)p.S.ndof;
@@ -215,6 +236,7 @@ static size_t tmp_layout(const bem_operator_s& A, void* base, AsmDev* d) {
     a.gx = b.take<double>(p.gx.size());
     a.gw = b.take<double>(p.gw.size());
     a.gpos = b.take<double>((size_t)S.nelem * p.P.qg * p.P.qg * 3);
+    a.gkap = S.form == 0 ? b.take<double>((size_t)S.nelem * p.P.qg * p.P.qg) : nullptr;
     a.psi = b.take<double>(p.psi.size());
     a.sx = b.take<double>(p.sx.size());
     a.sw = b.take<double>(p.sw.size());
@@ -336,6 +358,19 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws,
     return b.off + 256;
 }
 
+// y = A x for one column of global functions: on an S^0 space the column is spread to the
+// local functions, multiplied, and the local products of each global function summed.
+static hipError_t op_apply(const bem_operator_s* A, int prec, const void* x, void* y, hipStream_t stream) {
+    const SpaceDesc& S = A->dev.S;
+    if (S.form != 0) return launch_apply(A->dev, x, y, prec, stream);
+    const int cp = A->cplx ? 1 : 0;
+    hipError_t e = launch_glue_gather(S, cp, x, A->dev.xl, stream);
+    if (e != hipSuccess) return e;
+    e = launch_apply(A->dev, A->dev.xl, A->dev.yl, prec, stream);
+    if (e != hipSuccess) return e;
+    return launch_glue_scatter(S, cp, A->dev.yl, y, stream);
+}
+
 // One right-hand side.  The Givens step of Arnoldi step j runs inside step j+1's
 // dot-product kernel and writes its residual estimate straight to coherent host memory,
 // with a stamp (no copy, no event in the stream); having enqueued step j the host waits
@@ -401,7 +436,7 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
     for (int cycle = 0;; ++cycle) {
         W.st.stamp = ++A->stamp;
         if (cycle > 0) {
-            HIP_CHECK(launch_apply(A->dev, x, W.w, prec, stream));
+            HIP_CHECK(op_apply(A, prec, x, W.w, stream));
             HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
         }  // in the first cycle x = 0 and w already holds b
         HIP_CHECK(solve_start(cp, N, W.npart, W.w, Vj(0), W.st, stream));
@@ -414,9 +449,9 @@ static int gmres_one(bem_operator A, int prec, const void* b, void* x, int m, in
         for (int j = 0; j < m && total + j < maxit; ++j) {
             if (pc) {
                 HIP_CHECK(launch_prec_apply(A->dev, A->pdev, 1, Vj(j), W.z, stream));
-                HIP_CHECK(launch_apply(A->dev, W.z, W.w, prec, stream));
+                HIP_CHECK(op_apply(A, prec, W.z, W.w, stream));
             } else {
-                HIP_CHECK(launch_apply(A->dev, Vj(j), W.w, prec, stream));
+                HIP_CHECK(op_apply(A, prec, Vj(j), W.w, stream));
             }
             // the dot products of step j and the Givens step of step j-1
             HIP_CHECK(solve_dots(cp, N, j + 1, W.V, W.w, W.partA, j - 1, W.npart, W.st, stream));
@@ -514,7 +549,7 @@ static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_pa
         if (in.iterations == 0) break;  // no progress possible
         if (k == W.hist) k = 0;         // history full: restart the outer loop from x
         // u = A d (FP64), orthonormalised against U_0..U_{k-1}; d follows the same combination
-        HIP_CHECK(launch_apply(A->dev, W.d, W.w, 0, stream));
+        HIP_CHECK(op_apply(A, 0, W.d, W.w, stream));
         if (k > 0) {
             HIP_CHECK(solve_dots(cp, N, k, W.U, W.w, W.gpA, -1, W.npart, W.st, stream));
             HIP_CHECK(solve_update(cp, N, k, W.U, W.gpA, W.gh1, W.w, W.gpB, W.npart, 0, stream));
@@ -532,7 +567,7 @@ static int refine_one(bem_operator A, const void* b, void* x, const bem_solve_pa
         HIP_CHECK(solve_combine(cp, N, 1, Dj(k), W.gh1, 1.0, x, stream));
         ++k;
         // the FP64 residual of the new iterate
-        HIP_CHECK(launch_apply(A->dev, x, W.w, 0, stream));
+        HIP_CHECK(op_apply(A, 0, x, W.w, stream));
         HIP_CHECK(solve_residual(cp, N, b, W.w, W.npart, 0, stream));
         HIP_CHECK(hipMemcpyAsync(W.r, W.w, N * sc, hipMemcpyDeviceToDevice, stream));
         if (host_norm(rnorm) != BEM_OK) return BEM_EDEVICE;
@@ -886,7 +921,76 @@ void bem_geometry_destroy(bem_geometry g) { delete g; }
 static int need_device_geometry(const SpaceDesc& S) {
     if (S.geom.kind == GEOM_NURBS && !S.geom.tab_dev)
         return fail(BEM_EDEVICE, "NURBS geometry created without a GPU: no device copy of its tables");
+    if (S.form == 0 && !S.glue)
+        return fail(BEM_EDEVICE, "S^0 space created without a GPU: no device copy of its gluing");
     return BEM_OK;
+}
+
+// S^0 gluing (App. E: continuity across patch boundaries): every local B-spline is anchored
+// at the image of its Greville point; with clamped knots the functions that do not vanish
+// on a patch boundary have their anchors on it, and by the matching condition the functions
+// of neighbouring patches that coincide on a shared edge or vertex share their anchor.
+// Boundary anchors are sorted by their first coordinate; anchors that agree in all three
+// coordinates within 1e-10 of the largest coordinate are one global function (first local
+// occurrence numbers it).
+static bool build_glue(const SpaceDesc& S, GlueTab& T, int64_t& nglob) {
+    const int nb = S.nb, d = S.d;
+    std::vector<double> knots;
+    for (int i = 0; i <= d; ++i) knots.push_back(0.0);
+    for (int k = 1; k < S.nel; ++k)
+        for (int m = 0; m < S.r; ++m) knots.push_back((double)k / S.nel);
+    for (int i = 0; i <= d; ++i) knots.push_back(1.0);
+    std::vector<double> gr(nb);
+    for (int j = 0; j < nb; ++j) {
+        double a = 0.0;
+        for (int k = 1; k <= d; ++k) a += knots[j + k];
+        gr[j] = a / d;
+    }
+    struct Anchor {
+        double x[3];
+        int64_t g;
+    };
+    std::vector<Anchor> an;
+    double scale = 0.0;
+    for (int f = 0; f < S.geom.npatch; ++f)
+        for (int j1 = 0; j1 < nb; ++j1)
+            for (int j2 = 0; j2 < nb; ++j2) {
+                if (j1 != 0 && j1 != nb - 1 && j2 != 0 && j2 != nb - 1) continue;
+                Anchor a;
+                patch_point(S.geom, f, gr[j1], gr[j2], a.x);
+                a.g = dof_id(S, f, j1, j2);
+                for (double v : a.x) scale = std::max(scale, std::fabs(v));
+                an.push_back(a);
+            }
+    const double tol = 1e-10 * std::max(scale, 1e-300);
+    std::sort(an.begin(), an.end(), [](const Anchor& u, const Anchor& v) { return u.x[0] < v.x[0]; });
+    std::vector<int64_t> parent(S.ndof);
+    for (int64_t g = 0; g < S.ndof; ++g) parent[g] = g;
+    auto root = [&](int64_t g) {
+        while (parent[g] != g) g = parent[g] = parent[parent[g]];
+        return g;
+    };
+    for (size_t a = 0; a < an.size(); ++a)
+        for (size_t b = a + 1; b < an.size() && an[b].x[0] - an[a].x[0] <= tol; ++b)
+            if (std::fabs(an[a].x[1] - an[b].x[1]) <= tol && std::fabs(an[a].x[2] - an[b].x[2]) <= tol) {
+                const int64_t ra = root(an[a].g), rb = root(an[b].g);
+                if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+            }
+    std::vector<int64_t> gid(S.ndof, -1);
+    T.glue.resize(S.ndof);
+    nglob = 0;
+    for (int64_t g = 0; g < S.ndof; ++g) {
+        const int64_t r = root(g);
+        if (gid[r] < 0) gid[r] = nglob++;
+        T.glue[g] = (int32_t)gid[r];
+    }
+    T.ginv_ptr.assign(nglob + 1, 0);
+    for (int64_t g = 0; g < S.ndof; ++g) ++T.ginv_ptr[T.glue[g] + 1];
+    for (int64_t k = 0; k < nglob; ++k) T.ginv_ptr[k + 1] += T.ginv_ptr[k];
+    T.ginv_idx.resize(S.ndof);
+    std::vector<int64_t> fill(T.ginv_ptr.begin(), T.ginv_ptr.end() - 1);
+    for (int64_t g = 0; g < S.ndof; ++g) T.ginv_idx[fill[T.glue[g]]++] = (int32_t)g;  // ascending per global
+    return true;
 }
 
 // Checks and packs NURBS patches into a geometry (table in host and device memory).
@@ -1124,7 +1228,14 @@ int bem_geometry_user(int npatch, bem_user_map gamma, void* user, int degree, in
 
 int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
                      int level, bem_space* out) {
+    return bem_space_create_ex(g, kernel, kappa_re, kappa_im, degree, knot_repetition, level, BEM_SPACE_S2, out);
+}
+
+int bem_space_create_ex(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
+                        int level, int space_kind, bem_space* out) {
     if (!g || !out) return fail(BEM_EINVAL, "NULL argument");
+    if (space_kind != BEM_SPACE_S2 && space_kind != BEM_SPACE_S0) return fail(BEM_EINVAL, "unknown space kind");
+    if (space_kind == BEM_SPACE_S0 && degree < 1) return fail(BEM_EINVAL, "continuous spaces need degree >= 1");
     if (kernel != BEM_LAPLACE_SINGLE && kernel != BEM_HELMHOLTZ_SINGLE) return fail(BEM_EINVAL, "unknown kernel");
     if (degree < 0) return fail(BEM_EINVAL, "degree must be >= 0");
     if (level < 0 || level > 12) return fail(BEM_EINVAL, "level must lie in [0, 12]");
@@ -1147,10 +1258,36 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
     S.nelem = (int64_t)S.geom.npatch * S.nel * S.nel;
     S.ndof = (int64_t)S.geom.npatch * S.nb * S.nb;
     S.h = 1.0 / S.nel;
+    S.form = space_kind == BEM_SPACE_S0 ? 0 : 2;
+    S.nglob = S.ndof;
+    std::shared_ptr<GlueTab> glue;
+    if (space_kind == BEM_SPACE_S0) {
+        if (S.ndof > 0x7fffffff) return fail(BEM_EINVAL, "too many functions for an S^0 space");
+        glue = std::make_shared<GlueTab>();
+        build_glue(S, *glue, S.nglob);
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+            HIP_CHECK(hipMalloc((void**)&glue->d_glue, sizeof(int32_t) * glue->glue.size()));
+            HIP_CHECK(hipMalloc((void**)&glue->d_ptr, sizeof(int64_t) * glue->ginv_ptr.size()));
+            HIP_CHECK(hipMalloc((void**)&glue->d_idx, sizeof(int32_t) * glue->ginv_idx.size()));
+            HIP_CHECK(hipMemcpy(glue->d_glue, glue->glue.data(), sizeof(int32_t) * glue->glue.size(),
+                                hipMemcpyHostToDevice));
+            HIP_CHECK(hipMemcpy(glue->d_ptr, glue->ginv_ptr.data(), sizeof(int64_t) * glue->ginv_ptr.size(),
+                                hipMemcpyHostToDevice));
+            HIP_CHECK(hipMemcpy(glue->d_idx, glue->ginv_idx.data(), sizeof(int32_t) * glue->ginv_idx.size(),
+                                hipMemcpyHostToDevice));
+            S.glue = glue->d_glue;
+            S.ginv_ptr = glue->d_ptr;
+            S.ginv_idx = glue->d_idx;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     bem_space_s* sp = new (std::nothrow) bem_space_s;
     if (!sp) return fail(BEM_ENOMEM, "host allocation failed");
     sp->S = S;
     sp->tab = g->tab;
+    sp->glue = glue;
     if (!make_basis_tab(S, sp->bt)) {
         delete sp;
         return fail(BEM_EUNSUPPORTED, "element basis classes do not repeat for this knot vector");
@@ -1161,7 +1298,19 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
 
 int bem_space_ndof(bem_space s, int64_t* n) {
     if (!s || !n) return fail(BEM_EINVAL, "NULL argument");
-    *n = s->S.ndof;
+    *n = s->S.nglob;
+    return BEM_OK;
+}
+
+int bem_space_glue(bem_space s, int64_t* nlocal, int32_t* glue_host) {
+    if (!s || !nlocal) return fail(BEM_EINVAL, "NULL argument");
+    *nlocal = s->S.ndof;
+    if (glue_host) {
+        if (s->glue)
+            std::copy(s->glue->glue.begin(), s->glue->glue.end(), glue_host);
+        else
+            for (int64_t g = 0; g < s->S.ndof; ++g) glue_host[g] = (int32_t)g;
+    }
     return BEM_OK;
 }
 
@@ -1172,7 +1321,7 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
     if (!s || !data_params || !b_dev) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
-    if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
+    if (ldb < s->S.nglob) return fail(BEM_EINVAL, "ldb must be >= N");
     if (data_kind != BEM_DATA_POINT_SOURCE && data_kind != BEM_DATA_PLANE_WAVE)
         return fail(BEM_EINVAL, "unknown data kind");
     if (data_kind == BEM_DATA_PLANE_WAVE && s->S.ker.pde != PDE_HELMHOLTZ)
@@ -1197,7 +1346,7 @@ int bem_rhs_from_samples(bem_space s, const void* g_dev, int64_t ldg, int nrhs, 
     if (!s || !g_dev || !b_dev) return fail(BEM_EINVAL, "NULL argument");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
-    if (ldb < s->S.ndof) return fail(BEM_EINVAL, "ldb must be >= N");
+    if (ldb < s->S.nglob) return fail(BEM_EINVAL, "ldb must be >= N");
     if (ldg < s->S.nelem * 64) return fail(BEM_EINVAL, "ldg must be >= the number of quadrature points");
     const Gauss8 g8 = gauss8();
     const size_t sc = s->S.ker.pde == PDE_HELMHOLTZ ? 16 : 8;
@@ -1212,7 +1361,7 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
     if (!s || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
     if (npts == 0) return BEM_OK;
-    if (ldr < s->S.ndof || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
+    if (ldr < s->S.nglob || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
     const Gauss8 g8 = gauss8();
@@ -1238,6 +1387,8 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     if (p->far_low < 0 || p->far_low > 2) return fail(BEM_EINVAL, "far_low must be 0, BEM_PREC_FP32 or BEM_PREC_BF16");
     if (p->batch_rhs < 0 || p->batch_rhs > 4096) return fail(BEM_EINVAL, "batch_rhs must lie in [0, 4096]");
     if (p->batch_rhs > 1 && p->q > 6) return fail(BEM_EUNSUPPORTED, "many-RHS kernels need q <= 6");
+    if (s->S.form == 0 && (p->far_low != 0 || p->batch_rhs > 1))
+        return fail(BEM_EUNSUPPORTED, "S^0 spaces: one column at a time in FP64 (far_low = 0, batch_rhs <= 1)");
     H2Params P;
     P.chunk = p->chunk_cols != 0 ? p->chunk_cols : (p->far_eval ? 256 : 128);
     P.q = p->q;
@@ -1296,7 +1447,8 @@ int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, be
     for (size_t lp = 0; lp + 1 < pl.touch_rowptr.size(); ++lp)
         if (pl.touch_rowptr[lp + 1] > pl.touch_rowptr[lp]) A->touch_lp.push_back((int32_t)lp);
     bem_operator_info& I = A->info;
-    I.ndof = s->S.ndof;
+    I.ndof = s->S.nglob;
+    I.nlocal = s->S.ndof;
     I.nclusters = pl.ncl;
     I.nfar = (int64_t)pl.far_t.size();
     I.nnear = (int64_t)pl.near_t.size();
@@ -1409,6 +1561,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     // coupling rows are padded to even length: clear them before the blocks are written
     if (p.ktotal > 0 && d.K) HIP_CHECK(hipMemsetAsync(d.K, 0, (size_t)p.ktotal * A->scal, stream));
     HIP_CHECK(launch_gauss_points(d, as, stream));
+    HIP_CHECK(launch_leaf_tables0(d, as, stream));
     HIP_CHECK(launch_near_regular(d, as, stream));
     HIP_CHECK(launch_near_singular(d, as, stream));
     HIP_CHECK(launch_near_gather(d, as, stream));
@@ -1498,7 +1651,7 @@ int bem_apply_ex(bem_operator A, int prec, const void* x_dev, int64_t ldx, void*
         const void* xr = xb + (size_t)r * ldx * A->scal;
         void* yr = yb + (size_t)r * ldy * A->scal;
         if (!A->prof) {
-            HIP_CHECK(launch_apply(A->dev, xr, yr, prec, stream));
+            HIP_CHECK(op_apply(A, prec, xr, yr, stream));
             continue;
         }
         const size_t need = A->ev_used + kApplyStages + 1;
@@ -1523,11 +1676,13 @@ int bem_apply_stage(bem_operator A, int prec, int stage, const void* x_dev, void
     if (prec != BEM_PREC_FP64 && prec != A->far_low)
         return fail(BEM_EINVAL, "precision not available (assemble with far_low set to it)");
     if (stage < 0 || stage >= kApplyStages) return fail(BEM_EINVAL, "stage must lie in [0, 4)");
+    if (A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "single stages need an S^2 space");
     HIP_CHECK(launch_apply_stage(A->dev, stage, x_dev, y_dev, prec, stream));
     return BEM_OK;
 }
 
 int bem_profile_enable(bem_operator A, int on) {
+    if (A && A->plan.S.form == 0 && on) return fail(BEM_EUNSUPPORTED, "stage timing needs an S^2 space");
     if (!A) return fail(BEM_EINVAL, "NULL argument");
     A->prof = on != 0;
     A->ev_used = 0;
@@ -1564,6 +1719,7 @@ static int64_t prec_tiles(const bem_operator_s& A, int* nt) {
 }
 
 int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes) {
+    if (A && A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
     if (!A || !ntiles || !ws_bytes) return fail(BEM_EINVAL, "NULL argument");
     *ntiles = prec_tiles(*A, nullptr);
     OpDev d{};
@@ -1574,6 +1730,7 @@ int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes) {
 }
 
 int bem_precond_build(bem_operator A, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (A && A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
     if (!A || !ws) return fail(BEM_EINVAL, "NULL argument");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     int nt = 0;
@@ -1904,6 +2061,10 @@ int bem_group_create(int nops, const bem_operator* ops, const int* ncols, bem_gr
             delete G;
             return fail(BEM_EINVAL, "every operator must be assembled and have >= 1 column");
         }
+        if (ops[i]->plan.S.form == 0) {
+            delete G;
+            return fail(BEM_EUNSUPPORTED, "grouped launches need S^2 spaces");
+        }
         const int c = ops[i]->cplx ? 1 : 0, q = ops[i]->plan.P.q;
         if (i == 0) {
             G->cplx = c;
@@ -2077,8 +2238,9 @@ int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int 
     if (nrhs < 0 || nrhs > 64) return fail(BEM_EINVAL, "nrhs must lie in [0, 64]");
     if (nsub < 1 || nsub > 64) return fail(BEM_EINVAL, "nsub must lie in [1, 64]");
     const SpaceDesc& S = s->S;
-    if (nrhs > 0 && ldr < S.ndof) return fail(BEM_EINVAL, "ldr must be >= N");
+    if (nrhs > 0 && ldr < S.nglob) return fail(BEM_EINVAL, "ldr must be >= N");
     const bool cplx = S.ker.pde == PDE_HELMHOLTZ;
+    const int32_t* glue = s->glue ? s->glue->glue.data() : nullptr;  // S^0: local -> global
     const int np1 = nsub + 1;
     const int64_t npe = (int64_t)np1 * np1;
     const int64_t npts = S.nelem * npe, ncell = S.nelem * nsub * nsub;
@@ -2118,7 +2280,8 @@ int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int 
                     for (int l1 = 0; l1 <= S.d; ++l1)
                         for (int l2 = 0; l2 <= S.d; ++l2) {
                             const double phi = basis_eval(s->bt, ca, l1, u1) * basis_eval(s->bt, cb, l2, u2);
-                            const int64_t g = dof_id(S, f, i1 * S.r + l1, i2 * S.r + l2) + (int64_t)r * ldr;
+                            const int64_t loc = dof_id(S, f, i1 * S.r + l1, i2 * S.r + l2);
+                            const int64_t g = (glue ? glue[loc] : loc) + (int64_t)r * ldr;
                             if (cplx) {
                                 re += phi * ((const double*)rho_host)[2 * g];
                                 im += phi * ((const double*)rho_host)[2 * g + 1];
@@ -2126,10 +2289,11 @@ int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int 
                                 re += phi * ((const double*)rho_host)[g];
                             }
                         }
-                    // 2-form lifting: the density on the surface is rho_hat / kappa
+                    // 2-form lifting: the density on the surface is rho_hat / kappa; 0-form: rho_hat
+                    const double sc = S.form == 0 ? 1.0 : 1.0 / kap[k];
                     const size_t o = ((size_t)r * npts + k) * (cplx ? 2 : 1);
-                    val[o] = re / kap[k];
-                    if (cplx) val[o + 1] = im / kap[k];
+                    val[o] = re * sc;
+                    if (cplx) val[o + 1] = im * sc;
                 }
             }
     }
@@ -2168,7 +2332,12 @@ int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, c
     const Gauss8 g8 = gauss8();
     for (int r = 0; r < nrhs; ++r) {
         const char* rho = (const char*)rho_dev + (size_t)r * ldr * A->scal;
-        HIP_CHECK(launch_moments(A->dev, rho, stream));
+        if (A->dev.S.form == 0) {  // the moments of the local functions
+            HIP_CHECK(launch_glue_gather(A->dev.S, A->cplx ? 1 : 0, rho, A->dev.xl, stream));
+            HIP_CHECK(launch_moments(A->dev, A->dev.xl, stream));
+        } else {
+            HIP_CHECK(launch_moments(A->dev, rho, stream));
+        }
         HIP_CHECK(launch_potential_tree(A->dev, g8, eta, pts_dev, npts, rho, (char*)u_dev + (size_t)r * ldu * A->scal,
                                         stream));
     }
@@ -2178,7 +2347,12 @@ int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, c
 int bem_export_moments(bem_operator A, const void* x_dev, double* mom_host, hipStream_t stream) {
     if (!A || !x_dev || !mom_host) return fail(BEM_EINVAL, "NULL argument");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
-    HIP_CHECK(launch_moments(A->dev, x_dev, stream));
+    if (A->dev.S.form == 0) {
+        HIP_CHECK(launch_glue_gather(A->dev.S, A->cplx ? 1 : 0, x_dev, A->dev.xl, stream));
+        HIP_CHECK(launch_moments(A->dev, A->dev.xl, stream));
+    } else {
+        HIP_CHECK(launch_moments(A->dev, x_dev, stream));
+    }
     HIP_CHECK(hipMemcpyAsync(mom_host, A->dev.mom, (size_t)A->plan.ncl * A->plan.q2 * A->scal, hipMemcpyDeviceToHost,
                              stream));
     HIP_CHECK(hipStreamSynchronize(stream));

@@ -192,6 +192,99 @@ __host__ __device__ inline void patch_point(const GeomDesc& g, int f, double s, 
     }
 }
 
+// Surface element |d_s gamma x d_t gamma| of a NURBS patch at (s, t): the derivatives of
+// the p + 1 basis functions of a span follow from the p functions of degree p - 1,
+// d/dx b_j^p = p (b_j^{p-1} / (xi_{j+p} - xi_j) - b_{j+1}^{p-1} / (xi_{j+p+1} - xi_{j+1})),
+// and the map's derivatives from the quotient rule.
+__host__ __device__ inline void nurbs_dfuns(const double* xi, int p, int mu, double x, double* N, double* dN) {
+    nurbs_funs(xi, p, mu, x, N);
+    if (p == 0) {
+        dN[0] = 0.0;
+        return;
+    }
+    double Nm[kNurbsMaxDeg + 1];
+    nurbs_funs(xi, p - 1, mu, x, Nm);  // Nm[k] = b_{mu-p+1+k}^{p-1}
+    for (int r = 0; r <= p; ++r) {
+        double v = 0.0;
+        if (r >= 1) v += Nm[r - 1] / (xi[mu + r] - xi[mu - p + r]);
+        if (r <= p - 1) v -= Nm[r] / (xi[mu + r + 1] - xi[mu - p + r + 1]);
+        dN[r] = p * v;
+    }
+}
+
+__host__ __device__ __attribute__((noinline)) inline double nurbs_kappa(const double* tab, int f, double s,
+                                                                       double t) {
+    const double* h = tab + 1 + 6 * f;
+    const int p1 = (int)h[0], p2 = (int)h[1], k1 = (int)h[2], k2 = (int)h[3];
+    const double* xi1 = tab + (int64_t)h[4];
+    const double* xi2 = xi1 + k1 + p1 + 1;
+    const double* cw = tab + (int64_t)h[5];
+    const int m1 = nurbs_span(xi1, p1, k1, s), m2 = nurbs_span(xi2, p2, k2, t);
+    double N1[kNurbsMaxDeg + 1], N2[kNurbsMaxDeg + 1], D1[kNurbsMaxDeg + 1], D2[kNurbsMaxDeg + 1];
+    nurbs_dfuns(xi1, p1, m1, s, N1, D1);
+    nurbs_dfuns(xi2, p2, m2, t, N2, D2);
+    double A[3] = {0, 0, 0}, As[3] = {0, 0, 0}, At[3] = {0, 0, 0}, W = 0.0, Ws = 0.0, Wt = 0.0;
+    for (int i = 0; i <= p1; ++i)
+        for (int j = 0; j <= p2; ++j) {
+            const double* c = cw + 4 * ((int64_t)(m1 - p1 + i) * k2 + (m2 - p2 + j));
+            const double v = N1[i] * N2[j] * c[3], vs = D1[i] * N2[j] * c[3], vt = N1[i] * D2[j] * c[3];
+            for (int d = 0; d < 3; ++d) {
+                A[d] += v * c[d];
+                As[d] += vs * c[d];
+                At[d] += vt * c[d];
+            }
+            W += v;
+            Ws += vs;
+            Wt += vt;
+        }
+    double xs[3], xt[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x = A[d] / W;
+        xs[d] = (As[d] - x * Ws) / W;
+        xt[d] = (At[d] - x * Wt) / W;
+    }
+    const double n0 = xs[1] * xt[2] - xs[2] * xt[1], n1 = xs[2] * xt[0] - xs[0] * xt[2], n2 = xs[0] * xt[1] - xs[1] * xt[0];
+    return sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+}
+
+// Surface element kappa_f(s, t) = |d_s gamma_f x d_t gamma_f| of every patch kind, from the
+// maps' derivatives (the 0-form lifting multiplies every surface integral by it).
+__host__ __device__ inline double patch_kappa(const GeomDesc& g, int f, double s, double t) {
+    if (g.kind == GEOM_SPHERE6 || g.kind == GEOM_ELLIPSOID6) {
+        int iu, iv, ic;
+        double cv;
+        cube_face_layout(f, iu, iv, ic, cv);
+        double c[3];
+        c[iu] = 2.0 * s - 1.0;
+        c[iv] = 2.0 * t - 1.0;
+        c[ic] = cv;
+        const double rr = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        const double n[3] = {c[0] / rr, c[1] / rr, c[2] / rr};
+        // d(c/|c|)/ds = (dc/ds - n (n . dc/ds)) / |c| with dc/ds = 2 e_iu (and e_iv for t)
+        double xs[3], xt[3];
+        const double sc[3] = {g.kind == GEOM_SPHERE6 ? 1.0 : g.a, g.kind == GEOM_SPHERE6 ? 1.0 : g.b,
+                              g.kind == GEOM_SPHERE6 ? 1.0 : g.c};
+        for (int d = 0; d < 3; ++d) {
+            xs[d] = sc[d] * 2.0 * ((d == iu ? 1.0 : 0.0) - n[d] * n[iu]) / rr;
+            xt[d] = sc[d] * 2.0 * ((d == iv ? 1.0 : 0.0) - n[d] * n[iv]) / rr;
+        }
+        const double n0 = xs[1] * xt[2] - xs[2] * xt[1], n1 = xs[2] * xt[0] - xs[0] * xt[2],
+                     n2 = xs[0] * xt[1] - xs[1] * xt[0];
+        return sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    } else if (g.kind == GEOM_TORUS16) {
+        // d_s gamma and d_t gamma are orthogonal, of lengths pi/2 (R + r cos v) and pi/2 r
+        const double v = 0.5 * kPi * ((f & 3) + t);
+        return 0.25 * kPi * kPi * g.b * (g.a + g.b * cos(v));
+    } else if (g.kind == GEOM_NURBS) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        return nurbs_kappa(g.tab_dev, f, s, t);
+#else
+        return nurbs_kappa(g.tab_host, f, s, t);
+#endif
+    }
+    return g.a * g.a;
+}
+
 // ------------------------------------------------------------------ single-layer kernels
 enum PdeKind : int { PDE_LAPLACE = 0, PDE_HELMHOLTZ = 1 };
 
@@ -221,8 +314,18 @@ struct SpaceDesc {
     KernelDesc ker;
     int d, r, L;       // degree, knot repetition, level
     int nel, nb;       // elements and B-splines per direction
-    int64_t nelem, ndof;
+    int64_t nelem, ndof;  // ndof: local functions (patch by patch)
     double h;          // element width 2^-L
+    // Lifting to the surface: 2 for S^2 (2-form: the surface element cancels), 0 for S^0
+    // (0-form: every surface integral carries kappa), whose local functions are glued across
+    // patch boundaries into nglob global ones: glue[local] = global (device), and the local
+    // functions of global g are ginv_idx[ginv_ptr[g] .. ginv_ptr[g+1]) (device).  S^2:
+    // nglob = ndof and no maps.
+    int form;
+    int64_t nglob;
+    const int32_t* glue;
+    const int64_t* ginv_ptr;
+    const int32_t* ginv_idx;
 };
 
 __host__ __device__ inline int64_t dof_id(const SpaceDesc& S, int f, int j1, int j2) {

@@ -76,6 +76,9 @@ struct OpDev {
     const double* ball;  // [ncl][4]: centre and radius of every cluster (admissibility)
     // transforms
     const double* V1;  // [nleaf1][q][nloc]
+    const double* Vd;  // 0-form lifting: [nleaves][q*q][nloc*nloc] full leaf tables (else null)
+    void* xl;          // S^0: the applied vector on the local functions (and the product)
+    void* yl;
     const double* E;   // [2][q][q]
     // matvec scratch: moments and local expansions of all clusters (one RHS)
     void* mom;
@@ -102,6 +105,7 @@ struct AsmDev {
     const int32_t* vid;
     const double* gx;     // [qg]
     const double* gpos;   // [nelem][qg*qg][3]
+    const double* gkap;   // [nelem][qg*qg] surface element at the Gauss points (0-form lifting only)
     const double* psi;    // [nel][qg][d+1]
     const double* gw;     // [qg]
     const double* sx;     // [qs]
@@ -113,6 +117,10 @@ struct AsmDev {
 };
 
 hipError_t launch_gauss_points(const OpDev& op, const AsmDev& as, hipStream_t st);
+hipError_t launch_leaf_tables0(const OpDev& op, const AsmDev& as, hipStream_t st);
+// S^0: x_loc[i] = x[glue[i]] and y[g] = sum of y_loc over the local functions of g
+hipError_t launch_glue_gather(const SpaceDesc& S, int cplx, const void* x, void* x_loc, hipStream_t st);
+hipError_t launch_glue_scatter(const SpaceDesc& S, int cplx, const void* y_loc, void* y, hipStream_t st);
 hipError_t launch_near_regular(const OpDev& op, const AsmDev& as, hipStream_t st);
 hipError_t launch_near_singular(const OpDev& op, const AsmDev& as, hipStream_t st);
 hipError_t launch_near_gather(const OpDev& op, const AsmDev& as, hipStream_t st);

@@ -75,18 +75,21 @@ __device__ inline void duffy_point(int type, int reg, double xi, double e1, doub
 }
 
 // ------------------------------------------------------------------ geometry tables
-__global__ void k_gauss_points(SpaceDesc S, int qg, const double* __restrict__ gx, double* __restrict__ gpos) {
+__global__ void k_gauss_points(SpaceDesc S, int qg, const double* __restrict__ gx, double* __restrict__ gpos,
+                               double* __restrict__ gkap) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int qg2 = qg * qg;
     if (idx >= S.nelem * qg2) return;
     const int a = (int)(idx % qg2);
     const int64_t e = idx / qg2;
     const int i2 = (int)(e % S.nel), i1 = (int)((e / S.nel) % S.nel), f = (int)(e / ((int64_t)S.nel * S.nel));
+    const double ps = (i1 + gx[a / qg]) * S.h, pt = (i2 + gx[a % qg]) * S.h;
     double x[3];
-    patch_point(S.geom, f, (i1 + gx[a / qg]) * S.h, (i2 + gx[a % qg]) * S.h, x);
+    patch_point(S.geom, f, ps, pt, x);
     gpos[3 * idx] = x[0];
     gpos[3 * idx + 1] = x[1];
     gpos[3 * idx + 2] = x[2];
+    if (gkap) gkap[idx] = patch_kappa(S.geom, f, ps, pt);  // 0-form lifting only
 }
 
 // ------------------------------------------------------------------ near field: regular pairs
@@ -150,6 +153,7 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
                 const double* yp = as.gpos + e2 * qg2 * 3;
                 const double* p1 = as.psi + (int64_t)fi1 * qg * D1;
                 const double* p2 = as.psi + (int64_t)fi2 * qg * D1;
+                const double* yk = as.gkap ? as.gkap + e2 * qg2 : nullptr;  // 0-form: kappa(y)
                 for (int b1 = 0; b1 < qg; ++b1) {
                     T sacc[D1];
 #pragma unroll
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
                         const double* y = yp + (b1 * qg + b2) * 3;
                         const double dx = xa0 - y[0], dy = xa1 - y[1], dz = xa2 - y[2];
                         const T kv = kernel_val(kd, dx * dx + dy * dy + dz * dz, T());
-                        const double wb = as.gw[b2];
+                        const double wb = yk ? as.gw[b2] * yk[b1 * qg + b2] : as.gw[b2];
 #pragma unroll
                         for (int l = 0; l < D1; ++l) sacc[l] += kv * (wb * p2[b2 * D1 + l]);
                     }
@@ -179,9 +183,11 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
                 for (int t = lane; t < NB * NB; t += kWave) {
                     const int i = t / NB, j = t % NB, k1 = i / D1, k2 = i % D1;
                     T B = zero<T>();
+                    const double* xk = as.gkap ? as.gkap + e * qg2 + chunk : nullptr;  // 0-form: kappa(x)
                     for (int aa = 0; aa < amax; ++aa) {
                         const int ag = chunk + aa, a1 = ag / qg, a2 = ag % qg;
-                        B += (as.gw[a1] * q1[a1 * D1 + k1] * as.gw[a2] * q2[a2 * D1 + k2]) * myTB[aa * NB + j];
+                        const double wa = as.gw[a1] * q1[a1 * D1 + k1] * as.gw[a2] * q2[a2 * D1 + k2];
+                        B += (xk ? wa * xk[aa] : wa) * myTB[aa * NB + j];
                     }
                     const int r1 = (et / m) * S.r + k1, r2 = (et % m) * S.r + k2;
                     const int c1 = (es / m) * S.r + j / D1, c2 = (es % m) * S.r + j % D1;
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
 // integrated one after the other (all 256 threads share the Duffy cube points of a pair),
 // each block reduced over the workgroup and added to the leaf-pair block in a fixed order.
 // ROWS rows of the element-pair block are accumulated per pass to bound registers.
-template <class T, int D, int ROWS>
+template <class T, int D, int ROWS, int FORM>
 __global__ __launch_bounds__(256) void k_near_singular(OpDev op, AsmDev as) {
     constexpr int D1 = D + 1, NB = D1 * D1;
     __shared__ T red[4][ROWS * NB];
@@ -246,12 +252,15 @@ __global__ __launch_bounds__(256) void k_near_singular(OpDev op, AsmDev as) {
                 const int i1 = rem % qs, i0 = rem / qs;
                 double xh1, xh2, yh1, yh2, jac;
                 duffy_point(type, reg, as.sx[i0], as.sx[i1], as.sx[i2], as.sx[i3], xh1, xh2, yh1, yh2, jac);
-                const double wq = as.sw[i0] * as.sw[i1] * as.sw[i2] * as.sw[i3] * jac * h4;
+                double wq = as.sw[i0] * as.sw[i1] * as.sw[i2] * as.sw[i3] * jac * h4;
                 double u1, u2, w1, w2, X[3], Y[3];
                 d4_apply(k1, xh1, xh2, u1, u2);
                 d4_apply(k2, yh1, yh2, w1, w2);
                 patch_point(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h, X);
                 patch_point(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h, Y);
+                if (FORM == 0)  // 0-form lifting: both surface elements
+                    wq *= patch_kappa(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h) *
+                          patch_kappa(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h);
                 double pa[D1], pb[D1], qa[D1], qb[D1];
 #pragma unroll
                 for (int l = 0; l < D1; ++l) {
@@ -431,6 +440,57 @@ __device__ inline void wave_reduce_scatter(T* v, int lane, int& idx, bool& ok) {
     ok = real > 0;
 }
 
+// ------------------------------------------------------------------ 0-form leaf tables
+// Lagrange basis polynomial a of the q nodes at y (product form)
+__device__ inline double lagrange_dev(const double* nodes, int q, int a, double y) {
+    double v = 1.0;
+    for (int b = 0; b < q; ++b)
+        if (b != a) v *= (y - nodes[b]) / (nodes[a] - nodes[b]);
+    return v;
+}
+
+// Vd[leaf][a][m1 nloc + m2] = integral over the leaf of L_a1 L_a2 b_{first1+m1} b_{first2+m2} kappa,
+// by the qg x qg Gauss rule of the regular near field on every element (points, weights,
+// basis values and kappa from its tables), one block per leaf, the leaf's elements one after
+// the other (the map from a thread to its (a, l1, l2) entries does not depend on the element,
+// so each entry is only ever added to by one thread).
+template <int Q>
+__global__ __launch_bounds__(256) void k_leaf_tables0(OpDev op, AsmDev as, double* __restrict__ Vd) {
+    constexpr int Q2 = Q * Q;
+    __shared__ double wk[256], L1[256][Q], L2[256][Q], B1[256][3], B2[256][3];
+    const SpaceDesc& S = op.S;
+    const int n1 = op.nleaf1, m = op.m, nloc = op.nloc, D1 = S.d + 1, r = S.r, qg = op.qg, qg2 = qg * qg;
+    const int64_t leaf = blockIdx.x;
+    const int j = (int)(leaf % n1), i = (int)((leaf / n1) % n1), f = (int)(leaf / ((int64_t)n1 * n1));
+    double* V = Vd + leaf * Q2 * nloc * nloc;
+    for (int t = threadIdx.x; t < Q2 * nloc * nloc; t += blockDim.x) V[t] = 0.0;
+    for (int e = 0; e < m * m; ++e) {
+        const int e1 = e / m, e2 = e % m, ei1 = i * m + e1, ei2 = j * m + e2;
+        const int64_t eid = elem_id(S, f, ei1, ei2);
+        __syncthreads();
+        for (int pq = threadIdx.x; pq < qg2; pq += blockDim.x) {
+            const int a1 = pq / qg, a2 = pq % qg;
+            wk[pq] = as.gw[a1] * as.gw[a2] * S.h * S.h * as.gkap[eid * qg2 + pq];
+            const double sl = (e1 + as.gx[a1]) / m, tl = (e2 + as.gx[a2]) / m;
+            for (int a = 0; a < Q; ++a) {
+                L1[pq][a] = lagrange_dev(as.cheb, Q, a, sl);
+                L2[pq][a] = lagrange_dev(as.cheb, Q, a, tl);
+            }
+            for (int l = 0; l < D1; ++l) {
+                B1[pq][l] = as.psi[((int64_t)ei1 * qg + a1) * D1 + l];
+                B2[pq][l] = as.psi[((int64_t)ei2 * qg + a2) * D1 + l];
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < Q2 * D1 * D1; t += blockDim.x) {
+            const int a = t / (D1 * D1), l = t % (D1 * D1), a1 = a / Q, a2 = a % Q, l1 = l / D1, l2 = l % D1;
+            double acc = 0.0;
+            for (int pq = 0; pq < qg2; ++pq) acc += wk[pq] * L1[pq][a1] * L2[pq][a2] * B1[pq][l1] * B2[pq][l2];
+            V[(int64_t)a * nloc * nloc + (e1 * r + l1) * nloc + (e2 * r + l2)] += acc;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ H^2 matvec
 // Stage 0.  Blocks [0, nup): forward transform of the leaves of one subtree rooted at level
 // up_root and upward transfer inside it (LDS).  Blocks [nup, ...): near-field product
@@ -446,7 +506,6 @@ __device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict_
     const int nr = 1 << r0, w = 1 << s;  // roots per direction, leaves per root direction
     const int f = blk / (nr * nr), loc = blk % (nr * nr), ri = loc / nr, rj = loc % nr;
     const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
-    (void)n1;
     // LDS slots of the subtree: depth-2 clusters (16) at 0, depth-1 (4) at 16, root at 20
     const int lb = s == 2 ? 0 : (s == 1 ? 16 : 20);
     // the coefficients under the subtree's leaves form an E x E square; when it fits, it
@@ -471,7 +530,15 @@ __device__ inline void up_subtree(const OpDev& op, int blk, const T* __restrict_
         const double* Vi = op.V1 + ((int64_t)i * Q + a1) * nloc;
         const double* Vj = op.V1 + ((int64_t)j * Q + a2) * nloc;
         T acc = zero<T>();
-        if (staged) {
+        if (op.Vd) {
+            // 0-form lifting: the leaf's full table (the surface element does not separate)
+            const double* V = op.Vd + (((int64_t)f * n1 + i) * n1 + j) * Q2 * nloc * nloc + (int64_t)a * nloc * nloc;
+            for (int m1 = 0; m1 < nloc; ++m1)
+                for (int m2 = 0; m2 < nloc; ++m2)
+                    acc += V[m1 * nloc + m2] *
+                           (staged ? xs[((l / w) * stride + m1) * E + (l % w) * stride + m2]
+                                   : x[dof_id(op.S, f, i * stride + m1, j * stride + m2)]);
+        } else if (staged) {
             const T* xl = xs + (l / w) * stride * E + (l % w) * stride;
 #pragma unroll 2
             for (int m1 = 0; m1 < nloc; ++m1) {
@@ -1106,6 +1173,13 @@ __device__ inline void down_back_body(const OpDev& op, int64_t blk_, T* __restri
         for (int li = lo1; li <= hi1; ++li)
             for (int lj = lo2; lj <= hi2; ++lj) {
                 const T* L = vbuf[cur][(li - i0) * wj + (lj - j0)];
+                if (op.Vd) {  // 0-form lifting: the leaf's full table
+                    const double* V = op.Vd + (((int64_t)f * n1 + li) * n1 + lj) * Q2 * nloc * nloc +
+                                      (jj1 - li * stride) * nloc + (jj2 - lj * stride);
+#pragma unroll
+                    for (int a = 0; a < Q2; ++a) acc += V[(int64_t)a * nloc * nloc] * L[a];
+                    continue;
+                }
                 const double* Vi = op.V1 + (int64_t)li * Q * nloc + (jj1 - li * stride);
                 const double* Vj = op.V1 + (int64_t)lj * Q * nloc + (jj2 - lj * stride);
 #pragma unroll
@@ -1149,31 +1223,53 @@ __device__ inline cdbl data_value<cdbl>(int kind, const KernelDesc& kd, double p
     return {mag * c, -mag * s};
 }
 
-// b_g = sum over the elements of supp(g) of 8x8 Gauss sums of g(x) phi_g; one wave per DOF
+// Local functions of global function G: itself (S^2) or its glued ones (S^0)
+__device__ inline void glue_range(const SpaceDesc& S, int64_t G, int64_t& k0, int64_t& k1) {
+    if (S.ginv_ptr) {
+        k0 = S.ginv_ptr[G];
+        k1 = S.ginv_ptr[G + 1];
+    } else {
+        k0 = G;
+        k1 = G + 1;
+    }
+}
+__device__ inline int64_t glue_local(const SpaceDesc& S, int64_t k) { return S.ginv_ptr ? S.ginv_idx[k] : k; }
+__device__ inline int64_t glue_global(const SpaceDesc& S, int64_t g) { return S.glue ? S.glue[g] : g; }
+
+// b_G = sum over the local functions g of G (S^0: the glued ones, in ascending order) and the
+// elements of supp(g) of 8x8 Gauss sums of g(x) phi_g (times kappa for the 0-form lifting);
+// one wave per global function
 template <class T>
 __global__ __launch_bounds__(256) void k_rhs(SpaceDesc S, BasisTab bt, Gauss8 g8, int kind, double p0, double p1,
                                              double p2, T* b) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t G = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (g >= S.ndof) return;
+    if (G >= S.nglob) return;
     const int nb = S.nb, d = S.d, r = S.r;
-    const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
     const int a1 = lane >> 3, a2 = lane & 7;
     T acc = zero<T>();
-    const int i1lo = j1 - d <= 0 ? 0 : (j1 - d + r - 1) / r, i1hi = min(j1 / r, S.nel - 1);
-    const int i2lo = j2 - d <= 0 ? 0 : (j2 - d + r - 1) / r, i2hi = min(j2 / r, S.nel - 1);
-    for (int i1 = i1lo; i1 <= i1hi; ++i1)
-        for (int i2 = i2lo; i2 <= i2hi; ++i2) {
-            const int l1 = j1 - i1 * r, l2 = j2 - i2 * r;
-            if (l1 > d || l2 > d) continue;
-            double x[3];
-            patch_point(S.geom, f, (i1 + g8.x[a1]) * S.h, (i2 + g8.x[a2]) * S.h, x);
-            const double phi = basis_eval(bt, basis_class(bt, i1), l1, g8.x[a1]) *
-                               basis_eval(bt, basis_class(bt, i2), l2, g8.x[a2]);
-            acc += data_value<T>(kind, S.ker, p0, p1, p2, x) * (g8.w[a1] * g8.w[a2] * S.h * S.h * phi);
-        }
+    int64_t k0, k1;
+    glue_range(S, G, k0, k1);
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t g = glue_local(S, k);
+        const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
+        const int i1lo = j1 - d <= 0 ? 0 : (j1 - d + r - 1) / r, i1hi = min(j1 / r, S.nel - 1);
+        const int i2lo = j2 - d <= 0 ? 0 : (j2 - d + r - 1) / r, i2hi = min(j2 / r, S.nel - 1);
+        for (int i1 = i1lo; i1 <= i1hi; ++i1)
+            for (int i2 = i2lo; i2 <= i2hi; ++i2) {
+                const int l1 = j1 - i1 * r, l2 = j2 - i2 * r;
+                if (l1 > d || l2 > d) continue;
+                double x[3];
+                const double ps = (i1 + g8.x[a1]) * S.h, pt = (i2 + g8.x[a2]) * S.h;
+                patch_point(S.geom, f, ps, pt, x);
+                double phi = basis_eval(bt, basis_class(bt, i1), l1, g8.x[a1]) *
+                             basis_eval(bt, basis_class(bt, i2), l2, g8.x[a2]);
+                if (S.form == 0) phi *= patch_kappa(S.geom, f, ps, pt);
+                acc += data_value<T>(kind, S.ker, p0, p1, p2, x) * (g8.w[a1] * g8.w[a2] * S.h * S.h * phi);
+            }
+    }
     const T s = wave_sum(acc);
-    if (lane == 0) b[g] = s;
+    if (lane == 0) b[G] = s;
 }
 
 // The load vector's quadrature points: point e * 64 + 8 a1 + a2 is the Gauss point (a1, a2)
@@ -1196,25 +1292,31 @@ __global__ __launch_bounds__(256) void k_quadpoints(SpaceDesc S, Gauss8 g8, doub
 template <class T>
 __global__ __launch_bounds__(256) void k_rhs_samples(SpaceDesc S, BasisTab bt, Gauss8 g8, const T* __restrict__ gv,
                                                      T* b) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t G = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (g >= S.ndof) return;
+    if (G >= S.nglob) return;
     const int nb = S.nb, d = S.d, r = S.r;
-    const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
     const int a1 = lane >> 3, a2 = lane & 7;
     T acc = zero<T>();
-    const int i1lo = j1 - d <= 0 ? 0 : (j1 - d + r - 1) / r, i1hi = min(j1 / r, S.nel - 1);
-    const int i2lo = j2 - d <= 0 ? 0 : (j2 - d + r - 1) / r, i2hi = min(j2 / r, S.nel - 1);
-    for (int i1 = i1lo; i1 <= i1hi; ++i1)
-        for (int i2 = i2lo; i2 <= i2hi; ++i2) {
-            const int l1 = j1 - i1 * r, l2 = j2 - i2 * r;
-            if (l1 > d || l2 > d) continue;
-            const double phi = basis_eval(bt, basis_class(bt, i1), l1, g8.x[a1]) *
-                               basis_eval(bt, basis_class(bt, i2), l2, g8.x[a2]);
-            acc += gv[elem_id(S, f, i1, i2) * 64 + lane] * (g8.w[a1] * g8.w[a2] * S.h * S.h * phi);
-        }
+    int64_t k0, k1;
+    glue_range(S, G, k0, k1);
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t g = glue_local(S, k);
+        const int j2 = (int)(g % nb), j1 = (int)((g / nb) % nb), f = (int)(g / ((int64_t)nb * nb));
+        const int i1lo = j1 - d <= 0 ? 0 : (j1 - d + r - 1) / r, i1hi = min(j1 / r, S.nel - 1);
+        const int i2lo = j2 - d <= 0 ? 0 : (j2 - d + r - 1) / r, i2hi = min(j2 / r, S.nel - 1);
+        for (int i1 = i1lo; i1 <= i1hi; ++i1)
+            for (int i2 = i2lo; i2 <= i2hi; ++i2) {
+                const int l1 = j1 - i1 * r, l2 = j2 - i2 * r;
+                if (l1 > d || l2 > d) continue;
+                double phi = basis_eval(bt, basis_class(bt, i1), l1, g8.x[a1]) *
+                             basis_eval(bt, basis_class(bt, i2), l2, g8.x[a2]);
+                if (S.form == 0) phi *= patch_kappa(S.geom, f, (i1 + g8.x[a1]) * S.h, (i2 + g8.x[a2]) * S.h);
+                acc += gv[elem_id(S, f, i1, i2) * 64 + lane] * (g8.w[a1] * g8.w[a2] * S.h * S.h * phi);
+            }
+    }
     const T s = wave_sum(acc);
-    if (lane == 0) b[g] = s;
+    if (lane == 0) b[G] = s;
 }
 
 // u(x_p) = sum_e 8x8 Gauss sum of k(x_p, y) rho_hat(y); one workgroup per point
@@ -1239,8 +1341,9 @@ __global__ __launch_bounds__(256) void k_potential(SpaceDesc S, BasisTab bt, Gau
         for (int l1 = 0; l1 <= d; ++l1) {
             const double ba = basis_eval(bt, ca, l1, u1);
             for (int l2 = 0; l2 <= d; ++l2)
-                rh += (ba * basis_eval(bt, cb, l2, u2)) * rho[dof_id(S, f, i1 * r + l1, i2 * r + l2)];
+                rh += (ba * basis_eval(bt, cb, l2, u2)) * rho[glue_global(S, dof_id(S, f, i1 * r + l1, i2 * r + l2))];
         }
+        if (S.form == 0) rh = rh * patch_kappa(S.geom, f, (i1 + u1) * S.h, (i2 + u2) * S.h);
         const double dx = px - y[0], dy = py - y[1], dz = pz - y[2];
         acc += kernel_val(S.ker, dx * dx + dy * dy + dz * dz, T()) * rh * (g8.w[a >> 3] * g8.w[a & 7] * S.h * S.h);
     }
@@ -1303,8 +1406,10 @@ __global__ __launch_bounds__(256) void k_potential_tree(OpDev op, Gauss8 g8, dou
                         for (int l1 = 0; l1 <= d; ++l1) {
                             const double ba = basis_eval(op.bt, ca, l1, u1);
                             for (int l2 = 0; l2 <= d; ++l2)
-                                rh += (ba * basis_eval(op.bt, cb, l2, u2)) * rho[dof_id(S, f, i1 * r + l1, i2 * r + l2)];
+                                rh += (ba * basis_eval(op.bt, cb, l2, u2)) *
+                                      rho[glue_global(S, dof_id(S, f, i1 * r + l1, i2 * r + l2))];
                         }
+                        if (S.form == 0) rh = rh * patch_kappa(S.geom, f, (i1 + u1) * S.h, (i2 + u2) * S.h);
                         const double ex = px - y[0], ey = py - y[1], ez = pz - y[2];
                         acc += kernel_val(S.ker, ex * ex + ey * ey + ez * ez, T()) * rh * wq;
                     }
@@ -1392,10 +1497,66 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 }  // namespace
 
 // =========================================================================== launchers
+hipError_t launch_leaf_tables0(const OpDev& op, const AsmDev& as, hipStream_t st) {
+    if (!op.Vd || op.nleaves == 0) return hipSuccess;
+    if (op.qg * op.qg > 256 || op.S.d > 2) return hipErrorInvalidValue;  // the kernel's LDS tables
+    const dim3 g((unsigned)op.nleaves), b(256);
+    switch (op.q) {
+        case 1: hipLaunchKernelGGL(k_leaf_tables0<1>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 2: hipLaunchKernelGGL(k_leaf_tables0<2>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 3: hipLaunchKernelGGL(k_leaf_tables0<3>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 4: hipLaunchKernelGGL(k_leaf_tables0<4>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 5: hipLaunchKernelGGL(k_leaf_tables0<5>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 6: hipLaunchKernelGGL(k_leaf_tables0<6>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        case 7: hipLaunchKernelGGL(k_leaf_tables0<7>, g, b, 0, st, op, as, (double*)op.Vd); break;
+        default: hipLaunchKernelGGL(k_leaf_tables0<8>, g, b, 0, st, op, as, (double*)op.Vd); break;
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_glue_gather(int64_t n, const int32_t* __restrict__ glue,
+                                                     const T* __restrict__ x, T* __restrict__ xl) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) xl[i] = x[glue[i]];
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_glue_scatter(int64_t n, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ idx, const T* __restrict__ yl,
+                                                      T* __restrict__ y) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    T acc = zero<T>();
+    for (int64_t k = ptr[g]; k < ptr[g + 1]; ++k) acc += yl[idx[k]];  // ascending local order
+    y[g] = acc;
+}
+
+hipError_t launch_glue_gather(const SpaceDesc& S, int cplx, const void* x, void* x_loc, hipStream_t st) {
+    const dim3 g(nblk(S.ndof, 256));
+    if (cplx)
+        hipLaunchKernelGGL(k_glue_gather<cdbl>, g, dim3(256), 0, st, S.ndof, S.glue, (const cdbl*)x, (cdbl*)x_loc);
+    else
+        hipLaunchKernelGGL(k_glue_gather<double>, g, dim3(256), 0, st, S.ndof, S.glue, (const double*)x,
+                           (double*)x_loc);
+    return hipGetLastError();
+}
+
+hipError_t launch_glue_scatter(const SpaceDesc& S, int cplx, const void* y_loc, void* y, hipStream_t st) {
+    const dim3 g(nblk(S.nglob, 256));
+    if (cplx)
+        hipLaunchKernelGGL(k_glue_scatter<cdbl>, g, dim3(256), 0, st, S.nglob, S.ginv_ptr, S.ginv_idx,
+                           (const cdbl*)y_loc, (cdbl*)y);
+    else
+        hipLaunchKernelGGL(k_glue_scatter<double>, g, dim3(256), 0, st, S.nglob, S.ginv_ptr, S.ginv_idx,
+                           (const double*)y_loc, (double*)y);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauss_points(const OpDev& op, const AsmDev& as, hipStream_t st) {
     const int64_t n = op.S.nelem * op.qg * op.qg;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gauss_points, dim3(nblk(n, 256)), dim3(256), 0, st, op.S, op.qg, as.gx, (double*)as.gpos);
+    hipLaunchKernelGGL(k_gauss_points, dim3(nblk(n, 256)), dim3(256), 0, st, op.S, op.qg, as.gx, (double*)as.gpos,
+                       (double*)as.gkap);
     return hipGetLastError();
 }
 
@@ -1436,14 +1597,24 @@ hipError_t launch_near_singular(const OpDev& op, const AsmDev& as, hipStream_t s
     if (as.ntouch_lp == 0) return hipSuccess;
     const dim3 g((unsigned)as.ntouch_lp), b(256);
     const int d = op.S.d;
+    if (op.S.form == 0) {  // S^0 (degree >= 1)
+        if (op.cplx) {
+            if (d == 1) hipLaunchKernelGGL((k_near_singular<cdbl, 1, 4, 0>), g, b, 0, st, op, as);
+            else hipLaunchKernelGGL((k_near_singular<cdbl, 2, 5, 0>), g, b, 0, st, op, as);
+        } else {
+            if (d == 1) hipLaunchKernelGGL((k_near_singular<double, 1, 4, 0>), g, b, 0, st, op, as);
+            else hipLaunchKernelGGL((k_near_singular<double, 2, 9, 0>), g, b, 0, st, op, as);
+        }
+        return hipGetLastError();
+    }
     if (op.cplx) {
-        if (d == 0) hipLaunchKernelGGL((k_near_singular<cdbl, 0, 1>), g, b, 0, st, op, as);
-        else if (d == 1) hipLaunchKernelGGL((k_near_singular<cdbl, 1, 4>), g, b, 0, st, op, as);
-        else hipLaunchKernelGGL((k_near_singular<cdbl, 2, 5>), g, b, 0, st, op, as);
+        if (d == 0) hipLaunchKernelGGL((k_near_singular<cdbl, 0, 1, 2>), g, b, 0, st, op, as);
+        else if (d == 1) hipLaunchKernelGGL((k_near_singular<cdbl, 1, 4, 2>), g, b, 0, st, op, as);
+        else hipLaunchKernelGGL((k_near_singular<cdbl, 2, 5, 2>), g, b, 0, st, op, as);
     } else {
-        if (d == 0) hipLaunchKernelGGL((k_near_singular<double, 0, 1>), g, b, 0, st, op, as);
-        else if (d == 1) hipLaunchKernelGGL((k_near_singular<double, 1, 4>), g, b, 0, st, op, as);
-        else hipLaunchKernelGGL((k_near_singular<double, 2, 9>), g, b, 0, st, op, as);
+        if (d == 0) hipLaunchKernelGGL((k_near_singular<double, 0, 1, 2>), g, b, 0, st, op, as);
+        else if (d == 1) hipLaunchKernelGGL((k_near_singular<double, 1, 4, 2>), g, b, 0, st, op, as);
+        else hipLaunchKernelGGL((k_near_singular<double, 2, 9, 2>), g, b, 0, st, op, as);
     }
     return hipGetLastError();
 }
@@ -1573,7 +1744,7 @@ hipError_t launch_group_apply(const GroupDev& g, int cplx, int q, hipStream_t st
 
 hipError_t launch_rhs(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, int kind, const double* prm,
                       void* b, hipStream_t st) {
-    const dim3 g(nblk(S.ndof, 4)), blk(256);
+    const dim3 g(nblk(S.nglob, 4)), blk(256);
     if (S.ker.pde == PDE_HELMHOLTZ)
         hipLaunchKernelGGL(k_rhs<cdbl>, g, blk, 0, st, S, bt, g8, kind, prm[0], prm[1], prm[2], (cdbl*)b);
     else
@@ -1590,7 +1761,7 @@ hipError_t launch_quadpoints(const SpaceDesc& S, const Gauss8& g8, double* xyz, 
 
 hipError_t launch_rhs_samples(const SpaceDesc& S, const BasisTab& bt, const Gauss8& g8, const void* gv, void* b,
                               hipStream_t st) {
-    const dim3 g(nblk(S.ndof, 4)), blk(256);
+    const dim3 g(nblk(S.nglob, 4)), blk(256);
     if (S.ker.pde == PDE_HELMHOLTZ)
         hipLaunchKernelGGL(k_rhs_samples<cdbl>, g, blk, 0, st, S, bt, g8, (const cdbl*)gv, (cdbl*)b);
     else

@@ -316,3 +316,76 @@ def torch_free(a):
     import torch
 
     return torch.from_numpy(np.ascontiguousarray(a))
+
+
+@pytest.mark.parametrize("geom,prm,d,L", [(0, (), 1, 2), (0, (), 2, 3), (2, (1.0, 0.4), 2, 2), (1, (0.8, 1.1, 1.3), 1, 1),
+                                          (3, (1.7,), 2, 2)])
+def test_s0_gluing_equals_oracle(B, orc, geom, prm, d, L):
+    """The host gluing of a continuous space (App. E) equals the oracle's map, function by
+    function, and its count is the space's N."""
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=d, level=L, continuous=True)
+    So = orc.Space(geom, list(prm), orc.LAPLACE, 0.0, degree=d, level=L, form=0)
+    m, n = So.glue()
+    assert s.ndof == n and np.array_equal(s.glue(), m.astype(np.int32))
+    A = B.Operator(s, q=4, eta=1.6, leaf_level=min(L, 1), assemble=False)
+    assert A.ndof == n and A.info.nlocal == So.ndof
+    # the discontinuous space of the same geometry: the identity map
+    s2 = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=d, level=L)
+    assert s2.ndof == So.ndof and np.array_equal(s2.glue(), np.arange(So.ndof, dtype=np.int32))
+
+
+def test_s0_nurbs_gluing_equals_oracle(B, orc):
+    g = B.Geometry.nurbs(W.nurbs_torus(1.0, 0.4))
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=2, level=2, continuous=True)
+    So = orc.Space(4, W.nurbs_torus(1.0, 0.4), orc.LAPLACE, 0.0, degree=2, level=2, form=0)
+    m, n = So.glue()
+    assert s.ndof == n == 16 * 4 ** 2 + 32 * 4 + 16 and np.array_equal(s.glue(), m.astype(np.int32))
+
+
+def test_s0_argument_validation(B):
+    C = B._bem
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    with pytest.raises(C.BemError) as e:
+        B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=0, level=2, continuous=True)
+    assert e.value.code == C.BEM_EINVAL
+    h = ctypes.c_void_p()
+    assert C.lib.bem_space_create_ex(g.h, 0, 0.0, 0.0, 1, 1, 2, 7, ctypes.byref(h)) == C.BEM_EINVAL
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=2, continuous=True)
+    for kw in (dict(far_low=1), dict(far_low=2), dict(batch_rhs=8)):
+        with pytest.raises(C.BemError) as e:
+            B.Operator(s, q=4, eta=1.6, leaf_level=1, assemble=False, **kw)
+        assert e.value.code == C.BEM_EUNSUPPORTED, kw
+    B.Operator(s, q=4, eta=1.6, leaf_level=1, assemble=False, far_eval=True)
+
+
+def test_vtk_output_of_a_continuous_density(B, orc, tmp_path):
+    """S^0: the density written is rho_hat = sum over local functions of the coefficient of
+    their global function times the B-splines (no division by kappa), and it is continuous:
+    points shared by neighbouring patches carry the same value."""
+    L, d, nsub = 1, 2, 2
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=d, level=L, continuous=True)
+    rho = W.random_vector(W.rng(9, 41), s.ndof)
+    path = str(tmp_path / "s0.vtk")
+    s.write_vtk(path, torch_free(rho), nsub=nsub)
+    pts, cells, types, data = _read_vtk(path)
+    So = orc.Space(orc.SPHERE, [], orc.LAPLACE, 0.0, degree=d, level=L, form=0)
+    m, _ = So.glue()
+    nel, nb, np1 = 1 << L, (1 << L) + d, nsub + 1
+    k = 0
+    for e in range(So.nelem):
+        f, i1, i2 = e // (nel * nel), (e // nel) % nel, e % nel
+        st = np.array([[(i1 + a / nsub) / nel, (i2 + b / nsub) / nel] for a in range(np1) for b in range(np1)])
+        B1 = np.stack([orc.bspline(d, 1, L, j, st[:, 0]) for j in range(nb)], 1)
+        B2 = np.stack([orc.bspline(d, 1, L, j, st[:, 1]) for j in range(nb)], 1)
+        c = rho[m].reshape(-1, nb, nb)[f]
+        np.testing.assert_allclose(data["rho_0"][k:k + np1 * np1], np.einsum("pi,pj,ij->p", B1, B2, c), rtol=1e-12,
+                                   atol=1e-13)
+        k += np1 * np1
+    # continuity: equal points, equal values
+    order = np.lexsort(np.round(pts, 9).T)
+    ps, vs = pts[order], data["rho_0"][order]
+    same = np.all(np.abs(np.diff(ps, axis=0)) <= 1e-12, axis=1)
+    assert same.sum() > 0
+    assert np.max(np.abs(np.diff(vs)[same])) <= 1e-12 * np.max(np.abs(vs))
