@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--only-main", action="store_true", help="main workload matvec only (for profiling)")
+    ap.add_argument("--only-c2", action="store_true", help="many-RHS Helmholtz matvecs only (for profiling)")
     ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
     ap.add_argument("--no-cpu-legs", action="store_true", help="skip the oracle's timings of the other workloads")
     return ap.parse_args()
@@ -470,6 +471,10 @@ def main():
     cfg = W.CONFIGS[1]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.only_c2:
+        args.no_gmres = True
+        print(json.dumps({"many_rhs": bench_c2(B, W, torch, np, stream, args)}))
+        return
     g = B.Geometry(B.BEM_GEOM_SPHERE6)
     s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=cfg["degree"], level=cfg["level"])
     t0 = time.perf_counter()

@@ -238,12 +238,15 @@ static size_t tmp_layout(const bem_operator_s& A, void* base, AsmDev* d) {
     a.gpos = b.take<double>((size_t)S.nelem * p.P.qg * p.P.qg * 3);
     a.gkap = S.form == 0 ? b.take<double>((size_t)S.nelem * p.P.qg * p.P.qg) : nullptr;
     a.psi = b.take<double>(p.psi.size());
+    a.psiw = b.take<double>(p.psiw.size());
     a.sx = b.take<double>(p.sx.size());
     a.sw = b.take<double>(p.sw.size());
     a.cheb = b.take<double>(p.cheb.size());
     a.own_t = b.take<int32_t>(p.own_t.size());
     a.xc = b.take<double>((size_t)p.ncl * p.q2 * 3);
     a.lb = b.take<char>((size_t)p.near_t.size() * p.nloc * p.nloc * p.nloc * p.nloc * A.scal);
+    const size_t nb2 = (size_t)(S.d + 1) * (S.d + 1) * (S.d + 1) * (S.d + 1);
+    a.sblk = b.take<char>(p.touch.size() / 5 * nb2 * A.scal);
     if (d) *d = a;
     return b.off + 256;
 }
@@ -1554,6 +1557,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     HIP_CHECK(up(as.gx, p.gx.data(), p.gx.size() * 8));
     HIP_CHECK(up(as.gw, p.gw.data(), p.gw.size() * 8));
     HIP_CHECK(up(as.psi, p.psi.data(), p.psi.size() * 8));
+    HIP_CHECK(up(as.psiw, p.psiw.data(), p.psiw.size() * 8));
     HIP_CHECK(up(as.sx, p.sx.data(), p.sx.size() * 8));
     HIP_CHECK(up(as.sw, p.sw.data(), p.sw.size() * 8));
     HIP_CHECK(up(as.cheb, p.cheb.data(), p.cheb.size() * 8));

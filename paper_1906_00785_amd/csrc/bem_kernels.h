@@ -107,6 +107,7 @@ struct AsmDev {
     const double* gpos;   // [nelem][qg*qg][3]
     const double* gkap;   // [nelem][qg*qg] surface element at the Gauss points (0-form lifting only)
     const double* psi;    // [nel][qg][d+1]
+    const double* psiw;   // [nel][qg][d+1] psi times the Gauss weights
     const double* gw;     // [qg]
     const double* sx;     // [qs]
     const double* sw;     // [qs]
@@ -114,6 +115,7 @@ struct AsmDev {
     const int32_t* own_t; // owner of each stored block
     double* xc;           // [ncl][q2][3] Chebyshev points on the surface
     void* lb;             // [nnear][nloc^2][nloc^2] leaf-pair blocks
+    void* sblk;           // [ntouch][(d+1)^2][(d+1)^2] element blocks of the touching pairs
 };
 
 hipError_t launch_gauss_points(const OpDev& op, const AsmDev& as, hipStream_t st);

@@ -92,19 +92,67 @@ __global__ void k_gauss_points(SpaceDesc S, int qg, const double* __restrict__ g
     if (gkap) gkap[idx] = patch_kappa(S.geom, f, ps, pt);  // 0-form lifting only
 }
 
+// 1/r for NS values r^2 > 0 (finite).  From the hardware estimate y (relative error
+// about 5e-8), e = 1 - r^2 y^2 and the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// give y (1 + e/2 + 3e^2/8), whose truncation error (5e^3/16) lies far below FP64
+// rounding; the NS chains are interleaved step by step.
+template <int NS>
+__device__ inline void rinv_nr(const double* r2, double* y) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) y[u] = __builtin_amdgcn_rsq(r2[u]);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const double e = __builtin_fma(-(r2[u] * y[u]), y[u], 1.0);
+        const double c = __builtin_fma(e, 0.375, 0.5);
+        y[u] = __builtin_fma(y[u] * e, c, y[u]);
+    }
+}
+
+// The single-layer kernel without its factor 1/(4 pi), for the near-field quadrature: 1/r
+// by rinv_nr (Laplace); exp(-i kappa r)/r with the library's sine, cosine and exponential
+// (Helmholtz: near pairs put no bound on kappa r).
+__device__ inline double near_kernel(const KernelDesc&, double r2, double) {
+    double y;
+    rinv_nr<1>(&r2, &y);
+    return y;
+}
+__device__ inline cdbl near_kernel(const KernelDesc& k, double r2, cdbl) {
+    double ir;
+    rinv_nr<1>(&r2, &ir);
+    const double r = r2 * ir;
+    double s, c;
+    sincos(k.kre * r, &s, &c);
+    const double mag = k.kim != 0.0 ? ir * exp(k.kim * r) : ir;
+    return {mag * c, -mag * s};
+}
+
+// Read-only tables addressed through the constant address space: loads at wave-uniform
+// addresses become scalar loads (the tables are not written while a kernel reads them).
+typedef const __attribute__((address_space(4))) double* cdptr;
+__device__ inline cdptr as_const(const double* p) { return (cdptr)p; }
+
+typedef double f64x4n __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------------------ near field: regular pairs
 // One workgroup per near leaf pair (tau, sigma).  Wave w takes the tau-elements w, w+W, ...
-// and integrates each against every sigma-element that does not touch it: lane a holds
-// Gauss point a of the tau-element; the sigma-element's points, weights and 1-D basis
-// values are wave-uniform (scalar loads).  Per lane the inner integral over sigma is
-// accumulated in tensor form (first over b2, then b1); the outer sum over the lanes is a
-// small LDS contraction.  Element-pair blocks are accumulated into the wave's own copy of
-// the leaf-pair block (DOFs of tau x DOFs of sigma), the copies summed in a fixed order.
-template <class T, int D>
+// and integrates each against every sigma-element that does not touch it.  Lane a holds
+// Gauss point a of the tau-element (64 points per pass); the sigma-element's points and
+// weighted basis values are wave-uniform and come through scalar loads.  Per lane the inner
+// integral over sigma is accumulated in tensor form (first over b2, then b1):
+// T[a][j] = sum_b k(x_a, y_b) w_b phi_j(y_b).  The outer sum over tau's points,
+// B[k][j] = sum_a w_a phi_k(x_a) T[a][j], runs on the matrix cores (v_mfma_f64_16x16x4f64,
+// the pass's 64 points in 16 steps of 4): lane l holds the weight of point 4 s + l / 16 for
+// basis l % 16 (built once per tau-element and pass) and reads T of that point from LDS.
+// Element-pair blocks are accumulated into the wave's own copy of the leaf-pair block
+// (DOFs of tau x DOFs of sigma), the copies summed in a fixed order.
+// QG: the Gauss points per direction when fixed at compile time (0: op.qg); K0: 0-form lifting.
+template <class T, int D, int QG, bool K0>
 __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W, int lb_in_lds) {
     constexpr int D1 = D + 1, NB = D1 * D1;
+    static_assert(NB <= 16, "element blocks of at most 16 x 16");
+    constexpr bool kCplx = std::is_same<T, cdbl>::value;
     const SpaceDesc S = op.S;
-    const int qg = op.qg, qg2 = qg * qg, m = op.m, m2 = m * m, nloc = op.nloc, nl2 = nloc * nloc;
+    const int qg = QG > 0 ? QG : op.qg, qg2 = qg * qg, m = op.m, m2 = m * m, nloc = op.nloc, nl2 = nloc * nloc;
     const int64_t blk = (int64_t)nl2 * nl2;
     const int64_t lp = blockIdx.x;
     int tf, ti, tj, sf, si, sj;
@@ -121,7 +169,10 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
     for (int64_t i = threadIdx.x; i < nzero; i += blockDim.x) LB[i] = zero<T>();
     __syncthreads();
     const KernelDesc kd = S.ker;
-    const double h2 = S.h * S.h, h4 = h2 * h2;
+    const double h2 = S.h * S.h, scale = kInv4Pi * h2 * h2;
+    const cdptr gpos = as_const(as.gpos), psiw = as_const(as.psiw);
+    const cdptr gkap = K0 ? as_const(as.gkap) : nullptr;  // 0-form lifting: kappa at the points
+    const int kq = lane & 15, aq = lane >> 4;                 // matrix-core operand roles of this lane
     for (int et = wave; et < m2; et += W) {
         const int ei1 = ti * m + et / m, ei2 = tj * m + et % m;
         const int64_t e = elem_id(S, tf, ei1, ei2);
@@ -135,6 +186,19 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
                 xa0 = xp[0];
                 xa1 = xp[1];
                 xa2 = xp[2];
+            }
+            // first operand: w_a phi_k(x_a) for point a = chunk + 4 s + aq and basis k = kq
+            double wA[16];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int ap = chunk + 4 * st + aq;
+                double w = 0.0;
+                if (ap < qg2 && kq < NB) {
+                    w = as.psiw[((int64_t)ei1 * qg + ap / qg) * D1 + kq / D1] *
+                        as.psiw[((int64_t)ei2 * qg + ap % qg) * D1 + kq % D1];
+                    if (K0) w *= as.gkap[e * qg2 + ap];
+                }
+                wA[st] = w;
             }
             for (int es = 0; es < m2; ++es) {
                 const int fi1 = si * m + es / m, fi2 = sj * m + es % m;
@@ -150,26 +214,26 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
                 T acc[NB];
 #pragma unroll
                 for (int j = 0; j < NB; ++j) acc[j] = zero<T>();
-                const double* yp = as.gpos + e2 * qg2 * 3;
-                const double* p1 = as.psi + (int64_t)fi1 * qg * D1;
-                const double* p2 = as.psi + (int64_t)fi2 * qg * D1;
-                const double* yk = as.gkap ? as.gkap + e2 * qg2 : nullptr;  // 0-form: kappa(y)
+                const cdptr yp = gpos + e2 * qg2 * 3;
+                const cdptr p1 = psiw + (int64_t)fi1 * qg * D1;
+                const cdptr p2 = psiw + (int64_t)fi2 * qg * D1;
+                const cdptr yk = K0 ? gkap + e2 * qg2 : nullptr;
                 for (int b1 = 0; b1 < qg; ++b1) {
                     T sacc[D1];
 #pragma unroll
                     for (int l = 0; l < D1; ++l) sacc[l] = zero<T>();
+#pragma unroll 8
                     for (int b2 = 0; b2 < qg; ++b2) {
-                        const double* y = yp + (b1 * qg + b2) * 3;
+                        const cdptr y = yp + (b1 * qg + b2) * 3;
                         const double dx = xa0 - y[0], dy = xa1 - y[1], dz = xa2 - y[2];
-                        const T kv = kernel_val(kd, dx * dx + dy * dy + dz * dz, T());
-                        const double wb = yk ? as.gw[b2] * yk[b1 * qg + b2] : as.gw[b2];
+                        T kv = near_kernel(kd, dx * dx + dy * dy + dz * dz, T());
+                        if (K0) kv = kv * yk[b1 * qg + b2];
 #pragma unroll
-                        for (int l = 0; l < D1; ++l) sacc[l] += kv * (wb * p2[b2 * D1 + l]);
+                        for (int l = 0; l < D1; ++l) sacc[l] += kv * p2[b2 * D1 + l];
                     }
-                    const double wb = as.gw[b1];
 #pragma unroll
                     for (int l1 = 0; l1 < D1; ++l1) {
-                        const double c1 = wb * p1[b1 * D1 + l1];
+                        const double c1 = p1[b1 * D1 + l1];
 #pragma unroll
                         for (int l2 = 0; l2 < D1; ++l2) acc[l1 * D1 + l2] += c1 * sacc[l2];
                     }
@@ -177,21 +241,31 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
 #pragma unroll
                 for (int j = 0; j < NB; ++j) myTB[lane * NB + j] = valid ? acc[j] : zero<T>();
                 wave_sync();
-                const double* q1 = as.psi + (int64_t)ei1 * qg * D1;
-                const double* q2 = as.psi + (int64_t)ei2 * qg * D1;
-                const int amax = min(kWave, qg2 - chunk);
-                for (int t = lane; t < NB * NB; t += kWave) {
-                    const int i = t / NB, j = t % NB, k1 = i / D1, k2 = i % D1;
-                    T B = zero<T>();
-                    const double* xk = as.gkap ? as.gkap + e * qg2 + chunk : nullptr;  // 0-form: kappa(x)
-                    for (int aa = 0; aa < amax; ++aa) {
-                        const int ag = chunk + aa, a1 = ag / qg, a2 = ag % qg;
-                        const double wa = as.gw[a1] * q1[a1 * D1 + k1] * as.gw[a2] * q2[a2 * D1 + k2];
-                        B += (xk ? wa * xk[aa] : wa) * myTB[aa * NB + j];
+                // B = sum over the pass's points of w_a phi_k(x_a) T[a][j]; lane l, entry u of
+                // the result: tau basis aq + 4 u, sigma basis kq
+                f64x4n cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    const T tb = kq < NB ? myTB[(4 * st + aq) * NB + kq] : zero<T>();
+                    if constexpr (kCplx) {
+                        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(wA[st], tb.re, cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(wA[st], tb.im, cim, 0, 0, 0);
+                    } else {
+                        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(wA[st], tb, cre, 0, 0, 0);
                     }
-                    const int r1 = (et / m) * S.r + k1, r2 = (et % m) * S.r + k2;
-                    const int c1 = (es / m) * S.r + j / D1, c2 = (es % m) * S.r + j % D1;
-                    myLB[(int64_t)(r1 * nloc + r2) * nl2 + c1 * nloc + c2] += B * h4;
+                }
+                if (kq < NB) {
+                    const int c1 = (es / m) * S.r + kq / D1, c2 = (es % m) * S.r + kq % D1;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int kk = aq + 4 * u;
+                        if (kk >= NB) continue;
+                        const int r1 = (et / m) * S.r + kk / D1, r2 = (et % m) * S.r + kk % D1;
+                        T v;
+                        if constexpr (kCplx) v = cdbl{cre[u] * scale, cim[u] * scale};
+                        else v = cre[u] * scale;
+                        myLB[(int64_t)(r1 * nloc + r2) * nl2 + c1 * nloc + c2] += v;
+                    }
                 }
                 wave_sync();
             }
@@ -208,95 +282,151 @@ __global__ __launch_bounds__(256) void k_near_regular(OpDev op, AsmDev as, int W
 }
 
 // ------------------------------------------------------------------ near field: touching pairs
-// One workgroup per near leaf pair that contains touching element pairs; the pairs are
-// integrated one after the other (all 256 threads share the Duffy cube points of a pair),
-// each block reduced over the workgroup and added to the leaf-pair block in a fixed order.
-// ROWS rows of the element-pair block are accumulated per pass to bound registers.
-template <class T, int D, int ROWS, int FORM>
+// gamma_f(s, t) with the geometry kind fixed at compile time (GK < 0: any kind).  Sphere and
+// ellipsoid: the radial projection of the cube face with 1/|c| from rinv_nr.
+template <int GK>
+__device__ inline void patch_point_k(const GeomDesc& g, int f, double s, double t, double* x) {
+    if constexpr (GK == GEOM_SPHERE6 || GK == GEOM_ELLIPSOID6) {
+        int iu, iv, ic;
+        double cv;
+        cube_face_layout(f, iu, iv, ic, cv);
+        double c[3];
+        c[iu] = 2.0 * s - 1.0;
+        c[iv] = 2.0 * t - 1.0;
+        c[ic] = cv;
+        double inv;
+        const double n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        rinv_nr<1>(&n2, &inv);
+        if constexpr (GK == GEOM_SPHERE6) {
+            x[0] = c[0] * inv;
+            x[1] = c[1] * inv;
+            x[2] = c[2] * inv;
+        } else {
+            x[0] = g.a * (c[0] * inv);
+            x[1] = g.b * (c[1] * inv);
+            x[2] = g.c * (c[2] * inv);
+        }
+    } else if constexpr (GK >= 0) {
+        GeomDesc h = g;
+        h.kind = GK;  // the other branches of patch_point fold away
+        patch_point(h, f, s, t, x);
+    } else {
+        patch_point(g, f, s, t, x);
+    }
+}
+
+// One workgroup per touching element pair (identical, common edge or common vertex).  The
+// pair's Duffy cube points are (xi, e1, e2, e3) per region; thread t takes the (e1, e2, e3)
+// combinations t, t + 256, ... of the qs^3 and, for each, every region and every xi, so the
+// region and xi are wave-uniform and no point index is divided.  The element block is
+// reduced over the workgroup and written to the pair's slot in sblk (ROWS rows of the block
+// per pass, to bound registers); k_near_singular_add adds the slots of each leaf pair to its
+// leaf-pair block in a fixed order.
+template <class T, int D, int ROWS, int FORM, int GK>
 __global__ __launch_bounds__(256) void k_near_singular(OpDev op, AsmDev as) {
     constexpr int D1 = D + 1, NB = D1 * D1;
     __shared__ T red[4][ROWS * NB];
     const SpaceDesc S = op.S;
     const BasisTab& bt = op.bt;
-    const int m = op.m, nloc = op.nloc, nl2 = nloc * nloc, qs = op.qs, qs2 = qs * qs, qs4 = qs2 * qs2;
-    const int64_t blk = (int64_t)nl2 * nl2;
-    const int lp = as.touch_lp[blockIdx.x];
+    const int m = op.m, qs = op.qs, qs3 = qs * qs * qs;
+    const int64_t tp = blockIdx.x;
+    // the leaf pair of tp: the last lp with touch_rowptr[lp] <= tp
+    int lo = 0, hi = (int)op.nnear;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (as.touch_rowptr[mid] <= tp) lo = mid;
+        else hi = mid;
+    }
     int tf, ti, tj, sf, si, sj;
-    leaf_decode(as.near_t[lp], op.nleaf1, tf, ti, tj);
-    leaf_decode(as.near_s[lp], op.nleaf1, sf, si, sj);
-    T* out = (T*)as.lb + (int64_t)lp * blk;
+    leaf_decode(as.near_t[lo], op.nleaf1, tf, ti, tj);
+    leaf_decode(as.near_s[lo], op.nleaf1, sf, si, sj);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const KernelDesc kd = S.ker;
     const double h2 = S.h * S.h, h4 = h2 * h2;
-    for (int tp = as.touch_rowptr[lp]; tp < as.touch_rowptr[lp + 1]; ++tp) {
-        const int et = as.touch[5 * tp], es = as.touch[5 * tp + 1], type = as.touch[5 * tp + 2];
-        const int k1 = as.touch[5 * tp + 3], k2 = as.touch[5 * tp + 4];
-        const int ei1 = ti * m + et / m, ei2 = tj * m + et % m;
-        const int fi1 = si * m + es / m, fi2 = sj * m + es % m;
-        const int c1a = basis_class(bt, ei1), c1b = basis_class(bt, ei2);
-        const int c2a = basis_class(bt, fi1), c2b = basis_class(bt, fi2);
-        const int nreg = type == PT_IDENTICAL ? 8 : (type == PT_EDGE ? 6 : 4);
-        const int npts = nreg * qs4;
+    const int et = as.touch[5 * tp], es = as.touch[5 * tp + 1], type = as.touch[5 * tp + 2];
+    const int k1 = as.touch[5 * tp + 3], k2 = as.touch[5 * tp + 4];
+    const int ei1 = ti * m + et / m, ei2 = tj * m + et % m;
+    const int fi1 = si * m + es / m, fi2 = sj * m + es % m;
+    const int c1a = basis_class(bt, ei1), c1b = basis_class(bt, ei2);
+    const int c2a = basis_class(bt, fi1), c2b = basis_class(bt, fi2);
+    const int nreg = type == PT_IDENTICAL ? 8 : (type == PT_EDGE ? 6 : 4);
+    const cdptr sx = as_const(as.sx), sw = as_const(as.sw);
+    T* sb = (T*)as.sblk + tp * NB * NB;
 #pragma unroll
-        for (int r0 = 0; r0 < NB; r0 += ROWS) {
-            T acc[ROWS * NB];
+    for (int r0 = 0; r0 < NB; r0 += ROWS) {
+        T acc[ROWS * NB];
 #pragma unroll
-            for (int v = 0; v < ROWS * NB; ++v) acc[v] = zero<T>();
-            for (int p = threadIdx.x; p < npts; p += blockDim.x) {
-                const int reg = p / qs4;
-                int rem = p - reg * qs4;
-                const int i3 = rem % qs;
-                rem /= qs;
-                const int i2 = rem % qs;
-                rem /= qs;
-                const int i1 = rem % qs, i0 = rem / qs;
-                double xh1, xh2, yh1, yh2, jac;
-                duffy_point(type, reg, as.sx[i0], as.sx[i1], as.sx[i2], as.sx[i3], xh1, xh2, yh1, yh2, jac);
-                double wq = as.sw[i0] * as.sw[i1] * as.sw[i2] * as.sw[i3] * jac * h4;
-                double u1, u2, w1, w2, X[3], Y[3];
-                d4_apply(k1, xh1, xh2, u1, u2);
-                d4_apply(k2, yh1, yh2, w1, w2);
-                patch_point(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h, X);
-                patch_point(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h, Y);
-                if (FORM == 0)  // 0-form lifting: both surface elements
-                    wq *= patch_kappa(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h) *
-                          patch_kappa(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h);
-                double pa[D1], pb[D1], qa[D1], qb[D1];
+        for (int v = 0; v < ROWS * NB; ++v) acc[v] = zero<T>();
+        for (int c = threadIdx.x; c < qs3; c += blockDim.x) {
+            const int i3 = c % qs, i2 = (c / qs) % qs, i1 = c / (qs * qs);
+            const double e1 = as.sx[i1], e2 = as.sx[i2], e3 = as.sx[i3];
+            const double w123 = as.sw[i1] * as.sw[i2] * as.sw[i3] * h4;
+            for (int reg = 0; reg < nreg; ++reg)
+                for (int i0 = 0; i0 < qs; ++i0) {
+                    double xh1, xh2, yh1, yh2, jac;
+                    duffy_point(type, reg, sx[i0], e1, e2, e3, xh1, xh2, yh1, yh2, jac);
+                    double wq = sw[i0] * w123 * jac;
+                    double u1, u2, w1, w2, X[3], Y[3];
+                    d4_apply(k1, xh1, xh2, u1, u2);
+                    d4_apply(k2, yh1, yh2, w1, w2);
+                    patch_point_k<GK>(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h, X);
+                    patch_point_k<GK>(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h, Y);
+                    if (FORM == 0)  // 0-form lifting: both surface elements
+                        wq *= patch_kappa(S.geom, tf, (ei1 + u1) * S.h, (ei2 + u2) * S.h) *
+                              patch_kappa(S.geom, sf, (fi1 + w1) * S.h, (fi2 + w2) * S.h);
+                    double pa[D1], pb[D1], qa[D1], qb[D1];
 #pragma unroll
-                for (int l = 0; l < D1; ++l) {
-                    pa[l] = basis_eval(bt, c1a, l, u1);
-                    pb[l] = basis_eval(bt, c1b, l, u2);
-                    qa[l] = basis_eval(bt, c2a, l, w1);
-                    qb[l] = basis_eval(bt, c2b, l, w2);
-                }
-                const double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
-                const T kv = kernel_val(kd, dx * dx + dy * dy + dz * dz, T()) * wq;
+                    for (int l = 0; l < D1; ++l) {
+                        pa[l] = basis_eval(bt, c1a, l, u1);
+                        pb[l] = basis_eval(bt, c1b, l, u2);
+                        qa[l] = basis_eval(bt, c2a, l, w1);
+                        qb[l] = basis_eval(bt, c2b, l, w2);
+                    }
+                    const double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+                    const T kv = near_kernel(kd, dx * dx + dy * dy + dz * dz, T()) * (wq * kInv4Pi);
 #pragma unroll
-                for (int ii = 0; ii < ROWS; ++ii) {
-                    const int i = r0 + ii;
-                    if (i < NB) {
-                        const T fi = kv * (pa[i / D1] * pb[i % D1]);
+                    for (int ii = 0; ii < ROWS; ++ii) {
+                        const int i = r0 + ii;
+                        if (i < NB) {
+                            const T fi = kv * (pa[i / D1] * pb[i % D1]);
 #pragma unroll
-                        for (int j = 0; j < NB; ++j) acc[ii * NB + j] += fi * (qa[j / D1] * qb[j % D1]);
+                            for (int j = 0; j < NB; ++j) acc[ii * NB + j] += fi * (qa[j / D1] * qb[j % D1]);
+                        }
                     }
                 }
-            }
-#pragma unroll
-            for (int v = 0; v < ROWS * NB; ++v) {
-                const T s = wave_sum(acc[v]);
-                if (lane == 0) red[wave][v] = s;
-            }
-            __syncthreads();
-            for (int t = threadIdx.x; t < ROWS * NB; t += blockDim.x) {
-                const int i = r0 + t / NB, j = t % NB;
-                if (i >= NB) continue;
-                const T B = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-                const int r1 = (et / m) * S.r + i / D1, r2 = (et % m) * S.r + i % D1;
-                const int cc1 = (es / m) * S.r + j / D1, cc2 = (es % m) * S.r + j % D1;
-                out[(int64_t)(r1 * nloc + r2) * nl2 + cc1 * nloc + cc2] += B;
-            }
-            __syncthreads();
         }
+#pragma unroll
+        for (int v = 0; v < ROWS * NB; ++v) {
+            const T s = wave_sum(acc[v]);
+            if (lane == 0) red[wave][v] = s;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < ROWS * NB; t += blockDim.x) {
+            const int i = r0 + t / NB;
+            if (i < NB) sb[i * NB + t % NB] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per near leaf pair with touching element pairs: their element blocks, in
+// the order of the pairs, added to the leaf-pair block.
+template <class T, int D>
+__global__ __launch_bounds__(128) void k_near_singular_add(OpDev op, AsmDev as) {
+    constexpr int D1 = D + 1, NB = D1 * D1;
+    const int m = op.m, nloc = op.nloc, nl2 = nloc * nloc, r = op.S.r;
+    const int lp = as.touch_lp[blockIdx.x];
+    T* out = (T*)as.lb + (int64_t)lp * nl2 * nl2;
+    const T* sb = (const T*)as.sblk;
+    for (int tp = as.touch_rowptr[lp]; tp < as.touch_rowptr[lp + 1]; ++tp) {
+        const int et = as.touch[5 * tp], es = as.touch[5 * tp + 1];
+        for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+            const int i = t / NB, j = t % NB;
+            const int r1 = (et / m) * r + i / D1, r2 = (et % m) * r + i % D1;
+            const int cc1 = (es / m) * r + j / D1, cc2 = (es % m) * r + j % D1;
+            out[(int64_t)(r1 * nloc + r2) * nl2 + cc1 * nloc + cc2] += sb[(int64_t)tp * NB * NB + t];
+        }
+        __syncthreads();
     }
 }
 
@@ -797,21 +927,6 @@ __device__ inline void coupling_body(const OpDev& op, int64_t blk_) {
     if (ok) ((T*)op.partial)[c * Q2 + idx] = acc[0];
 }
 
-// 1/r for NS values r^2 > 0 (finite).  From the hardware estimate y (relative error
-// about 5e-8), e = 1 - r^2 y^2 and the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
-// give y (1 + e/2 + 3e^2/8), whose truncation error (5e^3/16) lies far below FP64
-// rounding; the NS chains are interleaved step by step.
-template <int NS>
-__device__ inline void rinv_nr(const double* r2, double* y) {
-#pragma unroll
-    for (int u = 0; u < NS; ++u) y[u] = __builtin_amdgcn_rsq(r2[u]);
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        const double e = __builtin_fma(-(r2[u] * y[u]), y[u], 1.0);
-        const double c = __builtin_fma(e, 0.375, 0.5);
-        y[u] = __builtin_fma(y[u] * e, c, y[u]);
-    }
-}
 
 // sin x and cos x for |x| < 2^20: x = k pi/2 + y with |y| <= pi/4 (pi/2 split into three
 // doubles, each product subtracted with one rounding), then the Taylor series of sin and
@@ -1560,6 +1675,19 @@ hipError_t launch_gauss_points(const OpDev& op, const AsmDev& as, hipStream_t st
     return hipGetLastError();
 }
 
+template <class T, int D, int QG, bool K0>
+static hipError_t near_regular_launch(const OpDev& op, const AsmDev& as, int W, int in_lds, size_t shm,
+                                      hipStream_t st) {
+    if (shm > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_near_regular<T, D, QG, K0>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_near_regular<T, D, QG, K0>), dim3((unsigned)op.nnear), dim3(64 * W), shm, st, op, as, W,
+                       in_lds);
+    return hipGetLastError();
+}
+
 template <class T, int D>
 static hipError_t near_regular_t(const OpDev& op, const AsmDev& as, hipStream_t st) {
     constexpr int NB = (D + 1) * (D + 1);
@@ -1571,13 +1699,12 @@ static hipError_t near_regular_t(const OpDev& op, const AsmDev& as, hipStream_t 
     int in_lds = W * (lb + tb) <= budget ? 1 : 0;
     if (!in_lds) W = 1;
     const size_t shm = in_lds ? W * (lb + tb) : tb;
-    if (shm > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_near_regular<T, D>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_near_regular<T, D>), dim3((unsigned)op.nnear), dim3(64 * W), shm, st, op, as, W, in_lds);
-    return hipGetLastError();
+    const bool k0 = as.gkap != nullptr;
+    if (op.qg == 8)
+        return k0 ? near_regular_launch<T, D, 8, true>(op, as, W, in_lds, shm, st)
+                  : near_regular_launch<T, D, 8, false>(op, as, W, in_lds, shm, st);
+    return k0 ? near_regular_launch<T, D, 0, true>(op, as, W, in_lds, shm, st)
+              : near_regular_launch<T, D, 0, false>(op, as, W, in_lds, shm, st);
 }
 
 hipError_t launch_near_regular(const OpDev& op, const AsmDev& as, hipStream_t st) {
@@ -1593,28 +1720,41 @@ hipError_t launch_near_regular(const OpDev& op, const AsmDev& as, hipStream_t st
     return near_regular_t<double, 2>(op, as, st);
 }
 
+template <class T, int D, int ROWS, int FORM>
+static void near_singular_geom(const OpDev& op, const AsmDev& as, hipStream_t st) {
+    const dim3 g((unsigned)op.ntouch), b(256);
+    switch (FORM == 2 ? op.S.geom.kind : -1) {
+        case GEOM_SPHERE6: hipLaunchKernelGGL((k_near_singular<T, D, ROWS, FORM, GEOM_SPHERE6>), g, b, 0, st, op, as); break;
+        case GEOM_ELLIPSOID6:
+            hipLaunchKernelGGL((k_near_singular<T, D, ROWS, FORM, GEOM_ELLIPSOID6>), g, b, 0, st, op, as);
+            break;
+        case GEOM_TORUS16: hipLaunchKernelGGL((k_near_singular<T, D, ROWS, FORM, GEOM_TORUS16>), g, b, 0, st, op, as); break;
+        default: hipLaunchKernelGGL((k_near_singular<T, D, ROWS, FORM, -1>), g, b, 0, st, op, as); break;
+    }
+    hipLaunchKernelGGL((k_near_singular_add<T, D>), dim3((unsigned)as.ntouch_lp), dim3(128), 0, st, op, as);
+}
+
 hipError_t launch_near_singular(const OpDev& op, const AsmDev& as, hipStream_t st) {
-    if (as.ntouch_lp == 0) return hipSuccess;
-    const dim3 g((unsigned)as.ntouch_lp), b(256);
+    if (as.ntouch_lp == 0 || op.ntouch == 0) return hipSuccess;
     const int d = op.S.d;
     if (op.S.form == 0) {  // S^0 (degree >= 1)
         if (op.cplx) {
-            if (d == 1) hipLaunchKernelGGL((k_near_singular<cdbl, 1, 4, 0>), g, b, 0, st, op, as);
-            else hipLaunchKernelGGL((k_near_singular<cdbl, 2, 5, 0>), g, b, 0, st, op, as);
+            if (d == 1) near_singular_geom<cdbl, 1, 4, 0>(op, as, st);
+            else near_singular_geom<cdbl, 2, 5, 0>(op, as, st);
         } else {
-            if (d == 1) hipLaunchKernelGGL((k_near_singular<double, 1, 4, 0>), g, b, 0, st, op, as);
-            else hipLaunchKernelGGL((k_near_singular<double, 2, 9, 0>), g, b, 0, st, op, as);
+            if (d == 1) near_singular_geom<double, 1, 4, 0>(op, as, st);
+            else near_singular_geom<double, 2, 9, 0>(op, as, st);
         }
         return hipGetLastError();
     }
     if (op.cplx) {
-        if (d == 0) hipLaunchKernelGGL((k_near_singular<cdbl, 0, 1, 2>), g, b, 0, st, op, as);
-        else if (d == 1) hipLaunchKernelGGL((k_near_singular<cdbl, 1, 4, 2>), g, b, 0, st, op, as);
-        else hipLaunchKernelGGL((k_near_singular<cdbl, 2, 5, 2>), g, b, 0, st, op, as);
+        if (d == 0) near_singular_geom<cdbl, 0, 1, 2>(op, as, st);
+        else if (d == 1) near_singular_geom<cdbl, 1, 4, 2>(op, as, st);
+        else near_singular_geom<cdbl, 2, 5, 2>(op, as, st);
     } else {
-        if (d == 0) hipLaunchKernelGGL((k_near_singular<double, 0, 1, 2>), g, b, 0, st, op, as);
-        else if (d == 1) hipLaunchKernelGGL((k_near_singular<double, 1, 4, 2>), g, b, 0, st, op, as);
-        else hipLaunchKernelGGL((k_near_singular<double, 2, 9, 2>), g, b, 0, st, op, as);
+        if (d == 0) near_singular_geom<double, 0, 1, 2>(op, as, st);
+        else if (d == 1) near_singular_geom<double, 1, 4, 2>(op, as, st);
+        else near_singular_geom<double, 2, 9, 2>(op, as, st);
     }
     return hipGetLastError();
 }

@@ -546,6 +546,8 @@ bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& p, std::string& err
         for (int a = 0; a < P.qg; ++a)
             for (int l = 0; l < d1; ++l)
                 p.psi[((size_t)i * P.qg + a) * d1 + l] = poly_eval(&p.bpoly[((size_t)i * d1 + l) * d1], S.d, p.gx[a]);
+    p.psiw.resize(p.psi.size());
+    for (size_t k = 0; k < p.psi.size(); ++k) p.psiw[k] = p.gw[(k / d1) % P.qg] * p.psi[k];
     p.cheb.resize(P.q);
     for (int a = 0; a < P.q; ++a) p.cheb[a] = 0.5 + 0.5 * std::cos((2.0 * a + 1.0) * kPi / (2.0 * P.q));
     p.E.assign(2 * p.q2, 0.0);

@@ -95,6 +95,7 @@ struct Plan {
     std::vector<double> sx, sw;   // qs-point rule
     std::vector<double> bpoly;    // local B-spline polynomials (see bspline_local_polys)
     std::vector<double> psi;      // [nel][qg][d+1] B-spline values at the qg Gauss points
+    std::vector<double> psiw;     // [nel][qg][d+1] the same times the Gauss weights
     std::vector<double> cheb;     // q Chebyshev nodes on [0,1]
     std::vector<double> E;        // [2][q][q]: E[b][a'][a] = L_a((b + x_a')/2)
     std::vector<double> V1;       // [nleaf1][q][nloc] 1-D leaf moments
