@@ -28,6 +28,14 @@ __host__ __device__ inline double basis_eval(const BasisTab& t, int cls, int l, 
     for (int k = t.d - 1; k >= 0; --k) v = v * x + t.c[cls][l][k];
     return v;
 }
+// the same with the degree D = t.d known at compile time
+template <int D>
+__host__ __device__ inline double basis_eval_d(const BasisTab& t, int cls, int l, double x) {
+    double v = t.c[cls][l][D];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) v = v * x + t.c[cls][l][k];
+    return v;
+}
 
 struct Gauss8 {
     double x[8], w[8];

@@ -377,10 +377,10 @@ __global__ __launch_bounds__(256) void k_near_singular(OpDev op, AsmDev as) {
                     double pa[D1], pb[D1], qa[D1], qb[D1];
 #pragma unroll
                     for (int l = 0; l < D1; ++l) {
-                        pa[l] = basis_eval(bt, c1a, l, u1);
-                        pb[l] = basis_eval(bt, c1b, l, u2);
-                        qa[l] = basis_eval(bt, c2a, l, w1);
-                        qb[l] = basis_eval(bt, c2b, l, w2);
+                        pa[l] = basis_eval_d<D>(bt, c1a, l, u1);
+                        pb[l] = basis_eval_d<D>(bt, c1b, l, u2);
+                        qa[l] = basis_eval_d<D>(bt, c2a, l, w1);
+                        qb[l] = basis_eval_d<D>(bt, c2b, l, w2);
                     }
                     const double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
                     const T kv = near_kernel(kd, dx * dx + dy * dy + dz * dz, T()) * (wq * kInv4Pi);
