@@ -438,17 +438,18 @@ def bench_c4(B, W, torch, np, args):
             t1 = time.perf_counter()
             _, st = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], precond=pc)
             torch.cuda.synchronize()
-            res[name] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1]}
+            res[name] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1],
+                         "relres": st[0][2]}
         t1 = time.perf_counter()
         kept, rr = L.install(A, net, b, restart=cfg["restart"])
         _, st = A.solve(b, tol=cfg["tol"], restart=cfg["restart"], maxit=cfg["maxit"], precond=True)
         torch.cuda.synchronize()
         res["learned"] = {"iterations": st[0][0], "time_s": time.perf_counter() - t1, "converged": st[0][1],
-                          "kept": kept, "cycle_relres_plain_learned": rr}
+                          "relres": st[0][2], "kept": kept, "cycle_relres_plain_learned": rr}
         rows.append({"instance": [inst[0], list(inst[1]), inst[2]], "level": level, "ndof": s.ndof, **res})
-        print(f"bench c4: L{level} {inst}: none {res['none']['iterations']} its, block-Jacobi "
-              f"{res['block_jacobi']['iterations']} its, learned {res['learned']['iterations']} its "
-              f"(kept {kept})", file=sys.stderr, flush=True)
+        print(f"bench c4: L{level} {inst}: " + ", ".join(
+            f"{k} {res[k]['iterations']} its {res[k]['time_s']:.2f}s relres {res[k]['relres']:.1e}"
+            for k in ("none", "block_jacobi", "learned")) + f" (learned kept {kept})", file=sys.stderr, flush=True)
         del A, s
     return {"workload": cfg["name"], "levels": sorted(set(used)), "kappa_range": list(cfg["kappa_range"]),
             "train_blocks": int(X.shape[0]), "train_instances": len(used), "data_s": t_data, "train_s": t_train,
@@ -606,6 +607,40 @@ def main():
     extra["copy_gbs"] = copy_gbs
     print(f"bench: 1 GiB device copy {copy_gbs:.0f} GB/s; stored-block coupling at {achieved_st / copy_gbs:.2f} of it",
           file=sys.stderr, flush=True)
+    # MALL-cold figures: before every timed launch a 1 GiB copy (4x the 256 MB last-level
+    # cache) evicts the operator's data, so the launch streams its bytes from HBM; the
+    # back-to-back figures above may partly hit in that cache
+    flush_src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(2.0)
+    flush_dst = torch.empty_like(flush_src)
+
+    def cold_ms(fn, reps=10):
+        fn()
+        tot = 0.0
+        for _ in range(reps):
+            flush_dst.copy_(flush_src)
+            a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b_.record(stream)
+            torch.cuda.synchronize()
+            tot += a.elapsed_time(b_)
+        return tot / reps
+
+    A.apply(x, out=y)
+    cold_cpl = cold_ms(lambda: A.apply_stage(1, x, y))
+    cold_near = cold_ms(lambda: A.apply_stage(0, x, y))
+    cold_st = cold_ms(lambda: A.apply(x, out=y))
+    cold_ot = cold_ms(lambda: Aot.apply(x, out=y))
+    del flush_src, flush_dst
+    extra["mall_cold"] = {
+        "stored_coupling_kernel_ms": cold_cpl, "stored_coupling_gbs": coupling_bytes / (cold_cpl * 1e-3) / 1e9,
+        "near_and_up_stage_ms": cold_near, "near_gbs": near_bytes / (cold_near * 1e-3) / 1e9,
+        "matvec_stored_ms": cold_st, "matvec_on_the_fly_ms": cold_ot,
+        "dof_per_s_on_the_fly": N / (cold_ot * 1e-3), "dof_per_s_stored": N / (cold_st * 1e-3),
+        "flush": "1 GiB device copy before every timed launch"}
+    print(f"bench: MALL-cold: stored coupling {cold_cpl*1e3:.1f} us ({coupling_bytes/(cold_cpl*1e-3)/1e9:.0f} GB/s), "
+          f"near+up stage {cold_near*1e3:.1f} us ({near_bytes/(cold_near*1e-3)/1e9:.0f} GB/s), matvec stored "
+          f"{cold_st*1e3:.1f} us, on the fly {cold_ot*1e3:.1f} us", file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)  # 1 GiB
         dst = torch.empty_like(src)

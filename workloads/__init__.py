@@ -45,8 +45,11 @@ CONFIGS[3] = dict(
 CONFIGS[4] = dict(
     name="learned_precond_ellipsoid_torus_L5-6_d2_helmholtz_k4-20",
     level=5, levels=(5, 6), degree=2, kappa_range=(4.0, 20.0), semiaxes=(0.5, 2.0), torus_R=1.0,
-    torus_r=(0.2, 0.5), q=5, eta=1.6, tol=1e-8, restart=30, maxit=2000, ring=2, train_blocks=10000,
+    torus_r=(0.2, 0.5), q=5, eta=1.6, tol=1e-8, restart=64, maxit=15000, ring=2, train_blocks=10000,
 )
+# At wavenumbers up to 20 on these meshes GMRES(30) stalls even with block-Jacobi (measured
+# on the held-out instances: relative residuals 1e-6..7e-3 after 12,000 steps), so this
+# family solves with the longest restart the library takes and a step cap of 15,000.
 
 GEOM_KIND = {"sphere": 0, "ellipsoid": 1, "torus": 2, "flat": 3}
 PDE_KIND = {"laplace": 0, "helmholtz": 1}
