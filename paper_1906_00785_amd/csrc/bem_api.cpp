@@ -105,6 +105,7 @@ struct bem_operator_s {
     std::vector<int32_t> touch_lp;
     std::vector<int64_t> fb_off;  // host copies of the per-pair block table (kept until destroy,
     std::vector<int32_t> fb_rs;   // the uploads above are asynchronous)
+    std::vector<double> ec;       // leaf-to-ancestor transfers of the many-RHS path (same)
     // dense near-field tiles of the many-RHS path (see BatchDev)
     std::vector<int64_t> tile_rowptr, tile_colptr, tile_voff;
     std::vector<int32_t> tile_rows, tile_cols;
@@ -212,6 +213,7 @@ static size_t op_layout(const bem_operator_s& A, void* base, OpDev* d, BatchDev*
             bd.Bf = b.take<char>((size_t)p.ncl * nch * bf_col_tiles(A.cplx) * kBatchChunk * 16);
         }
         if (A.far_low == 1) bd.mlow = b.take<char>((size_t)p.ncl * p.q2 * Rb * (A.scal / 2));
+        bd.Ec = b.take<double>((size_t)p.q2 * ((size_t(2) << p.P.leaf) - 2) + 1);
         if (bdo) *bdo = bd;
     }
     if (d) *d = o;
@@ -1599,6 +1601,26 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
         HIP_CHECK(up(bd.fb_off, A->fb_off.data(), np * 8));
         HIP_CHECK(up(bd.fb_rs, A->fb_rs.data(), np * 4));
         if (A->far_low == 2 && p.P.q <= 5) HIP_CHECK(launch_build_bf_blocks(d, bd, (int64_t)np, stream));
+        // leaf-to-ancestor transfers: E^(1)_b = E_b; E^(k)_b = E_(b mod 2) E^(k-1)_(b div 2)
+        const int Q = p.P.q, q2 = p.q2;
+        A->ec.assign((size_t)q2 * ((size_t(2) << p.P.leaf) - 2) + 1, 0.0);
+        for (int k = 1; k <= p.P.leaf; ++k) {
+            double* Ek = A->ec.data() + (size_t)q2 * ((size_t(1) << k) - 2);
+            const double* Ep = A->ec.data() + (size_t)q2 * ((size_t(1) << (k - 1)) - 2);
+            for (int b = 0; b < (1 << k); ++b)
+                for (int pp = 0; pp < Q; ++pp)
+                    for (int a = 0; a < Q; ++a) {
+                        double v = 0.0;
+                        if (k == 1) {
+                            v = p.E[((size_t)b * Q + pp) * Q + a];
+                        } else {
+                            for (int mid = 0; mid < Q; ++mid)
+                                v += p.E[((size_t)(b & 1) * Q + pp) * Q + mid] * Ep[((size_t)(b >> 1) * Q + mid) * Q + a];
+                        }
+                        Ek[((size_t)b * Q + pp) * Q + a] = v;
+                    }
+        }
+        HIP_CHECK(up(bd.Ec, A->ec.data(), A->ec.size() * 8));
     }
     A->bdev = bd;
     // the host tables above are copied from pageable memory; make sure they have been read

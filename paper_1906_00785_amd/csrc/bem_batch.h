@@ -49,6 +49,10 @@ struct BatchDev {
     void* Af;                   // [npairs][RT][64 lanes] x 8 bf16
     void* Bf;                   // [ncl][nchunks][NT][64 lanes] x 8 bf16
     void* mlow;                 // FP32 copy of the moments' slab (FP32 coupling), or null
+    // transfer from a leaf to its ancestor k levels up, k = 1..leaf: for each leaf position
+    // b in [0, 2^k) along one direction a q x q matrix [p][a] (leaf index p, ancestor index
+    // a); level k starts at q^2 (2^k - 2)
+    const double* Ec;
 };
 
 // fragment counts of the BF16 coupling: row tiles of 16 (real: K padded to 32 rows;

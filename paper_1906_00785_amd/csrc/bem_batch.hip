@@ -406,56 +406,11 @@ __global__ __launch_bounds__(256) void kb_coupling_mfma(OpDev op, BatchDev bd) {
 }
 
 // ------------------------------------------------------------------ downward + backward
-// Local expansions at level lev >= 1 receive their parent's (complete) expansion:
-// l_c[p] += sum_a E_b1[p1][a1] E_b2[p2][a2] l_P[a].
-template <class T, int Q>
-__global__ __launch_bounds__(256) void kb_downward(OpDev op, BatchDev bd, int lev) {
-    constexpr int Q2 = Q * Q;
-    const int nch = nchunks(bd.R);
-    const int n = 1 << lev, np = n >> 1;
-    const int64_t nl = (int64_t)op.S.geom.npatch * n * n;
-    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
-    if (item >= nl * nch) return;
-    const int64_t loc = item / nch;
-    const int ch = (int)(item % nch);
-    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
-    if (r >= R) return;
-    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const int b1 = i & 1, b2 = j & 1;
-    const double* __restrict__ E = op.E;
-    const int64_t P = op.lev_off[lev - 1] + ((int64_t)f * np + (i >> 1)) * np + (j >> 1);
-    const T* vp = (const T*)bd.lv + P * Q2 * R + r;
-    T* vc = (T*)bd.lv + (op.lev_off[lev] + loc) * Q2 * R + r;
-    T acc[Q2];
-#pragma unroll
-    for (int p = 0; p < Q2; ++p) acc[p] = vc[(int64_t)p * R];
-    T vall[Q2];
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) vall[a] = vp[(int64_t)a * R];
-#pragma unroll
-    for (int a1 = 0; a1 < Q; ++a1) {
-        T in[Q];
-#pragma unroll
-        for (int p2 = 0; p2 < Q; ++p2) in[p2] = zero<T>();
-#pragma unroll
-        for (int a2 = 0; a2 < Q; ++a2) {
-            const T v = vall[a1 * Q + a2];
-#pragma unroll
-            for (int p2 = 0; p2 < Q; ++p2) in[p2] += E[(b2 * Q + p2) * Q + a2] * v;
-        }
-#pragma unroll
-        for (int p1 = 0; p1 < Q; ++p1) {
-            const double w = E[(b1 * Q + p1) * Q + a1];
-#pragma unroll
-            for (int p2 = 0; p2 < Q; ++p2) acc[p1 * Q + p2] += w * in[p2];
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < Q2; ++p) vc[(int64_t)p * R] = acc[p];
-}
-
-// Backward transform of one leaf: its contribution V_tau^T l_tau to each of the nloc^2
-// B-splines that meet it, stored per leaf (added per DOF by the near-field kernel).
+// Downward transfer and backward transform of one leaf: the leaf's local expansion plus
+// those of all its ancestors carried down in one step each (l_leaf[p] += sum_a
+// E^(k)_b1[p1][a1] E^(k)_b2[p2][a2] l_anc[a], E^(k) the leaf-to-ancestor transfer k levels
+// up), then its contribution V_tau^T l_tau to each of the nloc^2 B-splines that meet it,
+// stored per leaf (added per DOF by the near-field kernel).
 template <class T, int Q>
 __global__ __launch_bounds__(256) void kb_leaf_back(OpDev op, BatchDev bd) {
     constexpr int Q2 = Q * Q;
@@ -466,13 +421,40 @@ __global__ __launch_bounds__(256) void kb_leaf_back(OpDev op, BatchDev bd) {
     const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
     if (r >= R) return;
     const int n1 = op.nleaf1, nloc = op.nloc;
-    const int j = l % n1, i = (l / n1) % n1;
+    const int j = l % n1, i = (l / n1) % n1, f = l / (n1 * n1);
     const double* __restrict__ Vi = op.V1 + (int64_t)i * Q * nloc;
     const double* __restrict__ Vj = op.V1 + (int64_t)j * Q * nloc;
     const T* lvp = (const T*)bd.lv + (op.lev_off[op.leaf] + l) * Q2 * R + r;
     T v[Q2];
 #pragma unroll
     for (int a = 0; a < Q2; ++a) v[a] = lvp[(int64_t)a * R];
+    for (int k = 1; k <= op.leaf; ++k) {
+        const int na = n1 >> k, b1 = i & ((1 << k) - 1), b2 = j & ((1 << k) - 1);
+        const int64_t anc = op.lev_off[op.leaf - k] + ((int64_t)f * na + (i >> k)) * na + (j >> k);
+        const double* __restrict__ Ek = bd.Ec + (int64_t)Q2 * ((1 << k) - 2);
+        const T* vp = (const T*)bd.lv + anc * Q2 * R + r;
+        T vall[Q2];
+#pragma unroll
+        for (int a = 0; a < Q2; ++a) vall[a] = vp[(int64_t)a * R];
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) {
+            T in[Q];
+#pragma unroll
+            for (int p2 = 0; p2 < Q; ++p2) in[p2] = zero<T>();
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) {
+                const T w = vall[a1 * Q + a2];
+#pragma unroll
+                for (int p2 = 0; p2 < Q; ++p2) in[p2] += Ek[(b2 * Q + p2) * Q + a2] * w;
+            }
+#pragma unroll
+            for (int p1 = 0; p1 < Q; ++p1) {
+                const double e = Ek[(b1 * Q + p1) * Q + a1];
+#pragma unroll
+                for (int p2 = 0; p2 < Q; ++p2) v[p1 * Q + p2] += e * in[p2];
+            }
+        }
+    }
     T* yl = (T*)bd.yl + (int64_t)l * nloc * nloc * R + r;
     for (int m2 = 0; m2 < nloc; ++m2) {
         T t[Q];
@@ -778,14 +760,13 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
                     int prec, hipStream_t st) {
     const int R = bd.R, nch = (R + kBatchChunk - 1) / kBatchChunk;
     const int64_t N = op.S.ndof;
-    const int npatch = op.S.geom.npatch;
     if (stage == 0) {
         if (x)
             hipLaunchKernelGGL(kb_to_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R, (const T*)x, ldx,
                                (T*)bd.xs);
         hipLaunchKernelGGL((kb_leaf_moments<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
         for (int lev = op.leaf - 1; lev >= 0; --lev) {
-            const int64_t nl = (int64_t)npatch << (2 * lev);
+            const int64_t nl = (int64_t)op.S.geom.npatch << (2 * lev);
             hipLaunchKernelGGL((kb_upward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
         }
         if (prec == 2) hipLaunchKernelGGL((kb_bf_moments<T, Q>), dim3(nblk(op.ncl * nch, 4)), dim3(256), 0, st, op, bd);
@@ -827,10 +808,6 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
                 return hipErrorInvalidValue;
         }
     } else if (stage == 2) {
-        for (int lev = 1; lev <= op.leaf; ++lev) {
-            const int64_t nl = (int64_t)npatch << (2 * lev);
-            hipLaunchKernelGGL((kb_downward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
-        }
         hipLaunchKernelGGL((kb_leaf_back<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
     } else {
         hipLaunchKernelGGL(kb_near_mfma<T>, dim3((unsigned)(bd.ntiles * nch)), dim3(256), 0, st, op, bd);

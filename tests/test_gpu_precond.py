@@ -19,6 +19,8 @@ CASES = {
     "sphere_L2_d1_laplace": (0, (), 0, 0.0, 2, 1, 4, 1.6, 1),           # nb 5: short tiles only
     "flat_L3_d1_helmholtz": (3, (2.0,), 1, 2.0, 3, 1, 4, 1.6, 2),       # nb 9: tiles 8 and 1
     "torus_L2_d2_laplace": (2, (1.0, 0.4), 0, 0.0, 2, 2, 4, 1.6, 1),    # 16 patches, nb 6
+    # leaf level = L: one element per leaf, so admissible pairs join elements of one tile
+    "sphere_L3_d1_laplace_leaf_eq_L": (0, (), 0, 0.0, 3, 1, 4, 1.6, 3),  # nb 9: tiles 8 and 1
 }
 
 
@@ -188,3 +190,27 @@ def test_full_size_preconditioned_solve(B):
     assert stp[0][1] and stp[0][2] <= c["tol"] and stp[0][0] < st[0][0]
     r = (b[0] - A.apply(xp[0])).norm() / b[0].norm()
     assert float(r) <= c["tol"]
+
+
+def test_block_is_the_near_part_when_far_pairs_fall_inside_a_tile(B, orc):
+    """With single-element leaves, admissible (far) pairs join elements inside one tile.  The
+    block is the near-field part of A[b, b], the stated reading: the inverse the library
+    built inverts the exported near field restricted to the tile, and the far part inside
+    the tile that it leaves out is non-zero (the preconditioned solve above still reaches
+    the oracle's solution)."""
+    g, s, A, So, Ho, bj = case(B, orc, "sphere_L3_d1_laplace_leaf_eq_L")
+    N = s.ndof
+    Afull = np.stack([Ho.apply(np.eye(N)[:, j]) for j in range(N)], 1)
+    rowptr, col, val = A.export_near()
+    Nn = np.zeros((N, N))
+    for r in range(N):
+        Nn[r, col[rowptr[r]:rowptr[r + 1]]] = val[rowptr[r]:rowptr[r + 1]]
+    inv = A.precond_export(1)
+    far_inside = 0.0
+    for k in range(bj.ntiles):
+        sl, dofs = slots(bj, k)
+        Dn = Nn[np.ix_(dofs, dofs)]
+        assert np.max(np.abs(inv[k][np.ix_(sl, sl)] @ Dn - np.eye(len(sl)))) <= 1e-11, k
+        far_inside = max(far_inside, float(np.max(np.abs(Afull[np.ix_(dofs, dofs)] - Dn))))
+    print(f"largest far entry inside a tile: {far_inside:.2e} (largest entry {np.abs(Afull).max():.2e})")
+    assert far_inside > 1e-6 * np.abs(Afull).max()
