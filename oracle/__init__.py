@@ -92,6 +92,17 @@ def lib():
             "orc_bj_target": (I, [P, I64, I, P]),
             "orc_h2_gmres_bj": (I, [P, P, P, P, D, I, I, P]),
             "orc_tile_features": (I, [P, I, P]),
+            "orc_mspace_new": (I, [I, P, I, D, D, I, I, P]),
+            "orc_mspace_new_nurbs": (I, [I, P, P, P, D, D, I, I, P]),
+            "orc_mspace_free": (None, [P]),
+            "orc_mspace_info": (I, [P, P]),
+            "orc_mspace_glue": (I, [P, P, P]),
+            "orc_m_elem_eval": (I, [P, I64, D, D, P, P, P, P]),
+            "orc_m_pair_block": (I, [P, I64, I64, I, I, I, P]),
+            "orc_m_dense": (I, [P, I, I, I, P]),
+            "orc_m_rhs": (I, [P, I, P, I, I, P]),
+            "orc_m_potential": (I, [P, I, P, I64, P, P]),
+            "orc_m_field": (I, [I, P, D, D, I64, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -449,3 +460,98 @@ def user_map_patches(fn, npatch: int, degree: int = 5, intervals: int = 8):
         cw = np.concatenate([C, np.ones((k, k, 1))], axis=2)
         out.append({"degree": (degree, degree), "knots": (knots, knots), "cw": cw})
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# Maxwell single layer (App. A (MP), App. B (MS)) on the div-conforming spaces S^1 (App. E)
+DIPOLE, PLANE_WAVE_E = 0, 1
+
+
+class MSpace:
+    """S^1 = S_p x S_{p-1} (x) S_{p-1} x S_p on every patch, lifted by the Piola transform and
+    glued by normal continuity (p >= 1), with the wavenumber of (MS)."""
+
+    def __init__(self, geom: int, gparams=(), kappa: complex = 1.0, p: int = 1, level: int = 0):
+        h = ctypes.c_void_p()
+        if geom == NURBS:
+            meta, knots, cw = [], [], []
+            for P in gparams:
+                c = np.asarray(P["cw"], dtype=np.float64)
+                meta += [int(P["degree"][0]), int(P["degree"][1]), c.shape[0], c.shape[1]]
+                knots += [np.asarray(P["knots"][0], dtype=np.float64), np.asarray(P["knots"][1], dtype=np.float64)]
+                cw.append(c.reshape(-1))
+            m = np.ascontiguousarray(meta, dtype=np.int32)
+            kn = np.ascontiguousarray(np.concatenate(knots))
+            cc = np.ascontiguousarray(np.concatenate(cw))
+            _check(lib().orc_mspace_new_nurbs(len(gparams), m.ctypes.data, _p(kn), _p(cc), float(np.real(kappa)),
+                                              float(np.imag(kappa)), p, level, ctypes.byref(h)))
+        else:
+            gp = np.ascontiguousarray(np.asarray(gparams, dtype=np.float64).reshape(-1))
+            if gp.size == 0:
+                gp = np.zeros(1)
+            _check(lib().orc_mspace_new(geom, _p(gp), int(len(gparams)), float(np.real(kappa)),
+                                        float(np.imag(kappa)), p, level, ctypes.byref(h)))
+        self._h = h
+        self.kappa, self.p, self.level = complex(kappa), p, level
+        info = np.zeros(4, dtype=np.int64)
+        _check(lib().orc_mspace_info(self._h, _p(info)))
+        self.nloc, self.nglob, self.nelem, self.nl = (int(v) for v in info)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                lib().orc_mspace_free(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+    def glue(self):
+        """(local -> global map with -1 for dropped functions, sign of each local function)."""
+        g = np.zeros(self.nloc, dtype=np.int64)
+        sg = np.zeros(self.nloc, dtype=np.int32)
+        _check(lib().orc_mspace_glue(self._h, _p(g), sg.ctypes.data))
+        return g, sg
+
+    def elem_eval(self, e: int, s: float, t: float):
+        """(point, lifted fields (nl, 3), reference divergences (nl,), local indices (nl,))."""
+        x = np.zeros(3)
+        V = np.zeros((self.nl, 3))
+        D = np.zeros(self.nl)
+        lid = np.zeros(self.nl, dtype=np.int64)
+        _check(lib().orc_m_elem_eval(self._h, e, s, t, _p(x), _p(V), _p(D), _p(lid)))
+        return x, V, D, lid
+
+    def pair_block(self, e1: int, e2: int, qg: int = 8, qs: int = 8, part: int = 0) -> np.ndarray:
+        B = np.zeros((self.nl, self.nl), dtype=np.complex128)
+        _check(lib().orc_m_pair_block(self._h, e1, e2, qg, qs, part, _p(B)))
+        return B
+
+    def dense(self, qg: int = 8, qs: int = 8, part: int = 0) -> np.ndarray:
+        """Galerkin matrix on the global functions (row: test, column: trial); part 1: the
+        vector term only, 2: the divergence term only."""
+        M = np.zeros((self.nglob, self.nglob), dtype=np.complex128)
+        _check(lib().orc_m_dense(self._h, qg, qs, part, _p(M)))
+        return M
+
+    def rhs(self, kind: int, params, q: int = 8) -> np.ndarray:
+        prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, 6))
+        b = np.zeros((prm.shape[0], self.nglob), dtype=np.complex128)
+        _check(lib().orc_m_rhs(self._h, kind, _p(prm), prm.shape[0], q, _p(b)))
+        return b[0] if prm.shape[0] == 1 else b
+
+    def potential(self, j, pts, q: int = 8) -> np.ndarray:
+        j = np.ascontiguousarray(j, dtype=np.complex128)
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        E = np.zeros((pts.shape[0], 3), dtype=np.complex128)
+        _check(lib().orc_m_potential(self._h, q, _p(j), pts.shape[0], _p(pts), _p(E)))
+        return E
+
+
+def m_field(kind: int, params, kappa: complex, pts) -> np.ndarray:
+    """Data fields of (MP): kind DIPOLE (x0, moment) or PLANE_WAVE_E (direction, polarisation)."""
+    prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(6))
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    E = np.zeros((pts.shape[0], 3), dtype=np.complex128)
+    _check(lib().orc_m_field(kind, _p(prm), float(np.real(kappa)), float(np.imag(kappa)), pts.shape[0], _p(pts),
+                             _p(E)))
+    return E

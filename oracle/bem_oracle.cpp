@@ -1,6 +1,7 @@
 // Oracle of the isogeometric Galerkin BEM hot path: Laplace and Helmholtz single-layer
 // operators on multi-patch surfaces, assembled densely or as an interpolation-based H^2
-// matrix, plus the right-hand side, the potential and restarted GMRES.
+// matrix, plus the right-hand side, the potential and restarted GMRES; the Maxwell single
+// layer on div-conforming spaces, assembled densely, with its load vector and field.
 //
 // TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which is loaded by
 // tests/, by the smoke check and by the CPU-baseline leg of bench.py, and by nothing on the
@@ -8,13 +9,13 @@
 // (Bembel, arXiv 1906.00785), not to be fast.  It shares no code with the HIP library.
 //
 // Paper sections followed (cited by section / equation, never by line):
-//   App. A  PDEs (LP), (HP)                     App. B  single-layer ansatz (LS), (HS), (BIE)
+//   App. A  PDEs (LP), (HP), (MP)               App. B  single-layer ansatz (LS), (HS), (MS), (BIE)
 //   App. C  B-spline recursion                  App. D  multi-patch B-rep, matching condition
-//   App. E  spline spaces S^2, Piola lifting    Sec. 2  singular integrals by regularisation,
+//   App. E  spaces S^0, S^1, S^2, Piola lifting Sec. 2  singular integrals by regularisation,
 //                                                       embedded FMM / H^2 on the unit square
 //   Sec. 4  API: Discretization, computeRhs, HierarchicalMatrix, H*x, GMRES, evalSolution
-// Where the paper is silent the readings used are the ones listed in the design doc (A1..A23);
-// each is named in the function that takes it.
+// Where the paper is silent a reading is taken (A1..A23 and the named ones below); each is
+// stated in the function that takes it.
 //
 // Parity status: every function here is pinned by a CPU test (tests/test_oracle_*.py)
 // against a closed form, an invariant, a library routine or brute force.  The compressed
@@ -638,6 +639,66 @@ static PairInfo classify_pair(const Space& S, int64_t e1, int64_t e2) {
     throw std::runtime_error("no symmetry aligns the shared entity (matching condition)");
 }
 
+// Duffy-type regularisation of a touching pair (Sec. 2 cites [SS97]; regions of reading
+// A6): calls f(x1, x2, y1, y2, w) for every point of every region's 4D unit cube, qs Gauss
+// points per dimension, with local points x (first element) and y (second element) in the
+// aligned frames and w the Gauss weight times the substitution's Jacobian.
+template <class F>
+static void duffy_each(int type, int qs, F&& f) {
+    const Rule g = gauss01(qs);
+    for (int i0 = 0; i0 < qs; ++i0)
+        for (int i1 = 0; i1 < qs; ++i1)
+            for (int i2 = 0; i2 < qs; ++i2)
+                for (int i3 = 0; i3 < qs; ++i3) {
+                    const double xi = g.x[i0], e1v = g.x[i1], e2v = g.x[i2], e3v = g.x[i3];
+                    const double wq = g.w[i0] * g.w[i1] * g.w[i2] * g.w[i3];
+                    if (type == PAIR_IDENTICAL) {
+                        // (xi, eta, u1, u2); the difference vector y - x = (s1 t1, s2 t2)
+                        const double u1 = e2v, u2 = e3v;
+                        for (int ord = 0; ord < 2; ++ord) {
+                            const double t1 = ord == 0 ? xi : xi * e1v;
+                            const double t2 = ord == 0 ? xi * e1v : xi;
+                            for (int sg = 0; sg < 4; ++sg) {
+                                const double s1 = (sg & 1) ? -1.0 : 1.0;
+                                const double s2 = (sg & 2) ? -1.0 : 1.0;
+                                const double x1 = (1.0 - t1) * u1 + (s1 < 0 ? t1 : 0.0);
+                                const double x2 = (1.0 - t2) * u2 + (s2 < 0 ? t2 : 0.0);
+                                const double y1 = x1 + s1 * t1, y2 = x2 + s2 * t2;
+                                f(x1, x2, y1, y2, wq * xi * (1.0 - t1) * (1.0 - t2));
+                            }
+                        }
+                    } else if (type == PAIR_EDGE) {
+                        // shared edge at local first coordinate 0 on both sides; (xi, eta1,
+                        // eta2, u): the largest of (x1, y1, t) is xi
+                        const double u = e3v;
+                        for (int c = 0; c < 3; ++c) {
+                            double v3[3];
+                            v3[c] = xi;
+                            int m = 0;
+                            for (int k = 0; k < 3; ++k)
+                                if (k != c) v3[k] = xi * (m++ == 0 ? e1v : e2v);
+                            const double x1 = v3[0], y1 = v3[1], t = v3[2];
+                            for (int sg = 0; sg < 2; ++sg) {
+                                const double s2 = sg ? -1.0 : 1.0;
+                                const double x2 = (1.0 - t) * u + (s2 < 0 ? t : 0.0);
+                                const double y2 = x2 + s2 * t;
+                                f(x1, x2, y1, y2, wq * xi * xi * (1.0 - t));
+                            }
+                        }
+                    } else {  // PAIR_VERTEX: shared vertex at local (0,0) on both sides
+                        for (int c = 0; c < 4; ++c) {
+                            double z[4];
+                            z[c] = xi;
+                            int m = 0;
+                            const double et[3] = {e1v, e2v, e3v};
+                            for (int k = 0; k < 4; ++k)
+                                if (k != c) z[k] = xi * et[m++];
+                            f(z[0], z[1], z[2], z[3], wq * xi * xi * xi);
+                        }
+                    }
+                }
+}
+
 // ---------------------------------------------------------------------------------------
 // Element-pair integral  B[i][j] = int_tau int_sigma k(x,y) Phi_i(x) Psi_j(y)  over the
 // two elements' parameter squares (each of area h^2).
@@ -684,69 +745,16 @@ static void pair_block(const Space& S, const SideFn& Ft, const SideFn& Fs, int64
         return;
     }
 
-    const Rule g = gauss01(qs);
     std::vector<double> pt(nt), ps(ns);
     double xv[3], yv[3];
     // accumulate one point of a Duffy cube: local points xh (on tau) and yh (on sigma)
-    auto acc = [&](double xh1, double xh2, double yh1, double yh2, double w) {
+    duffy_each(P.type, qs, [&](double xh1, double xh2, double yh1, double yh2, double w) {
         side_eval(S, Ft, A, P.k1, xh1, xh2, xv, pt.data());
         side_eval(S, Fs, Bel, P.k2, yh1, yh2, yv, ps.data());
         T kv = kernel_r<T>(S.pde, S.kappa, dist3(xv, yv)) * w;
         for (int i = 0; i < nt; ++i)
             for (int j = 0; j < ns; ++j) B[i * ns + j] += kv * pt[i] * ps[j];
-    };
-
-    for (int i0 = 0; i0 < qs; ++i0)
-        for (int i1 = 0; i1 < qs; ++i1)
-            for (int i2 = 0; i2 < qs; ++i2)
-                for (int i3 = 0; i3 < qs; ++i3) {
-                    const double xi = g.x[i0], e1v = g.x[i1], e2v = g.x[i2], e3v = g.x[i3];
-                    const double wq = g.w[i0] * g.w[i1] * g.w[i2] * g.w[i3];
-                    if (P.type == PAIR_IDENTICAL) {
-                        // (xi, eta, u1, u2); the difference vector y - x = (s1 t1, s2 t2)
-                        const double u1 = e2v, u2 = e3v;
-                        for (int ord = 0; ord < 2; ++ord) {
-                            const double t1 = ord == 0 ? xi : xi * e1v;
-                            const double t2 = ord == 0 ? xi * e1v : xi;
-                            for (int sg = 0; sg < 4; ++sg) {
-                                const double s1 = (sg & 1) ? -1.0 : 1.0;
-                                const double s2 = (sg & 2) ? -1.0 : 1.0;
-                                const double x1 = (1.0 - t1) * u1 + (s1 < 0 ? t1 : 0.0);
-                                const double x2 = (1.0 - t2) * u2 + (s2 < 0 ? t2 : 0.0);
-                                const double y1 = x1 + s1 * t1, y2 = x2 + s2 * t2;
-                                acc(x1, x2, y1, y2, wq * xi * (1.0 - t1) * (1.0 - t2));
-                            }
-                        }
-                    } else if (P.type == PAIR_EDGE) {
-                        // shared edge at local first coordinate 0 on both sides; (xi, eta1,
-                        // eta2, u): the largest of (x1, y1, t) is xi
-                        const double u = e3v;
-                        for (int c = 0; c < 3; ++c) {
-                            double v3[3];
-                            v3[c] = xi;
-                            int m = 0;
-                            for (int k = 0; k < 3; ++k)
-                                if (k != c) v3[k] = xi * (m++ == 0 ? e1v : e2v);
-                            const double x1 = v3[0], y1 = v3[1], t = v3[2];
-                            for (int sg = 0; sg < 2; ++sg) {
-                                const double s2 = sg ? -1.0 : 1.0;
-                                const double x2 = (1.0 - t) * u + (s2 < 0 ? t : 0.0);
-                                const double y2 = x2 + s2 * t;
-                                acc(x1, x2, y1, y2, wq * xi * xi * (1.0 - t));
-                            }
-                        }
-                    } else {  // PAIR_VERTEX: shared vertex at local (0,0) on both sides
-                        for (int c = 0; c < 4; ++c) {
-                            double z[4];
-                            z[c] = xi;
-                            int m = 0;
-                            const double et[3] = {e1v, e2v, e3v};
-                            for (int k = 0; k < 4; ++k)
-                                if (k != c) z[k] = xi * et[m++];
-                            acc(z[0], z[1], z[2], z[3], wq * xi * xi * xi);
-                        }
-                    }
-                }
+    });
     for (int i = 0; i < nt * ns; ++i) B[i] *= h4;
 }
 
@@ -1722,6 +1730,371 @@ static void tile_features(const Space& S, const Tile& t, double* out) {
     out[98] = S.K.L / 8.0;
 }
 
+// ---------------------------------------------------------------------------------------
+// Maxwell single layer: the electric wave equation (App. A (MP)) through the single-layer
+// ansatz (MS) of App. B, on the div-conforming spaces S^1 of App. E.
+//
+// Reference space (App. E): S^1 = S_p (x) S_{p-1}  x  S_{p-1} (x) S_p on the unit square,
+// p >= 1, the degree p - 1 factor on the truncated knot vector (the clamped uniform knots of
+// degree p - 1).  Component 0 is the field b^p_j1(s) b^{p-1}_j2(t) e_s, component 1 the
+// field b^{p-1}_j1(s) b^p_j2(t) e_t.  Lifting by the Piola transform of div-conforming
+// fields: j(gamma(s)) = D gamma(s) j_hat(s) / kappa(s) and div_Gamma j = div_hat j_hat /
+// kappa(s), so with d sigma = kappa ds the surface element cancels.  Testing the trace of
+// (MS) with v and moving the gradient onto v by integration by parts on the closed surface,
+//   a(j, v) = int int G(x, y) [ j(y) . v(x) - kappa^-2 div j(y) div v(x) ] d sigma d sigma
+//           = int int G [ (D gamma_x v_hat) . (D gamma_y j_hat) - kappa^-2 div v_hat div j_hat ] ds dt,
+// with G the Helmholtz kernel of (HS).  The load vector of data E is int E . v d sigma =
+// int E(gamma) . (D gamma v_hat) ds, and the field of a density is (MS) itself.
+//
+// Continuity (App. E: normal continuity gives S^1(Gamma) in H^-1/2(div)).  A reference field
+// has a normal component on an edge only for the functions whose degree-p index is first or
+// last (b^p_0 = 1 at 0, b^p_last = 1 at 1); its flux through the edge is the tangential
+// B-spline, which the matching condition (App. D) carries onto the neighbour's.  Reading:
+// the edge function of one patch and the one of the neighbour whose anchors (images of the
+// point (edge coordinate, a(tangential factor))) coincide within 1e-10 of
+// the largest anchor coordinate form one global function, the second with the sign
+// -o1 o2 (o = +1 where the reference direction leaves its patch, at coordinate 1, and -1
+// at coordinate 0), so that the flux leaving one patch enters the other.  An edge function
+// without a partner (open surface) is dropped: the normal trace vanishes on the boundary.
+// Global functions are numbered in the order of their first local function.
+// ---------------------------------------------------------------------------------------
+struct MSpace {
+    Geom G;
+    cplx kappa;
+    int p = 1, L = 0, nel = 1;
+    double h = 1.0;
+    Knots Kp, Kq;          // degree p and p - 1 on 2^L elements
+    int nbp = 0, nbq = 0;  // functions per direction of each degree
+    int64_t nelem = 0, nloc = 0, nglob = 0;
+    std::vector<int64_t> glob;  // local -> global (-1: dropped)
+    std::vector<int> sgn;       // sign of the local function in its global one
+    Space geo;                  // scalar space of the same geometry and level (pair classification)
+};
+
+// local function of patch f, component c, indices (j1, j2)
+static int64_t mlocal(const MSpace& S, int f, int c, int j1, int j2) {
+    const int64_t per = (int64_t)S.nbp * S.nbq;
+    return ((int64_t)f * 2 + c) * per + (c == 0 ? (int64_t)j1 * S.nbq + j2 : (int64_t)j1 * S.nbp + j2);
+}
+
+// Anchor a(j) of B-spline j along an edge: the mean of its Greville abscissa and the centre
+// of its support [xi_j, xi_{j+d+1}].  Both are symmetric under reversal of the parameter; the
+// Greville abscissae increase strictly with j and the centres do not decrease, so the
+// anchors are distinct, and they lie strictly inside (0, 1) (the Greville abscissa alone
+// puts the first and last function on the patch corners, the centre alone can repeat).
+static double edge_anchor(const Knots& K, int j) {
+    double gr;
+    if (K.d == 0) {
+        gr = 0.5 * (K.xi[j] + K.xi[j + 1]);
+    } else {
+        gr = 0.0;
+        for (int k = 1; k <= K.d; ++k) gr += K.xi[j + k];
+        gr /= K.d;
+    }
+    return 0.5 * (gr + 0.5 * (K.xi[j] + K.xi[j + K.d + 1]));
+}
+
+static MSpace make_mspace(const Geom& G, cplx kappa, int p, int L) {
+    if (p < 1 || L < 0) throw std::runtime_error("S^1 needs p >= 1 and L >= 0");
+    MSpace S;
+    S.G = G;
+    S.kappa = kappa;
+    S.p = p;
+    S.L = L;
+    S.Kp = make_knots(p, 1, L);
+    S.Kq = make_knots(p - 1, 1, L);
+    S.nbp = S.Kp.nb;
+    S.nbq = S.Kq.nb;
+    S.nel = 1 << L;
+    S.h = 1.0 / S.nel;
+    S.geo = make_space(G, PDE_HELMHOLTZ, kappa, 0, 1, L);
+    S.nelem = (int64_t)G.npatch * S.nel * S.nel;
+    S.nloc = (int64_t)G.npatch * 2 * S.nbp * S.nbq;
+    // anchors of the edge functions
+    struct Anc {
+        double x[3];
+        int64_t lid;
+        int o;
+    };
+    std::vector<Anc> an;
+    std::vector<int> edge(S.nloc, 0), orient(S.nloc, 0);
+    double scale = 0.0;
+    for (int f = 0; f < G.npatch; ++f)
+        for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 2; ++e) {
+                const int jn = e == 0 ? 0 : S.nbp - 1;
+                for (int jt = 0; jt < S.nbq; ++jt) {
+                    Anc a;
+                    const double en = e == 0 ? 0.0 : 1.0, tg = edge_anchor(S.Kq, jt);
+                    if (c == 0) {
+                        gamma(G, f, en, tg, a.x);
+                        a.lid = mlocal(S, f, 0, jn, jt);
+                    } else {
+                        gamma(G, f, tg, en, a.x);
+                        a.lid = mlocal(S, f, 1, jt, jn);
+                    }
+                    a.o = e == 0 ? -1 : 1;
+                    edge[a.lid] = 1;
+                    orient[a.lid] = a.o;
+                    for (double v : a.x) scale = std::max(scale, std::fabs(v));
+                    an.push_back(a);
+                }
+            }
+    const double tol = 1e-10 * std::max(scale, 1e-300);
+    std::vector<int64_t> partner(S.nloc, -1);
+    for (size_t a = 0; a < an.size(); ++a)
+        for (size_t b = 0; b < an.size(); ++b) {
+            if (a == b || dist3(an[a].x, an[b].x) > tol) continue;
+            if (partner[an[a].lid] >= 0 && partner[an[a].lid] != an[b].lid)
+                throw std::runtime_error("an edge function matches more than one neighbour");
+            partner[an[a].lid] = an[b].lid;
+        }
+    S.glob.assign(S.nloc, -2);
+    S.sgn.assign(S.nloc, 1);
+    int64_t n = 0;
+    for (int64_t l = 0; l < S.nloc; ++l) {
+        if (S.glob[l] != -2) continue;
+        if (!edge[l]) {
+            S.glob[l] = n++;
+        } else if (partner[l] < 0) {
+            S.glob[l] = -1;
+            S.sgn[l] = 0;
+        } else {
+            const int64_t m = partner[l];
+            S.glob[l] = S.glob[m] = n++;
+            S.sgn[l] = 1;
+            S.sgn[m] = -orient[l] * orient[m];
+        }
+    }
+    S.nglob = n;
+    return S;
+}
+
+// derivative of B-spline j of degree K.d at x in span `span` (App. C recursion differentiated)
+static double dbspline(const Knots& K, int j, double x, int span) {
+    const int p = K.d;
+    if (p == 0) return 0.0;
+    double v = 0.0;
+    const double d1 = K.xi[j + p] - K.xi[j], d2 = K.xi[j + p + 1] - K.xi[j + 1];
+    if (d1 > 0.0) v += p * bspline(K, j, p - 1, x, span) / d1;
+    if (d2 > 0.0) v -= p * bspline(K, j + 1, p - 1, x, span) / d2;
+    return v;
+}
+
+// the 2 p (p + 1) local functions of element E at parameter (s, t): lifted field V (3 per
+// function, D gamma times the reference field), reference divergence Dv and local index
+static int m_nl(const MSpace& S) { return 2 * S.p * (S.p + 1); }
+
+static void m_elem_eval(const MSpace& S, const Elem& E, double s, double t, double x[3], double* V, double* Dv,
+                        int64_t* lid) {
+    double xs[3], xt[3];
+    gamma(S.G, E.f, s, t, x, xs, xt);
+    const int p = S.p;
+    const int spp1 = elem_span(S.Kp, E.i1), spp2 = elem_span(S.Kp, E.i2);
+    const int spq1 = elem_span(S.Kq, E.i1), spq2 = elem_span(S.Kq, E.i2);
+    int k = 0;
+    for (int l1 = 0; l1 <= p; ++l1)  // component 0: degree p in s, p - 1 in t
+        for (int l2 = 0; l2 < p; ++l2, ++k) {
+            const int j1 = E.i1 + l1, j2 = E.i2 + l2;
+            const double bs = bspline(S.Kp, j1, p, s, spp1), bt = bspline(S.Kq, j2, p - 1, t, spq2);
+            for (int c = 0; c < 3; ++c) V[3 * k + c] = xs[c] * bs * bt;
+            Dv[k] = dbspline(S.Kp, j1, s, spp1) * bt;
+            lid[k] = mlocal(S, E.f, 0, j1, j2);
+        }
+    for (int l1 = 0; l1 < p; ++l1)  // component 1: degree p - 1 in s, p in t
+        for (int l2 = 0; l2 <= p; ++l2, ++k) {
+            const int j1 = E.i1 + l1, j2 = E.i2 + l2;
+            const double bs = bspline(S.Kq, j1, p - 1, s, spq1), bt = bspline(S.Kp, j2, p, t, spp2);
+            for (int c = 0; c < 3; ++c) V[3 * k + c] = xt[c] * bs * bt;
+            Dv[k] = bs * dbspline(S.Kp, j2, t, spp2);
+            lid[k] = mlocal(S, E.f, 1, j1, j2);
+        }
+}
+
+// part: 0 the whole form, 1 the vector term only, 2 the divergence term only (with its
+// factor -kappa^-2)
+static void m_pair_block(const MSpace& S, int64_t e1, int64_t e2, int qg, int qs, int part, cplx* B) {
+    const int nl = m_nl(S);
+    for (int i = 0; i < nl * nl; ++i) B[i] = cplx(0.0);
+    const Elem A = elem_of(S.geo, e1), Bel = elem_of(S.geo, e2);
+    const PairInfo P = classify_pair(S.geo, e1, e2);
+    const double h4 = S.h * S.h * S.h * S.h;
+    const cplx ik2 = -1.0 / (S.kappa * S.kappa);
+    const double wv = part == 2 ? 0.0 : 1.0;
+    const cplx wd = part == 1 ? cplx(0.0) : ik2;
+    std::vector<double> Vx(3 * nl), Vy(3 * nl), Dx(nl), Dy(nl);
+    std::vector<int64_t> lx(nl), ly(nl);
+    double xv[3], yv[3];
+    auto accum = [&](double w) {
+        const cplx kv = kernel_r<cplx>(PDE_HELMHOLTZ, S.kappa, dist3(xv, yv)) * w;
+        for (int i = 0; i < nl; ++i)
+            for (int j = 0; j < nl; ++j) {
+                const double vv = Vx[3 * i] * Vy[3 * j] + Vx[3 * i + 1] * Vy[3 * j + 1] + Vx[3 * i + 2] * Vy[3 * j + 2];
+                B[i * nl + j] += kv * (wv * vv + wd * (Dx[i] * Dy[j]));
+            }
+    };
+    if (P.type == PAIR_REGULAR) {
+        const Rule g = gauss01(qg);
+        for (int a1 = 0; a1 < qg; ++a1)
+            for (int a2 = 0; a2 < qg; ++a2) {
+                double s, t;
+                elem_param(S.geo, A, 0, g.x[a1], g.x[a2], s, t);
+                m_elem_eval(S, A, s, t, xv, Vx.data(), Dx.data(), lx.data());
+                for (int b1 = 0; b1 < qg; ++b1)
+                    for (int b2 = 0; b2 < qg; ++b2) {
+                        double s2, t2;
+                        elem_param(S.geo, Bel, 0, g.x[b1], g.x[b2], s2, t2);
+                        m_elem_eval(S, Bel, s2, t2, yv, Vy.data(), Dy.data(), ly.data());
+                        accum(g.w[a1] * g.w[a2] * g.w[b1] * g.w[b2]);
+                    }
+            }
+    } else {
+        duffy_each(P.type, qs, [&](double xh1, double xh2, double yh1, double yh2, double w) {
+            double s, t, s2, t2;
+            elem_param(S.geo, A, P.k1, xh1, xh2, s, t);
+            elem_param(S.geo, Bel, P.k2, yh1, yh2, s2, t2);
+            m_elem_eval(S, A, s, t, xv, Vx.data(), Dx.data(), lx.data());
+            m_elem_eval(S, Bel, s2, t2, yv, Vy.data(), Dy.data(), ly.data());
+            accum(w);
+        });
+    }
+    for (int i = 0; i < nl * nl; ++i) B[i] *= h4;
+}
+
+// local indices of element e's functions (in the order of m_elem_eval)
+static void m_elem_lids(const MSpace& S, int64_t e, int64_t* lid) {
+    const Elem E = elem_of(S.geo, e);
+    int k = 0;
+    for (int l1 = 0; l1 <= S.p; ++l1)
+        for (int l2 = 0; l2 < S.p; ++l2) lid[k++] = mlocal(S, E.f, 0, E.i1 + l1, E.i2 + l2);
+    for (int l1 = 0; l1 < S.p; ++l1)
+        for (int l2 = 0; l2 <= S.p; ++l2) lid[k++] = mlocal(S, E.f, 1, E.i1 + l1, E.i2 + l2);
+}
+
+// dense Galerkin matrix on the global functions (row = test, column = trial), row-major
+static void m_dense(const MSpace& S, int qg, int qs, int part, cplx* M) {
+    const int64_t N = S.nglob, ne = S.nelem;
+    const int nl = m_nl(S);
+    std::fill(M, M + N * N, cplx(0.0));
+    std::vector<std::vector<cplx>> rows(ne);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e1 = 0; e1 < ne; ++e1) {
+        rows[e1].assign((size_t)ne * nl * nl, cplx(0.0));
+        for (int64_t e2 = 0; e2 < ne; ++e2) m_pair_block(S, e1, e2, qg, qs, part, &rows[e1][(size_t)e2 * nl * nl]);
+    }
+    std::vector<int64_t> l1(nl), l2(nl);
+    for (int64_t e1 = 0; e1 < ne; ++e1) {
+        m_elem_lids(S, e1, l1.data());
+        for (int64_t e2 = 0; e2 < ne; ++e2) {
+            m_elem_lids(S, e2, l2.data());
+            const cplx* B = &rows[e1][(size_t)e2 * nl * nl];
+            for (int i = 0; i < nl; ++i) {
+                const int64_t g = S.glob[l1[i]];
+                if (g < 0) continue;
+                for (int j = 0; j < nl; ++j) {
+                    const int64_t hcol = S.glob[l2[j]];
+                    if (hcol < 0) continue;
+                    M[g * N + hcol] += (double)(S.sgn[l1[i]] * S.sgn[l2[j]]) * B[i * nl + j];
+                }
+            }
+        }
+        std::vector<cplx>().swap(rows[e1]);
+    }
+}
+
+// Data fields (solutions of (MP) away from their source).  kind 0: the field of a point
+// dipole of moment m at x0, E = curl curl (m G(x - x0)) = kappa^2 m G + grad (m . grad G);
+// kind 1: a plane wave E = e exp(-i kappa d . x) (e perpendicular to d), the sign of the
+// exponent matching the kernel's.
+static void m_field(int kind, const double* prm, cplx kappa, const double x[3], cplx E[3]) {
+    if (kind == 0) {
+        const double R[3] = {x[0] - prm[0], x[1] - prm[1], x[2] - prm[2]};
+        const double r = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        const cplx ik = cplx(0.0, 1.0) * kappa, ex = std::exp(-ik * r) / (4.0 * PI);
+        const cplx G = ex / r;
+        const cplx G1 = -ex * (1.0 + ik * r) / (r * r);                          // G'(r)
+        const cplx G2 = ex * (2.0 + 2.0 * ik * r + ik * ik * r * r) / (r * r * r);  // G''(r)
+        const cplx g = G1 / r, gp = (G2 - G1 / r) / r;  // g(r) = G'/r and its derivative
+        const double mR = prm[3] * R[0] + prm[4] * R[1] + prm[5] * R[2];
+        for (int c = 0; c < 3; ++c) E[c] = kappa * kappa * prm[3 + c] * G + gp * mR * R[c] / r + g * prm[3 + c];
+    } else {
+        const cplx ph = std::exp(-cplx(0.0, 1.0) * kappa * (prm[0] * x[0] + prm[1] * x[1] + prm[2] * x[2]));
+        for (int c = 0; c < 3; ++c) E[c] = prm[3 + c] * ph;
+    }
+}
+
+// load vector b_g = int E . v_g d sigma, q x q Gauss points per element
+static void m_rhs(const MSpace& S, int kind, const double* prm, int q, cplx* b) {
+    const int nl = m_nl(S);
+    std::fill(b, b + S.nglob, cplx(0.0));
+    const Rule g = gauss01(q);
+    std::vector<double> V(3 * nl), Dv(nl);
+    std::vector<int64_t> lid(nl);
+    for (int64_t e = 0; e < S.nelem; ++e) {
+        const Elem E = elem_of(S.geo, e);
+        for (int a1 = 0; a1 < q; ++a1)
+            for (int a2 = 0; a2 < q; ++a2) {
+                const double s = (E.i1 + g.x[a1]) * S.h, t = (E.i2 + g.x[a2]) * S.h;
+                double x[3];
+                m_elem_eval(S, E, s, t, x, V.data(), Dv.data(), lid.data());
+                cplx F[3];
+                m_field(kind, prm, S.kappa, x, F);
+                const double w = g.w[a1] * g.w[a2] * S.h * S.h;
+                for (int i = 0; i < nl; ++i) {
+                    const int64_t G = S.glob[lid[i]];
+                    if (G < 0) continue;
+                    b[G] += (double)S.sgn[lid[i]] * w * (F[0] * V[3 * i] + F[1] * V[3 * i + 1] + F[2] * V[3 * i + 2]);
+                }
+            }
+    }
+}
+
+// field (MS) of the density j (global coefficients) at points: int G j + kappa^-2 grad int G div j
+static void m_potential(const MSpace& S, int q, const cplx* j, int64_t npts, const double* pts, cplx* out) {
+    const int nl = m_nl(S);
+    const Rule g = gauss01(q);
+    const cplx ik = cplx(0.0, 1.0) * S.kappa, ik2 = 1.0 / (S.kappa * S.kappa);
+    // the density and its divergence at every quadrature point
+    const int64_t nq = S.nelem * q * q;
+    std::vector<double> Y(3 * nq), W(nq);
+    std::vector<cplx> J(3 * nq), Dj(nq);
+    std::vector<double> V(3 * nl), Dv(nl);
+    std::vector<int64_t> lid(nl);
+    for (int64_t e = 0; e < S.nelem; ++e) {
+        const Elem E = elem_of(S.geo, e);
+        for (int a1 = 0; a1 < q; ++a1)
+            for (int a2 = 0; a2 < q; ++a2) {
+                const int64_t k = (e * q + a1) * q + a2;
+                const double s = (E.i1 + g.x[a1]) * S.h, t = (E.i2 + g.x[a2]) * S.h;
+                m_elem_eval(S, E, s, t, &Y[3 * k], V.data(), Dv.data(), lid.data());
+                W[k] = g.w[a1] * g.w[a2] * S.h * S.h;
+                cplx jj[3] = {0.0, 0.0, 0.0}, dd = 0.0;
+                for (int i = 0; i < nl; ++i) {
+                    const int64_t G = S.glob[lid[i]];
+                    if (G < 0) continue;
+                    const cplx c = (double)S.sgn[lid[i]] * j[G];
+                    for (int d = 0; d < 3; ++d) jj[d] += c * V[3 * i + d];
+                    dd += c * Dv[i];
+                }
+                for (int d = 0; d < 3; ++d) J[3 * k + d] = jj[d];
+                Dj[k] = dd;
+            }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        const double* x = &pts[3 * p];
+        cplx E[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = 0; k < nq; ++k) {
+            const double R[3] = {x[0] - Y[3 * k], x[1] - Y[3 * k + 1], x[2] - Y[3 * k + 2]};
+            const double r = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+            const cplx ex = std::exp(-ik * r) / (4.0 * PI);
+            const cplx G = ex / r, G1 = -ex * (1.0 + ik * r) / (r * r);
+            for (int d = 0; d < 3; ++d) E[d] += W[k] * (G * J[3 * k + d] + ik2 * G1 * (R[d] / r) * Dj[k]);
+        }
+        for (int d = 0; d < 3; ++d) out[3 * p + d] = E[d];
+    }
+}
+
 }  // namespace orc
 
 // =======================================================================================
@@ -2378,6 +2751,98 @@ int orc_h2_gmres_bj(void* hp, void* bp, const double* b, double* x, double tol, 
         stats[0] = it;
         stats[1] = rr;
         stats[2] = rc == 0 ? 1.0 : 0.0;
+    })
+}
+
+// ---- Maxwell single layer on S^1 (App. A (MP), App. B (MS), App. E)
+struct OrcMSpace {
+    MSpace S;
+};
+
+int orc_mspace_new(int gkind, const double* gparams, int nparams, double kre, double kim, int p, int level,
+                   void** out) {
+    ORC_TRY({
+        OrcMSpace* s = new OrcMSpace;
+        try {
+            s->S = make_mspace(make_geom(gkind, gparams, nparams), cplx(kre, kim), p, level);
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = s;
+    })
+}
+
+int orc_mspace_new_nurbs(int npatch, const int* meta, const double* knots, const double* cw, double kre, double kim,
+                         int p, int level, void** out) {
+    ORC_TRY({
+        OrcMSpace* s = new OrcMSpace;
+        try {
+            s->S = make_mspace(make_nurbs_geom(npatch, meta, knots, cw), cplx(kre, kim), p, level);
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = s;
+    })
+}
+
+void orc_mspace_free(void* s) { delete (OrcMSpace*)s; }
+
+// info: local functions, global functions, elements, functions per element
+int orc_mspace_info(void* sp, int64_t* info) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        info[0] = S.nloc;
+        info[1] = S.nglob;
+        info[2] = S.nelem;
+        info[3] = m_nl(S);
+    })
+}
+
+int orc_mspace_glue(void* sp, int64_t* glob, int32_t* sgn) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        std::copy(S.glob.begin(), S.glob.end(), glob);
+        std::copy(S.sgn.begin(), S.sgn.end(), sgn);
+    })
+}
+
+// the local functions of element e at parameter (s, t): point, lifted fields, divergences
+int orc_m_elem_eval(void* sp, int64_t e, double s, double t, double* x, double* V, double* Dv, int64_t* lid) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        if (e < 0 || e >= S.nelem) throw std::runtime_error("element out of range");
+        m_elem_eval(S, elem_of(S.geo, e), s, t, x, V, Dv, lid);
+    })
+}
+
+int orc_m_pair_block(void* sp, int64_t e1, int64_t e2, int qg, int qs, int part, double* B) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        m_pair_block(S, e1, e2, qg, qs, part, (cplx*)B);
+    })
+}
+
+int orc_m_dense(void* sp, int qg, int qs, int part, double* M) {
+    ORC_TRY({ m_dense(((OrcMSpace*)sp)->S, qg, qs, part, (cplx*)M); })
+}
+
+// nrhs load vectors, 6 parameters each (dipole: x0, moment; plane wave: direction, polarisation)
+int orc_m_rhs(void* sp, int kind, const double* prm, int nrhs, int q, double* b) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        for (int r = 0; r < nrhs; ++r) m_rhs(S, kind, prm + 6 * r, q, (cplx*)b + (size_t)r * S.nglob);
+    })
+}
+
+int orc_m_potential(void* sp, int q, const double* j, int64_t npts, const double* pts, double* E) {
+    ORC_TRY({ m_potential(((OrcMSpace*)sp)->S, q, (const cplx*)j, npts, pts, (cplx*)E); })
+}
+
+int orc_m_field(int kind, const double* prm, double kre, double kim, int64_t npts, const double* pts, double* E) {
+    ORC_TRY({
+        for (int64_t p = 0; p < npts; ++p) m_field(kind, prm, cplx(kre, kim), &pts[3 * p], (cplx*)E + 3 * p);
     })
 }
 
