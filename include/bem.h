@@ -53,6 +53,11 @@ extern "C" {
 /* PDEs of Sec. 4 "PDE": single-layer kernels (LS) 1/(4 pi r) and (HS) exp(-i kappa r)/(4 pi r) */
 #define BEM_LAPLACE_SINGLE 0
 #define BEM_HELMHOLTZ_SINGLE 1
+/* Maxwell single layer (App. A (MP), App. B (MS)): for test and trial fields v, j on the
+ * surface, the bilinear form of the integrals over Gamma x Gamma of the Helmholtz kernel
+ * (HS) times v(x) . j(y) - kappa^-2 div_Gamma v(x) div_Gamma j(y) (the electric field
+ * integral operator); lives on S^1 spaces (bem_space_create_ex with BEM_SPACE_S1). */
+#define BEM_MAXWELL_SINGLE 2
 
 /* multi-patch geometries (App. D; arbitrary smooth maps are allowed, Sec. 4).  Analytic:
  *   SPHERE6     unit sphere, 6 cube faces projected radially               params: none
@@ -72,6 +77,15 @@ extern "C" {
  *   PLANE_WAVE    g(x) = exp(-i kappa d.x), Helmholtz only                  params: d (3)  */
 #define BEM_DATA_POINT_SOURCE 0
 #define BEM_DATA_PLANE_WAVE 1
+/* tangential data of the Maxwell single layer (S^1 spaces; b_g = int_Gamma E . psi_g with the
+ * lifted vector field psi_g of the global function g; 6 params per RHS):
+ *   DIPOLE        E = curl curl (m G(x - x0)) = kappa^2 G m + grad (m . grad G), G the (HS)
+ *                 kernel: the field of an electric dipole of moment m at x0, a solution of
+ *                 the Maxwell equations (App. A) away from x0          params: x0 (3), m (3)
+ *   PLANE_WAVE_E  E = e exp(-i kappa d . x)                            params: d (3), e (3)
+ *                 (a Maxwell solution when |d| = 1 and e . d = 0; not checked)           */
+#define BEM_DATA_DIPOLE 2
+#define BEM_DATA_PLANE_WAVE_E 3
 
 typedef struct bem_geometry_s* bem_geometry;
 typedef struct bem_space_s* bem_space;
@@ -130,7 +144,7 @@ typedef struct bem_operator_info {
     int64_t nstored;         /* stored coupling blocks (= nfar / 2) */
     int64_t nchunks;         /* work chunks of the coupling kernel */
     double transposed_bytes; /* bytes of the per-column transposed products */
-    int64_t nlocal;          /* local functions (patch by patch); = ndof except on S^0 spaces */
+    int64_t nlocal;          /* local functions (patch by patch); = ndof except on S^0 and S^1 spaces */
 } bem_operator_info;
 
 /* GMRES(m) parameters (reading: restart 30, x0 = 0, relative residual tolerance). */
@@ -236,6 +250,7 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
 /* The spline spaces of App. E on the patches: */
 #define BEM_SPACE_S2 2 /* S^2: discontinuous across patches, 2-form (Piola) lifting (default) */
 #define BEM_SPACE_S0 0 /* S^0: continuous across patch boundaries, 0-form lifting */
+#define BEM_SPACE_S1 1 /* S^1: div-conforming vector fields, normal continuity across patches */
 /* bem_space_create with the space kind.  S^0 (conforming in H^1/2; degree >= 1): the local
  * B-splines of a patch are lifted as phi = phi_hat o gamma^-1, so every surface integral
  * (Galerkin entries, moments, load vector, potential) carries the surface element kappa;
@@ -247,6 +262,29 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
  * densities, products, solutions) has the global length bem_space_ndof returns.  Operators
  * on S^0 spaces: FP64, one column per pass (far_low = 0, batch_rhs <= 1), no block
  * preconditioner, no grouped launches, no stage timing (EUNSUPPORTED). */
+/* S^1 (conforming in H^-1/2(div); kernel BEM_MAXWELL_SINGLE, which needs this space kind and
+ * kappa != 0; degree p = 1 or 2, EINVAL below, EUNSUPPORTED above; knot_repetition 1 only,
+ * EUNSUPPORTED otherwise): on every patch the reference fields of component 0,
+ * b^p_j1(s) b^{p-1}_j2(t) e_s (j1 < 2^L + p, j2 < 2^L + p - 1), and of component 1,
+ * b^{p-1}_j1(s) b^p_j2(t) e_t (j1 < 2^L + p - 1, j2 < 2^L + p), with the B-splines b of the
+ * indicated degrees on simple interior knots; local index
+ * (patch * 2 + component) * (2^L + p) * (2^L + p - 1) + (component 0: j1 * (2^L + p - 1) + j2,
+ * component 1: j1 * (2^L + p) + j2).  They are lifted by the Piola transform of vector fields
+ * (D gamma v_hat / kappa on the surface; divergence div v_hat / kappa).  The functions whose
+ * degree-p index is first or last have a normal component on that patch edge; by the
+ * matching condition (App. D) each meets one function of the neighbouring patch with the
+ * same trace of its tangential factor, and the two are glued into one global function, the
+ * second taken with the sign that makes the flux leaving one patch enter the other (reading:
+ * partners are the functions whose anchors coincide within 1e-10 of the largest coordinate,
+ * the anchor being the image of the edge point at the mean of the Greville abscissa and the
+ * support centre of the tangential factor).  Edge functions without a partner (open
+ * surfaces) are dropped.  Global functions are numbered in the order of their first local
+ * function; bem_space_glue gives the map (-1: dropped), bem_space_glue_sign the signs.
+ * Operators on S^1 spaces are dense (bem_assemble_plan needs eta = 0; far_low = 0,
+ * batch_rhs <= 1, far_eval = 0; 1 <= qg <= 8 and 1 <= qs <= 16; at most 32768 elements), FP64
+ * complex; bem_apply and bem_solve (no preconditioner, no refinement) work as for the other
+ * spaces; the block preconditioner, grouped launches, stage timing, the exports, the
+ * cluster-tree potential, sampled data and VTK output return EUNSUPPORTED. */
 int bem_space_create_ex(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
                         int knot_repetition, int level, int space_kind, bem_space* out);
 /* N: the space's functions (S^0: global, glued ones). */
@@ -255,12 +293,16 @@ int bem_space_ndof(bem_space s, int64_t* n);
  * *nlocal and, if glue_host is not NULL, the global function of each (host, nlocal entries;
  * the identity for S^2). */
 int bem_space_glue(bem_space s, int64_t* nlocal, int32_t* glue_host);
+/* Sign of every local function in its global function (host, nlocal entries): S^1 +1 or -1
+ * (0 for dropped functions), +1 on the other spaces. */
+int bem_space_glue_sign(bem_space s, int32_t* sign_host);
 void bem_space_destroy(bem_space s);
 
 /* Load vectors (Sec. 4 "Boundary Values"): b_g = int_Gamma g psi_g for nrhs data sets.
  * data_params: host array of 3 doubles per RHS.  b_dev: device, N x nrhs column-major with
  * leading dimension ldb >= N, written (not accumulated).  Gauss with 8 points per direction
- * per element.  EINVAL on PLANE_WAVE for Laplace. */
+ * per element.  EINVAL on PLANE_WAVE for Laplace.  S^1 spaces: the kinds DIPOLE and
+ * PLANE_WAVE_E only, 6 doubles per RHS, complex b. */
 int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, void* b_dev,
             int64_t ldb, hipStream_t stream);
 
@@ -334,7 +376,11 @@ int bem_solve(bem_operator A, const void* b_dev, int64_t ldb, void* x_dev, int64
  * the Solution"; App. B (LS)/(HS)), Gauss with 8 points per direction per element.
  * pts_dev: device, npts x 3 row-major.  rho_dev: device N x nrhs (leading dim ldr).
  * u_dev: device npts x nrhs column-major (leading dim ldu >= npts), overwritten.
- * With npts == 0 nothing is done and pts_dev, u_dev may be NULL. */
+ * With npts == 0 nothing is done and pts_dev, u_dev may be NULL.  S^1 spaces (Maxwell): the
+ * field (MS), E(x) = int_Gamma G(x - y) j(y) dsigma_y + kappa^-2 grad_x int_Gamma G(x - y)
+ * div_Gamma j(y) dsigma_y with the (HS) kernel G and the surface current j of the
+ * coefficients rho, by the same rule; u_dev then holds 3 complex values per point (npts x 3
+ * row-major per column, ldu >= 3 npts). */
 int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const void* rho_dev,
                        int64_t ldr, int nrhs, void* u_dev, int64_t ldu, hipStream_t stream);
 

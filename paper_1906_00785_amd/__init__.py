@@ -16,13 +16,15 @@ import numpy as np
 import torch
 
 from . import _bem as C
-from ._bem import (BEM_DATA_PLANE_WAVE, BEM_DATA_POINT_SOURCE, BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1, BEM_GEOM_NURBS,
-                   BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16, BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BEM_PREC_BF16,
-                   BEM_PREC_FP32, BEM_PREC_FP64, BemError)
+from ._bem import (BEM_DATA_DIPOLE, BEM_DATA_PLANE_WAVE, BEM_DATA_PLANE_WAVE_E, BEM_DATA_POINT_SOURCE,
+                   BEM_GEOM_ELLIPSOID6, BEM_GEOM_FLAT1, BEM_GEOM_NURBS, BEM_GEOM_SPHERE6, BEM_GEOM_TORUS16,
+                   BEM_HELMHOLTZ_SINGLE, BEM_LAPLACE_SINGLE, BEM_MAXWELL_SINGLE, BEM_PREC_BF16, BEM_PREC_FP32,
+                   BEM_PREC_FP64, BemError)
 
 __all__ = ["Geometry", "Space", "Operator", "BemError", "BEM_GEOM_SPHERE6", "BEM_GEOM_ELLIPSOID6",
            "BEM_GEOM_TORUS16", "BEM_GEOM_FLAT1", "BEM_GEOM_NURBS", "BEM_LAPLACE_SINGLE", "BEM_HELMHOLTZ_SINGLE",
-           "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE", "BEM_PREC_FP64", "BEM_PREC_FP32", "BEM_PREC_BF16"]
+           "BEM_MAXWELL_SINGLE", "BEM_DATA_POINT_SOURCE", "BEM_DATA_PLANE_WAVE", "BEM_DATA_DIPOLE",
+           "BEM_DATA_PLANE_WAVE_E", "BEM_PREC_FP64", "BEM_PREC_FP32", "BEM_PREC_BF16"]
 
 
 def _stream() -> int:
@@ -72,19 +74,26 @@ class Geometry:
 class Space:
     def __init__(self, geom: Geometry, kernel: int = BEM_LAPLACE_SINGLE, kappa: complex = 0.0, degree: int = 1,
                  knot_repetition: int = 1, level: int = 0, continuous: bool = False):
-        """continuous=True: the S^0 space (glued across patches, 0-form lifting); else S^2."""
-        self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level,
-                                    C.BEM_SPACE_S0 if continuous else C.BEM_SPACE_S2)
+        """continuous=True: the S^0 space (glued across patches, 0-form lifting); else S^2.  The
+        Maxwell single layer (kernel BEM_MAXWELL_SINGLE) takes the div-conforming S^1 space of
+        that degree (vector densities, complex)."""
+        self.vector = kernel == C.BEM_MAXWELL_SINGLE
+        kind = C.BEM_SPACE_S1 if self.vector else (C.BEM_SPACE_S0 if continuous else C.BEM_SPACE_S2)
+        self.h = C.bem_space_create(geom.h, kernel, kappa, degree, knot_repetition, level, kind)
         self.continuous = bool(continuous)
         self.geom = geom
         self.kernel, self.kappa, self.degree, self.level = kernel, complex(kappa), degree, level
         self.knot_repetition = knot_repetition
         self.ndof = C.bem_space_ndof(self.h)
-        self.dtype = torch.complex128 if kernel == BEM_HELMHOLTZ_SINGLE else torch.float64
+        self.dtype = torch.complex128 if kernel != BEM_LAPLACE_SINGLE else torch.float64
 
     def glue(self) -> np.ndarray:
-        """Global function of every local function (the identity for S^2)."""
+        """Global function of every local function (the identity for S^2; -1: dropped S^1 function)."""
         return C.bem_space_glue(self.h)[1]
+
+    def glue_sign(self) -> np.ndarray:
+        """Sign of every local function in its global function (+1 except on S^1 spaces)."""
+        return C.bem_space_glue_sign(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -95,7 +104,8 @@ class Space:
             self.h = None
 
     def rhs(self, data_kind: int, params) -> torch.Tensor:
-        """Load vectors, one per row of params (3 numbers each): tensor (nrhs, N)."""
+        """Load vectors, one per row of params (3 numbers each; 6 for the Maxwell data kinds):
+        tensor (nrhs, N)."""
         params = [tuple(float(v) for v in p) for p in params]
         b = torch.empty((len(params), self.ndof), dtype=self.dtype, device=_dev())
         C.bem_rhs(self.h, data_kind, params, len(params), b.data_ptr(), self.ndof, _stream())
@@ -125,9 +135,15 @@ class Space:
         C.bem_write_vtk(self.h, r.data_ptr(), self.ndof, r.shape[0], nsub, path)
 
     def potential(self, pts, rho: torch.Tensor) -> torch.Tensor:
-        """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,)."""
+        """Potential at points (npts, 3) for densities rho (nrhs, N) or (N,); for the Maxwell
+        single layer the field (MS), shape (nrhs, npts, 3) or (npts, 3)."""
         pts = torch.as_tensor(np.asarray(pts, dtype=np.float64)).to(_dev()).contiguous()
         r = rho.reshape(-1, self.ndof).contiguous()
+        if self.vector:
+            E = torch.empty((r.shape[0], pts.shape[0], 3), dtype=self.dtype, device=_dev())
+            C.bem_eval_potential(self.h, pts.data_ptr(), pts.shape[0], r.data_ptr(), self.ndof, r.shape[0],
+                                 E.data_ptr(), 3 * pts.shape[0], _stream())
+            return E[0] if rho.dim() == 1 else E
         u = torch.empty((r.shape[0], pts.shape[0]), dtype=self.dtype, device=_dev())
         C.bem_eval_potential(self.h, pts.data_ptr(), pts.shape[0], r.data_ptr(), self.ndof, r.shape[0], u.data_ptr(),
                              pts.shape[0], _stream())
@@ -137,10 +153,12 @@ class Space:
 class Operator:
     """Compressed single-layer operator: plan on the host, assemble on the GPU."""
 
-    def __init__(self, space: Space, q: int = 5, eta: float = 1.6, leaf_level: int = -1, qg: int = 8, qs: int = 8,
+    def __init__(self, space: Space, q: int = 5, eta: float | None = None, leaf_level: int = -1, qg: int = 8, qs: int = 8,
                  assemble: bool = True, chunk_cols: int = 0, far_low: int = 0, batch_rhs: int = 0,
                  far_eval: bool = False, kappa_adm: float = 0.0):
         self.space = space
+        if eta is None:
+            eta = 0.0 if space.vector else 1.6  # Maxwell operators are dense
         self.far_low = far_low
         self.batch_rhs = batch_rhs
         self.far_eval = bool(far_eval)

@@ -12,10 +12,10 @@ LIB_PATH = os.path.join(HERE, "libbem_hip.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bem.h")
 
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE = 0, 1
+BEM_LAPLACE_SINGLE, BEM_HELMHOLTZ_SINGLE, BEM_MAXWELL_SINGLE = 0, 1, 2
 BEM_GEOM_SPHERE6, BEM_GEOM_ELLIPSOID6, BEM_GEOM_TORUS16, BEM_GEOM_FLAT1, BEM_GEOM_NURBS = 0, 1, 2, 3, 4
-BEM_SPACE_S2, BEM_SPACE_S0 = 2, 0
-BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE = 0, 1
+BEM_SPACE_S2, BEM_SPACE_S0, BEM_SPACE_S1 = 2, 0, 1
+BEM_DATA_POINT_SOURCE, BEM_DATA_PLANE_WAVE, BEM_DATA_DIPOLE, BEM_DATA_PLANE_WAVE_E = 0, 1, 2, 3
 BEM_PREC_FP64, BEM_PREC_FP32, BEM_PREC_BF16 = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_BLOCK = 0, 1
 
@@ -66,6 +66,7 @@ _SIGNATURES = {
     "bem_space_create": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _P(_vp)]),
     "bem_space_create_ex": (_c_int, [_vp, _c_int, _c_dbl, _c_dbl, _c_int, _c_int, _c_int, _c_int, _P(_vp)]),
     "bem_space_glue": (_c_int, [_vp, _P(_c_i64), _vp]),
+    "bem_space_glue_sign": (_c_int, [_vp, _vp]),
     "bem_space_ndof": (_c_int, [_vp, _P(_c_i64)]),
     "bem_space_destroy": (None, [_vp]),
     "bem_rhs": (_c_int, [_vp, _c_int, _P(_c_dbl), _c_int, _vp, _c_i64, _vp]),
@@ -231,6 +232,17 @@ def bem_space_glue(s: int):
     m = np.zeros(n.value, dtype=np.int32)
     check(lib.bem_space_glue(s, ctypes.byref(n), m.ctypes.data))
     return n.value, m
+
+
+def bem_space_glue_sign(s: int):
+    """int32 array: sign of every local function in its global function."""
+    import numpy as np
+
+    n = _c_i64()
+    check(lib.bem_space_glue(s, ctypes.byref(n), None))
+    m = np.zeros(n.value, dtype=np.int32)
+    check(lib.bem_space_glue_sign(s, m.ctypes.data))
+    return m
 
 
 def bem_space_ndof(s: int) -> int:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem_hip.so")
-SOURCES = ["bem_plan.cpp", "bem_kernels.hip", "bem_batch.hip", "bem_solve.hip", "bem_bsolve.hip", "bem_precond.hip", "bem_mlp.hip", "bem_api.cpp"]
+SOURCES = ["bem_plan.cpp", "bem_kernels.hip", "bem_batch.hip", "bem_solve.hip", "bem_bsolve.hip", "bem_precond.hip", "bem_mlp.hip", "bem_maxwell.hip", "bem_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -22,6 +22,7 @@
 #include "bem_batch.h"
 #include "bem_kernels.h"
 #include "bem_mlp.h"
+#include "bem_maxwell.h"
 #include "bem_plan.h"
 #include "bem_precond.h"
 #include "bem_solve.h"
@@ -89,11 +90,37 @@ struct GlueTab {
     }
 };
 
+// S^1 (div-conforming) tables of a space: local B-spline polynomials of degrees p and p - 1,
+// the local -> global map with signs per element position, and the pieces of every global
+// function; host copies and device copies
+struct MxTab {
+    int p = 1, nbp = 0, nbq = 0, nl = 0;
+    int64_t nloc = 0, nglob = 0;
+    std::vector<double> polp, polq;
+    std::vector<int32_t> glob, sgn;    // per local function
+    std::vector<int32_t> eglob, esgn;  // per element position
+    std::vector<int64_t> gptr;
+    std::vector<int32_t> gpos, gsgn;
+    double* d_polp = nullptr;
+    double* d_polq = nullptr;
+    int32_t* d_eglob = nullptr;
+    int32_t* d_esgn = nullptr;
+    int64_t* d_gptr = nullptr;
+    int32_t* d_gpos = nullptr;
+    int32_t* d_gsgn = nullptr;
+    ~MxTab() {
+        for (void* q : {(void*)d_polp, (void*)d_polq, (void*)d_eglob, (void*)d_esgn, (void*)d_gptr, (void*)d_gpos,
+                        (void*)d_gsgn})
+            if (q) (void)hipFree(q);
+    }
+};
+
 struct bem_space_s {
     SpaceDesc S;
     BasisTab bt;
     std::shared_ptr<GeomTab> tab;    // keeps a NURBS geometry's tables alive
     std::shared_ptr<GlueTab> glue;   // S^0 only
+    std::shared_ptr<MxTab> mx;       // S^1 only
 };
 
 struct bem_operator_s {
@@ -110,6 +137,11 @@ struct bem_operator_s {
     std::vector<int64_t> tile_rowptr, tile_colptr, tile_voff;
     std::vector<int32_t> tile_rows, tile_cols;
     OpDev dev{};
+    // Maxwell single layer on S^1: dense operator (element-pair classification in plan)
+    bool mx = false;
+    MxDev mxd{};
+    std::vector<int32_t> mx_tinfo;  // host copies of the pair types and the Gauss rules (kept,
+    std::vector<double> mx_rules;   // the uploads are asynchronous)
     size_t scal = 8;  // bytes per scalar
     int far_low = 0;  // low-precision copy of the coupling blocks: 0 none, 1 FP32, 2 BF16
     int batch_rhs = 0;  // columns per many-RHS pass (slabs in the operator workspace)
@@ -366,6 +398,7 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws,
 // y = A x for one column of global functions: on an S^0 space the column is spread to the
 // local functions, multiplied, and the local products of each global function summed.
 static hipError_t op_apply(const bem_operator_s* A, int prec, const void* x, void* y, hipStream_t stream) {
+    if (A->mx) return launch_mx_matvec(A->mxd, x, y, stream);
     const SpaceDesc& S = A->dev.S;
     if (S.form != 0) return launch_apply(A->dev, x, y, prec, stream);
     const int cp = A->cplx ? 1 : 0;
@@ -998,6 +1031,184 @@ static bool build_glue(const SpaceDesc& S, GlueTab& T, int64_t& nglob) {
     return true;
 }
 
+// S^1 spaces (App. E): component 0 = b^p_j1(s) b^{p-1}_j2(t) e_s (j1 < nbp, j2 < nbq),
+// component 1 = b^{p-1}_j1(s) b^p_j2(t) e_t (j1 < nbq, j2 < nbp), local index
+// ((f * 2 + c) * nbp * nbq) + (c == 0 ? j1 * nbq + j2 : j1 * nbp + j2).
+static int64_t mx_local(const MxTab& T, int f, int c, int j1, int j2) {
+    const int64_t per = (int64_t)T.nbp * T.nbq;
+    return ((int64_t)f * 2 + c) * per + (c == 0 ? (int64_t)j1 * T.nbq + j2 : (int64_t)j1 * T.nbp + j2);
+}
+
+// Normal continuity across patch edges (App. E).  The functions whose degree-p index is first
+// or last carry a normal component on that edge, their flux being the tangential B-spline.
+// Each such edge function is anchored at the image of (edge coordinate, a), a the mean of
+// the Greville abscissa of its tangential factor and the centre of that factor's support
+// (distinct for distinct functions, strictly inside the edge, invariant under reversal of
+// the edge parameter); by the matching condition (App. D) the function of the neighbour
+// with the same anchor is its partner.  Partners form one global function, the second with
+// sign -o1 o2 (o = +1 where the reference direction leaves the patch, at coordinate 1, -1 at
+// coordinate 0), so that the flux leaving one patch enters the other; an edge function
+// without partner (open surface) is dropped.  Globals are numbered in local order.
+static bool build_mx(const SpaceDesc& S, int p, MxTab& T, std::string& err) {
+    const int nel = S.nel;
+    T.p = p;
+    T.nbp = nel + p;
+    T.nbq = nel + p - 1;
+    T.nl = 2 * p * (p + 1);
+    const int npatch = S.geom.npatch;
+    T.nloc = (int64_t)npatch * 2 * T.nbp * T.nbq;
+    // degree p - 1 knots: clamped, 2^L equal elements
+    std::vector<double> kq;
+    for (int i = 0; i < p; ++i) kq.push_back(0.0);
+    for (int k = 1; k < nel; ++k) kq.push_back((double)k / nel);
+    for (int i = 0; i < p; ++i) kq.push_back(1.0);
+    auto anchor = [&](int j) {
+        const int d = p - 1;
+        double gr;
+        if (d == 0) {
+            gr = 0.5 * (kq[j] + kq[j + 1]);
+        } else {
+            gr = 0.0;
+            for (int k = 1; k <= d; ++k) gr += kq[j + k];
+            gr /= d;
+        }
+        return 0.5 * (gr + 0.5 * (kq[j] + kq[j + d + 1]));
+    };
+    struct Anc {
+        double x[3];
+        int64_t lid;
+    };
+    std::vector<Anc> an;
+    std::vector<int8_t> orient(T.nloc, 0);  // 0: interior function
+    double scale = 0.0;
+    for (int f = 0; f < npatch; ++f)
+        for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 2; ++e) {
+                const int jn = e == 0 ? 0 : T.nbp - 1;
+                const double en = e == 0 ? 0.0 : 1.0;
+                for (int jt = 0; jt < T.nbq; ++jt) {
+                    Anc a;
+                    const double at = anchor(jt);
+                    if (c == 0) {
+                        patch_point(S.geom, f, en, at, a.x);
+                        a.lid = mx_local(T, f, 0, jn, jt);
+                    } else {
+                        patch_point(S.geom, f, at, en, a.x);
+                        a.lid = mx_local(T, f, 1, jt, jn);
+                    }
+                    orient[a.lid] = e == 0 ? -1 : 1;
+                    for (double v : a.x) scale = std::max(scale, std::fabs(v));
+                    an.push_back(a);
+                }
+            }
+    const double tol = 1e-10 * std::max(scale, 1e-300);
+    std::sort(an.begin(), an.end(), [](const Anc& u, const Anc& v) { return u.x[0] < v.x[0]; });
+    std::vector<int64_t> partner(T.nloc, -1);
+    for (size_t a = 0; a < an.size(); ++a)
+        for (size_t b = a + 1; b < an.size() && an[b].x[0] - an[a].x[0] <= tol; ++b)
+            if (std::fabs(an[a].x[1] - an[b].x[1]) <= tol && std::fabs(an[a].x[2] - an[b].x[2]) <= tol) {
+                if (partner[an[a].lid] >= 0 || partner[an[b].lid] >= 0) {
+                    err = "an S^1 edge function matches more than one neighbour (matching condition)";
+                    return false;
+                }
+                partner[an[a].lid] = an[b].lid;
+                partner[an[b].lid] = an[a].lid;
+            }
+    T.glob.assign(T.nloc, -2);
+    T.sgn.assign(T.nloc, 1);
+    int64_t n = 0;
+    for (int64_t l = 0; l < T.nloc; ++l) {
+        if (T.glob[l] != -2) continue;
+        if (orient[l] == 0) {
+            T.glob[l] = (int32_t)n++;
+        } else if (partner[l] < 0) {
+            T.glob[l] = -1;
+            T.sgn[l] = 0;
+        } else {
+            const int64_t m = partner[l];
+            T.glob[l] = T.glob[m] = (int32_t)n++;
+            T.sgn[m] = -orient[l] * orient[m];
+        }
+    }
+    T.nglob = n;
+    // per element position, in the order of the device evaluation (component 0 with l1 outer,
+    // then component 1), and the pieces of every global function in element order
+    T.eglob.assign((size_t)S.nelem * T.nl, -1);
+    T.esgn.assign((size_t)S.nelem * T.nl, 0);
+    std::vector<int64_t> cnt(T.nglob + 1, 0);
+    for (int64_t e = 0; e < S.nelem; ++e) {
+        const int i2 = (int)(e % nel), i1 = (int)((e / nel) % nel), f = (int)(e / ((int64_t)nel * nel));
+        int k = 0;
+        for (int l1 = 0; l1 <= p; ++l1)
+            for (int l2 = 0; l2 < p; ++l2, ++k) {
+                const int64_t l = mx_local(T, f, 0, i1 + l1, i2 + l2);
+                T.eglob[e * T.nl + k] = T.glob[l];
+                T.esgn[e * T.nl + k] = T.sgn[l];
+            }
+        for (int l1 = 0; l1 < p; ++l1)
+            for (int l2 = 0; l2 <= p; ++l2, ++k) {
+                const int64_t l = mx_local(T, f, 1, i1 + l1, i2 + l2);
+                T.eglob[e * T.nl + k] = T.glob[l];
+                T.esgn[e * T.nl + k] = T.sgn[l];
+            }
+    }
+    for (size_t q = 0; q < T.eglob.size(); ++q)
+        if (T.eglob[q] >= 0) ++cnt[T.eglob[q] + 1];
+    for (int64_t g = 0; g < T.nglob; ++g) cnt[g + 1] += cnt[g];
+    T.gptr = cnt;
+    T.gpos.assign(cnt[T.nglob], 0);
+    T.gsgn.assign(cnt[T.nglob], 0);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (size_t q = 0; q < T.eglob.size(); ++q)
+        if (T.eglob[q] >= 0) {
+            const int64_t at = fill[T.eglob[q]]++;
+            T.gpos[at] = (int32_t)q;
+            T.gsgn[at] = T.esgn[q];
+        }
+    bspline_local_polys(p, 1, S.L, T.polp);
+    bspline_local_polys(p - 1, 1, S.L, T.polq);
+    return true;
+}
+
+static hipError_t mx_upload(MxTab& T) {
+    auto put = [](auto** dst, const auto& v) -> hipError_t {
+        const size_t bytes = sizeof(v[0]) * std::max<size_t>(v.size(), 1);
+        hipError_t e = hipMalloc((void**)dst, bytes);
+        if (e != hipSuccess) return e;
+        return v.empty() ? hipSuccess : hipMemcpy(*dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice);
+    };
+    hipError_t e;
+    if ((e = put(&T.d_polp, T.polp)) != hipSuccess) return e;
+    if ((e = put(&T.d_polq, T.polq)) != hipSuccess) return e;
+    if ((e = put(&T.d_eglob, T.eglob)) != hipSuccess) return e;
+    if ((e = put(&T.d_esgn, T.esgn)) != hipSuccess) return e;
+    if ((e = put(&T.d_gptr, T.gptr)) != hipSuccess) return e;
+    if ((e = put(&T.d_gpos, T.gpos)) != hipSuccess) return e;
+    return put(&T.d_gsgn, T.gsgn);
+}
+
+// device description of an S^1 space (no operator parts)
+static MxDev mx_dev_of(const bem_space_s* s) {
+    const MxTab& T = *s->mx;
+    MxDev d{};
+    d.geom = s->S.geom;
+    d.ker = s->S.ker;
+    d.p = T.p;
+    d.nel = s->S.nel;
+    d.nl = T.nl;
+    d.h = s->S.h;
+    d.nelem = s->S.nelem;
+    d.nglob = T.nglob;
+    d.polp = T.d_polp;
+    d.polq = T.d_polq;
+    d.eglob = T.d_eglob;
+    d.esgn = T.d_esgn;
+    d.gptr = T.d_gptr;
+    d.gpos = T.d_gpos;
+    d.gsgn = T.d_gsgn;
+    return d;
+}
+
 // Checks and packs NURBS patches into a geometry (table in host and device memory).
 static int make_nurbs_geometry(int npatch, const int* meta, const double* knots, const double* cw,
                                bem_geometry* out) {
@@ -1231,6 +1442,174 @@ int bem_geometry_user(int npatch, bem_user_map gamma, void* user, int degree, in
     return make_nurbs_geometry(npatch, meta.data(), knots.data(), cw.data(), out);
 }
 
+}  // extern "C"
+
+// S^1 space (App. E) for the Maxwell single layer (MS): degree p in the normal direction of
+// each component, p - 1 along it, simple interior knots.
+static int create_s1(bem_geometry g, double kappa_re, double kappa_im, int p, int knot_repetition, int level,
+                     bem_space* out) {
+    if (p < 1) return fail(BEM_EINVAL, "S^1 spaces need degree >= 1");
+    if (level < 0 || level > 12) return fail(BEM_EINVAL, "level must lie in [0, 12]");
+    if (!std::isfinite(kappa_re) || !std::isfinite(kappa_im)) return fail(BEM_EINVAL, "wavenumber must be finite");
+    if (kappa_re == 0.0 && kappa_im == 0.0) return fail(BEM_EINVAL, "the Maxwell single layer needs a non-zero wavenumber");
+    if (p > kMxMaxP) return fail(BEM_EUNSUPPORTED, "S^1 spaces: this build supports degree <= 2");
+    if (knot_repetition != 1) return fail(BEM_EUNSUPPORTED, "S^1 spaces: simple interior knots only (knot repetition 1)");
+    SpaceDesc S{};
+    S.geom = g->g;
+    S.ker.pde = PDE_HELMHOLTZ;  // the fundamental solution of (MS)
+    S.ker.kre = kappa_re;
+    S.ker.kim = kappa_im;
+    S.d = p;
+    S.r = 1;
+    S.L = level;
+    S.nel = 1 << level;
+    S.nb = S.nel + p;
+    S.nelem = (int64_t)S.geom.npatch * S.nel * S.nel;
+    S.h = 1.0 / S.nel;
+    S.form = 1;
+    auto T = std::make_shared<MxTab>();
+    std::string err;
+    try {
+        if (!build_mx(S, p, *T, err)) return fail(BEM_EINVAL, err);
+    } catch (const std::bad_alloc&) {
+        return fail(BEM_ENOMEM, "host allocation failed");
+    }
+    if (T->nloc > 0x7fffffff || S.nelem * T->nl > 0x7fffffff) return fail(BEM_EINVAL, "too many functions for an S^1 space");
+    S.ndof = T->nloc;
+    S.nglob = T->nglob;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0)
+        HIP_CHECK(mx_upload(*T));
+    else
+        (void)hipGetLastError();
+    bem_space_s* sp = new (std::nothrow) bem_space_s;
+    if (!sp) return fail(BEM_ENOMEM, "host allocation failed");
+    sp->S = S;
+    sp->tab = g->tab;
+    sp->mx = T;
+    *out = sp;
+    return BEM_OK;
+}
+
+// S^1 kernels read the gluing tables from device memory.
+static int need_mx_device(const bem_space_s* s) {
+    if (s->S.geom.kind == GEOM_NURBS && !s->S.geom.tab_dev)
+        return fail(BEM_EDEVICE, "NURBS geometry created without a GPU: no device copy of its tables");
+    if (!s->mx->d_eglob) return fail(BEM_EDEVICE, "S^1 space created without a GPU: no device copy of its tables");
+    return BEM_OK;
+}
+
+// Workspace of a dense S^1 operator: the Galerkin matrix (op), and for the assembly the
+// element-pair blocks, the pair types and the two Gauss rules (tmp).
+static size_t mx_layout(const bem_operator_s& A, char* ob, char* tb, MxDev* d) {
+    const int64_t ne = A.mxd.nelem, nl = A.mxd.nl;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    if (ob) d->M = ob;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* q = tb ? tb + off : nullptr;
+        off += al(bytes);
+        return q;
+    };
+    char* B = take((size_t)ne * ne * nl * nl * 16);
+    char* ti = take((size_t)ne * ne * 4);
+    char* r = take(sizeof(double) * (2 * A.mxd.qg + 2 * A.mxd.qs));
+    if (tb) {
+        d->B = B;
+        d->tinfo = (const int32_t*)ti;
+        d->gx = (const double*)r;
+        d->gw = d->gx + A.mxd.qg;
+        d->sx = d->gw + A.mxd.qg;
+        d->sw = d->sx + A.mxd.qs;
+    }
+    return off + 256;  // + base alignment
+}
+
+// Plan of the dense Maxwell operator: every element pair, touching ones classified as for the
+// scalar near field (App. C: Duffy rules of the identical, edge and vertex cases).
+static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
+    if (p->eta != 0.0) return fail(BEM_EUNSUPPORTED, "S^1 operators are assembled densely: set eta = 0");
+    if (p->far_low != 0 || p->batch_rhs > 1 || p->far_eval != 0)
+        return fail(BEM_EUNSUPPORTED, "S^1 operators: FP64, one column per pass (far_low = 0, batch_rhs <= 1, far_eval = 0)");
+    if (p->qg < 1 || p->qg > 8 || p->qs < 1 || p->qs > 16)
+        return fail(BEM_EINVAL, "S^1 operators: qg must lie in [1, 8] and qs in [1, 16]");
+    const SpaceDesc& S = s->S;
+    if (S.nelem > 32768) return fail(BEM_EUNSUPPORTED, "S^1 operators: at most 32768 elements (dense pair table)");
+    std::vector<int64_t> pairs;
+    std::vector<int32_t> tinfo;
+    std::string err;
+    bem_operator_s* A = new (std::nothrow) bem_operator_s;
+    if (!A) return fail(BEM_ENOMEM, "host allocation failed");
+    try {
+        if (!element_touch_pairs(S, pairs, tinfo, err)) {
+            delete A;
+            return fail(BEM_EINVAL, err);
+        }
+        A->mx_tinfo.assign((size_t)(S.nelem * S.nelem), 0);
+        for (size_t k = 0; k < tinfo.size(); ++k) A->mx_tinfo[pairs[2 * k] * S.nelem + pairs[2 * k + 1]] = tinfo[k];
+        gauss_legendre01(p->qg, A->plan.gx, A->plan.gw);
+        gauss_legendre01(p->qs, A->plan.sx, A->plan.sw);
+        A->mx_rules.clear();
+        for (auto* v : {&A->plan.gx, &A->plan.gw, &A->plan.sx, &A->plan.sw})
+            A->mx_rules.insert(A->mx_rules.end(), v->begin(), v->end());
+    } catch (const std::bad_alloc&) {
+        delete A;
+        return fail(BEM_ENOMEM, "host allocation failed while planning");
+    }
+    A->sp = s;
+    A->mx = true;
+    A->cplx = true;
+    A->scal = 16;
+    A->plan.S = S;
+    A->plan.leaf = S.L;
+    A->dev.S = S;
+    MxDev& d = A->mxd;
+    d = MxDev{};
+    d.p = s->mx->p;
+    d.nl = s->mx->nl;
+    d.nelem = S.nelem;
+    d.nglob = S.nglob;
+    d.qg = p->qg;
+    d.qs = p->qs;
+    const int64_t N = S.nglob;
+    bem_operator_info& I = A->info;
+    I.ndof = N;
+    I.nlocal = S.ndof;
+    I.nnear = S.nelem * S.nelem;
+    I.ntouch = (int64_t)tinfo.size();
+    I.near_nnz = N * N;
+    I.leaf_level = S.L;
+    I.op_bytes = (size_t)N * N * 16 + 256;
+    I.tmp_bytes = mx_layout(*A, nullptr, nullptr, nullptr);
+    I.near_bytes = (double)N * N * 16;
+    if (info) *info = I;
+    *out = A;
+    return BEM_OK;
+}
+
+static int mx_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t stream) {
+    if (need_mx_device(A->sp) != BEM_OK) return BEM_EDEVICE;
+    char* ob = (char*)(((uintptr_t)op_ws + 255) / 256 * 256);
+    char* tb = (char*)(((uintptr_t)tmp_ws + 255) / 256 * 256);
+    MxDev d = mx_dev_of(A->sp);
+    d.qg = A->mxd.qg;
+    d.qs = A->mxd.qs;
+    mx_layout(*A, ob, tb, &d);
+    HIP_CHECK(hipMemcpyAsync((void*)d.tinfo, A->mx_tinfo.data(), A->mx_tinfo.size() * 4, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)d.gx, A->mx_rules.data(), A->mx_rules.size() * 8, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(launch_mx_pairs(d, stream));
+    HIP_CHECK(launch_mx_gather(d, stream));
+    // the pair blocks, pair types and rules live in the temporary workspace
+    d.B = nullptr;
+    d.tinfo = nullptr;
+    d.gx = d.gw = d.sx = d.sw = nullptr;
+    A->mxd = d;
+    A->assembled = true;
+    return BEM_OK;
+}
+
+extern "C" {
+
 int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
                      int level, bem_space* out) {
     return bem_space_create_ex(g, kernel, kappa_re, kappa_im, degree, knot_repetition, level, BEM_SPACE_S2, out);
@@ -1239,7 +1618,12 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
 int bem_space_create_ex(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree, int knot_repetition,
                         int level, int space_kind, bem_space* out) {
     if (!g || !out) return fail(BEM_EINVAL, "NULL argument");
-    if (space_kind != BEM_SPACE_S2 && space_kind != BEM_SPACE_S0) return fail(BEM_EINVAL, "unknown space kind");
+    if (space_kind != BEM_SPACE_S2 && space_kind != BEM_SPACE_S0 && space_kind != BEM_SPACE_S1)
+        return fail(BEM_EINVAL, "unknown space kind");
+    if ((kernel == BEM_MAXWELL_SINGLE) != (space_kind == BEM_SPACE_S1))
+        return fail(BEM_EINVAL, "the Maxwell single layer lives on S^1 spaces, the scalar kernels on S^0 and S^2");
+    if (space_kind == BEM_SPACE_S1)
+        return create_s1(g, kappa_re, kappa_im, degree, knot_repetition, level, out);
     if (space_kind == BEM_SPACE_S0 && degree < 1) return fail(BEM_EINVAL, "continuous spaces need degree >= 1");
     if (kernel != BEM_LAPLACE_SINGLE && kernel != BEM_HELMHOLTZ_SINGLE) return fail(BEM_EINVAL, "unknown kernel");
     if (degree < 0) return fail(BEM_EINVAL, "degree must be >= 0");
@@ -1310,12 +1694,23 @@ int bem_space_ndof(bem_space s, int64_t* n) {
 int bem_space_glue(bem_space s, int64_t* nlocal, int32_t* glue_host) {
     if (!s || !nlocal) return fail(BEM_EINVAL, "NULL argument");
     *nlocal = s->S.ndof;
-    if (glue_host) {
+    if (glue_host && s->mx) {
+        std::copy(s->mx->glob.begin(), s->mx->glob.end(), glue_host);
+    } else if (glue_host) {
         if (s->glue)
             std::copy(s->glue->glue.begin(), s->glue->glue.end(), glue_host);
         else
             for (int64_t g = 0; g < s->S.ndof; ++g) glue_host[g] = (int32_t)g;
     }
+    return BEM_OK;
+}
+
+int bem_space_glue_sign(bem_space s, int32_t* sign_host) {
+    if (!s || !sign_host) return fail(BEM_EINVAL, "NULL argument");
+    if (s->mx)
+        std::copy(s->mx->sgn.begin(), s->mx->sgn.end(), sign_host);
+    else
+        std::fill(sign_host, sign_host + s->S.ndof, 1);
     return BEM_OK;
 }
 
@@ -1327,6 +1722,17 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (ldb < s->S.nglob) return fail(BEM_EINVAL, "ldb must be >= N");
+    if (s->mx) {
+        if (data_kind != BEM_DATA_DIPOLE && data_kind != BEM_DATA_PLANE_WAVE_E)
+            return fail(BEM_EINVAL, "S^1 spaces take BEM_DATA_DIPOLE or BEM_DATA_PLANE_WAVE_E");
+        if (need_mx_device(s) != BEM_OK) return BEM_EDEVICE;
+        const MxDev d = mx_dev_of(s);
+        const Gauss8 g8 = gauss8();
+        for (int r = 0; r < nrhs; ++r)
+            HIP_CHECK(launch_mx_rhs(d, g8, data_kind - BEM_DATA_DIPOLE, data_params + 6 * r, (char*)b_dev + r * ldb * 16,
+                                    stream));
+        return BEM_OK;
+    }
     if (data_kind != BEM_DATA_POINT_SOURCE && data_kind != BEM_DATA_PLANE_WAVE)
         return fail(BEM_EINVAL, "unknown data kind");
     if (data_kind == BEM_DATA_PLANE_WAVE && s->S.ker.pde != PDE_HELMHOLTZ)
@@ -1340,6 +1746,7 @@ int bem_rhs(bem_space s, int data_kind, const double* data_params, int nrhs, voi
 
 int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t stream) {
     if (!s || !npts) return fail(BEM_EINVAL, "NULL argument");
+    if (s->mx) return fail(BEM_EUNSUPPORTED, "sampled data: scalar spaces only");
     *npts = s->S.nelem * 64;
     if (xyz_dev && need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (xyz_dev) HIP_CHECK(launch_quadpoints(s->S, gauss8(), xyz_dev, stream));
@@ -1349,6 +1756,7 @@ int bem_rhs_quadpoints(bem_space s, double* xyz_dev, int64_t* npts, hipStream_t 
 int bem_rhs_from_samples(bem_space s, const void* g_dev, int64_t ldg, int nrhs, void* b_dev, int64_t ldb,
                          hipStream_t stream) {
     if (!s || !g_dev || !b_dev) return fail(BEM_EINVAL, "NULL argument");
+    if (s->mx) return fail(BEM_EUNSUPPORTED, "sampled data: scalar spaces only");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (nrhs < 1) return fail(BEM_EINVAL, "nrhs must be >= 1");
     if (ldb < s->S.nglob) return fail(BEM_EINVAL, "ldb must be >= N");
@@ -1366,6 +1774,17 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
     if (!s || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");
     if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
     if (npts == 0) return BEM_OK;
+    if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
+    if (s->mx) {
+        if (ldr < s->S.nglob || ldu < 3 * npts) return fail(BEM_EINVAL, "leading dimension too small (S^1: ldu >= 3 npts)");
+        if (need_mx_device(s) != BEM_OK) return BEM_EDEVICE;
+        const MxDev d = mx_dev_of(s);
+        const Gauss8 g8 = gauss8();
+        for (int r = 0; r < nrhs; ++r)
+            HIP_CHECK(launch_mx_field(d, g8, pts_dev, npts, (const char*)rho_dev + r * ldr * 16,
+                                      (char*)u_dev + r * ldu * 16, stream));
+        return BEM_OK;
+    }
     if (ldr < s->S.nglob || ldu < npts) return fail(BEM_EINVAL, "leading dimension too small");
     if (need_device_geometry(s->S) != BEM_OK) return BEM_EDEVICE;
     if (npts > 0x7fffffff) return fail(BEM_EINVAL, "too many points");
@@ -1379,6 +1798,7 @@ int bem_eval_potential(bem_space s, const double* pts_dev, int64_t npts, const v
 
 int bem_assemble_plan(bem_space s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (!s || !p || !out) return fail(BEM_EINVAL, "NULL argument");
+    if (s->mx) return mx_plan(s, p, out, info);
     if (p->far_eval != 0 && p->far_eval != 1) return fail(BEM_EINVAL, "far_eval must be 0 or 1");
     if (p->far_eval && (p->far_low != 0 || p->batch_rhs > 1))
         return fail(BEM_EUNSUPPORTED, "far_eval needs far_low = 0 and batch_rhs <= 1");
@@ -1488,6 +1908,7 @@ int bem_assemble(bem_operator A, void* op_ws, size_t op_bytes, void* tmp_ws, siz
     if (!A || !op_ws || !tmp_ws) return fail(BEM_EINVAL, "NULL argument");
     if (op_bytes < A->info.op_bytes || tmp_bytes < A->info.tmp_bytes)
         return fail(BEM_ENOMEM, "workspace smaller than bem_assemble_plan reported");
+    if (A->mx) return mx_assemble(A, op_ws, tmp_ws, stream);
     if (need_device_geometry(A->sp->S) != BEM_OK) return BEM_EDEVICE;
     const Plan& p = A->plan;
     // align the workspaces' bases to 256 bytes
@@ -1702,13 +2123,13 @@ int bem_apply_stage(bem_operator A, int prec, int stage, const void* x_dev, void
     if (prec != BEM_PREC_FP64 && prec != A->far_low)
         return fail(BEM_EINVAL, "precision not available (assemble with far_low set to it)");
     if (stage < 0 || stage >= kApplyStages) return fail(BEM_EINVAL, "stage must lie in [0, 4)");
-    if (A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "single stages need an S^2 space");
+    if (A->plan.S.form != 2) return fail(BEM_EUNSUPPORTED, "single stages need an S^2 space");
     HIP_CHECK(launch_apply_stage(A->dev, stage, x_dev, y_dev, prec, stream));
     return BEM_OK;
 }
 
 int bem_profile_enable(bem_operator A, int on) {
-    if (A && A->plan.S.form == 0 && on) return fail(BEM_EUNSUPPORTED, "stage timing needs an S^2 space");
+    if (A && A->plan.S.form != 2 && on) return fail(BEM_EUNSUPPORTED, "stage timing needs an S^2 space");
     if (!A) return fail(BEM_EINVAL, "NULL argument");
     A->prof = on != 0;
     A->ev_used = 0;
@@ -1745,7 +2166,7 @@ static int64_t prec_tiles(const bem_operator_s& A, int* nt) {
 }
 
 int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes) {
-    if (A && A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
+    if (A && A->plan.S.form != 2) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
     if (!A || !ntiles || !ws_bytes) return fail(BEM_EINVAL, "NULL argument");
     *ntiles = prec_tiles(*A, nullptr);
     OpDev d{};
@@ -1756,7 +2177,7 @@ int bem_precond_info(bem_operator A, int64_t* ntiles, size_t* ws_bytes) {
 }
 
 int bem_precond_build(bem_operator A, void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (A && A->plan.S.form == 0) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
+    if (A && A->plan.S.form != 2) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
     if (!A || !ws) return fail(BEM_EINVAL, "NULL argument");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     int nt = 0;
@@ -1806,6 +2227,7 @@ int bem_precond_features(bem_operator A, float* feats_dev, hipStream_t stream) {
 
 int bem_precond_target_bytes(bem_operator A, int ring, int64_t nt, size_t* bytes) {
     if (!A || !bytes) return fail(BEM_EINVAL, "NULL argument");
+    if (A->plan.S.form != 2) return fail(BEM_EUNSUPPORTED, "the block preconditioner needs an S^2 space");
     if (ring < 0 || ring > 8 || nt < 1) return fail(BEM_EINVAL, "ring in [0, 8] and nt >= 1");
     OpDev d{};
     d.S = A->plan.S;
@@ -2087,7 +2509,7 @@ int bem_group_create(int nops, const bem_operator* ops, const int* ncols, bem_gr
             delete G;
             return fail(BEM_EINVAL, "every operator must be assembled and have >= 1 column");
         }
-        if (ops[i]->plan.S.form == 0) {
+        if (ops[i]->plan.S.form != 2) {
             delete G;
             return fail(BEM_EUNSUPPORTED, "grouped launches need S^2 spaces");
         }
@@ -2204,6 +2626,7 @@ void bem_graph_destroy(bem_graph g) { delete g; }
 // ------------------------------------------------------------------------------ exports
 int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, hipStream_t stream) {
     if (!A) return fail(BEM_EINVAL, "NULL argument");
+    if (A->mx) return fail(BEM_EUNSUPPORTED, "S^1 operators are dense: no near/far split to export");
     if (val && !A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     const Plan& p = A->plan;
     if (rowptr) std::memcpy(rowptr, p.rowptr.data(), p.rowptr.size() * 8);
@@ -2225,6 +2648,7 @@ int bem_export_near(bem_operator A, int64_t* rowptr, int32_t* col, double* val, 
 
 int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t stream) {
     if (!A) return fail(BEM_EINVAL, "NULL argument");
+    if (A->mx) return fail(BEM_EUNSUPPORTED, "S^1 operators are dense: no near/far split to export");
     if (blocks && !A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     const Plan& p = A->plan;
     const size_t nf = p.far_t.size();
@@ -2261,6 +2685,7 @@ int bem_export_far(bem_operator A, int64_t* pairs, double* blocks, hipStream_t s
 
 int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int nsub, const char* path) {
     if (!s || !path || (nrhs > 0 && !rho_host)) return fail(BEM_EINVAL, "NULL argument");
+    if (s->mx) return fail(BEM_EUNSUPPORTED, "VTK output: scalar spaces only");
     if (nrhs < 0 || nrhs > 64) return fail(BEM_EINVAL, "nrhs must lie in [0, 64]");
     if (nsub < 1 || nsub > 64) return fail(BEM_EINVAL, "nsub must lie in [1, 64]");
     const SpaceDesc& S = s->S;
@@ -2348,6 +2773,7 @@ int bem_write_vtk(bem_space s, const void* rho_host, int64_t ldr, int nrhs, int 
 int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, const void* rho_dev, int64_t ldr,
                           int nrhs, void* u_dev, int64_t ldu, double eta, hipStream_t stream) {
     if (!A || !rho_dev || (npts > 0 && (!pts_dev || !u_dev))) return fail(BEM_EINVAL, "NULL argument");
+    if (A->mx) return fail(BEM_EUNSUPPORTED, "S^1 operators have no cluster tree: use bem_eval_potential");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     if (nrhs < 1 || npts < 0) return fail(BEM_EINVAL, "nrhs must be >= 1 and npts >= 0");
     if (!(eta >= 0.0) || !std::isfinite(eta)) return fail(BEM_EINVAL, "eta must be finite and >= 0");
@@ -2372,6 +2798,7 @@ int bem_eval_potential_h2(bem_operator A, const double* pts_dev, int64_t npts, c
 
 int bem_export_moments(bem_operator A, const void* x_dev, double* mom_host, hipStream_t stream) {
     if (!A || !x_dev || !mom_host) return fail(BEM_EINVAL, "NULL argument");
+    if (A->mx) return fail(BEM_EUNSUPPORTED, "S^1 operators have no cluster tree");
     if (!A->assembled) return fail(BEM_EINVAL, "operator not assembled");
     if (A->dev.S.form == 0) {
         HIP_CHECK(launch_glue_gather(A->dev.S, A->cplx ? 1 : 0, x_dev, A->dev.xl, stream));

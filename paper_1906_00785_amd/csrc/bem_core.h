@@ -212,8 +212,10 @@ __host__ __device__ inline void nurbs_dfuns(const double* xi, int p, int mu, dou
     }
 }
 
-__host__ __device__ __attribute__((noinline)) inline double nurbs_kappa(const double* tab, int f, double s,
-                                                                       double t) {
+// Point and first derivatives d_s gamma, d_t gamma of a NURBS patch at (s, t) (quotient rule
+// on the rational map, basis derivatives from nurbs_dfuns).
+__host__ __device__ __attribute__((noinline)) inline void nurbs_jac(const double* tab, int f, double s, double t,
+                                                                    double* x, double* xs, double* xt) {
     const double* h = tab + 1 + 6 * f;
     const int p1 = (int)h[0], p2 = (int)h[1], k1 = (int)h[2], k2 = (int)h[3];
     const double* xi1 = tab + (int64_t)h[4];
@@ -237,12 +239,16 @@ __host__ __device__ __attribute__((noinline)) inline double nurbs_kappa(const do
             Ws += vs;
             Wt += vt;
         }
-    double xs[3], xt[3];
     for (int d = 0; d < 3; ++d) {
-        const double x = A[d] / W;
-        xs[d] = (As[d] - x * Ws) / W;
-        xt[d] = (At[d] - x * Wt) / W;
+        x[d] = A[d] / W;
+        xs[d] = (As[d] - x[d] * Ws) / W;
+        xt[d] = (At[d] - x[d] * Wt) / W;
     }
+}
+
+__host__ __device__ inline double nurbs_kappa(const double* tab, int f, double s, double t) {
+    double x[3], xs[3], xt[3];
+    nurbs_jac(tab, f, s, t, x, xs, xt);
     const double n0 = xs[1] * xt[2] - xs[2] * xt[1], n1 = xs[2] * xt[0] - xs[0] * xt[2], n2 = xs[0] * xt[1] - xs[1] * xt[0];
     return sqrt(n0 * n0 + n1 * n1 + n2 * n2);
 }
@@ -283,6 +289,62 @@ __host__ __device__ inline double patch_kappa(const GeomDesc& g, int f, double s
 #endif
     }
     return g.a * g.a;
+}
+
+// gamma_f(s, t) and its partial derivatives d_s gamma, d_t gamma (the Piola transform of
+// div-conforming fields is D gamma (x) e_s, e_t)
+__host__ __device__ inline void patch_jac(const GeomDesc& g, int f, double s, double t, double* x, double* xs,
+                                          double* xt) {
+    if (g.kind == GEOM_SPHERE6 || g.kind == GEOM_ELLIPSOID6) {
+        int iu, iv, ic;
+        double cv;
+        cube_face_layout(f, iu, iv, ic, cv);
+        double c[3];
+        c[iu] = 2.0 * s - 1.0;
+        c[iv] = 2.0 * t - 1.0;
+        c[ic] = cv;
+        const double rr = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        const double n[3] = {c[0] / rr, c[1] / rr, c[2] / rr};
+        const double sc[3] = {g.kind == GEOM_SPHERE6 ? 1.0 : g.a, g.kind == GEOM_SPHERE6 ? 1.0 : g.b,
+                              g.kind == GEOM_SPHERE6 ? 1.0 : g.c};
+        // d(c/|c|)/ds = (dc/ds - n (n . dc/ds)) / |c| with dc/ds = 2 e_iu (and e_iv for t)
+        for (int d = 0; d < 3; ++d) {
+            x[d] = sc[d] * n[d];
+            xs[d] = sc[d] * 2.0 * ((d == iu ? 1.0 : 0.0) - n[d] * n[iu]) / rr;
+            xt[d] = sc[d] * 2.0 * ((d == iv ? 1.0 : 0.0) - n[d] * n[iv]) / rr;
+        }
+    } else if (g.kind == GEOM_TORUS16) {
+        const double u = 0.5 * kPi * ((f >> 2) + s), v = 0.5 * kPi * ((f & 3) + t);
+        double su, cu, sv, cvv;
+        sincos(u, &su, &cu);
+        sincos(v, &sv, &cvv);
+        const double rr = g.a + g.b * cvv, du = 0.5 * kPi;
+        x[0] = rr * cu;
+        x[1] = rr * su;
+        x[2] = g.b * sv;
+        xs[0] = -rr * su * du;
+        xs[1] = rr * cu * du;
+        xs[2] = 0.0;
+        xt[0] = -g.b * sv * cu * du;
+        xt[1] = -g.b * sv * su * du;
+        xt[2] = g.b * cvv * du;
+    } else if (g.kind == GEOM_NURBS) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        nurbs_jac(g.tab_dev, f, s, t, x, xs, xt);
+#else
+        nurbs_jac(g.tab_host, f, s, t, x, xs, xt);
+#endif
+    } else {
+        x[0] = g.a * s;
+        x[1] = g.a * t;
+        x[2] = 0.0;
+        xs[0] = g.a;
+        xs[1] = 0.0;
+        xs[2] = 0.0;
+        xt[0] = 0.0;
+        xt[1] = g.a;
+        xt[2] = 0.0;
+    }
 }
 
 // ------------------------------------------------------------------ single-layer kernels
@@ -349,5 +411,47 @@ __host__ __device__ inline void d4_apply(int k, double a, double b, double& o1, 
 
 // Touching element pair types
 enum PairType : int { PT_REGULAR = 0, PT_VERTEX = 1, PT_EDGE = 2, PT_IDENTICAL = 3 };
+
+// Duffy-type substitution of region `reg` for a touching pair of type `type` at the cube
+// point (xi, e1, e2, e3): local points xh (first element) and yh (second element) with the
+// Jacobian of the substitution.  Identical: 8 regions (4 sign patterns of y - x times the
+// 2 simplices of (t1, t2)); edge (shared edge at first local coordinate 0 on both sides):
+// 6 regions (sign of y2 - x2 times which of x1, y1, t is largest); vertex (shared vertex at
+// the local origin on both sides): 4 regions (which of the 4 coordinates is largest).
+__host__ __device__ inline void duffy_point(int type, int reg, double xi, double e1, double e2, double e3, double& x1,
+                                   double& x2, double& y1, double& y2, double& jac) {
+    if (type == PT_IDENTICAL) {
+        const int ord = reg >> 2, sg = reg & 3;
+        const double t1 = ord == 0 ? xi : xi * e1;
+        const double t2 = ord == 0 ? xi * e1 : xi;
+        const double u1 = e2, u2 = e3;
+        const bool n1 = sg & 1, n2 = sg & 2;
+        x1 = (1.0 - t1) * u1 + (n1 ? t1 : 0.0);
+        x2 = (1.0 - t2) * u2 + (n2 ? t2 : 0.0);
+        y1 = n1 ? x1 - t1 : x1 + t1;
+        y2 = n2 ? x2 - t2 : x2 + t2;
+        jac = xi * (1.0 - t1) * (1.0 - t2);
+    } else if (type == PT_EDGE) {
+        const int c = reg >> 1;
+        const bool neg = reg & 1;
+        double v[3];
+        v[0] = c == 0 ? xi : xi * e1;
+        v[1] = c == 1 ? xi : (c == 0 ? xi * e1 : xi * e2);
+        v[2] = c == 2 ? xi : xi * e2;
+        const double t = v[2];
+        x1 = v[0];
+        y1 = v[1];
+        x2 = (1.0 - t) * e3 + (neg ? t : 0.0);
+        y2 = neg ? x2 - t : x2 + t;
+        jac = xi * xi * (1.0 - t);
+    } else {
+        // coordinate `reg` of (x1, x2, y1, y2) is xi, the others xi*e1, xi*e2, xi*e3 in order
+        x1 = reg == 0 ? xi : xi * e1;
+        x2 = reg == 1 ? xi : (reg < 1 ? xi * e1 : xi * e2);
+        y1 = reg == 2 ? xi : (reg < 2 ? xi * e2 : xi * e3);
+        y2 = reg == 3 ? xi : xi * e3;
+        jac = xi * xi * xi;
+    }
+}
 
 }  // namespace bem

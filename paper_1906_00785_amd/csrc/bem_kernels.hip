@@ -32,47 +32,6 @@ __device__ inline void leaf_decode(int l, int n1, int& f, int& i, int& j) {
     f = l / (n1 * n1);
 }
 
-// Duffy-type substitution of region `reg` for a touching pair of type `type` at the cube
-// point (xi, e1, e2, e3): local points xh (first element) and yh (second element) with the
-// Jacobian of the substitution.  Identical: 8 regions (4 sign patterns of y - x times the
-// 2 simplices of (t1, t2)); edge (shared edge at first local coordinate 0 on both sides):
-// 6 regions (sign of y2 - x2 times which of x1, y1, t is largest); vertex (shared vertex at
-// the local origin on both sides): 4 regions (which of the 4 coordinates is largest).
-__device__ inline void duffy_point(int type, int reg, double xi, double e1, double e2, double e3, double& x1,
-                                   double& x2, double& y1, double& y2, double& jac) {
-    if (type == PT_IDENTICAL) {
-        const int ord = reg >> 2, sg = reg & 3;
-        const double t1 = ord == 0 ? xi : xi * e1;
-        const double t2 = ord == 0 ? xi * e1 : xi;
-        const double u1 = e2, u2 = e3;
-        const bool n1 = sg & 1, n2 = sg & 2;
-        x1 = (1.0 - t1) * u1 + (n1 ? t1 : 0.0);
-        x2 = (1.0 - t2) * u2 + (n2 ? t2 : 0.0);
-        y1 = n1 ? x1 - t1 : x1 + t1;
-        y2 = n2 ? x2 - t2 : x2 + t2;
-        jac = xi * (1.0 - t1) * (1.0 - t2);
-    } else if (type == PT_EDGE) {
-        const int c = reg >> 1;
-        const bool neg = reg & 1;
-        double v[3];
-        v[0] = c == 0 ? xi : xi * e1;
-        v[1] = c == 1 ? xi : (c == 0 ? xi * e1 : xi * e2);
-        v[2] = c == 2 ? xi : xi * e2;
-        const double t = v[2];
-        x1 = v[0];
-        y1 = v[1];
-        x2 = (1.0 - t) * e3 + (neg ? t : 0.0);
-        y2 = neg ? x2 - t : x2 + t;
-        jac = xi * xi * (1.0 - t);
-    } else {
-        // coordinate `reg` of (x1, x2, y1, y2) is xi, the others xi*e1, xi*e2, xi*e3 in order
-        x1 = reg == 0 ? xi : xi * e1;
-        x2 = reg == 1 ? xi : (reg < 1 ? xi * e1 : xi * e2);
-        y1 = reg == 2 ? xi : (reg < 2 ? xi * e2 : xi * e3);
-        y2 = reg == 3 ? xi : xi * e3;
-        jac = xi * xi * xi;
-    }
-}
 
 // ------------------------------------------------------------------ geometry tables
 __global__ void k_gauss_points(SpaceDesc S, int qg, const double* __restrict__ gx, double* __restrict__ gpos,

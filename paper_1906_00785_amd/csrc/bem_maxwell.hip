@@ -1,0 +1,482 @@
+// gfx950 kernels of the Maxwell single layer on the div-conforming spaces S^1 (App. E):
+// element-pair blocks (regular pairs by tensor Gauss rules, touching pairs by the Duffy
+// rules of the scalar operators), the glued dense matrix and its product, load vectors and
+// the field (MS).
+#include "bem_device.h"
+#include "bem_maxwell.h"
+
+namespace bem {
+
+namespace {
+
+__device__ inline cdbl cmul(cdbl a, cdbl b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// exp(-i kappa r) with kappa = kre + i kim
+__device__ inline cdbl cexp_mikr(const KernelDesc& k, double r) {
+    double s, c;
+    sincos(k.kre * r, &s, &c);
+    const double mag = k.kim != 0.0 ? exp(k.kim * r) : 1.0;
+    return {mag * c, -mag * s};
+}
+
+// the local functions of element (f, i1, i2) at element coordinates (u1, u2): point x, the
+// lifted fields V[k] = D gamma (reference field) and the reference divergences D[k], in the
+// order: component 0 (degree p in s, p - 1 in t; l1 outer), then component 1
+template <int P>
+__device__ inline void mx_eval(const MxDev& d, int f, int i1, int i2, double u1, double u2, double* x,
+                               double (*V)[3], double* D) {
+    double xs[3], xt[3];
+    patch_jac(d.geom, f, (i1 + u1) * d.h, (i2 + u2) * d.h, x, xs, xt);
+    const double ih = 1.0 / d.h;
+    double bp1[P + 1], dp1[P + 1], bp2[P + 1], dp2[P + 1], bq1[P], bq2[P];
+    const double* c1 = d.polp + (int64_t)i1 * (P + 1) * (P + 1);
+    const double* c2 = d.polp + (int64_t)i2 * (P + 1) * (P + 1);
+#pragma unroll
+    for (int l = 0; l <= P; ++l) {
+        double v1 = c1[l * (P + 1) + P], v2 = c2[l * (P + 1) + P], w1 = 0.0, w2 = 0.0;
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) {
+            w1 = w1 * u1 + v1;  // derivative by Horner alongside the value
+            w2 = w2 * u2 + v2;
+            v1 = v1 * u1 + c1[l * (P + 1) + k];
+            v2 = v2 * u2 + c2[l * (P + 1) + k];
+        }
+        bp1[l] = v1;
+        bp2[l] = v2;
+        dp1[l] = w1 * ih;
+        dp2[l] = w2 * ih;
+    }
+    const double* q1 = d.polq + (int64_t)i1 * P * P;
+    const double* q2 = d.polq + (int64_t)i2 * P * P;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        double v1 = q1[l * P + P - 1], v2 = q2[l * P + P - 1];
+#pragma unroll
+        for (int k = P - 2; k >= 0; --k) {
+            v1 = v1 * u1 + q1[l * P + k];
+            v2 = v2 * u2 + q2[l * P + k];
+        }
+        bq1[l] = v1;
+        bq2[l] = v2;
+    }
+    int k = 0;
+#pragma unroll
+    for (int l1 = 0; l1 <= P; ++l1)
+#pragma unroll
+        for (int l2 = 0; l2 < P; ++l2, ++k) {
+            const double b = bp1[l1] * bq2[l2];
+            V[k][0] = xs[0] * b;
+            V[k][1] = xs[1] * b;
+            V[k][2] = xs[2] * b;
+            D[k] = dp1[l1] * bq2[l2];
+        }
+#pragma unroll
+    for (int l1 = 0; l1 < P; ++l1)
+#pragma unroll
+        for (int l2 = 0; l2 <= P; ++l2, ++k) {
+            const double b = bq1[l1] * bp2[l2];
+            V[k][0] = xt[0] * b;
+            V[k][1] = xt[1] * b;
+            V[k][2] = xt[2] * b;
+            D[k] = bq1[l1] * dp2[l2];
+        }
+}
+
+// Element-pair block B[i][j] = int_tau int_sigma G(x, y) [V_i(x) . V_j(y) - kappa^-2 D_i(x) D_j(y)]
+// over the parameter squares (times h^4).  One wave per pair.  Both parts are contractions
+// over point pairs of F[i][c] (complex, the kernel-weighted test side, channel c = field
+// component 0..2 or the divergence 3) with W[j][c] (real, the trial side): the lanes write
+// 64 points' F and W to LDS and each lane adds its entries of B.
+//   regular pairs: lane b is trial point b and sums F_b[i][c] = sum_a w_a G(x_a, y_b) Wx_a[i][c]
+//                  over the 64 test points (uniform, from LDS); one contraction.
+//   touching pairs: lane = one Duffy point (x, y) at a time, F = w G Wx(x), W = Wy(y); one
+//                  contraction per 64 points.
+template <int P>
+__global__ __launch_bounds__(64) void k_mx_pairs(MxDev d) {
+    constexpr int NL = 2 * P * (P + 1), NC = 4 * NL, NE = (NL * NL + 63) / 64;
+    extern __shared__ double sm[];
+    double* Fr = sm;                 // [64][NC]
+    double* Fi = Fr + 64 * NC;       // [64][NC]
+    double* Wl = Fi + 64 * NC;       // [64][NC]
+    double* Xt = Wl + 64 * NC;       // [64][3] test points (regular pairs)
+    double* WX = Xt + 64 * 3;        // [64][NC] test-side values times weights (regular pairs)
+    const int64_t pr = blockIdx.x;
+    const int64_t e1 = pr / d.nelem, e2 = pr % d.nelem;
+    const int lane = threadIdx.x;
+    const int n = d.nel;
+    const int ti2 = (int)(e1 % n), ti1 = (int)((e1 / n) % n), tf = (int)(e1 / ((int64_t)n * n));
+    const int si2 = (int)(e2 % n), si1 = (int)((e2 / n) % n), sf = (int)(e2 / ((int64_t)n * n));
+    const int info = d.tinfo[pr];
+    double accr[NE][2], acci[NE][2];  // [entry][vector part, divergence part]
+#pragma unroll
+    for (int e = 0; e < NE; ++e) accr[e][0] = accr[e][1] = acci[e][0] = acci[e][1] = 0.0;
+    double x[3], V[NL][3], D[NL];
+    // adds the contraction of the 64 points now in LDS to this lane's entries
+    auto contract = [&]() {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int ent = lane + 64 * e;
+            if (ent >= NL * NL) continue;
+            const int i = ent / NL, j = ent % NL;
+            for (int b = 0; b < 64; ++b) {
+                const double* fr = Fr + b * NC + 4 * i;
+                const double* fi = Fi + b * NC + 4 * i;
+                const double* w = Wl + b * NC + 4 * j;
+                accr[e][0] += fr[0] * w[0] + fr[1] * w[1] + fr[2] * w[2];
+                acci[e][0] += fi[0] * w[0] + fi[1] * w[1] + fi[2] * w[2];
+                accr[e][1] += fr[3] * w[3];
+                acci[e][1] += fi[3] * w[3];
+            }
+        }
+    };
+    if (info == 0) {
+        const int qg = d.qg;  // qg * qg <= 64 (checked at planning)
+        const int np = qg * qg;
+        // test points and their weighted values
+        if (lane < np) {
+            const int a1 = lane / qg, a2 = lane % qg;
+            mx_eval<P>(d, tf, ti1, ti2, d.gx[a1], d.gx[a2], x, V, D);
+            const double w = d.gw[a1] * d.gw[a2];
+            Xt[3 * lane] = x[0];
+            Xt[3 * lane + 1] = x[1];
+            Xt[3 * lane + 2] = x[2];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                WX[lane * NC + 4 * k] = w * V[k][0];
+                WX[lane * NC + 4 * k + 1] = w * V[k][1];
+                WX[lane * NC + 4 * k + 2] = w * V[k][2];
+                WX[lane * NC + 4 * k + 3] = w * D[k];
+            }
+        }
+        __syncthreads();
+        // trial point of this lane
+        double Sr[NC], Si[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Sr[c] = Si[c] = 0.0;
+        double y[3] = {0.0, 0.0, 0.0}, wb = 0.0;
+        if (lane < np) {
+            const int b1 = lane / qg, b2 = lane % qg;
+            mx_eval<P>(d, sf, si1, si2, d.gx[b1], d.gx[b2], y, V, D);
+            wb = d.gw[b1] * d.gw[b2];
+        }
+        // the trial side goes to LDS first (its registers are free during the sums)
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            Wl[lane * NC + 4 * k] = lane < np ? wb * V[k][0] : 0.0;
+            Wl[lane * NC + 4 * k + 1] = lane < np ? wb * V[k][1] : 0.0;
+            Wl[lane * NC + 4 * k + 2] = lane < np ? wb * V[k][2] : 0.0;
+            Wl[lane * NC + 4 * k + 3] = lane < np ? wb * D[k] : 0.0;
+        }
+        if (lane < np) {
+            for (int a = 0; a < np; ++a) {
+                const double dx = Xt[3 * a] - y[0], dy = Xt[3 * a + 1] - y[1], dz = Xt[3 * a + 2] - y[2];
+                const cdbl G = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
+                const double* wx = WX + a * NC;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    Sr[c] += G.re * wx[c];
+                    Si[c] += G.im * wx[c];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Fr[lane * NC + c] = Sr[c];
+            Fi[lane * NC + c] = Si[c];
+        }
+        __syncthreads();
+        contract();
+    } else {
+        const int type = info & 15, k1 = (info >> 4) & 15, k2 = (info >> 8) & 15;
+        const int qs = d.qs, qs4 = qs * qs * qs * qs;
+        const int nreg = type == PT_IDENTICAL ? 8 : (type == PT_EDGE ? 6 : 4);
+        const int npts = nreg * qs4;
+        double Vy[NL][3], Dy[NL];
+        for (int p0 = 0; p0 < npts; p0 += 64) {
+            const int pt = p0 + lane;
+            double gr = 0.0, gi = 0.0;
+            if (pt < npts) {
+                const int reg = pt / qs4;
+                int rem = pt - reg * qs4;
+                const int i3 = rem % qs;
+                rem /= qs;
+                const int i2 = rem % qs;
+                rem /= qs;
+                const int i1 = rem % qs, i0 = rem / qs;
+                double xh1, xh2, yh1, yh2, jac;
+                duffy_point(type, reg, d.sx[i0], d.sx[i1], d.sx[i2], d.sx[i3], xh1, xh2, yh1, yh2, jac);
+                double u1, u2, w1, w2, y[3];
+                d4_apply(k1, xh1, xh2, u1, u2);
+                d4_apply(k2, yh1, yh2, w1, w2);
+                mx_eval<P>(d, tf, ti1, ti2, u1, u2, x, V, D);
+                mx_eval<P>(d, sf, si1, si2, w1, w2, y, Vy, Dy);
+                const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+                const cdbl G = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
+                const double w = d.sw[i0] * d.sw[i1] * d.sw[i2] * d.sw[i3] * jac;
+                gr = G.re * w;
+                gi = G.im * w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {
+                    V[k][0] = V[k][1] = V[k][2] = D[k] = 0.0;
+                    Vy[k][0] = Vy[k][1] = Vy[k][2] = Dy[k] = 0.0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const double vx[4] = {V[k][0], V[k][1], V[k][2], D[k]};
+                const double vy[4] = {Vy[k][0], Vy[k][1], Vy[k][2], Dy[k]};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    Fr[lane * NC + 4 * k + c] = gr * vx[c];
+                    Fi[lane * NC + 4 * k + c] = gi * vx[c];
+                    Wl[lane * NC + 4 * k + c] = vy[c];
+                }
+            }
+            __syncthreads();
+            contract();
+        }
+    }
+    // B = (vector part - kappa^-2 divergence part) h^4
+    const double h2 = d.h * d.h, h4 = h2 * h2;
+    const cdbl k2 = cmul(cdbl{d.ker.kre, d.ker.kim}, cdbl{d.ker.kre, d.ker.kim});
+    const double den = k2.re * k2.re + k2.im * k2.im;
+    const cdbl mik2 = {-k2.re / den, k2.im / den};  // -1 / kappa^2
+    cdbl* B = (cdbl*)d.B + pr * NL * NL;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int ent = lane + 64 * e;
+        if (ent >= NL * NL) continue;
+        const cdbl dv = cmul(mik2, cdbl{accr[e][1], acci[e][1]});
+        B[ent] = cdbl{(accr[e][0] + dv.re) * h4, (acci[e][0] + dv.im) * h4};
+    }
+}
+
+// M[g][h]: one thread per entry, the pieces of g (outer) and h (inner) in table order
+__global__ __launch_bounds__(256) void k_mx_gather(MxDev d) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t N = d.nglob;
+    if (id >= N * N) return;
+    const int64_t g = id / N, hc = id % N;
+    const int nl = d.nl;
+    const cdbl* B = (const cdbl*)d.B;
+    double sr = 0.0, si = 0.0;
+    for (int64_t a = d.gptr[g]; a < d.gptr[g + 1]; ++a) {
+        const int pa = d.gpos[a], ea = pa / nl, ia = pa % nl;
+        const double sa = d.gsgn[a];
+        for (int64_t b = d.gptr[hc]; b < d.gptr[hc + 1]; ++b) {
+            const int pb = d.gpos[b], eb = pb / nl, ib = pb % nl;
+            const cdbl v = B[((int64_t)ea * d.nelem + eb) * nl * nl + ia * nl + ib];
+            const double s = sa * d.gsgn[b];
+            sr += s * v.re;
+            si += s * v.im;
+        }
+    }
+    ((cdbl*)d.M)[id] = cdbl{sr, si};
+}
+
+// y = M x, one wave per row
+__global__ __launch_bounds__(256) void k_mx_matvec(MxDev d, const cdbl* __restrict__ x, cdbl* __restrict__ y) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= d.nglob) return;
+    const cdbl* row = (const cdbl*)d.M + g * d.nglob;
+    double sr = 0.0, si = 0.0;
+    for (int64_t h = lane; h < d.nglob; h += 64) {
+        const cdbl a = row[h], b = x[h];
+        sr += a.re * b.re - a.im * b.im;
+        si += a.re * b.im + a.im * b.re;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+    }
+    if (lane == 0) y[g] = cdbl{sr, si};
+}
+
+// data fields: 0 the point dipole curl curl (m G(x - x0)) = kappa^2 m G + grad (m . grad G),
+// 1 the plane wave e exp(-i kappa d . x)
+__device__ inline void mx_data(const KernelDesc& kd, int kind, const double* p, const double* x, cdbl* E) {
+    if (kind == 0) {
+        const double R[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        const cdbl ex = cexp_mikr(kd, r) * (0.07957747154594767);  // exp(-i kappa r) / (4 pi)
+        const cdbl ik = {-kd.kim, kd.kre};                        // i kappa
+        const cdbl one_ikr = {1.0 + ik.re * r, ik.im * r};
+        const cdbl ikr2 = cmul(ik, ik) * (r * r);
+        const cdbl G = ex * (1.0 / r);
+        const cdbl G1 = cmul(ex, one_ikr) * (-1.0 / (r * r));
+        const cdbl G2 = cmul(ex, cdbl{2.0 + 2.0 * ik.re * r + ikr2.re, 2.0 * ik.im * r + ikr2.im}) * (1.0 / (r * r * r));
+        const cdbl g = G1 * (1.0 / r);
+        const cdbl gp = (G2 - G1 * (1.0 / r)) * (1.0 / r);
+        const cdbl k2 = cmul(cdbl{kd.kre, kd.kim}, cdbl{kd.kre, kd.kim});
+        const double mR = p[3] * R[0] + p[4] * R[1] + p[5] * R[2];
+        for (int c = 0; c < 3; ++c)
+            E[c] = cmul(k2, G) * p[3 + c] + gp * (mR * R[c] / r) + g * p[3 + c];
+    } else {
+        const cdbl ph = cexp_mikr(kd, p[0] * x[0] + p[1] * x[1] + p[2] * x[2]);
+        for (int c = 0; c < 3; ++c) E[c] = ph * p[3 + c];
+    }
+}
+
+// b_g = sum over the pieces (element, position, sign) of g of the 8 x 8 Gauss sums of
+// E(gamma) . V; one wave per global function, lane = Gauss point
+template <int P>
+__global__ __launch_bounds__(256) void k_mx_rhs(MxDev d, Gauss8 g8, int kind, double p0, double p1, double p2,
+                                                double p3, double p4, double p5, cdbl* b) {
+    constexpr int NL = 2 * P * (P + 1);
+    const int64_t G = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (G >= d.nglob) return;
+    const double prm[6] = {p0, p1, p2, p3, p4, p5};
+    const int n = d.nel, a1 = lane >> 3, a2 = lane & 7;
+    double sr = 0.0, si = 0.0;
+    for (int64_t a = d.gptr[G]; a < d.gptr[G + 1]; ++a) {
+        const int pa = d.gpos[a], e = pa / NL, pos = pa % NL;
+        const int i2 = e % n, i1 = (e / n) % n, f = e / (n * n);
+        double x[3], V[NL][3], D[NL];
+        mx_eval<P>(d, f, i1, i2, g8.x[a1], g8.x[a2], x, V, D);
+        cdbl E[3];
+        mx_data(d.ker, kind, prm, x, E);
+        const double w = g8.w[a1] * g8.w[a2] * d.h * d.h * d.gsgn[a];
+        sr += w * (E[0].re * V[pos][0] + E[1].re * V[pos][1] + E[2].re * V[pos][2]);
+        si += w * (E[0].im * V[pos][0] + E[1].im * V[pos][1] + E[2].im * V[pos][2]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+    }
+    if (lane == 0) b[G] = cdbl{sr, si};
+}
+
+// E(x_p) = sum over elements and 8 x 8 Gauss points of w [G J + kappa^-2 G'(r) (x - y)/r Div],
+// J and Div the density and its divergence at the point; one workgroup per point
+template <int P>
+__global__ __launch_bounds__(256) void k_mx_field(MxDev d, Gauss8 g8, const double* __restrict__ pts,
+                                                  const cdbl* __restrict__ j, cdbl* __restrict__ out) {
+    constexpr int NL = 2 * P * (P + 1);
+    __shared__ double red[6][4];
+    const int64_t p = blockIdx.x;
+    const double px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+    const int n = d.nel;
+    const cdbl k2 = cmul(cdbl{d.ker.kre, d.ker.kim}, cdbl{d.ker.kre, d.ker.kim});
+    const double den = k2.re * k2.re + k2.im * k2.im;
+    const cdbl ik2 = {k2.re / den, -k2.im / den};  // 1 / kappa^2
+    const cdbl ik = {-d.ker.kim, d.ker.kre};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t total = d.nelem * 64;
+    for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int a = (int)(idx & 63);
+        const int64_t e = idx >> 6;
+        const int i2 = (int)(e % n), i1 = (int)((e / n) % n), f = (int)(e / ((int64_t)n * n));
+        double y[3], V[NL][3], D[NL];
+        mx_eval<P>(d, f, i1, i2, g8.x[a >> 3], g8.x[a & 7], y, V, D);
+        cdbl J[3] = {{0, 0}, {0, 0}, {0, 0}}, Dv = {0, 0};
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int gk = d.eglob[e * NL + k];
+            if (gk < 0) continue;
+            const cdbl c = j[gk] * (double)d.esgn[e * NL + k];
+            J[0] = J[0] + c * V[k][0];
+            J[1] = J[1] + c * V[k][1];
+            J[2] = J[2] + c * V[k][2];
+            Dv = Dv + c * D[k];
+        }
+        const double R[3] = {px - y[0], py - y[1], pz - y[2]};
+        const double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        const cdbl ex = cexp_mikr(d.ker, r) * 0.07957747154594767;
+        const cdbl G = ex * (1.0 / r);
+        const cdbl G1 = cmul(ex, cdbl{1.0 + ik.re * r, ik.im * r}) * (-1.0 / (r * r));
+        const double w = g8.w[a >> 3] * g8.w[a & 7] * d.h * d.h;
+        const cdbl gd = cmul(cmul(ik2, G1), Dv) * (w / r);
+        for (int c = 0; c < 3; ++c) {
+            const cdbl v = cmul(G, J[c]) * w + gd * R[c];
+            acc[2 * c] += v.re;
+            acc[2 * c + 1] += v.im;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        out[3 * p + c] = cdbl{red[2 * c][0] + red[2 * c][1] + red[2 * c][2] + red[2 * c][3],
+                              red[2 * c + 1][0] + red[2 * c + 1][1] + red[2 * c + 1][2] + red[2 * c + 1][3]};
+    }
+}
+
+inline unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <int P>
+constexpr size_t mx_pairs_lds() {
+    constexpr int NC = 4 * 2 * P * (P + 1);
+    return sizeof(double) * (size_t)(64 * NC * 4 + 64 * 3);
+}
+
+template <int P>
+hipError_t mx_pairs_p(const MxDev& d, hipStream_t st) {
+    constexpr size_t lds = mx_pairs_lds<P>();
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_mx_pairs<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_mx_pairs<P>, dim3((unsigned)(d.nelem * d.nelem)), dim3(64), lds, st, d);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mx_pairs(const MxDev& d, hipStream_t st) {
+    if (d.nelem == 0) return hipSuccess;
+    if (d.p == 1) return mx_pairs_p<1>(d, st);
+    if (d.p == 2) return mx_pairs_p<2>(d, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mx_gather(const MxDev& d, hipStream_t st) {
+    if (d.nglob == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mx_gather, dim3(nb(d.nglob * d.nglob, 256)), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_mx_matvec(const MxDev& d, const void* x, void* y, hipStream_t st) {
+    if (d.nglob == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mx_matvec, dim3(nb(d.nglob, 4)), dim3(256), 0, st, d, (const cdbl*)x, (cdbl*)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_mx_rhs(const MxDev& d, const Gauss8& g8, int kind, const double* q, void* b, hipStream_t st) {
+    if (d.nglob == 0) return hipSuccess;
+    const dim3 g(nb(d.nglob, 4)), blk(256);
+    if (d.p == 1)
+        hipLaunchKernelGGL(k_mx_rhs<1>, g, blk, 0, st, d, g8, kind, q[0], q[1], q[2], q[3], q[4], q[5], (cdbl*)b);
+    else if (d.p == 2)
+        hipLaunchKernelGGL(k_mx_rhs<2>, g, blk, 0, st, d, g8, kind, q[0], q[1], q[2], q[3], q[4], q[5], (cdbl*)b);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_mx_field(const MxDev& d, const Gauss8& g8, const double* pts, int64_t npts, const void* j, void* E,
+                           hipStream_t st) {
+    if (npts == 0) return hipSuccess;
+    if (d.p == 1)
+        hipLaunchKernelGGL(k_mx_field<1>, dim3((unsigned)npts), dim3(256), 0, st, d, g8, pts, (const cdbl*)j, (cdbl*)E);
+    else if (d.p == 2)
+        hipLaunchKernelGGL(k_mx_field<2>, dim3((unsigned)npts), dim3(256), 0, st, d, g8, pts, (const cdbl*)j, (cdbl*)E);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace bem

@@ -269,6 +269,66 @@ struct Builder {
         return p.vid[4 * e + ((int)o1) * 2 + (int)o2];
     }
 
+    // kind of the touching pair (e, e2) (elements sharing a vertex) and the symmetries of the
+    // unit square that move the common vertex (and edge) to the origin (and the edge t = 0)
+    bool classify(int64_t e, int64_t e2, int& type, int& k1, int& k2, std::string& err) const {
+        int shared = 0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (p.vid[4 * e + a] == p.vid[4 * e2 + b]) ++shared;
+        k1 = k2 = 0;
+        if (e == e2) {
+            type = PT_IDENTICAL;
+            return true;
+        }
+        if (shared != 2 && shared != 1) {
+            err = "distinct elements share more than an edge";
+            return false;
+        }
+        type = shared == 2 ? PT_EDGE : PT_VERTEX;
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) {
+                if (corner_vid(e, a, 0, 0) != corner_vid(e2, b, 0, 0)) continue;
+                if (type == PT_EDGE && corner_vid(e, a, 0, 1) != corner_vid(e2, b, 0, 1)) continue;
+                k1 = a;
+                k2 = b;
+                return true;
+            }
+        err = "no symmetry aligns a shared edge/vertex (matching condition)";
+        return false;
+    }
+
+    // every touching element pair (both orders, e1 == e2 included), sorted
+    bool touching_elements(std::vector<int64_t>& pairs, std::vector<int32_t>& info, std::string& err) const {
+        const SpaceDesc& S = p.S;
+        int32_t nv = 0;
+        for (int32_t v : p.vid) nv = std::max(nv, v + 1);
+        std::vector<std::vector<int64_t>> vel(nv);
+        for (int64_t e = 0; e < S.nelem; ++e)
+            for (int c = 0; c < 4; ++c) {
+                auto& L = vel[p.vid[4 * e + c]];
+                if (L.empty() || L.back() != e) L.push_back(e);
+            }
+        std::vector<int64_t> nb;
+        pairs.clear();
+        info.clear();
+        for (int64_t e = 0; e < S.nelem; ++e) {
+            nb.clear();
+            for (int c = 0; c < 4; ++c)
+                for (int64_t e2 : vel[p.vid[4 * e + c]]) nb.push_back(e2);
+            std::sort(nb.begin(), nb.end());
+            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+            for (int64_t e2 : nb) {
+                int type, k1, k2;
+                if (!classify(e, e2, type, k1, k2, err)) return false;
+                pairs.push_back(e);
+                pairs.push_back(e2);
+                info.push_back(type | k1 << 4 | k2 << 8);
+            }
+        }
+        return true;
+    }
+
     bool touching(bool& ok, std::string& err) {
         const SpaceDesc& S = p.S;
         // vertex -> elements
@@ -303,31 +363,8 @@ struct Builder {
                     return false;
                 }
                 const int64_t lp = it - p.near_s.begin();
-                int shared = 0;
-                for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b)
-                        if (p.vid[4 * e + a] == p.vid[4 * e2 + b]) ++shared;
-                int type, k1 = 0, k2 = 0;
-                if (e == e2) {
-                    type = PT_IDENTICAL;
-                } else if (shared == 2 || shared == 1) {
-                    type = shared == 2 ? PT_EDGE : PT_VERTEX;
-                    bool found = false;
-                    for (int a = 0; a < 8 && !found; ++a)
-                        for (int b = 0; b < 8 && !found; ++b) {
-                            if (corner_vid(e, a, 0, 0) != corner_vid(e2, b, 0, 0)) continue;
-                            if (type == PT_EDGE && corner_vid(e, a, 0, 1) != corner_vid(e2, b, 0, 1)) continue;
-                            k1 = a;
-                            k2 = b;
-                            found = true;
-                        }
-                    if (!found) {
-                        err = "no symmetry aligns a shared edge/vertex (matching condition)";
-                        ok = false;
-                        return false;
-                    }
-                } else {
-                    err = "distinct elements share more than an edge";
+                int type, k1, k2;
+                if (!classify(e, e2, type, k1, k2, err)) {
                     ok = false;
                     return false;
                 }
@@ -423,6 +460,15 @@ struct Builder {
 };
 
 }  // namespace
+
+bool element_touch_pairs(const SpaceDesc& S, std::vector<int64_t>& pairs, std::vector<int32_t>& info,
+                         std::string& err) {
+    Plan p;
+    p.S = S;
+    Builder B(p);
+    B.vertex_ids();
+    return B.touching_elements(pairs, info, err);
+}
 
 bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& p, std::string& err) {
     p = Plan();

@@ -104,6 +104,12 @@ struct Plan {
 // Builds the whole plan; returns false and sets err on invalid input.
 bool build_plan(const SpaceDesc& S, const H2Params& P, Plan& plan, std::string& err);
 
+// All touching element pairs of a space (sharing at least a vertex; both orders and e1 == e2
+// included), as (e1, e2) in pairs and type | k1 << 4 | k2 << 8 in info (k1, k2 the symmetries
+// of the unit square that bring the common vertex, or edge, to the origin, or to t = 0).
+bool element_touch_pairs(const SpaceDesc& S, std::vector<int64_t>& pairs, std::vector<int32_t>& info,
+                         std::string& err);
+
 // Leaf-interval index range [lo, hi] that contains B-spline j (per direction)
 inline void leaves_of_basis(const Plan& p, int j, int& lo, int& hi) {
     const int stride = p.m * p.S.r;  // first basis of leaf i is i*stride

@@ -389,3 +389,71 @@ def test_vtk_output_of_a_continuous_density(B, orc, tmp_path):
     same = np.all(np.abs(np.diff(ps, axis=0)) <= 1e-12, axis=1)
     assert same.sum() > 0
     assert np.max(np.abs(np.diff(vs)[same])) <= 1e-12 * np.max(np.abs(vs))
+
+
+@pytest.mark.parametrize("geom,prm,p,L", [(0, (), 1, 0), (0, (), 2, 1), (0, (), 1, 2), (1, (0.8, 1.1, 1.3), 2, 1),
+                                          (2, (1.0, 0.4), 1, 1), (2, (1.0, 0.4), 2, 1), (3, (1.7,), 1, 1),
+                                          (3, (1.7,), 2, 2)])
+def test_s1_gluing_equals_oracle(B, orc, geom, prm, p, L):
+    """The host gluing of a div-conforming space (App. E: normal continuity across patch
+    edges, dropped edge functions on open surfaces) equals the oracle's, map and signs."""
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, B.BEM_MAXWELL_SINGLE, 1.5, degree=p, level=L)
+    So = orc.MSpace(geom, list(prm), 1.5, p=p, level=L)
+    m, sg = So.glue()
+    assert s.ndof == So.nglob
+    assert np.array_equal(s.glue(), m.astype(np.int32)) and np.array_equal(s.glue_sign(), sg)
+    A = B.Operator(s, qg=6, qs=5, assemble=False)
+    assert A.ndof == So.nglob and A.info.nlocal == So.nloc
+    # the touching element pairs are those of the scalar near field at the finest leaf level
+    s2 = B.Space(g, B.BEM_HELMHOLTZ_SINGLE, 1.5, degree=0, level=L)
+    A2 = B.Operator(s2, q=3, eta=1.6, leaf_level=L, assemble=False)
+    assert A.info.ntouch == A2.info.ntouch and A.info.nnear == (s2.ndof) ** 2
+    assert A.info.op_bytes >= 16 * So.nglob ** 2
+
+
+def test_s1_nurbs_gluing_equals_oracle(B, orc):
+    g = B.Geometry.nurbs(W.nurbs_torus(1.0, 0.4))
+    s = B.Space(g, B.BEM_MAXWELL_SINGLE, 1.5, degree=2, level=1)
+    So = orc.MSpace(4, W.nurbs_torus(1.0, 0.4), 1.5, p=2, level=1)
+    m, sg = So.glue()
+    assert s.ndof == So.nglob == 16 * 2 * 4 * 3 - 32 * 3
+    assert np.array_equal(s.glue(), m.astype(np.int32)) and np.array_equal(s.glue_sign(), sg)
+
+
+def test_s1_argument_validation(B, tmp_path):
+    C = B._bem
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    h = ctypes.c_void_p()
+    # kernel and space kind go together
+    assert C.lib.bem_space_create_ex(g.h, 2, 1.0, 0.0, 1, 1, 1, C.BEM_SPACE_S2, ctypes.byref(h)) == C.BEM_EINVAL
+    assert C.lib.bem_space_create_ex(g.h, 1, 1.0, 0.0, 1, 1, 1, C.BEM_SPACE_S1, ctypes.byref(h)) == C.BEM_EINVAL
+    for kw, code in [(dict(degree=0), C.BEM_EINVAL), (dict(degree=3), C.BEM_EUNSUPPORTED),
+                     (dict(degree=2, knot_repetition=2), C.BEM_EUNSUPPORTED), (dict(kappa=0.0), C.BEM_EINVAL)]:
+        args = dict(kappa=1.5, degree=1, level=1)
+        args.update(kw)
+        with pytest.raises(C.BemError) as e:
+            B.Space(g, B.BEM_MAXWELL_SINGLE, **args)
+        assert e.value.code == code, kw
+    s = B.Space(g, B.BEM_MAXWELL_SINGLE, 1.5, degree=1, level=1)
+    for kw, code in [(dict(eta=1.6), C.BEM_EUNSUPPORTED), (dict(far_low=1), C.BEM_EUNSUPPORTED),
+                     (dict(batch_rhs=8), C.BEM_EUNSUPPORTED), (dict(far_eval=True), C.BEM_EUNSUPPORTED),
+                     (dict(qg=9), C.BEM_EINVAL), (dict(qs=0), C.BEM_EINVAL)]:
+        with pytest.raises(C.BemError) as e:
+            B.Operator(s, assemble=False, **kw)
+        assert e.value.code == code, kw
+    A = B.Operator(s, assemble=False)
+    n64, sz = ctypes.c_int64(), ctypes.c_size_t()
+    for call in (lambda: C.check(C.lib.bem_export_near(A.h, None, None, None, None)),
+                 lambda: C.check(C.lib.bem_export_far(A.h, None, None, None)),
+                 lambda: C.check(C.lib.bem_precond_info(A.h, ctypes.byref(n64), ctypes.byref(sz))),
+                 lambda: s.write_vtk(str(tmp_path / "s1.vtk")),
+                 lambda: C.check(C.lib.bem_rhs_quadpoints(s.h, None, ctypes.byref(ctypes.c_int64()), None)),
+                 lambda: C.check(C.lib.bem_profile_enable(A.h, 1)),
+                 lambda: C.check(C.lib.bem_apply_stage(A.h, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None))):
+        with pytest.raises(C.BemError) as e:
+            call()
+        assert e.value.code in (C.BEM_EUNSUPPORTED, C.BEM_EINVAL)
+    # scalar spaces: all signs +1
+    s2 = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=1, continuous=True)
+    assert (s2.glue_sign() == 1).all() and s2.glue_sign().size == C.bem_space_glue(s2.h)[0]
