@@ -100,6 +100,7 @@ def lib():
             "orc_m_elem_eval": (I, [P, I64, D, D, P, P, P, P]),
             "orc_m_pair_block": (I, [P, I64, I64, I, I, I, P]),
             "orc_m_dense": (I, [P, I, I, I, P]),
+            "orc_m_h2_dense": (I, [P, I, D, I, I, I, D, I, P]),
             "orc_m_rhs": (I, [P, I, P, I, I, P]),
             "orc_m_potential": (I, [P, I, P, I64, P, P]),
             "orc_m_field": (I, [I, P, D, D, I64, P, P]),
@@ -531,6 +532,14 @@ class MSpace:
         vector term only, 2: the divergence term only."""
         M = np.zeros((self.nglob, self.nglob), dtype=np.complex128)
         _check(lib().orc_m_dense(self._h, qg, qs, part, _p(M)))
+        return M
+
+    def h2_dense(self, q: int = 5, eta: float = 1.6, leaf: int = 0, qg: int = 8, qs: int = 8,
+                 kappa_adm: float = 0.0, part: int = 0) -> np.ndarray:
+        """The Galerkin matrix with the far field of the scalar H^2 partition replaced by the
+        Chebyshev interpolation of the kernel on both clusters (four channels)."""
+        M = np.zeros((self.nglob, self.nglob), dtype=np.complex128)
+        _check(lib().orc_m_h2_dense(self._h, q, float(eta), leaf, qg, qs, float(kappa_adm), part, _p(M)))
         return M
 
     def rhs(self, kind: int, params, q: int = 8) -> np.ndarray:

@@ -1,7 +1,9 @@
 // Oracle of the isogeometric Galerkin BEM hot path: Laplace and Helmholtz single-layer
 // operators on multi-patch surfaces, assembled densely or as an interpolation-based H^2
 // matrix, plus the right-hand side, the potential and restarted GMRES; the Maxwell single
-// layer on div-conforming spaces, assembled densely, with its load vector and field.
+// layer on div-conforming spaces, assembled densely or with its far field compressed by the
+// same interpolation (four channels on the scalar block partition), with its load vector
+// and field.
 //
 // TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which is loaded by
 // tests/, by the smoke check and by the CPU-baseline leg of bench.py, and by nothing on the
@@ -22,6 +24,9 @@
 // operator itself is pinned three ways: eta -> 0 gives the dense matrix, the error decays
 // geometrically in q, and its matvec equals the operator written out from the definition
 // (interpolated kernel on every far pair, scipy B-splines and Gauss rules; flat square).
+// The compressed Maxwell form is pinned the same way (eta = 0 gives its dense matrix, the
+// error decays geometrically in q) and its divergence channel equals the scalar compressed
+// operator of the divergences.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -2002,6 +2007,122 @@ static void m_dense(const MSpace& S, int qg, int qs, int part, cplx* M) {
     }
 }
 
+// Maxwell single layer compressed by the interpolation of Sec. 2 on the block partition of
+// the scalar operators (same cluster tree, admissibility and Chebyshev nodes; the partition
+// and the kernel blocks are those of the scalar H^2 operator of the element space of the
+// same surface and wavenumber).  Element pairs inside near leaf pairs keep their Galerkin
+// blocks.  For element pairs inside an admissible block (t, s) the kernel is replaced by its
+// tensor interpolant in the two clusters' parameter squares, which turns the form into four
+// scalar products, one per channel c (the three components of the lifted field, and the
+// divergence with the factor -kappa^-2):
+//   B[i][j] = sum_c w_c sum_a sum_b Mt_c[i][a] G(x_a^t, x_b^s) Ms_c[j][b],
+//   Mt_c[i][a] = integral over the element of L_a^t times channel c of function i
+// (qg x qg Gauss points per element, the element's parameter area h^2 included).  Every
+// block interpolates directly on its own two clusters (no nested transfers).  part as in
+// m_pair_block.  Dense output on the global functions, as m_dense.
+static void m_h2_dense(const MSpace& S, int q, double eta, int leaf, int qg, int qs, double kadm, int part, cplx* M) {
+    H2<cplx> H;
+    h2_build(H, S.geo, q, eta, leaf, qg, qs, false, kadm);
+    const int64_t N = S.nglob;
+    const int nl = m_nl(S), q2 = q * q;
+    const cplx ik2 = -1.0 / (S.kappa * S.kappa);
+    const cplx wc[4] = {part == 2 ? 0.0 : 1.0, part == 2 ? 0.0 : 1.0, part == 2 ? 0.0 : 1.0,
+                        part == 1 ? cplx(0.0) : ik2};
+    std::fill(M, M + N * N, cplx(0.0));
+    std::vector<int64_t> l1(nl), l2(nl);
+    auto glue_block = [&](int64_t e1, int64_t e2, const cplx* B) {
+        m_elem_lids(S, e1, l1.data());
+        m_elem_lids(S, e2, l2.data());
+        for (int i = 0; i < nl; ++i) {
+            const int64_t g = S.glob[l1[i]];
+            if (g < 0) continue;
+            for (int j = 0; j < nl; ++j) {
+                const int64_t hcol = S.glob[l2[j]];
+                if (hcol < 0) continue;
+                M[g * N + hcol] += (double)(S.sgn[l1[i]] * S.sgn[l2[j]]) * B[i * nl + j];
+            }
+        }
+    };
+    // channel moments of element e against the Lagrange polynomials of cluster c
+    const Rule g = gauss01(qg);
+    std::map<std::pair<int64_t, int64_t>, std::vector<double>> cache;
+    auto moments = [&](int64_t c, int64_t e) -> const std::vector<double>& {
+        auto it = cache.find({c, e});
+        if (it != cache.end()) return it->second;
+        std::vector<double> Mo((size_t)nl * 4 * q2, 0.0);  // [i][c][a]
+        const Cluster& C = H.cl[c];
+        const Elem E = elem_of(S.geo, e);
+        const double n = (double)(1 << C.lev);
+        std::vector<double> V(3 * nl), Dv(nl);
+        std::vector<int64_t> lid(nl);
+        double x[3];
+        for (int k1 = 0; k1 < qg; ++k1)
+            for (int k2 = 0; k2 < qg; ++k2) {
+                const double s = (E.i1 + g.x[k1]) * S.h, t = (E.i2 + g.x[k2]) * S.h;
+                m_elem_eval(S, E, s, t, x, V.data(), Dv.data(), lid.data());
+                const double w = g.w[k1] * g.w[k2] * S.h * S.h;
+                for (int a = 0; a < q2; ++a) {
+                    const double La = lagrange(H.xi, a / q, s * n - C.i) * lagrange(H.xi, a % q, t * n - C.j) * w;
+                    for (int i = 0; i < nl; ++i) {
+                        double* m = &Mo[((size_t)i * 4) * q2 + a];
+                        m[0] += La * V[3 * i];
+                        m[q2] += La * V[3 * i + 1];
+                        m[2 * q2] += La * V[3 * i + 2];
+                        m[3 * q2] += La * Dv[i];
+                    }
+                }
+            }
+        return cache.emplace(std::make_pair(c, e), std::move(Mo)).first->second;
+    };
+    std::vector<cplx> B((size_t)nl * nl), T((size_t)nl * 4 * q2);
+    std::vector<int64_t> et, es;
+    for (size_t blk = 0; blk < H.far.size(); ++blk) {
+        const int64_t t = H.far[blk].first, sc = H.far[blk].second;
+        const cplx* K = &H.K[blk * (size_t)q2 * q2];
+        leaf_elements(H, t, et);
+        leaf_elements(H, sc, es);
+        for (int64_t e2 : es) {
+            // T[j][c][a] = sum_b K[a][b] Ms_c[j][b]
+            const std::vector<double>& Ms = moments(sc, e2);
+            for (int j = 0; j < nl; ++j)
+                for (int c = 0; c < 4; ++c)
+                    for (int a = 0; a < q2; ++a) {
+                        cplx v = 0.0;
+                        for (int b = 0; b < q2; ++b) v += K[a * q2 + b] * Ms[((size_t)j * 4 + c) * q2 + b];
+                        T[((size_t)j * 4 + c) * q2 + a] = v;
+                    }
+            for (int64_t e1 : et) {
+                const std::vector<double>& Mt = moments(t, e1);
+                for (int i = 0; i < nl; ++i)
+                    for (int j = 0; j < nl; ++j) {
+                        cplx v = 0.0;
+                        for (int c = 0; c < 4; ++c) {
+                            cplx u = 0.0;
+                            for (int a = 0; a < q2; ++a)
+                                u += Mt[((size_t)i * 4 + c) * q2 + a] * T[((size_t)j * 4 + c) * q2 + a];
+                            v += wc[c] * u;
+                        }
+                        B[i * nl + j] = v;
+                    }
+                glue_block(e1, e2, B.data());
+            }
+        }
+    }
+    // near element pairs: blocks in parallel, glued in list order
+    std::vector<std::pair<int64_t, int64_t>> np;
+    for (const auto& pr : H.near) {
+        leaf_elements(H, pr.first, et);
+        leaf_elements(H, pr.second, es);
+        for (int64_t e1 : et)
+            for (int64_t e2 : es) np.push_back({e1, e2});
+    }
+    std::vector<cplx> NB(np.size() * (size_t)nl * nl);
+    const int64_t nnp = (int64_t)np.size();
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nnp; ++k) m_pair_block(S, np[k].first, np[k].second, qg, qs, part, &NB[k * nl * nl]);
+    for (int64_t k = 0; k < nnp; ++k) glue_block(np[k].first, np[k].second, &NB[k * nl * nl]);
+}
+
 // Data fields (solutions of (MP) away from their source).  kind 0: the field of a point
 // dipole of moment m at x0, E = curl curl (m G(x - x0)) = kappa^2 m G + grad (m . grad G);
 // kind 1: a plane wave E = e exp(-i kappa d . x) (e perpendicular to d), the sign of the
@@ -2826,6 +2947,15 @@ int orc_m_pair_block(void* sp, int64_t e1, int64_t e2, int qg, int qs, int part,
 
 int orc_m_dense(void* sp, int qg, int qs, int part, double* M) {
     ORC_TRY({ m_dense(((OrcMSpace*)sp)->S, qg, qs, part, (cplx*)M); })
+}
+
+// Maxwell matrix with the far field compressed on the scalar H^2 partition (q, eta, leaf, kadm)
+int orc_m_h2_dense(void* sp, int q, double eta, int leaf, int qg, int qs, double kadm, int part, double* M) {
+    ORC_TRY({
+        const MSpace& S = ((OrcMSpace*)sp)->S;
+        if (leaf < 0 || leaf > S.L) throw std::runtime_error("leaf level must lie in [0, L]");
+        m_h2_dense(S, q, eta, leaf, qg, qs, kadm, part, (cplx*)M);
+    })
 }
 
 // nrhs load vectors, 6 parameters each (dipole: x0, moment; plane wave: direction, polarisation)

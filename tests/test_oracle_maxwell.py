@@ -17,6 +17,10 @@ div-conforming spaces S^1 (App. E) against facts outside the Maxwell code.
 - Exterior problem: the field of the solved density reproduces the dipole's field outside
   the sphere, converging with order about 3 for p = 1 and about 5 for p = 2 (Fig. 1 reports
   orders 3, 5 and 7 for P = 1, 2, 3).
+- The compressed form (the far field of the scalar H^2 partition interpolated, four
+  channels): with eta = 0 it is the Galerkin matrix; its error against the Galerkin matrix
+  decays geometrically in q (Sec. 2); its divergence channel is -kappa^-2 D^T H D with H the
+  scalar oracle's H^2 matrix of the S^2 space of degree p - 1 (pinned on its own).
 All run on the CPU.
 """
 import numpy as np
@@ -96,16 +100,14 @@ def test_normal_component_is_continuous(orc):
     assert checked > 100
 
 
-@pytest.mark.parametrize("p,L", [(1, 1), (2, 1)])
-def test_divergence_term_is_the_scalar_single_layer_of_the_divergences(orc, p, L):
-    S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
-    Md = S.dense(part=2)
-    V = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, KAPPA, degree=p - 1, level=L).dense()
+def divergence_map(S, p, L, nrows):
+    """D: glued S^1 coefficients -> coefficients of the S^2 space of degree p - 1 of their
+    surface divergences (times the surface element), from the B-spline derivative identity:
+    on the degree-p knots d/dx b^p_j = p b^{p-1}_j / (xi_{j+p} - xi_j)
+    - p b^{p-1}_{j+1} / (xi_{j+p+1} - xi_{j+1}), the degree-(p-1) functions of the degree-p
+    knots being those of the truncated knots shifted by one index (App. C, App. E)."""
     g, sg = S.glue()
     nbp, nbq = (1 << L) + p, (1 << L) + p - 1
-    # degree-p knots; d/dx b^p_j = p b^{p-1}_j / (xi_{j+p} - xi_j) - p b^{p-1}_{j+1} / (xi_{j+p+1} - xi_{j+1}),
-    # the degree-(p-1) functions of the degree-p knots being those of the truncated knots
-    # shifted by one index (App. C, App. E)
     xi = np.concatenate([np.zeros(p + 1), np.arange(1, 1 << L) / (1 << L), np.ones(p + 1)])
 
     def dcoef(j):
@@ -117,7 +119,7 @@ def test_divergence_term_is_the_scalar_single_layer_of_the_divergences(orc, p, L
             out[j] = out.get(j, 0.0) - p / (xi[j + p + 1] - xi[j + 1])
         return {k: v for k, v in out.items() if 0 <= k < nbq}
 
-    D = np.zeros((V.shape[0], S.nglob))
+    D = np.zeros((nrows, S.nglob))
     per = nbp * nbq
     for f in range(6):
         for c in range(2):
@@ -128,8 +130,58 @@ def test_divergence_term_is_the_scalar_single_layer_of_the_divergences(orc, p, L
                     for k, v in dcoef(a).items():
                         j1, j2 = (k, b) if c == 0 else (b, k)
                         D[(f * nbq + j1) * nbq + j2, g[lid]] += sg[lid] * v
+    return D
+
+
+@pytest.mark.parametrize("p,L", [(1, 1), (2, 1)])
+def test_divergence_term_is_the_scalar_single_layer_of_the_divergences(orc, p, L):
+    S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
+    Md = S.dense(part=2)
+    V = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, KAPPA, degree=p - 1, level=L).dense()
+    D = divergence_map(S, p, L, V.shape[0])
     ref = -(D.T @ V @ D) / KAPPA ** 2
     assert np.max(np.abs(Md - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# ---- the compressed form (Sec. 2 interpolation on the scalar block partition)
+
+def test_compressed_form_without_admissible_blocks_is_the_galerkin_matrix(orc):
+    """eta = 0 admits no block: every element pair keeps its Galerkin block."""
+    S = orc.MSpace(orc.TORUS, [1.0, 0.4], KAPPA, p=2, level=1)
+    M = S.dense(qg=6, qs=5)
+    H = S.h2_dense(q=3, eta=0.0, leaf=1, qg=6, qs=5)
+    assert np.max(np.abs(H - M)) <= 1e-14 * np.max(np.abs(M))
+
+
+@pytest.mark.parametrize("p,L,leaf", [(1, 2, 2), (2, 2, 1)])
+def test_compressed_form_converges_geometrically_in_q(orc, p, L, leaf):
+    """The interpolation error of an analytic kernel on admissible blocks decays
+    geometrically with the number of Chebyshev nodes (Sec. 2): the compressed matrix tends
+    to the pinned Galerkin matrix, two orders of magnitude per two more nodes."""
+    S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
+    M = S.dense()
+    errs = [np.max(np.abs(S.h2_dense(q=q, eta=1.6, leaf=leaf) - M)) / np.max(np.abs(M)) for q in (2, 4, 6)]
+    print(f"p = {p}: compressed-form errors for q = 2, 4, 6: {errs}")
+    assert errs[0] / errs[1] >= 30 and errs[1] / errs[2] >= 30 and errs[2] <= 1e-6
+
+
+def test_compressed_divergence_term_is_the_scalar_compressed_operator(orc):
+    """The divergence channel of the compressed form is the scalar H^2 operator of the
+    divergences: -kappa^-2 D^T H D with H the oracle's own (separately pinned) H^2 matrix of
+    the S^2 space of degree p - 1 on the same partition; both moment rules are exact for
+    these polynomial integrands, so the two agree to rounding."""
+    p, L, q, leaf = 2, 2, 4, 1
+    S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
+    Md = S.h2_dense(q=q, eta=1.6, leaf=leaf, part=2)
+    Sc = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, KAPPA, degree=p - 1, level=L)
+    Hs = orc.H2(Sc, q=q, eta=1.6, leaf=leaf)
+    assert Hs.nfar > 0
+    Hm = Hs.apply(np.eye(Sc.ndof, dtype=np.complex128))
+    D = divergence_map(S, p, L, Sc.ndof)
+    ref = -(D.T @ Hm @ D) / KAPPA ** 2
+    assert np.max(np.abs(Md - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # and it is not the uncompressed term (the far field is really replaced)
+    assert np.max(np.abs(Md - S.dense(part=2))) >= 1e-8 * np.max(np.abs(ref))
 
 
 def curl_curl_residual(field, x, kappa, d=1e-3):
