@@ -280,11 +280,22 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
  * support centre of the tangential factor).  Edge functions without a partner (open
  * surfaces) are dropped.  Global functions are numbered in the order of their first local
  * function; bem_space_glue gives the map (-1: dropped), bem_space_glue_sign the signs.
- * Operators on S^1 spaces are dense (bem_assemble_plan needs eta = 0; far_low = 0,
- * batch_rhs <= 1, far_eval = 0; 1 <= qg <= 8 and 1 <= qs <= 16; at most 32768 elements), FP64
- * complex; bem_apply and bem_solve (no preconditioner, no refinement) work as for the other
- * spaces; the block preconditioner, grouped launches, stage timing, the exports, the
- * cluster-tree potential, sampled data and VTK output return EUNSUPPORTED. */
+ * Operators on S^1 spaces (FP64 complex; far_low = 0, batch_rhs <= 1, far_eval = 0;
+ * 1 <= qg <= 8, 1 <= qs <= 16):
+ *   eta = 0: dense Galerkin matrix (at most 32768 elements; tmp workspace of every element
+ *     pair's block, nelem^2 (2p(p+1))^2 complex);
+ *   eta > 0: compressed by the interpolation of Sec. 2 on the block partition of the scalar
+ *     operators of the same surface (cluster tree, admissibility, q Chebyshev nodes per
+ *     direction, 1 <= q <= 8, leaf_level; default leaf level L - 1).  The form splits into
+ *     four scalar kernel products, one per channel: the three components of the lifted
+ *     field and the divergence (weight -kappa^-2), so one coupling block of the kernel serves
+ *     all four; element pairs in near leaf pairs keep their Galerkin blocks.  The channel
+ *     moments of every element against its leaf's Lagrange polynomials use the qg x qg
+ *     Gauss rule per element.  info.nfar/nnear/nclusters describe the partition, near_nnz the
+ *     stored near-block entries.
+ * bem_apply and bem_solve (no preconditioner, no refinement) work as for the other spaces;
+ * the block preconditioner, grouped launches, stage timing, the exports, the cluster-tree
+ * potential, sampled data and VTK output return EUNSUPPORTED. */
 int bem_space_create_ex(bem_geometry g, int kernel, double kappa_re, double kappa_im, int degree,
                         int knot_repetition, int level, int space_kind, bem_space* out);
 /* N: the space's functions (S^0: global, glued ones). */

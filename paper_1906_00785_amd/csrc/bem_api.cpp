@@ -140,6 +140,10 @@ struct bem_operator_s {
     // Maxwell single layer on S^1: dense operator (element-pair classification in plan)
     bool mx = false;
     MxDev mxd{};
+    bool mxh = false;  // far field compressed (Sec. 2 interpolation, four channels)
+    MxhDev mxhd{};
+    std::vector<int64_t> mxh_plist;  // near element pairs (host copy, as the pair types)
+    std::vector<double> mxh_lg;      // leaf Lagrange values at the Gauss points (same)
     std::vector<int32_t> mx_tinfo;  // host copies of the pair types and the Gauss rules (kept,
     std::vector<double> mx_rules;   // the uploads are asynchronous)
     size_t scal = 8;  // bytes per scalar
@@ -398,6 +402,7 @@ static size_t solve_layout(int64_t N, int m, size_t sc, void* base, SolveWs* ws,
 // y = A x for one column of global functions: on an S^0 space the column is spread to the
 // local functions, multiplied, and the local products of each global function summed.
 static hipError_t op_apply(const bem_operator_s* A, int prec, const void* x, void* y, hipStream_t stream) {
+    if (A->mxh) return launch_mxh_apply(A->mxhd, x, y, stream);
     if (A->mx) return launch_mx_matvec(A->mxd, x, y, stream);
     const SpaceDesc& S = A->dev.S;
     if (S.form != 0) return launch_apply(A->dev, x, y, prec, stream);
@@ -1527,12 +1532,15 @@ static size_t mx_layout(const bem_operator_s& A, char* ob, char* tb, MxDev* d) {
 
 // Plan of the dense Maxwell operator: every element pair, touching ones classified as for the
 // scalar near field (App. C: Duffy rules of the identical, edge and vertex cases).
+static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info);
+
 static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
-    if (p->eta != 0.0) return fail(BEM_EUNSUPPORTED, "S^1 operators are assembled densely: set eta = 0");
     if (p->far_low != 0 || p->batch_rhs > 1 || p->far_eval != 0)
         return fail(BEM_EUNSUPPORTED, "S^1 operators: FP64, one column per pass (far_low = 0, batch_rhs <= 1, far_eval = 0)");
     if (p->qg < 1 || p->qg > 8 || p->qs < 1 || p->qs > 16)
         return fail(BEM_EINVAL, "S^1 operators: qg must lie in [1, 8] and qs in [1, 16]");
+    if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(BEM_EINVAL, "eta must be finite and >= 0");
+    if (p->eta > 0.0) return mxh_plan(s, p, out, info);
     const SpaceDesc& S = s->S;
     if (S.nelem > 32768) return fail(BEM_EUNSUPPORTED, "S^1 operators: at most 32768 elements (dense pair table)");
     std::vector<int64_t> pairs;
@@ -1571,6 +1579,7 @@ static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, be
     d.nglob = S.nglob;
     d.qg = p->qg;
     d.qs = p->qs;
+    d.npairs = S.nelem * S.nelem;
     const int64_t N = S.nglob;
     bem_operator_info& I = A->info;
     I.ndof = N;
@@ -1587,13 +1596,17 @@ static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, be
     return BEM_OK;
 }
 
+static int mxh_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t stream);
+
 static int mx_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t stream) {
     if (need_mx_device(A->sp) != BEM_OK) return BEM_EDEVICE;
+    if (A->mxh) return mxh_assemble(A, op_ws, tmp_ws, stream);
     char* ob = (char*)(((uintptr_t)op_ws + 255) / 256 * 256);
     char* tb = (char*)(((uintptr_t)tmp_ws + 255) / 256 * 256);
     MxDev d = mx_dev_of(A->sp);
     d.qg = A->mxd.qg;
     d.qs = A->mxd.qs;
+    d.npairs = A->mxd.npairs;
     mx_layout(*A, ob, tb, &d);
     HIP_CHECK(hipMemcpyAsync((void*)d.tinfo, A->mx_tinfo.data(), A->mx_tinfo.size() * 4, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync((void*)d.gx, A->mx_rules.data(), A->mx_rules.size() * 8, hipMemcpyHostToDevice, stream));
@@ -1604,6 +1617,234 @@ static int mx_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t
     d.tinfo = nullptr;
     d.gx = d.gw = d.sx = d.sw = nullptr;
     A->mxd = d;
+    A->assembled = true;
+    return BEM_OK;
+}
+
+// Workspace of the compressed S^1 operator.  op: kernel blocks, near element-pair blocks,
+// channel moments, the matvec scratch and the tree tables; tmp: the near pair list and
+// types, the cluster points and the quadrature tables of the assembly.
+static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d, size_t* tmp_bytes) {
+    const Plan& pl = A.plan;
+    const MxhDev& h = A.mxhd;
+    const int64_t q2 = h.q2, nl = h.s.nl, ne = h.s.nelem, npairs = h.s.npairs;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* q = ob ? ob + off : nullptr;
+        off += al(bytes);
+        return q;
+    };
+    char* K = take((size_t)h.nfar * q2 * q2 * 16);
+    char* NB = take((size_t)npairs * nl * nl * 16);
+    char* Mt = take((size_t)ne * nl * 4 * q2 * 8);
+    char* xl = take((size_t)ne * nl * 16);
+    char* yl = take((size_t)ne * nl * 16);
+    char* mom = take((size_t)h.ncl * 4 * q2 * 16);
+    char* lv = take((size_t)h.ncl * 4 * q2 * 16);
+    char* lev = take(pl.lev_off.size() * 8);
+    char* frp = take(pl.far_rowptr.size() * 8);
+    char* fs = take(pl.far_s.size() * 4);
+    char* ft = take(pl.far_t.size() * 4);
+    char* nrp = take(pl.near_rowptr.size() * 4);
+    char* ns = take(pl.near_s.size() * 4);
+    char* cheb = take(pl.cheb.size() * 8);
+    char* E = take(pl.E.size() * 8);
+    const size_t op_total = off + 256;
+    size_t toff = 0;
+    auto ttake = [&](size_t bytes) {
+        char* q = tb ? tb + toff : nullptr;
+        toff += al(bytes);
+        return q;
+    };
+    char* plist = ttake((size_t)npairs * 8);
+    char* tinfo = ttake((size_t)npairs * 4);
+    char* xc = ttake((size_t)h.ncl * q2 * 3 * 8);
+    char* rules = ttake(sizeof(double) * (2 * h.s.qg + 2 * h.s.qs));
+    char* lg = ttake(A.mxh_lg.size() * 8);
+    if (tmp_bytes) *tmp_bytes = toff + 256;
+    if (ob && tb && d) {
+        d->K = K;
+        d->s.B = NB;
+        d->Mt = (double*)Mt;
+        d->xl = xl;
+        d->yl = yl;
+        d->mom = mom;
+        d->lv = lv;
+        d->lev_off = (const int64_t*)lev;
+        d->far_rowptr = (const int64_t*)frp;
+        d->far_s = (const int32_t*)fs;
+        d->far_t = (const int32_t*)ft;
+        d->near_rowptr = (const int32_t*)nrp;
+        d->near_s = (const int32_t*)ns;
+        d->cheb = (const double*)cheb;
+        d->E = (const double*)E;
+        d->s.plist = (const int64_t*)plist;
+        d->s.tinfo = (const int32_t*)tinfo;
+        d->xc = (double*)xc;
+        d->s.gx = (const double*)rules;
+        d->s.gw = d->s.gx + h.s.qg;
+        d->s.sx = d->s.gw + h.s.qg;
+        d->s.sw = d->s.sx + h.s.qs;
+        d->Lg = (const double*)lg;
+    }
+    return op_total;
+}
+
+// Plan of the compressed S^1 operator: the block partition of the scalar operators on the
+// same patches (cluster tree, admissibility, near leaf pairs with their touching element
+// pairs), from the element space of the same surface and wavenumber.
+static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
+    if (p->q < 1 || p->q > 8) return fail(BEM_EINVAL, "q must lie in [1, 8]");
+    if (!(p->kappa_adm >= 0.0) || !std::isfinite(p->kappa_adm)) return fail(BEM_EINVAL, "kappa_adm must be finite and >= 0");
+    const SpaceDesc& S = s->S;
+    if (p->leaf_level > S.L) return fail(BEM_EINVAL, "leaf level must lie in [0, L]");
+    SpaceDesc Sc = S;  // element space (degree 0) of the same surface and wavenumber
+    Sc.form = 2;
+    Sc.d = 0;
+    Sc.r = 1;
+    Sc.nb = Sc.nel;
+    Sc.ndof = Sc.nglob = S.nelem;
+    H2Params P;
+    P.q = p->q;
+    P.eta = p->eta;
+    P.leaf = p->leaf_level < 0 ? std::max(S.L - 1, 0) : p->leaf_level;
+    P.qg = p->qg;
+    P.qs = p->qs;
+    P.kadm = p->kappa_adm;
+    bem_operator_s* A = new (std::nothrow) bem_operator_s;
+    if (!A) return fail(BEM_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        if (!build_plan(Sc, P, A->plan, err)) {
+            delete A;
+            return fail(BEM_EINVAL, err);
+        }
+        const Plan& pl = A->plan;
+        const int m = pl.m, m2 = m * m;
+        const int64_t nnear = (int64_t)pl.near_t.size(), npairs = nnear * m2 * m2;
+        if (npairs > 0x7fffffff) {
+            delete A;
+            return fail(BEM_EUNSUPPORTED, "too many near element pairs (lower the leaf level's element count)");
+        }
+        auto elem = [&](int64_t l, int v) {
+            const int n1 = pl.nleaf1;
+            const int64_t f = l / ((int64_t)n1 * n1);
+            const int li = (int)((l / n1) % n1), lj = (int)(l % n1);
+            return (f * S.nel + li * m + v / m) * S.nel + lj * m + v % m;
+        };
+        A->mxh_plist.resize(npairs);
+        A->mx_tinfo.assign(npairs, 0);
+        for (int64_t lp = 0; lp < nnear; ++lp) {
+            for (int u = 0; u < m2; ++u)
+                for (int v = 0; v < m2; ++v)
+                    A->mxh_plist[(lp * m2 + u) * m2 + v] = elem(pl.near_t[lp], u) * S.nelem + elem(pl.near_s[lp], v);
+            for (int32_t k = pl.touch_rowptr[lp]; k < pl.touch_rowptr[lp + 1]; ++k) {
+                const int32_t* t5 = &pl.touch[5 * (size_t)k];
+                A->mx_tinfo[(lp * m2 + t5[0]) * m2 + t5[1]] = t5[2] | t5[3] << 4 | t5[4] << 8;
+            }
+        }
+        A->mx_rules.clear();
+        for (auto* v : {&pl.gx, &pl.gw, &pl.sx, &pl.sw}) A->mx_rules.insert(A->mx_rules.end(), v->begin(), v->end());
+        A->mxh_lg.assign((size_t)m * P.qg * P.q, 0.0);
+        for (int i = 0; i < m; ++i)
+            for (int k = 0; k < P.qg; ++k)
+                for (int a = 0; a < P.q; ++a)
+                    A->mxh_lg[((size_t)i * P.qg + k) * P.q + a] = lagrange_bary(pl.cheb, a, (i + pl.gx[k]) / m);
+    } catch (const std::bad_alloc&) {
+        delete A;
+        return fail(BEM_ENOMEM, "host allocation failed while planning");
+    }
+    const Plan& pl = A->plan;
+    A->sp = s;
+    A->mx = true;
+    A->mxh = true;
+    A->cplx = true;
+    A->scal = 16;
+    A->dev.S = S;
+    MxhDev& d = A->mxhd;
+    d = MxhDev{};
+    d.s.p = s->mx->p;
+    d.s.nl = s->mx->nl;
+    d.s.nel = S.nel;
+    d.s.nelem = S.nelem;
+    d.s.nglob = S.nglob;
+    d.s.qg = P.qg;
+    d.s.qs = P.qs;
+    d.s.npairs = (int64_t)A->mxh_plist.size();
+    d.q = P.q;
+    d.q2 = P.q * P.q;
+    d.leaf = pl.leaf;
+    d.m = pl.m;
+    d.nleaf1 = pl.nleaf1;
+    d.ncl = pl.ncl;
+    d.nleaves = pl.nleaves;
+    d.nfar = (int64_t)pl.far_t.size();
+    d.nnear = (int64_t)pl.near_t.size();
+    const int64_t N = S.nglob;
+    bem_operator_info& I = A->info;
+    I.ndof = N;
+    I.nlocal = S.ndof;
+    I.nclusters = pl.ncl;
+    I.nfar = d.nfar;
+    I.nnear = d.nnear;
+    I.ntouch = (int64_t)(pl.touch.size() / 5);
+    I.near_nnz = d.s.npairs * d.s.nl * d.s.nl;
+    I.leaf_level = pl.leaf;
+    size_t tmpb = 0;
+    I.op_bytes = mxh_layout(*A, nullptr, nullptr, nullptr, &tmpb);
+    I.tmp_bytes = tmpb;
+    I.far_bytes = (double)d.nfar * d.q2 * d.q2 * 16;
+    I.near_bytes = (double)I.near_nnz * 16;
+    // the plan's own arrays (they stay with the operator) are the scalar element space's;
+    // the operator is reported on S^1
+    A->plan.S.form = 1;
+    if (info) *info = I;
+    *out = A;
+    return BEM_OK;
+}
+
+static int mxh_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t stream) {
+    char* ob = (char*)(((uintptr_t)op_ws + 255) / 256 * 256);
+    char* tb = (char*)(((uintptr_t)tmp_ws + 255) / 256 * 256);
+    const Plan& pl = A->plan;
+    MxhDev d = A->mxhd;
+    const MxDev sd = mx_dev_of(A->sp);
+    d.s.geom = sd.geom;
+    d.s.ker = sd.ker;
+    d.s.h = sd.h;
+    d.s.polp = sd.polp;
+    d.s.polq = sd.polq;
+    d.s.eglob = sd.eglob;
+    d.s.esgn = sd.esgn;
+    d.s.gptr = sd.gptr;
+    d.s.gpos = sd.gpos;
+    d.s.gsgn = sd.gsgn;
+    mxh_layout(*A, ob, tb, &d, nullptr);
+    auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
+    };
+    HIP_CHECK(up(d.lev_off, pl.lev_off.data(), pl.lev_off.size() * 8));
+    HIP_CHECK(up(d.far_rowptr, pl.far_rowptr.data(), pl.far_rowptr.size() * 8));
+    HIP_CHECK(up(d.far_s, pl.far_s.data(), pl.far_s.size() * 4));
+    HIP_CHECK(up(d.far_t, pl.far_t.data(), pl.far_t.size() * 4));
+    HIP_CHECK(up(d.near_rowptr, pl.near_rowptr.data(), pl.near_rowptr.size() * 4));
+    HIP_CHECK(up(d.near_s, pl.near_s.data(), pl.near_s.size() * 4));
+    HIP_CHECK(up(d.cheb, pl.cheb.data(), pl.cheb.size() * 8));
+    HIP_CHECK(up(d.E, pl.E.data(), pl.E.size() * 8));
+    HIP_CHECK(up(d.s.plist, A->mxh_plist.data(), A->mxh_plist.size() * 8));
+    HIP_CHECK(up(d.s.tinfo, A->mx_tinfo.data(), A->mx_tinfo.size() * 4));
+    HIP_CHECK(up(d.s.gx, A->mx_rules.data(), A->mx_rules.size() * 8));
+    HIP_CHECK(up(d.Lg, A->mxh_lg.data(), A->mxh_lg.size() * 8));
+    HIP_CHECK(launch_mxh_assemble(d, stream));
+    // tables of the temporary workspace
+    d.s.plist = nullptr;
+    d.s.tinfo = nullptr;
+    d.s.gx = d.s.gw = d.s.sx = d.s.sw = nullptr;
+    d.xc = nullptr;
+    d.Lg = nullptr;
+    A->mxhd = d;
     A->assembled = true;
     return BEM_OK;
 }

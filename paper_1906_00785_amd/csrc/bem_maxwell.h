@@ -1,6 +1,7 @@
 // Maxwell single layer (App. A (MP), App. B (MS)) on the div-conforming spaces S^1 of App. E,
-// assembled densely on the device: element-pair blocks, the glued dense matrix, its
-// product, the load vector of dipole and plane-wave data and the field (MS) of a density.
+// assembled on the device densely (element-pair blocks, the glued dense matrix and its
+// product) or with the far field compressed by the interpolation of Sec. 2; the load vector
+// of dipole and plane-wave data and the field (MS) of a density.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,12 +33,43 @@ struct MxDev {
     const double* gw;
     const double* sx;        // [qs] Gauss rule of the Duffy cubes
     const double* sw;
-    void* B;                 // [nelem * nelem][nl][nl] complex element-pair blocks (test x trial)
+    void* B;                 // [npairs][nl][nl] complex element-pair blocks (test x trial)
     void* M;                 // [nglob][nglob] complex dense matrix, row-major (test x trial)
+    const int64_t* plist;    // [npairs] e1 * nelem + e2 of each block (null: all pairs, in order)
+    int64_t npairs;          // blocks to compute (nelem * nelem without a list)
 };
 
-// element-pair blocks of every pair (tau test, sigma trial)
+// The compressed operator (Sec. 2 interpolation on the scalar block partition, four
+// channels: the three components of the lifted field and the divergence).
+struct MxhDev {
+    MxDev s;                     // space, Gauss rules; s.B: near element-pair blocks
+    int q, q2, leaf, m, nleaf1;  // m: elements per leaf per direction
+    int64_t ncl, nleaves, nfar, nnear;
+    const int64_t* lev_off;      // [leaf + 2] first cluster of every level
+    const double* cheb;          // [q] Chebyshev nodes on [0, 1]
+    const double* E;             // [2][q][q]: E[b][p][a] = L_a(child b's node p in the parent)
+    const int64_t* far_rowptr;   // [ncl + 1] ordered admissible pairs by target
+    const int32_t* far_s;        // [nfar] source
+    const int32_t* far_t;        // [nfar] target
+    void* K;                     // [nfar][q2 (source b)][q2 (target a)] complex G(x_a^t, x_b^s)
+    const int32_t* near_rowptr;  // [nleaves + 1] near leaf pairs by target leaf
+    const int32_t* near_s;       // [nnear] source leaf (leaf-local index)
+    double* Mt;                  // [nelem][nl][4][q2] channel moments against the leaf's Lagrange polynomials
+    double* xc;                  // [ncl][q2][3] Chebyshev points on the surface (assembly)
+    const double* Lg;            // [m][qg][q] L_a at Gauss point k of element position i in its
+                                 // leaf, (i + x_k) / m (assembly)
+    void* xl;                    // [nelem][nl] complex: signed coefficients per element
+    void* yl;                    // [nelem][nl] complex: product per element
+    void* mom;                   // [ncl][4][q2] complex moments
+    void* lv;                    // [ncl][4][q2] complex local expansions
+};
+
+// element-pair blocks (tau test, sigma trial) of every pair, or of the pairs in d.plist
 hipError_t launch_mx_pairs(const MxDev& d, hipStream_t st);
+// compressed operator: cluster points, kernel blocks, channel moments, near blocks
+hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st);
+// y = A x with the compressed operator (complex, one column)
+hipError_t launch_mxh_apply(const MxhDev& d, const void* x, void* y, hipStream_t st);
 // M[g][h] = sum over the pieces of g and h of the signed block entries
 hipError_t launch_mx_gather(const MxDev& d, hipStream_t st);
 // y = M x (complex, one column)

@@ -100,13 +100,14 @@ __global__ __launch_bounds__(64) void k_mx_pairs(MxDev d) {
     double* Wl = Fi + 64 * NC;       // [64][NC]
     double* Xt = Wl + 64 * NC;       // [64][3] test points (regular pairs)
     double* WX = Xt + 64 * 3;        // [64][NC] test-side values times weights (regular pairs)
-    const int64_t pr = blockIdx.x;
+    const int64_t blk = blockIdx.x;
+    const int64_t pr = d.plist ? d.plist[blk] : blk;
     const int64_t e1 = pr / d.nelem, e2 = pr % d.nelem;
     const int lane = threadIdx.x;
     const int n = d.nel;
     const int ti2 = (int)(e1 % n), ti1 = (int)((e1 / n) % n), tf = (int)(e1 / ((int64_t)n * n));
     const int si2 = (int)(e2 % n), si1 = (int)((e2 / n) % n), sf = (int)(e2 / ((int64_t)n * n));
-    const int info = d.tinfo[pr];
+    const int info = d.tinfo[blk];
     double accr[NE][2], acci[NE][2];  // [entry][vector part, divergence part]
 #pragma unroll
     for (int e = 0; e < NE; ++e) accr[e][0] = accr[e][1] = acci[e][0] = acci[e][1] = 0.0;
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(64) void k_mx_pairs(MxDev d) {
     const cdbl k2 = cmul(cdbl{d.ker.kre, d.ker.kim}, cdbl{d.ker.kre, d.ker.kim});
     const double den = k2.re * k2.re + k2.im * k2.im;
     const cdbl mik2 = {-k2.re / den, k2.im / den};  // -1 / kappa^2
-    cdbl* B = (cdbl*)d.B + pr * NL * NL;
+    cdbl* B = (cdbl*)d.B + blk * NL * NL;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         const int ent = lane + 64 * e;
@@ -414,6 +415,330 @@ __global__ __launch_bounds__(256) void k_mx_field(MxDev d, Gauss8 g8, const doub
     }
 }
 
+// ------------------------------------------------------------------ compressed operator
+// Cluster c = (level, patch, i, j) of the uniform quadtree of every patch.
+__device__ inline void cluster_of(const MxhDev& d, int64_t c, int& lev, int& f, int& i, int& j) {
+    lev = 0;
+    while (c >= d.lev_off[lev + 1]) ++lev;
+    const int64_t loc = c - d.lev_off[lev];
+    const int n = 1 << lev;
+    j = (int)(loc % n);
+    i = (int)((loc / n) % n);
+    f = (int)(loc / ((int64_t)n * n));
+}
+
+// element of leaf l (leaf-local index) at position v (row-major m x m)
+__device__ inline int64_t leaf_elem(const MxhDev& d, int64_t l, int v) {
+    const int n1 = d.nleaf1, m = d.m;
+    const int64_t f = l / ((int64_t)n1 * n1);
+    const int li = (int)((l / n1) % n1), lj = (int)(l % n1);
+    return (f * d.s.nel + li * m + v / m) * d.s.nel + lj * m + v % m;
+}
+
+// Chebyshev points of every cluster on the surface; one thread per (cluster, node)
+__global__ __launch_bounds__(256) void k_mxh_points(MxhDev d) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= d.ncl * d.q2) return;
+    const int64_t c = id / d.q2;
+    const int a = (int)(id % d.q2);
+    int lev, f, i, j;
+    cluster_of(d, c, lev, f, i, j);
+    const double w = 1.0 / (double)(1 << lev);
+    patch_point(d.s.geom, f, (i + d.cheb[a / d.q]) * w, (j + d.cheb[a % d.q]) * w, d.xc + 3 * id);
+}
+
+// kernel at the nodes of every ordered admissible pair, stored [pair][b][a]
+__global__ __launch_bounds__(256) void k_mxh_far(MxhDev d) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per = (int64_t)d.q2 * d.q2;
+    if (id >= d.nfar * per) return;
+    const int64_t pr = id / per;
+    const int rem = (int)(id % per), b = rem / d.q2, a = rem % d.q2;
+    const double* x = d.xc + ((int64_t)d.far_t[pr] * d.q2 + a) * 3;
+    const double* y = d.xc + ((int64_t)d.far_s[pr] * d.q2 + b) * 3;
+    const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+    ((cdbl*)d.K)[id] = kernel_val(d.s.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
+}
+
+// Channel moments of every element against its leaf's Lagrange polynomials:
+// Mt[e][k][c][a] = h^2 sum over the qg x qg Gauss points of w W_c,k L_a1 L_a2.
+// One 64-lane block per element, lane = Gauss point; the products are summed from LDS.
+template <int P>
+__global__ __launch_bounds__(64) void k_mxh_moments(MxhDev d) {
+    constexpr int NL = 2 * P * (P + 1), NC = 4 * NL;
+    __shared__ double W[64][NC];
+    __shared__ double L1[64][8], L2[64][8];
+    const int64_t e = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int n = d.s.nel, qg = d.s.qg, q = d.q, m = d.m;
+    const int i2 = (int)(e % n), i1 = (int)((e / n) % n), f = (int)(e / ((int64_t)n * n));
+    const int np = qg * qg;
+    if (lane < np) {
+        const int k1 = lane / qg, k2 = lane % qg;
+        double x[3], V[NL][3], D[NL];
+        mx_eval<P>(d.s, f, i1, i2, d.s.gx[k1], d.s.gx[k2], x, V, D);
+        const double w = d.s.gw[k1] * d.s.gw[k2] * d.s.h * d.s.h;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            W[lane][4 * k] = w * V[k][0];
+            W[lane][4 * k + 1] = w * V[k][1];
+            W[lane][4 * k + 2] = w * V[k][2];
+            W[lane][4 * k + 3] = w * D[k];
+        }
+        for (int a = 0; a < q; ++a) {
+            L1[lane][a] = d.Lg[((i1 % m) * qg + k1) * q + a];
+            L2[lane][a] = d.Lg[((i2 % m) * qg + k2) * q + a];
+        }
+    }
+    __syncthreads();
+    const int q2 = d.q2, nout = NC * q2;
+    double* out = d.Mt + e * (int64_t)nout;
+    for (int o = lane; o < nout; o += 64) {
+        const int kc = o / q2, a = o % q2, a1 = a / q, a2 = a % q;
+        double acc = 0.0;
+        for (int pt = 0; pt < np; ++pt) acc += W[pt][kc] * L1[pt][a1] * L2[pt][a2];
+        out[o] = acc;
+    }
+}
+
+// xl[e][k] = sign * x[global of (e, k)] (0 for dropped functions)
+__global__ __launch_bounds__(256) void k_mxh_gather_x(MxhDev d, const cdbl* __restrict__ x) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= d.s.nelem * d.s.nl) return;
+    const int g = d.s.eglob[id];
+    ((cdbl*)d.xl)[id] = g < 0 ? cdbl{0.0, 0.0} : x[g] * (double)d.s.esgn[id];
+}
+
+// Leaf moments (forward transform): mom[leaf][c][a] = sum over its elements and their
+// functions of Mt[e][k][c][a] xl[e][k]; one wave per leaf, lanes over (c, a).
+template <int NO>
+__global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
+    const int64_t l = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= d.nleaves) return;
+    const int nl = d.s.nl, nout = 4 * d.q2, m2 = d.m * d.m;
+    cdbl acc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
+    const cdbl* xl = (const cdbl*)d.xl;
+    for (int v = 0; v < m2; ++v) {
+        const int64_t e = leaf_elem(d, l, v);
+        for (int k = 0; k < nl; ++k) {
+            const cdbl xv = xl[e * nl + k];
+            const double* mt = d.Mt + (e * nl + k) * (int64_t)nout;
+#pragma unroll
+            for (int u = 0; u < NO; ++u) {
+                const int o = lane + 64 * u;
+                if (o < nout) acc[u] = acc[u] + xv * mt[o];
+            }
+        }
+    }
+    cdbl* mom = (cdbl*)d.mom + (d.lev_off[d.leaf] + l) * nout;
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int o = lane + 64 * u;
+        if (o < nout) mom[o] = acc[u];
+    }
+}
+
+// Upward transfer to level lev: m_P[c][a] = sum over the four children b and their nodes p
+// of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent.
+template <int NO>
+__global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
+    const int n = 1 << lev;
+    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
+    const int64_t loc = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (loc >= nc) return;
+    const int q = d.q, q2 = d.q2, nout = 4 * q2;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    const cdbl* mom = (const cdbl*)d.mom;
+    cdbl acc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
+    for (int b = 0; b < 4; ++b) {
+        const int b1 = b >> 1, b2 = b & 1;
+        const int64_t ch = d.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
+        const cdbl* mc = mom + ch * nout;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int o = lane + 64 * u;
+            if (o >= nout) continue;
+            const int c = o / q2, a = o % q2, a1 = a / q, a2 = a % q;
+            cdbl s = {0.0, 0.0};
+            for (int p1 = 0; p1 < q; ++p1) {
+                const double e1 = d.E[(b1 * q + p1) * q + a1];
+                for (int p2 = 0; p2 < q; ++p2) s = s + mc[c * q2 + p1 * q + p2] * (e1 * d.E[(b2 * q + p2) * q + a2]);
+            }
+            acc[u] = acc[u] + s;
+        }
+    }
+    cdbl* out = (cdbl*)d.mom + (d.lev_off[lev] + loc) * nout;
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int o = lane + 64 * u;
+        if (o < nout) out[o] = acc[u];
+    }
+}
+
+// Coupling: lv[t][c][a] = sum over the admissible sources s of t of
+// sum_b G(x_a^t, x_b^s) mom[s][c][b]; one wave per target, lanes over (c, a); the source's
+// moments are staged in the wave's LDS slice, the kernel block is read coalesced ([b][a]).
+template <int NO>
+__global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
+    __shared__ cdbl ms[4][4 * 64];
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t t = (int64_t)blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    const int q2 = d.q2, nout = 4 * q2;
+    cdbl acc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
+    const bool on = t < d.ncl;
+    const int64_t beg = on ? d.far_rowptr[t] : 0, end = on ? d.far_rowptr[t + 1] : 0;
+    const cdbl* mom = (const cdbl*)d.mom;
+    for (int64_t pr = beg; pr < end; ++pr) {
+        const cdbl* msrc = mom + (int64_t)d.far_s[pr] * nout;
+        for (int o = lane; o < nout; o += 64) ms[w][o] = msrc[o];
+        wave_sync();
+        const cdbl* K = (const cdbl*)d.K + pr * (int64_t)q2 * q2;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int o = lane + 64 * u;
+            if (o >= nout) continue;
+            const int c = o / q2, a = o % q2;
+            cdbl s = {0.0, 0.0};
+            for (int b = 0; b < q2; ++b) s = s + K[b * q2 + a] * ms[w][c * q2 + b];
+            acc[u] = acc[u] + s;
+        }
+        wave_sync();
+    }
+    if (!on) return;
+    cdbl* lv = (cdbl*)d.lv + t * nout;
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int o = lane + 64 * u;
+        if (o < nout) lv[o] = acc[u];
+    }
+}
+
+// Downward transfer to level lev: lv[child][c][p] += sum_a E_b1[p1][a1] E_b2[p2][a2]
+// lv[parent][c][a]; one wave per child.
+template <int NO>
+__global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
+    const int n = 1 << lev;
+    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
+    const int64_t loc = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (loc >= nc) return;
+    const int q = d.q, q2 = d.q2, nout = 4 * q2;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    const int b1 = i & 1, b2 = j & 1, h = n / 2;
+    const int64_t par = d.lev_off[lev - 1] + ((int64_t)f * h + i / 2) * h + j / 2;
+    const cdbl* lp = (const cdbl*)d.lv + par * nout;
+    cdbl* lc = (cdbl*)d.lv + (d.lev_off[lev] + loc) * nout;
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int o = lane + 64 * u;
+        if (o >= nout) continue;
+        const int c = o / q2, p = o % q2, p1 = p / q, p2 = p % q;
+        cdbl s = {0.0, 0.0};
+        for (int a1 = 0; a1 < q; ++a1) {
+            const double e1 = d.E[(b1 * q + p1) * q + a1];
+            for (int a2 = 0; a2 < q; ++a2) s = s + lp[c * q2 + a1 * q + a2] * (e1 * d.E[(b2 * q + p2) * q + a2]);
+        }
+        lc[o] = lc[o] + s;
+    }
+}
+
+// Backward transform and near field per element: yl[e][k] = sum_c w_c sum_a Mt[e][k][c][a]
+// lv[leaf][c][a] (w = 1, 1, 1, -kappa^-2) plus the near blocks of the element's row times
+// the coefficients of their trial elements.  One wave per element.
+template <int P, int NO>
+__global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
+    constexpr int NL = 2 * P * (P + 1), NE = (NL * NL + 63) / 64;
+    __shared__ cdbl red[4][NL * NL];
+    __shared__ cdbl yf[4][NL];
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t e = (int64_t)blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    if (e >= d.s.nelem) return;
+    const int n = d.s.nel, m = d.m, q2 = d.q2, nout = 4 * q2;
+    const int i2 = (int)(e % n), i1 = (int)((e / n) % n), f = (int)(e / ((int64_t)n * n));
+    const int64_t l = ((int64_t)f * d.nleaf1 + i1 / m) * d.nleaf1 + i2 / m;
+    const int u = (i1 % m) * m + i2 % m, m2 = m * m;
+    // far: the leaf's local expansion, weighted per channel
+    const KernelDesc& kd = d.s.ker;
+    const double k2r = kd.kre * kd.kre - kd.kim * kd.kim, k2i = 2.0 * kd.kre * kd.kim;
+    const double den = k2r * k2r + k2i * k2i;
+    const cdbl mik2 = {-k2r / den, k2i / den};
+    const cdbl* lv = (const cdbl*)d.lv + (d.lev_off[d.leaf] + l) * nout;
+    cdbl lw[NO];
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+        const int o = lane + 64 * s;
+        lw[s] = cdbl{0.0, 0.0};
+        if (o < nout) lw[s] = o / q2 == 3 ? cmul(mik2, lv[o]) : lv[o];
+    }
+    for (int k = 0; k < NL; ++k) {
+        const double* mt = d.Mt + (e * NL + k) * (int64_t)nout;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int s = 0; s < NO; ++s) {
+            const int o = lane + 64 * s;
+            if (o < nout) {
+                sr += mt[o] * lw[s].re;
+                si += mt[o] * lw[s].im;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            si += __shfl_xor(si, o, 64);
+        }
+        if (lane == 0) yf[w][k] = cdbl{sr, si};
+    }
+    // near: the element's blocks, lanes over block entries (k, j)
+    cdbl acc[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) acc[r] = cdbl{0.0, 0.0};
+    const cdbl* NB = (const cdbl*)d.s.B;
+    const cdbl* xl = (const cdbl*)d.xl;
+    for (int64_t lp = d.near_rowptr[l]; lp < d.near_rowptr[l + 1]; ++lp) {
+        const int64_t ls = d.near_s[lp];
+        for (int v = 0; v < m2; ++v) {
+            const int64_t e2 = leaf_elem(d, ls, v);
+            const cdbl* blk = NB + ((lp * m2 + u) * m2 + v) * (int64_t)(NL * NL);
+#pragma unroll
+            for (int r = 0; r < NE; ++r) {
+                const int idx = lane + 64 * r;
+                if (idx < NL * NL) acc[r] = acc[r] + cmul(blk[idx], xl[e2 * NL + idx % NL]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const int idx = lane + 64 * r;
+        if (idx < NL * NL) red[w][idx] = acc[r];
+    }
+    wave_sync();
+    if (lane < NL) {
+        cdbl s = yf[w][lane];
+        for (int j = 0; j < NL; ++j) s = s + red[w][lane * NL + j];
+        ((cdbl*)d.yl)[e * NL + lane] = s;
+    }
+}
+
+// y[g] = sum over the pieces of g of sign * yl[piece]
+__global__ __launch_bounds__(256) void k_mxh_scatter(MxhDev d, cdbl* __restrict__ y) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= d.s.nglob) return;
+    const cdbl* yl = (const cdbl*)d.yl;
+    cdbl s = {0.0, 0.0};
+    for (int64_t a = d.s.gptr[g]; a < d.s.gptr[g + 1]; ++a) s = s + yl[d.s.gpos[a]] * (double)d.s.gsgn[a];
+    y[g] = s;
+}
+
 inline unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <int P>
@@ -430,14 +755,14 @@ hipError_t mx_pairs_p(const MxDev& d, hipStream_t st) {
                                                  (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_mx_pairs<P>, dim3((unsigned)(d.nelem * d.nelem)), dim3(64), lds, st, d);
+    hipLaunchKernelGGL(k_mx_pairs<P>, dim3((unsigned)d.npairs), dim3(64), lds, st, d);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_mx_pairs(const MxDev& d, hipStream_t st) {
-    if (d.nelem == 0) return hipSuccess;
+    if (d.npairs == 0) return hipSuccess;
     if (d.p == 1) return mx_pairs_p<1>(d, st);
     if (d.p == 2) return mx_pairs_p<2>(d, st);
     return hipErrorInvalidValue;
@@ -477,6 +802,58 @@ hipError_t launch_mx_field(const MxDev& d, const Gauss8& g8, const double* pts, 
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st) {
+    if (d.ncl * d.q2 > 0) hipLaunchKernelGGL(k_mxh_points, dim3(nb(d.ncl * d.q2, 256)), dim3(256), 0, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nk = d.nfar * d.q2 * d.q2;
+    if (nk > 0) hipLaunchKernelGGL(k_mxh_far, dim3(nb(nk, 256)), dim3(256), 0, st, d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (d.s.nelem > 0) {
+        if (d.s.p == 1)
+            hipLaunchKernelGGL(k_mxh_moments<1>, dim3((unsigned)d.s.nelem), dim3(64), 0, st, d);
+        else if (d.s.p == 2)
+            hipLaunchKernelGGL(k_mxh_moments<2>, dim3((unsigned)d.s.nelem), dim3(64), 0, st, d);
+        else
+            return hipErrorInvalidValue;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return launch_mx_pairs(d.s, st);
+}
+
+template <int NO>
+static hipError_t mxh_apply_no(const MxhDev& d, const void* x, void* y, hipStream_t st) {
+    const int64_t nx = d.s.nelem * d.s.nl;
+    hipLaunchKernelGGL(k_mxh_gather_x, dim3(nb(nx, 256)), dim3(256), 0, st, d, (const cdbl*)x);
+    hipLaunchKernelGGL(k_mxh_forward<NO>, dim3(nb(d.nleaves, 4)), dim3(256), 0, st, d);
+    for (int lev = d.leaf - 1; lev >= 0; --lev) {
+        const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
+        hipLaunchKernelGGL(k_mxh_up<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+    }
+    hipLaunchKernelGGL(k_mxh_coupling<NO>, dim3(nb(d.ncl, 4)), dim3(256), 0, st, d);
+    for (int lev = 1; lev <= d.leaf; ++lev) {
+        const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
+        hipLaunchKernelGGL(k_mxh_down<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+    }
+    if (d.s.p == 1)
+        hipLaunchKernelGGL((k_mxh_back<1, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
+    else
+        hipLaunchKernelGGL((k_mxh_back<2, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_mxh_scatter, dim3(nb(d.s.nglob, 256)), dim3(256), 0, st, d, (cdbl*)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_mxh_apply(const MxhDev& d, const void* x, void* y, hipStream_t st) {
+    if (d.s.nglob == 0) return hipSuccess;
+    if (d.s.p != 1 && d.s.p != 2) return hipErrorInvalidValue;
+    const int nout = 4 * d.q2;
+    if (nout <= 64) return mxh_apply_no<1>(d, x, y, st);
+    if (nout <= 128) return mxh_apply_no<2>(d, x, y, st);
+    if (nout <= 192) return mxh_apply_no<3>(d, x, y, st);
+    if (nout <= 256) return mxh_apply_no<4>(d, x, y, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace bem

@@ -436,13 +436,16 @@ def test_s1_argument_validation(B, tmp_path):
             B.Space(g, B.BEM_MAXWELL_SINGLE, **args)
         assert e.value.code == code, kw
     s = B.Space(g, B.BEM_MAXWELL_SINGLE, 1.5, degree=1, level=1)
-    for kw, code in [(dict(eta=1.6), C.BEM_EUNSUPPORTED), (dict(far_low=1), C.BEM_EUNSUPPORTED),
+    for kw, code in [(dict(eta=-1.0), C.BEM_EINVAL), (dict(eta=1.6, q=9), C.BEM_EINVAL),
+                     (dict(eta=1.6, leaf_level=2), C.BEM_EINVAL), (dict(far_low=1), C.BEM_EUNSUPPORTED),
                      (dict(batch_rhs=8), C.BEM_EUNSUPPORTED), (dict(far_eval=True), C.BEM_EUNSUPPORTED),
                      (dict(qg=9), C.BEM_EINVAL), (dict(qs=0), C.BEM_EINVAL)]:
         with pytest.raises(C.BemError) as e:
             B.Operator(s, assemble=False, **kw)
         assert e.value.code == code, kw
     A = B.Operator(s, assemble=False)
+    Ah = B.Operator(s, eta=1.6, q=3, assemble=False)  # compressed: the same operations are unsupported
+    assert Ah.info.leaf_level == 0  # default leaf level L - 1
     n64, sz = ctypes.c_int64(), ctypes.c_size_t()
     for call in (lambda: C.check(C.lib.bem_export_near(A.h, None, None, None, None)),
                  lambda: C.check(C.lib.bem_export_far(A.h, None, None, None)),
@@ -457,3 +460,18 @@ def test_s1_argument_validation(B, tmp_path):
     # scalar spaces: all signs +1
     s2 = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=1, level=1, continuous=True)
     assert (s2.glue_sign() == 1).all() and s2.glue_sign().size == C.bem_space_glue(s2.h)[0]
+
+
+@pytest.mark.parametrize("geom,prm,p,L,q,leaf", [(0, (), 2, 2, 5, 2), (2, (1.0, 0.4), 1, 2, 4, 1), (3, (1.7,), 2, 3, 3, 2)])
+def test_s1_compressed_partition_equals_oracle(B, orc, geom, prm, p, L, q, leaf):
+    """The compressed S^1 operator plans on the block partition of the scalar operators of
+    the same surface: far and near counts equal the oracle's scalar partition."""
+    g = B.Geometry(geom, prm)
+    s = B.Space(g, B.BEM_MAXWELL_SINGLE, 1.5, degree=p, level=L)
+    A = B.Operator(s, q=q, eta=1.6, leaf_level=leaf, assemble=False)
+    Ho = orc.H2(orc.Space(geom, list(prm), orc.HELMHOLTZ, 1.5, degree=0, level=L), q=q, eta=1.6, leaf=leaf,
+                assemble_near=False)
+    nl = 2 * p * (p + 1)
+    m = 1 << (L - leaf)
+    assert (A.info.nfar, A.info.nnear, A.info.nclusters) == (Ho.nfar, Ho.nnear, Ho.nclusters)
+    assert A.info.near_nnz == Ho.nnear * m ** 4 * nl * nl and A.info.leaf_level == leaf

@@ -129,3 +129,48 @@ def test_solution_reproduces_the_dipole_field(B, orc):
     print(f"GMRES its {st[0][0]}, solution vs direct solve {ej:.2e}, field error vs the dipole {ef:.2e}")
     assert ej <= 1e-8
     assert ef <= relerr(So.potential(jo, pts), ex) * (1 + 1e-6) + 1e-12
+
+
+# ---- the compressed operator (far field by the interpolation of Sec. 2, four channels)
+
+H2_CASES = {
+    # id: (geometry maker, oracle geometry, kappa, p, L, q, leaf, qg, qs)
+    "sphere_L2_p1_q4_leaf1": (lambda B: B.Geometry(B.BEM_GEOM_SPHERE6), (0, []), 1.5, 1, 2, 4, 1, 6, 5),
+    "sphere_L2_p2_q5_leaf2": (lambda B: B.Geometry(B.BEM_GEOM_SPHERE6), (0, []), 1.5, 2, 2, 5, 2, 5, 4),
+    "sphere_L2_p1_q8_leaf1": (lambda B: B.Geometry(B.BEM_GEOM_SPHERE6), (0, []), 1.5, 1, 2, 8, 1, 8, 5),
+    "ellipsoid_L2_p1_cplx_q6_leaf1": (lambda B: B.Geometry(B.BEM_GEOM_ELLIPSOID6, (0.8, 1.1, 1.3)),
+                                      (1, [0.8, 1.1, 1.3]), 1.2 + 0.3j, 1, 2, 6, 1, 5, 4),
+    "torus_L2_p1_q4_leaf2": (lambda B: B.Geometry(B.BEM_GEOM_TORUS16, (1.0, 0.4)), (2, [1.0, 0.4]), 2.0, 1, 2, 4, 2,
+                             5, 4),
+    "flat_L3_p2_q3_leaf2_open": (lambda B: B.Geometry(B.BEM_GEOM_FLAT1, (1.7,)), (3, [1.7]), 1.5, 2, 3, 3, 2, 5, 4),
+    "nurbs_torus_L1_p1_q4_leaf1": (lambda B: B.Geometry.nurbs(W.nurbs_torus(1.0, 0.4)), (4, W.nurbs_torus(1.0, 0.4)),
+                                   1.5, 1, 1, 4, 1, 5, 4),
+}
+_h2cache = {}
+
+
+def h2case(B, orc, cid):
+    if cid not in _h2cache:
+        mk, (og, oprm), kappa, p, L, q, leaf, qg, qs = H2_CASES[cid]
+        print(f"[maxwell compressed case {cid}] assemble on GPU and in the oracle", flush=True)
+        s = B.Space(mk(B), B.BEM_MAXWELL_SINGLE, kappa, degree=p, level=L)
+        A = B.Operator(s, q=q, eta=1.6, leaf_level=leaf, qg=qg, qs=qs)
+        So = orc.MSpace(og, oprm, kappa, p=p, level=L)
+        _h2cache[cid] = (s, A, So, So.h2_dense(q=q, eta=1.6, leaf=leaf, qg=qg, qs=qs))
+    return _h2cache[cid]
+
+
+@pytest.mark.parametrize("cid", list(H2_CASES))
+def test_compressed_matrix_matches_oracle(B, orc, cid):
+    """Every column of the compressed operator (gather, leaf moments, upward, coupling,
+    downward, backward, near blocks, scatter) equals the oracle's compressed matrix, which
+    interpolates each admissible block directly on its clusters."""
+    s, A, So, Mh = h2case(B, orc, cid)
+    assert A.info.nfar > 0 and A.ndof == So.nglob
+    Mg = dense_gpu(A)
+    e = relerr(Mg, Mh)
+    print(f"{cid}: N = {A.ndof}, far pairs {A.info.nfar}, near leaf pairs {A.info.nnear}, matrix error {e:.2e}")
+    assert e <= TOL
+    # a second apply with another vector: no state kept between calls
+    x = torch.from_numpy(W.random_vector(W.rng(13, A.ndof), A.ndof, True)).cuda()
+    assert relerr(A.apply(x).cpu().numpy(), Mh @ x.cpu().numpy()) <= TOL
