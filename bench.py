@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--only-c2", action="store_true", help="many-RHS Helmholtz matvecs only (for profiling)")
     ap.add_argument("--cpu-rows", type=int, default=24, help="sampled rows for the oracle's near-field timing")
     ap.add_argument("--no-cpu-legs", action="store_true", help="skip the oracle's timings of the other workloads")
+    ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell single-layer workload")
+    ap.add_argument("--only-maxwell", action="store_true", help="Maxwell workload only")
+    ap.add_argument("--maxwell-matvec-only", action="store_true",
+                    help="Maxwell workload: assembly and matvec timings only (for profiling)")
     return ap.parse_args()
 
 
@@ -301,6 +305,157 @@ def bench_c2(B, W, torch, np, stream, args):
     return out
 
 
+def dipole_field(prm, kappa, pts, np):
+    """Field of the electric dipole (moment m at x0) at the points, closed form:
+    E = kappa^2 G m + g'(r) (m . R) R / r + g(r) m with G = exp(-i kappa r) / (4 pi r) and
+    g = G' / r (the curl curl of m G)."""
+    x0, m = np.asarray(prm[:3]), np.asarray(prm[3:])
+    R = pts - x0
+    r = np.linalg.norm(R, axis=1)[:, None]
+    ik = 1j * kappa
+    ex = np.exp(-ik * r) / (4 * np.pi)
+    G = ex / r
+    G1 = -ex * (1 + ik * r) / r ** 2
+    G2 = ex * (2 + 2 * ik * r + (ik * r) ** 2) / r ** 3
+    gg, gp = G1 / r, (G2 - G1 / r) / r
+    return kappa ** 2 * G * m + gp * (R @ m)[:, None] * R / r + gg * m
+
+
+def bench_maxwell(B, W, torch, np, stream, args):
+    """Maxwell single layer (EFIE) on the unit sphere, dipole data: compressed operator at
+    the workload level (plan, assembly, matvec by HIP events, GMRES to 1e-8, field error at
+    exterior points), the dense operator's matvec at a small level, the field error over the
+    levels at degrees 1 and 2 (the paper's Fig. 1 series), and the oracle's compressed
+    assembly timed on the host beside the GPU's at a small level."""
+    c = W.MAXWELL
+    prm, pts = W.maxwell_inputs()
+    g = B.Geometry(B.BEM_GEOM_SPHERE6)
+    exact = dipole_field(prm, c["kappa"], pts, np)
+    out = {"workload": c["name"], "kappa": c["kappa"], "q": c["q"], "eta": c["eta"]}
+
+    def field_err(s, x):
+        E = s.potential(pts, x).cpu().numpy()
+        return float(np.abs(E - exact).max() / np.abs(exact).max())
+
+    steps = max(5, min(args.steps // 4, 50))
+    for leaf_off in (1, 0):
+        s = B.Space(g, B.BEM_MAXWELL_SINGLE, c["kappa"], degree=c["degree"], level=c["level"])
+        leaf = c["level"] - leaf_off
+        t0 = time.perf_counter()
+        A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=leaf, qg=c["qg"], qs=c["qs"], assemble=False)
+        t_plan = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.assemble()
+        torch.cuda.synchronize()
+        t_asm = time.perf_counter() - t0
+        N, info = A.ndof, A.info
+        x = torch.from_numpy(W.random_vector(W.rng(14, N), N, True)).cuda()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            A.apply(x, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            A.apply(x, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        nl, q2 = 2 * c["degree"] * (c["degree"] + 1), c["q"] ** 2
+        nelem = 6 * 4 ** c["level"]
+        # bytes every apply must move: kernel blocks, near blocks, channel moments (read in the
+        # forward and the backward transform)
+        byts = info.far_bytes + info.near_bytes + 2.0 * nelem * nl * 4 * q2 * 8
+        ent = {"leaf_level": leaf, "ndof": N, "nfar": info.nfar, "near_leaf_pairs": info.nnear,
+               "near_block_entries": info.near_nnz, "far_bytes": info.far_bytes, "near_bytes": info.near_bytes,
+               "plan_s": t_plan, "assembly_s": t_asm, "matvec_ms": ms, "dof_per_s": N / (ms * 1e-3),
+               "matvec_gbs": byts / (ms * 1e-3) / 1e9}
+        print(f"bench maxwell: leaf {leaf} N={N} far={info.nfar} near={info.nnear} plan {t_plan:.2f}s assemble "
+              f"{t_asm:.3f}s matvec {ms:.3f} ms ({N/(ms*1e-3):.3e} DOF/s, {ent['matvec_gbs']:.0f} GB/s of "
+              f"{byts/1e9:.2f} GB)", file=sys.stderr, flush=True)
+        if leaf_off == 1 and not args.no_gmres:
+            b = s.rhs(B.BEM_DATA_DIPOLE, [prm])[0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol, st = A.solve(b, tol=c["tol"], restart=c["restart"], maxit=c["maxit"])
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            rr = float((b - A.apply(sol)).norm() / b.norm())
+            ent["gmres"] = {"time_to_tol_s": t, "iterations": st[0][0], "converged": bool(st[0][1]), "relres": rr,
+                            "field_rel_err": field_err(s, sol)}
+            print(f"bench maxwell: GMRES({c['restart']}) {st[0][0]} its {t:.3f}s relres {rr:.2e} field error "
+                  f"{ent['gmres']['field_rel_err']:.2e}", file=sys.stderr, flush=True)
+        out[f"leaf_L-{leaf_off}"] = ent
+        del A
+    if args.maxwell_matvec_only:
+        return out
+    # dense operator at a small level: the matvec reads N^2 complex entries
+    Ld = c["dense_level"]
+    s = B.Space(g, B.BEM_MAXWELL_SINGLE, c["kappa"], degree=c["degree"], level=Ld)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ad = B.Operator(s, eta=0.0, qg=c["qg"], qs=c["qs"])
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    N = Ad.ndof
+    x = torch.from_numpy(W.random_vector(W.rng(14, N), N, True)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        Ad.apply(x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        Ad.apply(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out["dense"] = {"level": Ld, "ndof": N, "assembly_s": t_asm, "matvec_ms": ms,
+                    "matvec_gbs": N * N * 16 / (ms * 1e-3) / 1e9}
+    print(f"bench maxwell: dense L{Ld} N={N} assemble {t_asm:.3f}s matvec {ms:.4f} ms "
+          f"({out['dense']['matvec_gbs']:.0f} GB/s of the matrix)", file=sys.stderr, flush=True)
+    del Ad
+    # field error over the levels (compressed operator, leaf L - 1), degrees 1 and 2
+    series = {}
+    for p in (1, 2):
+        errs = []
+        for L in c["levels"]:
+            s = B.Space(g, B.BEM_MAXWELL_SINGLE, c["kappa"], degree=p, level=L)
+            A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=max(L - 1, 0), qg=c["qg"], qs=c["qs"])
+            b = s.rhs(B.BEM_DATA_DIPOLE, [prm])[0]
+            sol, st = A.solve(b, tol=1e-10, restart=c["restart"], maxit=c["maxit"])
+            errs.append(field_err(s, sol))
+            del A
+        eoc = [float(np.log2(errs[k] / errs[k + 1])) for k in range(len(errs) - 1)]
+        series[f"p{p}"] = {"levels": list(c["levels"]), "field_rel_err": errs, "eoc": eoc}
+        print(f"bench maxwell: p = {p} field errors {['%.2e' % e for e in errs]} orders {['%.2f' % v for v in eoc]}",
+              file=sys.stderr, flush=True)
+    out["convergence"] = series
+    if not args.no_cpu_baseline:
+        # cpu-baseline leg: the oracle's compressed matrix (host, all cores) beside the GPU's
+        # assembly + N matvecs
+        import oracle
+
+        Lc = 2
+        So = oracle.MSpace(oracle.SPHERE, [], c["kappa"], p=c["degree"], level=Lc)
+        t0 = time.perf_counter()
+        So.h2_dense(q=c["q"], eta=c["eta"], leaf=Lc - 1, qg=c["qg"], qs=c["qs"])
+        t_orc = time.perf_counter() - t0
+        s = B.Space(g, B.BEM_MAXWELL_SINGLE, c["kappa"], degree=c["degree"], level=Lc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=Lc - 1, qg=c["qg"], qs=c["qs"])
+        A.apply(torch.eye(A.ndof, dtype=torch.complex128, device="cuda"))
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+        out["cpu_oracle"] = {"kind": "oracle", "sample": f"compressed matrix, sphere L{Lc} p{c['degree']}",
+                             "ndof": A.ndof, "oracle_s": t_orc, "gpu_assembly_and_columns_s": t_gpu}
+        print(f"bench maxwell: oracle compressed matrix L{Lc} {t_orc:.2f}s, GPU assembly + {A.ndof} columns "
+              f"{t_gpu:.3f}s", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_c3(B, W, torch, np, args):
     """Batched uneven instances, every instance and right-hand side in FP64: per-column
     applies, one grouped launch per stage over every instance and column, and the grouped
@@ -475,6 +630,9 @@ def main():
     if args.only_c2:
         args.no_gmres = True
         print(json.dumps({"many_rhs": bench_c2(B, W, torch, np, stream, args)}))
+        return
+    if args.only_maxwell:
+        print(json.dumps({"maxwell": bench_maxwell(B, W, torch, np, stream, args)}))
         return
     g = B.Geometry(B.BEM_GEOM_SPHERE6)
     s = B.Space(g, B.BEM_LAPLACE_SINGLE, 0.0, degree=cfg["degree"], level=cfg["level"])
@@ -732,6 +890,8 @@ def main():
         extra["batched_uneven"] = bench_c3(B, W, torch, np, args)
     if not args.no_c4:
         extra["learned_precond"] = bench_c4(B, W, torch, np, args)
+    if not args.no_maxwell:
+        extra["maxwell"] = bench_maxwell(B, W, torch, np, stream, args)
     if args.tune:
         import paper_1906_00785_amd.autotune as AT
 

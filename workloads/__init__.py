@@ -51,12 +51,33 @@ CONFIGS[4] = dict(
 # on the held-out instances: relative residuals 1e-6..7e-3 after 12,000 steps), so this
 # family solves with the longest restart the library takes and a step cap of 15,000.
 
+# Maxwell single layer (electric field integral equation) on the unit sphere with the field
+# of an electric dipole inside as data, the setting of the paper's example (Sec. 5, Fig. 1:
+# field error at exterior points against the level): degree 2 on level 5 for the timings,
+# levels 1..5 at degrees 1 and 2 for the convergence series; wavenumber below the first
+# interior resonance of the unit sphere (about 2.74).
+MAXWELL = dict(
+    name="maxwell_efie_sphere6_L5_p2_h2_q5_eta1.6",
+    level=5, degree=2, kappa=1.5, q=5, eta=1.6, qg=8, qs=8,
+    x0=(0.1, 0.2, -0.1), moment=(0.3, -0.5, 1.0), npts=20, r_range=(2.0, 4.0),
+    tol=1e-8, restart=64, maxit=5000, levels=(1, 2, 3, 4, 5), dense_level=3,
+)
+
 GEOM_KIND = {"sphere": 0, "ellipsoid": 1, "torus": 2, "flat": 3}
 PDE_KIND = {"laplace": 0, "helmholtz": 1}
 
 
 def rng(config_index: int, *extra: int) -> np.random.Generator:
     return np.random.default_rng([1906, config_index, *extra])
+
+
+def maxwell_inputs():
+    """(dipole parameters x0 + unit moment, exterior evaluation points) of the Maxwell workload."""
+    c = MAXWELL
+    mom = np.asarray(c["moment"], dtype=np.float64)
+    mom = mom / np.linalg.norm(mom)
+    pts = exterior_points(rng(9, 73), c["npts"], *c["r_range"])
+    return list(c["x0"]) + mom.tolist(), pts
 
 
 def ndof(npatch: int, level: int, degree: int, knot_rep: int = 1) -> int:
