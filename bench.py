@@ -419,18 +419,22 @@ def bench_maxwell(B, W, torch, np, stream, args):
     # field error over the levels (compressed operator, leaf L - 1), degrees 1 and 2
     series = {}
     for p in (1, 2):
-        errs = []
+        errs, its, res = [], [], []
         for L in c["levels"]:
             s = B.Space(g, B.BEM_MAXWELL_SINGLE, c["kappa"], degree=p, level=L)
-            A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=max(L - 1, 0), qg=c["qg"], qs=c["qs"])
+            A = B.Operator(s, q=c["series_q"], eta=c["eta"], leaf_level=max(L - 1, 0), qg=c["qg"], qs=c["qs"])
             b = s.rhs(B.BEM_DATA_DIPOLE, [prm])[0]
-            sol, st = A.solve(b, tol=1e-10, restart=c["restart"], maxit=c["maxit"])
+            sol, st = A.solve(b, tol=c["series_tol"], restart=c["restart"], maxit=c["series_maxit"])
             errs.append(field_err(s, sol))
+            its.append(st[0][0])
+            res.append(st[0][2])
             del A
         eoc = [float(np.log2(errs[k] / errs[k + 1])) for k in range(len(errs) - 1)]
-        series[f"p{p}"] = {"levels": list(c["levels"]), "field_rel_err": errs, "eoc": eoc}
-        print(f"bench maxwell: p = {p} field errors {['%.2e' % e for e in errs]} orders {['%.2f' % v for v in eoc]}",
-              file=sys.stderr, flush=True)
+        series[f"p{p}"] = {"levels": list(c["levels"]), "q": c["series_q"], "field_rel_err": errs, "eoc": eoc,
+                           "gmres_iterations": its, "gmres_relres": res}
+        print(f"bench maxwell: p = {p} (q = {c['series_q']}) field errors {['%.2e' % e for e in errs]} orders "
+              f"{['%.2f' % v for v in eoc]} GMRES its {its} relres {['%.1e' % v for v in res]}", file=sys.stderr,
+              flush=True)
     out["convergence"] = series
     if not args.no_cpu_baseline:
         # cpu-baseline leg: the oracle's compressed matrix (host, all cores) beside the GPU's

@@ -144,6 +144,9 @@ struct bem_operator_s {
     MxhDev mxhd{};
     std::vector<int64_t> mxh_plist;  // near element pairs (host copy, as the pair types)
     std::vector<double> mxh_lg;      // leaf Lagrange values at the Gauss points (same)
+    std::vector<int32_t> mxh_ch_p0, mxh_ch_p1;  // coupling work chunks (same)
+    std::vector<int64_t> mx_blist;              // pair blocks by kind: regular, then touching (same)
+    std::vector<int64_t> mxh_cl_chunk;
     std::vector<int32_t> mx_tinfo;  // host copies of the pair types and the Gauss rules (kept,
     std::vector<double> mx_rules;   // the uploads are asynchronous)
     size_t scal = 8;  // bytes per scalar
@@ -1518,10 +1521,12 @@ static size_t mx_layout(const bem_operator_s& A, char* ob, char* tb, MxDev* d) {
     };
     char* B = take((size_t)ne * ne * nl * nl * 16);
     char* ti = take((size_t)ne * ne * 4);
+    char* bl = take((size_t)ne * ne * 8);
     char* r = take(sizeof(double) * (2 * A.mxd.qg + 2 * A.mxd.qs));
     if (tb) {
         d->B = B;
         d->tinfo = (const int32_t*)ti;
+        d->blist = (const int64_t*)bl;
         d->gx = (const double*)r;
         d->gw = d->gx + A.mxd.qg;
         d->sx = d->gw + A.mxd.qg;
@@ -1533,6 +1538,18 @@ static size_t mx_layout(const bem_operator_s& A, char* ob, char* tb, MxDev* d) {
 // Plan of the dense Maxwell operator: every element pair, touching ones classified as for the
 // scalar near field (App. C: Duffy rules of the identical, edge and vertex cases).
 static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info);
+
+// pair blocks grouped by kind (the regular ones first, each group in block order)
+static int64_t mx_block_list(const std::vector<int32_t>& tinfo, std::vector<int64_t>& bl) {
+    bl.clear();
+    bl.reserve(tinfo.size());
+    for (size_t k = 0; k < tinfo.size(); ++k)
+        if (tinfo[k] == 0) bl.push_back((int64_t)k);
+    const int64_t nreg = (int64_t)bl.size();
+    for (size_t k = 0; k < tinfo.size(); ++k)
+        if (tinfo[k] != 0) bl.push_back((int64_t)k);
+    return nreg;
+}
 
 static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, bem_operator_info* info) {
     if (p->far_low != 0 || p->batch_rhs > 1 || p->far_eval != 0)
@@ -1555,6 +1572,7 @@ static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, be
         }
         A->mx_tinfo.assign((size_t)(S.nelem * S.nelem), 0);
         for (size_t k = 0; k < tinfo.size(); ++k) A->mx_tinfo[pairs[2 * k] * S.nelem + pairs[2 * k + 1]] = tinfo[k];
+        mx_block_list(A->mx_tinfo, A->mx_blist);
         gauss_legendre01(p->qg, A->plan.gx, A->plan.gw);
         gauss_legendre01(p->qs, A->plan.sx, A->plan.sw);
         A->mx_rules.clear();
@@ -1580,6 +1598,7 @@ static int mx_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, be
     d.qg = p->qg;
     d.qs = p->qs;
     d.npairs = S.nelem * S.nelem;
+    d.nreg = (int64_t)std::count(A->mx_tinfo.begin(), A->mx_tinfo.end(), 0);
     const int64_t N = S.nglob;
     bem_operator_info& I = A->info;
     I.ndof = N;
@@ -1607,14 +1626,17 @@ static int mx_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_t
     d.qg = A->mxd.qg;
     d.qs = A->mxd.qs;
     d.npairs = A->mxd.npairs;
+    d.nreg = A->mxd.nreg;
     mx_layout(*A, ob, tb, &d);
     HIP_CHECK(hipMemcpyAsync((void*)d.tinfo, A->mx_tinfo.data(), A->mx_tinfo.size() * 4, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync((void*)d.blist, A->mx_blist.data(), A->mx_blist.size() * 8, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync((void*)d.gx, A->mx_rules.data(), A->mx_rules.size() * 8, hipMemcpyHostToDevice, stream));
     HIP_CHECK(launch_mx_pairs(d, stream));
     HIP_CHECK(launch_mx_gather(d, stream));
     // the pair blocks, pair types and rules live in the temporary workspace
     d.B = nullptr;
     d.tinfo = nullptr;
+    d.blist = nullptr;
     d.gx = d.gw = d.sx = d.sw = nullptr;
     A->mxd = d;
     A->assembled = true;
@@ -1650,6 +1672,10 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     char* ns = take(pl.near_s.size() * 4);
     char* cheb = take(pl.cheb.size() * 8);
     char* E = take(pl.E.size() * 8);
+    char* chp0 = take(A.mxh_ch_p0.size() * 4);
+    char* chp1 = take(A.mxh_ch_p1.size() * 4);
+    char* clch = take(A.mxh_cl_chunk.size() * 8);
+    char* part = take(A.mxh_ch_p0.size() * 4 * q2 * 16);
     const size_t op_total = off + 256;
     size_t toff = 0;
     auto ttake = [&](size_t bytes) {
@@ -1659,6 +1685,7 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     };
     char* plist = ttake((size_t)npairs * 8);
     char* tinfo = ttake((size_t)npairs * 4);
+    char* blist = ttake((size_t)npairs * 8);
     char* xc = ttake((size_t)h.ncl * q2 * 3 * 8);
     char* rules = ttake(sizeof(double) * (2 * h.s.qg + 2 * h.s.qs));
     char* lg = ttake(A.mxh_lg.size() * 8);
@@ -1679,8 +1706,13 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         d->near_s = (const int32_t*)ns;
         d->cheb = (const double*)cheb;
         d->E = (const double*)E;
+        d->ch_p0 = (const int32_t*)chp0;
+        d->ch_p1 = (const int32_t*)chp1;
+        d->cl_chunk = (const int64_t*)clch;
+        d->partial = part;
         d->s.plist = (const int64_t*)plist;
         d->s.tinfo = (const int32_t*)tinfo;
+        d->s.blist = (const int64_t*)blist;
         d->xc = (double*)xc;
         d->s.gx = (const double*)rules;
         d->s.gw = d->s.gx + h.s.qg;
@@ -1746,6 +1778,20 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
         }
         A->mx_rules.clear();
         for (auto* v : {&pl.gx, &pl.gw, &pl.sx, &pl.sw}) A->mx_rules.insert(A->mx_rules.end(), v->begin(), v->end());
+        if (pl.far_t.size() > 0x7fffffff) {
+            delete A;
+            return fail(BEM_EUNSUPPORTED, "too many admissible pairs");
+        }
+        mx_block_list(A->mx_tinfo, A->mx_blist);
+        // coupling work chunks: up to kMxhChunk consecutive pairs of one target
+        A->mxh_cl_chunk.assign(pl.ncl + 1, 0);
+        for (int64_t c = 0; c < pl.ncl; ++c) {
+            for (int64_t q0 = pl.far_rowptr[c]; q0 < pl.far_rowptr[c + 1]; q0 += kMxhChunk) {
+                A->mxh_ch_p0.push_back((int32_t)q0);
+                A->mxh_ch_p1.push_back((int32_t)std::min<int64_t>(q0 + kMxhChunk, pl.far_rowptr[c + 1]));
+            }
+            A->mxh_cl_chunk[c + 1] = (int64_t)A->mxh_ch_p0.size();
+        }
         A->mxh_lg.assign((size_t)m * P.qg * P.q, 0.0);
         for (int i = 0; i < m; ++i)
             for (int k = 0; k < P.qg; ++k)
@@ -1772,6 +1818,7 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     d.s.qg = P.qg;
     d.s.qs = P.qs;
     d.s.npairs = (int64_t)A->mxh_plist.size();
+    d.s.nreg = (int64_t)std::count(A->mx_tinfo.begin(), A->mx_tinfo.end(), 0);
     d.q = P.q;
     d.q2 = P.q * P.q;
     d.leaf = pl.leaf;
@@ -1781,11 +1828,13 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     d.nleaves = pl.nleaves;
     d.nfar = (int64_t)pl.far_t.size();
     d.nnear = (int64_t)pl.near_t.size();
+    d.nchunks = (int64_t)A->mxh_ch_p0.size();
     const int64_t N = S.nglob;
     bem_operator_info& I = A->info;
     I.ndof = N;
     I.nlocal = S.ndof;
     I.nclusters = pl.ncl;
+    I.nchunks = d.nchunks;
     I.nfar = d.nfar;
     I.nnear = d.nnear;
     I.ntouch = (int64_t)(pl.touch.size() / 5);
@@ -1833,14 +1882,19 @@ static int mxh_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_
     HIP_CHECK(up(d.near_s, pl.near_s.data(), pl.near_s.size() * 4));
     HIP_CHECK(up(d.cheb, pl.cheb.data(), pl.cheb.size() * 8));
     HIP_CHECK(up(d.E, pl.E.data(), pl.E.size() * 8));
+    HIP_CHECK(up(d.ch_p0, A->mxh_ch_p0.data(), A->mxh_ch_p0.size() * 4));
+    HIP_CHECK(up(d.ch_p1, A->mxh_ch_p1.data(), A->mxh_ch_p1.size() * 4));
+    HIP_CHECK(up(d.cl_chunk, A->mxh_cl_chunk.data(), A->mxh_cl_chunk.size() * 8));
     HIP_CHECK(up(d.s.plist, A->mxh_plist.data(), A->mxh_plist.size() * 8));
     HIP_CHECK(up(d.s.tinfo, A->mx_tinfo.data(), A->mx_tinfo.size() * 4));
+    HIP_CHECK(up(d.s.blist, A->mx_blist.data(), A->mx_blist.size() * 8));
     HIP_CHECK(up(d.s.gx, A->mx_rules.data(), A->mx_rules.size() * 8));
     HIP_CHECK(up(d.Lg, A->mxh_lg.data(), A->mxh_lg.size() * 8));
     HIP_CHECK(launch_mxh_assemble(d, stream));
     // tables of the temporary workspace
     d.s.plist = nullptr;
     d.s.tinfo = nullptr;
+    d.s.blist = nullptr;
     d.s.gx = d.s.gw = d.s.sx = d.s.sw = nullptr;
     d.xc = nullptr;
     d.Lg = nullptr;

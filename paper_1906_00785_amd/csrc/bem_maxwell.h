@@ -12,7 +12,8 @@
 
 namespace bem {
 
-constexpr int kMxMaxP = 2;  // degrees p of the device kernels (register budget of the pair kernel)
+constexpr int kMxMaxP = 2;    // degrees p of the device kernels (register budget of the pair kernel)
+constexpr int kMxhChunk = 8;  // admissible pairs per coupling work chunk
 
 struct MxDev {
     GeomDesc geom;
@@ -37,6 +38,8 @@ struct MxDev {
     void* M;                 // [nglob][nglob] complex dense matrix, row-major (test x trial)
     const int64_t* plist;    // [npairs] e1 * nelem + e2 of each block (null: all pairs, in order)
     int64_t npairs;          // blocks to compute (nelem * nelem without a list)
+    const int64_t* blist;    // [npairs] the blocks by kind: the nreg regular ones, then the touching ones
+    int64_t nreg;
 };
 
 // The compressed operator (Sec. 2 interpolation on the scalar block partition, four
@@ -52,6 +55,12 @@ struct MxhDev {
     const int32_t* far_s;        // [nfar] source
     const int32_t* far_t;        // [nfar] target
     void* K;                     // [nfar][q2 (source b)][q2 (target a)] complex G(x_a^t, x_b^s)
+    // coupling work chunks: up to kMxhChunk consecutive pairs of one target each
+    int64_t nchunks;
+    const int32_t* ch_p0;        // [nchunks] first pair
+    const int32_t* ch_p1;        // [nchunks] end pair
+    const int64_t* cl_chunk;     // [ncl + 1] chunks of every cluster
+    void* partial;               // [nchunks][4][q2] complex partial local expansions
     const int32_t* near_rowptr;  // [nleaves + 1] near leaf pairs by target leaf
     const int32_t* near_s;       // [nnear] source leaf (leaf-local index)
     double* Mt;                  // [nelem][nl][4][q2] channel moments against the leaf's Lagrange polynomials

@@ -82,165 +82,83 @@ __device__ inline void mx_eval(const MxDev& d, int f, int i1, int i2, double u1,
         }
 }
 
-// Element-pair block B[i][j] = int_tau int_sigma G(x, y) [V_i(x) . V_j(y) - kappa^-2 D_i(x) D_j(y)]
-// over the parameter squares (times h^4).  One wave per pair.  Both parts are contractions
-// over point pairs of F[i][c] (complex, the kernel-weighted test side, channel c = field
-// component 0..2 or the divergence 3) with W[j][c] (real, the trial side): the lanes write
-// 64 points' F and W to LDS and each lane adds its entries of B.
-//   regular pairs: lane b is trial point b and sums F_b[i][c] = sum_a w_a G(x_a, y_b) Wx_a[i][c]
-//                  over the 64 test points (uniform, from LDS); one contraction.
-//   touching pairs: lane = one Duffy point (x, y) at a time, F = w G Wx(x), W = Wy(y); one
-//                  contraction per 64 points.
+// The local functions of element (f, i1, i2) at (u1, u2) in factored form: point x, the
+// tangents xs = d_s gamma and xt = d_t gamma, the scalar factors b[k] (the lifted field of
+// function k is xs b[k] for component 0, k < p (p + 1), and xt b[k] for component 1) and the
+// reference divergences dv[k]; the order of mx_eval.
 template <int P>
-__global__ __launch_bounds__(64) void k_mx_pairs(MxDev d) {
-    constexpr int NL = 2 * P * (P + 1), NC = 4 * NL, NE = (NL * NL + 63) / 64;
-    extern __shared__ double sm[];
-    double* Fr = sm;                 // [64][NC]
-    double* Fi = Fr + 64 * NC;       // [64][NC]
-    double* Wl = Fi + 64 * NC;       // [64][NC]
-    double* Xt = Wl + 64 * NC;       // [64][3] test points (regular pairs)
-    double* WX = Xt + 64 * 3;        // [64][NC] test-side values times weights (regular pairs)
-    const int64_t blk = blockIdx.x;
+__device__ inline void mx_eval_f(const MxDev& d, int f, int i1, int i2, double u1, double u2, double* x,
+                                 double* xs, double* xt, double* bv, double* dv) {
+    patch_jac(d.geom, f, (i1 + u1) * d.h, (i2 + u2) * d.h, x, xs, xt);
+    const double ih = 1.0 / d.h;
+    double bp1[P + 1], dp1[P + 1], bp2[P + 1], dp2[P + 1], bq1[P], bq2[P];
+    const double* c1 = d.polp + (int64_t)i1 * (P + 1) * (P + 1);
+    const double* c2 = d.polp + (int64_t)i2 * (P + 1) * (P + 1);
+#pragma unroll
+    for (int l = 0; l <= P; ++l) {
+        double v1 = c1[l * (P + 1) + P], v2 = c2[l * (P + 1) + P], w1 = 0.0, w2 = 0.0;
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) {
+            w1 = w1 * u1 + v1;
+            w2 = w2 * u2 + v2;
+            v1 = v1 * u1 + c1[l * (P + 1) + k];
+            v2 = v2 * u2 + c2[l * (P + 1) + k];
+        }
+        bp1[l] = v1;
+        bp2[l] = v2;
+        dp1[l] = w1 * ih;
+        dp2[l] = w2 * ih;
+    }
+    const double* q1 = d.polq + (int64_t)i1 * P * P;
+    const double* q2 = d.polq + (int64_t)i2 * P * P;
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+        double v1 = q1[l * P + P - 1], v2 = q2[l * P + P - 1];
+#pragma unroll
+        for (int k = P - 2; k >= 0; --k) {
+            v1 = v1 * u1 + q1[l * P + k];
+            v2 = v2 * u2 + q2[l * P + k];
+        }
+        bq1[l] = v1;
+        bq2[l] = v2;
+    }
+    int k = 0;
+#pragma unroll
+    for (int l1 = 0; l1 <= P; ++l1)
+#pragma unroll
+        for (int l2 = 0; l2 < P; ++l2, ++k) {
+            bv[k] = bp1[l1] * bq2[l2];
+            dv[k] = dp1[l1] * bq2[l2];
+        }
+#pragma unroll
+    for (int l1 = 0; l1 < P; ++l1)
+#pragma unroll
+        for (int l2 = 0; l2 <= P; ++l2, ++k) {
+            bv[k] = bq1[l1] * bp2[l2];
+            dv[k] = bq1[l1] * dp2[l2];
+        }
+}
+
+// Element-pair block B[i][j] = int_tau int_sigma G(x, y) [V_i(x) . V_j(y) - kappa^-2 D_i(x) D_j(y)]
+// over the parameter squares (times h^4), i test, j trial.  Block blk = blist[...] of the
+// launch; its element pair is plist[blk] (or blk itself without a list), its type tinfo[blk].
+__device__ inline void mx_pair_of(const MxDev& d, int64_t blk, int& tf, int& ti1, int& ti2, int& sf, int& si1,
+                                  int& si2) {
     const int64_t pr = d.plist ? d.plist[blk] : blk;
     const int64_t e1 = pr / d.nelem, e2 = pr % d.nelem;
-    const int lane = threadIdx.x;
     const int n = d.nel;
-    const int ti2 = (int)(e1 % n), ti1 = (int)((e1 / n) % n), tf = (int)(e1 / ((int64_t)n * n));
-    const int si2 = (int)(e2 % n), si1 = (int)((e2 / n) % n), sf = (int)(e2 / ((int64_t)n * n));
-    const int info = d.tinfo[blk];
-    double accr[NE][2], acci[NE][2];  // [entry][vector part, divergence part]
-#pragma unroll
-    for (int e = 0; e < NE; ++e) accr[e][0] = accr[e][1] = acci[e][0] = acci[e][1] = 0.0;
-    double x[3], V[NL][3], D[NL];
-    // adds the contraction of the 64 points now in LDS to this lane's entries
-    auto contract = [&]() {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            const int ent = lane + 64 * e;
-            if (ent >= NL * NL) continue;
-            const int i = ent / NL, j = ent % NL;
-            for (int b = 0; b < 64; ++b) {
-                const double* fr = Fr + b * NC + 4 * i;
-                const double* fi = Fi + b * NC + 4 * i;
-                const double* w = Wl + b * NC + 4 * j;
-                accr[e][0] += fr[0] * w[0] + fr[1] * w[1] + fr[2] * w[2];
-                acci[e][0] += fi[0] * w[0] + fi[1] * w[1] + fi[2] * w[2];
-                accr[e][1] += fr[3] * w[3];
-                acci[e][1] += fi[3] * w[3];
-            }
-        }
-    };
-    if (info == 0) {
-        const int qg = d.qg;  // qg * qg <= 64 (checked at planning)
-        const int np = qg * qg;
-        // test points and their weighted values
-        if (lane < np) {
-            const int a1 = lane / qg, a2 = lane % qg;
-            mx_eval<P>(d, tf, ti1, ti2, d.gx[a1], d.gx[a2], x, V, D);
-            const double w = d.gw[a1] * d.gw[a2];
-            Xt[3 * lane] = x[0];
-            Xt[3 * lane + 1] = x[1];
-            Xt[3 * lane + 2] = x[2];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) {
-                WX[lane * NC + 4 * k] = w * V[k][0];
-                WX[lane * NC + 4 * k + 1] = w * V[k][1];
-                WX[lane * NC + 4 * k + 2] = w * V[k][2];
-                WX[lane * NC + 4 * k + 3] = w * D[k];
-            }
-        }
-        __syncthreads();
-        // trial point of this lane
-        double Sr[NC], Si[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Sr[c] = Si[c] = 0.0;
-        double y[3] = {0.0, 0.0, 0.0}, wb = 0.0;
-        if (lane < np) {
-            const int b1 = lane / qg, b2 = lane % qg;
-            mx_eval<P>(d, sf, si1, si2, d.gx[b1], d.gx[b2], y, V, D);
-            wb = d.gw[b1] * d.gw[b2];
-        }
-        // the trial side goes to LDS first (its registers are free during the sums)
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            Wl[lane * NC + 4 * k] = lane < np ? wb * V[k][0] : 0.0;
-            Wl[lane * NC + 4 * k + 1] = lane < np ? wb * V[k][1] : 0.0;
-            Wl[lane * NC + 4 * k + 2] = lane < np ? wb * V[k][2] : 0.0;
-            Wl[lane * NC + 4 * k + 3] = lane < np ? wb * D[k] : 0.0;
-        }
-        if (lane < np) {
-            for (int a = 0; a < np; ++a) {
-                const double dx = Xt[3 * a] - y[0], dy = Xt[3 * a + 1] - y[1], dz = Xt[3 * a + 2] - y[2];
-                const cdbl G = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
-                const double* wx = WX + a * NC;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    Sr[c] += G.re * wx[c];
-                    Si[c] += G.im * wx[c];
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            Fr[lane * NC + c] = Sr[c];
-            Fi[lane * NC + c] = Si[c];
-        }
-        __syncthreads();
-        contract();
-    } else {
-        const int type = info & 15, k1 = (info >> 4) & 15, k2 = (info >> 8) & 15;
-        const int qs = d.qs, qs4 = qs * qs * qs * qs;
-        const int nreg = type == PT_IDENTICAL ? 8 : (type == PT_EDGE ? 6 : 4);
-        const int npts = nreg * qs4;
-        double Vy[NL][3], Dy[NL];
-        for (int p0 = 0; p0 < npts; p0 += 64) {
-            const int pt = p0 + lane;
-            double gr = 0.0, gi = 0.0;
-            if (pt < npts) {
-                const int reg = pt / qs4;
-                int rem = pt - reg * qs4;
-                const int i3 = rem % qs;
-                rem /= qs;
-                const int i2 = rem % qs;
-                rem /= qs;
-                const int i1 = rem % qs, i0 = rem / qs;
-                double xh1, xh2, yh1, yh2, jac;
-                duffy_point(type, reg, d.sx[i0], d.sx[i1], d.sx[i2], d.sx[i3], xh1, xh2, yh1, yh2, jac);
-                double u1, u2, w1, w2, y[3];
-                d4_apply(k1, xh1, xh2, u1, u2);
-                d4_apply(k2, yh1, yh2, w1, w2);
-                mx_eval<P>(d, tf, ti1, ti2, u1, u2, x, V, D);
-                mx_eval<P>(d, sf, si1, si2, w1, w2, y, Vy, Dy);
-                const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-                const cdbl G = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
-                const double w = d.sw[i0] * d.sw[i1] * d.sw[i2] * d.sw[i3] * jac;
-                gr = G.re * w;
-                gi = G.im * w;
-            } else {
-#pragma unroll
-                for (int k = 0; k < NL; ++k) {
-                    V[k][0] = V[k][1] = V[k][2] = D[k] = 0.0;
-                    Vy[k][0] = Vy[k][1] = Vy[k][2] = Dy[k] = 0.0;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < NL; ++k) {
-                const double vx[4] = {V[k][0], V[k][1], V[k][2], D[k]};
-                const double vy[4] = {Vy[k][0], Vy[k][1], Vy[k][2], Dy[k]};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    Fr[lane * NC + 4 * k + c] = gr * vx[c];
-                    Fi[lane * NC + 4 * k + c] = gi * vx[c];
-                    Wl[lane * NC + 4 * k + c] = vy[c];
-                }
-            }
-            __syncthreads();
-            contract();
-        }
-    }
-    // B = (vector part - kappa^-2 divergence part) h^4
+    ti2 = (int)(e1 % n);
+    ti1 = (int)((e1 / n) % n);
+    tf = (int)(e1 / ((int64_t)n * n));
+    si2 = (int)(e2 % n);
+    si1 = (int)((e2 / n) % n);
+    sf = (int)(e2 / ((int64_t)n * n));
+}
+
+// B = (vector part - kappa^-2 divergence part) h^4 for this lane's entries
+template <int NL, int NE>
+__device__ inline void mx_store_block(const MxDev& d, int64_t blk, int lane, const double (*accr)[2],
+                                      const double (*acci)[2]) {
     const double h2 = d.h * d.h, h4 = h2 * h2;
     const cdbl k2 = cmul(cdbl{d.ker.kre, d.ker.kim}, cdbl{d.ker.kre, d.ker.kim});
     const double den = k2.re * k2.re + k2.im * k2.im;
@@ -253,6 +171,210 @@ __global__ __launch_bounds__(64) void k_mx_pairs(MxDev d) {
         const cdbl dv = cmul(mik2, cdbl{accr[e][1], acci[e][1]});
         B[ent] = cdbl{(accr[e][0] + dv.re) * h4, (acci[e][0] + dv.im) * h4};
     }
+}
+
+// Regular pairs, one wave each: lane b is trial point b and sums F_b[i][c] =
+// sum_a w_a G(x_a, y_b) Wx_a[i][c] over the qg^2 test points (uniform, from LDS), channel c =
+// field component 0..2 or the divergence 3; then B[i][j] += sum_b F_b[i][c] w_b Wy_b[j][c]
+// from LDS.  The test-side tables and the contraction operands share the LDS.
+template <int P>
+__global__ __launch_bounds__(64) void k_mx_regular(MxDev d) {
+    constexpr int NL = 2 * P * (P + 1), NC = 4 * NL, NE = (NL * NL + 63) / 64;
+    extern __shared__ double sm[];
+    double* WX = sm;               // [64][NC] test-side values times weights (phase 1)
+    double* Xt = sm + 64 * NC;     // [64][3] test points (phase 1)
+    double* Fr = sm;               // [64][NC] (phase 2)
+    double* Fi = sm + 64 * NC;     // [64][NC]
+    double* Wl = sm + 128 * NC;    // [64][NC]
+    const int64_t blk = d.blist[blockIdx.x];
+    int tf, ti1, ti2, sf, si1, si2;
+    mx_pair_of(d, blk, tf, ti1, ti2, sf, si1, si2);
+    const int lane = threadIdx.x;
+    const int qg = d.qg, np = qg * qg;  // qg * qg <= 64 (checked at planning)
+    double x[3], V[NL][3], D[NL];
+    if (lane < np) {
+        const int a1 = lane / qg, a2 = lane % qg;
+        mx_eval<P>(d, tf, ti1, ti2, d.gx[a1], d.gx[a2], x, V, D);
+        const double w = d.gw[a1] * d.gw[a2];
+        Xt[3 * lane] = x[0];
+        Xt[3 * lane + 1] = x[1];
+        Xt[3 * lane + 2] = x[2];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            WX[lane * NC + 4 * k] = w * V[k][0];
+            WX[lane * NC + 4 * k + 1] = w * V[k][1];
+            WX[lane * NC + 4 * k + 2] = w * V[k][2];
+            WX[lane * NC + 4 * k + 3] = w * D[k];
+        }
+    }
+    __syncthreads();
+    double Sr[NC], Si[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Sr[c] = Si[c] = 0.0;
+    const int b1 = lane / qg, b2 = lane % qg;
+    if (lane < np) {
+        double y[3], ys[3], yt[3];
+        patch_jac(d.geom, sf, (si1 + d.gx[b1]) * d.h, (si2 + d.gx[b2]) * d.h, y, ys, yt);
+        for (int a = 0; a < np; ++a) {
+            const double dx = Xt[3 * a] - y[0], dy = Xt[3 * a + 1] - y[1], dz = Xt[3 * a + 2] - y[2];
+            const cdbl G = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
+            const double* wx = WX + a * NC;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Sr[c] += G.re * wx[c];
+                Si[c] += G.im * wx[c];
+            }
+        }
+    }
+    __syncthreads();  // phase 1 tables dead
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        Fr[lane * NC + c] = Sr[c];
+        Fi[lane * NC + c] = Si[c];
+    }
+    double wb = 0.0;
+    if (lane < np) {
+        mx_eval<P>(d, sf, si1, si2, d.gx[b1], d.gx[b2], x, V, D);
+        wb = d.gw[b1] * d.gw[b2];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        Wl[lane * NC + 4 * k] = lane < np ? wb * V[k][0] : 0.0;
+        Wl[lane * NC + 4 * k + 1] = lane < np ? wb * V[k][1] : 0.0;
+        Wl[lane * NC + 4 * k + 2] = lane < np ? wb * V[k][2] : 0.0;
+        Wl[lane * NC + 4 * k + 3] = lane < np ? wb * D[k] : 0.0;
+    }
+    __syncthreads();
+    double accr[NE][2], acci[NE][2];  // [entry][vector part, divergence part]
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        accr[e][0] = accr[e][1] = acci[e][0] = acci[e][1] = 0.0;
+        const int ent = lane + 64 * e;
+        if (ent >= NL * NL) continue;
+        const int i = ent / NL, j = ent % NL;
+        for (int b = 0; b < 64; ++b) {
+            const double* fr = Fr + b * NC + 4 * i;
+            const double* fi = Fi + b * NC + 4 * i;
+            const double* w = Wl + b * NC + 4 * j;
+            accr[e][0] += fr[0] * w[0] + fr[1] * w[1] + fr[2] * w[2];
+            acci[e][0] += fi[0] * w[0] + fi[1] * w[1] + fi[2] * w[2];
+            accr[e][1] += fr[3] * w[3];
+            acci[e][1] += fi[3] * w[3];
+        }
+    }
+    mx_store_block<NL, NE>(d, blk, lane, accr, acci);
+}
+
+// Touching pairs (identical, common edge, common vertex), one wave each, over the Duffy
+// points of the scalar operators in batches of 32: the lower half-wave evaluates the test
+// side of point p, the upper half the trial side of the same point, and the lower half
+// takes the trial geometry from its partner lane.  Per point the lower lane stores the five
+// kernel weights w G (t_a(x) . t_b(y)) (a, b = s, t: the tangents of the two components) and
+// w G, and both halves their factors b and divergences; each lane then adds its block
+// entries over the batch: B_vec[i][j] += w G (t_(c i)(x) . t_(c j)(y)) b_i(x) b_j(y),
+// B_div[i][j] += w G dv_i(x) dv_j(y).
+template <int P>
+__global__ __launch_bounds__(64) void k_mx_touch(MxDev d) {
+    constexpr int NL = 2 * P * (P + 1), NE = (NL * NL + 63) / 64, NC0 = (P + 1) * P;
+    constexpr int ST = 10 + 4 * NL;  // per point: 5 complex weights, bx, dx, by, dy
+    __shared__ double T[32][ST];
+    const int64_t blk = d.blist[d.nreg + blockIdx.x];
+    int tf, ti1, ti2, sf, si1, si2;
+    mx_pair_of(d, blk, tf, ti1, ti2, sf, si1, si2);
+    const int info = d.tinfo[blk];
+    const int type = info & 15, k1 = (info >> 4) & 15, k2 = (info >> 8) & 15;
+    const int lane = threadIdx.x, half = lane >> 5, pl = lane & 31;
+    const int qs = d.qs, qs4 = qs * qs * qs * qs;
+    const int nreg = type == PT_IDENTICAL ? 8 : (type == PT_EDGE ? 6 : 4);
+    const int npts = nreg * qs4;
+    double accr[NE][2], acci[NE][2];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) accr[e][0] = accr[e][1] = acci[e][0] = acci[e][1] = 0.0;
+    for (int p0 = 0; p0 < npts; p0 += 32) {
+        const int pt = p0 + pl;
+        double X[3] = {0.0, 0.0, 0.0}, Xs[3] = {0.0, 0.0, 0.0}, Xt[3] = {0.0, 0.0, 0.0}, bv[NL], dv[NL], w = 0.0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) bv[k] = dv[k] = 0.0;
+        if (pt < npts) {
+            const int reg = pt / qs4;
+            int rem = pt - reg * qs4;
+            const int i3 = rem % qs;
+            rem /= qs;
+            const int i2 = rem % qs;
+            rem /= qs;
+            const int i1 = rem % qs, i0 = rem / qs;
+            double xh1, xh2, yh1, yh2, jac, u1, u2;
+            duffy_point(type, reg, d.sx[i0], d.sx[i1], d.sx[i2], d.sx[i3], xh1, xh2, yh1, yh2, jac);
+            if (half == 0) {
+                d4_apply(k1, xh1, xh2, u1, u2);
+                mx_eval_f<P>(d, tf, ti1, ti2, u1, u2, X, Xs, Xt, bv, dv);
+            } else {
+                d4_apply(k2, yh1, yh2, u1, u2);
+                mx_eval_f<P>(d, sf, si1, si2, u1, u2, X, Xs, Xt, bv, dv);
+            }
+            w = d.sw[i0] * d.sw[i1] * d.sw[i2] * d.sw[i3] * jac;
+        }
+        double Y[3], Ys[3], Yt[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Y[c] = __shfl_xor(X[c], 32, 64);
+            Ys[c] = __shfl_xor(Xs[c], 32, 64);
+            Yt[c] = __shfl_xor(Xt[c], 32, 64);
+        }
+        __syncthreads();  // the previous batch has been read
+        double* t = T[pl];
+        if (half == 0) {
+            cdbl g = {0.0, 0.0};
+            if (pt < npts) {
+                const double dx = X[0] - Y[0], dy = X[1] - Y[1], dz = X[2] - Y[2];
+                g = kernel_val(d.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0}) * w;
+            }
+            const double ss = Xs[0] * Ys[0] + Xs[1] * Ys[1] + Xs[2] * Ys[2];
+            const double st = Xs[0] * Yt[0] + Xs[1] * Yt[1] + Xs[2] * Yt[2];
+            const double ts = Xt[0] * Ys[0] + Xt[1] * Ys[1] + Xt[2] * Ys[2];
+            const double tt = Xt[0] * Yt[0] + Xt[1] * Yt[1] + Xt[2] * Yt[2];
+            t[0] = g.re * ss;
+            t[1] = g.im * ss;
+            t[2] = g.re * st;
+            t[3] = g.im * st;
+            t[4] = g.re * ts;
+            t[5] = g.im * ts;
+            t[6] = g.re * tt;
+            t[7] = g.im * tt;
+            t[8] = g.re;
+            t[9] = g.im;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                t[10 + k] = bv[k];
+                t[10 + NL + k] = dv[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                t[10 + 2 * NL + k] = bv[k];
+                t[10 + 3 * NL + k] = dv[k];
+            }
+        }
+        __syncthreads();
+        for (int p = 0; p < 32; ++p) {
+            const double* u = T[p];
+            const double gdr = u[8], gdi = u[9];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ent = lane + 64 * e;
+                if (ent >= NL * NL) continue;
+                const int i = ent / NL, j = ent % NL;
+                const int gi = 2 * (2 * (i >= NC0) + (j >= NC0));
+                const double bb = u[10 + i] * u[10 + 2 * NL + j];
+                const double dd = u[10 + NL + i] * u[10 + 3 * NL + j];
+                accr[e][0] += u[gi] * bb;
+                acci[e][0] += u[gi + 1] * bb;
+                accr[e][1] += gdr * dd;
+                acci[e][1] += gdi * dd;
+            }
+        }
+    }
+    mx_store_block<NL, NE>(d, blk, lane, accr, acci);
 }
 
 // M[g][h]: one thread per entry, the pieces of g (outer) and h (inner) in table order
@@ -541,89 +663,117 @@ __global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
     }
 }
 
+typedef const __attribute__((address_space(4))) double* mx_cdptr;
+typedef const __attribute__((address_space(4))) int32_t* mx_ciptr;
+
 // Upward transfer to level lev: m_P[c][a] = sum over the four children b and their nodes p
-// of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent.
+// of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent.  The children's moments
+// are staged in the wave's LDS slice (coalesced), the transfer matrices come through the
+// scalar cache, and the transfer is applied one direction at a time.
 template <int NO>
 __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
+    __shared__ cdbl mc[4][4 * 64 * NO];  // [wave][child][c][p]
     const int n = 1 << lev;
     const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
-    const int64_t loc = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
     const int lane = threadIdx.x & 63;
     if (loc >= nc) return;
     const int q = d.q, q2 = d.q2, nout = 4 * q2;
     const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
     const cdbl* mom = (const cdbl*)d.mom;
-    cdbl acc[NO];
+    cdbl* sm = mc[w];
+    // the four children are consecutive in pairs along j: (2i + b1, 2j), (2i + b1, 2j + 1)
+    for (int b1 = 0; b1 < 2; ++b1) {
+        const int64_t ch = d.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j;
+        const cdbl* src = mom + ch * nout;
+        for (int o = lane; o < 2 * nout; o += 64) sm[b1 * 2 * nout + o] = src[o];
+    }
+    wave_sync();
+    const mx_cdptr E = (mx_cdptr)d.E;
 #pragma unroll
-    for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
-    for (int b = 0; b < 4; ++b) {
-        const int b1 = b >> 1, b2 = b & 1;
-        const int64_t ch = d.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
-        const cdbl* mc = mom + ch * nout;
-#pragma unroll
-        for (int u = 0; u < NO; ++u) {
-            const int o = lane + 64 * u;
-            if (o >= nout) continue;
-            const int c = o / q2, a = o % q2, a1 = a / q, a2 = a % q;
-            cdbl s = {0.0, 0.0};
+    for (int u = 0; u < NO; ++u) {
+        const int o = lane + 64 * u;
+        if (o >= nout) continue;
+        const int c = o / q2, a = o % q2, a1 = a / q, a2 = a % q;
+        cdbl acc = {0.0, 0.0};
+        for (int b = 0; b < 4; ++b) {
+            const int b1 = b >> 1, b2 = b & 1;
+            const cdbl* m = sm + b * nout + c * q2;
             for (int p1 = 0; p1 < q; ++p1) {
-                const double e1 = d.E[(b1 * q + p1) * q + a1];
-                for (int p2 = 0; p2 < q; ++p2) s = s + mc[c * q2 + p1 * q + p2] * (e1 * d.E[(b2 * q + p2) * q + a2]);
+                cdbl t = {0.0, 0.0};
+                for (int p2 = 0; p2 < q; ++p2) t = t + m[p1 * q + p2] * E[(b2 * q + p2) * q + a2];
+                acc = acc + t * E[(b1 * q + p1) * q + a1];
             }
-            acc[u] = acc[u] + s;
         }
-    }
-    cdbl* out = (cdbl*)d.mom + (d.lev_off[lev] + loc) * nout;
-#pragma unroll
-    for (int u = 0; u < NO; ++u) {
-        const int o = lane + 64 * u;
-        if (o < nout) out[o] = acc[u];
+        ((cdbl*)d.mom)[(d.lev_off[lev] + loc) * nout + o] = acc;
     }
 }
 
-// Coupling: lv[t][c][a] = sum over the admissible sources s of t of
-// sum_b G(x_a^t, x_b^s) mom[s][c][b]; one wave per target, lanes over (c, a); the source's
-// moments are staged in the wave's LDS slice, the kernel block is read coalesced ([b][a]).
-template <int NO>
+// Coupling, one wave per work chunk (consecutive admissible pairs of one target t):
+// partial[chunk][c][a] = sum over its pairs (t, s) of sum_b G(x_a^t, x_b^s) mom[s][c][b].
+// Lane a holds the four channels of node a; with q^2 <= 32 the two half-waves take
+// alternate pairs.  The kernel block is read coalesced ([b][a]); the sources' moments are
+// uniform per half-wave and come through the scalar cache.
+template <int Q>
 __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
-    __shared__ cdbl ms[4][4 * 64];
-    const int w = uniform_int(threadIdx.x >> 6);
-    const int64_t t = (int64_t)blockIdx.x * 4 + w;
-    const int lane = threadIdx.x & 63;
-    const int q2 = d.q2, nout = 4 * q2;
-    cdbl acc[NO];
+    constexpr int Q2 = Q * Q, PPW = Q2 <= 32 ? 2 : 1, HW = 64 / PPW;
+    const int64_t k = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (k >= d.nchunks) return;
+    const int lane = threadIdx.x & 63, h = lane / HW, a = lane % HW;
+    const mx_ciptr cp0 = (mx_ciptr)d.ch_p0, cp1 = (mx_ciptr)d.ch_p1, cfs = (mx_ciptr)d.far_s;
+    const mx_cdptr mom = (mx_cdptr)d.mom;
+    const int p0 = cp0[k], p1 = cp1[k];
+    const cdbl* __restrict__ Kb = (const cdbl*)d.K;
+    cdbl acc[4];
 #pragma unroll
-    for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
-    const bool on = t < d.ncl;
-    const int64_t beg = on ? d.far_rowptr[t] : 0, end = on ? d.far_rowptr[t + 1] : 0;
-    const cdbl* mom = (const cdbl*)d.mom;
-    for (int64_t pr = beg; pr < end; ++pr) {
-        const cdbl* msrc = mom + (int64_t)d.far_s[pr] * nout;
-        for (int o = lane; o < nout; o += 64) ms[w][o] = msrc[o];
-        wave_sync();
-        const cdbl* K = (const cdbl*)d.K + pr * (int64_t)q2 * q2;
+    for (int c = 0; c < 4; ++c) acc[c] = cdbl{0.0, 0.0};
+    for (int pp = p0; pp < p1; pp += PPW) {
+        const int s0 = cfs[pp];
+        const int s1 = (PPW == 2 && pp + 1 < p1) ? cfs[pp + 1] : s0;
+        const bool on = a < Q2 && pp + h < p1;
+        const cdbl* __restrict__ K = Kb + (int64_t)(pp + h) * Q2 * Q2;
+        const mx_cdptr m0 = mom + (int64_t)s0 * 8 * Q2, m1 = mom + (int64_t)s1 * 8 * Q2;
+        // the lane's column of the block, all loads in flight before the products
+        constexpr int KB = Q2 <= 32 ? Q2 : 16;
+#pragma unroll 1
+        for (int b0 = 0; b0 < Q2; b0 += KB) {
+            cdbl kcol[KB];
 #pragma unroll
-        for (int u = 0; u < NO; ++u) {
-            const int o = lane + 64 * u;
-            if (o >= nout) continue;
-            const int c = o / q2, a = o % q2;
-            cdbl s = {0.0, 0.0};
-            for (int b = 0; b < q2; ++b) s = s + K[b * q2 + a] * ms[w][c * q2 + b];
-            acc[u] = acc[u] + s;
+            for (int bb = 0; bb < KB; ++bb)
+                kcol[bb] = (on && b0 + bb < Q2) ? K[(b0 + bb) * Q2 + a] : cdbl{0.0, 0.0};
+#pragma unroll
+            for (int bb = 0; bb < KB; ++bb) {
+                const int b = b0 + bb;
+                if (b >= Q2) break;
+                const cdbl kv = kcol[bb];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int o = 2 * (c * Q2 + b);
+                    const double mr = h ? m1[o] : m0[o], mi = h ? m1[o + 1] : m0[o + 1];
+                    acc[c].re += kv.re * mr - kv.im * mi;
+                    acc[c].im += kv.re * mi + kv.im * mr;
+                }
+            }
         }
-        wave_sync();
     }
-    if (!on) return;
-    cdbl* lv = (cdbl*)d.lv + t * nout;
+    if (PPW == 2) {
 #pragma unroll
-    for (int u = 0; u < NO; ++u) {
-        const int o = lane + 64 * u;
-        if (o < nout) lv[o] = acc[u];
+        for (int c = 0; c < 4; ++c) {
+            acc[c].re += __shfl_xor(acc[c].re, 32, 64);
+            acc[c].im += __shfl_xor(acc[c].im, 32, 64);
+        }
+    }
+    if (h == 0 && a < Q2) {
+        cdbl* out = (cdbl*)d.partial + k * 4 * Q2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c * Q2 + a] = acc[c];
     }
 }
 
-// Downward transfer to level lev: lv[child][c][p] += sum_a E_b1[p1][a1] E_b2[p2][a2]
-// lv[parent][c][a]; one wave per child.
+// Local expansions at level lev, top down: lv[c] = the sum of the cluster's chunk partials
+// (in chunk order) plus, below the roots, the parent's expansion transferred:
+// sum_a E_b1[p1][a1] E_b2[p2][a2] lv[parent][c][a].  One wave per cluster.
 template <int NO>
 __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
     const int n = 1 << lev;
@@ -633,21 +783,40 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
     if (loc >= nc) return;
     const int q = d.q, q2 = d.q2, nout = 4 * q2;
     const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const int b1 = i & 1, b2 = j & 1, h = n / 2;
-    const int64_t par = d.lev_off[lev - 1] + ((int64_t)f * h + i / 2) * h + j / 2;
-    const cdbl* lp = (const cdbl*)d.lv + par * nout;
-    cdbl* lc = (cdbl*)d.lv + (d.lev_off[lev] + loc) * nout;
+    const int64_t cl = d.lev_off[lev] + loc;
+    const cdbl* part = (const cdbl*)d.partial;
+    const int64_t k0 = d.cl_chunk[cl], k1 = d.cl_chunk[cl + 1];
+    const mx_cdptr E = (mx_cdptr)d.E;
+    __shared__ cdbl ps[4][4 * 64];  // [wave][c][a]: the parent's expansion
+    const int w = threadIdx.x >> 6;
+    const cdbl* lp = nullptr;
+    int b1 = 0, b2 = 0;
+    if (lev > 0) {
+        const int hh = n / 2;
+        b1 = i & 1;
+        b2 = j & 1;
+        const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + ((int64_t)f * hh + i / 2) * hh + j / 2) * nout;
+        for (int o = lane; o < nout; o += 64) ps[w][o] = src[o];
+        wave_sync();
+        lp = ps[w];
+    }
+    cdbl* lc = (cdbl*)d.lv + cl * nout;
 #pragma unroll
     for (int u = 0; u < NO; ++u) {
         const int o = lane + 64 * u;
         if (o >= nout) continue;
-        const int c = o / q2, p = o % q2, p1 = p / q, p2 = p % q;
         cdbl s = {0.0, 0.0};
-        for (int a1 = 0; a1 < q; ++a1) {
-            const double e1 = d.E[(b1 * q + p1) * q + a1];
-            for (int a2 = 0; a2 < q; ++a2) s = s + lp[c * q2 + a1 * q + a2] * (e1 * d.E[(b2 * q + p2) * q + a2]);
+        for (int64_t k = k0; k < k1; ++k) s = s + part[k * nout + o];
+        if (lp) {
+            const int c = o / q2, p = o % q2, p1 = p / q, p2 = p % q;
+            for (int a1 = 0; a1 < q; ++a1) {
+                const double e1 = E[(b1 * q + p1) * q + a1];
+                cdbl t = {0.0, 0.0};
+                for (int a2 = 0; a2 < q; ++a2) t = t + lp[c * q2 + a1 * q + a2] * E[(b2 * q + p2) * q + a2];
+                s = s + t * e1;
+            }
         }
-        lc[o] = lc[o] + s;
+        lc[o] = s;
     }
 }
 
@@ -742,20 +911,24 @@ __global__ __launch_bounds__(256) void k_mxh_scatter(MxhDev d, cdbl* __restrict_
 inline unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <int P>
-constexpr size_t mx_pairs_lds() {
+constexpr size_t mx_regular_lds() {
     constexpr int NC = 4 * 2 * P * (P + 1);
-    return sizeof(double) * (size_t)(64 * NC * 4 + 64 * 3);
+    return sizeof(double) * (size_t)(64 * NC * 3);
 }
 
 template <int P>
 hipError_t mx_pairs_p(const MxDev& d, hipStream_t st) {
-    constexpr size_t lds = mx_pairs_lds<P>();
+    constexpr size_t lds = mx_regular_lds<P>();
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_mx_pairs<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)lds);
+        const hipError_t e = hipFuncSetAttribute((const void*)k_mx_regular<P>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_mx_pairs<P>, dim3((unsigned)d.npairs), dim3(64), lds, st, d);
+    if (d.nreg > 0) hipLaunchKernelGGL(k_mx_regular<P>, dim3((unsigned)d.nreg), dim3(64), lds, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = d.npairs - d.nreg;
+    if (nt > 0) hipLaunchKernelGGL(k_mx_touch<P>, dim3((unsigned)nt), dim3(64), 0, st, d);
     return hipGetLastError();
 }
 
@@ -832,8 +1005,20 @@ static hipError_t mxh_apply_no(const MxhDev& d, const void* x, void* y, hipStrea
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
         hipLaunchKernelGGL(k_mxh_up<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
-    hipLaunchKernelGGL(k_mxh_coupling<NO>, dim3(nb(d.ncl, 4)), dim3(256), 0, st, d);
-    for (int lev = 1; lev <= d.leaf; ++lev) {
+    if (d.nchunks > 0) {
+        const dim3 g(nb(d.nchunks, 4)), blk(256);
+        switch (d.q) {
+            case 1: hipLaunchKernelGGL(k_mxh_coupling<1>, g, blk, 0, st, d); break;
+            case 2: hipLaunchKernelGGL(k_mxh_coupling<2>, g, blk, 0, st, d); break;
+            case 3: hipLaunchKernelGGL(k_mxh_coupling<3>, g, blk, 0, st, d); break;
+            case 4: hipLaunchKernelGGL(k_mxh_coupling<4>, g, blk, 0, st, d); break;
+            case 5: hipLaunchKernelGGL(k_mxh_coupling<5>, g, blk, 0, st, d); break;
+            case 6: hipLaunchKernelGGL(k_mxh_coupling<6>, g, blk, 0, st, d); break;
+            case 7: hipLaunchKernelGGL(k_mxh_coupling<7>, g, blk, 0, st, d); break;
+            default: hipLaunchKernelGGL(k_mxh_coupling<8>, g, blk, 0, st, d); break;
+        }
+    }
+    for (int lev = 0; lev <= d.leaf; ++lev) {
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
         hipLaunchKernelGGL(k_mxh_down<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
