@@ -180,11 +180,15 @@ __host__ __device__ inline void patch_point(const GeomDesc& g, int f, double s, 
         x[1] = rr * su;
         x[2] = g.b * sv;
     } else if (g.kind == GEOM_NURBS) {
+        double px[3];  // own array for the out-of-line evaluation (see patch_jac)
 #if defined(__HIP_DEVICE_COMPILE__)
-        nurbs_point(g.tab_dev, f, s, t, x);
+        nurbs_point(g.tab_dev, f, s, t, px);
 #else
-        nurbs_point(g.tab_host, f, s, t, x);
+        nurbs_point(g.tab_host, f, s, t, px);
 #endif
+        x[0] = px[0];
+        x[1] = px[1];
+        x[2] = px[2];
     } else {
         x[0] = g.a * s;
         x[1] = g.a * t;
@@ -329,11 +333,19 @@ __host__ __device__ inline void patch_jac(const GeomDesc& g, int f, double s, do
         xt[1] = -g.b * sv * su * du;
         xt[2] = g.b * cvv * du;
     } else if (g.kind == GEOM_NURBS) {
+        // the out-of-line evaluation writes through pointers: it gets arrays of its own, so
+        // that the caller's x, xs, xt can stay in registers on the other branches
+        double px[3], ps[3], pt[3];
 #if defined(__HIP_DEVICE_COMPILE__)
-        nurbs_jac(g.tab_dev, f, s, t, x, xs, xt);
+        nurbs_jac(g.tab_dev, f, s, t, px, ps, pt);
 #else
-        nurbs_jac(g.tab_host, f, s, t, x, xs, xt);
+        nurbs_jac(g.tab_host, f, s, t, px, ps, pt);
 #endif
+        for (int d = 0; d < 3; ++d) {
+            x[d] = px[d];
+            xs[d] = ps[d];
+            xt[d] = pt[d];
+        }
     } else {
         x[0] = g.a * s;
         x[1] = g.a * t;

@@ -174,3 +174,43 @@ def test_compressed_matrix_matches_oracle(B, orc, cid):
     # a second apply with another vector: no state kept between calls
     x = torch.from_numpy(W.random_vector(W.rng(13, A.ndof), A.ndof, True)).cuda()
     assert relerr(A.apply(x).cpu().numpy(), Mh @ x.cpu().numpy()) <= TOL
+
+
+# ---- full size: properties (the oracle's dense forms are out of reach at these levels)
+
+def test_compressed_product_approaches_the_dense_one_at_level_4(B):
+    """Sphere, degree 2, level 4 (N = 3468): the compressed product differs from the dense
+    Galerkin product by the interpolation error only, which drops by more than an order of
+    magnitude from q = 5 to q = 7."""
+    s = B.Space(B.Geometry(B.BEM_GEOM_SPHERE6), B.BEM_MAXWELL_SINGLE, 1.5, degree=2, level=4)
+    print("[maxwell full size] dense level 4 (tmp workspace 5.4 GB)", flush=True)
+    Ad = B.Operator(s, eta=0.0)
+    x = torch.from_numpy(W.random_vector(W.rng(15, s.ndof), s.ndof, True)).cuda()
+    yd = Ad.apply(x).cpu().numpy()
+    del Ad
+    errs = []
+    for q in (5, 7):
+        A = B.Operator(s, q=q, eta=1.6, leaf_level=3)
+        errs.append(relerr(A.apply(x).cpu().numpy(), yd))
+        del A
+    print(f"level 4: compressed vs dense product, q = 5: {errs[0]:.2e}, q = 7: {errs[1]:.2e}")
+    assert errs[0] <= 1e-4 and errs[1] <= errs[0] / 10
+
+
+def test_workload_solution_reproduces_the_dipole_field(B):
+    """The benchmark's Maxwell workload (sphere, degree 2, level 5, q = 5, leaf level 4): the
+    GMRES solution's field at exterior points matches the dipole's within the compression
+    and discretisation error (the field error of the q = 7 series at this level is 2e-8)."""
+    c = W.MAXWELL
+    prm, pts = W.maxwell_inputs()
+    s = B.Space(B.Geometry(B.BEM_GEOM_SPHERE6), B.BEM_MAXWELL_SINGLE, c["kappa"], degree=c["degree"],
+                level=c["level"])
+    A = B.Operator(s, q=c["q"], eta=c["eta"], leaf_level=c["level"] - 1)
+    b = s.rhs(B.BEM_DATA_DIPOLE, [prm])[0]
+    x, st = A.solve(b, tol=1e-8, restart=c["restart"], maxit=3000)
+    import oracle
+
+    ex = oracle.m_field(oracle.DIPOLE, prm, c["kappa"], pts)
+    e = relerr(s.potential(pts, x).cpu().numpy(), ex)
+    print(f"level 5 workload: GMRES {st[0][0]} its relres {st[0][2]:.1e}, field error {e:.2e}")
+    assert st[0][2] <= 1e-6 and e <= 5e-6
