@@ -812,7 +812,7 @@ def main():
         extra["copy_calibration_bytes"] = src.numel() * 8
         del src, dst
     if args.only_main:
-        args.no_gmres = args.no_c2 = args.no_c3 = args.no_c4 = True
+        args.no_gmres = args.no_c2 = args.no_c3 = args.no_c4 = args.no_maxwell = True
         args.no_cpu_baseline = True
     # mixed precision: FP32 and BF16 copies of the coupling blocks (FP32 accumulation)
     A16 = None if args.only_main else B.Operator(s, q=cfg["q"], eta=cfg["eta"], leaf_level=cfg["leaf"], qg=cfg["qg"],
