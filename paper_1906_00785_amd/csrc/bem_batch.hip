@@ -79,103 +79,6 @@ __global__ __launch_bounds__(256) void kb_from_slab(int64_t N, int R, const T* _
         if (r0 + i < R && g < N) y[g + (int64_t)(r0 + i) * ldy] = tile[i][tx];
 }
 
-// ------------------------------------------------------------------ forward + upward
-// Leaf moments m_tau[a] = sum_g V_tau[a, g] x_g, with the 1-D moment tables of both
-// directions applied one after the other; one wave per (leaf, 64 right-hand sides).
-template <class T, int Q>
-__global__ __launch_bounds__(256) void kb_leaf_moments(OpDev op, BatchDev bd) {
-    constexpr int Q2 = Q * Q;
-    const int nch = nchunks(bd.R);
-    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
-    if (item >= op.nleaves * nch) return;
-    const int l = (int)(item / nch), ch = (int)(item % nch);
-    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
-    const bool on = r < R;
-    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r;
-    const int j = l % n1, i = (l / n1) % n1, f = l / (n1 * n1);
-    const T* __restrict__ xs = (const T*)bd.xs;
-    const double* __restrict__ Vi = op.V1 + (int64_t)i * Q * nloc;
-    const double* __restrict__ Vj = op.V1 + (int64_t)j * Q * nloc;
-    T acc[Q2];
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) acc[a] = zero<T>();
-    for (int m1 = 0; m1 < nloc; ++m1) {
-        const int64_t g0 = dof_id(op.S, f, i * stride + m1, j * stride);
-        T t[Q];
-#pragma unroll
-        for (int a2 = 0; a2 < Q; ++a2) t[a2] = zero<T>();
-        for (int m2 = 0; m2 < nloc; ++m2) {
-            const T xv = on ? xs[(g0 + m2) * R + r] : zero<T>();
-#pragma unroll
-            for (int a2 = 0; a2 < Q; ++a2) t[a2] += Vj[a2 * nloc + m2] * xv;
-        }
-#pragma unroll
-        for (int a1 = 0; a1 < Q; ++a1) {
-            const double w = Vi[a1 * nloc + m1];
-#pragma unroll
-            for (int a2 = 0; a2 < Q; ++a2) acc[a1 * Q + a2] += w * t[a2];
-        }
-    }
-    if (!on) return;
-    T* mom = (T*)bd.mom + (op.lev_off[op.leaf] + l) * (int64_t)Q2 * R + r;
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) mom[(int64_t)a * R] = acc[a];
-}
-
-// Moments at level lev from the four children at lev + 1 (upward transfer):
-// m_P[a] = sum_children sum_p E_b1[p1][a1] E_b2[p2][a2] m_c[p].
-template <class T, int Q>
-__global__ __launch_bounds__(256) void kb_upward(OpDev op, BatchDev bd, int lev) {
-    constexpr int Q2 = Q * Q;
-    const int nch = nchunks(bd.R);
-    const int n = 1 << lev;
-    const int64_t nl = (int64_t)op.S.geom.npatch * n * n;
-    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
-    if (item >= nl * nch) return;
-    const int64_t loc = item / nch;
-    const int ch = (int)(item % nch);
-    const int R = bd.R, r = ch * kBatchChunk + (threadIdx.x & 63);
-    const bool on = r < R;
-    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const double* __restrict__ E = op.E;
-    const T* __restrict__ mom = (const T*)bd.mom;
-    T acc[Q2];
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) acc[a] = zero<T>();
-#pragma unroll 1
-    for (int c4 = 0; c4 < 4; ++c4) {
-        const int b1 = c4 >> 1, b2 = c4 & 1;
-        const int64_t c = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j + b2;
-        const T* mc = mom + c * Q2 * R + r;
-        // all of the child's moments first (independent loads), then the transfer
-        T mall[Q2];
-#pragma unroll
-        for (int p = 0; p < Q2; ++p) mall[p] = on ? mc[(int64_t)p * R] : zero<T>();
-#pragma unroll
-        for (int p1 = 0; p1 < Q; ++p1) {
-            T in[Q];
-#pragma unroll
-            for (int a2 = 0; a2 < Q; ++a2) in[a2] = zero<T>();
-#pragma unroll
-            for (int p2 = 0; p2 < Q; ++p2) {
-                const T mv = mall[p1 * Q + p2];
-#pragma unroll
-                for (int a2 = 0; a2 < Q; ++a2) in[a2] += E[(b2 * Q + p2) * Q + a2] * mv;
-            }
-#pragma unroll
-            for (int a1 = 0; a1 < Q; ++a1) {
-                const double w = E[(b1 * Q + p1) * Q + a1];
-#pragma unroll
-                for (int a2 = 0; a2 < Q; ++a2) acc[a1 * Q + a2] += w * in[a2];
-            }
-        }
-    }
-    if (!on) return;
-    T* out = (T*)bd.mom + (op.lev_off[lev] + loc) * Q2 * R + r;
-#pragma unroll
-    for (int a = 0; a < Q2; ++a) out[(int64_t)a * R] = acc[a];
-}
-
 // ------------------------------------------------------------------ coupling (vector units)
 // Local expansion of target cluster t for 64 right-hand sides: l_t = sum over its
 // admissible sources s of K_ts m_s, in the arithmetic type F (FP64, or FP32 from the FP32
@@ -622,6 +525,162 @@ struct Mfma16<float> {
     __device__ static int row(int kq, int e) { return 4 * kq + e; }
 };
 
+// ------------------------------------------------------------------ forward + upward (matrix cores)
+// Leaf moments m_tau[a][r] = sum over the nloc^2 B-splines g meeting the leaf of
+// V_tau[a][g] x[g][r], V_tau[(a1, a2)][(m1, m2)] = V1_i[a1][m1] V1_j[a2][m2] (the 1-D moment
+// tables of the two directions), as FP64 matrix-core steps: A = V_tau (rows a in tiles of
+// 16, columns g in steps of 4), B = the slab rows of the leaf's B-splines for 16 right-hand
+// sides per tile; a complex slab takes one real step per part.  One wave per leaf and
+// 16 NTW right-hand sides.
+template <class T, int Q, int NTW>
+__global__ __launch_bounds__(256) void kb_leaf_moments(OpDev op, BatchDev bd) {
+    constexpr int Q2 = Q * Q, RT = (Q2 + 15) / 16;
+    constexpr bool CP = sizeof(T) == 16;
+    const int R = bd.R, CW = 16 * NTW, ng = (R + CW - 1) / CW;
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    if (item >= op.nleaves * ng) return;
+    const int l = (int)(item / ng), grp = (int)(item % ng);
+    const int lane = threadIdx.x & 63, kq = lane >> 4, rl = lane & 15;
+    const int n1 = op.nleaf1, nloc = op.nloc, stride = op.m * op.S.r, nl2 = nloc * nloc;
+    const int j = l % n1, i = (l / n1) % n1, f = l / (n1 * n1);
+    const double* __restrict__ Vi = op.V1 + (int64_t)i * Q * nloc;
+    const double* __restrict__ Vj = op.V1 + (int64_t)j * Q * nloc;
+    const T* __restrict__ xs = (const T*)bd.xs;
+    int rr[NTW];
+    bool on[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        rr[t] = grp * CW + 16 * t + rl;
+        on[t] = rr[t] < R;
+    }
+    f64x4 ar[RT][NTW], ai[RT][NTW];
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) ar[u][t] = ai[u][t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int b0 = 0; b0 < nl2; b0 += 4) {
+        const int b = b0 + kq;
+        const bool bon = b < nl2;
+        const int m1 = bon ? b / nloc : 0, m2 = bon ? b % nloc : 0;
+        const int64_t g = dof_id(op.S, f, i * stride + m1, j * stride + m2);
+        T xv[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) xv[t] = (bon && on[t]) ? xs[g * R + rr[t]] : zero<T>();
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            const int a = 16 * u + rl;
+            const double av = (bon && a < Q2) ? Vi[(a / Q) * nloc + m1] * Vj[(a % Q) * nloc + m2] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                if constexpr (CP) {
+                    ar[u][t] = mfma64(av, part_re(xv[t]), ar[u][t]);
+                    ai[u][t] = mfma64(av, part_im(xv[t]), ai[u][t]);
+                } else {
+                    ar[u][t] = mfma64(av, *(const double*)&xv[t], ar[u][t]);
+                }
+            }
+        }
+    }
+    T* mom = (T*)bd.mom + (op.lev_off[op.leaf] + l) * (int64_t)Q2 * R;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (!on[t]) continue;
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = 16 * u + kq + 4 * e;
+                if (a >= Q2) continue;
+                if constexpr (CP)
+                    ((cdbl*)mom)[(int64_t)a * R + rr[t]] = cdbl{ar[u][t][e], ai[u][t][e]};
+                else
+                    ((double*)mom)[(int64_t)a * R + rr[t]] = ar[u][t][e];
+            }
+    }
+}
+
+// Moments at level lev from the four children at lev + 1 (upward transfer):
+// m_P[a][r] = sum over the children b and their nodes p of E_b1[p1][a1] E_b2[p2][a2]
+// m_child[p][r], as FP64 matrix-core steps with A[(a1, a2)][(b, p)] formed from the two
+// 1-D transfers and B the children's slab rows.  One wave per parent and 16 NTW
+// right-hand sides.
+template <class T, int Q, int NTW>
+__global__ __launch_bounds__(256) void kb_upward(OpDev op, BatchDev bd, int lev) {
+    constexpr int Q2 = Q * Q, RT = (Q2 + 15) / 16, KS = (4 * Q2 + 3) / 4;
+    constexpr bool CP = sizeof(T) == 16;
+    const int R = bd.R, CW = 16 * NTW, ng = (R + CW - 1) / CW;
+    const int n = 1 << lev;
+    const int64_t nl = (int64_t)op.S.geom.npatch * n * n;
+    const int64_t item = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int64_t loc = item / ng;
+    const int grp = (int)(item % ng);
+    const int lane = threadIdx.x & 63, kq = lane >> 4, rl = lane & 15;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    __shared__ double Es[2 * Q * Q];
+    for (int idx = threadIdx.x; idx < 2 * Q * Q; idx += blockDim.x) Es[idx] = op.E[idx];
+    __syncthreads();
+    if (item >= nl * ng) return;
+    const T* __restrict__ mom = (const T*)bd.mom;
+    int rr[NTW];
+    bool on[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        rr[t] = grp * CW + 16 * t + rl;
+        on[t] = rr[t] < R;
+    }
+    // all of the lane's slab values first (independent loads in flight), then the steps
+    T mv[KS][NTW];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int kk = 4 * k + kq;  // (child, node) = (kk / Q2, kk % Q2)
+        const int b = kk / Q2, p = kk % Q2;
+        const int64_t ch = op.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + (b >> 1)) * 2 * n + 2 * j + (b & 1);
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) mv[k][t] = on[t] ? mom[(ch * Q2 + p) * R + rr[t]] : zero<T>();
+    }
+    f64x4 ar[RT][NTW], ai[RT][NTW];
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) ar[u][t] = ai[u][t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int kk = 4 * k + kq;
+        const int b = kk / Q2, p = kk % Q2, b1 = b >> 1, b2 = b & 1;
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            const int a = 16 * u + rl;
+            const double av =
+                a < Q2 ? Es[(b1 * Q + p / Q) * Q + a / Q] * Es[(b2 * Q + p % Q) * Q + a % Q] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                if constexpr (CP) {
+                    ar[u][t] = mfma64(av, part_re(mv[k][t]), ar[u][t]);
+                    ai[u][t] = mfma64(av, part_im(mv[k][t]), ai[u][t]);
+                } else {
+                    ar[u][t] = mfma64(av, *(const double*)&mv[k][t], ar[u][t]);
+                }
+            }
+        }
+    }
+    T* out = (T*)bd.mom + (op.lev_off[lev] + loc) * (int64_t)Q2 * R;
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (!on[t]) continue;
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = 16 * u + kq + 4 * e;
+                if (a >= Q2) continue;
+                if constexpr (CP)
+                    ((cdbl*)out)[(int64_t)a * R + rr[t]] = cdbl{ar[u][t][e], ai[u][t][e]};
+                else
+                    ((double*)out)[(int64_t)a * R + rr[t]] = ar[u][t][e];
+            }
+    }
+}
+
 // l_t = sum_s K_ts m_s on the matrix cores for 64 NTW right-hand sides, in FP64 (F = T,
 // the stored blocks) or FP32 (F = float / cflt, the FP32 copy; moments rounded to FP32,
 // FP32 accumulation).  The block walks the sources of t in order; every source's block
@@ -764,10 +823,12 @@ hipError_t stage_tq(const OpDev& op, const BatchDev& bd, int stage, const void* 
         if (x)
             hipLaunchKernelGGL(kb_to_slab<T>, dim3(nblk(N, 64), nblk(R, 32)), dim3(256), 0, st, N, R, (const T*)x, ldx,
                                (T*)bd.xs);
-        hipLaunchKernelGGL((kb_leaf_moments<T, Q>), dim3(nblk(op.nleaves * nch, 4)), dim3(256), 0, st, op, bd);
+        constexpr int NTW = 2;  // 32 right-hand sides per wave
+        const int ng = (R + 16 * NTW - 1) / (16 * NTW);
+        hipLaunchKernelGGL((kb_leaf_moments<T, Q, NTW>), dim3(nblk(op.nleaves * ng, 4)), dim3(256), 0, st, op, bd);
         for (int lev = op.leaf - 1; lev >= 0; --lev) {
             const int64_t nl = (int64_t)op.S.geom.npatch << (2 * lev);
-            hipLaunchKernelGGL((kb_upward<T, Q>), dim3(nblk(nl * nch, 4)), dim3(256), 0, st, op, bd, lev);
+            hipLaunchKernelGGL((kb_upward<T, Q, NTW>), dim3(nblk(nl * ng, 4)), dim3(256), 0, st, op, bd, lev);
         }
         if (prec == 2) hipLaunchKernelGGL((kb_bf_moments<T, Q>), dim3(nblk(op.ncl * nch, 4)), dim3(256), 0, st, op, bd);
         if (prec == 1 && bd.mlow) {

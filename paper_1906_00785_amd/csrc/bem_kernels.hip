@@ -941,6 +941,69 @@ __device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cd
     }
 }
 
+// One pass of the on-the-fly coupling over NS * 64 columns from kb (see coupling_otf_body).
+template <class T, int Q, int NS>
+__device__ inline void otf_pass(const OpDev& op, int kb, int k1, int kend, int lane, int w,
+                                const int32_t* __restrict__ src, double o0, double o1, double o2,
+                                const double4 (*opt)[Q * Q], const T (*omo)[Q * Q], T (*racc)[Q * Q],
+                                T* __restrict__ P, const KernelDesc& kd) {
+    constexpr int Q2 = Q * Q;
+    constexpr int G = Q < 5 ? Q : 5;
+    const T* __restrict__ mom = (const T*)op.mom;
+    const double* __restrict__ xc = op.xc;
+    double y0[NS], y1[NS], y2[NS], yy[NS];
+    T ms[NS], p[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int k = kb + u * kWave + lane;
+        p[u] = zero<T>();
+        if (k < kend) {
+            const int sl = k / Q2, b = k - sl * Q2;
+            const int64_t g = (int64_t)src[sl] * Q2 + b;
+            y0[u] = xc[3 * g] - o0;
+            y1[u] = xc[3 * g + 1] - o1;
+            y2[u] = xc[3 * g + 2] - o2;
+            ms[u] = mom[g];
+        } else {
+            y0[u] = y1[u] = y2[u] = 64.0;
+            ms[u] = zero<T>();
+        }
+        yy[u] = y0[u] * y0[u] + y1[u] * y1[u] + y2[u] * y2[u];
+    }
+#pragma unroll 1
+    for (int a0 = 0; a0 < Q2; a0 += G) {
+        T sa[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            sa[g] = zero<T>();
+            const int a = a0 + g;
+            if (Q2 % G != 0 && a >= Q2) continue;
+            const double4 pa = opt[w][a];
+            const T ma = omo[w][a];
+            double r2[NS];
+            T kv[NS];
+#pragma unroll
+            for (int u = 0; u < NS; ++u)
+                r2[u] = __builtin_fma(pa.x, y0[u], __builtin_fma(pa.y, y1[u], __builtin_fma(pa.z, y2[u], pa.w + yy[u])));
+            kernel_unscaled<NS>(kd, r2, kv);
+#pragma unroll
+            for (int u = 0; u < NS; ++u) {
+                sa[g] += kv[u] * ms[u];
+                p[u] += kv[u] * ma;
+            }
+        }
+        int idx;
+        bool ok;
+        wave_reduce_scatter<T, G>(sa, lane, idx, ok);
+        if (ok && a0 + idx < Q2) racc[w][a0 + idx] += sa[0];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int k = kb + u * kWave + lane;
+        if (k < k1) P[k] = p[u] * kInv4Pi;
+    }
+}
+
 // Stage 1 without stored blocks: every coupling entry is the kernel at a pair of the
 // clusters' Chebyshev points on the surface, evaluated where it is used (the stored
 // blocks hold the same values).  Same chunks, row sums and transposed products as
@@ -949,12 +1012,12 @@ __device__ inline void kernel_unscaled(const KernelDesc& k, const double* r2, cd
 // moments staged in LDS per chunk): every lane adds k * m_owner[a] to its columns' transposed
 // products, and the G row sums of the pass are reduce-scattered across the wave and
 // added to the wave's row accumulators in LDS.  Columns past the row (its padding) or the
-// chunk get a distant point and a zero moment.
+// chunk get a distant point and a zero moment; a pass skips the 64-column slices that hold
+// padding only.
 template <class T, int Q, int NS>
 __device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
     constexpr int Q2 = Q * Q;
     static_assert(Q2 <= kWave, "one lane per row of the owner");
-    constexpr int G = Q < 5 ? Q : 5;
     __shared__ T racc[4][Q2];
     const int w = uniform_int(threadIdx.x >> 6);
     const int64_t c = (int64_t)blk_ * 4 + w;
@@ -988,57 +1051,19 @@ __device__ inline void coupling_otf_body(const OpDev& op, int64_t blk_) {
     }
     wave_sync();
     for (int kb = k0; kb < k1; kb += NS * kWave) {
-        double y0[NS], y1[NS], y2[NS], yy[NS];
-        T ms[NS], p[NS];
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int k = kb + u * kWave + lane;
-            p[u] = zero<T>();
-            if (k < kend) {
-                const int sl = k / Q2, b = k - sl * Q2;
-                const int64_t g = (int64_t)src[sl] * Q2 + b;
-                y0[u] = xc[3 * g] - o0;
-                y1[u] = xc[3 * g + 1] - o1;
-                y2[u] = xc[3 * g + 2] - o2;
-                ms[u] = mom[g];
-            } else {
-                y0[u] = y1[u] = y2[u] = 64.0;
-                ms[u] = zero<T>();
-            }
-            yy[u] = y0[u] * y0[u] + y1[u] * y1[u] + y2[u] * y2[u];
-        }
-#pragma unroll 1
-        for (int a0 = 0; a0 < Q2; a0 += G) {
-            T sa[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                sa[g] = zero<T>();
-                const int a = a0 + g;
-                if (Q2 % G != 0 && a >= Q2) continue;
-                const double4 pa = opt[w][a];
-                const T ma = omo[w][a];
-                double r2[NS];
-                T kv[NS];
-#pragma unroll
-                for (int u = 0; u < NS; ++u)
-                    r2[u] = __builtin_fma(pa.x, y0[u], __builtin_fma(pa.y, y1[u], __builtin_fma(pa.z, y2[u], pa.w + yy[u])));
-                kernel_unscaled<NS>(kd, r2, kv);
-#pragma unroll
-                for (int u = 0; u < NS; ++u) {
-                    sa[g] += kv[u] * ms[u];
-                    p[u] += kv[u] * ma;
-                }
-            }
-            int idx;
-            bool ok;
-            wave_reduce_scatter<T, G>(sa, lane, idx, ok);
-            if (ok && a0 + idx < Q2) racc[w][a0 + idx] += sa[0];
-        }
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int k = kb + u * kWave + lane;
-            if (k < k1) P[k] = p[u] * kInv4Pi;
-        }
+        // 64-column slices past the row's last real column carry only padding: the last
+        // pass of a row runs with as many slices as reach real columns
+        const int nu = kend - kb >= NS * kWave ? NS : (kend - kb + kWave - 1) / kWave;  // uniform
+        if (nu <= 0) continue;
+        // the narrowest pass that covers the nu slices: 1, 2, 4 or NS
+        if (nu == 1)
+            otf_pass<T, Q, 1>(op, kb, k1, kend, lane, w, src, o0, o1, o2, opt, omo, racc, P, kd);
+        else if (nu == 2 && NS > 2)
+            otf_pass<T, Q, (NS > 2 ? 2 : NS)>(op, kb, k1, kend, lane, w, src, o0, o1, o2, opt, omo, racc, P, kd);
+        else if (nu <= 4 && NS > 4)
+            otf_pass<T, Q, (NS > 4 ? 4 : NS)>(op, kb, k1, kend, lane, w, src, o0, o1, o2, opt, omo, racc, P, kd);
+        else
+            otf_pass<T, Q, NS>(op, kb, k1, kend, lane, w, src, o0, o1, o2, opt, omo, racc, P, kd);
     }
     if (lane < Q2) ((T*)op.partial)[c * Q2 + lane] = racc[w][lane] * kInv4Pi;
 }
