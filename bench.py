@@ -364,10 +364,11 @@ def bench_maxwell(B, W, torch, np, stream, args):
         ms = e0.elapsed_time(e1) / steps
         nl, q2 = 2 * c["degree"] * (c["degree"] + 1), c["q"] ** 2
         nelem = 6 * 4 ** c["level"]
-        # bytes every apply must move: kernel blocks, near blocks, channel moments (read in the
-        # forward and the backward transform)
-        byts = info.far_bytes + info.near_bytes + 2.0 * nelem * nl * 4 * q2 * 8
-        ent = {"leaf_level": leaf, "ndof": N, "nfar": info.nfar, "near_leaf_pairs": info.nnear,
+        # bytes every apply must move: kernel blocks (one per admissible pair), near blocks,
+        # channel moments (read in the forward and the backward transform), and the blocks'
+        # transposed products (written by the coupling, read by the top-down pass)
+        byts = info.far_bytes + info.near_bytes + 2.0 * nelem * nl * 4 * q2 * 8 + 2.0 * info.nstored * 4 * q2 * 16
+        ent = {"leaf_level": leaf, "ndof": N, "nfar": info.nfar, "nstored": info.nstored, "near_leaf_pairs": info.nnear,
                "near_block_entries": info.near_nnz, "far_bytes": info.far_bytes, "near_bytes": info.near_bytes,
                "plan_s": t_plan, "assembly_s": t_asm, "matvec_ms": ms, "dof_per_s": N / (ms * 1e-3),
                "matvec_gbs": byts / (ms * 1e-3) / 1e9}

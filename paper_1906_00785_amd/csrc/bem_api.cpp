@@ -145,6 +145,8 @@ struct bem_operator_s {
     std::vector<int64_t> mxh_plist;  // near element pairs (host copy, as the pair types)
     std::vector<double> mxh_lg;      // leaf Lagrange values at the Gauss points (same)
     std::vector<int32_t> mxh_ch_p0, mxh_ch_p1;  // coupling work chunks (same)
+    std::vector<int64_t> mxh_tr_ptr;            // per cluster: stored blocks where it is the partner
+    std::vector<int32_t> mxh_tr_blk;
     std::vector<int64_t> mx_blist;              // pair blocks by kind: regular, then touching (same)
     std::vector<int64_t> mxh_cl_chunk;
     std::vector<int32_t> mx_tinfo;  // host copies of the pair types and the Gauss rules (kept,
@@ -1657,7 +1659,7 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         off += al(bytes);
         return q;
     };
-    char* K = take((size_t)h.nfar * q2 * q2 * 16);
+    char* K = take((size_t)h.nstored * q2 * q2 * 16);
     char* NB = take((size_t)npairs * nl * nl * 16);
     char* Mt = take((size_t)ne * nl * 4 * q2 * 8);
     char* xl = take((size_t)ne * nl * 16);
@@ -1665,9 +1667,11 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     char* mom = take((size_t)h.ncl * 4 * q2 * 16);
     char* lv = take((size_t)h.ncl * 4 * q2 * 16);
     char* lev = take(pl.lev_off.size() * 8);
-    char* frp = take(pl.far_rowptr.size() * 8);
-    char* fs = take(pl.far_s.size() * 4);
-    char* ft = take(pl.far_t.size() * 4);
+    char* ot = take(pl.own_t.size() * 4);
+    char* os = take(pl.own_src.size() * 4);
+    char* trp = take(A.mxh_tr_ptr.size() * 8);
+    char* trb = take(A.mxh_tr_blk.size() * 4);
+    char* tpr = take((size_t)h.nstored * 4 * q2 * 16);
     char* nrp = take(pl.near_rowptr.size() * 4);
     char* ns = take(pl.near_s.size() * 4);
     char* cheb = take(pl.cheb.size() * 8);
@@ -1699,9 +1703,11 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         d->mom = mom;
         d->lv = lv;
         d->lev_off = (const int64_t*)lev;
-        d->far_rowptr = (const int64_t*)frp;
-        d->far_s = (const int32_t*)fs;
-        d->far_t = (const int32_t*)ft;
+        d->own_t = (const int32_t*)ot;
+        d->own_s = (const int32_t*)os;
+        d->tr_ptr = (const int64_t*)trp;
+        d->tr_blk = (const int32_t*)trb;
+        d->tprod = tpr;
         d->near_rowptr = (const int32_t*)nrp;
         d->near_s = (const int32_t*)ns;
         d->cheb = (const double*)cheb;
@@ -1778,20 +1784,27 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
         }
         A->mx_rules.clear();
         for (auto* v : {&pl.gx, &pl.gw, &pl.sx, &pl.sw}) A->mx_rules.insert(A->mx_rules.end(), v->begin(), v->end());
-        if (pl.far_t.size() > 0x7fffffff) {
+        if (pl.own_src.size() > 0x7fffffff) {
             delete A;
             return fail(BEM_EUNSUPPORTED, "too many admissible pairs");
         }
         mx_block_list(A->mx_tinfo, A->mx_blist);
-        // coupling work chunks: up to kMxhChunk consecutive pairs of one target
+        // coupling work chunks: up to kMxhChunk consecutive stored blocks of one owner;
+        // per cluster the stored blocks in which it is the partner (ascending)
         A->mxh_cl_chunk.assign(pl.ncl + 1, 0);
         for (int64_t c = 0; c < pl.ncl; ++c) {
-            for (int64_t q0 = pl.far_rowptr[c]; q0 < pl.far_rowptr[c + 1]; q0 += kMxhChunk) {
+            for (int64_t q0 = pl.own_rowptr[c]; q0 < pl.own_rowptr[c + 1]; q0 += kMxhChunk) {
                 A->mxh_ch_p0.push_back((int32_t)q0);
-                A->mxh_ch_p1.push_back((int32_t)std::min<int64_t>(q0 + kMxhChunk, pl.far_rowptr[c + 1]));
+                A->mxh_ch_p1.push_back((int32_t)std::min<int64_t>(q0 + kMxhChunk, pl.own_rowptr[c + 1]));
             }
             A->mxh_cl_chunk[c + 1] = (int64_t)A->mxh_ch_p0.size();
         }
+        A->mxh_tr_ptr.assign(pl.ncl + 1, 0);
+        for (int32_t v : pl.own_src) ++A->mxh_tr_ptr[v + 1];
+        for (int64_t c = 0; c < pl.ncl; ++c) A->mxh_tr_ptr[c + 1] += A->mxh_tr_ptr[c];
+        A->mxh_tr_blk.assign(pl.own_src.size(), 0);
+        std::vector<int64_t> fill(A->mxh_tr_ptr.begin(), A->mxh_tr_ptr.end() - 1);
+        for (size_t sb = 0; sb < pl.own_src.size(); ++sb) A->mxh_tr_blk[fill[pl.own_src[sb]]++] = (int32_t)sb;
         A->mxh_lg.assign((size_t)m * P.qg * P.q, 0.0);
         for (int i = 0; i < m; ++i)
             for (int k = 0; k < P.qg; ++k)
@@ -1829,6 +1842,7 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     d.nfar = (int64_t)pl.far_t.size();
     d.nnear = (int64_t)pl.near_t.size();
     d.nchunks = (int64_t)A->mxh_ch_p0.size();
+    d.nstored = (int64_t)pl.own_src.size();
     const int64_t N = S.nglob;
     bem_operator_info& I = A->info;
     I.ndof = N;
@@ -1843,7 +1857,8 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     size_t tmpb = 0;
     I.op_bytes = mxh_layout(*A, nullptr, nullptr, nullptr, &tmpb);
     I.tmp_bytes = tmpb;
-    I.far_bytes = (double)d.nfar * d.q2 * d.q2 * 16;
+    I.nstored = d.nstored;
+    I.far_bytes = (double)d.nstored * d.q2 * d.q2 * 16;
     I.near_bytes = (double)I.near_nnz * 16;
     // the plan's own arrays (they stay with the operator) are the scalar element space's;
     // the operator is reported on S^1
@@ -1875,9 +1890,10 @@ static int mxh_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_
         return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
     };
     HIP_CHECK(up(d.lev_off, pl.lev_off.data(), pl.lev_off.size() * 8));
-    HIP_CHECK(up(d.far_rowptr, pl.far_rowptr.data(), pl.far_rowptr.size() * 8));
-    HIP_CHECK(up(d.far_s, pl.far_s.data(), pl.far_s.size() * 4));
-    HIP_CHECK(up(d.far_t, pl.far_t.data(), pl.far_t.size() * 4));
+    HIP_CHECK(up(d.own_t, pl.own_t.data(), pl.own_t.size() * 4));
+    HIP_CHECK(up(d.own_s, pl.own_src.data(), pl.own_src.size() * 4));
+    HIP_CHECK(up(d.tr_ptr, A->mxh_tr_ptr.data(), A->mxh_tr_ptr.size() * 8));
+    HIP_CHECK(up(d.tr_blk, A->mxh_tr_blk.data(), A->mxh_tr_blk.size() * 4));
     HIP_CHECK(up(d.near_rowptr, pl.near_rowptr.data(), pl.near_rowptr.size() * 4));
     HIP_CHECK(up(d.near_s, pl.near_s.data(), pl.near_s.size() * 4));
     HIP_CHECK(up(d.cheb, pl.cheb.data(), pl.cheb.size() * 8));

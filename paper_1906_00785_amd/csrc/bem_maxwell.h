@@ -13,7 +13,7 @@
 namespace bem {
 
 constexpr int kMxMaxP = 2;    // degrees p of the device kernels (register budget of the pair kernel)
-constexpr int kMxhChunk = 8;  // admissible pairs per coupling work chunk
+constexpr int kMxhChunk = 8;  // stored admissible pairs per coupling work chunk
 
 struct MxDev {
     GeomDesc geom;
@@ -51,16 +51,22 @@ struct MxhDev {
     const int64_t* lev_off;      // [leaf + 2] first cluster of every level
     const double* cheb;          // [q] Chebyshev nodes on [0, 1]
     const double* E;             // [2][q][q]: E[b][p][a] = L_a(child b's node p in the parent)
-    const int64_t* far_rowptr;   // [ncl + 1] ordered admissible pairs by target
-    const int32_t* far_s;        // [nfar] source
-    const int32_t* far_t;        // [nfar] target
-    void* K;                     // [nfar][q2 (source b)][q2 (target a)] complex G(x_a^t, x_b^s)
-    // coupling work chunks: up to kMxhChunk consecutive pairs of one target each
+    // admissible pairs stored once: block s joins its owner own_t[s] and partner own_s[s]
+    // (the owner's blocks consecutive)
+    int64_t nstored;
+    const int32_t* own_t;        // [nstored]
+    const int32_t* own_s;        // [nstored]
+    void* K;                     // [nstored][q2 (partner b)][q2 (owner a)] complex G(x_a^owner, x_b^partner)
+    // coupling work chunks: up to kMxhChunk consecutive stored blocks of one owner each
     int64_t nchunks;
-    const int32_t* ch_p0;        // [nchunks] first pair
-    const int32_t* ch_p1;        // [nchunks] end pair
-    const int64_t* cl_chunk;     // [ncl + 1] chunks of every cluster
-    void* partial;               // [nchunks][4][q2] complex partial local expansions
+    const int32_t* ch_p0;        // [nchunks] first stored block
+    const int32_t* ch_p1;        // [nchunks] end stored block
+    const int64_t* cl_chunk;     // [ncl + 1] chunks of every cluster (as owner)
+    void* partial;               // [nchunks][4][q2] complex partial local expansions of the owners
+    void* tprod;                 // [nstored][4][q2] complex products of the blocks' transposes with
+                                 // the owners' moments (the partners' contributions)
+    const int64_t* tr_ptr;       // [ncl + 1] stored blocks in which each cluster is the partner
+    const int32_t* tr_blk;
     const int32_t* near_rowptr;  // [nleaves + 1] near leaf pairs by target leaf
     const int32_t* near_s;       // [nnear] source leaf (leaf-local index)
     double* Mt;                  // [nelem][nl][4][q2] channel moments against the leaf's Lagrange polynomials

@@ -569,15 +569,15 @@ __global__ __launch_bounds__(256) void k_mxh_points(MxhDev d) {
     patch_point(d.s.geom, f, (i + d.cheb[a / d.q]) * w, (j + d.cheb[a % d.q]) * w, d.xc + 3 * id);
 }
 
-// kernel at the nodes of every ordered admissible pair, stored [pair][b][a]
+// kernel at the nodes of every stored admissible pair, stored [block][partner node b][owner node a]
 __global__ __launch_bounds__(256) void k_mxh_far(MxhDev d) {
     const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t per = (int64_t)d.q2 * d.q2;
-    if (id >= d.nfar * per) return;
+    if (id >= d.nstored * per) return;
     const int64_t pr = id / per;
     const int rem = (int)(id % per), b = rem / d.q2, a = rem % d.q2;
-    const double* x = d.xc + ((int64_t)d.far_t[pr] * d.q2 + a) * 3;
-    const double* y = d.xc + ((int64_t)d.far_s[pr] * d.q2 + b) * 3;
+    const double* x = d.xc + ((int64_t)d.own_t[pr] * d.q2 + a) * 3;
+    const double* y = d.xc + ((int64_t)d.own_s[pr] * d.q2 + b) * 3;
     const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
     ((cdbl*)d.K)[id] = kernel_val(d.s.ker, dx * dx + dy * dy + dz * dz, cdbl{0.0, 0.0});
 }
@@ -710,32 +710,44 @@ __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
     }
 }
 
-// Coupling, one wave per work chunk (consecutive admissible pairs of one target t):
-// partial[chunk][c][a] = sum over its pairs (t, s) of sum_b G(x_a^t, x_b^s) mom[s][c][b].
-// Lane a holds the four channels of node a; with q^2 <= 32 the two half-waves take
-// alternate pairs.  The kernel block is read coalesced ([b][a]); the sources' moments are
-// uniform per half-wave and come through the scalar cache.
+// Coupling, one wave per work chunk (consecutive stored blocks of one owner u): for every
+// block (u, v) with entries K[b][a] = G(x_a^u, x_b^v)
+//   partial[chunk][c][a] += sum_b K[b][a] mom[v][c][b]   (the owner's expansion; lane a
+//                                                         reads the block's column a,
+//                                                         coalesced across the lanes)
+//   tprod[block][c][b]   = sum_a K[b][a] mom[u][c][a]    (the partner's; lane b reads row b,
+//                                                         just fetched by the column pass)
+// With q^2 <= 32 the two half-waves take alternate blocks.  The moments of the partners
+// and of the owner are uniform per half-wave and come through the scalar cache.
 template <int Q>
 __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
     constexpr int Q2 = Q * Q, PPW = Q2 <= 32 ? 2 : 1, HW = 64 / PPW;
     const int64_t k = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
     if (k >= d.nchunks) return;
     const int lane = threadIdx.x & 63, h = lane / HW, a = lane % HW;
-    const mx_ciptr cp0 = (mx_ciptr)d.ch_p0, cp1 = (mx_ciptr)d.ch_p1, cfs = (mx_ciptr)d.far_s;
+    const mx_ciptr cp0 = (mx_ciptr)d.ch_p0, cp1 = (mx_ciptr)d.ch_p1, cos_ = (mx_ciptr)d.own_s, cot = (mx_ciptr)d.own_t;
     const mx_cdptr mom = (mx_cdptr)d.mom;
     const int p0 = cp0[k], p1 = cp1[k];
+    // the owner's moments, staged in the wave's LDS slice (read uniformly by the row pass)
+    __shared__ cdbl mus[4][4 * Q2];
+    const int w = threadIdx.x >> 6;
+    {
+        const cdbl* mu = (const cdbl*)d.mom + (int64_t)cot[p0] * 4 * Q2;
+        for (int o = lane; o < 4 * Q2; o += 64) mus[w][o] = mu[o];
+        wave_sync();
+    }
     const cdbl* __restrict__ Kb = (const cdbl*)d.K;
     cdbl acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = cdbl{0.0, 0.0};
     for (int pp = p0; pp < p1; pp += PPW) {
-        const int s0 = cfs[pp];
-        const int s1 = (PPW == 2 && pp + 1 < p1) ? cfs[pp + 1] : s0;
+        const int s0 = cos_[pp];
+        const int s1 = (PPW == 2 && pp + 1 < p1) ? cos_[pp + 1] : s0;
         const bool on = a < Q2 && pp + h < p1;
         const cdbl* __restrict__ K = Kb + (int64_t)(pp + h) * Q2 * Q2;
         const mx_cdptr m0 = mom + (int64_t)s0 * 8 * Q2, m1 = mom + (int64_t)s1 * 8 * Q2;
         // the lane's column of the block, all loads in flight before the products
-        constexpr int KB = Q2 <= 32 ? Q2 : 16;
+        constexpr int KB = Q2 <= 16 ? Q2 : (Q2 <= 32 ? (Q2 + 1) / 2 : 16);
 #pragma unroll 1
         for (int b0 = 0; b0 < Q2; b0 += KB) {
             cdbl kcol[KB];
@@ -756,6 +768,35 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
                 }
             }
         }
+        // the transposed product: lane b = a takes row b of the block
+        cdbl tp[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tp[c] = cdbl{0.0, 0.0};
+        constexpr int KT = 8;  // row entries in flight (the row was just fetched by the column pass)
+#pragma unroll 1
+        for (int a0 = 0; a0 < Q2; a0 += KT) {
+            cdbl krow[KT];
+#pragma unroll
+            for (int aa = 0; aa < KT; ++aa)
+                krow[aa] = (on && a0 + aa < Q2) ? K[a * Q2 + a0 + aa] : cdbl{0.0, 0.0};
+#pragma unroll
+            for (int aa = 0; aa < KT; ++aa) {
+                const int ai = a0 + aa;
+                if (ai >= Q2) break;
+                const cdbl kv = krow[aa];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const cdbl mv = mus[w][c * Q2 + ai];
+                    tp[c].re += kv.re * mv.re - kv.im * mv.im;
+                    tp[c].im += kv.re * mv.im + kv.im * mv.re;
+                }
+            }
+        }
+        if (on) {
+            cdbl* out = (cdbl*)d.tprod + (int64_t)(pp + h) * 4 * Q2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[c * Q2 + a] = tp[c];
+        }
     }
     if (PPW == 2) {
 #pragma unroll
@@ -772,7 +813,8 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
 }
 
 // Local expansions at level lev, top down: lv[c] = the sum of the cluster's chunk partials
-// (in chunk order) plus, below the roots, the parent's expansion transferred:
+// (in chunk order), of the transposed products of the blocks in which it is the partner (in
+// block order) and, below the roots, the parent's expansion transferred:
 // sum_a E_b1[p1][a1] E_b2[p2][a2] lv[parent][c][a].  One wave per cluster.
 template <int NO>
 __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
@@ -785,6 +827,7 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
     const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
     const int64_t cl = d.lev_off[lev] + loc;
     const cdbl* part = (const cdbl*)d.partial;
+    const cdbl* tp = (const cdbl*)d.tprod;
     const int64_t k0 = d.cl_chunk[cl], k1 = d.cl_chunk[cl + 1];
     const mx_cdptr E = (mx_cdptr)d.E;
     __shared__ cdbl ps[4][4 * 64];  // [wave][c][a]: the parent's expansion
@@ -807,6 +850,16 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
         if (o >= nout) continue;
         cdbl s = {0.0, 0.0};
         for (int64_t k = k0; k < k1; ++k) s = s + part[k * nout + o];
+        // the transposed products: four independent sums, so that their loads overlap
+        cdbl t4[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        const int64_t e0 = d.tr_ptr[cl], e1 = d.tr_ptr[cl + 1];
+        int64_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) t4[v] = t4[v] + tp[(int64_t)d.tr_blk[e + v] * nout + o];
+        }
+        for (int v = 0; e < e1; ++e, ++v) t4[v] = t4[v] + tp[(int64_t)d.tr_blk[e] * nout + o];
+        s = s + ((t4[0] + t4[1]) + (t4[2] + t4[3]));
         if (lp) {
             const int c = o / q2, p = o % q2, p1 = p / q, p2 = p % q;
             for (int a1 = 0; a1 < q; ++a1) {
@@ -981,7 +1034,7 @@ hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st) {
     if (d.ncl * d.q2 > 0) hipLaunchKernelGGL(k_mxh_points, dim3(nb(d.ncl * d.q2, 256)), dim3(256), 0, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t nk = d.nfar * d.q2 * d.q2;
+    const int64_t nk = d.nstored * d.q2 * d.q2;
     if (nk > 0) hipLaunchKernelGGL(k_mxh_far, dim3(nb(nk, 256)), dim3(256), 0, st, d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (d.s.nelem > 0) {
