@@ -710,21 +710,104 @@ __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
     }
 }
 
-// Coupling, one wave per work chunk (consecutive stored blocks of one owner u): for every
-// block (u, v) with entries K[b][a] = G(x_a^u, x_b^v)
-//   partial[chunk][c][a] += sum_b K[b][a] mom[v][c][b]   (the owner's expansion; lane a
-//                                                         reads the block's column a,
-//                                                         coalesced across the lanes)
-//   tprod[block][c][b]   = sum_a K[b][a] mom[u][c][a]    (the partner's; lane b reads row b,
-//                                                         just fetched by the column pass)
-// With q^2 <= 32 the two half-waves take alternate blocks.  The moments of the partners
-// and of the owner are uniform per half-wave and come through the scalar cache.
+// Coupling.  For every stored block (u, v) of a work chunk (consecutive stored blocks of one
+// owner u), with entries K[b][a] = G(x_a^u, x_b^v):
+//   partial[chunk][c][a] += sum_b K[b][a] mom[v][c][b]   (the owner's expansion)
+//   tprod[block][c][b]   = sum_a K[b][a] mom[u][c][a]    (the partner's)
+// With q^2 <= 32 (q <= 5): one workgroup of eight waves per chunk, one block per wave.  The
+// wave copies its block into its LDS slice with global-to-LDS loads (no registers held, all
+// of the workgroup's loads in flight at once) and waits for its own copy only; both passes
+// then read LDS, lane (0, i) forming the real and lane (1, i) the imaginary part of node
+// i's sum, so that the moments (the partner's in the column pass, the owner's in the row
+// pass) are uniform over the wave and enter the products straight from scalar registers.
+// The eight waves' column sums are added in a fixed order.
+template <int Q>
+__global__ __launch_bounds__(512) void k_mxh_coupling_wg(MxhDev d) {
+    constexpr int Q2 = Q * Q, QQ = Q2 * Q2, NL = 8 * QQ > 32 * Q2 ? 8 * QQ : 32 * Q2;
+    static_assert(Q2 <= 32 && kMxhChunk == 8, "one block per wave, eight waves");
+    __shared__ cdbl kls[NL];  // block j of the chunk at j q^4, [b][a]; then the waves' column sums
+    const int64_t k = blockIdx.x;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63, h = lane >> 5, i = lane & 31;
+    const mx_ciptr cp0 = (mx_ciptr)d.ch_p0, cp1 = (mx_ciptr)d.ch_p1, cos_ = (mx_ciptr)d.own_s, cot = (mx_ciptr)d.own_t;
+    const int p0 = cp0[k], p1 = cp1[k];
+    const int pb = p0 + w;  // the wave's block
+    const int ic = i < Q2 ? i : 0;  // lanes past the nodes work on node 0; their results are dropped
+    // x K + y K' with (x, y) = (re, -im) of the entry for the real part, (im, re) for the
+    // imaginary part, and (K, K') = (re, im) of the moment
+    const int hx = h, hy = 1 - h;
+    const uint64_t neg = h ? 0ull : 0x8000000000000000ull;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (pb < p1) {
+        {
+            // 16 bytes per lane, 1 KiB per instruction: lane l of the instruction at byte off
+            // lands at LDS byte off + 16 l of the wave's slice
+            const char* src = (const char*)d.K + (int64_t)pb * QQ * 16;
+            char* dst = (char*)(kls + w * QQ);
+            for (int off = 0; off < QQ * 16; off += 1024)
+                if (off + 16 * lane < QQ * 16)
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + off + 16 * lane),
+                                                     (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copy has landed
+            wave_sync();
+        }
+        const double* ks = (const double*)(kls + w * QQ);
+        const mx_cdptr mom = (mx_cdptr)d.mom;
+        // column pass: lane i takes column i against the partner's moments
+        const mx_cdptr mp = mom + (int64_t)cos_[pb] * 8 * Q2;
+#pragma unroll 5
+        for (int b = 0; b < Q2; ++b) {
+            const int e = 2 * (b * Q2 + ic);
+            const double x = ks[e + hx];
+            const double y = __longlong_as_double(__double_as_longlong(ks[e + hy]) ^ (long long)neg);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int o = 2 * (c * Q2 + b);
+                acc[c] = fma(x, mp[o], fma(y, mp[o + 1], acc[c]));
+            }
+        }
+        // row pass: lane i takes row i against the owner's moments
+        const mx_cdptr mo = mom + (int64_t)cot[p0] * 8 * Q2;
+        double tp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 5
+        for (int a = 0; a < Q2; ++a) {
+            const int e = 2 * (ic * Q2 + a);
+            const double x = ks[e + hx];
+            const double y = __longlong_as_double(__double_as_longlong(ks[e + hy]) ^ (long long)neg);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int o = 2 * (c * Q2 + a);
+                tp[c] = fma(x, mo[o], fma(y, mo[o + 1], tp[c]));
+            }
+        }
+        if (i < Q2) {
+            double* out = (double*)d.tprod + (int64_t)pb * 8 * Q2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[2 * (c * Q2 + i) + h] = tp[c];
+        }
+    }
+    __syncthreads();  // every wave is done with its block
+    if (i < Q2)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ((double*)kls)[2 * (w * 4 * Q2 + c * Q2 + i) + h] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 4 * Q2) {
+        const int o = threadIdx.x;
+        cdbl s = kls[o];
+#pragma unroll
+        for (int v = 1; v < 8; ++v) s = s + kls[v * 4 * Q2 + o];
+        ((cdbl*)d.partial)[k * 4 * Q2 + o] = s;
+    }
+}
+
+// The same for q^2 > 32: one wave per work chunk, looping over its blocks; lane b reads row
+// b of the block for the transposed product right after the column pass fetched it.
 template <int Q>
 __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
-    constexpr int Q2 = Q * Q, PPW = Q2 <= 32 ? 2 : 1, HW = 64 / PPW;
+    constexpr int Q2 = Q * Q;
+    static_assert(Q2 > 32 && Q2 <= 64, "one block per wave");
     const int64_t k = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
     if (k >= d.nchunks) return;
-    const int lane = threadIdx.x & 63, h = lane / HW, a = lane % HW;
+    const int a = threadIdx.x & 63;
     const mx_ciptr cp0 = (mx_ciptr)d.ch_p0, cp1 = (mx_ciptr)d.ch_p1, cos_ = (mx_ciptr)d.own_s, cot = (mx_ciptr)d.own_t;
     const mx_cdptr mom = (mx_cdptr)d.mom;
     const int p0 = cp0[k], p1 = cp1[k];
@@ -733,21 +816,19 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
     const int w = threadIdx.x >> 6;
     {
         const cdbl* mu = (const cdbl*)d.mom + (int64_t)cot[p0] * 4 * Q2;
-        for (int o = lane; o < 4 * Q2; o += 64) mus[w][o] = mu[o];
+        for (int o = a; o < 4 * Q2; o += 64) mus[w][o] = mu[o];
         wave_sync();
     }
     const cdbl* __restrict__ Kb = (const cdbl*)d.K;
     cdbl acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = cdbl{0.0, 0.0};
-    for (int pp = p0; pp < p1; pp += PPW) {
-        const int s0 = cos_[pp];
-        const int s1 = (PPW == 2 && pp + 1 < p1) ? cos_[pp + 1] : s0;
-        const bool on = a < Q2 && pp + h < p1;
-        const cdbl* __restrict__ K = Kb + (int64_t)(pp + h) * Q2 * Q2;
-        const mx_cdptr m0 = mom + (int64_t)s0 * 8 * Q2, m1 = mom + (int64_t)s1 * 8 * Q2;
-        // the lane's column of the block, all loads in flight before the products
-        constexpr int KB = Q2 <= 16 ? Q2 : (Q2 <= 32 ? (Q2 + 1) / 2 : 16);
+    const bool on = a < Q2;
+    for (int pp = p0; pp < p1; ++pp) {
+        const cdbl* __restrict__ K = Kb + (int64_t)pp * Q2 * Q2;
+        const mx_cdptr m0 = mom + (int64_t)cos_[pp] * 8 * Q2;
+        // the lane's column of the block, all loads of a slice in flight before the products
+        constexpr int KB = 16;
 #pragma unroll 1
         for (int b0 = 0; b0 < Q2; b0 += KB) {
             cdbl kcol[KB];
@@ -762,7 +843,7 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int o = 2 * (c * Q2 + b);
-                    const double mr = h ? m1[o] : m0[o], mi = h ? m1[o + 1] : m0[o + 1];
+                    const double mr = m0[o], mi = m0[o + 1];
                     acc[c].re += kv.re * mr - kv.im * mi;
                     acc[c].im += kv.re * mi + kv.im * mr;
                 }
@@ -772,7 +853,7 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
         cdbl tp[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) tp[c] = cdbl{0.0, 0.0};
-        constexpr int KT = 8;  // row entries in flight (the row was just fetched by the column pass)
+        constexpr int KT = 8;  // row entries in flight
 #pragma unroll 1
         for (int a0 = 0; a0 < Q2; a0 += KT) {
             cdbl krow[KT];
@@ -793,19 +874,12 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
             }
         }
         if (on) {
-            cdbl* out = (cdbl*)d.tprod + (int64_t)(pp + h) * 4 * Q2;
+            cdbl* out = (cdbl*)d.tprod + (int64_t)pp * 4 * Q2;
 #pragma unroll
             for (int c = 0; c < 4; ++c) out[c * Q2 + a] = tp[c];
         }
     }
-    if (PPW == 2) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            acc[c].re += __shfl_xor(acc[c].re, 32, 64);
-            acc[c].im += __shfl_xor(acc[c].im, 32, 64);
-        }
-    }
-    if (h == 0 && a < Q2) {
+    if (on) {
         cdbl* out = (cdbl*)d.partial + k * 4 * Q2;
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[c * Q2 + a] = acc[c];
@@ -1059,13 +1133,13 @@ static hipError_t mxh_apply_no(const MxhDev& d, const void* x, void* y, hipStrea
         hipLaunchKernelGGL(k_mxh_up<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
     if (d.nchunks > 0) {
-        const dim3 g(nb(d.nchunks, 4)), blk(256);
+        const dim3 g(nb(d.nchunks, 4)), gw(d.nchunks), blk(256), blkw(512);
         switch (d.q) {
-            case 1: hipLaunchKernelGGL(k_mxh_coupling<1>, g, blk, 0, st, d); break;
-            case 2: hipLaunchKernelGGL(k_mxh_coupling<2>, g, blk, 0, st, d); break;
-            case 3: hipLaunchKernelGGL(k_mxh_coupling<3>, g, blk, 0, st, d); break;
-            case 4: hipLaunchKernelGGL(k_mxh_coupling<4>, g, blk, 0, st, d); break;
-            case 5: hipLaunchKernelGGL(k_mxh_coupling<5>, g, blk, 0, st, d); break;
+            case 1: hipLaunchKernelGGL(k_mxh_coupling_wg<1>, gw, blkw, 0, st, d); break;
+            case 2: hipLaunchKernelGGL(k_mxh_coupling_wg<2>, gw, blkw, 0, st, d); break;
+            case 3: hipLaunchKernelGGL(k_mxh_coupling_wg<3>, gw, blkw, 0, st, d); break;
+            case 4: hipLaunchKernelGGL(k_mxh_coupling_wg<4>, gw, blkw, 0, st, d); break;
+            case 5: hipLaunchKernelGGL(k_mxh_coupling_wg<5>, gw, blkw, 0, st, d); break;
             case 6: hipLaunchKernelGGL(k_mxh_coupling<6>, g, blk, 0, st, d); break;
             case 7: hipLaunchKernelGGL(k_mxh_coupling<7>, g, blk, 0, st, d); break;
             default: hipLaunchKernelGGL(k_mxh_coupling<8>, g, blk, 0, st, d); break;
