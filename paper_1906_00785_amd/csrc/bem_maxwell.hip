@@ -549,12 +549,13 @@ __device__ inline void cluster_of(const MxhDev& d, int64_t c, int& lev, int& f, 
     f = (int)(loc / ((int64_t)n * n));
 }
 
-// element of leaf l (leaf-local index) at position v (row-major m x m)
+// element of leaf l (leaf-local index) at position v (row-major m x m); the leaves per
+// direction and the elements per leaf and direction are powers of two
 __device__ inline int64_t leaf_elem(const MxhDev& d, int64_t l, int v) {
-    const int n1 = d.nleaf1, m = d.m;
-    const int64_t f = l / ((int64_t)n1 * n1);
-    const int li = (int)((l / n1) % n1), lj = (int)(l % n1);
-    return (f * d.s.nel + li * m + v / m) * d.s.nel + lj * m + v % m;
+    const int s1 = __builtin_ctz(d.nleaf1), sm = __builtin_ctz(d.m);
+    const int64_t f = l >> (2 * s1);
+    const int li = (int)(l >> s1) & (d.nleaf1 - 1), lj = (int)l & (d.nleaf1 - 1);
+    return (f * d.s.nel + (li << sm) + (v >> sm)) * d.s.nel + (lj << sm) + (v & (d.m - 1));
 }
 
 // Chebyshev points of every cluster on the surface; one thread per (cluster, node)
@@ -632,81 +633,117 @@ __global__ __launch_bounds__(256) void k_mxh_gather_x(MxhDev d, const cdbl* __re
 }
 
 // Leaf moments (forward transform): mom[leaf][c][a] = sum over its elements and their
-// functions of Mt[e][k][c][a] xl[e][k]; one wave per leaf, lanes over (c, a).
-template <int NO>
+// functions of Mt[e][k][c][a] xl[e][k]; lanes over (c, a).  With one element per leaf, one
+// wave per leaf; otherwise one workgroup per leaf, wave w taking the leaf's elements w,
+// w + 4, ..., and the four waves' sums added in a fixed order.  All loads of an element are
+// issued before its products.
+template <int P, int NO>
 __global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
-    const int64_t l = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (l >= d.nleaves) return;
-    const int nl = d.s.nl, nout = 4 * d.q2, m2 = d.m * d.m;
+    constexpr int NL = 2 * P * (P + 1);
+    __shared__ cdbl red[4][64 * NO];
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int m2 = d.m * d.m, nout = 4 * d.q2;
+    const bool one = m2 == 1;
+    const int64_t l = one ? (int64_t)blockIdx.x * 4 + w : (int64_t)blockIdx.x;
+    if (l >= d.nleaves) return;  // uniform over the workgroup unless one == true
     cdbl acc[NO];
 #pragma unroll
     for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
     const cdbl* xl = (const cdbl*)d.xl;
-    for (int v = 0; v < m2; ++v) {
+    for (int v = one ? 0 : w; v < m2; v += 4) {
         const int64_t e = leaf_elem(d, l, v);
-        for (int k = 0; k < nl; ++k) {
-            const cdbl xv = xl[e * nl + k];
-            const double* mt = d.Mt + (e * nl + k) * (int64_t)nout;
+        const double* mt = d.Mt + e * NL * (int64_t)nout;
+        cdbl xv[NL];
+        double mv[NL][NO];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            xv[k] = xl[e * NL + k];
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 const int o = lane + 64 * u;
-                if (o < nout) acc[u] = acc[u] + xv * mt[o];
+                const double x = mt[k * nout + (o < nout ? o : 0)];  // loads without branches
+                mv[k][u] = o < nout ? x : 0.0;
             }
         }
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+#pragma unroll
+            for (int u = 0; u < NO; ++u) acc[u] = acc[u] + xv[k] * mv[k][u];
     }
     cdbl* mom = (cdbl*)d.mom + (d.lev_off[d.leaf] + l) * nout;
+    if (one) {
 #pragma unroll
-    for (int u = 0; u < NO; ++u) {
-        const int o = lane + 64 * u;
-        if (o < nout) mom[o] = acc[u];
+        for (int u = 0; u < NO; ++u) {
+            const int o = lane + 64 * u;
+            if (o < nout) mom[o] = acc[u];
+        }
+        return;
     }
+#pragma unroll
+    for (int u = 0; u < NO; ++u) red[w][lane + 64 * u] = acc[u];
+    __syncthreads();
+    if (w == 0)
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int o = lane + 64 * u;
+            if (o < nout) mom[o] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+        }
 }
 
 typedef const __attribute__((address_space(4))) double* mx_cdptr;
 typedef const __attribute__((address_space(4))) int32_t* mx_ciptr;
 
 // Upward transfer to level lev: m_P[c][a] = sum over the four children b and their nodes p
-// of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent.  The children's moments
-// are staged in the wave's LDS slice (coalesced), the transfer matrices come through the
-// scalar cache, and the transfer is applied one direction at a time.
-template <int NO>
+// of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent, lanes over (c, a).  The
+// children's moments are staged in the wave's LDS slice (coalesced); each lane holds the
+// transfer entries of its node in registers, so the sums run without memory waits.
+template <int Q>
 __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
-    __shared__ cdbl mc[4][4 * 64 * NO];  // [wave][child][c][p]
+    constexpr int Q2 = Q * Q, NOUT = 4 * Q2, NO = (NOUT + 63) / 64;
+    __shared__ cdbl mc[4][4 * NOUT];  // [wave][child][c][p]
     const int n = 1 << lev;
     const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
     const int w = uniform_int(threadIdx.x >> 6);
     const int64_t loc = (int64_t)blockIdx.x * 4 + w;
     const int lane = threadIdx.x & 63;
     if (loc >= nc) return;
-    const int q = d.q, q2 = d.q2, nout = 4 * q2;
     const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
     const cdbl* mom = (const cdbl*)d.mom;
     cdbl* sm = mc[w];
     // the four children are consecutive in pairs along j: (2i + b1, 2j), (2i + b1, 2j + 1)
     for (int b1 = 0; b1 < 2; ++b1) {
         const int64_t ch = d.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j;
-        const cdbl* src = mom + ch * nout;
-        for (int o = lane; o < 2 * nout; o += 64) sm[b1 * 2 * nout + o] = src[o];
+        const cdbl* src = mom + ch * NOUT;
+        for (int o = lane; o < 2 * NOUT; o += 64) sm[b1 * 2 * NOUT + o] = src[o];
     }
     wave_sync();
-    const mx_cdptr E = (mx_cdptr)d.E;
 #pragma unroll
     for (int u = 0; u < NO; ++u) {
         const int o = lane + 64 * u;
-        if (o >= nout) continue;
-        const int c = o / q2, a = o % q2, a1 = a / q, a2 = a % q;
+        if (o >= NOUT) continue;
+        const int c = o / Q2, a = o % Q2, a1 = a / Q, a2 = a % Q;
+        double e1[2][Q], e2[2][Q];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                e1[bb][p] = d.E[(bb * Q + p) * Q + a1];
+                e2[bb][p] = d.E[(bb * Q + p) * Q + a2];
+            }
         cdbl acc = {0.0, 0.0};
+#pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int b1 = b >> 1, b2 = b & 1;
-            const cdbl* m = sm + b * nout + c * q2;
-            for (int p1 = 0; p1 < q; ++p1) {
+            const cdbl* m = sm + b * NOUT + c * Q2;
+#pragma unroll
+            for (int p1 = 0; p1 < Q; ++p1) {
                 cdbl t = {0.0, 0.0};
-                for (int p2 = 0; p2 < q; ++p2) t = t + m[p1 * q + p2] * E[(b2 * q + p2) * q + a2];
-                acc = acc + t * E[(b1 * q + p1) * q + a1];
+#pragma unroll
+                for (int p2 = 0; p2 < Q; ++p2) t = t + m[p1 * Q + p2] * e2[b2][p2];
+                acc = acc + t * e1[b1][p1];
             }
         }
-        ((cdbl*)d.mom)[(d.lev_off[lev] + loc) * nout + o] = acc;
+        ((cdbl*)d.mom)[(d.lev_off[lev] + loc) * NOUT + o] = acc;
     }
 }
 
@@ -886,62 +923,103 @@ __global__ __launch_bounds__(256) void k_mxh_coupling(MxhDev d) {
     }
 }
 
-// Local expansions at level lev, top down: lv[c] = the sum of the cluster's chunk partials
-// (in chunk order), of the transposed products of the blocks in which it is the partner (in
-// block order) and, below the roots, the parent's expansion transferred:
-// sum_a E_b1[p1][a1] E_b2[p2][a2] lv[parent][c][a].  One wave per cluster.
+// Local expansions, first part: lv[cl][c] = the sum of the cluster's chunk partials and of
+// the transposed products of the blocks in which it is the partner, for the clusters of
+// every level at once.  One workgroup per cluster, lanes over (c, a): the rows (partials in
+// chunk order, then the transposed products in block order) are dealt to the four waves in
+// turn, each wave keeps four running sums (row t to sum (t / 4) mod 4, the rows past the
+// last full group of sixteen to the first), and the sums are added pairwise, then the waves'
+// in wave order.
 template <int NO>
-__global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
-    const int n = 1 << lev;
-    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
-    const int64_t loc = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (loc >= nc) return;
-    const int q = d.q, q2 = d.q2, nout = 4 * q2;
-    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const int64_t cl = d.lev_off[lev] + loc;
+__global__ __launch_bounds__(256) void k_mxh_collect(MxhDev d) {
+    __shared__ cdbl red[4][64 * NO];
+    const int64_t cl = blockIdx.x;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nout = 4 * d.q2;
     const cdbl* part = (const cdbl*)d.partial;
     const cdbl* tp = (const cdbl*)d.tprod;
-    const int64_t k0 = d.cl_chunk[cl], k1 = d.cl_chunk[cl + 1];
-    const mx_cdptr E = (mx_cdptr)d.E;
-    __shared__ cdbl ps[4][4 * 64];  // [wave][c][a]: the parent's expansion
-    const int w = threadIdx.x >> 6;
-    const cdbl* lp = nullptr;
-    int b1 = 0, b2 = 0;
-    if (lev > 0) {
-        const int hh = n / 2;
-        b1 = i & 1;
-        b2 = j & 1;
-        const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + ((int64_t)f * hh + i / 2) * hh + j / 2) * nout;
-        for (int o = lane; o < nout; o += 64) ps[w][o] = src[o];
-        wave_sync();
-        lp = ps[w];
+    const mx_ciptr tb = (mx_ciptr)d.tr_blk;
+    const int64_t k0 = d.cl_chunk[cl], nk = d.cl_chunk[cl + 1] - k0;
+    const int64_t e0 = d.tr_ptr[cl], ni = nk + d.tr_ptr[cl + 1] - e0;
+    // lanes past the outputs read output 0 (loads without branches); their sums are not used
+    bool on[NO];
+    int oc[NO];
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        on[u] = lane + 64 * u < nout;
+        oc[u] = on[u] ? lane + 64 * u : 0;
     }
-    cdbl* lc = (cdbl*)d.lv + cl * nout;
+    cdbl a4[4][NO];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int u = 0; u < NO; ++u) a4[v][u] = cdbl{0.0, 0.0};
+    int64_t t = w;
+    for (; t + 12 < ni; t += 16) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t r = t + 4 * v;
+            const cdbl* row = r < nk ? part + (k0 + r) * nout : tp + (int64_t)tb[e0 + r - nk] * nout;
+#pragma unroll
+            for (int u = 0; u < NO; ++u) a4[v][u] = a4[v][u] + row[oc[u]];
+        }
+    }
+    for (; t < ni; t += 4) {
+        const cdbl* row = t < nk ? part + (k0 + t) * nout : tp + (int64_t)tb[e0 + t - nk] * nout;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) a4[0][u] = a4[0][u] + row[oc[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < NO; ++u) red[w][lane + 64 * u] = (a4[0][u] + a4[1][u]) + (a4[2][u] + a4[3][u]);
+    __syncthreads();
+    if (w == 0) {
+        cdbl* lc = (cdbl*)d.lv + cl * nout;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int o = lane + 64 * u;
+            if (on[u]) lc[o] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+        }
+    }
+}
+
+// Local expansions, second part, at level lev >= 1, top down: lv[cl][c][p] += sum_a
+// E_b1[p1][a1] E_b2[p2][a2] lv[parent][c][a].  One wave per cluster, lanes over (c, p); the
+// parent's expansion is staged in the wave's LDS slice, the transfer entries of the lane's
+// node are held in registers.
+template <int Q>
+__global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
+    constexpr int Q2 = Q * Q, NOUT = 4 * Q2, NO = (NOUT + 63) / 64;
+    const int n = 1 << lev, hh = n / 2;
+    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    if (loc >= nc) return;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    const int b1 = i & 1, b2 = j & 1;
+    __shared__ cdbl ps[4][NOUT];  // [wave][c][a]: the parent's expansion
+    const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + ((int64_t)f * hh + i / 2) * hh + j / 2) * NOUT;
+    for (int o = lane; o < NOUT; o += 64) ps[w][o] = src[o];
+    wave_sync();
+    cdbl* lc = (cdbl*)d.lv + (d.lev_off[lev] + loc) * NOUT;
 #pragma unroll
     for (int u = 0; u < NO; ++u) {
         const int o = lane + 64 * u;
-        if (o >= nout) continue;
-        cdbl s = {0.0, 0.0};
-        for (int64_t k = k0; k < k1; ++k) s = s + part[k * nout + o];
-        // the transposed products: four independent sums, so that their loads overlap
-        cdbl t4[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        const int64_t e0 = d.tr_ptr[cl], e1 = d.tr_ptr[cl + 1];
-        int64_t e = e0;
-        for (; e + 4 <= e1; e += 4) {
+        if (o >= NOUT) continue;
+        const int c = o / Q2, p = o % Q2, p1 = p / Q, p2 = p % Q;
+        double e1[Q], e2[Q];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) t4[v] = t4[v] + tp[(int64_t)d.tr_blk[e + v] * nout + o];
+        for (int a = 0; a < Q; ++a) {
+            e1[a] = d.E[(b1 * Q + p1) * Q + a];
+            e2[a] = d.E[(b2 * Q + p2) * Q + a];
         }
-        for (int v = 0; e < e1; ++e, ++v) t4[v] = t4[v] + tp[(int64_t)d.tr_blk[e] * nout + o];
-        s = s + ((t4[0] + t4[1]) + (t4[2] + t4[3]));
-        if (lp) {
-            const int c = o / q2, p = o % q2, p1 = p / q, p2 = p % q;
-            for (int a1 = 0; a1 < q; ++a1) {
-                const double e1 = E[(b1 * q + p1) * q + a1];
-                cdbl t = {0.0, 0.0};
-                for (int a2 = 0; a2 < q; ++a2) t = t + lp[c * q2 + a1 * q + a2] * E[(b2 * q + p2) * q + a2];
-                s = s + t * e1;
-            }
+        cdbl s = lc[o];
+#pragma unroll
+        for (int a1 = 0; a1 < Q; ++a1) {
+            cdbl t = {0.0, 0.0};
+#pragma unroll
+            for (int a2 = 0; a2 < Q; ++a2) t = t + ps[w][c * Q2 + a1 * Q + a2] * e2[a2];
+            s = s + t * e1[a1];
         }
         lc[o] = s;
     }
@@ -973,26 +1051,42 @@ __global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
 #pragma unroll
     for (int s = 0; s < NO; ++s) {
         const int o = lane + 64 * s;
-        lw[s] = cdbl{0.0, 0.0};
-        if (o < nout) lw[s] = o / q2 == 3 ? cmul(mik2, lv[o]) : lv[o];
+        const cdbl x = lv[o < nout ? o : 0];  // loads without branches
+        lw[s] = o >= nout ? cdbl{0.0, 0.0} : (o / q2 == 3 ? cmul(mik2, x) : x);
     }
-    for (int k = 0; k < NL; ++k) {
-        const double* mt = d.Mt + (e * NL + k) * (int64_t)nout;
-        double sr = 0.0, si = 0.0;
+    {
+        // all of the element's moment rows in flight, then the NL wave sums side by side
+        const double* mt = d.Mt + e * NL * (int64_t)nout;
+        double mv[NL][NO];
 #pragma unroll
-        for (int s = 0; s < NO; ++s) {
-            const int o = lane + 64 * s;
-            if (o < nout) {
-                sr += mt[o] * lw[s].re;
-                si += mt[o] * lw[s].im;
+        for (int k = 0; k < NL; ++k)
+#pragma unroll
+            for (int s = 0; s < NO; ++s) {
+                const int o = lane + 64 * s;
+                const double x = mt[k * nout + (o < nout ? o : 0)];  // loads without branches
+                mv[k][s] = o < nout ? x : 0.0;
+            }
+        double sr[NL], si[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            sr[k] = 0.0;
+            si[k] = 0.0;
+#pragma unroll
+            for (int s = 0; s < NO; ++s) {
+                sr[k] += mv[k][s] * lw[s].re;
+                si[k] += mv[k][s] * lw[s].im;
             }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            sr += __shfl_xor(sr, o, 64);
-            si += __shfl_xor(si, o, 64);
-        }
-        if (lane == 0) yf[w][k] = cdbl{sr, si};
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                sr[k] += __shfl_xor(sr[k], o, 64);
+                si[k] += __shfl_xor(si[k], o, 64);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < NL; ++k) yf[w][k] = cdbl{sr[k], si[k]};
     }
     // near: the element's blocks, lanes over block entries (k, j)
     cdbl acc[NE];
@@ -1000,16 +1094,22 @@ __global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
     for (int r = 0; r < NE; ++r) acc[r] = cdbl{0.0, 0.0};
     const cdbl* NB = (const cdbl*)d.s.B;
     const cdbl* xl = (const cdbl*)d.xl;
-    for (int64_t lp = d.near_rowptr[l]; lp < d.near_rowptr[l + 1]; ++lp) {
-        const int64_t ls = d.near_s[lp];
-        for (int v = 0; v < m2; ++v) {
-            const int64_t e2 = leaf_elem(d, ls, v);
-            const cdbl* blk = NB + ((lp * m2 + u) * m2 + v) * (int64_t)(NL * NL);
+    // the (near leaf pair, source element) blocks of the row as one sequence, four at a time;
+    // m2 is a power of two.  Lanes past the block's entries load entry 0 and their sums are
+    // not used, so the loads carry no branches.
+    const int lg = __builtin_ctz(m2);
+    const int64_t lp0 = d.near_rowptr[l];
+    const int nbk = (int)(d.near_rowptr[l + 1] - lp0) << lg;
+#pragma unroll 4
+    for (int it = 0; it < nbk; ++it) {
+        const int64_t lp = lp0 + (it >> lg);
+        const int v = it & (m2 - 1);
+        const int64_t e2 = leaf_elem(d, d.near_s[lp], v);
+        const cdbl* blk = NB + ((lp * m2 + u) * m2 + v) * (int64_t)(NL * NL);
 #pragma unroll
-            for (int r = 0; r < NE; ++r) {
-                const int idx = lane + 64 * r;
-                if (idx < NL * NL) acc[r] = acc[r] + cmul(blk[idx], xl[e2 * NL + idx % NL]);
-            }
+        for (int r = 0; r < NE; ++r) {
+            const int idx = lane + 64 * r < NL * NL ? lane + 64 * r : 0;
+            acc[r] = acc[r] + cmul(blk[idx], xl[e2 * NL + idx % NL]);
         }
     }
 #pragma unroll
@@ -1123,31 +1223,30 @@ hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st) {
     return launch_mx_pairs(d.s, st);
 }
 
-template <int NO>
-static hipError_t mxh_apply_no(const MxhDev& d, const void* x, void* y, hipStream_t st) {
+template <int Q>
+static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream_t st) {
+    constexpr int NO = (4 * Q * Q + 63) / 64;
     const int64_t nx = d.s.nelem * d.s.nl;
     hipLaunchKernelGGL(k_mxh_gather_x, dim3(nb(nx, 256)), dim3(256), 0, st, d, (const cdbl*)x);
-    hipLaunchKernelGGL(k_mxh_forward<NO>, dim3(nb(d.nleaves, 4)), dim3(256), 0, st, d);
+    const dim3 gf(d.m == 1 ? nb(d.nleaves, 4) : d.nleaves);
+    if (d.s.p == 1)
+        hipLaunchKernelGGL((k_mxh_forward<1, NO>), gf, dim3(256), 0, st, d);
+    else
+        hipLaunchKernelGGL((k_mxh_forward<2, NO>), gf, dim3(256), 0, st, d);
     for (int lev = d.leaf - 1; lev >= 0; --lev) {
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
-        hipLaunchKernelGGL(k_mxh_up<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+        hipLaunchKernelGGL(k_mxh_up<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
     if (d.nchunks > 0) {
-        const dim3 g(nb(d.nchunks, 4)), gw(d.nchunks), blk(256), blkw(512);
-        switch (d.q) {
-            case 1: hipLaunchKernelGGL(k_mxh_coupling_wg<1>, gw, blkw, 0, st, d); break;
-            case 2: hipLaunchKernelGGL(k_mxh_coupling_wg<2>, gw, blkw, 0, st, d); break;
-            case 3: hipLaunchKernelGGL(k_mxh_coupling_wg<3>, gw, blkw, 0, st, d); break;
-            case 4: hipLaunchKernelGGL(k_mxh_coupling_wg<4>, gw, blkw, 0, st, d); break;
-            case 5: hipLaunchKernelGGL(k_mxh_coupling_wg<5>, gw, blkw, 0, st, d); break;
-            case 6: hipLaunchKernelGGL(k_mxh_coupling<6>, g, blk, 0, st, d); break;
-            case 7: hipLaunchKernelGGL(k_mxh_coupling<7>, g, blk, 0, st, d); break;
-            default: hipLaunchKernelGGL(k_mxh_coupling<8>, g, blk, 0, st, d); break;
-        }
+        if constexpr (Q * Q <= 32)
+            hipLaunchKernelGGL(k_mxh_coupling_wg<Q>, dim3(d.nchunks), dim3(512), 0, st, d);
+        else
+            hipLaunchKernelGGL(k_mxh_coupling<Q>, dim3(nb(d.nchunks, 4)), dim3(256), 0, st, d);
     }
-    for (int lev = 0; lev <= d.leaf; ++lev) {
+    hipLaunchKernelGGL(k_mxh_collect<NO>, dim3(d.ncl), dim3(256), 0, st, d);
+    for (int lev = 1; lev <= d.leaf; ++lev) {
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
-        hipLaunchKernelGGL(k_mxh_down<NO>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+        hipLaunchKernelGGL(k_mxh_down<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
     if (d.s.p == 1)
         hipLaunchKernelGGL((k_mxh_back<1, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
@@ -1160,12 +1259,17 @@ static hipError_t mxh_apply_no(const MxhDev& d, const void* x, void* y, hipStrea
 hipError_t launch_mxh_apply(const MxhDev& d, const void* x, void* y, hipStream_t st) {
     if (d.s.nglob == 0) return hipSuccess;
     if (d.s.p != 1 && d.s.p != 2) return hipErrorInvalidValue;
-    const int nout = 4 * d.q2;
-    if (nout <= 64) return mxh_apply_no<1>(d, x, y, st);
-    if (nout <= 128) return mxh_apply_no<2>(d, x, y, st);
-    if (nout <= 192) return mxh_apply_no<3>(d, x, y, st);
-    if (nout <= 256) return mxh_apply_no<4>(d, x, y, st);
-    return hipErrorInvalidValue;
+    switch (d.q) {
+        case 1: return mxh_apply_q<1>(d, x, y, st);
+        case 2: return mxh_apply_q<2>(d, x, y, st);
+        case 3: return mxh_apply_q<3>(d, x, y, st);
+        case 4: return mxh_apply_q<4>(d, x, y, st);
+        case 5: return mxh_apply_q<5>(d, x, y, st);
+        case 6: return mxh_apply_q<6>(d, x, y, st);
+        case 7: return mxh_apply_q<7>(d, x, y, st);
+        case 8: return mxh_apply_q<8>(d, x, y, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace bem
