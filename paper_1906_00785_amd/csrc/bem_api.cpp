@@ -149,6 +149,8 @@ struct bem_operator_s {
     std::vector<int32_t> mxh_tr_blk;
     std::vector<int64_t> mx_blist;              // pair blocks by kind: regular, then touching (same)
     std::vector<int64_t> mxh_cl_chunk;
+    std::vector<int64_t> mxh_nrowptr;  // glued near field: CSR pattern over the global functions
+    std::vector<int32_t> mxh_ncol;
     std::vector<int32_t> mx_tinfo;  // host copies of the pair types and the Gauss rules (kept,
     std::vector<double> mx_rules;   // the uploads are asynchronous)
     size_t scal = 8;  // bytes per scalar
@@ -1680,6 +1682,9 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     char* chp1 = take(A.mxh_ch_p1.size() * 4);
     char* clch = take(A.mxh_cl_chunk.size() * 8);
     char* part = take(A.mxh_ch_p0.size() * 4 * q2 * 16);
+    char* nrow = take(A.mxh_nrowptr.size() * 8);
+    char* ncol = take(A.mxh_ncol.size() * 4);
+    char* nval = take(A.mxh_ncol.size() * 16);
     const size_t op_total = off + 256;
     size_t toff = 0;
     auto ttake = [&](size_t bytes) {
@@ -1716,6 +1721,9 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         d->ch_p1 = (const int32_t*)chp1;
         d->cl_chunk = (const int64_t*)clch;
         d->partial = part;
+        d->nrowptr = (const int64_t*)nrow;
+        d->ncol = (const int32_t*)ncol;
+        d->nval = nval;
         d->s.plist = (const int64_t*)plist;
         d->s.tinfo = (const int32_t*)tinfo;
         d->s.blist = (const int64_t*)blist;
@@ -1782,6 +1790,56 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
                 A->mx_tinfo[(lp * m2 + t5[0]) * m2 + t5[1]] = t5[2] | t5[3] << 4 | t5[4] << 8;
             }
         }
+        // glued near field: row g holds every global function h with a piece on an element
+        // that forms a near pair with an element of a piece of g (ascending columns).  Per
+        // leaf the functions with a piece on it; per row the near leaves of its pieces' leaves,
+        // each visited once.
+        {
+            const MxTab& T = *s->mx;
+            const int nl = T.nl;
+            const int64_t N = T.nglob, nlv = pl.nleaves;
+            std::vector<int64_t> stamp(N, -1), lptr(nlv + 1, 0);
+            std::vector<int32_t> ldof, cols;
+            for (int64_t l = 0; l < nlv; ++l) {
+                for (int v = 0; v < m2; ++v) {
+                    const int32_t* eg = &T.eglob[(size_t)elem(l, v) * nl];
+                    for (int k = 0; k < nl; ++k)
+                        if (eg[k] >= 0 && stamp[eg[k]] != l) {
+                            stamp[eg[k]] = l;
+                            ldof.push_back(eg[k]);
+                        }
+                }
+                lptr[l + 1] = (int64_t)ldof.size();
+            }
+            std::fill(stamp.begin(), stamp.end(), -1);
+            std::vector<int64_t> seen_src(nlv, -1), seen_near(nlv, -1);
+            A->mxh_nrowptr.assign(N + 1, 0);
+            A->mxh_ncol.clear();
+            for (int64_t g = 0; g < N; ++g) {
+                cols.clear();
+                for (int64_t t = T.gptr[g]; t < T.gptr[g + 1]; ++t) {
+                    const int64_t e1 = T.gpos[t] / nl;
+                    const int64_t f = e1 / ((int64_t)S.nel * S.nel);
+                    const int i = (int)((e1 / S.nel) % S.nel), j = (int)(e1 % S.nel);
+                    const int64_t l1 = (f * pl.nleaf1 + i / m) * pl.nleaf1 + j / m;
+                    if (seen_src[l1] == g) continue;
+                    seen_src[l1] = g;
+                    for (int32_t lp = pl.near_rowptr[l1]; lp < pl.near_rowptr[l1 + 1]; ++lp) {
+                        const int32_t l2 = pl.near_s[lp];
+                        if (seen_near[l2] == g) continue;
+                        seen_near[l2] = g;
+                        for (int64_t r = lptr[l2]; r < lptr[l2 + 1]; ++r)
+                            if (stamp[ldof[r]] != g) {
+                                stamp[ldof[r]] = g;
+                                cols.push_back(ldof[r]);
+                            }
+                    }
+                }
+                std::sort(cols.begin(), cols.end());
+                A->mxh_ncol.insert(A->mxh_ncol.end(), cols.begin(), cols.end());
+                A->mxh_nrowptr[g + 1] = (int64_t)A->mxh_ncol.size();
+            }
+        }
         A->mx_rules.clear();
         for (auto* v : {&pl.gx, &pl.gw, &pl.sx, &pl.sw}) A->mx_rules.insert(A->mx_rules.end(), v->begin(), v->end());
         if (pl.own_src.size() > 0x7fffffff) {
@@ -1843,6 +1901,7 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     d.nnear = (int64_t)pl.near_t.size();
     d.nchunks = (int64_t)A->mxh_ch_p0.size();
     d.nstored = (int64_t)pl.own_src.size();
+    d.nnzg = (int64_t)A->mxh_ncol.size();
     const int64_t N = S.nglob;
     bem_operator_info& I = A->info;
     I.ndof = N;
@@ -1859,7 +1918,8 @@ static int mxh_plan(bem_space_s* s, const bem_h2_params* p, bem_operator* out, b
     I.tmp_bytes = tmpb;
     I.nstored = d.nstored;
     I.far_bytes = (double)d.nstored * d.q2 * d.q2 * 16;
-    I.near_bytes = (double)I.near_nnz * 16;
+    // per apply the glued near field is read: values, columns and row pointers
+    I.near_bytes = (double)d.nnzg * 20 + (double)(N + 1) * 8;
     // the plan's own arrays (they stay with the operator) are the scalar element space's;
     // the operator is reported on S^1
     A->plan.S.form = 1;
@@ -1906,6 +1966,8 @@ static int mxh_assemble(bem_operator_s* A, void* op_ws, void* tmp_ws, hipStream_
     HIP_CHECK(up(d.s.blist, A->mx_blist.data(), A->mx_blist.size() * 8));
     HIP_CHECK(up(d.s.gx, A->mx_rules.data(), A->mx_rules.size() * 8));
     HIP_CHECK(up(d.Lg, A->mxh_lg.data(), A->mxh_lg.size() * 8));
+    HIP_CHECK(up(d.nrowptr, A->mxh_nrowptr.data(), A->mxh_nrowptr.size() * 8));
+    HIP_CHECK(up(d.ncol, A->mxh_ncol.data(), A->mxh_ncol.size() * 4));
     HIP_CHECK(launch_mxh_assemble(d, stream));
     // tables of the temporary workspace
     d.s.plist = nullptr;

@@ -45,7 +45,7 @@ struct MxDev {
 // The compressed operator (Sec. 2 interpolation on the scalar block partition, four
 // channels: the three components of the lifted field and the divergence).
 struct MxhDev {
-    MxDev s;                     // space, Gauss rules; s.B: near element-pair blocks
+    MxDev s;                     // space, Gauss rules; s.B: near element-pair blocks (assembly)
     int q, q2, leaf, m, nleaf1;  // m: elements per leaf per direction
     int64_t ncl, nleaves, nfar, nnear;
     const int64_t* lev_off;      // [leaf + 2] first cluster of every level
@@ -69,6 +69,12 @@ struct MxhDev {
     const int32_t* tr_blk;
     const int32_t* near_rowptr;  // [nleaves + 1] near leaf pairs by target leaf
     const int32_t* near_s;       // [nnear] source leaf (leaf-local index)
+    // glued near field over the global functions (CSR, ascending columns): entry (g, h) sums
+    // the signed entries of the near element-pair blocks between the pieces of g and of h
+    int64_t nnzg;
+    const int64_t* nrowptr;      // [nglob + 1]
+    const int32_t* ncol;         // [nnzg]
+    void* nval;                  // [nnzg] complex
     double* Mt;                  // [nelem][nl][4][q2] channel moments against the leaf's Lagrange polynomials
     double* xc;                  // [ncl][q2][3] Chebyshev points on the surface (assembly)
     const double* Lg;            // [m][qg][q] L_a at Gauss point k of element position i in its

@@ -1025,13 +1025,11 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
     }
 }
 
-// Backward transform and near field per element: yl[e][k] = sum_c w_c sum_a Mt[e][k][c][a]
-// lv[leaf][c][a] (w = 1, 1, 1, -kappa^-2) plus the near blocks of the element's row times
-// the coefficients of their trial elements.  One wave per element.
+// Backward transform per element: yl[e][k] = sum_c w_c sum_a Mt[e][k][c][a] lv[leaf][c][a]
+// (w = 1, 1, 1, -kappa^-2).  One wave per element.
 template <int P, int NO>
 __global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
-    constexpr int NL = 2 * P * (P + 1), NE = (NL * NL + 63) / 64;
-    __shared__ cdbl red[4][NL * NL];
+    constexpr int NL = 2 * P * (P + 1);
     __shared__ cdbl yf[4][NL];
     const int w = uniform_int(threadIdx.x >> 6);
     const int64_t e = (int64_t)blockIdx.x * 4 + w;
@@ -1040,7 +1038,6 @@ __global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
     const int n = d.s.nel, m = d.m, q2 = d.q2, nout = 4 * q2;
     const int i2 = (int)(e % n), i1 = (int)((e / n) % n), f = (int)(e / ((int64_t)n * n));
     const int64_t l = ((int64_t)f * d.nleaf1 + i1 / m) * d.nleaf1 + i2 / m;
-    const int u = (i1 % m) * m + i2 % m, m2 = m * m;
     // far: the leaf's local expansion, weighted per channel
     const KernelDesc& kd = d.s.ker;
     const double k2r = kd.kre * kd.kre - kd.kim * kd.kim, k2i = 2.0 * kd.kre * kd.kim;
@@ -1088,51 +1085,69 @@ __global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
 #pragma unroll
             for (int k = 0; k < NL; ++k) yf[w][k] = cdbl{sr[k], si[k]};
     }
-    // near: the element's blocks, lanes over block entries (k, j)
-    cdbl acc[NE];
-#pragma unroll
-    for (int r = 0; r < NE; ++r) acc[r] = cdbl{0.0, 0.0};
-    const cdbl* NB = (const cdbl*)d.s.B;
-    const cdbl* xl = (const cdbl*)d.xl;
-    // the (near leaf pair, source element) blocks of the row as one sequence, four at a time;
-    // m2 is a power of two.  Lanes past the block's entries load entry 0 and their sums are
-    // not used, so the loads carry no branches.
-    const int lg = __builtin_ctz(m2);
-    const int64_t lp0 = d.near_rowptr[l];
-    const int nbk = (int)(d.near_rowptr[l + 1] - lp0) << lg;
-#pragma unroll 4
-    for (int it = 0; it < nbk; ++it) {
-        const int64_t lp = lp0 + (it >> lg);
-        const int v = it & (m2 - 1);
-        const int64_t e2 = leaf_elem(d, d.near_s[lp], v);
-        const cdbl* blk = NB + ((lp * m2 + u) * m2 + v) * (int64_t)(NL * NL);
-#pragma unroll
-        for (int r = 0; r < NE; ++r) {
-            const int idx = lane + 64 * r < NL * NL ? lane + 64 * r : 0;
-            acc[r] = acc[r] + cmul(blk[idx], xl[e2 * NL + idx % NL]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NE; ++r) {
-        const int idx = lane + 64 * r;
-        if (idx < NL * NL) red[w][idx] = acc[r];
-    }
     wave_sync();
-    if (lane < NL) {
-        cdbl s = yf[w][lane];
-        for (int j = 0; j < NL; ++j) s = s + red[w][lane * NL + j];
-        ((cdbl*)d.yl)[e * NL + lane] = s;
-    }
+    if (lane < NL) ((cdbl*)d.yl)[e * NL + lane] = yf[w][lane];
 }
 
-// y[g] = sum over the pieces of g of sign * yl[piece]
-__global__ __launch_bounds__(256) void k_mxh_scatter(MxhDev d, cdbl* __restrict__ y) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// y[g] = sum over the pieces of g of sign * yl[piece] (the far field) + sum_h M[g][h] x[h]
+// (the glued near field); one wave per global function, lanes over the row's entries (four
+// at a time in flight), then a wave sum.
+__global__ __launch_bounds__(256) void k_mxh_scatter(MxhDev d, const cdbl* __restrict__ x, cdbl* __restrict__ y) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (g >= d.s.nglob) return;
     const cdbl* yl = (const cdbl*)d.yl;
+    const cdbl* val = (const cdbl*)d.nval;
     cdbl s = {0.0, 0.0};
-    for (int64_t a = d.s.gptr[g]; a < d.s.gptr[g + 1]; ++a) s = s + yl[d.s.gpos[a]] * (double)d.s.gsgn[a];
-    y[g] = s;
+    for (int64_t a = d.s.gptr[g] + lane; a < d.s.gptr[g + 1]; a += 64) s = s + yl[d.s.gpos[a]] * (double)d.s.gsgn[a];
+    const int64_t r0 = d.nrowptr[g], r1 = d.nrowptr[g + 1];
+#pragma unroll 4
+    for (int64_t r = r0 + lane; r < r1; r += 64) s = s + val[r] * x[d.ncol[r]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s.re += __shfl_xor(s.re, o, 64);
+        s.im += __shfl_xor(s.im, o, 64);
+    }
+    if (lane == 0) y[g] = s;
+}
+
+// Glued near field: M[g][h] = sum over the pieces (e1, k1, s1) of g and (e2, k2, s2) of h whose
+// elements lie in a near leaf pair of s1 s2 B[pair][k1][k2]; one thread per stored entry,
+// its row found by bisection of the row pointers.
+__global__ __launch_bounds__(256) void k_mxh_near_glue(MxhDev d) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= d.nnzg) return;
+    int64_t lo = 0, hi = d.s.nglob;  // nrowptr[lo] <= id < nrowptr[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (d.nrowptr[mid] <= id) lo = mid;
+        else hi = mid;
+    }
+    const int64_t g = lo, h = d.ncol[id];
+    const int nl = d.s.nl, n = d.s.nel, m = d.m, m2 = m * m;
+    const cdbl* B = (const cdbl*)d.s.B;
+    cdbl acc = {0.0, 0.0};
+    for (int64_t t1 = d.s.gptr[g]; t1 < d.s.gptr[g + 1]; ++t1) {
+        const int p1 = d.s.gpos[t1], k1 = p1 % nl;
+        const int64_t e1 = p1 / nl;
+        const int i1 = (int)((e1 / n) % n), j1 = (int)(e1 % n);
+        const int64_t l1 = ((e1 / ((int64_t)n * n)) * d.nleaf1 + i1 / m) * d.nleaf1 + j1 / m;
+        const int u1 = (i1 % m) * m + j1 % m;
+        for (int64_t t2 = d.s.gptr[h]; t2 < d.s.gptr[h + 1]; ++t2) {
+            const int p2 = d.s.gpos[t2], k2 = p2 % nl;
+            const int64_t e2 = p2 / nl;
+            const int i2 = (int)((e2 / n) % n), j2 = (int)(e2 % n);
+            const int64_t l2 = ((e2 / ((int64_t)n * n)) * d.nleaf1 + i2 / m) * d.nleaf1 + j2 / m;
+            const int v2 = (i2 % m) * m + j2 % m;
+            for (int64_t lp = d.near_rowptr[l1]; lp < d.near_rowptr[l1 + 1]; ++lp)
+                if (d.near_s[lp] == l2) {
+                    const cdbl b = B[((lp * m2 + u1) * m2 + v2) * (int64_t)(nl * nl) + k1 * nl + k2];
+                    acc = acc + b * (double)(d.s.gsgn[t1] * d.s.gsgn[t2]);
+                    break;
+                }
+        }
+    }
+    ((cdbl*)d.nval)[id] = acc;
 }
 
 inline unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1220,7 +1235,9 @@ hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st) {
             return hipErrorInvalidValue;
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    return launch_mx_pairs(d.s, st);
+    if ((e = launch_mx_pairs(d.s, st)) != hipSuccess) return e;
+    if (d.nnzg > 0) hipLaunchKernelGGL(k_mxh_near_glue, dim3(nb(d.nnzg, 256)), dim3(256), 0, st, d);
+    return hipGetLastError();
 }
 
 template <int Q>
@@ -1252,7 +1269,7 @@ static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream
         hipLaunchKernelGGL((k_mxh_back<1, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
     else
         hipLaunchKernelGGL((k_mxh_back<2, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_mxh_scatter, dim3(nb(d.s.nglob, 256)), dim3(256), 0, st, d, (cdbl*)y);
+    hipLaunchKernelGGL(k_mxh_scatter, dim3(nb(d.s.nglob, 4)), dim3(256), 0, st, d, (const cdbl*)x, (cdbl*)y);
     return hipGetLastError();
 }
 
