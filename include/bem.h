@@ -289,10 +289,12 @@ int bem_space_create(bem_geometry g, int kernel, double kappa_re, double kappa_i
  *     direction, 1 <= q <= 8, leaf_level; default leaf level L - 1).  The form splits into
  *     four scalar kernel products, one per channel: the three components of the lifted
  *     field and the divergence (weight -kappa^-2), so one coupling block of the kernel serves
- *     all four; element pairs in near leaf pairs keep their Galerkin blocks.  The channel
- *     moments of every element against its leaf's Lagrange polynomials use the qg x qg
- *     Gauss rule per element.  info.nfar/nnear/nclusters describe the partition, near_nnz the
- *     stored near-block entries.
+ *     all four; element pairs in near leaf pairs keep their Galerkin blocks, which are
+ *     summed with the gluing signs into a sparse matrix over the global functions at
+ *     assembly (the apply reads that matrix).  The channel moments of every element
+ *     against its leaf's Lagrange polynomials use the qg x qg Gauss rule per element.
+ *     info.nfar/nnear/nclusters describe the partition, near_nnz the near element-pair block
+ *     entries, near_bytes the bytes of the glued near matrix (values, columns, row pointers).
  * bem_apply and bem_solve (no preconditioner, no refinement) work as for the other spaces;
  * the block preconditioner, grouped launches, stage timing, the exports, the cluster-tree
  * potential, sampled data and VTK output return EUNSUPPORTED. */
