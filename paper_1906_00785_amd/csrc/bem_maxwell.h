@@ -13,7 +13,7 @@
 namespace bem {
 
 constexpr int kMxMaxP = 2;    // degrees p of the device kernels (register budget of the pair kernel)
-constexpr int kMxhChunk = 8;  // stored admissible pairs per coupling work chunk
+constexpr int kMxhChunk = 4;  // stored admissible pairs per coupling work chunk
 
 struct MxDev {
     GeomDesc geom;

@@ -751,17 +751,18 @@ __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
 // owner u), with entries K[b][a] = G(x_a^u, x_b^v):
 //   partial[chunk][c][a] += sum_b K[b][a] mom[v][c][b]   (the owner's expansion)
 //   tprod[block][c][b]   = sum_a K[b][a] mom[u][c][a]    (the partner's)
-// With q^2 <= 32 (q <= 5): one workgroup of eight waves per chunk, one block per wave.  The
+// With q^2 <= 32 (q <= 5): one workgroup per chunk, one wave per block of the chunk.  The
 // wave copies its block into its LDS slice with global-to-LDS loads (no registers held, all
 // of the workgroup's loads in flight at once) and waits for its own copy only; both passes
 // then read LDS, lane (0, i) forming the real and lane (1, i) the imaginary part of node
 // i's sum, so that the moments (the partner's in the column pass, the owner's in the row
 // pass) are uniform over the wave and enter the products straight from scalar registers.
-// The eight waves' column sums are added in a fixed order.
+// The waves' column sums are added in a fixed order.
 template <int Q>
-__global__ __launch_bounds__(512) void k_mxh_coupling_wg(MxhDev d) {
-    constexpr int Q2 = Q * Q, QQ = Q2 * Q2, NL = 8 * QQ > 32 * Q2 ? 8 * QQ : 32 * Q2;
-    static_assert(Q2 <= 32 && kMxhChunk == 8, "one block per wave, eight waves");
+__global__ __launch_bounds__(64 * kMxhChunk) void k_mxh_coupling_wg(MxhDev d) {
+    constexpr int W = kMxhChunk;  // waves, one block each
+    constexpr int Q2 = Q * Q, QQ = Q2 * Q2, NL = W * QQ > 4 * W * Q2 ? W * QQ : 4 * W * Q2;
+    static_assert(Q2 <= 32, "a node per lane and half-wave");
     __shared__ cdbl kls[NL];  // block j of the chunk at j q^4, [b][a]; then the waves' column sums
     const int64_t k = blockIdx.x;
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63, h = lane >> 5, i = lane & 31;
@@ -831,7 +832,7 @@ __global__ __launch_bounds__(512) void k_mxh_coupling_wg(MxhDev d) {
         const int o = threadIdx.x;
         cdbl s = kls[o];
 #pragma unroll
-        for (int v = 1; v < 8; ++v) s = s + kls[v * 4 * Q2 + o];
+        for (int v = 1; v < W; ++v) s = s + kls[v * 4 * Q2 + o];
         ((cdbl*)d.partial)[k * 4 * Q2 + o] = s;
     }
 }
@@ -1256,7 +1257,7 @@ static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream
     }
     if (d.nchunks > 0) {
         if constexpr (Q * Q <= 32)
-            hipLaunchKernelGGL(k_mxh_coupling_wg<Q>, dim3(d.nchunks), dim3(512), 0, st, d);
+            hipLaunchKernelGGL(k_mxh_coupling_wg<Q>, dim3(d.nchunks), dim3(64 * kMxhChunk), 0, st, d);
         else
             hipLaunchKernelGGL(k_mxh_coupling<Q>, dim3(nb(d.nchunks, 4)), dim3(256), 0, st, d);
     }
