@@ -1665,7 +1665,6 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     char* NB = take((size_t)npairs * nl * nl * 16);
     char* Mt = take((size_t)ne * nl * 4 * q2 * 8);
     char* xl = take((size_t)ne * nl * 16);
-    char* yl = take((size_t)ne * nl * 16);
     char* mom = take((size_t)h.ncl * 4 * q2 * 16);
     char* lv = take((size_t)h.ncl * 4 * q2 * 16);
     char* lev = take(pl.lev_off.size() * 8);
@@ -1704,7 +1703,6 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         d->s.B = NB;
         d->Mt = (double*)Mt;
         d->xl = xl;
-        d->yl = yl;
         d->mom = mom;
         d->lv = lv;
         d->lev_off = (const int64_t*)lev;

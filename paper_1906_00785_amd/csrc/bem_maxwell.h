@@ -80,7 +80,6 @@ struct MxhDev {
     const double* Lg;            // [m][qg][q] L_a at Gauss point k of element position i in its
                                  // leaf, (i + x_k) / m (assembly)
     void* xl;                    // [nelem][nl] complex: signed coefficients per element
-    void* yl;                    // [nelem][nl] complex: product per element
     void* mom;                   // [ncl][4][q2] complex moments
     void* lv;                    // [ncl][4][q2] complex local expansions
 };

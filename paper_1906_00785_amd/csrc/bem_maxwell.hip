@@ -1026,81 +1026,35 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
     }
 }
 
-// Backward transform per element: yl[e][k] = sum_c w_c sum_a Mt[e][k][c][a] lv[leaf][c][a]
-// (w = 1, 1, 1, -kappa^-2).  One wave per element.
-template <int P, int NO>
-__global__ __launch_bounds__(256) void k_mxh_back(MxhDev d) {
-    constexpr int NL = 2 * P * (P + 1);
-    __shared__ cdbl yf[4][NL];
-    const int w = uniform_int(threadIdx.x >> 6);
-    const int64_t e = (int64_t)blockIdx.x * 4 + w;
-    const int lane = threadIdx.x & 63;
-    if (e >= d.s.nelem) return;
-    const int n = d.s.nel, m = d.m, q2 = d.q2, nout = 4 * q2;
-    const int i2 = (int)(e % n), i1 = (int)((e / n) % n), f = (int)(e / ((int64_t)n * n));
-    const int64_t l = ((int64_t)f * d.nleaf1 + i1 / m) * d.nleaf1 + i2 / m;
-    // far: the leaf's local expansion, weighted per channel
-    const KernelDesc& kd = d.s.ker;
-    const double k2r = kd.kre * kd.kre - kd.kim * kd.kim, k2i = 2.0 * kd.kre * kd.kim;
-    const double den = k2r * k2r + k2i * k2i;
-    const cdbl mik2 = {-k2r / den, k2i / den};
-    const cdbl* lv = (const cdbl*)d.lv + (d.lev_off[d.leaf] + l) * nout;
-    cdbl lw[NO];
-#pragma unroll
-    for (int s = 0; s < NO; ++s) {
-        const int o = lane + 64 * s;
-        const cdbl x = lv[o < nout ? o : 0];  // loads without branches
-        lw[s] = o >= nout ? cdbl{0.0, 0.0} : (o / q2 == 3 ? cmul(mik2, x) : x);
-    }
-    {
-        // all of the element's moment rows in flight, then the NL wave sums side by side
-        const double* mt = d.Mt + e * NL * (int64_t)nout;
-        double mv[NL][NO];
-#pragma unroll
-        for (int k = 0; k < NL; ++k)
-#pragma unroll
-            for (int s = 0; s < NO; ++s) {
-                const int o = lane + 64 * s;
-                const double x = mt[k * nout + (o < nout ? o : 0)];  // loads without branches
-                mv[k][s] = o < nout ? x : 0.0;
-            }
-        double sr[NL], si[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            sr[k] = 0.0;
-            si[k] = 0.0;
-#pragma unroll
-            for (int s = 0; s < NO; ++s) {
-                sr[k] += mv[k][s] * lw[s].re;
-                si[k] += mv[k][s] * lw[s].im;
-            }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-            for (int k = 0; k < NL; ++k) {
-                sr[k] += __shfl_xor(sr[k], o, 64);
-                si[k] += __shfl_xor(si[k], o, 64);
-            }
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < NL; ++k) yf[w][k] = cdbl{sr[k], si[k]};
-    }
-    wave_sync();
-    if (lane < NL) ((cdbl*)d.yl)[e * NL + lane] = yf[w][lane];
-}
-
-// y[g] = sum over the pieces of g of sign * yl[piece] (the far field) + sum_h M[g][h] x[h]
-// (the glued near field); one wave per global function, lanes over the row's entries (four
-// at a time in flight), then a wave sum.
+// y[g] = sum over the pieces (e, k, s) of g of s sum_c w_c sum_a Mt[e][k][c][a] lv[leaf(e)][c][a]
+// (the backward transform of the far field, w = 1, 1, 1, -kappa^-2) + sum_h M[g][h] x[h] (the
+// glued near field).  One wave per global function: lanes over the (c, a) terms of each piece,
+// then over the row's entries (four at a time in flight), then a wave sum.
 __global__ __launch_bounds__(256) void k_mxh_scatter(MxhDev d, const cdbl* __restrict__ x, cdbl* __restrict__ y) {
     const int64_t g = (int64_t)blockIdx.x * 4 + uniform_int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= d.s.nglob) return;
-    const cdbl* yl = (const cdbl*)d.yl;
-    const cdbl* val = (const cdbl*)d.nval;
+    const int nl = d.s.nl, n = d.s.nel, m = d.m, q2 = d.q2, nout = 4 * q2;
+    const KernelDesc& kd = d.s.ker;
+    const double k2r = kd.kre * kd.kre - kd.kim * kd.kim, k2i = 2.0 * kd.kre * kd.kim;
+    const double den = k2r * k2r + k2i * k2i;
+    const cdbl mik2 = {-k2r / den, k2i / den};
+    const cdbl* lvb = (const cdbl*)d.lv + d.lev_off[d.leaf] * nout;
     cdbl s = {0.0, 0.0};
-    for (int64_t a = d.s.gptr[g] + lane; a < d.s.gptr[g + 1]; a += 64) s = s + yl[d.s.gpos[a]] * (double)d.s.gsgn[a];
+    for (int64_t t = d.s.gptr[g]; t < d.s.gptr[g + 1]; ++t) {  // uniform over the wave
+        const int p = d.s.gpos[t];
+        const int64_t e = p / nl;
+        const int i1 = (int)((e / n) % n), i2 = (int)(e % n);
+        const int64_t l = ((e / ((int64_t)n * n)) * d.nleaf1 + i1 / m) * d.nleaf1 + i2 / m;
+        const double* mt = d.Mt + (int64_t)p * nout;
+        const cdbl* lv = lvb + l * nout;
+        const double sg = (double)d.s.gsgn[t];
+        for (int o = lane; o < nout; o += 64) {
+            const cdbl v = lv[o];
+            s = s + (o >= 3 * q2 ? cmul(mik2, v) : v) * (mt[o] * sg);
+        }
+    }
+    const cdbl* val = (const cdbl*)d.nval;
     const int64_t r0 = d.nrowptr[g], r1 = d.nrowptr[g + 1];
 #pragma unroll 4
     for (int64_t r = r0 + lane; r < r1; r += 64) s = s + val[r] * x[d.ncol[r]];
@@ -1266,10 +1220,6 @@ static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
         hipLaunchKernelGGL(k_mxh_down<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
     }
-    if (d.s.p == 1)
-        hipLaunchKernelGGL((k_mxh_back<1, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
-    else
-        hipLaunchKernelGGL((k_mxh_back<2, NO>), dim3(nb(d.s.nelem, 4)), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_mxh_scatter, dim3(nb(d.s.nglob, 4)), dim3(256), 0, st, d, (const cdbl*)x, (cdbl*)y);
     return hipGetLastError();
 }
