@@ -697,26 +697,11 @@ typedef const __attribute__((address_space(4))) int32_t* mx_ciptr;
 // of E_b1[p1][a1] E_b2[p2][a2] m_child[c][p]; one wave per parent, lanes over (c, a).  The
 // children's moments are staged in the wave's LDS slice (coalesced); each lane holds the
 // transfer entries of its node in registers, so the sums run without memory waits.
+// sm: the four children [b = 2 b1 + b2][c][p]; the parent's moments go to out (and to lds
+// when given).
 template <int Q>
-__global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
+__device__ inline void mxh_up_transfer(const MxhDev& d, const cdbl* sm, int lane, cdbl* out, cdbl* lds) {
     constexpr int Q2 = Q * Q, NOUT = 4 * Q2, NO = (NOUT + 63) / 64;
-    __shared__ cdbl mc[4][4 * NOUT];  // [wave][child][c][p]
-    const int n = 1 << lev;
-    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
-    const int w = uniform_int(threadIdx.x >> 6);
-    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
-    const int lane = threadIdx.x & 63;
-    if (loc >= nc) return;
-    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const cdbl* mom = (const cdbl*)d.mom;
-    cdbl* sm = mc[w];
-    // the four children are consecutive in pairs along j: (2i + b1, 2j), (2i + b1, 2j + 1)
-    for (int b1 = 0; b1 < 2; ++b1) {
-        const int64_t ch = d.lev_off[lev + 1] + ((int64_t)f * 2 * n + 2 * i + b1) * 2 * n + 2 * j;
-        const cdbl* src = mom + ch * NOUT;
-        for (int o = lane; o < 2 * NOUT; o += 64) sm[b1 * 2 * NOUT + o] = src[o];
-    }
-    wave_sync();
 #pragma unroll
     for (int u = 0; u < NO; ++u) {
         const int o = lane + 64 * u;
@@ -743,8 +728,39 @@ __global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
                 acc = acc + t * e1[b1][p1];
             }
         }
-        ((cdbl*)d.mom)[(d.lev_off[lev] + loc) * NOUT + o] = acc;
+        out[o] = acc;
+        if (lds) lds[o] = acc;
     }
+}
+
+// stages the four children of cluster (f, i, j) at level lev (children at lev + 1) into sm
+template <int Q>
+__device__ inline void mxh_stage_children(const MxhDev& d, int lev, int64_t f, int i, int j, int lane, cdbl* sm) {
+    constexpr int NOUT = 4 * Q * Q;
+    const int n = 1 << lev;
+    // the four children are consecutive in pairs along j: (2i + b1, 2j), (2i + b1, 2j + 1)
+    for (int b1 = 0; b1 < 2; ++b1) {
+        const int64_t ch = d.lev_off[lev + 1] + (f * 2 * n + 2 * i + b1) * 2 * n + 2 * j;
+        const cdbl* src = (const cdbl*)d.mom + ch * NOUT;
+        for (int o = lane; o < 2 * NOUT; o += 64) sm[b1 * 2 * NOUT + o] = src[o];
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_mxh_up(MxhDev d, int lev) {
+    constexpr int NOUT = 4 * Q * Q;
+    __shared__ cdbl mc[4][4 * NOUT];  // [wave][child][c][p]
+    const int n = 1 << lev;
+    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    if (loc >= nc) return;
+    const int64_t f = loc / ((int64_t)n * n);
+    const int i = (int)((loc / n) % n), j = (int)(loc % n);
+    mxh_stage_children<Q>(d, lev, f, i, j, lane, mc[w]);
+    wave_sync();
+    mxh_up_transfer<Q>(d, mc[w], lane, (cdbl*)d.mom + (d.lev_off[lev] + loc) * NOUT, nullptr);
 }
 
 // Coupling.  For every stored block (u, v) of a work chunk (consecutive stored blocks of one
@@ -986,23 +1002,12 @@ __global__ __launch_bounds__(256) void k_mxh_collect(MxhDev d) {
 // Local expansions, second part, at level lev >= 1, top down: lv[cl][c][p] += sum_a
 // E_b1[p1][a1] E_b2[p2][a2] lv[parent][c][a].  One wave per cluster, lanes over (c, p); the
 // parent's expansion is staged in the wave's LDS slice, the transfer entries of the lane's
-// node are held in registers.
+// node are held in registers.  ps: the parent's expansion [c][a]; the result also goes to
+// lds when given.
 template <int Q>
-__global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
+__device__ inline void mxh_down_transfer(const MxhDev& d, const cdbl* ps, int b1, int b2, int lane, cdbl* lc,
+                                         cdbl* lds) {
     constexpr int Q2 = Q * Q, NOUT = 4 * Q2, NO = (NOUT + 63) / 64;
-    const int n = 1 << lev, hh = n / 2;
-    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
-    const int w = uniform_int(threadIdx.x >> 6);
-    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
-    const int lane = threadIdx.x & 63;
-    if (loc >= nc) return;
-    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
-    const int b1 = i & 1, b2 = j & 1;
-    __shared__ cdbl ps[4][NOUT];  // [wave][c][a]: the parent's expansion
-    const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + ((int64_t)f * hh + i / 2) * hh + j / 2) * NOUT;
-    for (int o = lane; o < NOUT; o += 64) ps[w][o] = src[o];
-    wave_sync();
-    cdbl* lc = (cdbl*)d.lv + (d.lev_off[lev] + loc) * NOUT;
 #pragma unroll
     for (int u = 0; u < NO; ++u) {
         const int o = lane + 64 * u;
@@ -1019,11 +1024,54 @@ __global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
         for (int a1 = 0; a1 < Q; ++a1) {
             cdbl t = {0.0, 0.0};
 #pragma unroll
-            for (int a2 = 0; a2 < Q; ++a2) t = t + ps[w][c * Q2 + a1 * Q + a2] * e2[a2];
+            for (int a2 = 0; a2 < Q; ++a2) t = t + ps[c * Q2 + a1 * Q + a2] * e2[a2];
             s = s + t * e1[a1];
         }
         lc[o] = s;
+        if (lds) lds[o] = s;
     }
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_mxh_down(MxhDev d, int lev) {
+    constexpr int NOUT = 4 * Q * Q;
+    const int n = 1 << lev, hh = n / 2;
+    const int64_t nc = (int64_t)d.s.geom.npatch * n * n;
+    const int w = uniform_int(threadIdx.x >> 6);
+    const int64_t loc = (int64_t)blockIdx.x * 4 + w;
+    const int lane = threadIdx.x & 63;
+    if (loc >= nc) return;
+    const int f = (int)(loc / ((int64_t)n * n)), i = (int)((loc / n) % n), j = (int)(loc % n);
+    __shared__ cdbl ps[4][NOUT];  // [wave][c][a]: the parent's expansion
+    const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + ((int64_t)f * hh + i / 2) * hh + j / 2) * NOUT;
+    for (int o = lane; o < NOUT; o += 64) ps[w][o] = src[o];
+    wave_sync();
+    mxh_down_transfer<Q>(d, ps[w], i & 1, j & 1, lane, (cdbl*)d.lv + (d.lev_off[lev] + loc) * NOUT, nullptr);
+}
+
+// Two levels in one launch: one workgroup per cluster at level lev >= 1; wave 0 adds the
+// parent's transfer to the cluster's expansion (kept in LDS), then wave w adds the cluster's
+// transfer to child w (level lev + 1).
+template <int Q>
+__global__ __launch_bounds__(256) void k_mxh_down2(MxhDev d, int lev) {
+    constexpr int NOUT = 4 * Q * Q;
+    const int n = 1 << lev, hh = n / 2;
+    const int64_t loc = blockIdx.x;
+    const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t f = loc / ((int64_t)n * n);
+    const int i = (int)((loc / n) % n), j = (int)(loc % n);
+    __shared__ cdbl ps[NOUT];   // the parent's expansion
+    __shared__ cdbl own[NOUT];  // the cluster's
+    if (w == 0) {
+        const cdbl* src = (const cdbl*)d.lv + (d.lev_off[lev - 1] + (f * hh + i / 2) * hh + j / 2) * NOUT;
+        for (int o = lane; o < NOUT; o += 64) ps[o] = src[o];
+        wave_sync();
+        mxh_down_transfer<Q>(d, ps, i & 1, j & 1, lane, (cdbl*)d.lv + (d.lev_off[lev] + loc) * NOUT, own);
+    }
+    __syncthreads();
+    const int ci = 2 * i + (w >> 1), cj = 2 * j + (w & 1);  // child w at level lev + 1
+    const int64_t ch = d.lev_off[lev + 1] + (f * 2 * n + ci) * 2 * n + cj;
+    mxh_down_transfer<Q>(d, own, w >> 1, w & 1, lane, (cdbl*)d.lv + ch * NOUT, nullptr);
 }
 
 // y[g] = sum over the pieces (e, k, s) of g of s sum_c w_c sum_a Mt[e][k][c][a] lv[leaf(e)][c][a]
@@ -1216,9 +1264,17 @@ static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream
             hipLaunchKernelGGL(k_mxh_coupling<Q>, dim3(nb(d.nchunks, 4)), dim3(256), 0, st, d);
     }
     hipLaunchKernelGGL(k_mxh_collect<NO>, dim3(d.ncl), dim3(256), 0, st, d);
-    for (int lev = 1; lev <= d.leaf; ++lev) {
-        const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
-        hipLaunchKernelGGL(k_mxh_down<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+    {
+        // levels 1 .. leaf, two per launch where they pair up
+        int lev = 1;
+        for (; lev + 1 <= d.leaf; lev += 2) {
+            const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
+            hipLaunchKernelGGL(k_mxh_down2<Q>, dim3((unsigned)nc), dim3(256), 0, st, d, lev);
+        }
+        if (lev == d.leaf) {
+            const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
+            hipLaunchKernelGGL(k_mxh_down<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
+        }
     }
     hipLaunchKernelGGL(k_mxh_scatter, dim3(nb(d.s.nglob, 4)), dim3(256), 0, st, d, (const cdbl*)x, (cdbl*)y);
     return hipGetLastError();
