@@ -1664,7 +1664,6 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
     char* K = take((size_t)h.nstored * q2 * q2 * 16);
     char* NB = take((size_t)npairs * nl * nl * 16);
     char* Mt = take((size_t)ne * nl * 4 * q2 * 8);
-    char* xl = take((size_t)ne * nl * 16);
     char* mom = take((size_t)h.ncl * 4 * q2 * 16);
     char* lv = take((size_t)h.ncl * 4 * q2 * 16);
     char* lev = take(pl.lev_off.size() * 8);
@@ -1702,7 +1701,6 @@ static size_t mxh_layout(const bem_operator_s& A, char* ob, char* tb, MxhDev* d,
         d->K = K;
         d->s.B = NB;
         d->Mt = (double*)Mt;
-        d->xl = xl;
         d->mom = mom;
         d->lv = lv;
         d->lev_off = (const int64_t*)lev;

@@ -79,7 +79,6 @@ struct MxhDev {
     double* xc;                  // [ncl][q2][3] Chebyshev points on the surface (assembly)
     const double* Lg;            // [m][qg][q] L_a at Gauss point k of element position i in its
                                  // leaf, (i + x_k) / m (assembly)
-    void* xl;                    // [nelem][nl] complex: signed coefficients per element
     void* mom;                   // [ncl][4][q2] complex moments
     void* lv;                    // [ncl][4][q2] complex local expansions
 };

@@ -624,21 +624,14 @@ __global__ __launch_bounds__(64) void k_mxh_moments(MxhDev d) {
     }
 }
 
-// xl[e][k] = sign * x[global of (e, k)] (0 for dropped functions)
-__global__ __launch_bounds__(256) void k_mxh_gather_x(MxhDev d, const cdbl* __restrict__ x) {
-    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (id >= d.s.nelem * d.s.nl) return;
-    const int g = d.s.eglob[id];
-    ((cdbl*)d.xl)[id] = g < 0 ? cdbl{0.0, 0.0} : x[g] * (double)d.s.esgn[id];
-}
-
 // Leaf moments (forward transform): mom[leaf][c][a] = sum over its elements and their
-// functions of Mt[e][k][c][a] xl[e][k]; lanes over (c, a).  With one element per leaf, one
+// functions of Mt[e][k][c][a] xl[e][k], xl[e][k] = sign * x[global function of (e, k)] (0
+// for dropped functions) read straight from x; lanes over (c, a).  With one element per leaf, one
 // wave per leaf; otherwise one workgroup per leaf, wave w taking the leaf's elements w,
 // w + 4, ..., and the four waves' sums added in a fixed order.  All loads of an element are
 // issued before its products.
 template <int P, int NO>
-__global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
+__global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d, const cdbl* __restrict__ x) {
     constexpr int NL = 2 * P * (P + 1);
     __shared__ cdbl red[4][64 * NO];
     const int w = uniform_int(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -649,7 +642,6 @@ __global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
     cdbl acc[NO];
 #pragma unroll
     for (int u = 0; u < NO; ++u) acc[u] = cdbl{0.0, 0.0};
-    const cdbl* xl = (const cdbl*)d.xl;
     for (int v = one ? 0 : w; v < m2; v += 4) {
         const int64_t e = leaf_elem(d, l, v);
         const double* mt = d.Mt + e * NL * (int64_t)nout;
@@ -657,7 +649,8 @@ __global__ __launch_bounds__(256) void k_mxh_forward(MxhDev d) {
         double mv[NL][NO];
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            xv[k] = xl[e * NL + k];
+            const int gk = d.s.eglob[e * NL + k];  // the element's signed coefficients
+            xv[k] = gk < 0 ? cdbl{0.0, 0.0} : x[gk] * (double)d.s.esgn[e * NL + k];
 #pragma unroll
             for (int u = 0; u < NO; ++u) {
                 const int o = lane + 64 * u;
@@ -1246,13 +1239,11 @@ hipError_t launch_mxh_assemble(const MxhDev& d, hipStream_t st) {
 template <int Q>
 static hipError_t mxh_apply_q(const MxhDev& d, const void* x, void* y, hipStream_t st) {
     constexpr int NO = (4 * Q * Q + 63) / 64;
-    const int64_t nx = d.s.nelem * d.s.nl;
-    hipLaunchKernelGGL(k_mxh_gather_x, dim3(nb(nx, 256)), dim3(256), 0, st, d, (const cdbl*)x);
     const dim3 gf(d.m == 1 ? nb(d.nleaves, 4) : d.nleaves);
     if (d.s.p == 1)
-        hipLaunchKernelGGL((k_mxh_forward<1, NO>), gf, dim3(256), 0, st, d);
+        hipLaunchKernelGGL((k_mxh_forward<1, NO>), gf, dim3(256), 0, st, d, (const cdbl*)x);
     else
-        hipLaunchKernelGGL((k_mxh_forward<2, NO>), gf, dim3(256), 0, st, d);
+        hipLaunchKernelGGL((k_mxh_forward<2, NO>), gf, dim3(256), 0, st, d, (const cdbl*)x);
     for (int lev = d.leaf - 1; lev >= 0; --lev) {
         const int64_t nc = (int64_t)d.s.geom.npatch << (2 * lev);
         hipLaunchKernelGGL(k_mxh_up<Q>, dim3(nb(nc, 4)), dim3(256), 0, st, d, lev);
